@@ -1,0 +1,130 @@
+"""Pins of the oracle's multilevel estimators (Sec. 2.2, Eqs. (8), (9)).
+
+Special cases where the nested averages collapse to the plain definitions
+(one update per level; updates that are the identity; a cold lattice), plus a
+statistical check that the multilevel estimator and the plain estimator agree.
+"""
+import math
+
+import numpy as np
+import pytest
+
+AX = {0: 0, 1: 3, 2: 2, 3: 1}
+FIELD_PLANES = [(0, 1), (0, 2), (0, 3), (2, 3), (3, 1), (1, 2)]  # E_x..E_z, B_x..B_z
+
+
+def polyakov_lines(th):
+    """P(x) = exp(i sum_t theta_0(x, t)), indexed [z][y][x]."""
+    return np.exp(1j * th[..., 0].sum(axis=0))
+
+
+def plain_corr(th, r):
+    P = polyakov_lines(th)
+    return np.mean(np.conj(P) * np.roll(P, -r, axis=2))
+
+
+def field_ops(th, beta):
+    """O_c(t, z, y, x) = sqrt(beta) sin(theta_munu) for the six components."""
+    out = []
+    for mu, nu in FIELD_PLANES:
+        p = (th[..., mu] + np.roll(th[..., nu], -1, axis=AX[mu])
+             - np.roll(th[..., mu], -1, axis=AX[nu]) - th[..., nu])
+        out.append(math.sqrt(beta) * np.sin(p))
+    return np.array(out)
+
+
+def field_identity(th, beta, r):
+    """(1/V) sum_x0 sum_t P*(x0) P(x0 + r) O(x0 + d, t) for d in both planes."""
+    T, L = th.shape[0], th.shape[1]
+    P = polyakov_lines(th)
+    w = np.conj(P) * np.roll(P, -r, axis=2)          # [z][y][x]
+    Osum = field_ops(th, beta).sum(axis=1)           # [c][z][y][x]
+    res = np.zeros((2, 6, L, L), dtype=complex)
+    for plane, m in enumerate([(r - 1) // 2, r // 2]):
+        for dy in range(L):
+            for dz in range(L):
+                sh = np.roll(np.roll(np.roll(Osum, -m, axis=3), -dy, axis=2), -dz, axis=1)
+                res[plane, :, dy, dz] = (w[None] * sh).sum(axis=(1, 2, 3))
+    return res / (T * L ** 3)
+
+
+@pytest.mark.parametrize("levels", [([2], [1]), ([4, 2], [1, 1]), ([4], [1])])
+def test_single_update_reduces_to_plain_correlator(oracle_mod, levels):
+    L, T = 4, 8
+    g = oracle_mod.OracleLattice(L, T, 1.0, 17)
+    for _ in range(3):
+        g.sweep(1, 2)
+    r_list = [1, 2, 3]
+    c, _, _ = g.multilevel(levels[0], levels[1], 1, 2, r_list)
+    th = g.get_links()
+    for k, r in enumerate(r_list):
+        assert abs(c[k] - plain_corr(th, r)) < 1e-13
+
+
+def test_identity_updates_give_plain_correlator(oracle_mod):
+    # eps = 0 and no overrelaxation: every update returns the same link
+    L, T = 4, 4
+    g = oracle_mod.OracleLattice(L, T, 1.0, 5, eps=0.0)
+    th = g.get_links()
+    c, _, _ = g.multilevel([2], [5], 1, 0, [1, 2])
+    np.testing.assert_array_equal(g.get_links(), th)
+    for k, r in enumerate([1, 2]):
+        assert abs(c[k] - plain_corr(th, r)) < 1e-13
+
+
+@pytest.mark.parametrize("levels,rf", [(([2], [1]), [2]), (([4, 2], [1, 1]), [1, 2])])
+def test_field_single_update_reduces_to_plain_definition(oracle_mod, levels, rf):
+    L, T, beta = 4, 8, 1.0
+    g = oracle_mod.OracleLattice(L, T, beta, 23)
+    g.sweep(1, 1)
+    c, f, _ = g.multilevel(levels[0], levels[1], 1, 1, [1, 2], rf_list=rf)
+    th = g.get_links()
+    for i, r in enumerate(rf):
+        ref = field_identity(th, beta, r)
+        np.testing.assert_allclose(f[i], ref, atol=1e-13)
+
+
+def test_cold_lattice_field_vanishes(oracle_mod):
+    g = oracle_mod.OracleLattice(4, 4, 1.0, 1, hot=False, eps=0.0)
+    c, f, _ = g.multilevel([2], [3], 1, 0, [1, 2], rf_list=[2])
+    np.testing.assert_array_equal(c, [1.0, 1.0])
+    np.testing.assert_array_equal(f, np.zeros_like(f))
+
+
+def test_accept_log_length(oracle_mod):
+    L, T = 4, 4
+    g = oracle_mod.OracleLattice(L, T, 1.0, 1)
+    _, _, log = g.multilevel([4, 2], [2, 3], 1, 3, [1], log_cap=10 ** 6)
+    n_sweeps = 2 + 2 * 3
+    assert len(log) == n_sweeps * 8 * (g.V // 2)
+    assert g.pass_id == n_sweeps
+
+
+@pytest.mark.slow
+def test_multilevel_and_plain_estimators_agree(oracle_mod):
+    # Both estimate <P*(0) P(r)>; compare at r = 1 on 4^3 x 4, beta = 1.
+    L, T, beta = 4, 4, 1.0
+    g = oracle_mod.OracleLattice(L, T, beta, 2024)
+    for _ in range(30):
+        g.sweep(1, 3)
+    plain, ml = [], []
+    for _ in range(400):
+        g.sweep(1, 3)
+        plain.append(g.plain_correlator([1])[0].real)
+    for _ in range(100):
+        for _ in range(2):
+            g.sweep(1, 3)
+        c, _, _ = g.multilevel([2], [8], 1, 3, [1])
+        ml.append(c[0].real)
+    plain, ml = np.array(plain), np.array(ml)
+
+    def err(x, b):
+        n = len(x) // b
+        m = x[: n * b].reshape(n, b).mean(axis=1)
+        return m.std(ddof=1) / math.sqrt(n)
+
+    d = abs(plain.mean() - ml.mean())
+    e = math.hypot(err(plain, 20), err(ml, 5))
+    assert d < 4 * e, (plain.mean(), ml.mean(), e)
+    # the multilevel estimate is the less noisy one per unit of measurement
+    assert ml.std() < plain.std()
