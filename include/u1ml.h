@@ -1,0 +1,215 @@
+/*
+ * u1ml.h -- C ABI of the u1ml library: Luscher-Weisz multilevel Monte Carlo
+ * for compact U(1) lattice gauge theory in 3+1 dimensions on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: Amado, Cardoso, Cardoso, Bicudo, "Study of compact U(1) flux tubes
+ * in 3+1 dimensions in lattice gauge theory using GPU's" (arXiv:1208.0166):
+ * Wilson action Eq. (3), Metropolis + overrelaxation updates (Sec. 2.1), the
+ * two-level multilevel algorithm with frozen time-slab boundaries (Sec. 2.2),
+ * the Polyakov-loop correlator <P*(0)P(r)> estimated by products of slab
+ * averaged two-link operators (Eq. (8)), and the field operators
+ * a^2 F_munu = sqrt(beta) Im P_munu (Eq. (5)) inserted as in Eq. (9).
+ *
+ * Conventions shared by every call:
+ *  - Sites (t, x, y, z), 0 <= t < T, 0 <= x, y, z < L, periodic; direction
+ *    mu = 0 is time, mu = 1, 2, 3 are x, y, z.  Link angles theta in [-pi, pi).
+ *  - Host link arrays are FP64 in the natural order theta[t][z][y][x][mu]
+ *    (4 L^3 T doubles).  On the device links are stored per direction and
+ *    parity, links[mu][parity][site/2], with time slowest, as FP64 or FP32.
+ *  - Random numbers are Philox4x64-10 with key (seed, 0) and counter
+ *    (site, purpose<<32 | hit<<8 | mu, pass_id, 0); pass_id counts Metropolis
+ *    passes.  FP64 updates use only IEEE +,-,*,/ plus exp, so they are a fixed
+ *    function of (links, beta, eps, seed, pass_id) on any run.
+ *  - Every int-returning call returns U1ML_OK (0) or a negative error code;
+ *    u1ml_last_error() gives a message for the most recent failure on the
+ *    calling thread.  Handles are owned by the library, are not thread safe,
+ *    and distinct handles are independent.  Host pointers are only read or
+ *    written during the call; the library never keeps them.
+ *  - Work is queued on the stream given in the options (NULL = a stream the
+ *    library creates, at default priority, and destroys with the handle).
+ *    Calls that return host data synchronise that stream.
+ */
+#ifndef U1ML_H
+#define U1ML_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define U1ML_OK 0
+#define U1ML_EINVAL (-1)  /* bad argument: sizes, ranges, NULL handle */
+#define U1ML_ENOMEM (-2)  /* device or host allocation failed */
+#define U1ML_EDEVICE (-3) /* HIP runtime error (message kept for u1ml_last_error) */
+#define U1ML_ESTATE (-4)  /* call not valid in the current state */
+#define U1ML_EIO (-5)     /* checkpoint file error */
+
+#define U1ML_COLD 0 /* all links theta = 0 */
+#define U1ML_HOT 1  /* theta = pi (2u - 1), u from counter (site, 1<<32 | mu, 0, 0) */
+
+#define U1ML_FP64 0 /* FP64 angles, deterministic elementary functions */
+#define U1ML_FP32 1 /* FP32 angles, hardware transcendentals; FP64 measurements */
+
+#define U1ML_MAX_LEVELS 3
+#define U1ML_MAX_FIELD_R 8
+
+/* Field components of Eq. (5), in this order, in every field output. */
+#define U1ML_EX 0 /* sqrt(beta) Im P_01 */
+#define U1ML_EY 1 /* sqrt(beta) Im P_02 */
+#define U1ML_EZ 2 /* sqrt(beta) Im P_03 */
+#define U1ML_BX 3 /* sqrt(beta) Im P_23 */
+#define U1ML_BY 4 /* sqrt(beta) Im P_31 */
+#define U1ML_BZ 5 /* sqrt(beta) Im P_12 */
+
+typedef struct u1ml_options {
+    int start;        /* U1ML_COLD or U1ML_HOT (default HOT) */
+    int precision;    /* U1ML_FP64 or U1ML_FP32 (default FP64) */
+    double eps;       /* Metropolis proposal theta + eps * U(-1, 1) (default 1.0) */
+    void *stream;     /* hipStream_t to queue work on; NULL = a library-owned stream */
+    void *dev_buf;    /* optional caller device buffer for the links, or NULL */
+    size_t dev_bytes; /* its size; must be >= u1ml_link_bytes(L, T, precision) */
+    int block;        /* threads per block of the update kernels; 0 = tuned default */
+} u1ml_options;
+
+typedef struct u1ml_observables {
+    double plaquette;     /* (1/6V) sum_x sum_{mu<nu} cos theta_munu(x), Eq. (3) */
+    double poly_re;       /* Re of L^-3 sum_x P(x), P = prod_t U_0(x, t) */
+    double poly_im;       /* Im of the same */
+    double poly_abs;      /* its modulus */
+    double field_mean[6]; /* lattice averages <O_c> of the Eq. (5) operators (Eq. (7) subtraction) */
+} u1ml_observables;
+
+typedef struct u1ml_lattice u1ml_lattice;
+typedef struct u1ml_batch u1ml_batch;
+
+/* Fill *opt with the defaults above. */
+void u1ml_default_options(u1ml_options *opt);
+
+/* Bytes of device memory the links of an L^3 x T lattice take (4 L^3 T words
+ * of 8 (FP64) or 4 (FP32) bytes).  Pure function; 0 for invalid sizes. */
+size_t u1ml_link_bytes(int L, int T, int precision);
+
+/* Create a lattice (Sec. 2, Sec. 2.1): L, T even, 2 <= L, T <= 256,
+ * L^3 T / 2 * L < 2^32; beta >= 0 finite (beta = 1/g^2 of Eq. (3)).
+ * Starts cold or hot per opt (NULL = defaults) and sets pass_id = 0.
+ * If opt->dev_buf is given the links live there (the caller keeps ownership
+ * and must keep it alive until u1ml_destroy); otherwise the library allocates.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+int u1ml_init_lattice(int L, int T, double beta, uint64_t seed, const u1ml_options *opt, u1ml_lattice **out);
+
+/* One compound sweep (Sec. 2.1): a Metropolis pass with n_metro hits per link
+ * followed by n_or overrelaxation passes; each pass visits the checkerboard
+ * classes mu = 0..3 (outer), parity 0, 1 (inner).  pass_id += (n_metro > 0).
+ * n_metro, n_or >= 0.  Asynchronous. */
+int u1ml_sweep(u1ml_lattice *lat, int n_metro, int n_or);
+
+/* The multilevel algorithm (Sec. 2.2) for the Polyakov correlator and the
+ * field insertion of Eq. (9).
+ *   slab_sizes[n_levels]: time-slab thickness per level, outer to inner; each
+ *     divides T and the previous one (e.g. {4, 2}).  At a level of thickness
+ *     th the spatial links on time slices t = 0 (mod th) are frozen.
+ *   n_sub[n_levels]: compound sweeps (n_metro, n_or) per level iteration;
+ *     every iteration updates, then measures (inner level) or recurses.
+ *   r_list[n_r]: separations along x, 1 <= r < L.
+ *   rf_list[n_rf] (n_rf <= U1ML_MAX_FIELD_R, may be 0): separations for which the
+ *     field profile is measured; each must appear in r_list.  n_rf > 0
+ *     requires n_levels <= 2 and replays the whole update sequence once
+ *     (same random numbers), so it costs two multilevel runs.
+ * The chain continues from the updated links (no restore).  Results are
+ * kept on the device until u1ml_measure.  Asynchronous; EINVAL on bad sizes. */
+int u1ml_multilevel(u1ml_lattice *lat, int n_levels, const int *slab_sizes, const int *n_sub, int n_metro,
+                    int n_or, int n_r, const int *r_list, int n_rf, const int *rf_list);
+
+/* Measure the current links and return the latest multilevel results.
+ *   obs (may be NULL): plain observables of the current links.
+ *   correlator (may be NULL): [n_r][2] (Re, Im) of the last multilevel C(r);
+ *     ESTATE if no multilevel has run.
+ *   field_profile (may be NULL): [n_rf][2 planes][6 comps][L dy][L dz][2]
+ *     (Re, Im) of <P*(x0) P(x0 + r e_x) O_c(x0 + d)> with
+ *     d = (m, dy, dz), m = (r-1)/2 for plane 0 and r/2 for plane 1 (the two
+ *     lattice planes around the mid-point of the charges); ESTATE if the last
+ *     multilevel had n_rf = 0.
+ * Synchronises the stream.  Caller owns the host buffers. */
+int u1ml_measure(u1ml_lattice *lat, u1ml_observables *obs, double *correlator, double *field_profile);
+
+/* Plain (single configuration) correlator of the current links:
+ * out[2k], out[2k+1] = L^-3 sum_x P*(x) P(x + r_k e_x).  Synchronises. */
+int u1ml_plain_correlator(u1ml_lattice *lat, int n_r, const int *r_list, double *out);
+
+/* Copy links to / from a host FP64 array theta[t][z][y][x][mu] (4 L^3 T values).
+ * set_links: every value must be finite with |theta| <= 64 (EINVAL otherwise);
+ * values outside [-pi, pi) are folded back by the next update of that link;
+ * FP32 lattices round them.  Synchronises. */
+int u1ml_get_links(u1ml_lattice *lat, double *host);
+int u1ml_set_links(u1ml_lattice *lat, const double *host);
+
+/* Metropolis pass counter used as the third Philox counter word. */
+int u1ml_get_pass_id(u1ml_lattice *lat, uint64_t *pass_id);
+int u1ml_set_pass_id(u1ml_lattice *lat, uint64_t pass_id);
+
+/* Debug recording of Metropolis decisions.  flags & 1 enables a device log of
+ * capacity bytes: one byte per (class pass, half-site, hit) in launch order,
+ * 1 = accepted, 0 = rejected, 2 = frozen.  Passes that no longer fit are not
+ * recorded.  flags = 0 disables and frees it.  Recording forces one launch
+ * per class pass (no fused or captured schedule). */
+int u1ml_set_debug(u1ml_lattice *lat, unsigned flags, size_t capacity);
+/* Copy the log out: *n_bytes = bytes recorded; copies min(cap, *n_bytes). */
+int u1ml_get_accept_log(u1ml_lattice *lat, uint8_t *out, size_t cap, size_t *n_bytes);
+
+/* Checkpoint: a text header line (format, L, T, beta, eps, seed, pass_id,
+ * precision) then the FP64 links in the host order.  load requires a lattice
+ * of the same L, T, precision and restores links, beta, eps, seed, pass_id.
+ * EIO on file errors, EINVAL on a mismatch. */
+int u1ml_save(u1ml_lattice *lat, const char *path);
+int u1ml_load(u1ml_lattice *lat, const char *path);
+
+/* Wait for all queued work of the lattice. */
+int u1ml_synchronize(u1ml_lattice *lat);
+
+/* Free the lattice and everything the library allocated for it. */
+void u1ml_destroy(u1ml_lattice *lat);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent lattices of different L = T and beta updated by
+ * the same launches (one launch per class pass covers all of them).
+ * ------------------------------------------------------------------------- */
+
+/* n lattices, L[i] = T[i] sizes, beta[i], seed[i]; options as for one lattice
+ * (dev_buf is ignored; precision and start apply to all). */
+int u1ml_batch_create(int n, const int *L, const int *T, const double *beta, const uint64_t *seed,
+                      const u1ml_options *opt, u1ml_batch **out);
+/* One compound sweep of every lattice (th_frozen = 0). */
+int u1ml_batch_sweep(u1ml_batch *b, int n_metro, int n_or);
+/* One measurement cycle of every lattice: n_sweeps compound sweeps, then a
+ * single-level multilevel with slab thickness th and n_sub iterations, with
+ * correlators at r = 1 .. T_i/2 for lattice i.  With use_graph != 0 the
+ * whole cycle is captured once into a HIP graph and replayed on later calls
+ * with the same arguments.  Asynchronous. */
+int u1ml_batch_cycle(u1ml_batch *b, int n_sweeps, int n_metro, int n_or, int th, int n_sub, int use_graph);
+/* Results of lattice i: observables of its current links and (correlator may
+ * be NULL) [L_i/2][2] from the last cycle.  Synchronises. */
+int u1ml_batch_measure(u1ml_batch *b, int i, u1ml_observables *obs, double *correlator);
+int u1ml_batch_get_links(u1ml_batch *b, int i, double *host);
+int u1ml_batch_set_links(u1ml_batch *b, int i, const double *host);
+int u1ml_batch_synchronize(u1ml_batch *b);
+void u1ml_batch_destroy(u1ml_batch *b);
+
+/* Time the update kernels at each candidate block size on this lattice's
+ * shape and keep the fastest for it; *best_block receives it (may be NULL).
+ * Results are bitwise identical for every block size.  Leaves the links
+ * unchanged (they are saved and restored).  Synchronises. */
+int u1ml_autotune(u1ml_lattice *lat, int *best_block);
+
+/* Text for an error code. */
+const char *u1ml_strerror(int code);
+/* Message of the most recent failure on this thread ("" if none). */
+const char *u1ml_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* U1ML_H */

@@ -1,0 +1,88 @@
+// engine.h -- host-side interface between the C ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace u1ml {
+
+enum Precision { kFP64 = 0, kFP32 = 1 };
+enum UpdateKind { kMetropolis = 0, kOverrelax = 1 };
+
+// Blocks of a batched launch: blocks[b] = {lattice, first item of the block}.
+struct BlockTable {
+  const int2* dev = nullptr;
+  int n_blocks = 0;
+  int block = 0;
+};
+
+// --- link updates (sweep_f64.hip, sweep_f32.hip) ---
+hipError_t launch_init_f64(double* links, const LatDesc* lats, BlockTable bt, int hot, hipStream_t st);
+hipError_t launch_init_f32(float* links, const LatDesc* lats, BlockTable bt, int hot, hipStream_t st);
+hipError_t launch_class_pass_f64(int kind, double* links, const LatDesc* lats, BlockTable bt, int mu, int parity,
+                                 int th_frozen, int n_hits, const uint64_t* pass_ids, uint8_t* log,
+                                 hipStream_t st);
+hipError_t launch_class_pass_f32(int kind, float* links, const LatDesc* lats, BlockTable bt, int mu, int parity,
+                                 int th_frozen, int n_hits, const uint64_t* pass_ids, uint8_t* log,
+                                 hipStream_t st);
+hipError_t launch_bump_pass_ids(uint64_t* pass_ids, int n, hipStream_t st);
+
+// --- measurements (measure.hip); prec selects the link element type ---
+// Per-lattice multilevel workspace layout (offsets in elements of the
+// corresponding buffer).
+constexpr int kMaxLevels = 3;
+struct MLDesc {
+  uint64_t ell;                  // doubles: [n_inner][ns_inner][L3] slab time-line angle sums
+  uint64_t acc[kMaxLevels + 1];  // double2: level l < inner: [ns_l][L3][nR]; index n_levels = top [L3][nR]
+  int ns[kMaxLevels];            // slabs per level
+  int nR;                        // separations
+  int r_off;                     // r values at rvals[r_off ...]
+};
+
+// plaquette sum and field sums: partial[blk][7] then final[7] per lattice
+hipError_t launch_plaq_field(int prec, const void* links, const LatDesc* lats, BlockTable bt, double* partial,
+                             hipStream_t st);
+// reduce per-lattice ranges of 'width'-wide partial rows: out[lat][width]
+hipError_t launch_reduce_rows(const double* partial, int width, const int* lat_row_begin, int n_lats,
+                              double* out, hipStream_t st);
+// Polyakov loop angles poly[lat_off + x3] = sum_t theta_0(x3, t)
+hipError_t launch_poly_lines(int prec, const void* links, const LatDesc* lats, BlockTable bt,
+                             const uint64_t* poly_off, double* poly, hipStream_t st);
+// per-block partials of P (re, im) and of P*(x)P(x + r e_x) for the r list
+// one row per spatial site: {cos P, sin P, (Re, Im) of P*(x)P(x + r e_x) per r}
+hipError_t launch_poly_corr(const LatDesc* lats, BlockTable bt, const uint64_t* poly_off, const double* poly,
+                            const int* rvals, int nR, const int* row_begin, double* rows, hipStream_t st);
+
+// multilevel
+hipError_t launch_ml_lines(int prec, const void* links, const LatDesc* lats, const MLDesc* mls, BlockTable bt,
+                           int inner_th, int sample, double* mlbuf, hipStream_t st);
+hipError_t launch_ml_fold(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int child_level, int parent_level,
+                          int n_levels, int child_is_inner, int n_child, const int* rvals, const double* mlbuf,
+                          double2* accbuf, hipStream_t st);
+hipError_t launch_ml_zero(double2* accbuf, uint64_t n, hipStream_t st);
+hipError_t launch_ml_final(const LatDesc* lats, const MLDesc* mls, int n_lats, int max_r, int top_level,
+                           const double2* accbuf, double* out, hipStream_t st);
+
+// field insertion by replay (single lattice)
+struct FieldDesc {
+  int n_rf;
+  int rf[8];      // field separations
+  int rf_k[8];    // index of each rf in the correlator r list
+  int n_levels;   // 1 or 2
+  int n_outer;    // n_0 for two levels (1 for one level)
+  int n_inner;    // samples per inner run
+  int ns_inner;   // inner slabs
+  int children;   // inner slabs per top slab (two levels) or ns_inner (one level)
+  int th_inner;
+};
+hipError_t launch_field_store_tavg(const LatDesc* lat, const MLDesc* ml, FieldDesc fd, int L3, int m,
+                                   const double* mlbuf, double2* tavg, hipStream_t st);
+hipError_t launch_field_weights(const LatDesc* lat, const MLDesc* ml, FieldDesc fd, int L3, const double2* tavg,
+                                const double2* accbuf, double2* w, hipStream_t st);
+hipError_t launch_field_sample(int prec, const void* links, const LatDesc* lat, const MLDesc* ml, FieldDesc fd,
+                               int L, int m, int sample, const double* mlbuf, const double2* w, double* oslab,
+                               double2* wslab, double2* fout, hipStream_t st);
+
+}  // namespace u1ml

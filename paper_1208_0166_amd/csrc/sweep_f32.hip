@@ -1,0 +1,27 @@
+// sweep_f32.hip -- FP32 link updates with hardware transcendentals.
+#include "engine.h"
+#include "sweep_impl.h"
+
+namespace u1ml {
+
+hipError_t launch_init_f32(float* links, const LatDesc* lats, BlockTable bt, int hot, hipStream_t st) {
+  if (bt.n_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(init_links_kernel<Fast32>, dim3(bt.n_blocks), dim3(bt.block), 0, st, links, lats, bt.dev,
+                     hot);
+  return hipGetLastError();
+}
+
+hipError_t launch_class_pass_f32(int kind, float* links, const LatDesc* lats, BlockTable bt, int mu, int parity,
+                                 int th_frozen, int n_hits, const uint64_t* pass_ids, uint8_t* log,
+                                 hipStream_t st) {
+  if (bt.n_blocks == 0) return hipSuccess;
+  if (kind == kMetropolis)
+    hipLaunchKernelGGL((class_pass_kernel<Fast32, 0>), dim3(bt.n_blocks), dim3(bt.block), 0, st, links, lats,
+                       bt.dev, mu, parity, th_frozen, n_hits, pass_ids, log);
+  else
+    hipLaunchKernelGGL((class_pass_kernel<Fast32, 1>), dim3(bt.n_blocks), dim3(bt.block), 0, st, links, lats,
+                       bt.dev, mu, parity, th_frozen, n_hits, pass_ids, log);
+  return hipGetLastError();
+}
+
+}  // namespace u1ml

@@ -1,0 +1,38 @@
+// sweep_f64.hip -- FP64 link updates with deterministic elementary functions.
+// Built with -ffp-contract=off: every floating-point step is one IEEE-754
+// operation in source order, so the update sequence is reproducible.
+#include "engine.h"
+#include "sweep_impl.h"
+
+namespace u1ml {
+
+hipError_t launch_init_f64(double* links, const LatDesc* lats, BlockTable bt, int hot, hipStream_t st) {
+  if (bt.n_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(init_links_kernel<Det64>, dim3(bt.n_blocks), dim3(bt.block), 0, st, links, lats, bt.dev, hot);
+  return hipGetLastError();
+}
+
+hipError_t launch_class_pass_f64(int kind, double* links, const LatDesc* lats, BlockTable bt, int mu, int parity,
+                                 int th_frozen, int n_hits, const uint64_t* pass_ids, uint8_t* log,
+                                 hipStream_t st) {
+  if (bt.n_blocks == 0) return hipSuccess;
+  if (kind == kMetropolis)
+    hipLaunchKernelGGL((class_pass_kernel<Det64, 0>), dim3(bt.n_blocks), dim3(bt.block), 0, st, links, lats,
+                       bt.dev, mu, parity, th_frozen, n_hits, pass_ids, log);
+  else
+    hipLaunchKernelGGL((class_pass_kernel<Det64, 1>), dim3(bt.n_blocks), dim3(bt.block), 0, st, links, lats,
+                       bt.dev, mu, parity, th_frozen, n_hits, pass_ids, log);
+  return hipGetLastError();
+}
+
+__global__ void bump_pass_ids_kernel(uint64_t* pass_ids, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) pass_ids[i] += 1;
+}
+
+hipError_t launch_bump_pass_ids(uint64_t* pass_ids, int n, hipStream_t st) {
+  hipLaunchKernelGGL(bump_pass_ids_kernel, dim3((n + 63) / 64), dim3(64), 0, st, pass_ids, n);
+  return hipGetLastError();
+}
+
+}  // namespace u1ml

@@ -1,0 +1,63 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function the header declares, and rejects bad arguments before touching
+the device."""
+import ctypes as C
+import os
+
+import pytest
+
+from paper_1208_0166_amd import u1ml
+
+pytestmark = pytest.mark.skipif(not os.path.exists(u1ml.LIB_PATH), reason="libu1ml.so not built")
+
+
+def test_every_declared_function_is_exported():
+    lib = u1ml.load_library()
+    names = u1ml.header_functions()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_link_bytes_and_defaults():
+    assert u1ml.link_bytes(24, 24, u1ml.FP64) == 4 * 24 ** 4 * 8
+    assert u1ml.link_bytes(24, 24, u1ml.FP32) == 4 * 24 ** 4 * 4
+    assert u1ml.link_bytes(3, 4, u1ml.FP64) == 0
+    assert u1ml.link_bytes(4, 4, 7) == 0
+    o = u1ml.default_options()
+    assert (o.start, o.precision, o.eps, o.block) == (u1ml.HOT, u1ml.FP64, 1.0, 0)
+
+
+def test_strerror_codes():
+    lib = u1ml.load_library()
+    for code in (0, -1, -2, -3, -4, -5, -99):
+        assert lib.u1ml_strerror(code)
+
+
+@pytest.mark.parametrize("L,T,beta,prec,eps,block", [
+    (3, 4, 1.0, 0, 1.0, 0),      # odd L
+    (4, 2 * 200, 1.0, 0, 1.0, 0),  # T too large
+    (0, 4, 1.0, 0, 1.0, 0),
+    (4, 4, -1.0, 0, 1.0, 0),     # negative beta
+    (4, 4, float("nan"), 0, 1.0, 0),
+    (4, 4, 1.0, 5, 1.0, 0),      # precision
+    (4, 4, 1.0, 0, -1.0, 0),     # eps
+    (4, 4, 1.0, 0, 1.0, 100),    # block not a multiple of 64
+])
+def test_init_rejects_bad_arguments(L, T, beta, prec, eps, block):
+    lib = u1ml.load_library()
+    o = u1ml.default_options()
+    o.precision, o.eps, o.block = prec, eps, block
+    h = C.c_void_p()
+    assert lib.u1ml_init_lattice(L, T, beta, 1, C.byref(o), C.byref(h)) == u1ml.EINVAL
+    assert not h.value
+    assert lib.u1ml_last_error()
+
+
+def test_null_handles_rejected():
+    lib = u1ml.load_library()
+    assert lib.u1ml_sweep(None, 1, 3) == u1ml.EINVAL
+    assert lib.u1ml_measure(None, None, None, None) == u1ml.EINVAL
+    assert lib.u1ml_init_lattice(4, 4, 1.0, 1, None, None) == u1ml.EINVAL
+    lib.u1ml_destroy(None)
+    lib.u1ml_batch_destroy(None)

@@ -1,0 +1,94 @@
+"""GPU multilevel estimators against the oracle: two levels, field insertion
+(Eq. (9)) evaluated by replay, and full-size properties at 24^4."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1208_0166_amd import u1ml
+from tests.test_oracle_multilevel import field_identity, plain_corr
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def close_rel(a, b, rel=1e-12):
+    scale = max(np.abs(b).max(), 1e-300)
+    assert np.abs(a - b).max() <= rel * scale, (np.abs(a - b).max(), scale)
+
+
+@pytest.mark.parametrize("levels,n_sub,L,T", [
+    ([4, 2], [3, 4], 4, 8),
+    ([2], [5], 4, 4),
+    ([6, 2], [2, 3], 4, 6),
+    ([4, 2, 1], [2, 2, 2], 4, 8),
+])
+def test_multilevel_correlator_and_field_parity(oracle_mod, levels, n_sub, L, T):
+    r_list = [1, 2, 3]
+    rf = [2, 3] if len(levels) <= 2 else []
+    say(f"[gpu] multilevel parity levels={levels} n={n_sub} L={L} T={T}")
+    o = oracle_mod.OracleLattice(L, T, 1.0, 5, hot=True)
+    g = u1ml.init_lattice(L, T, 1.0, 5)
+    for _ in range(2):
+        o.sweep(1, 3)
+        u1ml.sweep(g, 1, 3)
+    c_o, f_o, _ = o.multilevel(levels, n_sub, 1, 3, r_list, rf_list=rf)
+    u1ml.multilevel(g, levels, n_sub, 1, 3, r_list, rf_list=rf)
+    _, c_g, f_g = u1ml.measure(g, observables=False, correlator=True, field_profile=bool(rf))
+    np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
+    close_rel(c_g, c_o)
+    if rf:
+        assert f_g.shape == f_o.shape
+        close_rel(f_g, f_o)
+
+
+def test_multilevel_fp32_matches_identity_at_one_update():
+    # with one update per level the estimators reduce to the plain
+    # definitions on the final links, for the FP32 path as well
+    L, T = 6, 8
+    g = u1ml.init_lattice(L, T, 1.0, 8, precision=u1ml.FP32)
+    u1ml.sweep(g, 1, 3)
+    u1ml.multilevel(g, [4, 2], [1, 1], 1, 3, [1, 2, 3], rf_list=[2])
+    _, c, f = u1ml.measure(g, observables=False, correlator=True, field_profile=True)
+    th = u1ml.get_links(g)
+    ref = np.array([plain_corr(th, r) for r in (1, 2, 3)])
+    np.testing.assert_allclose(c, ref, atol=1e-12)
+    np.testing.assert_allclose(f[0], field_identity(th, 1.0, 2), atol=1e-12)
+
+
+@pytest.mark.parametrize("prec", [u1ml.FP64, u1ml.FP32])
+def test_full_size_24_identity_and_plain_observables(oracle_mod, prec):
+    # 24^4 in the configuration of the benchmark: after one update per level
+    # the multilevel correlator for r = 1..12 equals the plain correlator of
+    # the final links, and the field at r = 2 the plain Eq. (9) definition.
+    L = T = 24
+    say(f"[gpu] 24^4 identity prec={prec}")
+    g = u1ml.init_lattice(L, T, 1.0, 3, precision=prec, start=u1ml.COLD)
+    for _ in range(3):
+        u1ml.sweep(g, 1, 3)
+    rl = list(range(1, 13))
+    u1ml.multilevel(g, [4, 2], [1, 1], 1, 3, rl, rf_list=[2])
+    obs, c, f = u1ml.measure(g, correlator=True, field_profile=True)
+    th = u1ml.get_links(g)
+    np.testing.assert_allclose(c, [plain_corr(th, r) for r in rl], atol=1e-12)
+    np.testing.assert_allclose(f[0], field_identity(th, 1.0, 2), atol=1e-12)
+    o = oracle_mod.OracleLattice(L, T, 1.0, 3, hot=False)
+    o.set_links(th)
+    assert abs(obs["plaquette"] - o.plaquette()) < 1e-12
+    p = o.polyakov()
+    assert abs(obs["poly"] - complex(p[0], p[1])) < 1e-12
+
+
+def test_full_size_24_sweep_bit_exact(oracle_mod):
+    # one compound sweep of the 24^4 lattice from a hot start, FP64 path
+    L = T = 24
+    say("[gpu] 24^4 FP64 sweep vs oracle")
+    o = oracle_mod.OracleLattice(L, T, 1.0, 2, hot=True)
+    g = u1ml.init_lattice(L, T, 1.0, 2)
+    o.sweep(1, 3)
+    u1ml.sweep(g, 1, 3)
+    np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
