@@ -17,10 +17,13 @@
  *  - Host link arrays are FP64 in the natural order theta[t][z][y][x][mu]
  *    (4 L^3 T doubles).  On the device links are stored per direction and
  *    parity, links[mu][parity][site/2], with time slowest, as FP64 or FP32.
- *  - Random numbers are Philox4x64-10 with key (seed, 0) and counter
- *    (site, purpose<<32 | hit<<8 | mu, pass_id, 0); pass_id counts Metropolis
- *    passes.  FP64 updates use only IEEE +,-,*,/ plus exp, so they are a fixed
- *    function of (links, beta, eps, seed, pass_id) on any run.
+ *  - Random numbers (Salmon et al., SC'11): the FP64 path draws Philox4x64-10
+ *    with key (seed, 0) and counter (site, purpose<<32 | hit<<8 | mu,
+ *    pass_id, 0); the FP32 path draws Philox4x32-10 with key (seed low, seed
+ *    high) and counter (site, 2<<16 | hit<<8 | mu, pass_id low, pass_id high).
+ *    pass_id counts Metropolis passes.  FP64 updates use only IEEE +,-,*,/
+ *    plus exp, so they are a fixed function of (links, beta, eps, seed,
+ *    pass_id) on any run; FP32 results do not depend on launch geometry.
  *  - Every int-returning call returns U1ML_OK (0) or a negative error code;
  *    u1ml_last_error() gives a message for the most recent failure on the
  *    calling thread.  Handles are owned by the library, are not thread safe,
@@ -72,6 +75,9 @@ typedef struct u1ml_options {
     void *dev_buf;    /* optional caller device buffer for the links, or NULL */
     size_t dev_bytes; /* its size; must be >= u1ml_link_bytes(L, T, precision) */
     int block;        /* threads per block of the update kernels; 0 = tuned default */
+    int no_graphs;    /* 0 (default): repeated sweep / multilevel calls with the same
+                         arguments replay a HIP graph captured on the first call;
+                         1: always launch kernel by kernel */
 } u1ml_options;
 
 typedef struct u1ml_observables {
@@ -116,8 +122,9 @@ int u1ml_sweep(u1ml_lattice *lat, int n_metro, int n_or);
  *   r_list[n_r]: separations along x, 1 <= r < L.
  *   rf_list[n_rf] (n_rf <= U1ML_MAX_FIELD_R, may be 0): separations for which the
  *     field profile is measured; each must appear in r_list.  n_rf > 0
- *     requires n_levels <= 2 and replays the whole update sequence once
- *     (same random numbers), so it costs two multilevel runs.
+ *     requires n_levels <= 2 and L <= 62; every inner sample's time-line sums and field
+ *     slab sums are then kept in device memory (56 (T/th_inner) L^3 bytes
+ *     per sample) and contracted with the final weights at the end.
  * The chain continues from the updated links (no restore).  Results are
  * kept on the device until u1ml_measure.  Asynchronous; EINVAL on bad sizes. */
 int u1ml_multilevel(u1ml_lattice *lat, int n_levels, const int *slab_sizes, const int *n_sub, int n_metro,
@@ -183,15 +190,21 @@ int u1ml_batch_create(int n, const int *L, const int *T, const double *beta, con
                       const u1ml_options *opt, u1ml_batch **out);
 /* One compound sweep of every lattice (th_frozen = 0). */
 int u1ml_batch_sweep(u1ml_batch *b, int n_metro, int n_or);
+/* The multilevel algorithm of u1ml_multilevel on every lattice of the batch
+ * at once (same levels, updates and r lists; every r < L of every lattice). */
+int u1ml_batch_multilevel(u1ml_batch *b, int n_levels, const int *slab_sizes, const int *n_sub, int n_metro,
+                          int n_or, int n_r, const int *r_list, int n_rf, const int *rf_list);
 /* One measurement cycle of every lattice: n_sweeps compound sweeps, then a
  * single-level multilevel with slab thickness th and n_sub iterations, with
  * correlators at r = 1 .. T_i/2 for lattice i.  With use_graph != 0 the
  * whole cycle is captured once into a HIP graph and replayed on later calls
  * with the same arguments.  Asynchronous. */
 int u1ml_batch_cycle(u1ml_batch *b, int n_sweeps, int n_metro, int n_or, int th, int n_sub, int use_graph);
-/* Results of lattice i: observables of its current links and (correlator may
- * be NULL) [L_i/2][2] from the last cycle.  Synchronises. */
-int u1ml_batch_measure(u1ml_batch *b, int i, u1ml_observables *obs, double *correlator);
+/* Results of lattice i as in u1ml_measure: observables of its current links,
+ * correlator [n_r][2] of the last cycle or batch multilevel (r = 1..T_i/2
+ * after a cycle), field_profile as in u1ml_measure.  NULL pointers skip.
+ * Synchronises. */
+int u1ml_batch_measure(u1ml_batch *b, int i, u1ml_observables *obs, double *correlator, double *field_profile);
 int u1ml_batch_get_links(u1ml_batch *b, int i, double *host);
 int u1ml_batch_set_links(u1ml_batch *b, int i, const double *host);
 int u1ml_batch_synchronize(u1ml_batch *b);
@@ -202,6 +215,13 @@ void u1ml_batch_destroy(u1ml_batch *b);
  * Results are bitwise identical for every block size.  Leaves the links
  * unchanged (they are saved and restored).  Synchronises. */
 int u1ml_autotune(u1ml_lattice *lat, int *best_block);
+
+/* Run n_sweeps compound sweeps (n_metro, n_or) like u1ml_sweep, recording a
+ * HIP event pair on the lattice's stream around every class-pass kernel, and
+ * return the average kernel duration in microseconds: avg_us[0] over the
+ * Metropolis class passes, avg_us[1] over the overrelaxation ones (0 if none
+ * ran).  The sweeps are real updates of the chain.  Synchronises. */
+int u1ml_profile_sweeps(u1ml_lattice *lat, int n_sweeps, int n_metro, int n_or, double *avg_us);
 
 /* Text for an error code. */
 const char *u1ml_strerror(int code);

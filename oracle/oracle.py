@@ -48,6 +48,7 @@ def _load():
         "or_create": (P, [C.c_int, C.c_int, C.c_double, C.c_double, C.c_uint64, C.c_int]),
         "or_destroy": (None, [P]),
         "or_volume": (C.c_long, [P]),
+        "or_max_threads": (C.c_int, []),
         "or_get_pass_id": (C.c_uint64, [P]),
         "or_set_pass_id": (None, [P, C.c_uint64]),
         "or_set_beta": (None, [P, C.c_double]),
@@ -97,6 +98,10 @@ def philox4x64_10(ctr, key):
     p = C.POINTER(C.c_uint64)
     lib.or_philox4x64_10(c.ctypes.data_as(p), k.ctypes.data_as(p), out.ctypes.data_as(p))
     return out
+
+
+def max_threads() -> int:
+    return int(_load().or_max_threads())
 
 
 def sincos(x: float):

@@ -242,6 +242,17 @@ void or_destroy(or_lat *g)
 }
 
 long or_volume(const or_lat *g) { return g->V; }
+
+/* threads the OpenMP loops of the oracle use */
+int or_max_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 uint64_t or_get_pass_id(const or_lat *g) { return g->pass_id; }
 void or_set_pass_id(or_lat *g, uint64_t p) { g->pass_id = p; }
 void or_set_beta(or_lat *g, double beta) { g->beta = beta; }

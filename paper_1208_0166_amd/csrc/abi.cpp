@@ -1,12 +1,11 @@
 // abi.cpp -- the u1ml C ABI: lattice and batch handles, the update schedule
-// (compound sweeps, multilevel nesting, field replay), measurements,
-// checkpoints and the block-size autotuner.  Host code only; all lattice
-// arithmetic runs in the kernels of sweep_f64.hip, sweep_f32.hip and
-// measure.hip.
+// (compound sweeps, multilevel nesting, field insertion), measurements,
+// checkpoints, HIP-graph replay and the block-size autotuner.  Host code
+// only; all lattice arithmetic runs in the kernels of sweep_f64.hip,
+// sweep_f32.hip and measure.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -29,17 +28,35 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
-#define U1_HIP(expr)                                                                            \
-  do {                                                                                          \
-    hipError_t e_ = (expr);                                                                     \
+#define U1_HIP(expr)                                                                                      \
+  do {                                                                                                    \
+    hipError_t e_ = (expr);                                                                               \
     if (e_ != hipSuccess) return fail(U1ML_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+#define U1_TRY(expr)     \
+  do {                   \
+    int rc_ = (expr);    \
+    if (rc_) return rc_; \
+  } while (0)
+
+// largest |theta| accepted from the host; the updates fold angles back into
+// [-pi, pi) by whole periods, which needs them to be of moderate size
+constexpr double kMaxAngle = 64.0;
+// scratch for the field contraction, per engine
+constexpr size_t kFieldScratchBytes = 256u << 20;
+constexpr size_t kMaxGraphs = 16;
+// the mediator-plane transform keeps (L + L^2) complex values in 64 KiB of LDS
+constexpr int kMaxFieldL = 62;
 
 // device buffer that only grows
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   bool owned = true;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() {
     if (p && owned) (void)hipFree(p);
   }
@@ -64,10 +81,6 @@ struct DevBuf {
   }
 };
 
-// largest |theta| accepted from the host; the updates fold angles back into
-// [-pi, pi) by whole periods, which needs them to be of moderate size
-constexpr double kMaxAngle = 64.0;
-
 struct Table {
   DevBuf buf;
   int n_blocks = 0;
@@ -76,7 +89,9 @@ struct Table {
 };
 
 struct MLState {
-  bool valid = false;  // a multilevel has completed
+  bool valid = false;        // a multilevel has completed
+  bool field_valid = false;  // ... with the field insertion
+  std::vector<long long> key;
   int n_levels = 0;
   int th[U1ML_MAX_LEVELS] = {0, 0, 0};
   int n[U1ML_MAX_LEVELS] = {0, 0, 0};
@@ -86,12 +101,18 @@ struct MLState {
   std::vector<MLDesc> h_mls;  // per lattice
   DevBuf mls, rvals, mlbuf, accbuf, corr;
   uint64_t acc_elems = 0;
-  // field insertion (single lattice)
+  // field insertion
   bool field = false;
-  bool field_valid = false;
-  FieldDesc fd{};
-  DevBuf tavg, w, oslab, wslab, fout, snap_links, fd_dev;
-  int replay = 0;  // 1 while replaying
+  FieldParams fp{};
+  std::vector<FieldLat> h_fls;
+  std::vector<uint64_t> fout_off;  // per lattice, double2 elements
+  DevBuf fls, fbuf, fout, scratch;
+  size_t scratch_elems = 0;
+};
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  int metro_passes = 0;
 };
 
 }  // namespace
@@ -100,8 +121,8 @@ struct Engine {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  bool use_graphs = true;
   int prec = U1ML_FP64;
-  int start = U1ML_HOT;
   int block = 256;
   int n_lats = 0;
   std::vector<LatDesc> h_lats;
@@ -118,17 +139,21 @@ struct Engine {
   // measurement scratch
   DevBuf partial, rows, poly, poly_off, row_begin, red_out, rvals_tmp;
   MLState ml;
-  // batch cycle graph
-  hipGraphExec_t graph_exec = nullptr;
-  std::vector<int> graph_key;
-  int graph_metro_passes = 0;
+  // captured launch sequences
+  std::map<std::vector<long long>, GraphEntry> graphs;
+  bool capturing = false;
+  // optional per-kernel timing (u1ml_profile_sweeps)
+  std::vector<std::pair<hipEvent_t, hipEvent_t>>* prof[2] = {nullptr, nullptr};
 
   ~Engine() {
-    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
-    if (own_stream && stream) {
-      (void)hipStreamSynchronize(stream);
-      (void)hipStreamDestroy(stream);
-    }
+    if (stream) (void)hipStreamSynchronize(stream);
+    drop_graphs();
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+
+  void drop_graphs() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second.exec);
+    graphs.clear();
   }
 
   size_t elem_size() const { return prec == U1ML_FP64 ? 8 : 4; }
@@ -138,7 +163,7 @@ struct Engine {
     return U1ML_OK;
   }
 
-  // block table for per-lattice item counts
+  // block table for per-lattice item counts (built once, reused)
   int table(const std::vector<int>& items, int blk, Table** out) {
     auto key = std::make_pair(items, blk);
     auto it = tables.find(key);
@@ -146,6 +171,7 @@ struct Engine {
       *out = it->second.get();
       return U1ML_OK;
     }
+    if (capturing) return fail(U1ML_ESTATE, "internal: block table built during graph capture");
     std::unique_ptr<Table> t(new Table());
     std::vector<int2> h;
     t->lat_block_begin.push_back(0);
@@ -156,8 +182,7 @@ struct Engine {
     t->n_blocks = (int)h.size();
     t->block = blk;
     if (!h.empty()) {
-      int rc = t->buf.ensure(h.size() * sizeof(int2));
-      if (rc) return rc;
+      U1_TRY(t->buf.ensure(h.size() * sizeof(int2)));
       U1_HIP(hipMemcpy(t->buf.p, h.data(), h.size() * sizeof(int2), hipMemcpyHostToDevice));
     }
     *out = t.get();
@@ -173,28 +198,46 @@ struct Engine {
     return b;
   }
 
-  std::vector<int> items_half() const {
-    std::vector<int> v;
-    for (auto& d : h_lats) v.push_back(d.V2);
-    return v;
-  }
-
   // --- updates ---
   int class_pass(int kind, int mu, int parity, int th_frozen, int n_hits, uint8_t* logp) {
-    Table* t;
-    int rc = table(items_half(), block, &t);
-    if (rc) return rc;
     hipError_t e;
-    if (prec == U1ML_FP64)
-      e = launch_class_pass_f64(kind, links.as<double>(), lats.as<LatDesc>(), bt(t), mu, parity, th_frozen, n_hits,
-                                pass_ids.as<uint64_t>(), logp, stream);
-    else
-      e = launch_class_pass_f32(kind, links.as<float>(), lats.as<LatDesc>(), bt(t), mu, parity, th_frozen, n_hits,
-                                pass_ids.as<uint64_t>(), logp, stream);
+    if (n_lats == 1) {
+      if (prec == U1ML_FP64)
+        e = launch_class_pass_f64(kind, links.as<double>(), h_lats[0], block, mu, parity, th_frozen, n_hits,
+                                  pass_ids.as<uint64_t>(), logp, stream);
+      else
+        e = launch_class_pass_f32(kind, links.as<float>(), h_lats[0], block, mu, parity, th_frozen, n_hits,
+                                  pass_ids.as<uint64_t>(), logp, stream);
+    } else {
+      std::vector<int> items;
+      for (auto& d : h_lats) items.push_back(free_sites(d.L, d.T, mu, th_frozen));
+      Table* t;
+      U1_TRY(table(items, block, &t));
+      if (prec == U1ML_FP64)
+        e = launch_class_pass_batch_f64(kind, links.as<double>(), lats.as<LatDesc>(), bt(t), mu, parity, th_frozen,
+                                        n_hits, pass_ids.as<uint64_t>(), stream);
+      else
+        e = launch_class_pass_batch_f32(kind, links.as<float>(), lats.as<LatDesc>(), bt(t), mu, parity, th_frozen,
+                                        n_hits, pass_ids.as<uint64_t>(), stream);
+    }
     U1_HIP(e);
     return U1ML_OK;
   }
 
+  int timed_class_pass(int kind, int mu, int parity, int th_frozen, int n_hits, uint8_t* logp) {
+    if (!prof[kind]) return class_pass(kind, mu, parity, th_frozen, n_hits, logp);
+    hipEvent_t a, z;
+    U1_HIP(hipEventCreate(&a));
+    U1_HIP(hipEventCreate(&z));
+    prof[kind]->push_back(std::make_pair(a, z));
+    U1_HIP(hipEventRecord(a, stream));
+    int rc = class_pass(kind, mu, parity, th_frozen, n_hits, logp);
+    U1_HIP(hipEventRecord(z, stream));
+    return rc;
+  }
+
+  // Compound sweep (Sec. 2.1): Metropolis pass then n_or OR passes, classes
+  // mu = 0..3 outer, parity inner.
   int sweep(int n_metro, int n_or, int th_frozen) {
     if (n_metro > 0) {
       for (int mu = 0; mu < 4; ++mu)
@@ -207,18 +250,54 @@ struct Engine {
               log_used += want;
             }
           }
-          int rc = class_pass(kMetropolis, mu, p, th_frozen, n_metro, lp);
-          if (rc) return rc;
+          U1_TRY(timed_class_pass(kMetropolis, mu, p, th_frozen, n_metro, lp));
         }
       U1_HIP(launch_bump_pass_ids(pass_ids.as<uint64_t>(), n_lats, stream));
       for (auto& v : h_pass_ids) v += 1;
     }
     for (int k = 0; k < n_or; ++k)
       for (int mu = 0; mu < 4; ++mu)
-        for (int p = 0; p < 2; ++p) {
-          int rc = class_pass(kOverrelax, mu, p, th_frozen, 0, nullptr);
-          if (rc) return rc;
-        }
+        for (int p = 0; p < 2; ++p) U1_TRY(timed_class_pass(kOverrelax, mu, p, th_frozen, 0, nullptr));
+    return U1ML_OK;
+  }
+
+  // Run fn, or replay the graph captured for key.  The first call runs fn
+  // eagerly (allocating whatever it needs) and then captures a second copy
+  // of the same launch sequence for later calls.
+  template <class Fn>
+  int run_captured(const std::vector<long long>& key, Fn fn) {
+    const bool can = use_graphs && !debug && !prof[0] && !prof[1];
+    if (can) {
+      auto it = graphs.find(key);
+      if (it != graphs.end()) {
+        U1_HIP(hipGraphLaunch(it->second.exec, stream));
+        for (auto& v : h_pass_ids) v += it->second.metro_passes;
+        return U1ML_OK;
+      }
+    }
+    U1_TRY(fn());
+    if (!can) return U1ML_OK;
+    if (graphs.size() >= kMaxGraphs) drop_graphs();
+    const std::vector<uint64_t> ids = h_pass_ids;
+    hipGraph_t g;
+    U1_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    capturing = true;
+    int rc = fn();
+    capturing = false;
+    hipError_t ce = hipStreamEndCapture(stream, &g);
+    const int passes = (int)(h_pass_ids[0] - ids[0]);
+    h_pass_ids = ids;  // capturing ran nothing
+    if (rc) {
+      if (ce == hipSuccess) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (ce != hipSuccess) return fail(U1ML_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+    GraphEntry ge;
+    hipError_t ie = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(U1ML_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    ge.metro_passes = passes;
+    graphs[key] = ge;
     return U1ML_OK;
   }
 
@@ -226,8 +305,7 @@ struct Engine {
     std::vector<int> items;
     for (auto& d : h_lats) items.push_back(8 * d.V2);
     Table* t;
-    int rc = table(items, 256, &t);
-    if (rc) return rc;
+    U1_TRY(table(items, 256, &t));
     hipError_t e = prec == U1ML_FP64 ? launch_init_f64(links.as<double>(), lats.as<LatDesc>(), bt(t), hot, stream)
                                      : launch_init_f32(links.as<float>(), lats.as<LatDesc>(), bt(t), hot, stream);
     U1_HIP(e);
@@ -235,12 +313,31 @@ struct Engine {
   }
 
   int upload_pass_ids() {
-    U1_HIP(hipMemcpyAsync(pass_ids.p, h_pass_ids.data(), n_lats * sizeof(uint64_t), hipMemcpyHostToDevice, stream));
     U1_HIP(hipStreamSynchronize(stream));
+    U1_HIP(hipMemcpy(pass_ids.p, h_pass_ids.data(), n_lats * sizeof(uint64_t), hipMemcpyHostToDevice));
+    return U1ML_OK;
+  }
+
+  int upload_lats() {
+    U1_HIP(hipStreamSynchronize(stream));
+    U1_HIP(hipMemcpy(lats.p, h_lats.data(), n_lats * sizeof(LatDesc), hipMemcpyHostToDevice));
+    drop_graphs();  // single-lattice kernels take the descriptor by value
     return U1ML_OK;
   }
 
   // --- host <-> device link transfer (natural order theta[t][z][y][x][mu]) ---
+  static size_t natural_of(const LatDesc& d, int p, uint32_t h) {
+    const int Lh = d.L / 2;
+    uint32_t q = h / Lh, xh = h % Lh;
+    int y = q % d.L;
+    q /= d.L;
+    int z = q % d.L;
+    int t = q / d.L;
+    int b = (p ^ (t + z + y)) & 1;
+    int x = 2 * xh + b;
+    return (((size_t)t * d.L + z) * d.L + y) * d.L + x;
+  }
+
   int get_links(int i, double* host) {
     const LatDesc& d = h_lats[i];
     const size_t n = 8ull * d.V2;
@@ -251,9 +348,8 @@ struct Engine {
       for (int p = 0; p < 2; ++p)
         for (uint32_t h = 0; h < (uint32_t)d.V2; ++h) {
           size_t src = ((size_t)(mu * 2 + p)) * d.V2 + h;
-          size_t nat = natural_of(d, p, h);
           double v = prec == U1ML_FP64 ? ((double*)raw.data())[src] : (double)((float*)raw.data())[src];
-          host[nat * 4 + mu] = v;
+          host[natural_of(d, p, h) * 4 + mu] = v;
         }
     return U1ML_OK;
   }
@@ -262,7 +358,8 @@ struct Engine {
     const LatDesc& d = h_lats[i];
     const size_t n = 8ull * d.V2;
     for (size_t k = 0; k < n; ++k)
-      if (!(std::fabs(host[k]) <= kMaxAngle)) return fail(U1ML_EINVAL, "set_links: angles must be finite, |theta| <= 64");
+      if (!(std::fabs(host[k]) <= kMaxAngle))
+        return fail(U1ML_EINVAL, "set_links: angles must be finite, |theta| <= 64");
     std::vector<char> raw(n * elem_size());
     for (int mu = 0; mu < 4; ++mu)
       for (int p = 0; p < 2; ++p)
@@ -279,38 +376,24 @@ struct Engine {
     return U1ML_OK;
   }
 
-  static size_t natural_of(const LatDesc& d, int p, uint32_t h) {
-    const int Lh = d.L / 2;
-    uint32_t q = h / Lh, xh = h % Lh;
-    int y = q % d.L;
-    q /= d.L;
-    int z = q % d.L;
-    int t = q / d.L;
-    int b = (p ^ (t + z + y)) & 1;
-    int x = 2 * xh + b;
-    return (((size_t)t * d.L + z) * d.L + y) * d.L + x;
-  }
-
-  // --- plain observables for every lattice: out[lat][7] and poly rows ---
+  // --- plain observables of every lattice ---
   int observables(std::vector<u1ml_observables>& res) {
     std::vector<int> items;
     for (auto& d : h_lats) items.push_back(2 * d.V2);
     Table* t;
-    int rc = table(items, 256, &t);
-    if (rc) return rc;
-    if ((rc = partial.ensure((size_t)t->n_blocks * 7 * sizeof(double)))) return rc;
+    U1_TRY(table(items, 256, &t));
+    U1_TRY(partial.ensure((size_t)t->n_blocks * 7 * sizeof(double)));
+    U1_TRY(row_begin.ensure((n_lats + 1) * sizeof(int)));
+    U1_TRY(red_out.ensure((size_t)n_lats * 7 * sizeof(double)));
+    U1_HIP(hipStreamSynchronize(stream));
+    U1_HIP(hipMemcpy(row_begin.p, t->lat_block_begin.data(), (n_lats + 1) * sizeof(int), hipMemcpyHostToDevice));
     U1_HIP(launch_plaq_field(prec, links.p, lats.as<LatDesc>(), bt(t), partial.as<double>(), stream));
-    if ((rc = row_begin.ensure((n_lats + 1) * sizeof(int)))) return rc;
-    U1_HIP(hipMemcpyAsync(row_begin.p, t->lat_block_begin.data(), (n_lats + 1) * sizeof(int), hipMemcpyHostToDevice,
-                          stream));
-    if ((rc = red_out.ensure((size_t)n_lats * 7 * sizeof(double)))) return rc;
     U1_HIP(launch_reduce_rows(partial.as<double>(), 7, row_begin.as<int>(), n_lats, red_out.as<double>(), stream));
     std::vector<double> pf((size_t)n_lats * 7);
-    U1_HIP(hipMemcpyAsync(pf.data(), red_out.p, pf.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
     U1_HIP(hipStreamSynchronize(stream));
+    U1_HIP(hipMemcpy(pf.data(), red_out.p, pf.size() * sizeof(double), hipMemcpyDeviceToHost));
     std::vector<std::vector<double>> pc;
-    rc = poly_corr(std::vector<int>(), pc);
-    if (rc) return rc;
+    U1_TRY(poly_corr(std::vector<int>(), pc));
     res.resize(n_lats);
     for (int i = 0; i < n_lats; ++i) {
       const double V = 2.0 * h_lats[i].V2;
@@ -326,9 +409,8 @@ struct Engine {
   // Polyakov loop average and plain correlator of every lattice (same r list):
   // out[lat] = {Re P, Im P, Re C(r_0), Im C(r_0), ...}
   int poly_corr(const std::vector<int>& r_list, std::vector<std::vector<double>>& out) {
-    std::vector<int> items;
+    std::vector<int> items, rb{0};
     std::vector<uint64_t> offs;
-    std::vector<int> rb{0};
     uint64_t o = 0;
     for (auto& d : h_lats) {
       items.push_back(d.L3);
@@ -337,42 +419,43 @@ struct Engine {
       rb.push_back(rb.back() + d.L3);
     }
     Table* t;
-    int rc = table(items, 256, &t);
-    if (rc) return rc;
+    U1_TRY(table(items, 256, &t));
     const int nR = (int)r_list.size();
     const int width = 2 + 2 * nR;
-    if ((rc = poly.ensure(o * sizeof(double)))) return rc;
-    if ((rc = poly_off.ensure(offs.size() * sizeof(uint64_t)))) return rc;
-    if ((rc = rows.ensure(o * width * sizeof(double)))) return rc;
-    if ((rc = row_begin.ensure(rb.size() * sizeof(int)))) return rc;
-    if ((rc = rvals_tmp.ensure(std::max(nR, 1) * sizeof(int)))) return rc;
-    if ((rc = red_out.ensure((size_t)n_lats * width * sizeof(double)))) return rc;
-    U1_HIP(hipMemcpyAsync(poly_off.p, offs.data(), offs.size() * sizeof(uint64_t), hipMemcpyHostToDevice, stream));
-    U1_HIP(hipMemcpyAsync(row_begin.p, rb.data(), rb.size() * sizeof(int), hipMemcpyHostToDevice, stream));
-    if (nR) U1_HIP(hipMemcpyAsync(rvals_tmp.p, r_list.data(), nR * sizeof(int), hipMemcpyHostToDevice, stream));
+    U1_TRY(poly.ensure(o * sizeof(double)));
+    U1_TRY(poly_off.ensure(offs.size() * sizeof(uint64_t)));
+    U1_TRY(rows.ensure(o * width * sizeof(double)));
+    U1_TRY(row_begin.ensure(rb.size() * sizeof(int)));
+    U1_TRY(rvals_tmp.ensure(std::max(nR, 1) * sizeof(int)));
+    U1_TRY(red_out.ensure((size_t)n_lats * width * sizeof(double)));
+    U1_HIP(hipStreamSynchronize(stream));
+    U1_HIP(hipMemcpy(poly_off.p, offs.data(), offs.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    U1_HIP(hipMemcpy(row_begin.p, rb.data(), rb.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (nR) U1_HIP(hipMemcpy(rvals_tmp.p, r_list.data(), nR * sizeof(int), hipMemcpyHostToDevice));
     U1_HIP(launch_poly_lines(prec, links.p, lats.as<LatDesc>(), bt(t), poly_off.as<uint64_t>(), poly.as<double>(),
                              stream));
     U1_HIP(launch_poly_corr(lats.as<LatDesc>(), bt(t), poly_off.as<uint64_t>(), poly.as<double>(),
                             rvals_tmp.as<int>(), nR, row_begin.as<int>(), rows.as<double>(), stream));
     U1_HIP(launch_reduce_rows(rows.as<double>(), width, row_begin.as<int>(), n_lats, red_out.as<double>(), stream));
     std::vector<double> h((size_t)n_lats * width);
-    U1_HIP(hipMemcpyAsync(h.data(), red_out.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
     U1_HIP(hipStreamSynchronize(stream));
+    U1_HIP(hipMemcpy(h.data(), red_out.p, h.size() * sizeof(double), hipMemcpyDeviceToHost));
     out.assign(n_lats, std::vector<double>(width));
     for (int i = 0; i < n_lats; ++i)
       for (int c = 0; c < width; ++c) out[i][c] = h[(size_t)i * width + c] / (double)h_lats[i].L3;
     return U1ML_OK;
   }
 
-  // --- multilevel ---
-  // r lists: per lattice (rl[i]); field only for a single lattice.
+  // --- multilevel (Sec. 2.2) ---
+  // Allocate and describe the workspace; rl[i] = r list of lattice i; rf =
+  // field separations (shared; each in every r list).
   int ml_setup(int n_levels, const int* th, const int* n_sub, int n_metro, int n_or,
                const std::vector<std::vector<int>>& rl, const std::vector<int>& rf) {
     MLState& m = ml;
-    // buffers below may still be read by queued work of an earlier run
-    U1_HIP(hipStreamSynchronize(stream));
-    m.valid = false;
-    m.field_valid = false;
+    U1_HIP(hipStreamSynchronize(stream));  // buffers below may still be in use
+    drop_graphs();                         // captured sequences hold the old buffer addresses
+    m.key.clear();
+    m.valid = m.field_valid = false;
     m.n_levels = n_levels;
     for (int l = 0; l < n_levels; ++l) {
       m.th[l] = th[l];
@@ -380,12 +463,15 @@ struct Engine {
     }
     m.n_metro = n_metro;
     m.n_or = n_or;
+    m.field = !rf.empty();
+    const int inner = n_levels - 1;
+    const int n_outer = n_levels == 2 ? n_sub[0] : 1;
+    const int n_samples_kept = m.field ? n_outer * n_sub[inner] : n_sub[inner];
     m.h_mls.assign(n_lats, MLDesc{});
     m.nR.assign(n_lats, 0);
     std::vector<int> rv;
     uint64_t ell = 0, acc = 0;
     m.max_r = 0;
-    const int inner = n_levels - 1;
     for (int i = 0; i < n_lats; ++i) {
       const LatDesc& d = h_lats[i];
       MLDesc& md = m.h_mls[i];
@@ -396,7 +482,7 @@ struct Engine {
       m.max_r = std::max(m.max_r, md.nR);
       for (int l = 0; l < n_levels; ++l) md.ns[l] = d.T / th[l];
       md.ell = ell;
-      ell += (uint64_t)n_sub[inner] * md.ns[inner] * d.L3;
+      ell += (uint64_t)n_samples_kept * md.ns[inner] * d.L3;
       for (int l = 0; l < n_levels; ++l) {
         md.acc[l] = acc;
         if (l < inner) acc += (uint64_t)md.ns[l] * d.L3 * md.nR;
@@ -405,58 +491,56 @@ struct Engine {
       acc += (uint64_t)d.L3 * md.nR;
     }
     m.acc_elems = acc;
-    int rc;
-    if ((rc = m.mls.ensure(n_lats * sizeof(MLDesc)))) return rc;
-    if ((rc = m.rvals.ensure(rv.size() * sizeof(int)))) return rc;
-    if ((rc = m.mlbuf.ensure(ell * sizeof(double)))) return rc;
-    if ((rc = m.accbuf.ensure(acc * sizeof(double2)))) return rc;
-    if ((rc = m.corr.ensure((size_t)n_lats * m.max_r * 2 * sizeof(double)))) return rc;
+    U1_TRY(m.mls.ensure(n_lats * sizeof(MLDesc)));
+    U1_TRY(m.rvals.ensure(rv.size() * sizeof(int)));
+    U1_TRY(m.mlbuf.ensure(ell * sizeof(double)));
+    U1_TRY(m.accbuf.ensure(acc * sizeof(double2)));
+    U1_TRY(m.corr.ensure((size_t)n_lats * m.max_r * 2 * sizeof(double)));
     U1_HIP(hipMemcpy(m.mls.p, m.h_mls.data(), n_lats * sizeof(MLDesc), hipMemcpyHostToDevice));
     U1_HIP(hipMemcpy(m.rvals.p, rv.data(), rv.size() * sizeof(int), hipMemcpyHostToDevice));
-    // prepare block tables used by the run so that no allocation happens later
-    Table* t;
-    std::vector<int> it_lines, it_top;
-    for (int i = 0; i < n_lats; ++i) {
-      it_lines.push_back(m.h_mls[i].ns[inner] * h_lats[i].L3);
-      it_top.push_back(h_lats[i].L3 * m.h_mls[i].nR);
-    }
-    if ((rc = table(it_lines, 256, &t))) return rc;
-    if ((rc = table(it_top, 256, &t))) return rc;
-    for (int l = 0; l < inner; ++l) {
-      std::vector<int> it;
-      for (int i = 0; i < n_lats; ++i) it.push_back(m.h_mls[i].ns[l] * h_lats[i].L3 * m.h_mls[i].nR);
-      if ((rc = table(it, 256, &t))) return rc;
-    }
-    if ((rc = table(items_half(), block, &t))) return rc;
-    // field insertion workspace
-    m.field = !rf.empty();
     if (m.field) {
-      const LatDesc& d = h_lats[0];
-      FieldDesc& fd = m.fd;
-      fd = FieldDesc{};
-      fd.n_rf = (int)rf.size();
-      for (int f = 0; f < fd.n_rf; ++f) {
-        fd.rf[f] = rf[f];
-        fd.rf_k[f] = (int)(std::find(rl[0].begin(), rl[0].end(), rf[f]) - rl[0].begin());
+      FieldParams& fp = m.fp;
+      fp = FieldParams{};
+      fp.n_rf = (int)rf.size();
+      for (int f = 0; f < fp.n_rf; ++f) {
+        fp.rf[f] = rf[f];
+        fp.rf_k[f] = (int)(std::find(rl[0].begin(), rl[0].end(), rf[f]) - rl[0].begin());
       }
-      fd.n_levels = n_levels;
-      fd.n_outer = n_levels == 2 ? n_sub[0] : 1;
-      fd.n_inner = n_sub[inner];
-      fd.ns_inner = m.h_mls[0].ns[inner];
-      fd.children = n_levels == 2 ? th[0] / th[1] : fd.ns_inner;
-      fd.th_inner = th[inner];
-      const uint64_t tw = (uint64_t)fd.n_outer * fd.ns_inner * d.L3 * fd.n_rf;
-      if ((rc = m.tavg.ensure(tw * sizeof(double2)))) return rc;
-      if ((rc = m.w.ensure(tw * sizeof(double2)))) return rc;
-      if ((rc = m.oslab.ensure((uint64_t)6 * fd.ns_inner * d.L3 * sizeof(double)))) return rc;
-      if ((rc = m.wslab.ensure((uint64_t)fd.n_rf * fd.ns_inner * d.L3 * sizeof(double2)))) return rc;
-      if ((rc = m.fout.ensure((uint64_t)fd.n_rf * 12 * d.L * d.L * sizeof(double2)))) return rc;
-      if ((rc = m.snap_links.ensure(link_elems * elem_size()))) return rc;
+      fp.n_levels = n_levels;
+      fp.n_outer = n_outer;
+      fp.n_inner = n_sub[inner];
+      m.h_fls.assign(n_lats, FieldLat{});
+      m.fout_off.assign(n_lats, 0);
+      uint64_t fb = 0, fo = 0;
+      size_t per_sample_max = 0;
+      for (int i = 0; i < n_lats; ++i) {
+        const LatDesc& d = h_lats[i];
+        FieldLat& fl = m.h_fls[i];
+        fl.ns = m.h_mls[i].ns[inner];
+        const uint64_t L3 = d.L3, L2 = (uint64_t)d.L * d.L;
+        fl.oall = fb;
+        fb += (uint64_t)n_samples_kept * 6 * fl.ns * L3;
+        fl.tavg = fb;
+        fb += 2ull * n_outer * fl.ns * L3 * fp.n_rf;
+        fl.w = fb;
+        fb += 2ull * n_outer * fl.ns * L3 * fp.n_rf;
+        fl.g = fb;
+        fb += 2ull * fp.n_rf * 12 * L2;
+        m.fout_off[i] = fo;
+        fo += (uint64_t)fp.n_rf * 12 * L2;
+        per_sample_max = std::max<size_t>(per_sample_max, (size_t)(2 * fp.n_rf + 6) * fl.ns * L3);
+      }
+      m.scratch_elems = std::max(per_sample_max, kFieldScratchBytes / sizeof(double2));
+      U1_TRY(m.fls.ensure(n_lats * sizeof(FieldLat)));
+      U1_TRY(m.fbuf.ensure(fb * sizeof(double)));
+      U1_TRY(m.fout.ensure(fo * sizeof(double2)));
+      U1_TRY(m.scratch.ensure(m.scratch_elems * sizeof(double2)));
+      U1_HIP(hipMemcpy(m.fls.p, m.h_fls.data(), n_lats * sizeof(FieldLat), hipMemcpyHostToDevice));
     }
     return U1ML_OK;
   }
 
-  int ml_fold(int child, int parent) {
+  int ml_fold(int child, int parent, int sample_base) {
     MLState& m = ml;
     const int inner = m.n_levels - 1;
     std::vector<int> it;
@@ -465,91 +549,91 @@ struct Engine {
       it.push_back(nsp * h_lats[i].L3 * m.h_mls[i].nR);
     }
     Table* t;
-    int rc = table(it, 256, &t);
-    if (rc) return rc;
+    U1_TRY(table(it, 256, &t));
     U1_HIP(launch_ml_fold(lats.as<LatDesc>(), m.mls.as<MLDesc>(), bt(t), child, parent, m.n_levels, child == inner,
-                          m.n[child], m.rvals.as<int>(), m.mlbuf.as<double>(), m.accbuf.as<double2>(), stream));
+                          m.n[child], sample_base, m.rvals.as<int>(), m.mlbuf.as<double>(), m.accbuf.as<double2>(),
+                          stream));
     return U1ML_OK;
   }
 
-  int ml_lines(int sample) {
+  int ml_sample(int sample) {
     MLState& m = ml;
     const int inner = m.n_levels - 1;
     std::vector<int> it;
     for (int i = 0; i < n_lats; ++i) it.push_back(m.h_mls[i].ns[inner] * h_lats[i].L3);
     Table* t;
-    int rc = table(it, 256, &t);
-    if (rc) return rc;
+    U1_TRY(table(it, 256, &t));
     U1_HIP(launch_ml_lines(prec, links.p, lats.as<LatDesc>(), m.mls.as<MLDesc>(), bt(t), m.th[inner], sample,
                            m.mlbuf.as<double>(), stream));
+    if (m.field)
+      U1_HIP(launch_field_o(prec, links.p, lats.as<LatDesc>(), m.fls.as<FieldLat>(), bt(t), m.th[inner], sample,
+                            m.fbuf.as<double>(), stream));
     return U1ML_OK;
   }
 
+  // n[l] iterations of: update with level l frozen, then measure (innermost)
+  // or recurse and fold the inner averages into level l.
   int ml_level(int l, int outer_it) {
     MLState& m = ml;
     const int inner = m.n_levels - 1;
     for (int it = 0; it < m.n[l]; ++it) {
-      int rc = sweep(m.n_metro, m.n_or, m.th[l]);
-      if (rc) return rc;
+      U1_TRY(sweep(m.n_metro, m.n_or, m.th[l]));
       const int mo = l == 0 ? it : outer_it;
       if (l == inner) {
-        if ((rc = ml_lines(it))) return rc;
-        if (m.replay) {
-          U1_HIP(launch_field_sample(prec, links.p, lats.as<LatDesc>(), m.mls.as<MLDesc>(), m.fd, h_lats[0].L,
-                                     m.n_levels == 2 ? outer_it : 0, it, m.mlbuf.as<double>(), m.w.as<double2>(),
-                                     m.oslab.as<double>(), m.wslab.as<double2>(), m.fout.as<double2>(), stream));
-        }
+        const int base = (m.field && m.n_levels == 2) ? outer_it * m.n[inner] : 0;
+        U1_TRY(ml_sample(base + it));
       } else {
-        if ((rc = ml_level(l + 1, mo))) return rc;
-        if (!m.replay) {
-          if (m.field && l == 0)
-            U1_HIP(launch_field_store_tavg(lats.as<LatDesc>(), m.mls.as<MLDesc>(), m.fd, h_lats[0].L3, it,
-                                           m.mlbuf.as<double>(), m.tavg.as<double2>(), stream));
-          if ((rc = ml_fold(l + 1, l))) return rc;
-        }
+        U1_TRY(ml_level(l + 1, mo));
+        const int base = (m.field && l + 1 == inner) ? mo * m.n[inner] : 0;
+        U1_TRY(ml_fold(l + 1, l, base));
       }
     }
     return U1ML_OK;
   }
 
-  // full multilevel run, results to ml.corr (and ml.fout)
+  // full multilevel run, results in ml.corr (and ml.fout)
   int ml_run() {
     MLState& m = ml;
-    int rc;
     U1_HIP(launch_ml_zero(m.accbuf.as<double2>(), m.acc_elems, stream));
-    std::vector<uint64_t> snap_ids = h_pass_ids;
-    if (m.field) U1_HIP(hipMemcpyAsync(m.snap_links.p, links.p, link_elems * elem_size(), hipMemcpyDeviceToDevice,
-                                       stream));
-    m.replay = 0;
-    if ((rc = ml_level(0, 0))) return rc;
+    U1_TRY(ml_level(0, 0));
     if (m.field) {
-      if (m.n_levels == 1)
-        U1_HIP(launch_field_store_tavg(lats.as<LatDesc>(), m.mls.as<MLDesc>(), m.fd, h_lats[0].L3, 0,
-                                       m.mlbuf.as<double>(), m.tavg.as<double2>(), stream));
-      U1_HIP(launch_field_weights(lats.as<LatDesc>(), m.mls.as<MLDesc>(), m.fd, h_lats[0].L3, m.tavg.as<double2>(),
-                                  m.accbuf.as<double2>(), m.w.as<double2>(), stream));
+      // the weights need the top-level averages: contract before the top fold
+      for (int i = 0; i < n_lats; ++i)
+        U1_HIP(launch_field_contract(lats.as<LatDesc>() + i, m.mls.as<MLDesc>() + i, m.fls.as<FieldLat>() + i,
+                                     m.h_fls[i], m.fp, h_lats[i].L, m.mlbuf.as<double>(), m.accbuf.as<double2>(),
+                                     m.fbuf.as<double>(), m.scratch.as<double2>(), m.scratch_elems,
+                                     m.fout.as<double2>() + m.fout_off[i], stream));
     }
-    if ((rc = ml_fold(0, m.n_levels))) return rc;
+    U1_TRY(ml_fold(0, m.n_levels, 0));
     U1_HIP(launch_ml_final(lats.as<LatDesc>(), m.mls.as<MLDesc>(), n_lats, m.max_r, m.n_levels,
                            m.accbuf.as<double2>(), m.corr.as<double>(), stream));
-    if (m.field) {
-      // replay the identical update sequence, contracting the field insertion
-      U1_HIP(launch_ml_zero(m.fout.as<double2>(), (uint64_t)m.fd.n_rf * 12 * h_lats[0].L * h_lats[0].L, stream));
-      U1_HIP(hipMemcpyAsync(links.p, m.snap_links.p, link_elems * elem_size(), hipMemcpyDeviceToDevice, stream));
-      h_pass_ids = snap_ids;
-      if ((rc = upload_pass_ids())) return rc;
-      m.replay = 1;
-      size_t log_mark = log_used;
-      bool dbg = debug;
-      debug = false;  // the replay repeats decisions already recorded
-      rc = ml_level(0, 0);
-      debug = dbg;
-      log_used = log_mark;
-      m.replay = 0;
-      if (rc) return rc;
-      m.field_valid = true;
+    return U1ML_OK;
+  }
+
+  // n_sweeps_before unfrozen compound sweeps, then a multilevel run
+  int multilevel(int n_levels, const int* th, const int* n_sub, int n_metro, int n_or,
+                 const std::vector<std::vector<int>>& rl, const std::vector<int>& rf, int n_sweeps_before) {
+    std::vector<long long> key{1, n_levels, n_metro, n_or, n_sweeps_before, (long long)rf.size()};
+    for (int l = 0; l < n_levels; ++l) {
+      key.push_back(th[l]);
+      key.push_back(n_sub[l]);
     }
-    m.valid = true;
+    for (auto& v : rl) {
+      key.push_back(-(long long)v.size());
+      for (int r : v) key.push_back(r);
+    }
+    for (int r : rf) key.push_back(r);
+    if (ml.key != key) {
+      U1_TRY(ml_setup(n_levels, th, n_sub, n_metro, n_or, rl, rf));
+      ml.key = key;
+    }
+    ml.valid = ml.field_valid = false;
+    U1_TRY(run_captured(key, [&]() -> int {
+      for (int s = 0; s < n_sweeps_before; ++s) U1_TRY(sweep(n_metro, n_or, 0));
+      return ml_run();
+    }));
+    ml.valid = true;
+    ml.field_valid = ml.field;
     return U1ML_OK;
   }
 };
@@ -602,8 +686,7 @@ int engine_create(Engine& e, const std::vector<int>& L, const std::vector<int>& 
   const int n = (int)L.size();
   uint64_t off = 0;
   for (int i = 0; i < n; ++i) {
-    int rc = validate_size(L[i], T[i]);
-    if (rc) return rc;
+    U1_TRY(validate_size(L[i], T[i]));
     if (!std::isfinite(beta[i]) || beta[i] < 0) return fail(U1ML_EINVAL, "beta must be finite and >= 0");
     e.h_lats.push_back(make_desc(L[i], T[i], beta[i], o.eps, seed[i], off));
     off += 4ull * L[i] * L[i] * L[i] * T[i];
@@ -615,8 +698,8 @@ int engine_create(Engine& e, const std::vector<int>& L, const std::vector<int>& 
     U1_HIP(hipStreamCreateWithFlags(&e.stream, hipStreamNonBlocking));
     e.own_stream = true;
   }
+  e.use_graphs = o.no_graphs == 0;
   e.prec = o.precision;
-  e.start = o.start;
   e.n_lats = n;
   e.link_elems = off;
   if (o.block)
@@ -625,22 +708,76 @@ int engine_create(Engine& e, const std::vector<int>& L, const std::vector<int>& 
     auto it = g_tuned_block.find(std::make_tuple(L[0], T[0], o.precision));
     e.block = it != g_tuned_block.end() ? it->second : 256;
   }
-  int rc;
   if (allow_dev_buf && o.dev_buf) {
     if (o.dev_bytes < off * e.elem_size()) return fail(U1ML_EINVAL, "dev_buf smaller than u1ml_link_bytes");
     e.links.p = o.dev_buf;
     e.links.bytes = o.dev_bytes;
     e.links.owned = false;
-  } else if ((rc = e.links.ensure(off * e.elem_size()))) {
-    return rc;
+  } else {
+    U1_TRY(e.links.ensure(off * e.elem_size()));
   }
-  if ((rc = e.lats.ensure(n * sizeof(LatDesc)))) return rc;
-  U1_HIP(hipMemcpy(e.lats.p, e.h_lats.data(), n * sizeof(LatDesc), hipMemcpyHostToDevice));
-  if ((rc = e.pass_ids.ensure(n * sizeof(uint64_t)))) return rc;
+  U1_TRY(e.lats.ensure(n * sizeof(LatDesc)));
+  U1_TRY(e.upload_lats());
+  U1_TRY(e.pass_ids.ensure(n * sizeof(uint64_t)));
   e.h_pass_ids.assign(n, 0);
-  if ((rc = e.upload_pass_ids())) return rc;
-  if ((rc = e.init_links(o.start == U1ML_HOT))) return rc;
+  U1_TRY(e.upload_pass_ids());
+  U1_TRY(e.init_links(o.start == U1ML_HOT));
   U1_HIP(hipStreamSynchronize(e.stream));
+  return U1ML_OK;
+}
+
+int check_ml_args(const Engine& e, int n_levels, const int* th, const int* n_sub, int n_metro, int n_or) {
+  if (n_levels < 1 || n_levels > U1ML_MAX_LEVELS || !th || !n_sub || n_metro < 0 || n_or < 0)
+    return fail(U1ML_EINVAL, "multilevel arguments");
+  for (int l = 0; l < n_levels; ++l) {
+    if (th[l] < 1 || n_sub[l] < 1) return fail(U1ML_EINVAL, "slab sizes and n_sub must be >= 1");
+    if (l > 0 && th[l - 1] % th[l]) return fail(U1ML_EINVAL, "each slab size must divide the previous one");
+    for (auto& d : e.h_lats)
+      if (d.T % th[l]) return fail(U1ML_EINVAL, "slab sizes must divide T");
+  }
+  return U1ML_OK;
+}
+
+// shared argument checks of u1ml_multilevel / u1ml_batch_multilevel
+int ml_entry(Engine& e, int n_levels, const int* th, const int* n_sub, int n_metro, int n_or, int n_r,
+             const int* r_list, int n_rf, const int* rf_list) {
+  U1_TRY(check_ml_args(e, n_levels, th, n_sub, n_metro, n_or));
+  if (n_r < 1 || !r_list) return fail(U1ML_EINVAL, "need at least one r");
+  if (n_rf < 0 || n_rf > U1ML_MAX_FIELD_R || (n_rf > 0 && !rf_list)) return fail(U1ML_EINVAL, "field r list");
+  if (n_rf > 0 && n_levels > 2) return fail(U1ML_EINVAL, "field insertion supports one or two levels");
+  for (auto& d : e.h_lats)
+    if (n_rf > 0 && d.L > kMaxFieldL) return fail(U1ML_EINVAL, "field insertion supports L <= 62");
+  std::vector<int> rl(r_list, r_list + n_r), rf;
+  for (int r : rl)
+    for (auto& d : e.h_lats)
+      if (r < 1 || r >= d.L) return fail(U1ML_EINVAL, "r must be in [1, L)");
+  for (int f = 0; f < n_rf; ++f) {
+    if (std::find(rl.begin(), rl.end(), rf_list[f]) == rl.end())
+      return fail(U1ML_EINVAL, "every field r must appear in r_list");
+    rf.push_back(rf_list[f]);
+  }
+  U1_TRY(e.set_device());
+  return e.multilevel(n_levels, th, n_sub, n_metro, n_or, std::vector<std::vector<int>>(e.n_lats, rl), rf, 0);
+}
+
+int read_results(Engine& e, int i, u1ml_observables* obs, double* correlator, double* field_profile) {
+  U1_TRY(e.set_device());
+  if ((correlator && !e.ml.valid) || (field_profile && !e.ml.field_valid))
+    return fail(U1ML_ESTATE, "no multilevel result of that kind yet");
+  if (obs) {
+    std::vector<u1ml_observables> res;
+    U1_TRY(e.observables(res));
+    *obs = res[i];
+  }
+  U1_HIP(hipStreamSynchronize(e.stream));
+  if (correlator)
+    U1_HIP(hipMemcpy(correlator, e.ml.corr.as<double>() + (size_t)i * e.ml.max_r * 2, e.ml.nR[i] * 2 * sizeof(double),
+                     hipMemcpyDeviceToHost));
+  if (field_profile) {
+    const int L = e.h_lats[i].L;
+    U1_HIP(hipMemcpy(field_profile, e.ml.fout.as<double2>() + e.ml.fout_off[i],
+                     (size_t)e.ml.fp.n_rf * 12 * L * L * sizeof(double2), hipMemcpyDeviceToHost));
+  }
   return U1ML_OK;
 }
 
@@ -669,74 +806,27 @@ int u1ml_init_lattice(int L, int T, double beta, uint64_t seed, const u1ml_optio
   *out = nullptr;
   std::unique_ptr<u1ml_lattice> lat(new (std::nothrow) u1ml_lattice());
   if (!lat) return fail(U1ML_ENOMEM, "host allocation");
-  int rc = engine_create(lat->e, {L}, {T}, {beta}, {seed}, opt, true);
-  if (rc) return rc;
+  U1_TRY(engine_create(lat->e, {L}, {T}, {beta}, {seed}, opt, true));
   *out = lat.release();
   return U1ML_OK;
 }
 
 int u1ml_sweep(u1ml_lattice* lat, int n_metro, int n_or) {
   if (!lat || n_metro < 0 || n_or < 0) return fail(U1ML_EINVAL, "sweep arguments");
-  int rc = lat->e.set_device();
-  if (rc) return rc;
-  return lat->e.sweep(n_metro, n_or, 0);
-}
-
-static int check_ml_args(const Engine& e, int n_levels, const int* th, const int* n_sub, int n_metro, int n_or) {
-  if (n_levels < 1 || n_levels > U1ML_MAX_LEVELS || !th || !n_sub || n_metro < 0 || n_or < 0)
-    return fail(U1ML_EINVAL, "multilevel arguments");
-  for (int l = 0; l < n_levels; ++l) {
-    if (th[l] < 1 || n_sub[l] < 1) return fail(U1ML_EINVAL, "slab sizes and n_sub must be >= 1");
-    if (l > 0 && th[l - 1] % th[l]) return fail(U1ML_EINVAL, "each slab size must divide the previous one");
-    for (auto& d : e.h_lats)
-      if (d.T % th[l]) return fail(U1ML_EINVAL, "slab sizes must divide T");
-  }
-  return U1ML_OK;
+  Engine& e = lat->e;
+  U1_TRY(e.set_device());
+  return e.run_captured({0, n_metro, n_or}, [&]() { return e.sweep(n_metro, n_or, 0); });
 }
 
 int u1ml_multilevel(u1ml_lattice* lat, int n_levels, const int* slab_sizes, const int* n_sub, int n_metro, int n_or,
                     int n_r, const int* r_list, int n_rf, const int* rf_list) {
   if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
-  Engine& e = lat->e;
-  int rc = check_ml_args(e, n_levels, slab_sizes, n_sub, n_metro, n_or);
-  if (rc) return rc;
-  if (n_r < 1 || !r_list) return fail(U1ML_EINVAL, "need at least one r");
-  if (n_rf < 0 || n_rf > U1ML_MAX_FIELD_R || (n_rf > 0 && !rf_list)) return fail(U1ML_EINVAL, "field r list");
-  if (n_rf > 0 && n_levels > 2) return fail(U1ML_EINVAL, "field insertion supports one or two levels");
-  std::vector<int> rl(r_list, r_list + n_r), rf;
-  for (int r : rl)
-    if (r < 1 || r >= e.h_lats[0].L) return fail(U1ML_EINVAL, "r must be in [1, L)");
-  for (int f = 0; f < n_rf; ++f) {
-    if (std::find(rl.begin(), rl.end(), rf_list[f]) == rl.end())
-      return fail(U1ML_EINVAL, "every field r must appear in r_list");
-    rf.push_back(rf_list[f]);
-  }
-  if ((rc = e.set_device())) return rc;
-  if ((rc = e.ml_setup(n_levels, slab_sizes, n_sub, n_metro, n_or, {rl}, rf))) return rc;
-  return e.ml_run();
+  return ml_entry(lat->e, n_levels, slab_sizes, n_sub, n_metro, n_or, n_r, r_list, n_rf, rf_list);
 }
 
 int u1ml_measure(u1ml_lattice* lat, u1ml_observables* obs, double* correlator, double* field_profile) {
   if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
-  Engine& e = lat->e;
-  int rc = e.set_device();
-  if (rc) return rc;
-  if ((correlator && !e.ml.valid) || (field_profile && !e.ml.field_valid))
-    return fail(U1ML_ESTATE, "no multilevel result of that kind yet");
-  if (obs) {
-    std::vector<u1ml_observables> res;
-    if ((rc = e.observables(res))) return rc;
-    *obs = res[0];
-  }
-  U1_HIP(hipStreamSynchronize(e.stream));
-  if (correlator)
-    U1_HIP(hipMemcpy(correlator, e.ml.corr.p, e.ml.nR[0] * 2 * sizeof(double), hipMemcpyDeviceToHost));
-  if (field_profile) {
-    const int L = e.h_lats[0].L;
-    U1_HIP(hipMemcpy(field_profile, e.ml.fout.p, (size_t)e.ml.fd.n_rf * 12 * L * L * 2 * sizeof(double),
-                     hipMemcpyDeviceToHost));
-  }
-  return U1ML_OK;
+  return read_results(lat->e, 0, obs, correlator, field_profile);
 }
 
 int u1ml_plain_correlator(u1ml_lattice* lat, int n_r, const int* r_list, double* out) {
@@ -745,10 +835,9 @@ int u1ml_plain_correlator(u1ml_lattice* lat, int n_r, const int* r_list, double*
   std::vector<int> rl(r_list, r_list + n_r);
   for (int r : rl)
     if (r < 0 || r >= e.h_lats[0].L) return fail(U1ML_EINVAL, "r must be in [0, L)");
-  int rc = e.set_device();
-  if (rc) return rc;
+  U1_TRY(e.set_device());
   std::vector<std::vector<double>> pc;
-  if ((rc = e.poly_corr(rl, pc))) return rc;
+  U1_TRY(e.poly_corr(rl, pc));
   for (int k = 0; k < n_r; ++k) {
     out[2 * k] = pc[0][2 + 2 * k];
     out[2 * k + 1] = pc[0][3 + 2 * k];
@@ -758,14 +847,14 @@ int u1ml_plain_correlator(u1ml_lattice* lat, int n_r, const int* r_list, double*
 
 int u1ml_get_links(u1ml_lattice* lat, double* host) {
   if (!lat || !host) return fail(U1ML_EINVAL, "get_links arguments");
-  int rc = lat->e.set_device();
-  return rc ? rc : lat->e.get_links(0, host);
+  U1_TRY(lat->e.set_device());
+  return lat->e.get_links(0, host);
 }
 
 int u1ml_set_links(u1ml_lattice* lat, const double* host) {
   if (!lat || !host) return fail(U1ML_EINVAL, "set_links arguments");
-  int rc = lat->e.set_device();
-  return rc ? rc : lat->e.set_links(0, host);
+  U1_TRY(lat->e.set_device());
+  return lat->e.set_links(0, host);
 }
 
 int u1ml_get_pass_id(u1ml_lattice* lat, uint64_t* pass_id) {
@@ -776,8 +865,7 @@ int u1ml_get_pass_id(u1ml_lattice* lat, uint64_t* pass_id) {
 
 int u1ml_set_pass_id(u1ml_lattice* lat, uint64_t pass_id) {
   if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
-  int rc = lat->e.set_device();
-  if (rc) return rc;
+  U1_TRY(lat->e.set_device());
   lat->e.h_pass_ids[0] = pass_id;
   return lat->e.upload_pass_ids();
 }
@@ -785,11 +873,12 @@ int u1ml_set_pass_id(u1ml_lattice* lat, uint64_t pass_id) {
 int u1ml_set_debug(u1ml_lattice* lat, unsigned flags, size_t capacity) {
   if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
   Engine& e = lat->e;
-  int rc = e.set_device();
-  if (rc) return rc;
+  U1_TRY(e.set_device());
   U1_HIP(hipStreamSynchronize(e.stream));
   if (flags & 1u) {
-    if ((rc = e.log.ensure(capacity))) return rc;
+    U1_TRY(e.log.ensure(capacity));
+    // frozen links get no thread; their entries keep this marker
+    U1_HIP(launch_fill_u8(e.log.as<uint8_t>(), capacity, 2, e.stream));
     e.debug = true;
     e.log_cap = capacity;
   } else {
@@ -803,8 +892,7 @@ int u1ml_set_debug(u1ml_lattice* lat, unsigned flags, size_t capacity) {
 int u1ml_get_accept_log(u1ml_lattice* lat, uint8_t* out, size_t cap, size_t* n_bytes) {
   if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
   Engine& e = lat->e;
-  int rc = e.set_device();
-  if (rc) return rc;
+  U1_TRY(e.set_device());
   U1_HIP(hipStreamSynchronize(e.stream));
   if (n_bytes) *n_bytes = e.log_used;
   size_t n = std::min(cap, e.log_used);
@@ -817,8 +905,8 @@ int u1ml_save(u1ml_lattice* lat, const char* path) {
   Engine& e = lat->e;
   const LatDesc& d = e.h_lats[0];
   std::vector<double> h(8ull * d.V2);
-  int rc = e.set_device();
-  if (rc || (rc = e.get_links(0, h.data()))) return rc;
+  U1_TRY(e.set_device());
+  U1_TRY(e.get_links(0, h.data()));
   FILE* f = std::fopen(path, "wb");
   if (!f) return fail(U1ML_EIO, std::string("cannot open ") + path);
   std::fprintf(f, "u1ml-checkpoint-1 L=%d T=%d beta=%.17g eps=%.17g seed=%llu pass_id=%llu precision=%d\n", d.L, d.T,
@@ -852,26 +940,28 @@ int u1ml_load(u1ml_lattice* lat, const char* path) {
     std::fclose(f);
     return fail(U1ML_EINVAL, "checkpoint shape or precision differs from the lattice");
   }
+  if (!std::isfinite(beta) || beta < 0 || !std::isfinite(eps) || eps < 0) {
+    std::fclose(f);
+    return fail(U1ML_EINVAL, "checkpoint beta or eps out of range");
+  }
   std::vector<double> h(8ull * d.V2);
   size_t r = std::fread(h.data(), sizeof(double), h.size(), f);
   std::fclose(f);
   if (r != h.size()) return fail(U1ML_EIO, "short read");
-  int rc = e.set_device();
-  if (rc) return rc;
+  U1_TRY(e.set_device());
   d.beta = beta;
   d.eps = eps;
   d.sqrt_beta = std::sqrt(beta);
   d.seed = seed;
-  U1_HIP(hipMemcpy(e.lats.p, e.h_lats.data(), sizeof(LatDesc), hipMemcpyHostToDevice));
+  U1_TRY(e.upload_lats());
   e.h_pass_ids[0] = pid;
-  if ((rc = e.upload_pass_ids())) return rc;
+  U1_TRY(e.upload_pass_ids());
   return e.set_links(0, h.data());
 }
 
 int u1ml_synchronize(u1ml_lattice* lat) {
   if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
-  int rc = lat->e.set_device();
-  if (rc) return rc;
+  U1_TRY(lat->e.set_device());
   U1_HIP(hipStreamSynchronize(lat->e.stream));
   return U1ML_OK;
 }
@@ -879,7 +969,6 @@ int u1ml_synchronize(u1ml_lattice* lat) {
 void u1ml_destroy(u1ml_lattice* lat) {
   if (!lat) return;
   (void)hipSetDevice(lat->e.device);
-  (void)hipStreamSynchronize(lat->e.stream);
   delete lat;
 }
 
@@ -890,105 +979,60 @@ int u1ml_batch_create(int n, const int* L, const int* T, const double* beta, con
   *out = nullptr;
   std::unique_ptr<u1ml_batch> b(new (std::nothrow) u1ml_batch());
   if (!b) return fail(U1ML_ENOMEM, "host allocation");
-  int rc = engine_create(b->e, std::vector<int>(L, L + n), std::vector<int>(T, T + n),
-                         std::vector<double>(beta, beta + n), std::vector<uint64_t>(seed, seed + n), opt, false);
-  if (rc) return rc;
+  U1_TRY(engine_create(b->e, std::vector<int>(L, L + n), std::vector<int>(T, T + n),
+                       std::vector<double>(beta, beta + n), std::vector<uint64_t>(seed, seed + n), opt, false));
   *out = b.release();
   return U1ML_OK;
 }
 
 int u1ml_batch_sweep(u1ml_batch* b, int n_metro, int n_or) {
   if (!b || n_metro < 0 || n_or < 0) return fail(U1ML_EINVAL, "batch_sweep arguments");
-  int rc = b->e.set_device();
-  return rc ? rc : b->e.sweep(n_metro, n_or, 0);
+  Engine& e = b->e;
+  U1_TRY(e.set_device());
+  return e.run_captured({0, n_metro, n_or}, [&]() { return e.sweep(n_metro, n_or, 0); });
 }
 
-static int batch_cycle_eager(Engine& e, int n_sweeps, int n_metro, int n_or) {
-  int rc;
-  for (int s = 0; s < n_sweeps; ++s)
-    if ((rc = e.sweep(n_metro, n_or, 0))) return rc;
-  return e.ml_run();
+int u1ml_batch_multilevel(u1ml_batch* b, int n_levels, const int* slab_sizes, const int* n_sub, int n_metro,
+                          int n_or, int n_r, const int* r_list, int n_rf, const int* rf_list) {
+  if (!b) return fail(U1ML_EINVAL, "batch is NULL");
+  return ml_entry(b->e, n_levels, slab_sizes, n_sub, n_metro, n_or, n_r, r_list, n_rf, rf_list);
 }
 
 int u1ml_batch_cycle(u1ml_batch* b, int n_sweeps, int n_metro, int n_or, int th, int n_sub, int use_graph) {
   if (!b || n_sweeps < 0) return fail(U1ML_EINVAL, "batch_cycle arguments");
   Engine& e = b->e;
-  int rc = check_ml_args(e, 1, &th, &n_sub, n_metro, n_or);
-  if (rc) return rc;
-  if ((rc = e.set_device())) return rc;
-  std::vector<int> key{n_sweeps, n_metro, n_or, th, n_sub};
-  const bool have_graph = e.graph_exec && e.graph_key == key && !e.debug;
-  if (!have_graph) {
-    std::vector<std::vector<int>> rl(e.n_lats);
-    for (int i = 0; i < e.n_lats; ++i)
-      for (int r = 1; r <= e.h_lats[i].T / 2 && r < e.h_lats[i].L; ++r) rl[i].push_back(r);
-    if ((rc = e.ml_setup(1, &th, &n_sub, n_metro, n_or, rl, {}))) return rc;
-    if ((rc = batch_cycle_eager(e, n_sweeps, n_metro, n_or))) return rc;
-    if (use_graph && !e.debug) {
-      // capture the same cycle for later calls; all buffers and tables exist now
-      if (e.graph_exec) {
-        (void)hipGraphExecDestroy(e.graph_exec);
-        e.graph_exec = nullptr;
-      }
-      std::vector<uint64_t> ids = e.h_pass_ids;
-      hipGraph_t g;
-      U1_HIP(hipStreamBeginCapture(e.stream, hipStreamCaptureModeThreadLocal));
-      rc = batch_cycle_eager(e, n_sweeps, n_metro, n_or);
-      hipError_t ce = hipStreamEndCapture(e.stream, &g);
-      if (rc) return rc;
-      if (ce != hipSuccess) return fail(U1ML_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
-      e.graph_metro_passes = (int)(e.h_pass_ids[0] - ids[0]);
-      e.h_pass_ids = ids;  // capture did not run anything
-      hipError_t ie = hipGraphInstantiate(&e.graph_exec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (ie != hipSuccess) {
-        e.graph_exec = nullptr;
-        return fail(U1ML_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
-      }
-      e.graph_key = key;
-    }
-    return U1ML_OK;
-  }
-  U1_HIP(hipGraphLaunch(e.graph_exec, e.stream));
-  for (auto& v : e.h_pass_ids) v += e.graph_metro_passes;
-  e.ml.valid = true;
-  return U1ML_OK;
+  U1_TRY(check_ml_args(e, 1, &th, &n_sub, n_metro, n_or));
+  U1_TRY(e.set_device());
+  std::vector<std::vector<int>> rl(e.n_lats);
+  for (int i = 0; i < e.n_lats; ++i)
+    for (int r = 1; r <= e.h_lats[i].T / 2 && r < e.h_lats[i].L; ++r) rl[i].push_back(r);
+  const bool keep = e.use_graphs;
+  e.use_graphs = keep && use_graph != 0;
+  int rc = e.multilevel(1, &th, &n_sub, n_metro, n_or, rl, {}, n_sweeps);
+  e.use_graphs = keep;
+  return rc;
 }
 
-int u1ml_batch_measure(u1ml_batch* b, int i, u1ml_observables* obs, double* correlator) {
+int u1ml_batch_measure(u1ml_batch* b, int i, u1ml_observables* obs, double* correlator, double* field_profile) {
   if (!b || i < 0 || i >= b->e.n_lats) return fail(U1ML_EINVAL, "batch_measure arguments");
-  Engine& e = b->e;
-  int rc = e.set_device();
-  if (rc) return rc;
-  if (correlator && !e.ml.valid) return fail(U1ML_ESTATE, "no cycle has run yet");
-  if (obs) {
-    std::vector<u1ml_observables> res;
-    if ((rc = e.observables(res))) return rc;
-    *obs = res[i];
-  }
-  U1_HIP(hipStreamSynchronize(e.stream));
-  if (correlator)
-    U1_HIP(hipMemcpy(correlator, e.ml.corr.as<double>() + (size_t)i * e.ml.max_r * 2, e.ml.nR[i] * 2 * sizeof(double),
-                     hipMemcpyDeviceToHost));
-  return U1ML_OK;
+  return read_results(b->e, i, obs, correlator, field_profile);
 }
 
 int u1ml_batch_get_links(u1ml_batch* b, int i, double* host) {
   if (!b || i < 0 || i >= b->e.n_lats || !host) return fail(U1ML_EINVAL, "batch_get_links arguments");
-  int rc = b->e.set_device();
-  return rc ? rc : b->e.get_links(i, host);
+  U1_TRY(b->e.set_device());
+  return b->e.get_links(i, host);
 }
 
 int u1ml_batch_set_links(u1ml_batch* b, int i, const double* host) {
   if (!b || i < 0 || i >= b->e.n_lats || !host) return fail(U1ML_EINVAL, "batch_set_links arguments");
-  int rc = b->e.set_device();
-  return rc ? rc : b->e.set_links(i, host);
+  U1_TRY(b->e.set_device());
+  return b->e.set_links(i, host);
 }
 
 int u1ml_batch_synchronize(u1ml_batch* b) {
   if (!b) return fail(U1ML_EINVAL, "batch is NULL");
-  int rc = b->e.set_device();
-  if (rc) return rc;
+  U1_TRY(b->e.set_device());
   U1_HIP(hipStreamSynchronize(b->e.stream));
   return U1ML_OK;
 }
@@ -996,18 +1040,16 @@ int u1ml_batch_synchronize(u1ml_batch* b) {
 void u1ml_batch_destroy(u1ml_batch* b) {
   if (!b) return;
   (void)hipSetDevice(b->e.device);
-  (void)hipStreamSynchronize(b->e.stream);
   delete b;
 }
 
 int u1ml_autotune(u1ml_lattice* lat, int* best_block) {
   if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
   Engine& e = lat->e;
-  int rc = e.set_device();
-  if (rc) return rc;
+  U1_TRY(e.set_device());
   if (e.debug) return fail(U1ML_ESTATE, "autotune with the debug log enabled");
   DevBuf save;
-  if ((rc = save.ensure(e.link_elems * e.elem_size()))) return rc;
+  U1_TRY(save.ensure(e.link_elems * e.elem_size()));
   U1_HIP(hipMemcpyAsync(save.p, e.links.p, e.link_elems * e.elem_size(), hipMemcpyDeviceToDevice, e.stream));
   const std::vector<uint64_t> ids = e.h_pass_ids;
   hipEvent_t a, z;
@@ -1015,15 +1057,15 @@ int u1ml_autotune(u1ml_lattice* lat, int* best_block) {
   U1_HIP(hipEventCreate(&z));
   const int cand[] = {64, 128, 256, 512, 1024};
   float best_ms = 1e30f;
-  int best = e.block;
+  int best = e.block, rc = U1ML_OK;
   for (int blk : cand) {
     e.block = blk;
-    if ((rc = e.sweep(1, 1, 0))) break;  // warm-up (builds the table)
+    if ((rc = e.sweep(1, 1, 0))) break;  // warm-up
     (void)hipEventRecord(a, e.stream);
-    for (int k = 0; k < 3; ++k)
-      if ((rc = e.sweep(1, 3, 0))) break;
+    for (int k = 0; k < 3 && !rc; ++k) rc = e.sweep(1, 3, 0);
     (void)hipEventRecord(z, e.stream);
     (void)hipEventSynchronize(z);
+    if (rc) break;
     float ms = 0;
     (void)hipEventElapsedTime(&ms, a, z);
     if (ms < best_ms) {
@@ -1034,6 +1076,7 @@ int u1ml_autotune(u1ml_lattice* lat, int* best_block) {
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(z);
   e.block = best;
+  e.drop_graphs();  // captured launches carry the old block size
   U1_HIP(hipMemcpyAsync(e.links.p, save.p, e.link_elems * e.elem_size(), hipMemcpyDeviceToDevice, e.stream));
   e.h_pass_ids = ids;
   int rc2 = e.upload_pass_ids();
@@ -1041,6 +1084,33 @@ int u1ml_autotune(u1ml_lattice* lat, int* best_block) {
   if (rc2) return rc2;
   g_tuned_block[std::make_tuple(e.h_lats[0].L, e.h_lats[0].T, e.prec)] = best;
   if (best_block) *best_block = best;
+  return U1ML_OK;
+}
+
+int u1ml_profile_sweeps(u1ml_lattice* lat, int n_sweeps, int n_metro, int n_or, double* avg_us) {
+  if (!lat || !avg_us || n_sweeps < 0 || n_metro < 0 || n_or < 0) return fail(U1ML_EINVAL, "profile arguments");
+  Engine& e = lat->e;
+  U1_TRY(e.set_device());
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
+  e.prof[0] = &ev[0];
+  e.prof[1] = &ev[1];
+  int rc = U1ML_OK;
+  for (int s = 0; s < n_sweeps && !rc; ++s) rc = e.sweep(n_metro, n_or, 0);
+  e.prof[0] = e.prof[1] = nullptr;
+  hipError_t se = hipStreamSynchronize(e.stream);
+  for (int k = 0; k < 2; ++k) {
+    double tot = 0.0;
+    for (auto& pr : ev[k]) {
+      float ms = 0.f;
+      if (se == hipSuccess && !rc) (void)hipEventElapsedTime(&ms, pr.first, pr.second);
+      tot += ms;
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+    avg_us[k] = ev[k].empty() ? 0.0 : 1e3 * tot / (double)ev[k].size();
+  }
+  if (rc) return rc;
+  U1_HIP(se);
   return U1ML_OK;
 }
 

@@ -50,6 +50,38 @@ __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
   return r;
 }
 
+// Philox4x32-10 (same publication; 32-bit multipliers and Weyl increments).
+struct U32x4 {
+  uint32_t v[4];
+};
+
+__device__ __forceinline__ U32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                               uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint32_t hi0 = __umulhi(M0, c0), lo0 = M0 * c0;
+    const uint32_t hi1 = __umulhi(M1, c2), lo1 = M1 * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  U32x4 r;
+  r.v[0] = c0; r.v[1] = c1; r.v[2] = c2; r.v[3] = c3;
+  return r;
+}
+
+// FP32 uniform in [0, 1) from the top 24 bits of a 32-bit word
+__device__ __forceinline__ float u01_f32_w32(uint32_t w) { return (float)(w >> 8) * 0x1.0p-24f; }
+
 // counter word 1: purpose << 32 | hit << 8 | mu
 constexpr uint64_t kPurposeInit = 1ULL << 32;
 constexpr uint64_t kPurposeMetro = 2ULL << 32;
@@ -176,6 +208,14 @@ struct LatDesc {
   uint64_t seed;
   uint64_t off;  // offset of links[0][0][0] in the batch link buffer (elements)
 };
+
+// Number of links of class (mu, parity) that are updated: spatial links on
+// time slices t = 0 (mod th) are frozen when th > 0.
+__host__ __device__ inline int free_sites(int L, int T, int mu, int th) {
+  const int per_slice = L * L * L / 2;
+  if (mu == 0 || th <= 0) return per_slice * T;
+  return per_slice * (T / th) * (th - 1);
+}
 
 struct Site {
   int t, x, y, z;

@@ -21,13 +21,23 @@ struct BlockTable {
 // --- link updates (sweep_f64.hip, sweep_f32.hip) ---
 hipError_t launch_init_f64(double* links, const LatDesc* lats, BlockTable bt, int hot, hipStream_t st);
 hipError_t launch_init_f32(float* links, const LatDesc* lats, BlockTable bt, int hot, hipStream_t st);
-hipError_t launch_class_pass_f64(int kind, double* links, const LatDesc* lats, BlockTable bt, int mu, int parity,
+// one class pass of a single lattice (geometry by value); log as in u1ml_set_debug
+hipError_t launch_class_pass_f64(int kind, double* links, const LatDesc& d, int block, int mu, int parity,
                                  int th_frozen, int n_hits, const uint64_t* pass_ids, uint8_t* log,
                                  hipStream_t st);
-hipError_t launch_class_pass_f32(int kind, float* links, const LatDesc* lats, BlockTable bt, int mu, int parity,
+hipError_t launch_class_pass_f32(int kind, float* links, const LatDesc& d, int block, int mu, int parity,
                                  int th_frozen, int n_hits, const uint64_t* pass_ids, uint8_t* log,
                                  hipStream_t st);
+// one class pass of every lattice of a batch; bt covers free_sites() of each lattice
+hipError_t launch_class_pass_batch_f64(int kind, double* links, const LatDesc* lats, BlockTable bt, int mu,
+                                       int parity, int th_frozen, int n_hits, const uint64_t* pass_ids,
+                                       hipStream_t st);
+hipError_t launch_class_pass_batch_f32(int kind, float* links, const LatDesc* lats, BlockTable bt, int mu,
+                                       int parity, int th_frozen, int n_hits, const uint64_t* pass_ids,
+                                       hipStream_t st);
 hipError_t launch_bump_pass_ids(uint64_t* pass_ids, int n, hipStream_t st);
+// fill n bytes with v (graph-safe replacement of a memset)
+hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t st);
 
 // --- measurements (measure.hip); prec selects the link element type ---
 // Per-lattice multilevel workspace layout (offsets in elements of the
@@ -58,31 +68,35 @@ hipError_t launch_poly_corr(const LatDesc* lats, BlockTable bt, const uint64_t* 
 // multilevel
 hipError_t launch_ml_lines(int prec, const void* links, const LatDesc* lats, const MLDesc* mls, BlockTable bt,
                            int inner_th, int sample, double* mlbuf, hipStream_t st);
+// sample_base: first stored inner sample of the current inner run (field runs keep them all)
 hipError_t launch_ml_fold(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int child_level, int parent_level,
-                          int n_levels, int child_is_inner, int n_child, const int* rvals, const double* mlbuf,
-                          double2* accbuf, hipStream_t st);
+                          int n_levels, int child_is_inner, int n_child, int sample_base, const int* rvals,
+                          const double* mlbuf, double2* accbuf, hipStream_t st);
 hipError_t launch_ml_zero(double2* accbuf, uint64_t n, hipStream_t st);
 hipError_t launch_ml_final(const LatDesc* lats, const MLDesc* mls, int n_lats, int max_r, int top_level,
                            const double2* accbuf, double* out, hipStream_t st);
 
-// field insertion by replay (single lattice)
-struct FieldDesc {
-  int n_rf;
-  int rf[8];      // field separations
-  int rf_k[8];    // index of each rf in the correlator r list
-  int n_levels;   // 1 or 2
-  int n_outer;    // n_0 for two levels (1 for one level)
-  int n_inner;    // samples per inner run
-  int ns_inner;   // inner slabs
-  int children;   // inner slabs per top slab (two levels) or ns_inner (one level)
-  int th_inner;
+// field insertion: per-lattice layout of the field buffer (offsets in doubles)
+struct FieldLat {
+  int ns;         // inner slabs
+  uint64_t oall;  // [n_samples][6][ns][L3] slab sums of the field operators
+  uint64_t tavg;  // double2 [n_outer][ns][L3][n_rf]
+  uint64_t w;     // double2 [n_outer][ns][L3][n_rf]
+  uint64_t g;     // double2 [n_rf][2][6][L2] Fourier-space accumulator
 };
-hipError_t launch_field_store_tavg(const LatDesc* lat, const MLDesc* ml, FieldDesc fd, int L3, int m,
-                                   const double* mlbuf, double2* tavg, hipStream_t st);
-hipError_t launch_field_weights(const LatDesc* lat, const MLDesc* ml, FieldDesc fd, int L3, const double2* tavg,
-                                const double2* accbuf, double2* w, hipStream_t st);
-hipError_t launch_field_sample(int prec, const void* links, const LatDesc* lat, const MLDesc* ml, FieldDesc fd,
-                               int L, int m, int sample, const double* mlbuf, const double2* w, double* oslab,
-                               double2* wslab, double2* fout, hipStream_t st);
+struct FieldParams {
+  int n_rf;
+  int rf[8];     // field separations
+  int rf_k[8];   // index of each rf in the lattice's r list
+  int n_levels;  // 1 or 2
+  int n_outer;   // n_0 for two levels, 1 for one level
+  int n_inner;   // samples per inner run
+};
+hipError_t launch_field_o(int prec, const void* links, const LatDesc* lats, const FieldLat* fls, BlockTable bt,
+                          int th_inner, int sample, double* fbuf, hipStream_t st);
+// contraction of all stored samples of one lattice into F [n_rf][2][6][L][L] (complex)
+hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,
+                                 FieldParams fp, int L, const double* mlbuf, const double2* accbuf, double* fbuf,
+                                 double2* scratch, size_t scratch_elems, double2* F, hipStream_t st);
 
 }  // namespace u1ml

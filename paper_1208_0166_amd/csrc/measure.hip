@@ -6,10 +6,13 @@
 //    C(r) = L^-3 sum_x P*(x) P(x + r e_x);
 //  * multilevel (Sec. 2.2): time-line angle sums of the innermost slabs per
 //    sample, slab averages of the two-link products T(x0, r) of Eq. (8) and
-//    their nested products, and the field insertion of Eq. (9) evaluated by
-//    replaying the update sequence with precomputed weights.
+//    their nested products, and the field insertion of Eq. (9): every inner
+//    sample's time lines and field slab sums stay in HBM and are contracted
+//    with the final weights after the run, by 2D DFTs over the mediator plane.
 // All sums are FP64 with a fixed reduction order (results do not depend on
 // timing).  Links are read as FP64 or FP32 angles.
+#include <algorithm>
+
 #include "engine.h"
 
 namespace u1ml {
@@ -221,7 +224,7 @@ __device__ __forceinline__ double2 inner_avg(const double* ell, int n_samples, i
 // parent_level == n_levels denotes the top (one slab spanning all of T).
 __global__ void ml_fold_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls,
                                const int2* __restrict__ blocks, int child_level, int parent_level, int n_levels,
-                               int child_is_inner, int n_child, const int* __restrict__ rvals,
+                               int child_is_inner, int n_child, int sample_base, const int* __restrict__ rvals,
                                const double* __restrict__ mlbuf, double2* __restrict__ accbuf) {
   const int2 bk = blocks[blockIdx.x];
   const LatDesc d = lats[bk.x];
@@ -241,7 +244,7 @@ __global__ void ml_fold_kernel(const LatDesc* __restrict__ lats, const MLDesc* _
     const int cs = S * children + j;
     double2 avg;
     if (child_is_inner) {
-      avg = inner_avg(mlbuf + m.ell, n_child, ns_child, d.L3, cs, x0, x0r);
+      avg = inner_avg(mlbuf + m.ell + (size_t)sample_base * ns_child * d.L3, n_child, ns_child, d.L3, cs, x0, x0r);
     } else {
       double2* c = accbuf + m.acc[child_level] + ((size_t)cs * d.L3 + x0) * m.nR + k;
       avg = make_double2(c->x * inv, c->y * inv);
@@ -283,74 +286,29 @@ __global__ void ml_final_kernel(const LatDesc* __restrict__ lats, const MLDesc* 
 }
 
 // ---------------------------------------------------------------------------
-// field insertion (single lattice)
+// field insertion: every inner sample keeps its time-line sums (ell) and its
+// slab sums of the field operators; after the run they are contracted with
+// the final weights, as a correlation over the mediator plane evaluated by 2D
+// discrete Fourier transforms in (y, z).
 // ---------------------------------------------------------------------------
-// tavg[((m * ns + s) * L3 + x0) * n_rf + f] = inner average of T at separation rf[f]
-__global__ void field_store_tavg_kernel(const LatDesc* __restrict__ lat, const MLDesc* __restrict__ mlp,
-                                        FieldDesc fd, int m, const double* __restrict__ mlbuf,
-                                        double2* __restrict__ tavg) {
-  const LatDesc d = *lat;
-  const MLDesc ml = *mlp;
-  const int item = blockIdx.x * blockDim.x + threadIdx.x;
-  if (item >= fd.ns_inner * d.L3 * fd.n_rf) return;
-  const int f = item % fd.n_rf;
-  const int x0 = (item / fd.n_rf) % d.L3;
-  const int s = item / (fd.n_rf * d.L3);
-  const int x0r = shift_x(d, x0, fd.rf[f]);
-  tavg[(((size_t)m * fd.ns_inner + s) * d.L3 + x0) * fd.n_rf + f] =
-      inner_avg(mlbuf + ml.ell, fd.n_inner, fd.ns_inner, d.L3, s, x0, x0r);
-}
-
-// weight of an insertion in inner slab s during outer iteration m:
-//   one level:  prod_{s' != s} [T]_{s'} / (n V)
-//   two levels: prod_{j != k} A_j * prod_{s' in k, s' != s} [T]_{s',m} / (n_0 n_1 V)
-// with k the top slab holding s and A_j the top-level averages.
-__global__ void field_weights_kernel(const LatDesc* __restrict__ lat, const MLDesc* __restrict__ mlp, FieldDesc fd,
-                                     const double2* __restrict__ tavg, const double2* __restrict__ accbuf,
-                                     double2* __restrict__ w) {
-  const LatDesc d = *lat;
-  const MLDesc ml = *mlp;
-  const int item = blockIdx.x * blockDim.x + threadIdx.x;
-  if (item >= fd.n_outer * fd.ns_inner * d.L3 * fd.n_rf) return;
-  const int f = item % fd.n_rf;
-  const int x0 = (item / fd.n_rf) % d.L3;
-  const int s = (item / (fd.n_rf * d.L3)) % fd.ns_inner;
-  const int m = item / (fd.n_rf * d.L3 * fd.ns_inner);
-  const int k = s / fd.children;
-  double2 p = make_double2(1.0, 0.0);
-  for (int j = 0; j < fd.children; ++j) {
-    const int sp = k * fd.children + j;
-    if (sp == s) continue;
-    p = cmul(p, tavg[(((size_t)m * fd.ns_inner + sp) * d.L3 + x0) * fd.n_rf + f]);
-  }
-  double norm = (double)fd.n_inner * (double)d.V2 * 2.0;
-  if (fd.n_levels == 2) {
-    const int ntop = ml.ns[0];
-    const double inv = 1.0 / (double)fd.n_outer;
-    for (int j = 0; j < ntop; ++j) {
-      if (j == k) continue;
-      const double2 a = accbuf[ml.acc[0] + ((size_t)j * d.L3 + x0) * ml.nR + fd.rf_k[f]];
-      p = cmul(p, make_double2(a.x * inv, a.y * inv));
-    }
-    norm *= (double)fd.n_outer;
-  }
-  w[(((size_t)m * fd.ns_inner + s) * d.L3 + x0) * fd.n_rf + f] = make_double2(p.x / norm, p.y / norm);
-}
-
-// oslab[(c * ns + s) * L3 + y] = sum over the times t of inner slab s of O_c(y, t)
+// oall[((sample * 6 + c) * ns + s) * L3 + y] = sum over the times t of inner
+// slab s of O_c(y, t), O_c = sqrt(beta) Im P_munu (Eq. (5)).
 template <typename R>
-__global__ void field_oslab_kernel(const R* __restrict__ links, const LatDesc* __restrict__ lat, FieldDesc fd,
-                                   double* __restrict__ oslab) {
-  const LatDesc d = *lat;
-  const int item = blockIdx.x * blockDim.x + threadIdx.x;
-  if (item >= fd.ns_inner * d.L3) return;
+__global__ void field_o_kernel(const R* __restrict__ links, const LatDesc* __restrict__ lats,
+                               const FieldLat* __restrict__ fls, const int2* __restrict__ blocks, int th_inner,
+                               int sample, double* __restrict__ fbuf) {
+  const int2 bk = blocks[blockIdx.x];
+  const LatDesc d = lats[bk.x];
+  const FieldLat fl = fls[bk.x];
+  const int item = bk.y + (int)threadIdx.x;
+  if (item >= fl.ns * d.L3) return;
   const int s = item / d.L3, y3 = item - s * d.L3;
   Site st;
   st.x = y3 % d.L;
   st.y = (y3 / d.L) % d.L;
   st.z = y3 / (d.L * d.L);
   double o[6] = {0, 0, 0, 0, 0, 0};
-  for (int t = s * fd.th_inner; t < (s + 1) * fd.th_inner; ++t) {
+  for (int t = s * th_inner; t < (s + 1) * th_inner; ++t) {
     st.t = t;
     o[0] += sin(plaq_angle(links, d, st, 0, 1));
     o[1] += sin(plaq_angle(links, d, st, 0, 2));
@@ -359,62 +317,204 @@ __global__ void field_oslab_kernel(const R* __restrict__ links, const LatDesc* _
     o[4] -= sin(plaq_angle(links, d, st, 1, 3));
     o[5] += sin(plaq_angle(links, d, st, 1, 2));
   }
-  for (int c = 0; c < 6; ++c) oslab[((size_t)c * fd.ns_inner + s) * d.L3 + y3] = d.sqrt_beta * o[c];
+  double* out = fbuf + fl.oall + (size_t)sample * 6 * fl.ns * d.L3;
+  for (int c = 0; c < 6; ++c) out[((size_t)c * fl.ns + s) * d.L3 + y3] = d.sqrt_beta * o[c];
 }
 
-// wslab[(f * ns + s) * L3 + x0] = w[m][s][x0][f] * T_i(x0, s; rf[f]) for the current sample
-__global__ void field_wslab_kernel(const LatDesc* __restrict__ lat, const MLDesc* __restrict__ mlp, FieldDesc fd,
-                                   int m, int sample, const double* __restrict__ mlbuf,
-                                   const double2* __restrict__ w, double2* __restrict__ wslab) {
+// tavg[((m * ns + s) * L3 + x0) * n_rf + f] = average over the n_inner samples
+// of outer iteration m of T(x0, rf[f]) in inner slab s
+__global__ void field_tavg_kernel(const LatDesc* __restrict__ lat, const MLDesc* __restrict__ mlp,
+                                  const FieldLat* __restrict__ flp, FieldParams fp, const double* __restrict__ mlbuf,
+                                  double* __restrict__ fbuf) {
   const LatDesc d = *lat;
   const MLDesc ml = *mlp;
+  const FieldLat fl = *flp;
   const int item = blockIdx.x * blockDim.x + threadIdx.x;
-  if (item >= fd.n_rf * fd.ns_inner * d.L3) return;
-  const int x0 = item % d.L3;
-  const int s = (item / d.L3) % fd.ns_inner;
-  const int f = item / (d.L3 * fd.ns_inner);
-  const double* e = mlbuf + ml.ell + ((size_t)sample * fd.ns_inner + s) * d.L3;
-  const double2 t = cexpi(e[shift_x(d, x0, fd.rf[f])] - e[x0]);
-  const double2 ww = w[(((size_t)m * fd.ns_inner + s) * d.L3 + x0) * fd.n_rf + f];
-  wslab[item] = cmul(ww, t);
+  if (item >= fp.n_outer * fl.ns * d.L3 * fp.n_rf) return;
+  const int f = item % fp.n_rf;
+  const int x0 = (item / fp.n_rf) % d.L3;
+  const int s = (item / (fp.n_rf * d.L3)) % fl.ns;
+  const int m = item / (fp.n_rf * d.L3 * fl.ns);
+  const double* ell = mlbuf + ml.ell + (size_t)m * fp.n_inner * fl.ns * d.L3;
+  ((double2*)(fbuf + fl.tavg))[item] = inner_avg(ell, fp.n_inner, fl.ns, d.L3, s, x0, shift_x(d, x0, fp.rf[f]));
 }
 
-// fout[(((f * 2 + plane) * 6 + c) * L + dy) * L + dz] +=
-//   sum_s sum_x0 wslab[f][s][x0] * oslab[c][s][x0 + (m_plane, dy, dz)]
-__global__ void field_contract_kernel(const LatDesc* __restrict__ lat, FieldDesc fd,
-                                      const double* __restrict__ oslab, const double2* __restrict__ wslab,
-                                      double2* __restrict__ fout) {
+// weight of an insertion in inner slab s during outer iteration m:
+//   one level:  prod_{s' != s} [T]_{s'} / (n V)
+//   two levels: prod_{j != k} A_j * prod_{s' in k, s' != s} [T]_{s',m} / (n_0 n_1 V)
+// with k the top slab holding s and A_j the top-level averages.
+__global__ void field_weights_kernel(const LatDesc* __restrict__ lat, const MLDesc* __restrict__ mlp,
+                                     const FieldLat* __restrict__ flp, FieldParams fp,
+                                     const double2* __restrict__ accbuf, double* __restrict__ fbuf) {
   const LatDesc d = *lat;
-  const int L = d.L, L2 = L * L;
+  const MLDesc ml = *mlp;
+  const FieldLat fl = *flp;
   const int item = blockIdx.x * blockDim.x + threadIdx.x;
-  if (item >= fd.n_rf * 2 * 6 * L2) return;
-  const int dz = item % L, dy = (item / L) % L;
+  if (item >= fp.n_outer * fl.ns * d.L3 * fp.n_rf) return;
+  const int f = item % fp.n_rf;
+  const int x0 = (item / fp.n_rf) % d.L3;
+  const int s = (item / (fp.n_rf * d.L3)) % fl.ns;
+  const int m = item / (fp.n_rf * d.L3 * fl.ns);
+  const int children = fp.n_levels == 2 ? fl.ns / ml.ns[0] : fl.ns;
+  const int k = s / children;
+  const double2* tavg = (const double2*)(fbuf + fl.tavg);
+  double2 p = make_double2(1.0, 0.0);
+  for (int j = 0; j < children; ++j) {
+    const int sp = k * children + j;
+    if (sp == s) continue;
+    p = cmul(p, tavg[(((size_t)m * fl.ns + sp) * d.L3 + x0) * fp.n_rf + f]);
+  }
+  double norm = (double)fp.n_inner * (double)d.V2 * 2.0;
+  if (fp.n_levels == 2) {
+    const int ntop = ml.ns[0];
+    const double inv = 1.0 / (double)fp.n_outer;
+    for (int j = 0; j < ntop; ++j) {
+      if (j == k) continue;
+      const double2 a = accbuf[ml.acc[0] + ((size_t)j * d.L3 + x0) * ml.nR + fp.rf_k[f]];
+      p = cmul(p, make_double2(a.x * inv, a.y * inv));
+    }
+    norm *= (double)fp.n_outer;
+  }
+  ((double2*)(fbuf + fl.w))[item] = make_double2(p.x / norm, p.y / norm);
+}
+
+// wbuf[((k * n_rf + f) * ns + s) * L3 + x0] = w[m][s][x0][f] * T_sample(x0, s; rf[f])
+// for the samples sample0 + k, k < nk
+__global__ void field_wplanes_kernel(const LatDesc* __restrict__ lat, const MLDesc* __restrict__ mlp,
+                                     const FieldLat* __restrict__ flp, FieldParams fp, int sample0, int nk,
+                                     const double* __restrict__ mlbuf, const double* __restrict__ fbuf,
+                                     double2* __restrict__ wbuf) {
+  const LatDesc d = *lat;
+  const MLDesc ml = *mlp;
+  const FieldLat fl = *flp;
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= nk * fp.n_rf * fl.ns * d.L3) return;
+  const int x0 = item % d.L3;
+  const int s = (item / d.L3) % fl.ns;
+  const int f = (item / (d.L3 * fl.ns)) % fp.n_rf;
+  const int k = item / (d.L3 * fl.ns * fp.n_rf);
+  const int sample = sample0 + k;
+  const int m = sample / fp.n_inner;
+  const double* e = mlbuf + ml.ell + ((size_t)sample * fl.ns + s) * d.L3;
+  const double2 t = cexpi(e[shift_x(d, x0, fp.rf[f])] - e[x0]);
+  const double2 ww = ((const double2*)(fbuf + fl.w))[(((size_t)m * fl.ns + s) * d.L3 + x0) * fp.n_rf + f];
+  wbuf[item] = cmul(ww, t);
+}
+
+// 2D DFT over (y, z) of the x-planes of [n_planes / L][L3] arrays (site order
+// x fastest): out[b][p][q] = sum_{y,z} in_b(x, y, z) exp(-2 pi i (p y + q z) / L)
+// with b = (array * L + x).  One block per plane; LDS holds the L twiddles and
+// the L^2 complex results of the transform along z (L <= 62 keeps it below
+// 64 KiB).
+template <typename In>
+__device__ __forceinline__ double2 as_c(In v);
+template <>
+__device__ __forceinline__ double2 as_c<double>(double v) {
+  return make_double2(v, 0.0);
+}
+template <>
+__device__ __forceinline__ double2 as_c<double2>(double2 v) {
+  return v;
+}
+
+template <typename In>
+__global__ void dft2_kernel(const In* __restrict__ in, int L, double2* __restrict__ out) {
+  extern __shared__ double2 sm[];
+  const int L2 = L * L;
+  double2* tw = sm;       // L twiddles exp(-2 pi i k / L)
+  double2* mid = sm + L;  // [y][q]
+  const int b = blockIdx.x;
+  const int arr = b / L, x = b - arr * L;
+  const In* src = in + (size_t)arr * L2 * L;
+  for (int k = threadIdx.x; k < L; k += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)k / (double)L, &sn, &cs);
+    tw[k] = make_double2(cs, -sn);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < L2; i += blockDim.x) {
+    const int y = i / L, q = i - y * L;
+    double re = 0.0, im = 0.0;
+    int k = 0;
+    for (int z = 0; z < L; ++z) {
+      const double2 v = as_c<In>(src[(size_t)(z * L + y) * L + x]), w = tw[k];
+      re += v.x * w.x - v.y * w.y;
+      im += v.x * w.y + v.y * w.x;
+      k += q;
+      k -= (k >= L) ? L : 0;
+    }
+    mid[i] = make_double2(re, im);
+  }
+  __syncthreads();
+  double2* dst = out + (size_t)b * L2;
+  for (int i = threadIdx.x; i < L2; i += blockDim.x) {
+    const int p = i / L, q = i - p * L;
+    double re = 0.0, im = 0.0;
+    int k = 0;
+    for (int y = 0; y < L; ++y) {
+      const double2 v = mid[y * L + q], w = tw[k];
+      re += v.x * w.x - v.y * w.y;
+      im += v.x * w.y + v.y * w.x;
+      k += p;
+      k -= (k >= L) ? L : 0;
+    }
+    dst[i] = make_double2(re, im);
+  }
+}
+
+// G[((f * 2 + plane) * 6 + c) * L2 + (p, q)] +=
+//   sum_k sum_s sum_x What[k][f][s][x](-p, -q) * Ohat[k][c][s][x + m](p, q)
+__global__ void field_gacc_kernel(FieldParams fp, int L, int ns, int nk, const double2* __restrict__ what,
+                                  const double2* __restrict__ ohat, double2* __restrict__ G) {
+  const int L2 = L * L;
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= fp.n_rf * 12 * L2) return;
+  const int pq = item % L2;
   const int c = (item / L2) % 6;
   const int plane = (item / (6 * L2)) % 2;
   const int f = item / (12 * L2);
-  const int r = fd.rf[f];
+  const int p = pq / L, q = pq - p * L;
+  const int mpq = ((L - p) % L) * L + (L - q) % L;
+  const int r = fp.rf[f];
   const int mx = plane == 0 ? (r - 1) / 2 : r / 2;
   double re = 0.0, im = 0.0;
-  for (int s = 0; s < fd.ns_inner; ++s) {
-    const double2* W = wslab + ((size_t)f * fd.ns_inner + s) * d.L3;
-    const double* O = oslab + ((size_t)c * fd.ns_inner + s) * d.L3;
-    for (int z = 0; z < L; ++z) {
-      const int zz = (z + dz) % L;
-      for (int y = 0; y < L; ++y) {
-        const int yy = (y + dy) % L;
-        const double2* Wr = W + (z * L + y) * L;
-        const double* Or = O + (zz * L + yy) * L;
-        for (int x = 0; x < L; ++x) {
-          const int xx = (x + mx) % L;
-          const double o = Or[xx];
-          re += Wr[x].x * o;
-          im += Wr[x].y * o;
-        }
+  for (int k = 0; k < nk; ++k)
+    for (int s = 0; s < ns; ++s) {
+      const double2* W = what + ((size_t)(k * fp.n_rf + f) * ns + s) * L * L2;
+      const double2* O = ohat + ((size_t)(k * 6 + c) * ns + s) * L * L2;
+      for (int x = 0; x < L; ++x) {
+        int xx = x + mx;
+        xx -= (xx >= L) ? L : 0;
+        const double2 w = W[(size_t)x * L2 + mpq];
+        const double2 o = O[(size_t)xx * L2 + pq];
+        re += w.x * o.x - w.y * o.y;
+        im += w.x * o.y + w.y * o.x;
       }
     }
-  }
-  fout[item].x += re;
-  fout[item].y += im;
+  G[item].x += re;
+  G[item].y += im;
+}
+
+// F[((f * 2 + plane) * 6 + c) * L2 + (dy, dz)] = L^-2 sum_{p,q} G(p, q) exp(+2 pi i (p dy + q dz) / L)
+__global__ void field_final_kernel(FieldParams fp, int L, const double2* __restrict__ G, double2* __restrict__ F) {
+  const int L2 = L * L;
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= fp.n_rf * 12 * L2) return;
+  const int dd = item % L2;
+  const int dy = dd / L, dz = dd - dy * L;
+  const double2* g = G + (size_t)(item / L2) * L2;
+  double re = 0.0, im = 0.0;
+  for (int p = 0; p < L; ++p)
+    for (int q = 0; q < L; ++q) {
+      const int k = (p * dy + q * dz) % L;
+      double sn, cs;
+      sincospi(2.0 * (double)k / (double)L, &sn, &cs);
+      const double2 v = g[p * L + q];
+      re += v.x * cs - v.y * sn;
+      im += v.x * sn + v.y * cs;
+    }
+  const double inv = 1.0 / (double)L2;
+  F[item] = make_double2(re * inv, im * inv);
 }
 
 inline int blocks_for(uint64_t n, int b) { return (int)((n + b - 1) / b); }
@@ -472,10 +572,10 @@ hipError_t launch_ml_lines(int prec, const void* links, const LatDesc* lats, con
 }
 
 hipError_t launch_ml_fold(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int child_level, int parent_level,
-                          int n_levels, int child_is_inner, int n_child, const int* rvals, const double* mlbuf,
-                          double2* accbuf, hipStream_t st) {
+                          int n_levels, int child_is_inner, int n_child, int sample_base, const int* rvals,
+                          const double* mlbuf, double2* accbuf, hipStream_t st) {
   hipLaunchKernelGGL(ml_fold_kernel, dim3(bt.n_blocks), dim3(bt.block), 0, st, lats, mls, bt.dev, child_level,
-                     parent_level, n_levels, child_is_inner, n_child, rvals, mlbuf, accbuf);
+                     parent_level, n_levels, child_is_inner, n_child, sample_base, rvals, mlbuf, accbuf);
   return hipGetLastError();
 }
 
@@ -492,39 +592,50 @@ hipError_t launch_ml_final(const LatDesc* lats, const MLDesc* mls, int n_lats, i
   return hipGetLastError();
 }
 
-hipError_t launch_field_store_tavg(const LatDesc* lat, const MLDesc* ml, FieldDesc fd, int L3, int m,
-                                   const double* mlbuf, double2* tavg, hipStream_t st) {
-  const uint64_t n = (uint64_t)fd.ns_inner * L3 * fd.n_rf;
-  hipLaunchKernelGGL(field_store_tavg_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, lat, ml, fd, m, mlbuf,
-                     tavg);
-  return hipGetLastError();
-}
-
-hipError_t launch_field_weights(const LatDesc* lat, const MLDesc* ml, FieldDesc fd, int L3, const double2* tavg,
-                                const double2* accbuf, double2* w, hipStream_t st) {
-  const uint64_t n = (uint64_t)fd.n_outer * fd.ns_inner * L3 * fd.n_rf;
-  hipLaunchKernelGGL(field_weights_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, lat, ml, fd, tavg, accbuf,
-                     w);
-  return hipGetLastError();
-}
-
-hipError_t launch_field_sample(int prec, const void* links, const LatDesc* lat, const MLDesc* ml, FieldDesc fd,
-                               int L, int m, int sample, const double* mlbuf, const double2* w, double* oslab,
-                               double2* wslab, double2* fout, hipStream_t st) {
-  const uint64_t L3 = (uint64_t)L * L * L;
-  const uint64_t no = (uint64_t)fd.ns_inner * L3;
+hipError_t launch_field_o(int prec, const void* links, const LatDesc* lats, const FieldLat* fls, BlockTable bt,
+                          int th_inner, int sample, double* fbuf, hipStream_t st) {
+  if (bt.n_blocks == 0) return hipSuccess;
   if (prec == kFP64)
-    hipLaunchKernelGGL(field_oslab_kernel<double>, dim3(blocks_for(no, 256)), dim3(256), 0, st,
-                       (const double*)links, lat, fd, oslab);
+    hipLaunchKernelGGL(field_o_kernel<double>, dim3(bt.n_blocks), dim3(bt.block), 0, st, (const double*)links, lats,
+                       fls, bt.dev, th_inner, sample, fbuf);
   else
-    hipLaunchKernelGGL(field_oslab_kernel<float>, dim3(blocks_for(no, 256)), dim3(256), 0, st,
-                       (const float*)links, lat, fd, oslab);
-  const uint64_t nw = (uint64_t)fd.n_rf * no;
-  hipLaunchKernelGGL(field_wslab_kernel, dim3(blocks_for(nw, 256)), dim3(256), 0, st, lat, ml, fd, m, sample,
-                     mlbuf, w, wslab);
-  const uint64_t nf = (uint64_t)fd.n_rf * 12 * L * L;
-  hipLaunchKernelGGL(field_contract_kernel, dim3(blocks_for(nf, 64)), dim3(64), 0, st, lat, fd, oslab, wslab,
-                     fout);
+    hipLaunchKernelGGL(field_o_kernel<float>, dim3(bt.n_blocks), dim3(bt.block), 0, st, (const float*)links, lats,
+                       fls, bt.dev, th_inner, sample, fbuf);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,
+                                 FieldParams fp, int L, const double* mlbuf, const double2* accbuf, double* fbuf,
+                                 double2* scratch, size_t scratch_elems, double2* F, hipStream_t st) {
+  const uint64_t L3 = (uint64_t)L * L * L, L2 = (uint64_t)L * L;
+  const int ns = hfl.ns;
+  const uint64_t nt = (uint64_t)fp.n_outer * ns * L3 * fp.n_rf;
+  hipLaunchKernelGGL(field_tavg_kernel, dim3(blocks_for(nt, 256)), dim3(256), 0, st, lat, ml, fl, fp, mlbuf, fbuf);
+  hipLaunchKernelGGL(field_weights_kernel, dim3(blocks_for(nt, 256)), dim3(256), 0, st, lat, ml, fl, fp, accbuf,
+                     fbuf);
+  double2* G = (double2*)(fbuf + hfl.g);
+  const uint64_t ng = (uint64_t)fp.n_rf * 12 * L2;
+  hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(ng, 256)), dim3(256), 0, st, G, ng);
+  // per sample: W planes (n_rf ns L3) + their DFT + O DFT (6 ns L3)
+  const uint64_t per_sample = (uint64_t)(2 * fp.n_rf + 6) * ns * L3;
+  const int chunk = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, scratch_elems / per_sample));
+  const int n_samples = fp.n_outer * fp.n_inner;
+  const size_t shm = (size_t)(L + L2) * sizeof(double2);
+  for (int s0 = 0; s0 < n_samples; s0 += chunk) {
+    const int nk = std::min(chunk, n_samples - s0);
+    double2* wbuf = scratch;
+    double2* what = wbuf + (uint64_t)nk * fp.n_rf * ns * L3;
+    double2* ohat = what + (uint64_t)nk * fp.n_rf * ns * L3;
+    const uint64_t nw = (uint64_t)nk * fp.n_rf * ns * L3;
+    hipLaunchKernelGGL(field_wplanes_kernel, dim3(blocks_for(nw, 256)), dim3(256), 0, st, lat, ml, fl, fp, s0, nk,
+                       mlbuf, fbuf, wbuf);
+    hipLaunchKernelGGL(dft2_kernel<double2>, dim3((unsigned)((uint64_t)nk * fp.n_rf * ns * L)), dim3(256), shm, st,
+                       wbuf, L, what);
+    hipLaunchKernelGGL(dft2_kernel<double>, dim3((unsigned)((uint64_t)nk * 6 * ns * L)), dim3(256), shm, st,
+                       fbuf + hfl.oall + (size_t)s0 * 6 * ns * L3, L, ohat);
+    hipLaunchKernelGGL(field_gacc_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, ns, nk, what, ohat, G);
+  }
+  hipLaunchKernelGGL(field_final_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, G, F);
   return hipGetLastError();
 }
 

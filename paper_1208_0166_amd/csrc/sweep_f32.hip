@@ -11,17 +11,22 @@ hipError_t launch_init_f32(float* links, const LatDesc* lats, BlockTable bt, int
   return hipGetLastError();
 }
 
-hipError_t launch_class_pass_f32(int kind, float* links, const LatDesc* lats, BlockTable bt, int mu, int parity,
+hipError_t launch_class_pass_f32(int kind, float* links, const LatDesc& d, int block, int mu, int parity,
                                  int th_frozen, int n_hits, const uint64_t* pass_ids, uint8_t* log,
                                  hipStream_t st) {
-  if (bt.n_blocks == 0) return hipSuccess;
   if (kind == kMetropolis)
-    hipLaunchKernelGGL((class_pass_kernel<Fast32, 0>), dim3(bt.n_blocks), dim3(bt.block), 0, st, links, lats,
-                       bt.dev, mu, parity, th_frozen, n_hits, pass_ids, log);
-  else
-    hipLaunchKernelGGL((class_pass_kernel<Fast32, 1>), dim3(bt.n_blocks), dim3(bt.block), 0, st, links, lats,
-                       bt.dev, mu, parity, th_frozen, n_hits, pass_ids, log);
-  return hipGetLastError();
+    return launch_pass_single<Fast32, 0>(links, d, block, mu, parity, th_frozen, n_hits, pass_ids, log, st);
+  return launch_pass_single<Fast32, 1>(links, d, block, mu, parity, th_frozen, n_hits, pass_ids, log, st);
+}
+
+hipError_t launch_class_pass_batch_f32(int kind, float* links, const LatDesc* lats, BlockTable bt, int mu,
+                                       int parity, int th_frozen, int n_hits, const uint64_t* pass_ids,
+                                       hipStream_t st) {
+  if (kind == kMetropolis)
+    return launch_pass_batch<Fast32, 0>(links, lats, bt.dev, bt.n_blocks, bt.block, mu, parity, th_frozen, n_hits,
+                                   pass_ids, st);
+  return launch_pass_batch<Fast32, 1>(links, lats, bt.dev, bt.n_blocks, bt.block, mu, parity, th_frozen, n_hits,
+                                 pass_ids, st);
 }
 
 }  // namespace u1ml

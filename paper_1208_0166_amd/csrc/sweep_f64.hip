@@ -12,22 +12,38 @@ hipError_t launch_init_f64(double* links, const LatDesc* lats, BlockTable bt, in
   return hipGetLastError();
 }
 
-hipError_t launch_class_pass_f64(int kind, double* links, const LatDesc* lats, BlockTable bt, int mu, int parity,
+hipError_t launch_class_pass_f64(int kind, double* links, const LatDesc& d, int block, int mu, int parity,
                                  int th_frozen, int n_hits, const uint64_t* pass_ids, uint8_t* log,
                                  hipStream_t st) {
-  if (bt.n_blocks == 0) return hipSuccess;
   if (kind == kMetropolis)
-    hipLaunchKernelGGL((class_pass_kernel<Det64, 0>), dim3(bt.n_blocks), dim3(bt.block), 0, st, links, lats,
-                       bt.dev, mu, parity, th_frozen, n_hits, pass_ids, log);
-  else
-    hipLaunchKernelGGL((class_pass_kernel<Det64, 1>), dim3(bt.n_blocks), dim3(bt.block), 0, st, links, lats,
-                       bt.dev, mu, parity, th_frozen, n_hits, pass_ids, log);
-  return hipGetLastError();
+    return launch_pass_single<Det64, 0>(links, d, block, mu, parity, th_frozen, n_hits, pass_ids, log, st);
+  return launch_pass_single<Det64, 1>(links, d, block, mu, parity, th_frozen, n_hits, pass_ids, log, st);
+}
+
+hipError_t launch_class_pass_batch_f64(int kind, double* links, const LatDesc* lats, BlockTable bt, int mu,
+                                       int parity, int th_frozen, int n_hits, const uint64_t* pass_ids,
+                                       hipStream_t st) {
+  if (kind == kMetropolis)
+    return launch_pass_batch<Det64, 0>(links, lats, bt.dev, bt.n_blocks, bt.block, mu, parity, th_frozen, n_hits,
+                                   pass_ids, st);
+  return launch_pass_batch<Det64, 1>(links, lats, bt.dev, bt.n_blocks, bt.block, mu, parity, th_frozen, n_hits,
+                                 pass_ids, st);
 }
 
 __global__ void bump_pass_ids_kernel(uint64_t* pass_ids, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) pass_ids[i] += 1;
+}
+
+__global__ void fill_u8_kernel(uint8_t* p, size_t n, uint8_t v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u8_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
 }
 
 hipError_t launch_bump_pass_ids(uint64_t* pass_ids, int n, hipStream_t st) {

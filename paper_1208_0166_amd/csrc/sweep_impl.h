@@ -1,13 +1,18 @@
 // sweep_impl.h -- checkerboard link-update kernels (Metropolis and
 // overrelaxation) for compact U(1) with the Wilson action, Eq. (3).
 //
-// One launch updates one class (mu, parity) on every lattice of a batch.
-// Links of one class never share a plaquette, so the class is updated in
-// parallel with no ordering constraint.  The arithmetic policy P fixes the
-// number type and the elementary functions:
+// One launch updates one class (mu, parity): links of one class never share
+// a plaquette, so the class is updated in parallel with no ordering
+// constraint.  Kernels are specialised per direction mu so that the staple's
+// six plaquettes unroll with compile-time directions, and neighbour sites are
+// found as n +- stride (32-bit, periodic corrections precomputed per site).
+// With frozen slabs (multilevel) threads are mapped onto the free links only.
+//
+// The arithmetic policy P fixes the number type and elementary functions:
 //   Det64  - FP64 angles, deterministic sin/cos/atan2 (translation unit built
 //            with -ffp-contract=off): the reproducible update path;
-//   Fast32 - FP32 angles, hardware transcendentals: the fast update path.
+//   Fast32 - FP32 angles, hardware sin/cos/exp and a short atan2 series: the
+//            fast update path.
 #pragma once
 
 #include "device_common.h"
@@ -20,7 +25,14 @@ struct Det64 {
   static __device__ __forceinline__ double atan2(double y, double x) { return det_atan2(y, x); }
   static __device__ __forceinline__ double expo(double x) { return ::exp(x); }
   static __device__ __forceinline__ double wrap(double a) { return wrap_f64(a); }
-  static __device__ __forceinline__ double uni(uint64_t w) { return u01_f64(w); }
+  // Metropolis uniforms (u1, u2): Philox4x64-10, counter (n, 2<<32 | hit<<8 | mu, pass_id, 0),
+  // key (seed, 0); u = (w >> 11) 2^-53 from words 0 and 1
+  static __device__ __forceinline__ void metro_uniforms(uint32_t n, int hit, int mu, uint64_t pass_id,
+                                                        uint64_t seed, double& u1, double& u2) {
+    const U64x4 w = philox4x64_10(n, kPurposeMetro | ((uint64_t)hit << 8) | (uint64_t)mu, pass_id, 0, seed, 0);
+    u1 = u01_f64(w.v[0]);
+    u2 = u01_f64(w.v[1]);
+  }
   static __device__ __forceinline__ double from_f64(double v) { return v; }
 };
 
@@ -29,14 +41,46 @@ struct Fast32 {
   static constexpr float kPiF = 3.14159265358979f;
   static constexpr float kTwoPiF = 6.28318530717959f;
   static __device__ __forceinline__ void sincos(float x, float& s, float& c) { __sincosf(x, &s, &c); }
-  static __device__ __forceinline__ float atan2(float y, float x) { return ::atan2f(y, x); }
+  // atan2 to ~1e-7 rad: fold to t in [0, 1], t -> (t-1)/(t+1) above tan(pi/8),
+  // then the Gregory series through u^17 (|u| <= 0.4143).
+  static __device__ __forceinline__ float atan2(float y, float x) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const bool swap = ay > ax;
+    const float num = swap ? ax : ay, den = swap ? ay : ax;
+    const float t = den > 0.f ? __fdividef(num, den) : 0.f;
+    const bool red = t > 0.41421356f;
+    const float u = red ? __fdividef(t - 1.f, t + 1.f) : t;
+    const float z = u * u;
+    float p = 1.f / 17.f;
+    p = p * z - 1.f / 15.f;
+    p = p * z + 1.f / 13.f;
+    p = p * z - 1.f / 11.f;
+    p = p * z + 1.f / 9.f;
+    p = p * z - 1.f / 7.f;
+    p = p * z + 1.f / 5.f;
+    p = p * z - 1.f / 3.f;
+    float a = u + (u * z) * p;
+    a += red ? 0.78539816f : 0.f;
+    a = swap ? 1.57079633f - a : a;
+    a = x < 0.f ? 3.14159265f - a : a;
+    return y < 0.f ? -a : a;
+  }
   static __device__ __forceinline__ float expo(float x) { return __expf(x); }
   static __device__ __forceinline__ float wrap(float a) {
     while (a >= kPiF) a -= kTwoPiF;
     while (a < -kPiF) a += kTwoPiF;
     return a;
   }
-  static __device__ __forceinline__ float uni(uint64_t w) { return u01_f32(w); }
+  // Metropolis uniforms (u1, u2): Philox4x32-10, counter
+  // (n, 2<<16 | hit<<8 | mu, pass_id low, pass_id high), key (seed low, seed high);
+  // u = (w >> 8) 2^-24 from words 0 and 1
+  static __device__ __forceinline__ void metro_uniforms(uint32_t n, int hit, int mu, uint64_t pass_id,
+                                                        uint64_t seed, float& u1, float& u2) {
+    const U32x4 w = philox4x32_10(n, (2u << 16) | ((uint32_t)hit << 8) | (uint32_t)mu, (uint32_t)pass_id,
+                                  (uint32_t)(pass_id >> 32), (uint32_t)seed, (uint32_t)(seed >> 32));
+    u1 = u01_f32_w32(w.v[0]);
+    u2 = u01_f32_w32(w.v[1]);
+  }
   static __device__ __forceinline__ float from_f64(double v) { return wrap((float)v); }
 };
 
@@ -63,97 +107,166 @@ __global__ void init_links_kernel(typename P::real* __restrict__ links, const La
   links[d.off + i] = P::from_f64(th);
 }
 
-// Staple sum S of link (s, mu) so that the six plaquettes containing it add up
-// to Re(exp(i theta) S): for each nu != mu (ascending) the forward plaquette
-// phase  th_nu(x+mu) - th_mu(x+nu) - th_nu(x)  then the backward one
-// -(th_mu(x-nu) + th_nu(x+mu-nu) - th_nu(x-nu)).
-template <class P>
-__device__ __forceinline__ void staple(const typename P::real* __restrict__ links, const LatDesc& d, Site s,
-                                       int mu, typename P::real& sr, typename P::real& si) {
+// The per-link update.  g indexes the free links of class (MU, parity).
+template <class P, int MU, int KIND>
+__device__ __forceinline__ void update_link(typename P::real* __restrict__ base, const LatDesc& d, uint32_t g,
+                                            int parity, int th, int n_hits, uint64_t pass_id,
+                                            uint8_t* __restrict__ log) {
   using R = typename P::real;
-  R accr = (R)0, acci = (R)0;
+  const int L = d.L;
+  const uint32_t per_slice = (uint32_t)d.L3 >> 1;
+  uint32_t h = g;
+  if (MU > 0 && th > 0) {
+    // g -> (free slice j, offset); free slices are t = 1..th-1 (mod th)
+    const uint32_t j = g / per_slice;
+    const uint32_t off = g - j * per_slice;
+    const uint32_t tm1 = (uint32_t)th - 1u;
+    const uint32_t t = (j / tm1) * (uint32_t)th + (j % tm1) + 1u;
+    h = t * per_slice + off;
+  }
+  const Site s = site_of(d, h, parity);
+  const int n = (int)(2u * h) + (s.x & 1);  // natural index
+  // periodic forward / backward displacements of n per direction (t, x, y, z)
+  const int str[4] = {L * L * L, 1, L, L * L};
+  const int c[4] = {s.t, s.x, s.y, s.z};
+  const int ext[4] = {d.T, L, L, L};
+  int dp[4], dm[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    dp[k] = c[k] == ext[k] - 1 ? -(ext[k] - 1) * str[k] : str[k];
+    dm[k] = c[k] == 0 ? (ext[k] - 1) * str[k] : -str[k];
+  }
+  const uint32_t V2 = (uint32_t)d.V2;
+  const int q = parity ^ 1;
+  // plane(dir, par) = base + (2 dir + par) V2
+  // 32-bit byte offsets from the lattice base (scalar base + vector offset loads)
+  const char* cbase = (const char*)base;
+  auto ld = [&](int dir, int par, int nn) -> R {
+    const uint32_t byte = ((uint32_t)(2 * dir + par) * V2 + ((uint32_t)nn >> 1)) * (uint32_t)sizeof(R);
+    return *(const R*)(cbase + byte);
+  };
+  R sr = (R)0, si = (R)0;
 #pragma unroll
   for (int nu = 0; nu < 4; ++nu) {
-    if (nu == mu) continue;
-    const Site xpmu = shift2(d, s, mu, 1, nu, 0);
-    const Site xpnu = shift2(d, s, nu, 1, mu, 0);
-    const Site xmnu = shift2(d, s, nu, -1, mu, 0);
-    const Site xpmu_mnu = shift2(d, s, mu, 1, nu, -1);
-    const R a_nu_xpmu = links[link_at(d, nu, xpmu)];
-    const R a_mu_xpnu = links[link_at(d, mu, xpnu)];
-    const R a_nu_x = links[link_at(d, nu, s)];
-    const R a_mu_xmnu = links[link_at(d, mu, xmnu)];
-    const R a_nu_xpmumnu = links[link_at(d, nu, xpmu_mnu)];
-    const R a_nu_xmnu = links[link_at(d, nu, xmnu)];
+    if (nu == MU) continue;
+    const int n_xpmu = n + dp[MU];
+    const int n_xpnu = n + dp[nu];
+    const int n_xmnu = n + dm[nu];
+    const int n_xpmu_mnu = n_xpmu + dm[nu];
+    const R a_nu_xpmu = ld(nu, q, n_xpmu);
+    const R a_mu_xpnu = ld(MU, q, n_xpnu);
+    const R a_nu_x = ld(nu, parity, n);
+    const R a_mu_xmnu = ld(MU, q, n_xmnu);
+    const R a_nu_xpmumnu = ld(nu, parity, n_xpmu_mnu);
+    const R a_nu_xmnu = ld(nu, q, n_xmnu);
     const R ap = (a_nu_xpmu - a_mu_xpnu) - a_nu_x;
     const R am = -((a_mu_xmnu + a_nu_xpmumnu) - a_nu_xmnu);
     R sn, cs;
     P::sincos(ap, sn, cs);
-    accr += cs;
-    acci += sn;
+    sr += cs;
+    si += sn;
     P::sincos(am, sn, cs);
-    accr += cs;
-    acci += sn;
+    sr += cs;
+    si += sn;
   }
-  sr = accr;
-  si = acci;
-}
-
-// Re(exp(i phi) S)
-template <class P>
-__device__ __forceinline__ typename P::real re_phase(typename P::real phi, typename P::real sr,
-                                                     typename P::real si) {
-  typename P::real sn, cs;
-  P::sincos(phi, sn, cs);
-  return cs * sr - sn * si;
-}
-
-// kind 0: Metropolis with n_hits hits per link, proposal theta + eps (2u1 - 1),
-//         accepted iff u2 < exp(-dS), u1/u2 from counter
-//         (n, 2<<32 | hit<<8 | mu, pass_id, 0) under key (seed, 0);
-// kind 1: overrelaxation theta -> -theta - 2 arg S (identity when S = 0).
-// Frozen links (spatial links on time slices t = 0 mod th_frozen) are skipped.
-// log (optional, single lattice): one byte per (half-site, hit): 1 accepted,
-// 0 rejected, 2 frozen.
-template <class P, int kKind>
-__global__ void class_pass_kernel(typename P::real* __restrict__ links, const LatDesc* __restrict__ lats,
-                                  const int2* __restrict__ blocks, int mu, int parity, int th_frozen,
-                                  int n_hits, const uint64_t* __restrict__ pass_ids,
-                                  uint8_t* __restrict__ log) {
-  using R = typename P::real;
-  const int2 bk = blocks[blockIdx.x];
-  const LatDesc d = lats[bk.x];
-  const uint32_t h = (uint32_t)bk.y + threadIdx.x;
-  if (h >= (uint32_t)d.V2) return;
-  const Site s = site_of(d, h, parity);
-  if (th_frozen > 0 && mu > 0 && (s.t % th_frozen) == 0) {
-    if (kKind == 0 && log != nullptr)
-      for (int k = 0; k < n_hits; ++k) log[(size_t)h * n_hits + k] = 2;
-    return;
-  }
-  const uint64_t self = link_slot(d, mu, parity, h);
-  R sr, si;
-  staple<P>(links, d, s, mu, sr, si);
-  R th = links[self];
-  if (kKind == 0) {
-    const uint32_t n = natural_index(d, s.t, s.x, s.y, s.z);
-    const uint64_t pid = pass_ids[bk.x];
+  R* self = (R*)((char*)base + ((uint32_t)(2 * MU + parity) * V2 + h) * (uint32_t)sizeof(R));
+  R th0 = *self;
+  if (KIND == 0) {
     const R beta = (R)d.beta, eps = (R)d.eps;
     for (int k = 0; k < n_hits; ++k) {
-      const U64x4 w = philox4x64_10(n, kPurposeMetro | ((uint64_t)k << 8) | (uint64_t)mu, pid, 0, d.seed, 0);
-      const R u1 = P::uni(w.v[0]), u2 = P::uni(w.v[1]);
-      const R thn = P::wrap(th + eps * ((R)2 * u1 - (R)1));
-      const R dS = beta * (re_phase<P>(th, sr, si) - re_phase<P>(thn, sr, si));
+      R u1, u2;
+      P::metro_uniforms((uint32_t)n, k, MU, pass_id, d.seed, u1, u2);
+      const R thn = P::wrap(th0 + eps * ((R)2 * u1 - (R)1));
+      R s0, c0, s1, c1;
+      P::sincos(th0, s0, c0);
+      P::sincos(thn, s1, c1);
+      const R dS = beta * ((c0 * sr - s0 * si) - (c1 * sr - s1 * si));
       const bool acc = (dS <= (R)0) || (u2 < P::expo(-dS));
-      if (acc) th = thn;
+      if (acc) th0 = thn;
       if (log != nullptr) log[(size_t)h * n_hits + k] = acc ? 1 : 0;
     }
   } else {
     if (sr == (R)0 && si == (R)0) return;
     const R alpha = P::atan2(si, sr);
-    th = P::wrap(-th - (R)2 * alpha);
+    th0 = P::wrap(-th0 - (R)2 * alpha);
   }
-  links[self] = th;
+  *self = th0;
+}
+
+// Single lattice: geometry in the kernel arguments.
+template <class P, int MU, int KIND>
+__global__ void class_pass_kernel(typename P::real* __restrict__ links, LatDesc d, int parity, int th_frozen,
+                                  int n_hits, const uint64_t* __restrict__ pass_ids, uint8_t* __restrict__ log) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (uint32_t)free_sites(d.L, d.T, MU, th_frozen)) return;
+  update_link<P, MU, KIND>(links + d.off, d, g, parity, th_frozen, n_hits, KIND == 0 ? pass_ids[0] : 0, log);
+}
+
+// Batch: blocks[b] = {lattice, first free link of the block}.
+template <class P, int MU, int KIND>
+__global__ void class_pass_batch_kernel(typename P::real* __restrict__ links, const LatDesc* __restrict__ lats,
+                                        const int2* __restrict__ blocks, int parity, int th_frozen, int n_hits,
+                                        const uint64_t* __restrict__ pass_ids) {
+  const int2 bk = blocks[blockIdx.x];
+  const LatDesc d = lats[bk.x];
+  const uint32_t g = (uint32_t)bk.y + threadIdx.x;
+  if (g >= (uint32_t)free_sites(d.L, d.T, MU, th_frozen)) return;
+  update_link<P, MU, KIND>(links + d.off, d, g, parity, th_frozen, n_hits, KIND == 0 ? pass_ids[bk.x] : 0,
+                           nullptr);
+}
+
+// Launch helpers shared by the FP64 and FP32 translation units.
+template <class P, int KIND>
+hipError_t launch_pass_single(typename P::real* links, const LatDesc& d, int block, int mu, int parity, int th,
+                              int n_hits, const uint64_t* pass_ids, uint8_t* log, hipStream_t st) {
+  const int n = free_sites(d.L, d.T, mu, th);
+  if (n == 0) return hipSuccess;
+  const dim3 grid((n + block - 1) / block);
+  switch (mu) {
+    case 0:
+      hipLaunchKernelGGL((class_pass_kernel<P, 0, KIND>), grid, dim3(block), 0, st, links, d, parity, th, n_hits,
+                         pass_ids, log);
+      break;
+    case 1:
+      hipLaunchKernelGGL((class_pass_kernel<P, 1, KIND>), grid, dim3(block), 0, st, links, d, parity, th, n_hits,
+                         pass_ids, log);
+      break;
+    case 2:
+      hipLaunchKernelGGL((class_pass_kernel<P, 2, KIND>), grid, dim3(block), 0, st, links, d, parity, th, n_hits,
+                         pass_ids, log);
+      break;
+    default:
+      hipLaunchKernelGGL((class_pass_kernel<P, 3, KIND>), grid, dim3(block), 0, st, links, d, parity, th, n_hits,
+                         pass_ids, log);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <class P, int KIND>
+hipError_t launch_pass_batch(typename P::real* links, const LatDesc* lats, const int2* blocks, int n_blocks,
+                             int block, int mu, int parity, int th, int n_hits, const uint64_t* pass_ids,
+                             hipStream_t st) {
+  if (n_blocks == 0) return hipSuccess;
+  switch (mu) {
+    case 0:
+      hipLaunchKernelGGL((class_pass_batch_kernel<P, 0, KIND>), dim3(n_blocks), dim3(block), 0, st, links, lats,
+                         blocks, parity, th, n_hits, pass_ids);
+      break;
+    case 1:
+      hipLaunchKernelGGL((class_pass_batch_kernel<P, 1, KIND>), dim3(n_blocks), dim3(block), 0, st, links, lats,
+                         blocks, parity, th, n_hits, pass_ids);
+      break;
+    case 2:
+      hipLaunchKernelGGL((class_pass_batch_kernel<P, 2, KIND>), dim3(n_blocks), dim3(block), 0, st, links, lats,
+                         blocks, parity, th, n_hits, pass_ids);
+      break;
+    default:
+      hipLaunchKernelGGL((class_pass_batch_kernel<P, 3, KIND>), dim3(n_blocks), dim3(block), 0, st, links, lats,
+                         blocks, parity, th, n_hits, pass_ids);
+      break;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace u1ml

@@ -36,7 +36,7 @@ class U1MLError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("start", C.c_int), ("precision", C.c_int), ("eps", C.c_double), ("stream", C.c_void_p),
-                ("dev_buf", C.c_void_p), ("dev_bytes", C.c_size_t), ("block", C.c_int)]
+                ("dev_buf", C.c_void_p), ("dev_bytes", C.c_size_t), ("block", C.c_int), ("no_graphs", C.c_int)]
 
 
 class Observables(C.Structure):
@@ -85,13 +85,15 @@ def load_library(path: str = LIB_PATH):
         "u1ml_destroy": (None, [P]),
         "u1ml_batch_create": (I, [I, ip, ip, dp, C.POINTER(U64), C.POINTER(Options), C.POINTER(P)]),
         "u1ml_batch_sweep": (I, [P, I, I]),
+        "u1ml_batch_multilevel": (I, [P, I, ip, ip, I, I, I, ip, I, ip]),
         "u1ml_batch_cycle": (I, [P, I, I, I, I, I, I]),
-        "u1ml_batch_measure": (I, [P, I, C.POINTER(Observables), dp]),
+        "u1ml_batch_measure": (I, [P, I, C.POINTER(Observables), dp, dp]),
         "u1ml_batch_get_links": (I, [P, I, dp]),
         "u1ml_batch_set_links": (I, [P, I, dp]),
         "u1ml_batch_synchronize": (I, [P]),
         "u1ml_batch_destroy": (None, [P]),
         "u1ml_autotune": (I, [P, ip]),
+        "u1ml_profile_sweeps": (I, [P, I, I, I, dp]),
         "u1ml_strerror": (C.c_char_p, [I]),
         "u1ml_last_error": (C.c_char_p, []),
     }
@@ -163,11 +165,13 @@ class Lattice:
 
 
 def init_lattice(L: int, T: int, beta: float, seed: int, *, start: int = HOT, precision: int = FP64,
-                 eps: float = 1.0, block: int = 0, stream=None, torch_buffer: bool = True) -> Lattice:
+                 eps: float = 1.0, block: int = 0, stream=None, torch_buffer: bool = True,
+                 graphs: bool = True) -> Lattice:
     """u1ml_init_lattice; the link storage is a torch device tensor unless torch_buffer=False."""
     lib = load_library()
     o = default_options()
     o.start, o.precision, o.eps, o.block = start, precision, float(eps), block
+    o.no_graphs = 0 if graphs else 1
     keep = None
     if torch_buffer:
         import torch
@@ -278,12 +282,22 @@ def autotune(lat: Lattice) -> int:
     return int(b.value)
 
 
+def profile_sweeps(lat: Lattice, n_sweeps: int, n_metro: int = 1, n_or: int = 3):
+    """Average class-pass kernel durations in microseconds: (Metropolis, OR)."""
+    out = np.zeros(2)
+    _check(load_library().u1ml_profile_sweeps(lat.handle, n_sweeps, n_metro, n_or,
+                                              out.ctypes.data_as(C.POINTER(C.c_double))))
+    return float(out[0]), float(out[1])
+
+
 class Batch:
     """Many lattices updated by the same launches: wraps a ``u1ml_batch*``."""
 
     def __init__(self, handle, L, T, beta, seed):
         self._h = handle
         self.L, self.T, self.beta, self.seed = list(L), list(T), list(beta), list(seed)
+        self._n_r = None  # None: r = 1..T/2 of the last cycle
+        self._n_rf = 0
 
     def __del__(self):
         self.close()
@@ -299,11 +313,12 @@ class Batch:
 
 
 def batch_create(L, T, beta, seed, *, start: int = HOT, precision: int = FP64, eps: float = 1.0,
-                 block: int = 0, stream=None) -> Batch:
+                 block: int = 0, stream=None, graphs: bool = True) -> Batch:
     lib = load_library()
     n = len(L)
     o = default_options()
     o.start, o.precision, o.eps, o.block = start, precision, float(eps), block
+    o.no_graphs = 0 if graphs else 1
     if stream is not None:
         o.stream = C.c_void_p(int(stream))
     La, Lp = _ints(L)
@@ -322,15 +337,34 @@ def batch_sweep(b: Batch, n_metro: int = 1, n_or: int = 3):
 
 def batch_cycle(b: Batch, n_sweeps: int, n_metro: int, n_or: int, th: int, n_sub: int, use_graph: bool = True):
     _check(load_library().u1ml_batch_cycle(b.handle, n_sweeps, n_metro, n_or, th, n_sub, int(bool(use_graph))))
+    b._n_r, b._n_rf = None, 0
 
 
-def batch_measure(b: Batch, i: int, correlator: bool = True):
+def batch_multilevel(b: Batch, slab_sizes, n_sub, n_metro: int = 1, n_or: int = 3, r_list=(1,), rf_list=()):
+    th, thp = _ints(slab_sizes)
+    ns, nsp = _ints(n_sub)
+    r, rp = _ints(r_list)
+    rf, rfp = _ints(rf_list if len(rf_list) else [0])
+    _check(load_library().u1ml_batch_multilevel(b.handle, len(th), thp, nsp, n_metro, n_or, len(r), rp,
+                                                len(rf_list), rfp if len(rf_list) else None))
+    b._n_r, b._n_rf = [len(r)] * len(b.L), len(rf_list)
+
+
+def batch_measure(b: Batch, i: int, correlator: bool = True, field_profile: bool = False):
+    """Returns (obs dict, correlator complex[n_r] or None, field complex[n_rf][2][6][L][L] or None)."""
     obs = Observables()
-    nr = b.T[i] // 2
+    nr = b._n_r[i] if b._n_r is not None else b.T[i] // 2
     corr = np.zeros(2 * nr) if correlator else None
-    _check(load_library().u1ml_batch_measure(b.handle, i, C.byref(obs),
-                                             corr.ctypes.data_as(C.POINTER(C.c_double)) if correlator else None))
-    return obs.as_dict(), (corr[0::2] + 1j * corr[1::2]) if correlator else None
+    L = b.L[i]
+    fp = np.zeros(b._n_rf * 2 * 6 * L * L * 2) if field_profile else None
+    _check(load_library().u1ml_batch_measure(
+        b.handle, i, C.byref(obs), corr.ctypes.data_as(C.POINTER(C.c_double)) if correlator else None,
+        fp.ctypes.data_as(C.POINTER(C.c_double)) if field_profile else None))
+    f = None
+    if fp is not None:
+        f = fp.reshape(b._n_rf, 2, 6, L, L, 2)
+        f = f[..., 0] + 1j * f[..., 1]
+    return obs.as_dict(), (corr[0::2] + 1j * corr[1::2]) if correlator else None, f
 
 
 def batch_get_links(b: Batch, i: int) -> np.ndarray:

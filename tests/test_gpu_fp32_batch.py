@@ -64,7 +64,7 @@ def test_batch_matches_oracle_bit_exact(oracle_mod):
         for _ in range(2):
             o.sweep(1, 3)
         c_o, _, _ = o.multilevel([2], [4], 1, 3, list(range(1, Ls[i] // 2 + 1)))
-        obs, c_g = u1ml.batch_measure(b, i)
+        obs, c_g, _ = u1ml.batch_measure(b, i)
         np.testing.assert_array_equal(u1ml.batch_get_links(b, i), o.get_links())
         np.testing.assert_allclose(c_g, c_o, rtol=1e-12, atol=1e-15)
         assert abs(obs["plaquette"] - o.plaquette()) < 1e-13
@@ -77,14 +77,14 @@ def test_batch_graph_replay_matches_eager(prec):
     seeds = [7, 8, 9, 10]
     say(f"[gpu] graph vs eager prec={prec}")
     a = u1ml.batch_create(Ls, Ls, betas, seeds, precision=prec)
-    e = u1ml.batch_create(Ls, Ls, betas, seeds, precision=prec)
+    e = u1ml.batch_create(Ls, Ls, betas, seeds, precision=prec, graphs=False)
     for k in range(4):
         u1ml.batch_cycle(a, 2, 1, 3, 2, 3, use_graph=True)
         u1ml.batch_cycle(e, 2, 1, 3, 2, 3, use_graph=False)
         for i in range(len(Ls)):
             np.testing.assert_array_equal(u1ml.batch_get_links(a, i), u1ml.batch_get_links(e, i))
-            _, ca = u1ml.batch_measure(a, i)
-            _, ce = u1ml.batch_measure(e, i)
+            _, ca, _ = u1ml.batch_measure(a, i)
+            _, ce, _ = u1ml.batch_measure(e, i)
             np.testing.assert_array_equal(ca, ce)
 
 
@@ -95,3 +95,21 @@ def test_autotune_keeps_links_and_results():
     assert best in (64, 128, 256, 512, 1024)
     np.testing.assert_array_equal(u1ml.get_links(g), th)
     assert u1ml.get_pass_id(g) == 0
+
+
+def test_fp32_metropolis_draws_philox4x32():
+    # beta = 0 accepts every proposal, so theta' = eps (2 u1 - 1) from a cold
+    # start exposes u1 of every link: it must be the Philox4x32-10 word 0 of
+    # counter (n, 2<<16 | hit<<8 | mu, pass_id, 0) under key (seed lo, seed hi)
+    from tests.philox_ref import philox4x32_10
+    L, T, eps, seed = 4, 6, 0.5, (7 << 32) | 3
+    g = u1ml.init_lattice(L, T, 0.0, seed, precision=u1ml.FP32, start=u1ml.COLD, eps=eps)
+    u1ml.set_pass_id(g, 5)
+    u1ml.sweep(g, 1, 0)
+    th = u1ml.get_links(g).reshape(-1, 4)
+    n = np.arange(L ** 3 * T, dtype=np.uint64)
+    for mu in range(4):
+        w = philox4x32_10(n, (2 << 16) | mu, 5, 0, seed & 0xFFFFFFFF, seed >> 32)
+        u1 = (w[0] >> np.uint64(8)).astype(np.float32) * np.float32(2.0 ** -24)
+        expect = np.float32(eps) * (np.float32(2) * u1 - np.float32(1))
+        np.testing.assert_array_equal(th[:, mu].astype(np.float32), expect)

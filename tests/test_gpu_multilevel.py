@@ -92,3 +92,39 @@ def test_full_size_24_sweep_bit_exact(oracle_mod):
     o.sweep(1, 3)
     u1ml.sweep(g, 1, 3)
     np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
+
+
+@pytest.mark.parametrize("prec", [u1ml.FP64, u1ml.FP32])
+def test_multilevel_graph_replay_matches_eager(prec):
+    L, T = 6, 8
+    say(f"[gpu] multilevel graph vs eager prec={prec}")
+    a = u1ml.init_lattice(L, T, 1.0, 12, precision=prec)
+    b = u1ml.init_lattice(L, T, 1.0, 12, precision=prec, graphs=False)
+    for k in range(3):
+        for g in (a, b):
+            u1ml.sweep(g, 1, 3)
+            u1ml.multilevel(g, [4, 2], [2, 3], 1, 3, [1, 2, 3], rf_list=[2, 3])
+        np.testing.assert_array_equal(u1ml.get_links(a), u1ml.get_links(b))
+        _, ca, fa = u1ml.measure(a, observables=False, correlator=True, field_profile=True)
+        _, cb, fb = u1ml.measure(b, observables=False, correlator=True, field_profile=True)
+        np.testing.assert_array_equal(ca, cb)
+        np.testing.assert_array_equal(fa, fb)
+    assert u1ml.get_pass_id(a) == u1ml.get_pass_id(b) == 3 * (1 + 2 + 2 * 3)
+
+
+def test_batch_multilevel_with_field_matches_oracle(oracle_mod):
+    Ls, Ts = [4, 6], [8, 8]
+    seeds = [41, 42]
+    say("[gpu] batch multilevel with field vs oracle")
+    b = u1ml.batch_create(Ls, Ts, [1.0, 0.9], seeds)
+    ors = [oracle_mod.OracleLattice(L, T, be, s) for L, T, be, s in zip(Ls, Ts, [1.0, 0.9], seeds)]
+    u1ml.batch_sweep(b, 1, 2)
+    for o in ors:
+        o.sweep(1, 2)
+    u1ml.batch_multilevel(b, [4, 2], [2, 3], 1, 2, [1, 2, 3], rf_list=[2, 3])
+    for i, o in enumerate(ors):
+        c_o, f_o, _ = o.multilevel([4, 2], [2, 3], 1, 2, [1, 2, 3], rf_list=[2, 3])
+        _, c_g, f_g = u1ml.batch_measure(b, i, correlator=True, field_profile=True)
+        np.testing.assert_array_equal(u1ml.batch_get_links(b, i), o.get_links())
+        close_rel(c_g, c_o)
+        close_rel(f_g, f_o)
