@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-compare", action="store_true", help="also time one step of the FP64 path")
+    ap.add_argument("--replicas", type=int, default=1,
+                    help="independent 24^4 chains advanced by the same launches (one batch)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -128,46 +130,62 @@ def main():
     prec = u1ml.FP32 if args.precision == "fp32" else u1ml.FP64
     rf = [] if args.no_field else RF_LIST
 
+    R = args.replicas
+
     def make(pr):
-        lat = u1ml.init_lattice(L, T, BETA, 3, start=u1ml.COLD, precision=pr)
+        if R == 1:
+            lat = u1ml.init_lattice(L, T, BETA, 3, start=u1ml.COLD, precision=pr)
+            sw = lambda: u1ml.sweep(lat, 1, 3)  # noqa: E731
+        else:
+            lat = u1ml.batch_create([L] * R, [T] * R, [BETA] * R, [3 + i for i in range(R)], start=u1ml.COLD,
+                                    precision=pr, stream=stream.cuda_stream)
+            sw = lambda: u1ml.batch_sweep(lat, 1, 3)  # noqa: E731
         for _ in range(N_THERM):
-            u1ml.sweep(lat, 1, 3)
+            sw()
         torch.cuda.synchronize()
-        return lat
+        return lat, sw
 
-    lat = make(prec)
+    lat, sw = make(prec)
 
-    def step(lt, ev=None):
+    def step(lt, swf, ev=None):
         if ev:
             ev[0].record(stream)
         for _ in range(N_BETWEEN):
-            u1ml.sweep(lt, 1, 3)
+            swf()
         if ev:
             ev[1].record(stream)
-        u1ml.multilevel(lt, LEVELS, N_SUB, 1, 3, R_LIST, rf_list=rf)
+        if R == 1:
+            u1ml.multilevel(lt, LEVELS, N_SUB, 1, 3, R_LIST, rf_list=rf)
+        else:
+            u1ml.batch_multilevel(lt, LEVELS, N_SUB, 1, 3, R_LIST, rf_list=rf)
         if ev:
             ev[2].record(stream)
-        return u1ml.measure(lt, correlator=True, field_profile=bool(rf))
+        if R == 1:
+            return u1ml.measure(lt, correlator=True, field_profile=bool(rf))
+        res = [u1ml.batch_measure(lt, i, correlator=True, field_profile=bool(rf)) for i in range(R)]
+        return res[0]
 
     for _ in range(args.warmup):
-        step(lat)
+        step(lat, sw)
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     t0 = time.perf_counter()
     for k in range(args.steps):
-        obs, corr, field = step(lat, evs[k])
+        obs, corr, field = step(lat, sw, evs[k])
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms_sweeps = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
     ms_ml = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
 
     up_sw, up_ml = chain_updates_per_step()
+    up_sw, up_ml = up_sw * R, up_ml * R
     ms_step = 1e3 * el / args.steps
     value = (up_sw + up_ml) * args.steps / el
-    samples = samples_per_step()
+    samples = samples_per_step() * R
 
     # dominant kernel: the FP32/FP64 overrelaxation class pass on the full lattice
-    us_metro, us_or = u1ml.profile_sweeps(lat, 20, 1, 3)
+    prof_lat = lat if R == 1 else u1ml.init_lattice(L, T, BETA, 3, start=u1ml.COLD, precision=prec)
+    us_metro, us_or = u1ml.profile_sweeps(prof_lat, 20, 1, 3)
     bw = 4 if prec == u1ml.FP32 else 8
     updates_per_launch = L ** 3 * T // 2
     bytes_per_launch = updates_per_launch * WORDS_PER_UPDATE * bw
@@ -194,7 +212,7 @@ def main():
         "config": {"workload": "24^4 beta=1: 100 sweeps(1 Metropolis + 3 OR) + two-level multilevel "
                                "{4,2} x {10,20}, r=1..12, E/B mid-plane profiles at r=2,4,6",
                    "lattice": [L, L, L, T], "beta": BETA, "levels": LEVELS, "n_sub": N_SUB,
-                   "r": [1, 12], "field_r": rf, "accumulate": "f64"},
+                   "r": [1, 12], "field_r": rf, "accumulate": "f64", "replicas": R},
         "samples_per_s": samples / (ms_ml * 1e-3),
         "samples_per_step": samples,
         "chain_updates_per_step": up_sw + up_ml,
@@ -207,11 +225,11 @@ def main():
         "roofline": roofline,
     }
     if args.fp64_compare and prec == u1ml.FP32:
-        lat64 = make(u1ml.FP64)
-        step(lat64)
+        lat64, sw64 = make(u1ml.FP64)
+        step(lat64, sw64)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        step(lat64)
+        step(lat64, sw64)
         torch.cuda.synchronize()
         el64 = time.perf_counter() - t1
         out["fp64_path"] = {"ms_per_step": 1e3 * el64, "link_updates_per_s": (up_sw + up_ml) / el64,

@@ -99,7 +99,7 @@ void u1ml_default_options(u1ml_options *opt);
 size_t u1ml_link_bytes(int L, int T, int precision);
 
 /* Create a lattice (Sec. 2, Sec. 2.1): L, T even, 2 <= L, T <= 256,
- * L^3 T / 2 * L < 2^32; beta >= 0 finite (beta = 1/g^2 of Eq. (3)).
+ * L^4 T < 2^32; beta >= 0 finite (beta = 1/g^2 of Eq. (3)).
  * Starts cold or hot per opt (NULL = defaults) and sets pass_id = 0.
  * If opt->dev_buf is given the links live there (the caller keeps ownership
  * and must keep it alive until u1ml_destroy); otherwise the library allocates.

@@ -88,6 +88,11 @@ struct Table {
   std::vector<int> lat_block_begin;  // n_lats + 1
 };
 
+struct PassTable {
+  DevBuf buf;
+  int n_blocks = 0;
+};
+
 struct MLState {
   bool valid = false;        // a multilevel has completed
   bool field_valid = false;  // ... with the field insertion
@@ -132,6 +137,7 @@ struct Engine {
   DevBuf pass_ids;
   std::vector<uint64_t> h_pass_ids;
   std::map<std::pair<std::vector<int>, int>, std::unique_ptr<Table>> tables;
+  std::map<std::pair<int, int>, std::unique_ptr<PassTable>> pass_tables;
   // debug log (single lattice)
   DevBuf log;
   size_t log_cap = 0, log_used = 0;
@@ -190,6 +196,34 @@ struct Engine {
     return U1ML_OK;
   }
 
+  // class-pass blocks of a batch: {lattice, slice, first offset, 0} for every
+  // updated time slice (th = 0: all; else t != 0 mod th) of every lattice
+  int pass_table(int th, PassTable** out) {
+    auto key = std::make_pair(th, block);
+    auto it = pass_tables.find(key);
+    if (it != pass_tables.end()) {
+      *out = it->second.get();
+      return U1ML_OK;
+    }
+    if (capturing) return fail(U1ML_ESTATE, "internal: block table built during graph capture");
+    std::unique_ptr<PassTable> t(new PassTable());
+    std::vector<int4> h;
+    for (int i = 0; i < n_lats; ++i) {
+      const LatDesc& d = h_lats[i];
+      const int slices = class_slices(d.T, th > 0 ? 1 : 0, th);
+      for (int j = 0; j < slices; ++j)
+        for (int o = 0; o < d.L3 / 2; o += block) h.push_back(make_int4(i, class_slice(j, th > 0 ? 1 : 0, th), o, 0));
+    }
+    t->n_blocks = (int)h.size();
+    if (!h.empty()) {
+      U1_TRY(t->buf.ensure(h.size() * sizeof(int4)));
+      U1_HIP(hipMemcpy(t->buf.p, h.data(), h.size() * sizeof(int4), hipMemcpyHostToDevice));
+    }
+    *out = t.get();
+    pass_tables[key] = std::move(t);
+    return U1ML_OK;
+  }
+
   BlockTable bt(Table* t) const {
     BlockTable b;
     b.dev = t->buf.as<int2>();
@@ -209,16 +243,14 @@ struct Engine {
         e = launch_class_pass_f32(kind, links.as<float>(), h_lats[0], block, mu, parity, th_frozen, n_hits,
                                   pass_ids.as<uint64_t>(), logp, stream);
     } else {
-      std::vector<int> items;
-      for (auto& d : h_lats) items.push_back(free_sites(d.L, d.T, mu, th_frozen));
-      Table* t;
-      U1_TRY(table(items, block, &t));
+      PassTable* t;
+      U1_TRY(pass_table(mu > 0 && th_frozen > 0 ? th_frozen : 0, &t));
       if (prec == U1ML_FP64)
-        e = launch_class_pass_batch_f64(kind, links.as<double>(), lats.as<LatDesc>(), bt(t), mu, parity, th_frozen,
-                                        n_hits, pass_ids.as<uint64_t>(), stream);
+        e = launch_class_pass_batch_f64(kind, links.as<double>(), lats.as<LatDesc>(), t->buf.as<int4>(),
+                                        t->n_blocks, block, mu, parity, n_hits, pass_ids.as<uint64_t>(), stream);
       else
-        e = launch_class_pass_batch_f32(kind, links.as<float>(), lats.as<LatDesc>(), bt(t), mu, parity, th_frozen,
-                                        n_hits, pass_ids.as<uint64_t>(), stream);
+        e = launch_class_pass_batch_f32(kind, links.as<float>(), lats.as<LatDesc>(), t->buf.as<int4>(),
+                                        t->n_blocks, block, mu, parity, n_hits, pass_ids.as<uint64_t>(), stream);
     }
     U1_HIP(e);
     return U1ML_OK;
@@ -491,6 +523,11 @@ struct Engine {
       acc += (uint64_t)d.L3 * md.nR;
     }
     m.acc_elems = acc;
+    if (n_lats > 1) {
+      PassTable* pt;
+      U1_TRY(pass_table(0, &pt));
+      for (int l = 0; l < n_levels; ++l) U1_TRY(pass_table(th[l], &pt));
+    }
     U1_TRY(m.mls.ensure(n_lats * sizeof(MLDesc)));
     U1_TRY(m.rvals.ensure(rv.size() * sizeof(int)));
     U1_TRY(m.mlbuf.ensure(ell * sizeof(double)));
@@ -528,7 +565,9 @@ struct Engine {
         fb += 2ull * fp.n_rf * 12 * L2;
         m.fout_off[i] = fo;
         fo += (uint64_t)fp.n_rf * 12 * L2;
-        per_sample_max = std::max<size_t>(per_sample_max, (size_t)(2 * fp.n_rf + 6) * fl.ns * L3);
+        // contraction scratch: one sample's transformed planes plus the per-slab partial sums
+        per_sample_max = std::max<size_t>(per_sample_max, (size_t)(fp.n_rf + 6) * fl.ns * L3 +
+                                                              (size_t)fp.n_rf * fl.ns * 12 * L2);
       }
       m.scratch_elems = std::max(per_sample_max, kFieldScratchBytes / sizeof(double2));
       U1_TRY(m.fls.ensure(n_lats * sizeof(FieldLat)));
@@ -652,8 +691,9 @@ std::map<std::tuple<int, int, int>, int> g_tuned_block;  // (L, T, precision) ->
 int validate_size(int L, int T) {
   if (L < 2 || T < 2 || (L & 1) || (T & 1) || L > 256 || T > 256)
     return fail(U1ML_EINVAL, "L and T must be even and in [2, 256]");
-  const uint64_t V2 = (uint64_t)L * L * L * T / 2;
-  if (V2 * (uint64_t)L >= (1ull << 32) || 8 * V2 >= (1ull << 31)) return fail(U1ML_EINVAL, "lattice too large");
+  const uint64_t V = (uint64_t)L * L * L * T;
+  // 32-bit site arithmetic: the quotient tricks need V L < 2^32
+  if (V * (uint64_t)L >= (1ull << 32) || 4 * V >= (1ull << 31)) return fail(U1ML_EINVAL, "lattice too large");
   return U1ML_OK;
 }
 
@@ -665,6 +705,7 @@ LatDesc make_desc(int L, int T, double beta, double eps, uint64_t seed, uint64_t
   d.L3 = L * L * L;
   d.div_Lh = make_fastdiv((uint32_t)(L / 2));
   d.div_L = make_fastdiv((uint32_t)L);
+  d.div_slice = make_fastdiv((uint32_t)(L * L * L / 2));
   d.beta = beta;
   d.eps = eps;
   d.sqrt_beta = std::sqrt(beta);

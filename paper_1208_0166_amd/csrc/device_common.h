@@ -181,21 +181,21 @@ __device__ __forceinline__ double wrap_f64(double a) {
 // ---------------------------------------------------------------------------
 // Lattice geometry
 // ---------------------------------------------------------------------------
-// Exact unsigned division n / d by multiply-high, valid for n * d < 2^32.
+// Exact unsigned division n / d by multiply-high, valid for n * d < 2^32:
+// q = mulhi(n, ceil(2^32 / d)); d = 1 is carried by the mask (m = 0, q = n).
 struct FastDiv {
-  uint32_t d, m;
+  uint32_t d, m, one;
 };
 
 __host__ __device__ inline FastDiv make_fastdiv(uint32_t d) {
   FastDiv f;
   f.d = d;
-  f.m = (uint32_t)(0xFFFFFFFFULL / d + 1ULL);
+  f.m = d == 1 ? 0u : (uint32_t)(0xFFFFFFFFULL / d + 1ULL);
+  f.one = d == 1 ? 0xFFFFFFFFu : 0u;
   return f;
 }
 
-__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
-  return f.d == 1 ? n : __umulhi(n, f.m);
-}
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) { return __umulhi(n, f.m) + (n & f.one); }
 
 // One lattice of a batch.  Every launch covers all lattices of its batch; the
 // block table maps each block to (lattice, first half-site).
@@ -203,18 +203,21 @@ struct LatDesc {
   int L, T;
   int V2;        // L^3 T / 2
   int L3;        // L^3
-  FastDiv div_Lh, div_L;
+  FastDiv div_Lh, div_L, div_slice;  // by L/2, L, L^3/2
   double beta, eps, sqrt_beta;
   uint64_t seed;
   uint64_t off;  // offset of links[0][0][0] in the batch link buffer (elements)
 };
 
-// Number of links of class (mu, parity) that are updated: spatial links on
-// time slices t = 0 (mod th) are frozen when th > 0.
-__host__ __device__ inline int free_sites(int L, int T, int mu, int th) {
-  const int per_slice = L * L * L / 2;
-  if (mu == 0 || th <= 0) return per_slice * T;
-  return per_slice * (T / th) * (th - 1);
+// Time slice of the j-th updated slice of class mu: every slice, or with
+// frozen slabs (spatial mu, th > 0) the slices t = 1..th-1 (mod th).
+__host__ __device__ inline int class_slice(int j, int mu, int th) {
+  if (mu == 0 || th <= 0) return j;
+  return (j / (th - 1)) * th + (j % (th - 1)) + 1;
+}
+__host__ __device__ inline int class_slices(int T, int mu, int th) {
+  if (mu == 0 || th <= 0) return T;
+  return (T / th) * (th - 1);
 }
 
 struct Site {

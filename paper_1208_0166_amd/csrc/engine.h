@@ -28,13 +28,14 @@ hipError_t launch_class_pass_f64(int kind, double* links, const LatDesc& d, int 
 hipError_t launch_class_pass_f32(int kind, float* links, const LatDesc& d, int block, int mu, int parity,
                                  int th_frozen, int n_hits, const uint64_t* pass_ids, uint8_t* log,
                                  hipStream_t st);
-// one class pass of every lattice of a batch; bt covers free_sites() of each lattice
-hipError_t launch_class_pass_batch_f64(int kind, double* links, const LatDesc* lats, BlockTable bt, int mu,
-                                       int parity, int th_frozen, int n_hits, const uint64_t* pass_ids,
-                                       hipStream_t st);
-hipError_t launch_class_pass_batch_f32(int kind, float* links, const LatDesc* lats, BlockTable bt, int mu,
-                                       int parity, int th_frozen, int n_hits, const uint64_t* pass_ids,
-                                       hipStream_t st);
+// one class pass of every lattice of a batch; blocks[b] = {lattice, time slice,
+// first offset within the slice, 0}, one block per (updated slice, chunk)
+hipError_t launch_class_pass_batch_f64(int kind, double* links, const LatDesc* lats, const int4* blocks,
+                                       int n_blocks, int block, int mu, int parity, int n_hits,
+                                       const uint64_t* pass_ids, hipStream_t st);
+hipError_t launch_class_pass_batch_f32(int kind, float* links, const LatDesc* lats, const int4* blocks,
+                                       int n_blocks, int block, int mu, int parity, int n_hits,
+                                       const uint64_t* pass_ids, hipStream_t st);
 hipError_t launch_bump_pass_ids(uint64_t* pass_ids, int n, hipStream_t st);
 // fill n bytes with v (graph-safe replacement of a memset)
 hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t st);

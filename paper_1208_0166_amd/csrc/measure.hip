@@ -378,119 +378,160 @@ __global__ void field_weights_kernel(const LatDesc* __restrict__ lat, const MLDe
   ((double2*)(fbuf + fl.w))[item] = make_double2(p.x / norm, p.y / norm);
 }
 
-// wbuf[((k * n_rf + f) * ns + s) * L3 + x0] = w[m][s][x0][f] * T_sample(x0, s; rf[f])
-// for the samples sample0 + k, k < nk
-__global__ void field_wplanes_kernel(const LatDesc* __restrict__ lat, const MLDesc* __restrict__ mlp,
-                                     const FieldLat* __restrict__ flp, FieldParams fp, int sample0, int nk,
-                                     const double* __restrict__ mlbuf, const double* __restrict__ fbuf,
-                                     double2* __restrict__ wbuf) {
-  const LatDesc d = *lat;
-  const MLDesc ml = *mlp;
-  const FieldLat fl = *flp;
-  const int item = blockIdx.x * blockDim.x + threadIdx.x;
-  if (item >= nk * fp.n_rf * fl.ns * d.L3) return;
-  const int x0 = item % d.L3;
-  const int s = (item / d.L3) % fl.ns;
-  const int f = (item / (d.L3 * fl.ns)) % fp.n_rf;
-  const int k = item / (d.L3 * fl.ns * fp.n_rf);
-  const int sample = sample0 + k;
-  const int m = sample / fp.n_inner;
-  const double* e = mlbuf + ml.ell + ((size_t)sample * fl.ns + s) * d.L3;
-  const double2 t = cexpi(e[shift_x(d, x0, fp.rf[f])] - e[x0]);
-  const double2 ww = ((const double2*)(fbuf + fl.w))[(((size_t)m * fl.ns + s) * d.L3 + x0) * fp.n_rf + f];
-  wbuf[item] = cmul(ww, t);
-}
+// 2D DFT over (y, z) of one x-plane per block, in place in LDS:
+//   out[b][p][q] = sum_{y,z} v(x, y, z) exp(-2 pi i (p y + q z) / L)
+// KIND 0: v = the stored field slab sums O_c of sample k (real);
+// KIND 1: v = W_f(x0) = w[m][s][x0][f] T_k(x0, s; rf[f]) built on the fly.
+// Block b enumerates (k, a, s, x) with x fastest; a = c (KIND 0) or f (KIND 1).
+constexpr int kDftThreads = 256;
+constexpr int kDftMaxPer = 16;  // ceil(62^2 / 256)
 
-// 2D DFT over (y, z) of the x-planes of [n_planes / L][L3] arrays (site order
-// x fastest): out[b][p][q] = sum_{y,z} in_b(x, y, z) exp(-2 pi i (p y + q z) / L)
-// with b = (array * L + x).  One block per plane; LDS holds the L twiddles and
-// the L^2 complex results of the transform along z (L <= 62 keeps it below
-// 64 KiB).
-template <typename In>
-__device__ __forceinline__ double2 as_c(In v);
-template <>
-__device__ __forceinline__ double2 as_c<double>(double v) {
-  return make_double2(v, 0.0);
-}
-template <>
-__device__ __forceinline__ double2 as_c<double2>(double2 v) {
-  return v;
-}
-
-template <typename In>
-__global__ void dft2_kernel(const In* __restrict__ in, int L, double2* __restrict__ out) {
+template <int KIND>
+__global__ __launch_bounds__(kDftThreads) void field_dft_kernel(const LatDesc* __restrict__ lat,
+                                                                const MLDesc* __restrict__ mlp,
+                                                                const FieldLat* __restrict__ flp, FieldParams fp,
+                                                                int sample0, const double* __restrict__ mlbuf,
+                                                                const double* __restrict__ fbuf,
+                                                                double2* __restrict__ out) {
   extern __shared__ double2 sm[];
-  const int L2 = L * L;
-  double2* tw = sm;       // L twiddles exp(-2 pi i k / L)
-  double2* mid = sm + L;  // [y][q]
+  const LatDesc d = *lat;
+  const FieldLat fl = *flp;
+  const int L = d.L, L2 = L * L, ns = fl.ns;
+  const int A = KIND == 0 ? 6 : fp.n_rf;
+  double2* tw = sm;       // exp(-2 pi i k / L)
+  double2* buf = sm + L;  // plane [y][z] -> [y][q] -> [p][q]
   const int b = blockIdx.x;
-  const int arr = b / L, x = b - arr * L;
-  const In* src = in + (size_t)arr * L2 * L;
-  for (int k = threadIdx.x; k < L; k += blockDim.x) {
+  const int x = b % L, s = (b / L) % ns, a = (b / (L * ns)) % A, k = b / (L * ns * A);
+  const int sample = sample0 + k;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) {
     double sn, cs;
-    sincospi(2.0 * (double)k / (double)L, &sn, &cs);
-    tw[k] = make_double2(cs, -sn);
+    sincospi(2.0 * (double)i / (double)L, &sn, &cs);
+    tw[i] = make_double2(cs, -sn);
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < L2; i += blockDim.x) {
-    const int y = i / L, q = i - y * L;
-    double re = 0.0, im = 0.0;
-    int k = 0;
-    for (int z = 0; z < L; ++z) {
-      const double2 v = as_c<In>(src[(size_t)(z * L + y) * L + x]), w = tw[k];
-      re += v.x * w.x - v.y * w.y;
-      im += v.x * w.y + v.y * w.x;
-      k += q;
-      k -= (k >= L) ? L : 0;
+  if (KIND == 0) {
+    const double* src = fbuf + fl.oall + (((size_t)sample * 6 + a) * ns + s) * d.L3;
+    for (int i = threadIdx.x; i < L2; i += blockDim.x) {
+      const int y = i / L, z = i - y * L;
+      buf[i] = make_double2(src[(size_t)(z * L + y) * L + x], 0.0);
     }
-    mid[i] = make_double2(re, im);
+  } else {
+    const MLDesc ml = *mlp;
+    const int m = sample / fp.n_inner;
+    const double* e = mlbuf + ml.ell + ((size_t)sample * ns + s) * d.L3;
+    const double2* w = (const double2*)(fbuf + fl.w);
+    for (int i = threadIdx.x; i < L2; i += blockDim.x) {
+      const int y = i / L, z = i - y * L;
+      const int x0 = (z * L + y) * L + x;
+      const double2 t = cexpi(e[shift_x(d, x0, fp.rf[a])] - e[x0]);
+      buf[i] = cmul(w[(((size_t)m * ns + s) * d.L3 + x0) * fp.n_rf + a], t);
+    }
   }
   __syncthreads();
+  double2 r[kDftMaxPer];
+  // along z: buf[y][z] -> [y][q]
+#pragma unroll
+  for (int j = 0; j < kDftMaxPer; ++j) {
+    const int i = threadIdx.x + j * kDftThreads;
+    if (i < L2) {
+      const int y = i / L, q = i - y * L;
+      double re = 0.0, im = 0.0;
+      int kk = 0;
+      for (int z = 0; z < L; ++z) {
+        const double2 v = buf[y * L + z], t = tw[kk];
+        re += v.x * t.x - v.y * t.y;
+        im += v.x * t.y + v.y * t.x;
+        kk += q;
+        kk -= (kk >= L) ? L : 0;
+      }
+      r[j] = make_double2(re, im);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kDftMaxPer; ++j) {
+    const int i = threadIdx.x + j * kDftThreads;
+    if (i < L2) buf[i] = r[j];
+  }
+  __syncthreads();
+  // along y: [y][q] -> [p][q]
   double2* dst = out + (size_t)b * L2;
-  for (int i = threadIdx.x; i < L2; i += blockDim.x) {
-    const int p = i / L, q = i - p * L;
-    double re = 0.0, im = 0.0;
-    int k = 0;
-    for (int y = 0; y < L; ++y) {
-      const double2 v = mid[y * L + q], w = tw[k];
-      re += v.x * w.x - v.y * w.y;
-      im += v.x * w.y + v.y * w.x;
-      k += p;
-      k -= (k >= L) ? L : 0;
+#pragma unroll
+  for (int j = 0; j < kDftMaxPer; ++j) {
+    const int i = threadIdx.x + j * kDftThreads;
+    if (i < L2) {
+      const int p = i / L, q = i - p * L;
+      double re = 0.0, im = 0.0;
+      int kk = 0;
+      for (int y = 0; y < L; ++y) {
+        const double2 v = buf[y * L + q], t = tw[kk];
+        re += v.x * t.x - v.y * t.y;
+        im += v.x * t.y + v.y * t.x;
+        kk += p;
+        kk -= (kk >= L) ? L : 0;
+      }
+      dst[i] = make_double2(re, im);
     }
-    dst[i] = make_double2(re, im);
   }
 }
 
-// G[((f * 2 + plane) * 6 + c) * L2 + (p, q)] +=
-//   sum_k sum_s sum_x What[k][f][s][x](-p, -q) * Ohat[k][c][s][x + m](p, q)
+// part[(((f * ns + s) * 2 + plane) * 6 + c) * L2 + pq] =
+//   sum_k sum_x What[k][f][s][x](-p, -q) * Ohat[k][c][s][x + m_plane](p, q)
+// one thread per (f, s, pq); m_0 = (r-1)/2, m_1 = r/2
 __global__ void field_gacc_kernel(FieldParams fp, int L, int ns, int nk, const double2* __restrict__ what,
-                                  const double2* __restrict__ ohat, double2* __restrict__ G) {
+                                  const double2* __restrict__ ohat, double2* __restrict__ part) {
+  const int L2 = L * L;
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= fp.n_rf * ns * L2) return;
+  const int pq = item % L2;
+  const int s = (item / L2) % ns;
+  const int f = item / (L2 * ns);
+  const int p = pq / L, q = pq - p * L;
+  const int mpq = ((L - p) % L) * L + (L - q) % L;
+  const int r = fp.rf[f];
+  const int m0 = (r - 1) / 2, m1 = r / 2;
+  double2 acc[6][2];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) acc[c][0] = acc[c][1] = make_double2(0.0, 0.0);
+  for (int k = 0; k < nk; ++k) {
+    const double2* W = what + ((size_t)(k * fp.n_rf + f) * ns + s) * L * L2;
+    for (int x = 0; x < L; ++x) {
+      const double2 w = W[(size_t)x * L2 + mpq];
+      int x0 = x + m0, x1 = x + m1;
+      x0 -= (x0 >= L) ? L : 0;
+      x1 -= (x1 >= L) ? L : 0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double2* O = ohat + ((size_t)(k * 6 + c) * ns + s) * L * L2;
+        const double2 o0 = O[(size_t)x0 * L2 + pq];
+        const double2 o1 = m1 == m0 ? o0 : O[(size_t)x1 * L2 + pq];
+        acc[c][0].x += w.x * o0.x - w.y * o0.y;
+        acc[c][0].y += w.x * o0.y + w.y * o0.x;
+        acc[c][1].x += w.x * o1.x - w.y * o1.y;
+        acc[c][1].y += w.x * o1.y + w.y * o1.x;
+      }
+    }
+  }
+#pragma unroll
+  for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) part[((((size_t)f * ns + s) * 2 + pl) * 6 + c) * L2 + pq] = acc[c][pl];
+}
+
+// G[((f * 2 + plane) * 6 + c) * L2 + pq] += sum_s part[...] (slabs in order)
+__global__ void field_gred_kernel(FieldParams fp, int L, int ns, const double2* __restrict__ part,
+                                  double2* __restrict__ G) {
   const int L2 = L * L;
   const int item = blockIdx.x * blockDim.x + threadIdx.x;
   if (item >= fp.n_rf * 12 * L2) return;
   const int pq = item % L2;
-  const int c = (item / L2) % 6;
-  const int plane = (item / (6 * L2)) % 2;
+  const int pc = (item / L2) % 12;  // plane * 6 + c
   const int f = item / (12 * L2);
-  const int p = pq / L, q = pq - p * L;
-  const int mpq = ((L - p) % L) * L + (L - q) % L;
-  const int r = fp.rf[f];
-  const int mx = plane == 0 ? (r - 1) / 2 : r / 2;
   double re = 0.0, im = 0.0;
-  for (int k = 0; k < nk; ++k)
-    for (int s = 0; s < ns; ++s) {
-      const double2* W = what + ((size_t)(k * fp.n_rf + f) * ns + s) * L * L2;
-      const double2* O = ohat + ((size_t)(k * 6 + c) * ns + s) * L * L2;
-      for (int x = 0; x < L; ++x) {
-        int xx = x + mx;
-        xx -= (xx >= L) ? L : 0;
-        const double2 w = W[(size_t)x * L2 + mpq];
-        const double2 o = O[(size_t)xx * L2 + pq];
-        re += w.x * o.x - w.y * o.y;
-        im += w.x * o.y + w.y * o.x;
-      }
-    }
+  for (int s = 0; s < ns; ++s) {
+    const double2 v = part[(((size_t)f * ns + s) * 12 + pc) * L2 + pq];
+    re += v.x;
+    im += v.y;
+  }
   G[item].x += re;
   G[item].y += im;
 }
@@ -616,24 +657,25 @@ hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const Fie
   double2* G = (double2*)(fbuf + hfl.g);
   const uint64_t ng = (uint64_t)fp.n_rf * 12 * L2;
   hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(ng, 256)), dim3(256), 0, st, G, ng);
-  // per sample: W planes (n_rf ns L3) + their DFT + O DFT (6 ns L3)
-  const uint64_t per_sample = (uint64_t)(2 * fp.n_rf + 6) * ns * L3;
-  const int chunk = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, scratch_elems / per_sample));
+  // scratch per chunk: What [nk][n_rf][ns][L3], Ohat [nk][6][ns][L3], part [n_rf][ns][12][L2]
+  const uint64_t npart = (uint64_t)fp.n_rf * ns * 12 * L2;
+  const uint64_t per_sample = (uint64_t)(fp.n_rf + 6) * ns * L3;
+  const uint64_t avail = scratch_elems > npart ? scratch_elems - npart : 0;
+  const int chunk = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, avail / per_sample));
   const int n_samples = fp.n_outer * fp.n_inner;
   const size_t shm = (size_t)(L + L2) * sizeof(double2);
+  double2* part = scratch;
   for (int s0 = 0; s0 < n_samples; s0 += chunk) {
     const int nk = std::min(chunk, n_samples - s0);
-    double2* wbuf = scratch;
-    double2* what = wbuf + (uint64_t)nk * fp.n_rf * ns * L3;
+    double2* what = scratch + npart;
     double2* ohat = what + (uint64_t)nk * fp.n_rf * ns * L3;
-    const uint64_t nw = (uint64_t)nk * fp.n_rf * ns * L3;
-    hipLaunchKernelGGL(field_wplanes_kernel, dim3(blocks_for(nw, 256)), dim3(256), 0, st, lat, ml, fl, fp, s0, nk,
-                       mlbuf, fbuf, wbuf);
-    hipLaunchKernelGGL(dft2_kernel<double2>, dim3((unsigned)((uint64_t)nk * fp.n_rf * ns * L)), dim3(256), shm, st,
-                       wbuf, L, what);
-    hipLaunchKernelGGL(dft2_kernel<double>, dim3((unsigned)((uint64_t)nk * 6 * ns * L)), dim3(256), shm, st,
-                       fbuf + hfl.oall + (size_t)s0 * 6 * ns * L3, L, ohat);
-    hipLaunchKernelGGL(field_gacc_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, ns, nk, what, ohat, G);
+    hipLaunchKernelGGL(field_dft_kernel<1>, dim3((unsigned)((uint64_t)nk * fp.n_rf * ns * L)), dim3(kDftThreads), shm,
+                       st, lat, ml, fl, fp, s0, mlbuf, fbuf, what);
+    hipLaunchKernelGGL(field_dft_kernel<0>, dim3((unsigned)((uint64_t)nk * 6 * ns * L)), dim3(kDftThreads), shm, st,
+                       lat, ml, fl, fp, s0, mlbuf, fbuf, ohat);
+    const uint64_t na = (uint64_t)fp.n_rf * ns * L2;
+    hipLaunchKernelGGL(field_gacc_kernel, dim3(blocks_for(na, 64)), dim3(64), 0, st, fp, L, ns, nk, what, ohat, part);
+    hipLaunchKernelGGL(field_gred_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, ns, part, G);
   }
   hipLaunchKernelGGL(field_final_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, G, F);
   return hipGetLastError();

@@ -19,14 +19,12 @@ hipError_t launch_class_pass_f32(int kind, float* links, const LatDesc& d, int b
   return launch_pass_single<Fast32, 1>(links, d, block, mu, parity, th_frozen, n_hits, pass_ids, log, st);
 }
 
-hipError_t launch_class_pass_batch_f32(int kind, float* links, const LatDesc* lats, BlockTable bt, int mu,
-                                       int parity, int th_frozen, int n_hits, const uint64_t* pass_ids,
-                                       hipStream_t st) {
+hipError_t launch_class_pass_batch_f32(int kind, float* links, const LatDesc* lats, const int4* blocks,
+                                       int n_blocks, int block, int mu, int parity, int n_hits,
+                                       const uint64_t* pass_ids, hipStream_t st) {
   if (kind == kMetropolis)
-    return launch_pass_batch<Fast32, 0>(links, lats, bt.dev, bt.n_blocks, bt.block, mu, parity, th_frozen, n_hits,
-                                   pass_ids, st);
-  return launch_pass_batch<Fast32, 1>(links, lats, bt.dev, bt.n_blocks, bt.block, mu, parity, th_frozen, n_hits,
-                                 pass_ids, st);
+    return launch_pass_batch<Fast32, 0>(links, lats, blocks, n_blocks, block, mu, parity, n_hits, pass_ids, st);
+  return launch_pass_batch<Fast32, 1>(links, lats, blocks, n_blocks, block, mu, parity, n_hits, pass_ids, st);
 }
 
 }  // namespace u1ml

@@ -47,9 +47,9 @@ struct Fast32 {
     const float ax = fabsf(x), ay = fabsf(y);
     const bool swap = ay > ax;
     const float num = swap ? ax : ay, den = swap ? ay : ax;
-    const float t = den > 0.f ? __fdividef(num, den) : 0.f;
+    const float t = den > 0.f ? num * __builtin_amdgcn_rcpf(den) : 0.f;
     const bool red = t > 0.41421356f;
-    const float u = red ? __fdividef(t - 1.f, t + 1.f) : t;
+    const float u = red ? (t - 1.f) * __builtin_amdgcn_rcpf(t + 1.f) : t;
     const float z = u * u;
     float p = 1.f / 17.f;
     p = p * z - 1.f / 15.f;
@@ -66,11 +66,8 @@ struct Fast32 {
     return y < 0.f ? -a : a;
   }
   static __device__ __forceinline__ float expo(float x) { return __expf(x); }
-  static __device__ __forceinline__ float wrap(float a) {
-    while (a >= kPiF) a -= kTwoPiF;
-    while (a < -kPiF) a += kTwoPiF;
-    return a;
-  }
+  // fold into [-pi, pi] by whole periods (branch-free)
+  static __device__ __forceinline__ float wrap(float a) { return a - kTwoPiF * rintf(a * (1.f / kTwoPiF)); }
   // Metropolis uniforms (u1, u2): Philox4x32-10, counter
   // (n, 2<<16 | hit<<8 | mu, pass_id low, pass_id high), key (seed low, seed high);
   // u = (w >> 8) 2^-24 from words 0 and 1
@@ -107,58 +104,59 @@ __global__ void init_links_kernel(typename P::real* __restrict__ links, const La
   links[d.off + i] = P::from_f64(th);
 }
 
-// The per-link update.  g indexes the free links of class (MU, parity).
+// The per-link update of the link of class (MU, parity) at time slice t and
+// offset off = (z L + y) L/2 + x/2 within the slice.  Neighbour half-indices
+// are h plus per-direction half-displacements: the strides along t, y, z are
+// even, and along x the displacement depends on the parity of x; periodic
+// wrap-around is folded into the displacements.
 template <class P, int MU, int KIND>
-__device__ __forceinline__ void update_link(typename P::real* __restrict__ base, const LatDesc& d, uint32_t g,
-                                            int parity, int th, int n_hits, uint64_t pass_id,
+__device__ __forceinline__ void update_link(typename P::real* __restrict__ base, const LatDesc& d, int t,
+                                            uint32_t off, int parity, int n_hits, uint64_t pass_id,
                                             uint8_t* __restrict__ log) {
   using R = typename P::real;
-  const int L = d.L;
-  const uint32_t per_slice = (uint32_t)d.L3 >> 1;
-  uint32_t h = g;
-  if (MU > 0 && th > 0) {
-    // g -> (free slice j, offset); free slices are t = 1..th-1 (mod th)
-    const uint32_t j = g / per_slice;
-    const uint32_t off = g - j * per_slice;
-    const uint32_t tm1 = (uint32_t)th - 1u;
-    const uint32_t t = (j / tm1) * (uint32_t)th + (j % tm1) + 1u;
-    h = t * per_slice + off;
-  }
-  const Site s = site_of(d, h, parity);
-  const int n = (int)(2u * h) + (s.x & 1);  // natural index
-  // periodic forward / backward displacements of n per direction (t, x, y, z)
-  const int str[4] = {L * L * L, 1, L, L * L};
-  const int c[4] = {s.t, s.x, s.y, s.z};
-  const int ext[4] = {d.T, L, L, L};
-  int dp[4], dm[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    dp[k] = c[k] == ext[k] - 1 ? -(ext[k] - 1) * str[k] : str[k];
-    dm[k] = c[k] == 0 ? (ext[k] - 1) * str[k] : -str[k];
-  }
+  const int L = d.L, Lh = L >> 1;
+  const int per_slice = d.L3 >> 1;
+  const uint32_t h = (uint32_t)t * (uint32_t)per_slice + off;
+  const uint32_t qy = fdiv(off, d.div_Lh);
+  const int xh = (int)(off - qy * (uint32_t)Lh);
+  const uint32_t qz = fdiv(qy, d.div_L);
+  const int y = (int)(qy - qz * (uint32_t)L);
+  const int z = (int)qz;
+  const int xb = (parity ^ (t + z + y)) & 1;
+  const int x = 2 * xh + xb;
+  // half-displacements, directions (t, x, y, z)
+  int hp[4], hm[4];
+  hp[0] = t == d.T - 1 ? -(d.T - 1) * per_slice : per_slice;
+  hm[0] = t == 0 ? (d.T - 1) * per_slice : -per_slice;
+  hp[1] = x == L - 1 ? 1 - Lh : xb;
+  hm[1] = x == 0 ? Lh - 1 : xb - 1;
+  hp[2] = y == L - 1 ? -(L - 1) * Lh : Lh;
+  hm[2] = y == 0 ? (L - 1) * Lh : -Lh;
+  hp[3] = z == L - 1 ? -(L - 1) * Lh * L : Lh * L;
+  hm[3] = z == 0 ? (L - 1) * Lh * L : -Lh * L;
   const uint32_t V2 = (uint32_t)d.V2;
   const int q = parity ^ 1;
-  // plane(dir, par) = base + (2 dir + par) V2
+  const int hh = (int)h;
   // 32-bit byte offsets from the lattice base (scalar base + vector offset loads)
   const char* cbase = (const char*)base;
-  auto ld = [&](int dir, int par, int nn) -> R {
-    const uint32_t byte = ((uint32_t)(2 * dir + par) * V2 + ((uint32_t)nn >> 1)) * (uint32_t)sizeof(R);
+  auto ld = [&](int dir, int par, int hi) -> R {
+    const uint32_t byte = ((uint32_t)(2 * dir + par) * V2 + (uint32_t)hi) * (uint32_t)sizeof(R);
     return *(const R*)(cbase + byte);
   };
   R sr = (R)0, si = (R)0;
 #pragma unroll
   for (int nu = 0; nu < 4; ++nu) {
     if (nu == MU) continue;
-    const int n_xpmu = n + dp[MU];
-    const int n_xpnu = n + dp[nu];
-    const int n_xmnu = n + dm[nu];
-    const int n_xpmu_mnu = n_xpmu + dm[nu];
-    const R a_nu_xpmu = ld(nu, q, n_xpmu);
-    const R a_mu_xpnu = ld(MU, q, n_xpnu);
-    const R a_nu_x = ld(nu, parity, n);
-    const R a_mu_xmnu = ld(MU, q, n_xmnu);
-    const R a_nu_xpmumnu = ld(nu, parity, n_xpmu_mnu);
-    const R a_nu_xmnu = ld(nu, q, n_xmnu);
+    const int h_xpmu = hh + hp[MU];
+    const int h_xpnu = hh + hp[nu];
+    const int h_xmnu = hh + hm[nu];
+    const int h_xpmu_mnu = h_xpmu + hm[nu];
+    const R a_nu_xpmu = ld(nu, q, h_xpmu);
+    const R a_mu_xpnu = ld(MU, q, h_xpnu);
+    const R a_nu_x = ld(nu, parity, hh);
+    const R a_mu_xmnu = ld(MU, q, h_xmnu);
+    const R a_nu_xpmumnu = ld(nu, parity, h_xpmu_mnu);
+    const R a_nu_xmnu = ld(nu, q, h_xmnu);
     const R ap = (a_nu_xpmu - a_mu_xpnu) - a_nu_x;
     const R am = -((a_mu_xmnu + a_nu_xpmumnu) - a_nu_xmnu);
     R sn, cs;
@@ -172,10 +170,11 @@ __device__ __forceinline__ void update_link(typename P::real* __restrict__ base,
   R* self = (R*)((char*)base + ((uint32_t)(2 * MU + parity) * V2 + h) * (uint32_t)sizeof(R));
   R th0 = *self;
   if (KIND == 0) {
+    const uint32_t n = 2u * h + (uint32_t)xb;  // natural site index
     const R beta = (R)d.beta, eps = (R)d.eps;
     for (int k = 0; k < n_hits; ++k) {
       R u1, u2;
-      P::metro_uniforms((uint32_t)n, k, MU, pass_id, d.seed, u1, u2);
+      P::metro_uniforms(n, k, MU, pass_id, d.seed, u1, u2);
       const R thn = P::wrap(th0 + eps * ((R)2 * u1 - (R)1));
       R s0, c0, s1, c1;
       P::sincos(th0, s0, c0);
@@ -193,35 +192,36 @@ __device__ __forceinline__ void update_link(typename P::real* __restrict__ base,
   *self = th0;
 }
 
-// Single lattice: geometry in the kernel arguments.
+// Single lattice: geometry in the kernel arguments; grid (blocks per slice,
+// updated slices).
 template <class P, int MU, int KIND>
 __global__ void class_pass_kernel(typename P::real* __restrict__ links, LatDesc d, int parity, int th_frozen,
                                   int n_hits, const uint64_t* __restrict__ pass_ids, uint8_t* __restrict__ log) {
-  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= (uint32_t)free_sites(d.L, d.T, MU, th_frozen)) return;
-  update_link<P, MU, KIND>(links + d.off, d, g, parity, th_frozen, n_hits, KIND == 0 ? pass_ids[0] : 0, log);
+  const uint32_t off = blockIdx.x * blockDim.x + threadIdx.x;
+  if (off >= ((uint32_t)d.L3 >> 1)) return;
+  const int t = class_slice((int)blockIdx.y, MU, th_frozen);
+  update_link<P, MU, KIND>(links + d.off, d, t, off, parity, n_hits, KIND == 0 ? pass_ids[0] : 0, log);
 }
 
-// Batch: blocks[b] = {lattice, first free link of the block}.
+// Batch: blocks[b] = {lattice, time slice, first offset in the slice, 0}.
 template <class P, int MU, int KIND>
 __global__ void class_pass_batch_kernel(typename P::real* __restrict__ links, const LatDesc* __restrict__ lats,
-                                        const int2* __restrict__ blocks, int parity, int th_frozen, int n_hits,
+                                        const int4* __restrict__ blocks, int parity, int n_hits,
                                         const uint64_t* __restrict__ pass_ids) {
-  const int2 bk = blocks[blockIdx.x];
+  const int4 bk = blocks[blockIdx.x];
   const LatDesc d = lats[bk.x];
-  const uint32_t g = (uint32_t)bk.y + threadIdx.x;
-  if (g >= (uint32_t)free_sites(d.L, d.T, MU, th_frozen)) return;
-  update_link<P, MU, KIND>(links + d.off, d, g, parity, th_frozen, n_hits, KIND == 0 ? pass_ids[bk.x] : 0,
-                           nullptr);
+  const uint32_t off = (uint32_t)bk.z + threadIdx.x;
+  if (off >= ((uint32_t)d.L3 >> 1)) return;
+  update_link<P, MU, KIND>(links + d.off, d, bk.y, off, parity, n_hits, KIND == 0 ? pass_ids[bk.x] : 0, nullptr);
 }
 
 // Launch helpers shared by the FP64 and FP32 translation units.
 template <class P, int KIND>
 hipError_t launch_pass_single(typename P::real* links, const LatDesc& d, int block, int mu, int parity, int th,
                               int n_hits, const uint64_t* pass_ids, uint8_t* log, hipStream_t st) {
-  const int n = free_sites(d.L, d.T, mu, th);
-  if (n == 0) return hipSuccess;
-  const dim3 grid((n + block - 1) / block);
+  const int slices = class_slices(d.T, mu, th);
+  if (slices == 0) return hipSuccess;
+  const dim3 grid((d.L3 / 2 + block - 1) / block, slices);
   switch (mu) {
     case 0:
       hipLaunchKernelGGL((class_pass_kernel<P, 0, KIND>), grid, dim3(block), 0, st, links, d, parity, th, n_hits,
@@ -244,26 +244,25 @@ hipError_t launch_pass_single(typename P::real* links, const LatDesc& d, int blo
 }
 
 template <class P, int KIND>
-hipError_t launch_pass_batch(typename P::real* links, const LatDesc* lats, const int2* blocks, int n_blocks,
-                             int block, int mu, int parity, int th, int n_hits, const uint64_t* pass_ids,
-                             hipStream_t st) {
+hipError_t launch_pass_batch(typename P::real* links, const LatDesc* lats, const int4* blocks, int n_blocks,
+                             int block, int mu, int parity, int n_hits, const uint64_t* pass_ids, hipStream_t st) {
   if (n_blocks == 0) return hipSuccess;
   switch (mu) {
     case 0:
       hipLaunchKernelGGL((class_pass_batch_kernel<P, 0, KIND>), dim3(n_blocks), dim3(block), 0, st, links, lats,
-                         blocks, parity, th, n_hits, pass_ids);
+                         blocks, parity, n_hits, pass_ids);
       break;
     case 1:
       hipLaunchKernelGGL((class_pass_batch_kernel<P, 1, KIND>), dim3(n_blocks), dim3(block), 0, st, links, lats,
-                         blocks, parity, th, n_hits, pass_ids);
+                         blocks, parity, n_hits, pass_ids);
       break;
     case 2:
       hipLaunchKernelGGL((class_pass_batch_kernel<P, 2, KIND>), dim3(n_blocks), dim3(block), 0, st, links, lats,
-                         blocks, parity, th, n_hits, pass_ids);
+                         blocks, parity, n_hits, pass_ids);
       break;
     default:
       hipLaunchKernelGGL((class_pass_batch_kernel<P, 3, KIND>), dim3(n_blocks), dim3(block), 0, st, links, lats,
-                         blocks, parity, th, n_hits, pass_ids);
+                         blocks, parity, n_hits, pass_ids);
       break;
   }
   return hipGetLastError();
