@@ -222,6 +222,8 @@ int u1ml_autotune(u1ml_lattice *lat, int *best_block);
  * Metropolis class passes, avg_us[1] over the overrelaxation ones (0 if none
  * ran).  The sweeps are real updates of the chain.  Synchronises. */
 int u1ml_profile_sweeps(u1ml_lattice *lat, int n_sweeps, int n_metro, int n_or, double *avg_us);
+/* The same for a batch (one class-pass kernel covers every lattice). */
+int u1ml_batch_profile_sweeps(u1ml_batch *b, int n_sweeps, int n_metro, int n_or, double *avg_us);
 
 /* Text for an error code. */
 const char *u1ml_strerror(int code);

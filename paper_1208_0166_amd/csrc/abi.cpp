@@ -530,7 +530,7 @@ struct Engine {
     }
     U1_TRY(m.mls.ensure(n_lats * sizeof(MLDesc)));
     U1_TRY(m.rvals.ensure(rv.size() * sizeof(int)));
-    U1_TRY(m.mlbuf.ensure(ell * sizeof(double)));
+    U1_TRY(m.mlbuf.ensure(ell * sizeof(double2)));
     U1_TRY(m.accbuf.ensure(acc * sizeof(double2)));
     U1_TRY(m.corr.ensure((size_t)n_lats * m.max_r * 2 * sizeof(double)));
     U1_HIP(hipMemcpy(m.mls.p, m.h_mls.data(), n_lats * sizeof(MLDesc), hipMemcpyHostToDevice));
@@ -585,12 +585,12 @@ struct Engine {
     std::vector<int> it;
     for (int i = 0; i < n_lats; ++i) {
       int nsp = parent == m.n_levels ? 1 : m.h_mls[i].ns[parent];
-      it.push_back(nsp * h_lats[i].L3 * m.h_mls[i].nR);
+      it.push_back(nsp * h_lats[i].L3 * ((m.h_mls[i].nR + 7) / 8));  // blocks of 8 separations
     }
     Table* t;
     U1_TRY(table(it, 256, &t));
     U1_HIP(launch_ml_fold(lats.as<LatDesc>(), m.mls.as<MLDesc>(), bt(t), child, parent, m.n_levels, child == inner,
-                          m.n[child], sample_base, m.rvals.as<int>(), m.mlbuf.as<double>(), m.accbuf.as<double2>(),
+                          m.n[child], sample_base, m.rvals.as<int>(), m.mlbuf.as<double2>(), m.accbuf.as<double2>(),
                           stream));
     return U1ML_OK;
   }
@@ -603,7 +603,7 @@ struct Engine {
     Table* t;
     U1_TRY(table(it, 256, &t));
     U1_HIP(launch_ml_lines(prec, links.p, lats.as<LatDesc>(), m.mls.as<MLDesc>(), bt(t), m.th[inner], sample,
-                           m.mlbuf.as<double>(), stream));
+                           m.mlbuf.as<double2>(), stream));
     if (m.field)
       U1_HIP(launch_field_o(prec, links.p, lats.as<LatDesc>(), m.fls.as<FieldLat>(), bt(t), m.th[inner], sample,
                             m.fbuf.as<double>(), stream));
@@ -639,7 +639,7 @@ struct Engine {
       // the weights need the top-level averages: contract before the top fold
       for (int i = 0; i < n_lats; ++i)
         U1_HIP(launch_field_contract(lats.as<LatDesc>() + i, m.mls.as<MLDesc>() + i, m.fls.as<FieldLat>() + i,
-                                     m.h_fls[i], m.fp, h_lats[i].L, m.mlbuf.as<double>(), m.accbuf.as<double2>(),
+                                     m.h_fls[i], m.fp, h_lats[i].L, m.mlbuf.as<double2>(), m.accbuf.as<double2>(),
                                      m.fbuf.as<double>(), m.scratch.as<double2>(), m.scratch_elems,
                                      m.fout.as<double2>() + m.fout_off[i], stream));
     }
@@ -1128,9 +1128,8 @@ int u1ml_autotune(u1ml_lattice* lat, int* best_block) {
   return U1ML_OK;
 }
 
-int u1ml_profile_sweeps(u1ml_lattice* lat, int n_sweeps, int n_metro, int n_or, double* avg_us) {
-  if (!lat || !avg_us || n_sweeps < 0 || n_metro < 0 || n_or < 0) return fail(U1ML_EINVAL, "profile arguments");
-  Engine& e = lat->e;
+static int profile_sweeps(Engine& e, int n_sweeps, int n_metro, int n_or, double* avg_us) {
+  if (!avg_us || n_sweeps < 0 || n_metro < 0 || n_or < 0) return fail(U1ML_EINVAL, "profile arguments");
   U1_TRY(e.set_device());
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
   e.prof[0] = &ev[0];
@@ -1153,6 +1152,16 @@ int u1ml_profile_sweeps(u1ml_lattice* lat, int n_sweeps, int n_metro, int n_or, 
   if (rc) return rc;
   U1_HIP(se);
   return U1ML_OK;
+}
+
+int u1ml_profile_sweeps(u1ml_lattice* lat, int n_sweeps, int n_metro, int n_or, double* avg_us) {
+  if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
+  return profile_sweeps(lat->e, n_sweeps, n_metro, n_or, avg_us);
+}
+
+int u1ml_batch_profile_sweeps(u1ml_batch* b, int n_sweeps, int n_metro, int n_or, double* avg_us) {
+  if (!b) return fail(U1ML_EINVAL, "batch is NULL");
+  return profile_sweeps(b->e, n_sweeps, n_metro, n_or, avg_us);
 }
 
 const char* u1ml_strerror(int code) {

@@ -45,7 +45,7 @@ hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t st);
 // corresponding buffer).
 constexpr int kMaxLevels = 3;
 struct MLDesc {
-  uint64_t ell;                  // doubles: [n_inner][ns_inner][L3] slab time-line angle sums
+  uint64_t ell;                  // double2: [samples][ns_inner][L3] exp(i * slab time-line angle sum)
   uint64_t acc[kMaxLevels + 1];  // double2: level l < inner: [ns_l][L3][nR]; index n_levels = top [L3][nR]
   int ns[kMaxLevels];            // slabs per level
   int nR;                        // separations
@@ -68,11 +68,11 @@ hipError_t launch_poly_corr(const LatDesc* lats, BlockTable bt, const uint64_t* 
 
 // multilevel
 hipError_t launch_ml_lines(int prec, const void* links, const LatDesc* lats, const MLDesc* mls, BlockTable bt,
-                           int inner_th, int sample, double* mlbuf, hipStream_t st);
+                           int inner_th, int sample, double2* mlbuf, hipStream_t st);
 // sample_base: first stored inner sample of the current inner run (field runs keep them all)
 hipError_t launch_ml_fold(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int child_level, int parent_level,
                           int n_levels, int child_is_inner, int n_child, int sample_base, const int* rvals,
-                          const double* mlbuf, double2* accbuf, hipStream_t st);
+                          const double2* mlbuf, double2* accbuf, hipStream_t st);
 hipError_t launch_ml_zero(double2* accbuf, uint64_t n, hipStream_t st);
 hipError_t launch_ml_final(const LatDesc* lats, const MLDesc* mls, int n_lats, int max_r, int top_level,
                            const double2* accbuf, double* out, hipStream_t st);
@@ -97,7 +97,7 @@ hipError_t launch_field_o(int prec, const void* links, const LatDesc* lats, cons
                           int th_inner, int sample, double* fbuf, hipStream_t st);
 // contraction of all stored samples of one lattice into F [n_rf][2][6][L][L] (complex)
 hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,
-                                 FieldParams fp, int L, const double* mlbuf, const double2* accbuf, double* fbuf,
+                                 FieldParams fp, int L, const double2* mlbuf, const double2* accbuf, double* fbuf,
                                  double2* scratch, size_t scratch_elems, double2* F, hipStream_t st);
 
 }  // namespace u1ml

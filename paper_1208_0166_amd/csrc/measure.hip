@@ -196,25 +196,26 @@ __global__ void poly_corr_kernel(const LatDesc* __restrict__ lats, const int2* _
 template <typename R>
 __global__ void ml_lines_kernel(const R* __restrict__ links, const LatDesc* __restrict__ lats,
                                 const MLDesc* __restrict__ mls, const int2* __restrict__ blocks, int inner_th,
-                                int sample, double* __restrict__ mlbuf) {
+                                int sample, double2* __restrict__ mlbuf) {
   const int2 bk = blocks[blockIdx.x];
   const LatDesc d = lats[bk.x];
   const int ns = d.T / inner_th;
   const int item = bk.y + (int)threadIdx.x;
   if (item >= ns * d.L3) return;
   const int s = item / d.L3, x3 = item - s * d.L3;
-  mlbuf[mls[bk.x].ell + ((size_t)sample * ns + s) * d.L3 + x3] = time_line(links, d, x3, s * inner_th, inner_th);
+  // exp(i l), l = sum of theta_0 over the slab's times: the slab product of U_0
+  mlbuf[mls[bk.x].ell + ((size_t)sample * ns + s) * d.L3 + x3] = cexpi(time_line(links, d, x3, s * inner_th, inner_th));
 }
 
-// average over the stored samples of T(x0, r) = exp(i (l(x0 + r) - l(x0))) of inner slab cs
-__device__ __forceinline__ double2 inner_avg(const double* ell, int n_samples, int ns, int L3, int cs, int x0,
+// average over the stored samples of T(x0, r) = conj(e(x0)) e(x0 + r) of inner slab cs
+__device__ __forceinline__ double2 inner_avg(const double2* ell, int n_samples, int ns, int L3, int cs, int x0,
                                              int x0r) {
   double2 a = make_double2(0.0, 0.0);
   for (int i = 0; i < n_samples; ++i) {
-    const double* e = ell + ((size_t)i * ns + cs) * L3;
-    const double2 t = cexpi(e[x0r] - e[x0]);
-    a.x += t.x;
-    a.y += t.y;
+    const double2* e = ell + ((size_t)i * ns + cs) * L3;
+    const double2 u = e[x0], v = e[x0r];
+    a.x += u.x * v.x + u.y * v.y;
+    a.y += u.x * v.y - u.y * v.x;
   }
   const double inv = 1.0 / (double)n_samples;
   return make_double2(a.x * inv, a.y * inv);
@@ -222,39 +223,76 @@ __device__ __forceinline__ double2 inner_avg(const double* ell, int n_samples, i
 
 // acc_parent[S][x0][k] += prod over the children of S of the child averages.
 // parent_level == n_levels denotes the top (one slab spanning all of T).
+// One thread per (S, x0, block of up to kFoldR separations).
+constexpr int kFoldR = 8;
 __global__ void ml_fold_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls,
                                const int2* __restrict__ blocks, int child_level, int parent_level, int n_levels,
                                int child_is_inner, int n_child, int sample_base, const int* __restrict__ rvals,
-                               const double* __restrict__ mlbuf, double2* __restrict__ accbuf) {
+                               const double2* __restrict__ mlbuf, double2* __restrict__ accbuf) {
   const int2 bk = blocks[blockIdx.x];
   const LatDesc d = lats[bk.x];
   const MLDesc m = mls[bk.x];
   const int ns_child = m.ns[child_level];
   const int ns_parent = parent_level == n_levels ? 1 : m.ns[parent_level];
   const int children = ns_child / ns_parent;
+  const int nchunk = (m.nR + kFoldR - 1) / kFoldR;
   const int item = bk.y + (int)threadIdx.x;
-  if (item >= ns_parent * d.L3 * m.nR) return;
-  const int k = item % m.nR;
-  const int x0 = (item / m.nR) % d.L3;
-  const int S = item / (m.nR * d.L3);
-  const int x0r = shift_x(d, x0, rvals[m.r_off + k]);
-  double2 prod = make_double2(1.0, 0.0);
-  const double inv = 1.0 / (double)n_child;
-  for (int j = 0; j < children; ++j) {
-    const int cs = S * children + j;
-    double2 avg;
-    if (child_is_inner) {
-      avg = inner_avg(mlbuf + m.ell + (size_t)sample_base * ns_child * d.L3, n_child, ns_child, d.L3, cs, x0, x0r);
-    } else {
-      double2* c = accbuf + m.acc[child_level] + ((size_t)cs * d.L3 + x0) * m.nR + k;
-      avg = make_double2(c->x * inv, c->y * inv);
-      *c = make_double2(0.0, 0.0);
-    }
-    prod = cmul(prod, avg);
+  if (item >= ns_parent * d.L3 * nchunk) return;
+  const int chunk = item % nchunk;
+  const int x0 = (item / nchunk) % d.L3;
+  const int S = item / (nchunk * d.L3);
+  const int k0 = chunk * kFoldR;
+  const int kn = min(kFoldR, m.nR - k0);
+  int xr[kFoldR];
+  double2 prod[kFoldR];
+#pragma unroll
+  for (int j = 0; j < kFoldR; ++j) {
+    xr[j] = j < kn ? shift_x(d, x0, rvals[m.r_off + k0 + j]) : x0;
+    prod[j] = make_double2(1.0, 0.0);
   }
-  double2* p = accbuf + m.acc[parent_level] + ((size_t)S * d.L3 + x0) * m.nR + k;
-  p->x += prod.x;
-  p->y += prod.y;
+  const double inv = 1.0 / (double)n_child;
+  for (int c = 0; c < children; ++c) {
+    const int cs = S * children + c;
+    double2 avg[kFoldR];
+#pragma unroll
+    for (int j = 0; j < kFoldR; ++j) avg[j] = make_double2(0.0, 0.0);
+    if (child_is_inner) {
+      const double2* ell = mlbuf + m.ell + ((size_t)sample_base * ns_child + cs) * d.L3;
+      for (int i = 0; i < n_child; ++i) {
+        const double2* e = ell + (size_t)i * ns_child * d.L3;
+        const double2 u = e[x0];
+#pragma unroll
+        for (int j = 0; j < kFoldR; ++j) {
+          if (j < kn) {
+            const double2 v = e[xr[j]];
+            avg[j].x += u.x * v.x + u.y * v.y;
+            avg[j].y += u.x * v.y - u.y * v.x;
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kFoldR; ++j) avg[j] = make_double2(avg[j].x * inv, avg[j].y * inv);
+    } else {
+      double2* cp = accbuf + m.acc[child_level] + ((size_t)cs * d.L3 + x0) * m.nR + k0;
+#pragma unroll
+      for (int j = 0; j < kFoldR; ++j) {
+        if (j < kn) {
+          avg[j] = make_double2(cp[j].x * inv, cp[j].y * inv);
+          cp[j] = make_double2(0.0, 0.0);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kFoldR; ++j) prod[j] = cmul(prod[j], avg[j]);
+  }
+  double2* pp = accbuf + m.acc[parent_level] + ((size_t)S * d.L3 + x0) * m.nR + k0;
+#pragma unroll
+  for (int j = 0; j < kFoldR; ++j) {
+    if (j < kn) {
+      pp[j].x += prod[j].x;
+      pp[j].y += prod[j].y;
+    }
+  }
 }
 
 __global__ void zero_kernel(double2* __restrict__ p, uint64_t n) {
@@ -324,8 +362,8 @@ __global__ void field_o_kernel(const R* __restrict__ links, const LatDesc* __res
 // tavg[((m * ns + s) * L3 + x0) * n_rf + f] = average over the n_inner samples
 // of outer iteration m of T(x0, rf[f]) in inner slab s
 __global__ void field_tavg_kernel(const LatDesc* __restrict__ lat, const MLDesc* __restrict__ mlp,
-                                  const FieldLat* __restrict__ flp, FieldParams fp, const double* __restrict__ mlbuf,
-                                  double* __restrict__ fbuf) {
+                                  const FieldLat* __restrict__ flp, FieldParams fp,
+                                  const double2* __restrict__ mlbuf, double* __restrict__ fbuf) {
   const LatDesc d = *lat;
   const MLDesc ml = *mlp;
   const FieldLat fl = *flp;
@@ -335,7 +373,7 @@ __global__ void field_tavg_kernel(const LatDesc* __restrict__ lat, const MLDesc*
   const int x0 = (item / fp.n_rf) % d.L3;
   const int s = (item / (fp.n_rf * d.L3)) % fl.ns;
   const int m = item / (fp.n_rf * d.L3 * fl.ns);
-  const double* ell = mlbuf + ml.ell + (size_t)m * fp.n_inner * fl.ns * d.L3;
+  const double2* ell = mlbuf + ml.ell + (size_t)m * fp.n_inner * fl.ns * d.L3;
   ((double2*)(fbuf + fl.tavg))[item] = inner_avg(ell, fp.n_inner, fl.ns, d.L3, s, x0, shift_x(d, x0, fp.rf[f]));
 }
 
@@ -381,7 +419,8 @@ __global__ void field_weights_kernel(const LatDesc* __restrict__ lat, const MLDe
 // 2D DFT over (y, z) of one x-plane per block, in place in LDS:
 //   out[b][p][q] = sum_{y,z} v(x, y, z) exp(-2 pi i (p y + q z) / L)
 // KIND 0: v = the stored field slab sums O_c of sample k (real);
-// KIND 1: v = W_f(x0) = w[m][s][x0][f] T_k(x0, s; rf[f]) built on the fly.
+// KIND 1: v = W_f(x0) = w[m][s][x0][f] T_k(x0, s; rf[f]) built on the fly,
+//         transformed with exp(+2 pi i ...) so that out[b][p][q] = What(-p, -q).
 // Block b enumerates (k, a, s, x) with x fastest; a = c (KIND 0) or f (KIND 1).
 constexpr int kDftThreads = 256;
 constexpr int kDftMaxPer = 16;  // ceil(62^2 / 256)
@@ -390,7 +429,7 @@ template <int KIND>
 __global__ __launch_bounds__(kDftThreads) void field_dft_kernel(const LatDesc* __restrict__ lat,
                                                                 const MLDesc* __restrict__ mlp,
                                                                 const FieldLat* __restrict__ flp, FieldParams fp,
-                                                                int sample0, const double* __restrict__ mlbuf,
+                                                                int sample0, const double2* __restrict__ mlbuf,
                                                                 const double* __restrict__ fbuf,
                                                                 double2* __restrict__ out) {
   extern __shared__ double2 sm[];
@@ -406,7 +445,7 @@ __global__ __launch_bounds__(kDftThreads) void field_dft_kernel(const LatDesc* _
   for (int i = threadIdx.x; i < L; i += blockDim.x) {
     double sn, cs;
     sincospi(2.0 * (double)i / (double)L, &sn, &cs);
-    tw[i] = make_double2(cs, -sn);
+    tw[i] = make_double2(cs, KIND == 0 ? -sn : sn);
   }
   if (KIND == 0) {
     const double* src = fbuf + fl.oall + (((size_t)sample * 6 + a) * ns + s) * d.L3;
@@ -417,12 +456,13 @@ __global__ __launch_bounds__(kDftThreads) void field_dft_kernel(const LatDesc* _
   } else {
     const MLDesc ml = *mlp;
     const int m = sample / fp.n_inner;
-    const double* e = mlbuf + ml.ell + ((size_t)sample * ns + s) * d.L3;
+    const double2* e = mlbuf + ml.ell + ((size_t)sample * ns + s) * d.L3;
     const double2* w = (const double2*)(fbuf + fl.w);
     for (int i = threadIdx.x; i < L2; i += blockDim.x) {
       const int y = i / L, z = i - y * L;
       const int x0 = (z * L + y) * L + x;
-      const double2 t = cexpi(e[shift_x(d, x0, fp.rf[a])] - e[x0]);
+      const double2 u = e[x0], v = e[shift_x(d, x0, fp.rf[a])];
+      const double2 t = make_double2(u.x * v.x + u.y * v.y, u.x * v.y - u.y * v.x);
       buf[i] = cmul(w[(((size_t)m * ns + s) * d.L3 + x0) * fp.n_rf + a], t);
     }
   }
@@ -474,51 +514,62 @@ __global__ __launch_bounds__(kDftThreads) void field_dft_kernel(const LatDesc* _
   }
 }
 
-// part[(((f * ns + s) * 2 + plane) * 6 + c) * L2 + pq] =
-//   sum_k sum_x What[k][f][s][x](-p, -q) * Ohat[k][c][s][x + m_plane](p, q)
-// one thread per (f, s, pq); m_0 = (r-1)/2, m_1 = r/2
-__global__ void field_gacc_kernel(FieldParams fp, int L, int ns, int nk, const double2* __restrict__ what,
+// part[((((k * n_rf + f) * ns + s) * 2 + plane) * 6 + c) * L2 + pq] =
+//   sum_x What[k][f][s][x](-pq) * Ohat[k][c][s][x + m_plane](pq),  m_0 = (r-1)/2, m_1 = r/2.
+// Block (pq tile, s, k); threads (pq in tile, f, plane).  The W tile of all x
+// and the O tile of one component at a time are staged in LDS, so every
+// transformed value is read from memory once.
+__global__ void field_gacc_kernel(FieldParams fp, int L, int ns, int pt, const double2* __restrict__ what,
                                   const double2* __restrict__ ohat, double2* __restrict__ part) {
+  extern __shared__ double2 sm[];
   const int L2 = L * L;
-  const int item = blockIdx.x * blockDim.x + threadIdx.x;
-  if (item >= fp.n_rf * ns * L2) return;
-  const int pq = item % L2;
-  const int s = (item / L2) % ns;
-  const int f = item / (L2 * ns);
-  const int p = pq / L, q = pq - p * L;
-  const int mpq = ((L - p) % L) * L + (L - q) % L;
-  const int r = fp.rf[f];
-  const int m0 = (r - 1) / 2, m1 = r / 2;
-  double2 acc[6][2];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) acc[c][0] = acc[c][1] = make_double2(0.0, 0.0);
-  for (int k = 0; k < nk; ++k) {
-    const double2* W = what + ((size_t)(k * fp.n_rf + f) * ns + s) * L * L2;
-    for (int x = 0; x < L; ++x) {
-      const double2 w = W[(size_t)x * L2 + mpq];
-      int x0 = x + m0, x1 = x + m1;
-      x0 -= (x0 >= L) ? L : 0;
-      x1 -= (x1 >= L) ? L : 0;
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        const double2* O = ohat + ((size_t)(k * 6 + c) * ns + s) * L * L2;
-        const double2 o0 = O[(size_t)x0 * L2 + pq];
-        const double2 o1 = m1 == m0 ? o0 : O[(size_t)x1 * L2 + pq];
-        acc[c][0].x += w.x * o0.x - w.y * o0.y;
-        acc[c][0].y += w.x * o0.y + w.y * o0.x;
-        acc[c][1].x += w.x * o1.x - w.y * o1.y;
-        acc[c][1].y += w.x * o1.y + w.y * o1.x;
+  const int s = blockIdx.y, k = blockIdx.z;
+  const int pq0 = blockIdx.x * pt;
+  const int npq = min(pt, L2 - pq0);
+  double2* wt = sm;                      // [f][x][pt]
+  double2* ot = sm + fp.n_rf * L * pt;  // [x][pt]
+  const int tid = threadIdx.x;
+  const int j = tid % pt, fpl = tid / pt;  // fpl = f * 2 + plane
+  const bool active = fpl < 2 * fp.n_rf && j < npq;
+  const int f = fpl >> 1, plane = fpl & 1;
+  int m = 0;
+  if (fpl < 2 * fp.n_rf) {
+    const int r = fp.rf[f];
+    m = plane == 0 ? (r - 1) / 2 : r / 2;
+  }
+  for (int i = tid; i < fp.n_rf * L * pt; i += blockDim.x) {
+    const int jj = i % pt, x = (i / pt) % L, ff = i / (pt * L);
+    wt[i] = jj < npq ? what[((((size_t)k * fp.n_rf + ff) * ns + s) * L + x) * L2 + pq0 + jj] : make_double2(0.0, 0.0);
+  }
+  double2 acc[6];
+  for (int c = 0; c < 6; ++c) {
+    __syncthreads();
+    for (int i = tid; i < L * pt; i += blockDim.x) {
+      const int jj = i % pt, x = i / pt;
+      ot[i] = jj < npq ? ohat[((((size_t)k * 6 + c) * ns + s) * L + x) * L2 + pq0 + jj] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double re = 0.0, im = 0.0;
+    if (active) {
+      const double2* wr = wt + (size_t)f * L * pt + j;
+      int xx = m;
+      for (int x = 0; x < L; ++x) {
+        const double2 w = wr[x * pt], o = ot[xx * pt + j];
+        re += w.x * o.x - w.y * o.y;
+        im += w.x * o.y + w.y * o.x;
+        ++xx;
+        xx -= (xx >= L) ? L : 0;
       }
     }
+    acc[c] = make_double2(re, im);
   }
-#pragma unroll
-  for (int pl = 0; pl < 2; ++pl)
-#pragma unroll
-    for (int c = 0; c < 6; ++c) part[((((size_t)f * ns + s) * 2 + pl) * 6 + c) * L2 + pq] = acc[c][pl];
+  if (active)
+    for (int c = 0; c < 6; ++c)
+      part[(((((size_t)k * fp.n_rf + f) * ns + s) * 2 + plane) * 6 + c) * L2 + pq0 + j] = acc[c];
 }
 
-// G[((f * 2 + plane) * 6 + c) * L2 + pq] += sum_s part[...] (slabs in order)
-__global__ void field_gred_kernel(FieldParams fp, int L, int ns, const double2* __restrict__ part,
+// G[((f * 2 + plane) * 6 + c) * L2 + pq] += sum_k sum_s part[...] (fixed order)
+__global__ void field_gred_kernel(FieldParams fp, int L, int ns, int nk, const double2* __restrict__ part,
                                   double2* __restrict__ G) {
   const int L2 = L * L;
   const int item = blockIdx.x * blockDim.x + threadIdx.x;
@@ -527,11 +578,12 @@ __global__ void field_gred_kernel(FieldParams fp, int L, int ns, const double2* 
   const int pc = (item / L2) % 12;  // plane * 6 + c
   const int f = item / (12 * L2);
   double re = 0.0, im = 0.0;
-  for (int s = 0; s < ns; ++s) {
-    const double2 v = part[(((size_t)f * ns + s) * 12 + pc) * L2 + pq];
-    re += v.x;
-    im += v.y;
-  }
+  for (int k = 0; k < nk; ++k)
+    for (int s = 0; s < ns; ++s) {
+      const double2 v = part[((((size_t)k * fp.n_rf + f) * ns + s) * 12 + pc) * L2 + pq];
+      re += v.x;
+      im += v.y;
+    }
   G[item].x += re;
   G[item].y += im;
 }
@@ -602,7 +654,7 @@ hipError_t launch_poly_corr(const LatDesc* lats, BlockTable bt, const uint64_t* 
 }
 
 hipError_t launch_ml_lines(int prec, const void* links, const LatDesc* lats, const MLDesc* mls, BlockTable bt,
-                           int inner_th, int sample, double* mlbuf, hipStream_t st) {
+                           int inner_th, int sample, double2* mlbuf, hipStream_t st) {
   if (prec == kFP64)
     hipLaunchKernelGGL(ml_lines_kernel<double>, dim3(bt.n_blocks), dim3(bt.block), 0, st, (const double*)links,
                        lats, mls, bt.dev, inner_th, sample, mlbuf);
@@ -614,7 +666,7 @@ hipError_t launch_ml_lines(int prec, const void* links, const LatDesc* lats, con
 
 hipError_t launch_ml_fold(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int child_level, int parent_level,
                           int n_levels, int child_is_inner, int n_child, int sample_base, const int* rvals,
-                          const double* mlbuf, double2* accbuf, hipStream_t st) {
+                          const double2* mlbuf, double2* accbuf, hipStream_t st) {
   hipLaunchKernelGGL(ml_fold_kernel, dim3(bt.n_blocks), dim3(bt.block), 0, st, lats, mls, bt.dev, child_level,
                      parent_level, n_levels, child_is_inner, n_child, sample_base, rvals, mlbuf, accbuf);
   return hipGetLastError();
@@ -646,7 +698,7 @@ hipError_t launch_field_o(int prec, const void* links, const LatDesc* lats, cons
 }
 
 hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,
-                                 FieldParams fp, int L, const double* mlbuf, const double2* accbuf, double* fbuf,
+                                 FieldParams fp, int L, const double2* mlbuf, const double2* accbuf, double* fbuf,
                                  double2* scratch, size_t scratch_elems, double2* F, hipStream_t st) {
   const uint64_t L3 = (uint64_t)L * L * L, L2 = (uint64_t)L * L;
   const int ns = hfl.ns;
@@ -657,25 +709,28 @@ hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const Fie
   double2* G = (double2*)(fbuf + hfl.g);
   const uint64_t ng = (uint64_t)fp.n_rf * 12 * L2;
   hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(ng, 256)), dim3(256), 0, st, G, ng);
-  // scratch per chunk: What [nk][n_rf][ns][L3], Ohat [nk][6][ns][L3], part [n_rf][ns][12][L2]
-  const uint64_t npart = (uint64_t)fp.n_rf * ns * 12 * L2;
-  const uint64_t per_sample = (uint64_t)(fp.n_rf + 6) * ns * L3;
-  const uint64_t avail = scratch_elems > npart ? scratch_elems - npart : 0;
-  const int chunk = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, avail / per_sample));
+  // scratch per chunk: What [nk][n_rf][ns][L3], Ohat [nk][6][ns][L3], part [nk][n_rf][ns][12][L2]
+  const uint64_t per_sample = (uint64_t)(fp.n_rf + 6) * ns * L3 + (uint64_t)fp.n_rf * ns * 12 * L2;
+  const int chunk = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, scratch_elems / per_sample));
   const int n_samples = fp.n_outer * fp.n_inner;
   const size_t shm = (size_t)(L + L2) * sizeof(double2);
-  double2* part = scratch;
+  // pq tile of the accumulation: LDS holds (n_rf + 1) L pt complex values
+  int pt = 64;
+  while (pt > 1 && (size_t)(fp.n_rf + 1) * L * pt * sizeof(double2) > 60000) pt >>= 1;
+  const size_t gshm = (size_t)(fp.n_rf + 1) * L * pt * sizeof(double2);
+  const int gthreads = ((2 * fp.n_rf * pt + 63) / 64) * 64;
   for (int s0 = 0; s0 < n_samples; s0 += chunk) {
     const int nk = std::min(chunk, n_samples - s0);
-    double2* what = scratch + npart;
+    double2* what = scratch;
     double2* ohat = what + (uint64_t)nk * fp.n_rf * ns * L3;
+    double2* part = ohat + (uint64_t)nk * 6 * ns * L3;
     hipLaunchKernelGGL(field_dft_kernel<1>, dim3((unsigned)((uint64_t)nk * fp.n_rf * ns * L)), dim3(kDftThreads), shm,
                        st, lat, ml, fl, fp, s0, mlbuf, fbuf, what);
     hipLaunchKernelGGL(field_dft_kernel<0>, dim3((unsigned)((uint64_t)nk * 6 * ns * L)), dim3(kDftThreads), shm, st,
                        lat, ml, fl, fp, s0, mlbuf, fbuf, ohat);
-    const uint64_t na = (uint64_t)fp.n_rf * ns * L2;
-    hipLaunchKernelGGL(field_gacc_kernel, dim3(blocks_for(na, 64)), dim3(64), 0, st, fp, L, ns, nk, what, ohat, part);
-    hipLaunchKernelGGL(field_gred_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, ns, part, G);
+    hipLaunchKernelGGL(field_gacc_kernel, dim3((unsigned)((L2 + pt - 1) / pt), ns, nk), dim3(gthreads), gshm, st, fp, L,
+                       ns, pt, what, ohat, part);
+    hipLaunchKernelGGL(field_gred_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, ns, nk, part, G);
   }
   hipLaunchKernelGGL(field_final_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, G, F);
   return hipGetLastError();

@@ -94,6 +94,7 @@ def load_library(path: str = LIB_PATH):
         "u1ml_batch_destroy": (None, [P]),
         "u1ml_autotune": (I, [P, ip]),
         "u1ml_profile_sweeps": (I, [P, I, I, I, dp]),
+        "u1ml_batch_profile_sweeps": (I, [P, I, I, I, dp]),
         "u1ml_strerror": (C.c_char_p, [I]),
         "u1ml_last_error": (C.c_char_p, []),
     }
@@ -287,6 +288,14 @@ def profile_sweeps(lat: Lattice, n_sweeps: int, n_metro: int = 1, n_or: int = 3)
     out = np.zeros(2)
     _check(load_library().u1ml_profile_sweeps(lat.handle, n_sweeps, n_metro, n_or,
                                               out.ctypes.data_as(C.POINTER(C.c_double))))
+    return float(out[0]), float(out[1])
+
+
+def batch_profile_sweeps(b, n_sweeps: int, n_metro: int = 1, n_or: int = 3):
+    """Average class-pass kernel durations in microseconds for a batch: (Metropolis, OR)."""
+    out = np.zeros(2)
+    _check(load_library().u1ml_batch_profile_sweeps(b.handle, n_sweeps, n_metro, n_or,
+                                                    out.ctypes.data_as(C.POINTER(C.c_double))))
     return float(out[0]), float(out[1])
 
 
