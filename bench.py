@@ -1,6 +1,7 @@
-"""Benchmark: multilevel compact U(1) on a 24^4 lattice at beta = 1 on one MI355X.
+"""Benchmark: multilevel compact U(1) on 24^4 lattices at beta = 1 on one MI355X.
 
-One step is one pass of the whole method over the 24^4 lattice:
+One step advances R independent 24^4 chains (one batch, R = 8 by default) by
+one pass of the whole method each:
   * 100 compound sweeps (1 Metropolis hit + 3 overrelaxation passes per link)
     between measured configurations (Sec. 2.1);
   * one two-level multilevel measurement (Sec. 2.2): slabs of 4 (10 updates)
@@ -8,13 +9,15 @@ One step is one pass of the whole method over the 24^4 lattice:
     x, and the E/B field profiles (Eq. (5), Eq. (9)) over the 24^2 planes at
     the mid-point of charges at r = 2, 4, 6;
   * the plain observables and the read-back of all results.
-The lattice is synthetic (cold start + 200 thermalisation sweeps, seed 3).
+The lattices are synthetic (cold start + 200 thermalisation sweeps, seeds 3..).
 
-Printed: one JSON line with link updates/s of the Markov chain (the replay of
+Printed: one JSON line with link updates/s of the Markov chains (the replay of
 the update sequence that the field insertion needs is not counted as
 updates), multilevel samples/s (one sample = one innermost-slab update
 followed by its two-link measurement for all L^3 sources and all r), the
-roofline of the dominant kernel and the CPU oracle timed on this host.
+roofline of the dominant kernel, single-chain FP32 and FP64 legs, and the
+CPU oracle timed on this host.  --counters makes the short run used for the
+hardware-counter passes instead.
 """
 from __future__ import annotations
 
@@ -39,6 +42,9 @@ N_BETWEEN = 100
 N_THERM = 200
 HBM_PEAK_GBS = 8000.0
 WORDS_PER_UPDATE = 9  # 8 link reads + 1 write per update in a class pass
+DEFAULT_REPLICAS = 8
+CPU_N_SUB = [2, 5]  # reduced multilevel sample for the oracle
+COPY_ELEMS = 1 << 27  # calibration copy: 512 MiB read, 512 MiB written
 
 
 def chain_updates_per_step():
@@ -62,15 +68,16 @@ def sweep_sources_sha():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_key):
+def traffic_from_profiles(kernel_key, replicas, bytes_per_word):
     """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel sources; else None."""
+    on the current kernel sources and this batch shape; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(p) as f:
             d = json.load(f)
         e = d.get(kernel_key)
-        if e and e.get("sources_sha") == sweep_sources_sha():
+        if (e and e.get("sources_sha") == sweep_sources_sha() and e.get("replicas") == replicas
+                and e.get("bytes_per_word") == bytes_per_word):
             return e["bytes_per_launch"]
     except (OSError, ValueError):
         pass
@@ -92,13 +99,91 @@ def cpu_baseline(seconds: float):
             break
     ups = n * 16 * L ** 3 * T / el
     t0 = time.perf_counter()
-    o.multilevel(LEVELS, [1, 2], 1, 3, R_LIST)
+    o.multilevel(LEVELS, CPU_N_SUB, 1, 3, R_LIST)  # no field: the oracle's field accumulators exceed memory at 24^4
     el_ml = time.perf_counter() - t0
-    samp = 1 * 2 * (T // LEVELS[-1])
+    samp = CPU_N_SUB[0] * CPU_N_SUB[1] * (T // LEVELS[-1])
     return {"value": ups, "unit": "link updates/s", "cores": oracle.max_threads(), "kind": "oracle",
             "samples_per_s": samp / el_ml,
             "sample": f"{n} compound sweeps (1 Metropolis + 3 OR) of 24^4 FP64 in {el:.1f} s; "
-                      f"multilevel levels {LEVELS} with n_sub [1, 2], r = 1..12 ({samp} samples) in {el_ml:.1f} s"}
+                      f"multilevel levels {LEVELS} with n_sub {CPU_N_SUB}, r = 1..12, no field ({samp} samples) "
+                      f"in {el_ml:.1f} s"}
+
+
+def run_chain(u1ml, torch, stream, prec, R, rf, steps, warmup, with_events=True):
+    """Build R independent 24^4 chains (one batch when R > 1), thermalise, and
+    time `steps` steps.  Returns a dict of timings and the last results."""
+    if R == 1:
+        lat = u1ml.init_lattice(L, T, BETA, 3, start=u1ml.COLD, precision=prec)
+        sw = lambda: u1ml.sweep(lat, 1, 3)  # noqa: E731
+    else:
+        lat = u1ml.batch_create([L] * R, [T] * R, [BETA] * R, [3 + i for i in range(R)], start=u1ml.COLD,
+                                precision=prec, stream=stream.cuda_stream)
+        sw = lambda: u1ml.batch_sweep(lat, 1, 3)  # noqa: E731
+    for _ in range(N_THERM):
+        sw()
+    torch.cuda.synchronize()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        for _ in range(N_BETWEEN):
+            sw()
+        if ev:
+            ev[1].record(stream)
+        if R == 1:
+            u1ml.multilevel(lat, LEVELS, N_SUB, 1, 3, R_LIST, rf_list=rf)
+        else:
+            u1ml.batch_multilevel(lat, LEVELS, N_SUB, 1, 3, R_LIST, rf_list=rf)
+        if ev:
+            ev[2].record(stream)
+        if R == 1:
+            return u1ml.measure(lat, correlator=True, field_profile=bool(rf))
+        res = [u1ml.batch_measure(lat, i, correlator=True, field_profile=bool(rf)) for i in range(R)]
+        return res[0]
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        obs, corr, field = step(evs[k] if with_events else None)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_sweeps = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
+    ms_ml = sum(e[1].elapsed_time(e[2]) for e in evs) / steps
+    up_sw, up_ml = chain_updates_per_step()
+    return {"lat": lat, "el": el, "ms_step": 1e3 * el / steps, "ms_sweeps": ms_sweeps, "ms_ml": ms_ml,
+            "updates_per_s": R * (up_sw + up_ml) * steps / el, "sweep_updates_per_s": R * up_sw / (ms_sweeps * 1e-3),
+            "ml_updates_per_s": R * up_ml / (ms_ml * 1e-3), "samples_per_s": R * samples_per_step() / (ms_ml * 1e-3),
+            "obs": obs, "corr": corr}
+
+
+def counters_run(args):
+    """Short run for hardware-counter passes: a plain elementwise copy of a known
+    size (the calibration of FETCH_SIZE / WRITE_SIZE), then a few compound
+    sweeps of the benchmark batch."""
+    import torch
+    from paper_1208_0166_amd import u1ml
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    n = COPY_ELEMS
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    R = args.replicas
+    prec = u1ml.FP32 if args.precision == "fp32" else u1ml.FP64
+    lat = u1ml.batch_create([L] * R, [T] * R, [BETA] * R, [3 + i for i in range(R)], start=u1ml.COLD,
+                            precision=prec, stream=stream.cuda_stream)
+    for _ in range(4):
+        u1ml.batch_sweep(lat, 1, 3)
+    torch.cuda.synchronize()
+    print(json.dumps({"counters_run": True, "copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
+                      "replicas": R, "sweeps": 4}), flush=True)
 
 
 def main():
@@ -110,14 +195,22 @@ def main():
     ap.add_argument("--no-field", action="store_true", help="skip the field-profile insertion")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--fp64-compare", action="store_true", help="also time one step of the FP64 path")
-    ap.add_argument("--replicas", type=int, default=1,
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the single-chain FP32 and FP64 comparison legs")
+    ap.add_argument("--replicas", type=int, default=DEFAULT_REPLICAS,
                     help="independent 24^4 chains advanced by the same launches (one batch)")
+    ap.add_argument("--counters", action="store_true", help="short run for hardware-counter passes")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); there is no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    if args.replicas < 1:
+        print("--replicas must be >= 1", file=sys.stderr)
+        sys.exit(2)
+    if args.counters:
+        counters_run(args)
+        return
 
     import torch
     from paper_1208_0166_amd import u1ml
@@ -129,111 +222,76 @@ def main():
     torch.cuda.set_stream(stream)
     prec = u1ml.FP32 if args.precision == "fp32" else u1ml.FP64
     rf = [] if args.no_field else RF_LIST
-
     R = args.replicas
 
-    def make(pr):
-        if R == 1:
-            lat = u1ml.init_lattice(L, T, BETA, 3, start=u1ml.COLD, precision=pr)
-            sw = lambda: u1ml.sweep(lat, 1, 3)  # noqa: E731
-        else:
-            lat = u1ml.batch_create([L] * R, [T] * R, [BETA] * R, [3 + i for i in range(R)], start=u1ml.COLD,
-                                    precision=pr, stream=stream.cuda_stream)
-            sw = lambda: u1ml.batch_sweep(lat, 1, 3)  # noqa: E731
-        for _ in range(N_THERM):
-            sw()
-        torch.cuda.synchronize()
-        return lat, sw
+    main_run = run_chain(u1ml, torch, stream, prec, R, rf, args.steps, args.warmup)
+    lat = main_run["lat"]
 
-    lat, sw = make(prec)
-
-    def step(lt, swf, ev=None):
-        if ev:
-            ev[0].record(stream)
-        for _ in range(N_BETWEEN):
-            swf()
-        if ev:
-            ev[1].record(stream)
-        if R == 1:
-            u1ml.multilevel(lt, LEVELS, N_SUB, 1, 3, R_LIST, rf_list=rf)
-        else:
-            u1ml.batch_multilevel(lt, LEVELS, N_SUB, 1, 3, R_LIST, rf_list=rf)
-        if ev:
-            ev[2].record(stream)
-        if R == 1:
-            return u1ml.measure(lt, correlator=True, field_profile=bool(rf))
-        res = [u1ml.batch_measure(lt, i, correlator=True, field_profile=bool(rf)) for i in range(R)]
-        return res[0]
-
-    for _ in range(args.warmup):
-        step(lat, sw)
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        obs, corr, field = step(lat, sw, evs[k])
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ms_sweeps = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
-    ms_ml = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
-
-    up_sw, up_ml = chain_updates_per_step()
-    up_sw, up_ml = up_sw * R, up_ml * R
-    ms_step = 1e3 * el / args.steps
-    value = (up_sw + up_ml) * args.steps / el
-    samples = samples_per_step() * R
-
-    # dominant kernel: the FP32/FP64 overrelaxation class pass on the full lattice
-    prof_lat = lat if R == 1 else u1ml.init_lattice(L, T, BETA, 3, start=u1ml.COLD, precision=prec)
-    us_metro, us_or = u1ml.profile_sweeps(prof_lat, 20, 1, 3)
+    # dominant kernel: the class pass (Metropolis or OR, 9 words per update).
+    # Its average duration is taken over the timed region: the sweep phase of
+    # every step is N_BETWEEN compound sweeps of 4 x 8 class passes plus one
+    # pass-id bump, so (sweep phase time) / (class passes) bounds the duration
+    # from above.  The isolated per-launch figure is recorded beside it.
+    passes_per_step = N_BETWEEN * 4 * 8
+    avg_us = 1e3 * main_run["ms_sweeps"] / passes_per_step
     bw = 4 if prec == u1ml.FP32 else 8
-    updates_per_launch = L ** 3 * T // 2
+    updates_per_launch = R * L ** 3 * T // 2
     bytes_per_launch = updates_per_launch * WORDS_PER_UPDATE * bw
-    achieved = bytes_per_launch / (us_or * 1e-6) / 1e9
-    kname = f"class_pass_kernel<{'Fast32' if prec == u1ml.FP32 else 'Det64'}, OR>"
+    achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
+    pname = "Fast32" if prec == u1ml.FP32 else "Det64"
+    kname = f"class_pass_batch_kernel<{pname}, mu, kind>" if R > 1 else f"class_pass_kernel<{pname}, mu, kind>"
+    if R > 1:
+        iso_metro, iso_or = u1ml.batch_profile_sweeps(lat, 5, 1, 3)
+    else:
+        iso_metro, iso_or = u1ml.profile_sweeps(lat, 5, 1, 3)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(kname),
-                "kernel": kname, "avg_us": us_or, "metropolis_avg_us": us_metro,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(kname, R, bw),
+                "kernel": kname, "avg_us": avg_us, "launches_timed": passes_per_step * args.steps,
+                "isolated_event_us": {"metropolis": iso_metro, "or": iso_or},
                 "algorithmic_bytes_per_launch": bytes_per_launch}
 
+    obs, corr = main_run["obs"], main_run["corr"]
     out = {
         "metric": "link updates/s (Metropolis+OR) and multilevel correlator samples/s, 24^4 beta=1",
-        "value": value,
+        "value": main_run["updates_per_s"],
         "unit": "link updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": main_run["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if prec == u1ml.FP32 else "f64",
-        "data": "synthetic (cold start, 200 thermalisation sweeps, seed 3)",
-        "config": {"workload": "24^4 beta=1: 100 sweeps(1 Metropolis + 3 OR) + two-level multilevel "
-                               "{4,2} x {10,20}, r=1..12, E/B mid-plane profiles at r=2,4,6",
+        "data": "synthetic (cold start, 200 thermalisation sweeps, seeds 3..)",
+        "config": {"workload": f"{R} independent 24^4 beta=1 chains, each step per chain: 100 sweeps "
+                               "(1 Metropolis + 3 OR) + two-level multilevel {4,2} x {10,20}, r=1..12, "
+                               "E/B mid-plane profiles at r=2,4,6",
                    "lattice": [L, L, L, T], "beta": BETA, "levels": LEVELS, "n_sub": N_SUB,
                    "r": [1, 12], "field_r": rf, "accumulate": "f64", "replicas": R},
-        "samples_per_s": samples / (ms_ml * 1e-3),
-        "samples_per_step": samples,
-        "chain_updates_per_step": up_sw + up_ml,
-        "phase_ms": {"sweeps": ms_sweeps, "multilevel": ms_ml, "measure_and_readback": ms_step - ms_sweeps - ms_ml},
-        "sweep_updates_per_s": up_sw / (ms_sweeps * 1e-3),
-        "multilevel_chain_updates_per_s": up_ml / (ms_ml * 1e-3),
+        "samples_per_s": main_run["samples_per_s"],
+        "samples_per_step": samples_per_step() * R,
+        "chain_updates_per_step": R * sum(chain_updates_per_step()),
+        "phase_ms": {"sweeps": main_run["ms_sweeps"], "multilevel": main_run["ms_ml"],
+                     "measure_and_readback": main_run["ms_step"] - main_run["ms_sweeps"] - main_run["ms_ml"]},
+        "sweep_updates_per_s": main_run["sweep_updates_per_s"],
+        "multilevel_chain_updates_per_s": main_run["ml_updates_per_s"],
         "plaquette": obs["plaquette"],
         "poly_abs": obs["poly_abs"],
         "C_r1": [corr[0].real, corr[0].imag],
         "roofline": roofline,
     }
-    if args.fp64_compare and prec == u1ml.FP32:
-        lat64, sw64 = make(u1ml.FP64)
-        step(lat64, sw64)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        step(lat64, sw64)
-        torch.cuda.synchronize()
-        el64 = time.perf_counter() - t1
-        out["fp64_path"] = {"ms_per_step": 1e3 * el64, "link_updates_per_s": (up_sw + up_ml) / el64,
-                            "fp32_speedup": el64 / (el / args.steps)}
+    del lat, main_run
+    if not args.no_compare:
+        # one chain (no batching), FP32 path and plain FP64 path
+        legs = {}
+        for name, pr in (("single_chain_fp32", u1ml.FP32), ("single_chain_fp64", u1ml.FP64)):
+            r = run_chain(u1ml, torch, stream, pr, 1, rf, 1, 1)
+            legs[name] = {"updates_per_s": r["updates_per_s"], "samples_per_s": r["samples_per_s"],
+                          "ms_per_step": r["ms_step"], "phase_ms": {"sweeps": r["ms_sweeps"], "multilevel": r["ms_ml"]}}
+            del r
+        legs["speedup_vs_single_chain_fp64"] = out["value"] / legs["single_chain_fp64"]["updates_per_s"]
+        out["compare"] = legs
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

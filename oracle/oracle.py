@@ -13,6 +13,8 @@ import subprocess
 
 import numpy as np
 
+FIELD_MEMORY_LIMIT = 8 << 30  # bytes
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "u1ml_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
@@ -210,6 +212,14 @@ class OracleLattice:
         L = self.L
         field = np.zeros(max(n_rf, 1) * 2 * 6 * L * L * 2)
         log = np.zeros(max(log_cap, 1), dtype=np.uint8)
+        # the field accumulators hold every (slab, source, r, plane, offset,
+        # component) of a level: refuse sizes that would not fit in memory
+        if n_rf:
+            nslab = self.T // int(th[-1])
+            need = 2 * nslab * L ** 3 * n_rf * 2 * L * L * 6 * 16
+            if need > FIELD_MEMORY_LIMIT:
+                raise MemoryError(f"oracle field accumulators need {need / 2**30:.1f} GiB "
+                                  f"(limit {FIELD_MEMORY_LIMIT / 2**30:.0f} GiB); use a smaller lattice")
         used = C.c_long(0)
         rc = self._lib.or_multilevel(self._h, len(th), _ip(th), _ip(ns), n_metro, n_or, len(r), _ip(r),
                                      _dp(corr), n_rf, _ip(rf), _dp(field), _u8p(log) if log_cap else None,

@@ -233,37 +233,39 @@ struct Engine {
   }
 
   // --- updates ---
-  int class_pass(int kind, int mu, int parity, int th_frozen, int n_hits, uint8_t* logp) {
+  int class_pass(int kind, int mu, int parity, int th_frozen, int n_hits, uint8_t* logp, int bump_n = 0) {
     hipError_t e;
     if (n_lats == 1) {
       if (prec == U1ML_FP64)
         e = launch_class_pass_f64(kind, links.as<double>(), h_lats[0], block, mu, parity, th_frozen, n_hits,
-                                  pass_ids.as<uint64_t>(), logp, stream);
+                                  pass_ids.as<uint64_t>(), logp, bump_n, stream);
       else
         e = launch_class_pass_f32(kind, links.as<float>(), h_lats[0], block, mu, parity, th_frozen, n_hits,
-                                  pass_ids.as<uint64_t>(), logp, stream);
+                                  pass_ids.as<uint64_t>(), logp, bump_n, stream);
     } else {
       PassTable* t;
       U1_TRY(pass_table(mu > 0 && th_frozen > 0 ? th_frozen : 0, &t));
       if (prec == U1ML_FP64)
         e = launch_class_pass_batch_f64(kind, links.as<double>(), lats.as<LatDesc>(), t->buf.as<int4>(),
-                                        t->n_blocks, block, mu, parity, n_hits, pass_ids.as<uint64_t>(), stream);
+                                        t->n_blocks, block, mu, parity, n_hits, pass_ids.as<uint64_t>(), bump_n,
+                                        stream);
       else
         e = launch_class_pass_batch_f32(kind, links.as<float>(), lats.as<LatDesc>(), t->buf.as<int4>(),
-                                        t->n_blocks, block, mu, parity, n_hits, pass_ids.as<uint64_t>(), stream);
+                                        t->n_blocks, block, mu, parity, n_hits, pass_ids.as<uint64_t>(), bump_n,
+                                        stream);
     }
     U1_HIP(e);
     return U1ML_OK;
   }
 
-  int timed_class_pass(int kind, int mu, int parity, int th_frozen, int n_hits, uint8_t* logp) {
-    if (!prof[kind]) return class_pass(kind, mu, parity, th_frozen, n_hits, logp);
+  int timed_class_pass(int kind, int mu, int parity, int th_frozen, int n_hits, uint8_t* logp, int bump_n = 0) {
+    if (!prof[kind]) return class_pass(kind, mu, parity, th_frozen, n_hits, logp, bump_n);
     hipEvent_t a, z;
     U1_HIP(hipEventCreate(&a));
     U1_HIP(hipEventCreate(&z));
     prof[kind]->push_back(std::make_pair(a, z));
     U1_HIP(hipEventRecord(a, stream));
-    int rc = class_pass(kind, mu, parity, th_frozen, n_hits, logp);
+    int rc = class_pass(kind, mu, parity, th_frozen, n_hits, logp, bump_n);
     U1_HIP(hipEventRecord(z, stream));
     return rc;
   }
@@ -284,12 +286,17 @@ struct Engine {
           }
           U1_TRY(timed_class_pass(kMetropolis, mu, p, th_frozen, n_metro, lp));
         }
-      U1_HIP(launch_bump_pass_ids(pass_ids.as<uint64_t>(), n_lats, stream));
+      // the pass ids advance once per sweep with Metropolis hits: by the last
+      // OR pass (which reads none of them), else by a kernel of its own
+      if (n_or == 0) U1_HIP(launch_bump_pass_ids(pass_ids.as<uint64_t>(), n_lats, stream));
       for (auto& v : h_pass_ids) v += 1;
     }
     for (int k = 0; k < n_or; ++k)
       for (int mu = 0; mu < 4; ++mu)
-        for (int p = 0; p < 2; ++p) U1_TRY(timed_class_pass(kOverrelax, mu, p, th_frozen, 0, nullptr));
+        for (int p = 0; p < 2; ++p) {
+          const bool last = n_metro > 0 && k == n_or - 1 && mu == 3 && p == 1;
+          U1_TRY(timed_class_pass(kOverrelax, mu, p, th_frozen, 0, nullptr, last ? n_lats : 0));
+        }
     return U1ML_OK;
   }
 

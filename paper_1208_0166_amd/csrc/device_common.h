@@ -220,6 +220,17 @@ __host__ __device__ inline int class_slices(int T, int mu, int th) {
   return (T / th) * (th - 1);
 }
 
+// Workgroups go to the 8 XCDs round-robin by linear id, and every XCD has an
+// L2 of its own.  xcd_block maps the linear id b of nb workgroups to a logical
+// block such that XCD k runs one contiguous range of logical blocks, so that
+// neighbouring sites (which read each other's links) share an L2.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  const uint32_t xcd = b % kXcds, local = b / kXcds;
+  const uint32_t q = nb / kXcds, r = nb % kXcds;
+  return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
 struct Site {
   int t, x, y, z;
 };

@@ -21,21 +21,24 @@ struct BlockTable {
 // --- link updates (sweep_f64.hip, sweep_f32.hip) ---
 hipError_t launch_init_f64(double* links, const LatDesc* lats, BlockTable bt, int hot, hipStream_t st);
 hipError_t launch_init_f32(float* links, const LatDesc* lats, BlockTable bt, int hot, hipStream_t st);
-// one class pass of a single lattice (geometry by value); log as in u1ml_set_debug
+// one class pass of a single lattice (geometry by value); log as in u1ml_set_debug.
+// bump_n > 0 (overrelaxation passes only, which do not read the pass ids):
+// the pass also adds 1 to pass_ids[0 .. bump_n), once all its blocks are done
+// reading nothing from them; used on the last pass of a compound sweep.
 hipError_t launch_class_pass_f64(int kind, double* links, const LatDesc& d, int block, int mu, int parity,
-                                 int th_frozen, int n_hits, const uint64_t* pass_ids, uint8_t* log,
+                                 int th_frozen, int n_hits, uint64_t* pass_ids, uint8_t* log, int bump_n,
                                  hipStream_t st);
 hipError_t launch_class_pass_f32(int kind, float* links, const LatDesc& d, int block, int mu, int parity,
-                                 int th_frozen, int n_hits, const uint64_t* pass_ids, uint8_t* log,
+                                 int th_frozen, int n_hits, uint64_t* pass_ids, uint8_t* log, int bump_n,
                                  hipStream_t st);
 // one class pass of every lattice of a batch; blocks[b] = {lattice, time slice,
 // first offset within the slice, 0}, one block per (updated slice, chunk)
 hipError_t launch_class_pass_batch_f64(int kind, double* links, const LatDesc* lats, const int4* blocks,
                                        int n_blocks, int block, int mu, int parity, int n_hits,
-                                       const uint64_t* pass_ids, hipStream_t st);
+                                       uint64_t* pass_ids, int bump_n, hipStream_t st);
 hipError_t launch_class_pass_batch_f32(int kind, float* links, const LatDesc* lats, const int4* blocks,
                                        int n_blocks, int block, int mu, int parity, int n_hits,
-                                       const uint64_t* pass_ids, hipStream_t st);
+                                       uint64_t* pass_ids, int bump_n, hipStream_t st);
 hipError_t launch_bump_pass_ids(uint64_t* pass_ids, int n, hipStream_t st);
 // fill n bytes with v (graph-safe replacement of a memset)
 hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t st);

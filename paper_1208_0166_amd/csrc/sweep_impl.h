@@ -193,51 +193,61 @@ __device__ __forceinline__ void update_link(typename P::real* __restrict__ base,
 }
 
 // Single lattice: geometry in the kernel arguments; grid (blocks per slice,
-// updated slices).
+// updated slices), walked in XCD-contiguous order.
 template <class P, int MU, int KIND>
 __global__ void class_pass_kernel(typename P::real* __restrict__ links, LatDesc d, int parity, int th_frozen,
-                                  int n_hits, const uint64_t* __restrict__ pass_ids, uint8_t* __restrict__ log) {
-  const uint32_t off = blockIdx.x * blockDim.x + threadIdx.x;
+                                  int n_hits, uint64_t* __restrict__ pass_ids, uint8_t* __restrict__ log,
+                                  int bump_n) {
+  if (KIND == 1 && bump_n > 0 && blockIdx.x == 0 && blockIdx.y == 0)
+    for (int i = threadIdx.x; i < bump_n; i += blockDim.x) pass_ids[i] += 1;
+  const uint32_t lb = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const uint32_t by = lb / gridDim.x, bx = lb - by * gridDim.x;
+  const uint32_t off = bx * blockDim.x + threadIdx.x;
   if (off >= ((uint32_t)d.L3 >> 1)) return;
-  const int t = class_slice((int)blockIdx.y, MU, th_frozen);
+  const int t = class_slice((int)by, MU, th_frozen);
   update_link<P, MU, KIND>(links + d.off, d, t, off, parity, n_hits, KIND == 0 ? pass_ids[0] : 0, log);
 }
 
-// Batch: blocks[b] = {lattice, time slice, first offset in the slice, 0}.
+// Batch: blocks[b] = {lattice, time slice, first offset in the slice, 0},
+// walked in XCD-contiguous order.
 template <class P, int MU, int KIND>
 __global__ void class_pass_batch_kernel(typename P::real* __restrict__ links, const LatDesc* __restrict__ lats,
                                         const int4* __restrict__ blocks, int parity, int n_hits,
-                                        const uint64_t* __restrict__ pass_ids) {
-  const int4 bk = blocks[blockIdx.x];
+                                        uint64_t* __restrict__ pass_ids, int bump_n) {
+  if (KIND == 1 && bump_n > 0 && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < bump_n; i += blockDim.x) pass_ids[i] += 1;
+  const int4 bk = blocks[xcd_block(blockIdx.x, gridDim.x)];
   const LatDesc d = lats[bk.x];
   const uint32_t off = (uint32_t)bk.z + threadIdx.x;
   if (off >= ((uint32_t)d.L3 >> 1)) return;
   update_link<P, MU, KIND>(links + d.off, d, bk.y, off, parity, n_hits, KIND == 0 ? pass_ids[bk.x] : 0, nullptr);
 }
 
+hipError_t launch_bump_pass_ids(uint64_t* pass_ids, int n, hipStream_t st);
+
 // Launch helpers shared by the FP64 and FP32 translation units.
 template <class P, int KIND>
 hipError_t launch_pass_single(typename P::real* links, const LatDesc& d, int block, int mu, int parity, int th,
-                              int n_hits, const uint64_t* pass_ids, uint8_t* log, hipStream_t st) {
+                              int n_hits, uint64_t* pass_ids, uint8_t* log, int bump_n, hipStream_t st) {
   const int slices = class_slices(d.T, mu, th);
-  if (slices == 0) return hipSuccess;
+  if (slices == 0) return bump_n > 0 ? launch_bump_pass_ids(pass_ids, bump_n, st) : hipSuccess;
   const dim3 grid((d.L3 / 2 + block - 1) / block, slices);
   switch (mu) {
     case 0:
       hipLaunchKernelGGL((class_pass_kernel<P, 0, KIND>), grid, dim3(block), 0, st, links, d, parity, th, n_hits,
-                         pass_ids, log);
+                         pass_ids, log, bump_n);
       break;
     case 1:
       hipLaunchKernelGGL((class_pass_kernel<P, 1, KIND>), grid, dim3(block), 0, st, links, d, parity, th, n_hits,
-                         pass_ids, log);
+                         pass_ids, log, bump_n);
       break;
     case 2:
       hipLaunchKernelGGL((class_pass_kernel<P, 2, KIND>), grid, dim3(block), 0, st, links, d, parity, th, n_hits,
-                         pass_ids, log);
+                         pass_ids, log, bump_n);
       break;
     default:
       hipLaunchKernelGGL((class_pass_kernel<P, 3, KIND>), grid, dim3(block), 0, st, links, d, parity, th, n_hits,
-                         pass_ids, log);
+                         pass_ids, log, bump_n);
       break;
   }
   return hipGetLastError();
@@ -245,24 +255,25 @@ hipError_t launch_pass_single(typename P::real* links, const LatDesc& d, int blo
 
 template <class P, int KIND>
 hipError_t launch_pass_batch(typename P::real* links, const LatDesc* lats, const int4* blocks, int n_blocks,
-                             int block, int mu, int parity, int n_hits, const uint64_t* pass_ids, hipStream_t st) {
-  if (n_blocks == 0) return hipSuccess;
+                             int block, int mu, int parity, int n_hits, uint64_t* pass_ids, int bump_n,
+                             hipStream_t st) {
+  if (n_blocks == 0) return bump_n > 0 ? launch_bump_pass_ids(pass_ids, bump_n, st) : hipSuccess;
   switch (mu) {
     case 0:
       hipLaunchKernelGGL((class_pass_batch_kernel<P, 0, KIND>), dim3(n_blocks), dim3(block), 0, st, links, lats,
-                         blocks, parity, n_hits, pass_ids);
+                         blocks, parity, n_hits, pass_ids, bump_n);
       break;
     case 1:
       hipLaunchKernelGGL((class_pass_batch_kernel<P, 1, KIND>), dim3(n_blocks), dim3(block), 0, st, links, lats,
-                         blocks, parity, n_hits, pass_ids);
+                         blocks, parity, n_hits, pass_ids, bump_n);
       break;
     case 2:
       hipLaunchKernelGGL((class_pass_batch_kernel<P, 2, KIND>), dim3(n_blocks), dim3(block), 0, st, links, lats,
-                         blocks, parity, n_hits, pass_ids);
+                         blocks, parity, n_hits, pass_ids, bump_n);
       break;
     default:
       hipLaunchKernelGGL((class_pass_batch_kernel<P, 3, KIND>), dim3(n_blocks), dim3(block), 0, st, links, lats,
-                         blocks, parity, n_hits, pass_ids);
+                         blocks, parity, n_hits, pass_ids, bump_n);
       break;
   }
   return hipGetLastError();

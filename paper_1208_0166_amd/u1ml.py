@@ -150,13 +150,15 @@ class Lattice:
         self._keep = keepalive
         self._n_r = 0
         self._n_rf = 0
+        # bound now: module globals may already be gone when __del__ runs at exit
+        self._destroy = load_library().u1ml_destroy
 
     def __del__(self):
         self.close()
 
     def close(self):
         if getattr(self, "_h", None):
-            load_library().u1ml_destroy(self._h)
+            self._destroy(self._h)
             self._h = None
             self._keep = None
 
@@ -307,13 +309,14 @@ class Batch:
         self.L, self.T, self.beta, self.seed = list(L), list(T), list(beta), list(seed)
         self._n_r = None  # None: r = 1..T/2 of the last cycle
         self._n_rf = 0
+        self._destroy = load_library().u1ml_batch_destroy
 
     def __del__(self):
         self.close()
 
     def close(self):
         if getattr(self, "_h", None):
-            load_library().u1ml_batch_destroy(self._h)
+            self._destroy(self._h)
             self._h = None
 
     @property
