@@ -589,6 +589,28 @@ struct Engine {
   int ml_fold(int child, int parent, int sample_base) {
     MLState& m = ml;
     const int inner = m.n_levels - 1;
+    if (child == inner) {
+      int max_items = 0, max_L = 0;
+      for (int i = 0; i < n_lats; ++i) {
+        max_items = std::max(max_items, h_lats[i].L * m.h_mls[i].nR);
+        max_L = std::max(max_L, h_lats[i].L);
+      }
+      if (max_items <= ml_fold_rows_max_items()) {
+        std::vector<int> rows;
+        for (int i = 0; i < n_lats; ++i) {
+          const int nsp = parent == m.n_levels ? 1 : m.h_mls[i].ns[parent];
+          rows.push_back(nsp * h_lats[i].L * h_lats[i].L);
+        }
+        Table* t;
+        U1_TRY(table(rows, 1, &t));
+        const int per = (max_items + 1023) / 1024;  // items per thread, <= 4
+        const int threads = ((max_items + per - 1) / per + 63) / 64 * 64;
+        U1_HIP(launch_ml_fold_rows(lats.as<LatDesc>(), m.mls.as<MLDesc>(), bt(t), threads, max_L, child, parent,
+                                   m.n_levels, m.n[child], sample_base, m.rvals.as<int>(), m.mlbuf.as<double2>(),
+                                   m.accbuf.as<double2>(), stream));
+        return U1ML_OK;
+      }
+    }
     std::vector<int> it;
     for (int i = 0; i < n_lats; ++i) {
       int nsp = parent == m.n_levels ? 1 : m.h_mls[i].ns[parent];

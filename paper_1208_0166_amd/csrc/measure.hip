@@ -295,6 +295,80 @@ __global__ void ml_fold_kernel(const LatDesc* __restrict__ lats, const MLDesc* _
   }
 }
 
+// The same fold for innermost children, one block per (parent slab S, x-row
+// (y, z)): the rows of the stored samples are staged in LDS, so every time
+// line is read from memory once instead of once per separation.  Threads own
+// up to kFoldItems items (x0, k) with x0 fastest; the sample and child order of
+// the sums is that of ml_fold_kernel, so both give the same bits.
+constexpr int kFoldItems = 4;
+constexpr int kFoldStage = 8;  // samples per LDS round
+__global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls,
+                                    const int2* __restrict__ blocks, int child_level, int parent_level, int n_levels,
+                                    int n_child, int sample_base, const int* __restrict__ rvals,
+                                    const double2* __restrict__ mlbuf, double2* __restrict__ accbuf) {
+  extern __shared__ double2 rowbuf[];  // [kFoldStage][L]
+  const int2 bk = blocks[blockIdx.x];
+  const LatDesc d = lats[bk.x];
+  const MLDesc m = mls[bk.x];
+  const int L = d.L, L2 = L * L;
+  const int ns_child = m.ns[child_level];
+  const int ns_parent = parent_level == n_levels ? 1 : m.ns[parent_level];
+  const int children = ns_child / ns_parent;
+  const int S = bk.y / L2, row = bk.y - S * L2;
+  const int nitems = L * m.nR;
+  int x0[kFoldItems], xr[kFoldItems];
+  double2 prod[kFoldItems];
+#pragma unroll
+  for (int j = 0; j < kFoldItems; ++j) {
+    const int item = (int)threadIdx.x + j * (int)blockDim.x;
+    const int k = item / L;
+    x0[j] = item - k * L;
+    int x = item < nitems ? x0[j] + rvals[m.r_off + k] : x0[j];
+    x -= x >= L ? L : 0;
+    xr[j] = x;
+    prod[j] = make_double2(1.0, 0.0);
+  }
+  const double inv = 1.0 / (double)n_child;
+  for (int c = 0; c < children; ++c) {
+    const int cs = S * children + c;
+    double2 avg[kFoldItems];
+#pragma unroll
+    for (int j = 0; j < kFoldItems; ++j) avg[j] = make_double2(0.0, 0.0);
+    for (int i0 = 0; i0 < n_child; i0 += kFoldStage) {
+      const int nst = min(kFoldStage, n_child - i0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < nst * L; e += blockDim.x) {
+        const int i = e / L, x = e - i * L;
+        rowbuf[e] = mlbuf[m.ell + ((size_t)(sample_base + i0 + i) * ns_child + cs) * d.L3 + (size_t)row * L + x];
+      }
+      __syncthreads();
+      for (int i = 0; i < nst; ++i) {
+        const double2* e = rowbuf + i * L;
+#pragma unroll
+        for (int j = 0; j < kFoldItems; ++j) {
+          if ((int)threadIdx.x + j * (int)blockDim.x < nitems) {
+            const double2 u = e[x0[j]], v = e[xr[j]];
+            avg[j].x += u.x * v.x + u.y * v.y;
+            avg[j].y += u.x * v.y - u.y * v.x;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kFoldItems; ++j) prod[j] = cmul(prod[j], make_double2(avg[j].x * inv, avg[j].y * inv));
+  }
+#pragma unroll
+  for (int j = 0; j < kFoldItems; ++j) {
+    const int item = (int)threadIdx.x + j * (int)blockDim.x;
+    if (item < nitems) {
+      const int k = item / L;
+      double2* pp = accbuf + m.acc[parent_level] + ((size_t)S * d.L3 + (size_t)row * L + x0[j]) * m.nR + k;
+      pp->x += prod[j].x;
+      pp->y += prod[j].y;
+    }
+  }
+}
+
 __global__ void zero_kernel(double2* __restrict__ p, uint64_t n) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = make_double2(0.0, 0.0);
@@ -329,6 +403,19 @@ __global__ void ml_final_kernel(const LatDesc* __restrict__ lats, const MLDesc* 
 // the final weights, as a correlation over the mediator plane evaluated by 2D
 // discrete Fourier transforms in (y, z).
 // ---------------------------------------------------------------------------
+// sin of the plaquette angle: FP64 links in FP64; FP32 links (the fast path)
+// in FP32 arithmetic with the hardware sine, summed by the caller in FP64
+__device__ __forceinline__ double plaq_sin(const double* links, const LatDesc& d, Site s, int mu, int nu) {
+  return sin(plaq_angle(links, d, s, mu, nu));
+}
+__device__ __forceinline__ double plaq_sin(const float* links, const LatDesc& d, Site s, int mu, int nu) {
+  const float a = links[link_at(d, mu, s)];
+  const float b = links[link_at(d, nu, shift2(d, s, mu, 1, nu, 0))];
+  const float c = links[link_at(d, mu, shift2(d, s, nu, 1, mu, 0))];
+  const float e = links[link_at(d, nu, s)];
+  return (double)__sinf(((a + b) - c) - e);
+}
+
 // oall[((sample * 6 + c) * ns + s) * L3 + y] = sum over the times t of inner
 // slab s of O_c(y, t), O_c = sqrt(beta) Im P_munu (Eq. (5)).
 template <typename R>
@@ -348,12 +435,12 @@ __global__ void field_o_kernel(const R* __restrict__ links, const LatDesc* __res
   double o[6] = {0, 0, 0, 0, 0, 0};
   for (int t = s * th_inner; t < (s + 1) * th_inner; ++t) {
     st.t = t;
-    o[0] += sin(plaq_angle(links, d, st, 0, 1));
-    o[1] += sin(plaq_angle(links, d, st, 0, 2));
-    o[2] += sin(plaq_angle(links, d, st, 0, 3));
-    o[3] += sin(plaq_angle(links, d, st, 2, 3));
-    o[4] -= sin(plaq_angle(links, d, st, 1, 3));
-    o[5] += sin(plaq_angle(links, d, st, 1, 2));
+    o[0] += plaq_sin(links, d, st, 0, 1);
+    o[1] += plaq_sin(links, d, st, 0, 2);
+    o[2] += plaq_sin(links, d, st, 0, 3);
+    o[3] += plaq_sin(links, d, st, 2, 3);
+    o[4] -= plaq_sin(links, d, st, 1, 3);
+    o[5] += plaq_sin(links, d, st, 1, 2);
   }
   double* out = fbuf + fl.oall + (size_t)sample * 6 * fl.ns * d.L3;
   for (int c = 0; c < 6; ++c) out[((size_t)c * fl.ns + s) * d.L3 + y3] = d.sqrt_beta * o[c];
@@ -671,6 +758,18 @@ hipError_t launch_ml_fold(const LatDesc* lats, const MLDesc* mls, BlockTable bt,
                      parent_level, n_levels, child_is_inner, n_child, sample_base, rvals, mlbuf, accbuf);
   return hipGetLastError();
 }
+
+hipError_t launch_ml_fold_rows(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int threads, int max_L,
+                               int child_level, int parent_level, int n_levels, int n_child, int sample_base,
+                               const int* rvals, const double2* mlbuf, double2* accbuf, hipStream_t st) {
+  if (bt.n_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(ml_fold_rows_kernel, dim3(bt.n_blocks), dim3(threads),
+                     (size_t)kFoldStage * max_L * sizeof(double2), st, lats, mls, bt.dev, child_level, parent_level,
+                     n_levels, n_child, sample_base, rvals, mlbuf, accbuf);
+  return hipGetLastError();
+}
+
+int ml_fold_rows_max_items() { return kFoldItems * 1024; }
 
 hipError_t launch_ml_zero(double2* accbuf, uint64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;

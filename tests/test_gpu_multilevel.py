@@ -16,6 +16,12 @@ def say(*a):
     sys.stdout.flush()
 
 
+# field profile tolerance relative to its largest entry: FP64 sums of FP64
+# sines; for FP32 links the sines are FP32 (hardware sine, absolute error of
+# order 1e-6 on angles up to 4 pi) before the FP64 accumulation
+FIELD_REL = {u1ml.FP64: 1e-12, u1ml.FP32: 2e-5}
+
+
 def close_rel(a, b, rel=1e-12):
     scale = max(np.abs(b).max(), 1e-300)
     assert np.abs(a - b).max() <= rel * scale, (np.abs(a - b).max(), scale)
@@ -57,7 +63,8 @@ def test_multilevel_fp32_matches_identity_at_one_update():
     th = u1ml.get_links(g)
     ref = np.array([plain_corr(th, r) for r in (1, 2, 3)])
     np.testing.assert_allclose(c, ref, atol=1e-12)
-    np.testing.assert_allclose(f[0], field_identity(th, 1.0, 2), atol=1e-12)
+    # the FP32 path evaluates the plaquette sines of the field in FP32
+    close_rel(f[0], field_identity(th, 1.0, 2), rel=FIELD_REL[u1ml.FP32])
 
 
 @pytest.mark.parametrize("prec", [u1ml.FP64, u1ml.FP32])
@@ -75,7 +82,7 @@ def test_full_size_24_identity_and_plain_observables(oracle_mod, prec):
     obs, c, f = u1ml.measure(g, correlator=True, field_profile=True)
     th = u1ml.get_links(g)
     np.testing.assert_allclose(c, [plain_corr(th, r) for r in rl], atol=1e-12)
-    np.testing.assert_allclose(f[0], field_identity(th, 1.0, 2), atol=1e-12)
+    close_rel(f[0], field_identity(th, 1.0, 2), rel=FIELD_REL[prec])
     o = oracle_mod.OracleLattice(L, T, 1.0, 3, hot=False)
     o.set_links(th)
     assert abs(obs["plaquette"] - o.plaquette()) < 1e-12
