@@ -161,7 +161,10 @@ int u1ml_set_pass_id(u1ml_lattice *lat, uint64_t pass_id);
  * capacity bytes: one byte per (class pass, half-site, hit) in launch order,
  * 1 = accepted, 0 = rejected, 2 = frozen.  Passes that no longer fit are not
  * recorded.  flags = 0 disables and frees it.  Recording forces one launch
- * per class pass (no fused or captured schedule). */
+ * per class pass (no fused or captured schedule).  flags & 2 makes the field
+ * insertion use the general contraction (both transforms stored, then
+ * contracted by tiles) even where the fused one applies; results agree to
+ * rounding. */
 int u1ml_set_debug(u1ml_lattice *lat, unsigned flags, size_t capacity);
 /* Copy the log out: *n_bytes = bytes recorded; copies min(cap, *n_bytes). */
 int u1ml_get_accept_log(u1ml_lattice *lat, uint8_t *out, size_t cap, size_t *n_bytes);

@@ -24,6 +24,7 @@ SOURCES = {
     "sweep_f64.hip": ["-ffp-contract=off"],
     "sweep_f32.hip": [],
     "measure.hip": [],
+    "field.hip": [],
     "abi.cpp": ["-x", "hip"],
 }
 

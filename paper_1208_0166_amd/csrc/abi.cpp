@@ -142,6 +142,7 @@ struct Engine {
   DevBuf log;
   size_t log_cap = 0, log_used = 0;
   bool debug = false;
+  bool field_general = false;  // u1ml_set_debug flags & 2
   // measurement scratch
   DevBuf partial, rows, poly, poly_off, row_begin, red_out, rvals_tmp;
   MLState ml;
@@ -670,7 +671,7 @@ struct Engine {
         U1_HIP(launch_field_contract(lats.as<LatDesc>() + i, m.mls.as<MLDesc>() + i, m.fls.as<FieldLat>() + i,
                                      m.h_fls[i], m.fp, h_lats[i].L, m.mlbuf.as<double2>(), m.accbuf.as<double2>(),
                                      m.fbuf.as<double>(), m.scratch.as<double2>(), m.scratch_elems,
-                                     m.fout.as<double2>() + m.fout_off[i], stream));
+                                     m.fout.as<double2>() + m.fout_off[i], field_general, stream));
     }
     U1_TRY(ml_fold(0, m.n_levels, 0));
     U1_HIP(launch_ml_final(lats.as<LatDesc>(), m.mls.as<MLDesc>(), n_lats, m.max_r, m.n_levels,
@@ -945,6 +946,10 @@ int u1ml_set_debug(u1ml_lattice* lat, unsigned flags, size_t capacity) {
   Engine& e = lat->e;
   U1_TRY(e.set_device());
   U1_HIP(hipStreamSynchronize(e.stream));
+  if (e.field_general != ((flags & 2u) != 0)) {
+    e.drop_graphs();  // captured schedules hold the other contraction
+    e.field_general = (flags & 2u) != 0;
+  }
   if (flags & 1u) {
     U1_TRY(e.log.ensure(capacity));
     // frozen links get no thread; their entries keep this marker

@@ -105,9 +105,10 @@ struct FieldParams {
 };
 hipError_t launch_field_o(int prec, const void* links, const LatDesc* lats, const FieldLat* fls, BlockTable bt,
                           int th_inner, int sample, double* fbuf, hipStream_t st);
-// contraction of all stored samples of one lattice into F [n_rf][2][6][L][L] (complex)
+// contraction of all stored samples of one lattice into F [n_rf][2][6][L][L]
+// (complex); general = true takes the stored-transform path for any geometry
 hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,
                                  FieldParams fp, int L, const double2* mlbuf, const double2* accbuf, double* fbuf,
-                                 double2* scratch, size_t scratch_elems, double2* F, hipStream_t st);
+                                 double2* scratch, size_t scratch_elems, double2* F, bool general, hipStream_t st);
 
 }  // namespace u1ml

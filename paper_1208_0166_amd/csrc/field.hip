@@ -1,0 +1,550 @@
+// field.hip -- contraction of the stored field insertions (Eq. (9)) into the
+// E/B profiles over the mediator plane.
+//
+// Every inner sample keeps its slab time-line phases (ell) and the slab sums
+// of the field operators (oall).  After the run the weights are known, and
+//   F(dy, dz) = sum_{samples, slabs, x0} W(x0) O(x0 + m e_x + dy e_y + dz e_z)
+// is a cyclic correlation over the (y, z) plane for every x, evaluated with
+// 2D discrete Fourier transforms: G(p, q) = sum What(-p, -q) Ohat(p, q), and
+// F is L^-2 times the inverse transform of G.  All sums are FP64 in a fixed
+// order.
+#include <algorithm>
+
+#include "fft_reg.h"
+#include "measure_common.h"
+
+namespace u1ml {
+
+namespace {
+
+// tavg[((m * ns + s) * L3 + x0) * n_rf + f] = average over the n_inner samples
+// of outer iteration m of T(x0, rf[f]) in inner slab s
+__global__ void field_tavg_kernel(const LatDesc* __restrict__ lat, const MLDesc* __restrict__ mlp,
+                                  const FieldLat* __restrict__ flp, FieldParams fp,
+                                  const double2* __restrict__ mlbuf, double* __restrict__ fbuf) {
+  const LatDesc d = *lat;
+  const MLDesc ml = *mlp;
+  const FieldLat fl = *flp;
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= fp.n_outer * fl.ns * d.L3 * fp.n_rf) return;
+  const int f = item % fp.n_rf;
+  const int x0 = (item / fp.n_rf) % d.L3;
+  const int s = (item / (fp.n_rf * d.L3)) % fl.ns;
+  const int m = item / (fp.n_rf * d.L3 * fl.ns);
+  const double2* ell = mlbuf + ml.ell + (size_t)m * fp.n_inner * fl.ns * d.L3;
+  ((double2*)(fbuf + fl.tavg))[item] = inner_avg(ell, fp.n_inner, fl.ns, d.L3, s, x0, shift_x(d, x0, fp.rf[f]));
+}
+
+// weight of an insertion in inner slab s during outer iteration m:
+//   one level:  prod_{s' != s} [T]_{s'} / (n V)
+//   two levels: prod_{j != k} A_j * prod_{s' in k, s' != s} [T]_{s',m} / (n_0 n_1 V)
+// with k the top slab holding s and A_j the top-level averages.
+__global__ void field_weights_kernel(const LatDesc* __restrict__ lat, const MLDesc* __restrict__ mlp,
+                                     const FieldLat* __restrict__ flp, FieldParams fp,
+                                     const double2* __restrict__ accbuf, double* __restrict__ fbuf) {
+  const LatDesc d = *lat;
+  const MLDesc ml = *mlp;
+  const FieldLat fl = *flp;
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= fp.n_outer * fl.ns * d.L3 * fp.n_rf) return;
+  const int f = item % fp.n_rf;
+  const int x0 = (item / fp.n_rf) % d.L3;
+  const int s = (item / (fp.n_rf * d.L3)) % fl.ns;
+  const int m = item / (fp.n_rf * d.L3 * fl.ns);
+  const int children = fp.n_levels == 2 ? fl.ns / ml.ns[0] : fl.ns;
+  const int k = s / children;
+  const double2* tavg = (const double2*)(fbuf + fl.tavg);
+  double2 p = make_double2(1.0, 0.0);
+  for (int j = 0; j < children; ++j) {
+    const int sp = k * children + j;
+    if (sp == s) continue;
+    p = cmul(p, tavg[(((size_t)m * fl.ns + sp) * d.L3 + x0) * fp.n_rf + f]);
+  }
+  double norm = (double)fp.n_inner * (double)d.V2 * 2.0;
+  if (fp.n_levels == 2) {
+    const int ntop = ml.ns[0];
+    const double inv = 1.0 / (double)fp.n_outer;
+    for (int j = 0; j < ntop; ++j) {
+      if (j == k) continue;
+      const double2 a = accbuf[ml.acc[0] + ((size_t)j * d.L3 + x0) * ml.nR + fp.rf_k[f]];
+      p = cmul(p, make_double2(a.x * inv, a.y * inv));
+    }
+    norm *= (double)fp.n_outer;
+  }
+  ((double2*)(fbuf + fl.w))[item] = make_double2(p.x / norm, p.y / norm);
+}
+
+// 2D DFT over (y, z) of one x-plane per block, in place in LDS:
+//   out[b][p][q] = sum_{y,z} v(x, y, z) exp(-2 pi i (p y + q z) / L)
+// KIND 0: v = the stored field slab sums O_c of sample k (real);
+// KIND 1: v = W_f(x0) = w[m][s][x0][f] T_k(x0, s; rf[f]) built on the fly,
+//         transformed with exp(+2 pi i ...) so that out[b][p][q] = What(-p, -q).
+// Block b enumerates (k, a, s, x) with x fastest; a = c (KIND 0) or f (KIND 1).
+constexpr int kDftThreads = 256;
+constexpr int kDftMaxPer = 16;  // ceil(62^2 / 256)
+
+template <int KIND>
+__global__ __launch_bounds__(kDftThreads) void field_dft_kernel(const LatDesc* __restrict__ lat,
+                                                                const MLDesc* __restrict__ mlp,
+                                                                const FieldLat* __restrict__ flp, FieldParams fp,
+                                                                int sample0, const double2* __restrict__ mlbuf,
+                                                                const double* __restrict__ fbuf,
+                                                                double2* __restrict__ out) {
+  extern __shared__ double2 sm[];
+  const LatDesc d = *lat;
+  const FieldLat fl = *flp;
+  const int L = d.L, L2 = L * L, ns = fl.ns;
+  const int A = KIND == 0 ? 6 : fp.n_rf;
+  double2* tw = sm;       // exp(-2 pi i k / L)
+  double2* buf = sm + L;  // plane [y][z] -> [y][q] -> [p][q]
+  const int b = blockIdx.x;
+  const int x = b % L, s = (b / L) % ns, a = (b / (L * ns)) % A, k = b / (L * ns * A);
+  const int sample = sample0 + k;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)i / (double)L, &sn, &cs);
+    tw[i] = make_double2(cs, KIND == 0 ? -sn : sn);
+  }
+  if (KIND == 0) {
+    const double* src = fbuf + fl.oall + (((size_t)sample * 6 + a) * ns + s) * d.L3;
+    for (int i = threadIdx.x; i < L2; i += blockDim.x) {
+      const int y = i / L, z = i - y * L;
+      buf[i] = make_double2(src[(size_t)(z * L + y) * L + x], 0.0);
+    }
+  } else {
+    const MLDesc ml = *mlp;
+    const int m = sample / fp.n_inner;
+    const double2* e = mlbuf + ml.ell + ((size_t)sample * ns + s) * d.L3;
+    const double2* w = (const double2*)(fbuf + fl.w);
+    for (int i = threadIdx.x; i < L2; i += blockDim.x) {
+      const int y = i / L, z = i - y * L;
+      const int x0 = (z * L + y) * L + x;
+      const double2 u = e[x0], v = e[shift_x(d, x0, fp.rf[a])];
+      const double2 t = make_double2(u.x * v.x + u.y * v.y, u.x * v.y - u.y * v.x);
+      buf[i] = cmul(w[(((size_t)m * ns + s) * d.L3 + x0) * fp.n_rf + a], t);
+    }
+  }
+  __syncthreads();
+  double2 r[kDftMaxPer];
+  // along z: buf[y][z] -> [y][q]
+#pragma unroll
+  for (int j = 0; j < kDftMaxPer; ++j) {
+    const int i = threadIdx.x + j * kDftThreads;
+    if (i < L2) {
+      const int y = i / L, q = i - y * L;
+      double re = 0.0, im = 0.0;
+      int kk = 0;
+      for (int z = 0; z < L; ++z) {
+        const double2 v = buf[y * L + z], t = tw[kk];
+        re += v.x * t.x - v.y * t.y;
+        im += v.x * t.y + v.y * t.x;
+        kk += q;
+        kk -= (kk >= L) ? L : 0;
+      }
+      r[j] = make_double2(re, im);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kDftMaxPer; ++j) {
+    const int i = threadIdx.x + j * kDftThreads;
+    if (i < L2) buf[i] = r[j];
+  }
+  __syncthreads();
+  // along y: [y][q] -> [p][q]
+  double2* dst = out + (size_t)b * L2;
+#pragma unroll
+  for (int j = 0; j < kDftMaxPer; ++j) {
+    const int i = threadIdx.x + j * kDftThreads;
+    if (i < L2) {
+      const int p = i / L, q = i - p * L;
+      double re = 0.0, im = 0.0;
+      int kk = 0;
+      for (int y = 0; y < L; ++y) {
+        const double2 v = buf[y * L + q], t = tw[kk];
+        re += v.x * t.x - v.y * t.y;
+        im += v.x * t.y + v.y * t.x;
+        kk += p;
+        kk -= (kk >= L) ? L : 0;
+      }
+      dst[i] = make_double2(re, im);
+    }
+  }
+}
+
+// part[((((k * n_rf + f) * ns + s) * 2 + plane) * 6 + c) * L2 + pq] =
+//   sum_x What[k][f][s][x](-pq) * Ohat[k][c][s][x + m_plane](pq),  m_0 = (r-1)/2, m_1 = r/2.
+// Block (pq tile, s, k); threads (pq in tile, f, plane).  The W tile of all x
+// and the O tile of one component at a time are staged in LDS, so every
+// transformed value is read from memory once.
+__global__ void field_gacc_kernel(FieldParams fp, int L, int ns, int pt, const double2* __restrict__ what,
+                                  const double2* __restrict__ ohat, double2* __restrict__ part) {
+  extern __shared__ double2 sm[];
+  const int L2 = L * L;
+  const int s = blockIdx.y, k = blockIdx.z;
+  const int pq0 = blockIdx.x * pt;
+  const int npq = min(pt, L2 - pq0);
+  double2* wt = sm;                      // [f][x][pt]
+  double2* ot = sm + fp.n_rf * L * pt;  // [x][pt]
+  const int tid = threadIdx.x;
+  const int j = tid % pt, fpl = tid / pt;  // fpl = f * 2 + plane
+  const bool active = fpl < 2 * fp.n_rf && j < npq;
+  const int f = fpl >> 1, plane = fpl & 1;
+  int m = 0;
+  if (fpl < 2 * fp.n_rf) {
+    const int r = fp.rf[f];
+    m = plane == 0 ? (r - 1) / 2 : r / 2;
+  }
+  for (int i = tid; i < fp.n_rf * L * pt; i += blockDim.x) {
+    const int jj = i % pt, x = (i / pt) % L, ff = i / (pt * L);
+    wt[i] = jj < npq ? what[((((size_t)k * fp.n_rf + ff) * ns + s) * L + x) * L2 + pq0 + jj] : make_double2(0.0, 0.0);
+  }
+  double2 acc[6];
+  for (int c = 0; c < 6; ++c) {
+    __syncthreads();
+    for (int i = tid; i < L * pt; i += blockDim.x) {
+      const int jj = i % pt, x = i / pt;
+      ot[i] = jj < npq ? ohat[((((size_t)k * 6 + c) * ns + s) * L + x) * L2 + pq0 + jj] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double re = 0.0, im = 0.0;
+    if (active) {
+      const double2* wr = wt + (size_t)f * L * pt + j;
+      int xx = m;
+      for (int x = 0; x < L; ++x) {
+        const double2 w = wr[x * pt], o = ot[xx * pt + j];
+        re += w.x * o.x - w.y * o.y;
+        im += w.x * o.y + w.y * o.x;
+        ++xx;
+        xx -= (xx >= L) ? L : 0;
+      }
+    }
+    acc[c] = make_double2(re, im);
+  }
+  if (active)
+    for (int c = 0; c < 6; ++c)
+      part[(((((size_t)k * fp.n_rf + f) * ns + s) * 2 + plane) * 6 + c) * L2 + pq0 + j] = acc[c];
+}
+
+// G[((f * 2 + plane) * 6 + c) * L2 + pq] += sum_k sum_s part[...] (fixed order)
+__global__ void field_gred_kernel(FieldParams fp, int L, int ns, int nk, const double2* __restrict__ part,
+                                  double2* __restrict__ G) {
+  const int L2 = L * L;
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= fp.n_rf * 12 * L2) return;
+  const int pq = item % L2;
+  const int pc = (item / L2) % 12;  // plane * 6 + c
+  const int f = item / (12 * L2);
+  double re = 0.0, im = 0.0;
+  for (int k = 0; k < nk; ++k)
+    for (int s = 0; s < ns; ++s) {
+      const double2 v = part[((((size_t)k * fp.n_rf + f) * ns + s) * 12 + pc) * L2 + pq];
+      re += v.x;
+      im += v.y;
+    }
+  G[item].x += re;
+  G[item].y += im;
+}
+
+// F[((f * 2 + plane) * 6 + c) * L2 + (dy, dz)] = L^-2 sum_{p,q} G(p, q) exp(+2 pi i (p dy + q dz) / L)
+__global__ void field_final_kernel(FieldParams fp, int L, const double2* __restrict__ G, double2* __restrict__ F) {
+  const int L2 = L * L;
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= fp.n_rf * 12 * L2) return;
+  const int dd = item % L2;
+  const int dy = dd / L, dz = dd - dy * L;
+  const double2* g = G + (size_t)(item / L2) * L2;
+  double re = 0.0, im = 0.0;
+  for (int p = 0; p < L; ++p)
+    for (int q = 0; q < L; ++q) {
+      const int k = (p * dy + q * dz) % L;
+      double sn, cs;
+      sincospi(2.0 * (double)k / (double)L, &sn, &cs);
+      const double2 v = g[p * L + q];
+      re += v.x * cs - v.y * sn;
+      im += v.x * sn + v.y * cs;
+    }
+  const double inv = 1.0 / (double)L2;
+  F[item] = make_double2(re * inv, im * inv);
+}
+
+// ---------------------------------------------------------------------------
+// Fast path (L with factors 2, 3, 5 only, L <= kFxMaxL).  Each 1D transform is
+// a thread-private row or column FFT in registers (fft_reg.h) over planes
+// staged in LDS.  The O planes are real: two neighbouring x planes are
+// transformed together as one complex plane Z = O_a + i O_b and separated in
+// Fourier space,
+//   Ohat_a(k) = (Z(k) + conj Z(-k)) / 2,   Ohat_b(k) = (Z(k) - conj Z(-k)) / 2i.
+// The O transforms never leave LDS: field_ocon_kernel contracts them with the
+// stored W transforms right away.
+// ---------------------------------------------------------------------------
+constexpr int kFxMaxL = 32;
+constexpr int kFxAcc = 8;         // G accumulators (complex) per thread
+constexpr size_t kFxLds = 64512;  // LDS per block (bytes)
+
+// in-place FFT of the N values v[i * stride] (LDS)
+template <int N, int SIGN>
+__device__ __forceinline__ void fft_line(double2* v, int stride) {
+  double2 y[N];
+#pragma unroll
+  for (int n = 0; n < N; ++n) y[fftreg::kPos<N>.v[n]] = v[n * stride];
+  fftreg::run<N, SIGN>(y);
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k * stride] = y[k];
+}
+
+// What[((k * n_rf + f) * ns + s) * L + x][p * L + q] = sum_{y,z} W(x, y, z) exp(+2 pi i (p y + q z) / L),
+// i.e. the transform of W at (-p, -q).  Block: (k, f, s, group of npb x planes).
+// The planes are built in LDS (coalesced reads), transformed along z by rows
+// (thread = (x, y)) and along y by columns (thread = (x, q)), and stored.
+template <int L>
+__global__ __launch_bounds__(256) void field_what_kernel(const LatDesc* __restrict__ lat,
+                                                         const MLDesc* __restrict__ mlp,
+                                                         const FieldLat* __restrict__ flp, FieldParams fp,
+                                                         int sample0, int npb, const double2* __restrict__ mlbuf,
+                                                         const double* __restrict__ fbuf,
+                                                         double2* __restrict__ what) {
+  extern __shared__ double2 pl[];  // [nx][L (y)][L + 1]
+  constexpr int L1 = L + 1;
+  const LatDesc d = *lat;
+  const FieldLat fl = *flp;
+  const int ns = fl.ns;
+  const int ngroups = (L + npb - 1) / npb;
+  const int b = blockIdx.x;
+  const int grp = b % ngroups, s = (b / ngroups) % ns, f = (b / (ngroups * ns)) % fp.n_rf;
+  const int k = b / (ngroups * ns * fp.n_rf);
+  const int x0 = grp * npb, nx = min(npb, L - x0);
+  const int sample = sample0 + k, m = sample / fp.n_inner;
+  const MLDesc ml = *mlp;
+  const double2* e = mlbuf + ml.ell + ((size_t)sample * ns + s) * d.L3;
+  const double2* w = (const double2*)(fbuf + fl.w) + ((size_t)m * ns + s) * d.L3 * fp.n_rf + f;
+  const int r = fp.rf[f];
+  const int tid = threadIdx.x;
+  // W(x, y, z) = w(x0) conj(e(x0)) e(x0 + r), x0 = (z L + y) L + x, x fastest
+  for (int i = tid; i < nx * L * L; i += blockDim.x) {
+    const int xc = i % nx, yz = i / nx, y = yz % L, z = yz / L, x = x0 + xc;
+    int xr = x + r;
+    xr -= xr >= L ? L : 0;
+    const int row = (z * L + y) * L;
+    const double2 u = e[row + x], v = e[row + xr];
+    pl[(xc * L + y) * L1 + z] =
+        cmul(w[(size_t)(row + x) * fp.n_rf], make_double2(u.x * v.x + u.y * v.y, u.x * v.y - u.y * v.x));
+  }
+  __syncthreads();
+  const bool active = tid < nx * L;
+  const int xc = tid / L, t = tid - xc * L;
+  if (active) fft_line<L, 1>(pl + (xc * L + t) * L1, 1);  // row y = t, along z
+  __syncthreads();
+  if (active) {
+    double2* col = pl + xc * L * L1 + t;  // column q = t, along y
+    fft_line<L, 1>(col, L1);
+    double2* dst = what + ((((size_t)k * fp.n_rf + f) * ns + s) * L + x0 + xc) * L * L + t;
+#pragma unroll
+    for (int p = 0; p < L; ++p) dst[p * L] = col[p * L1];
+  }
+}
+
+// part[((k * ns + s) * 6 + c) * 2 n_rf L^2 + g], g = (f * 2 + plane) * L^2 + p * L + q:
+//   sum_x What[k][f][s][x - m](p, q) * Ohat_c[k][s][x](p, q),  m_0 = (r - 1) / 2, m_1 = r / 2.
+// Block: (k, s, c) over all x, in groups of npb planes (npb even, pairs of
+// planes as one complex plane).  Thread = row (pair, y) in pass 1, column
+// (pair, q) in pass 2, and owner of the G entries g = tid + j * blockDim.x.
+template <int L>
+__global__ __launch_bounds__(512) void field_ocon_kernel(const LatDesc* __restrict__ lat,
+                                                         const FieldLat* __restrict__ flp, FieldParams fp,
+                                                         int sample0, int npb, int nacc,
+                                                         const double* __restrict__ fbuf,
+                                                         const double2* __restrict__ what,
+                                                         double2* __restrict__ part) {
+  extern __shared__ double2 zb[];  // [pairs][L][L + 1]
+  constexpr int L1 = L + 1, L2 = L * L;
+  const LatDesc d = *lat;
+  const FieldLat fl = *flp;
+  const int ns = fl.ns;
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x);  // the six c of one (k, s) share an L2
+  const int c = lb % 6, s = (lb / 6) % ns, k = lb / (6 * ns);
+  const int sample = sample0 + k;
+  const double* o = fbuf + fl.oall + (((size_t)sample * 6 + c) * ns + s) * d.L3;
+  const double2* wk = what + ((size_t)k * fp.n_rf * ns + s) * L * L2;  // + (f * ns * L + x) * L2
+  const int tid = threadIdx.x;
+  const int n_ent = 2 * fp.n_rf * L2;
+  double2 g[kFxAcc];
+#pragma unroll
+  for (int j = 0; j < kFxAcc; ++j) g[j] = make_double2(0.0, 0.0);
+  for (int x0 = 0; x0 < L; x0 += npb) {
+    const int np = min(npb, L - x0) >> 1;  // pairs in this group
+    __syncthreads();  // the previous group's contraction is done with zb
+    // Z(y, z) = O(xa, y, z) + i O(xa + 1, y, z), xa = x0 + 2 pr, pairs fastest
+    for (int i = tid; i < np * L2; i += blockDim.x) {
+      const int pr = i % np, yz = i / np, y = yz % L, z = yz / L;
+      zb[(pr * L + y) * L1 + z] = *(const double2*)(o + (z * L + y) * L + x0 + 2 * pr);
+    }
+    __syncthreads();
+    const bool active = tid < np * L;
+    const int pr = tid / L, t = tid - pr * L;
+    if (active) fft_line<L, -1>(zb + (pr * L + t) * L1, 1);  // rows, along z
+    __syncthreads();
+    if (active) fft_line<L, -1>(zb + pr * L * L1 + t, L1);  // columns, along y
+    __syncthreads();
+    // contraction over the planes of this group
+#pragma unroll
+    for (int j = 0; j < kFxAcc; ++j) {
+      const int e = tid + j * (int)blockDim.x;
+      if (j < nacc && e < n_ent) {
+        const int fpl = e / L2, pq = e - fpl * L2;
+        const int f = fpl >> 1, r = fp.rf[f];
+        const int mm = (fpl & 1) ? r / 2 : (r - 1) / 2;
+        const int p = pq / L, qq = pq - p * L;
+        const int ia = p * L1 + qq;                                          // Z(k)
+        const int ib = (p == 0 ? 0 : L - p) * L1 + (qq == 0 ? 0 : L - qq);  // Z(-k)
+        const double2* wf = wk + (size_t)f * ns * L * L2 + pq;
+        int xw = x0 - mm;  // W plane paired with O plane x: x - m
+        xw += xw < 0 ? L : 0;
+        double gx = g[j].x, gy = g[j].y;
+        for (int pp = 0; pp < np; ++pp) {
+          const double2 a = zb[pp * L * L1 + ia], bm = zb[pp * L * L1 + ib];
+          const double2 sum = make_double2(0.5 * (a.x + bm.x), 0.5 * (a.y - bm.y));   // Ohat of x
+          const double2 dif = make_double2(0.5 * (a.y + bm.y), -0.5 * (a.x - bm.x));  // Ohat of x + 1
+          int xw1 = xw + 1;
+          xw1 -= xw1 >= L ? L : 0;
+          const double2 wa = wf[(size_t)xw * L2], wb = wf[(size_t)xw1 * L2];
+          gx += (wa.x * sum.x - wa.y * sum.y) + (wb.x * dif.x - wb.y * dif.y);
+          gy += (wa.x * sum.y + wa.y * sum.x) + (wb.x * dif.y + wb.y * dif.x);
+          xw = xw1 + 1;
+          xw -= xw >= L ? L : 0;
+        }
+        g[j] = make_double2(gx, gy);
+      }
+    }
+  }
+  double2* out = part + ((size_t)(k * ns + s) * 6 + c) * n_ent;
+#pragma unroll
+  for (int j = 0; j < kFxAcc; ++j) {
+    const int e = tid + j * (int)blockDim.x;
+    if (j < nacc && e < n_ent) out[e] = g[j];
+  }
+}
+
+// G[((f * 2 + plane) * 6 + c) * L2 + pq] += sum over k, s of part (fixed order)
+__global__ void field_gsum_kernel(FieldParams fp, int L, int ns, int nk, const double2* __restrict__ part,
+                                  double2* __restrict__ G) {
+  const int L2 = L * L, n_ent = 2 * fp.n_rf * L2;
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= 6 * n_ent) return;
+  const int pq = item % L2, c = (item / L2) % 6, fpl = item / (6 * L2);
+  const int e = fpl * L2 + pq;
+  double re = 0.0, im = 0.0;
+  for (int k = 0; k < nk; ++k)
+    for (int s = 0; s < ns; ++s) {
+      const double2 v = part[((size_t)(k * ns + s) * 6 + c) * n_ent + e];
+      re += v.x;
+      im += v.y;
+    }
+  G[item].x += re;
+  G[item].y += im;
+}
+
+}  // namespace
+
+template <int L>
+hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, int ns, FieldParams fp,
+                                const double2* mlbuf, const double* fbuf, double2* scratch, size_t scratch_elems,
+                                double2* G, hipStream_t st) {
+  const uint64_t L3 = (uint64_t)L * L * L, L2 = (uint64_t)L * L;
+  const size_t plane_bytes = (size_t)L * (L + 1) * sizeof(double2);  // LDS rows padded to L + 1
+  const int planes = (int)(kFxLds / plane_bytes);
+  const int npb_w = std::min(L, planes);
+  const int npb_o = 2 * std::min(L / 2, planes);
+  const int n_ent = 2 * fp.n_rf * (int)L2;
+  const int thr_w = (npb_w * L + 63) / 64 * 64;
+  const int thr_o = std::max((npb_o / 2 * L + 63) / 64 * 64, ((n_ent + kFxAcc - 1) / kFxAcc + 63) / 64 * 64);
+  const int nacc = (n_ent + thr_o - 1) / thr_o;
+  const int ngroups_w = (L + npb_w - 1) / npb_w;
+  const uint64_t per_sample = (uint64_t)fp.n_rf * ns * L3 + (uint64_t)ns * 6 * n_ent;
+  const int chunk = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, scratch_elems / per_sample));
+  const int n_samples = fp.n_outer * fp.n_inner;
+  for (int s0 = 0; s0 < n_samples; s0 += chunk) {
+    const int nk = std::min(chunk, n_samples - s0);
+    double2* what = scratch;
+    double2* part = what + (uint64_t)nk * fp.n_rf * ns * L3;
+    hipLaunchKernelGGL(field_what_kernel<L>, dim3((unsigned)((uint64_t)nk * fp.n_rf * ns * ngroups_w)), dim3(thr_w),
+                       npb_w * plane_bytes, st, lat, ml, fl, fp, s0, npb_w, mlbuf, fbuf, what);
+    hipLaunchKernelGGL(field_ocon_kernel<L>, dim3((unsigned)((uint64_t)nk * ns * 6)), dim3(thr_o),
+                       (npb_o / 2) * plane_bytes, st, lat, fl, fp, s0, npb_o, nacc, fbuf, what, part);
+    hipLaunchKernelGGL(field_gsum_kernel, dim3(blocks_for(6 * (uint64_t)n_ent, 64)), dim3(64), 0, st, fp, L, ns, nk,
+                       part, G);
+  }
+  return hipGetLastError();
+}
+
+// the fast path for lattice size L: one of the instantiated lengths, and the G
+// accumulators of one block fit in 512 threads x kFxAcc
+typedef hipError_t (*FastContract)(const LatDesc*, const MLDesc*, const FieldLat*, int, FieldParams, const double2*,
+                                   const double*, double2*, size_t, double2*, hipStream_t);
+FastContract fast_contract_for(int L, FieldParams fp) {
+  if (L > kFxMaxL || 2 * fp.n_rf * L * L > 512 * kFxAcc) return nullptr;
+  switch (L) {
+    case 2: return launch_fast_contract<2>;
+    case 4: return launch_fast_contract<4>;
+    case 6: return launch_fast_contract<6>;
+    case 8: return launch_fast_contract<8>;
+    case 10: return launch_fast_contract<10>;
+    case 12: return launch_fast_contract<12>;
+    case 16: return launch_fast_contract<16>;
+    case 18: return launch_fast_contract<18>;
+    case 20: return launch_fast_contract<20>;
+    case 24: return launch_fast_contract<24>;
+    case 30: return launch_fast_contract<30>;
+    case 32: return launch_fast_contract<32>;
+    default: return nullptr;
+  }
+}
+
+hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,
+                                 FieldParams fp, int L, const double2* mlbuf, const double2* accbuf, double* fbuf,
+                                 double2* scratch, size_t scratch_elems, double2* F, bool general, hipStream_t st) {
+  const uint64_t L3 = (uint64_t)L * L * L, L2 = (uint64_t)L * L;
+  const int ns = hfl.ns;
+  const uint64_t nt = (uint64_t)fp.n_outer * ns * L3 * fp.n_rf;
+  hipLaunchKernelGGL(field_tavg_kernel, dim3(blocks_for(nt, 256)), dim3(256), 0, st, lat, ml, fl, fp, mlbuf, fbuf);
+  hipLaunchKernelGGL(field_weights_kernel, dim3(blocks_for(nt, 256)), dim3(256), 0, st, lat, ml, fl, fp, accbuf,
+                     fbuf);
+  double2* G = (double2*)(fbuf + hfl.g);
+  const uint64_t ng = (uint64_t)fp.n_rf * 12 * L2;
+  hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(ng, 256)), dim3(256), 0, st, G, ng);
+  if (FastContract fc = general ? nullptr : fast_contract_for(L, fp)) {
+    const hipError_t e = fc(lat, ml, fl, ns, fp, mlbuf, fbuf, scratch, scratch_elems, G, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(field_final_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, G, F);
+    return hipGetLastError();
+  }
+  // general path: both transforms stored, contraction by pq tiles
+  // scratch per chunk: What [nk][n_rf][ns][L3], Ohat [nk][6][ns][L3], part [nk][n_rf][ns][12][L2]
+  const uint64_t per_sample = (uint64_t)(fp.n_rf + 6) * ns * L3 + (uint64_t)fp.n_rf * ns * 12 * L2;
+  const int chunk = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, scratch_elems / per_sample));
+  const int n_samples = fp.n_outer * fp.n_inner;
+  const size_t shm = (size_t)(L + L2) * sizeof(double2);
+  // pq tile of the accumulation: LDS holds (n_rf + 1) L pt complex values
+  int pt = 64;
+  while (pt > 1 && (size_t)(fp.n_rf + 1) * L * pt * sizeof(double2) > 60000) pt >>= 1;
+  const size_t gshm = (size_t)(fp.n_rf + 1) * L * pt * sizeof(double2);
+  const int gthreads = ((2 * fp.n_rf * pt + 63) / 64) * 64;
+  for (int s0 = 0; s0 < n_samples; s0 += chunk) {
+    const int nk = std::min(chunk, n_samples - s0);
+    double2* what = scratch;
+    double2* ohat = what + (uint64_t)nk * fp.n_rf * ns * L3;
+    double2* part = ohat + (uint64_t)nk * 6 * ns * L3;
+    hipLaunchKernelGGL(field_dft_kernel<1>, dim3((unsigned)((uint64_t)nk * fp.n_rf * ns * L)), dim3(kDftThreads), shm,
+                       st, lat, ml, fl, fp, s0, mlbuf, fbuf, what);
+    hipLaunchKernelGGL(field_dft_kernel<0>, dim3((unsigned)((uint64_t)nk * 6 * ns * L)), dim3(kDftThreads), shm, st,
+                       lat, ml, fl, fp, s0, mlbuf, fbuf, ohat);
+    hipLaunchKernelGGL(field_gacc_kernel, dim3((unsigned)((L2 + pt - 1) / pt), ns, nk), dim3(gthreads), gshm, st, fp, L,
+                       ns, pt, what, ohat, part);
+    hipLaunchKernelGGL(field_gred_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, ns, nk, part, G);
+  }
+  hipLaunchKernelGGL(field_final_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, G, F);
+  return hipGetLastError();
+}
+
+
+}  // namespace u1ml

@@ -1,0 +1,124 @@
+// measure_common.h -- device helpers shared by the measurement and field
+// contraction translation units (internal linkage in each).
+#pragma once
+
+#include "engine.h"
+
+namespace u1ml {
+namespace {
+
+constexpr int kRedBlock = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Sum v over the block (blockDim.x a multiple of 64, at most 1024); result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+    for (int w = 0; w < nw; ++w) r += sh[w];
+  }
+  __syncthreads();
+  return r;
+}
+
+template <typename R>
+__device__ __forceinline__ double ld(const R* links, uint64_t i) {
+  return (double)links[i];
+}
+
+struct Coords {
+  int t, x, y, z;
+};
+
+__device__ __forceinline__ Coords coords_natural(const LatDesc& d, uint32_t n) {
+  Coords c;
+  const uint32_t q = fdiv(n, d.div_L);
+  c.x = (int)(n - q * (uint32_t)d.L);
+  const uint32_t q2 = fdiv(q, d.div_L);
+  c.y = (int)(q - q2 * (uint32_t)d.L);
+  const uint32_t q3 = fdiv(q2, d.div_L);
+  c.z = (int)(q2 - q3 * (uint32_t)d.L);
+  c.t = (int)q3;
+  return c;
+}
+
+__device__ __forceinline__ Site as_site(Coords c) {
+  Site s;
+  s.t = c.t; s.x = c.x; s.y = c.y; s.z = c.z;
+  return s;
+}
+
+// plaquette angle theta_mu(x) + theta_nu(x+mu) - theta_mu(x+nu) - theta_nu(x)
+template <typename R>
+__device__ __forceinline__ double plaq_angle(const R* links, const LatDesc& d, Site s, int mu, int nu) {
+  const double a = ld(links, link_at(d, mu, s));
+  const double b = ld(links, link_at(d, nu, shift2(d, s, mu, 1, nu, 0)));
+  const double c = ld(links, link_at(d, mu, shift2(d, s, nu, 1, mu, 0)));
+  const double e = ld(links, link_at(d, nu, s));
+  return ((a + b) - c) - e;
+}
+
+// sum_t theta_0 over [t0, t0 + nt) at spatial site x3
+template <typename R>
+__device__ __forceinline__ double time_line(const R* links, const LatDesc& d, int x3, int t0, int nt) {
+  Site s;
+  s.x = x3 % d.L;
+  s.y = (x3 / d.L) % d.L;
+  s.z = x3 / (d.L * d.L);
+  double a = 0.0;
+  for (int t = t0; t < t0 + nt; ++t) {
+    s.t = t;
+    a += ld(links, link_at(d, 0, s));
+  }
+  return a;
+}
+
+__device__ __forceinline__ int shift_x(const LatDesc& d, int x3, int r) {
+  const int x = x3 % d.L;
+  int xr = x + r;
+  xr -= (xr >= d.L) ? d.L : 0;
+  return x3 - x + xr;
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ __forceinline__ double2 cexpi(double phi) {
+  double s, c;
+  sincos(phi, &s, &c);
+  return make_double2(c, s);
+}
+
+// average over the stored samples of T(x0, r) = conj(e(x0)) e(x0 + r) of inner slab cs
+__device__ __forceinline__ double2 inner_avg(const double2* ell, int n_samples, int ns, int L3, int cs, int x0,
+                                             int x0r) {
+  double2 a = make_double2(0.0, 0.0);
+  for (int i = 0; i < n_samples; ++i) {
+    const double2* e = ell + ((size_t)i * ns + cs) * L3;
+    const double2 u = e[x0], v = e[x0r];
+    a.x += u.x * v.x + u.y * v.y;
+    a.y += u.x * v.y - u.y * v.x;
+  }
+  const double inv = 1.0 / (double)n_samples;
+  return make_double2(a.x * inv, a.y * inv);
+}
+
+__global__ void zero_kernel(double2* __restrict__ p, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = make_double2(0.0, 0.0);
+}
+
+inline int blocks_for(uint64_t n, int b) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+}  // namespace u1ml

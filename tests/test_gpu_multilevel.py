@@ -27,18 +27,23 @@ def close_rel(a, b, rel=1e-12):
     assert np.abs(a - b).max() <= rel * scale, (np.abs(a - b).max(), scale)
 
 
-@pytest.mark.parametrize("levels,n_sub,L,T", [
-    ([4, 2], [3, 4], 4, 8),
-    ([2], [5], 4, 4),
-    ([6, 2], [2, 3], 4, 6),
-    ([4, 2, 1], [2, 2, 2], 4, 8),
+@pytest.mark.parametrize("levels,n_sub,L,T,general", [
+    ([4, 2], [3, 4], 4, 8, False),
+    ([4, 2], [3, 4], 4, 8, True),
+    ([2], [5], 4, 4, False),
+    ([2], [5], 6, 4, True),
+    ([6, 2], [2, 3], 4, 6, False),
+    ([4, 2, 1], [2, 2, 2], 4, 8, False),
 ])
-def test_multilevel_correlator_and_field_parity(oracle_mod, levels, n_sub, L, T):
+def test_multilevel_correlator_and_field_parity(oracle_mod, levels, n_sub, L, T, general):
+    # general: the field contraction by stored transforms instead of the fused one
     r_list = [1, 2, 3]
     rf = [2, 3] if len(levels) <= 2 else []
-    say(f"[gpu] multilevel parity levels={levels} n={n_sub} L={L} T={T}")
+    say(f"[gpu] multilevel parity levels={levels} n={n_sub} L={L} T={T} general={general}")
     o = oracle_mod.OracleLattice(L, T, 1.0, 5, hot=True)
     g = u1ml.init_lattice(L, T, 1.0, 5)
+    if general:
+        u1ml.set_debug(g, 2)
     for _ in range(2):
         o.sweep(1, 3)
         u1ml.sweep(g, 1, 3)
@@ -135,3 +140,23 @@ def test_batch_multilevel_with_field_matches_oracle(oracle_mod):
         np.testing.assert_array_equal(u1ml.batch_get_links(b, i), o.get_links())
         close_rel(c_g, c_o)
         close_rel(f_g, f_o)
+
+
+@pytest.mark.parametrize("L", [10, 12, 20, 32])
+def test_fused_field_contraction_matches_general(L):
+    # the fused contraction (register FFTs of radices 2, 3, 4, 5) against the
+    # general one (stored direct transforms) on the same chain
+    T = 4
+    say(f"[gpu] fused vs general field contraction L={L}")
+    res = []
+    for general in (False, True):
+        g = u1ml.init_lattice(L, T, 1.0, 21)
+        if general:
+            u1ml.set_debug(g, 2)
+        u1ml.sweep(g, 1, 2)
+        u1ml.multilevel(g, [2], [2], 1, 2, [1, 2, 3], rf_list=[2, 3])
+        _, c, f = u1ml.measure(g, observables=False, correlator=True, field_profile=True)
+        res.append((u1ml.get_links(g), c, f))
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    np.testing.assert_array_equal(res[0][1], res[1][1])
+    close_rel(res[0][2], res[1][2])
