@@ -591,12 +591,15 @@ struct Engine {
     MLState& m = ml;
     const int inner = m.n_levels - 1;
     if (child == inner) {
-      int max_items = 0, max_L = 0;
+      int max_items = 0;
+      size_t max_lds = 0;
       for (int i = 0; i < n_lats; ++i) {
+        const int nsp = parent == m.n_levels ? 1 : m.h_mls[i].ns[parent];
+        const int children = m.h_mls[i].ns[child] / nsp;
         max_items = std::max(max_items, h_lats[i].L * m.h_mls[i].nR);
-        max_L = std::max(max_L, h_lats[i].L);
+        max_lds = std::max(max_lds, (size_t)children * m.n[child] * h_lats[i].L * sizeof(double2));
       }
-      if (max_items <= ml_fold_rows_max_items()) {
+      if (max_items <= ml_fold_rows_max_items() && max_lds <= ml_fold_rows_max_lds()) {
         std::vector<int> rows;
         for (int i = 0; i < n_lats; ++i) {
           const int nsp = parent == m.n_levels ? 1 : m.h_mls[i].ns[parent];
@@ -606,7 +609,7 @@ struct Engine {
         U1_TRY(table(rows, 1, &t));
         const int per = (max_items + 1023) / 1024;  // items per thread, <= 4
         const int threads = ((max_items + per - 1) / per + 63) / 64 * 64;
-        U1_HIP(launch_ml_fold_rows(lats.as<LatDesc>(), m.mls.as<MLDesc>(), bt(t), threads, max_L, child, parent,
+        U1_HIP(launch_ml_fold_rows(lats.as<LatDesc>(), m.mls.as<MLDesc>(), bt(t), threads, max_lds, child, parent,
                                    m.n_levels, m.n[child], sample_base, m.rvals.as<int>(), m.mlbuf.as<double2>(),
                                    m.accbuf.as<double2>(), stream));
         return U1ML_OK;

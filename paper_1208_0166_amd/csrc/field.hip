@@ -425,23 +425,34 @@ __global__ __launch_bounds__(512) void field_ocon_kernel(const LatDesc* __restri
   }
 }
 
-// G[((f * 2 + plane) * 6 + c) * L2 + pq] += sum over k, s of part (fixed order)
+// G[((f * 2 + plane) * 6 + c) * L2 + pq] += sum over (k, s) of part, in four
+// interleaved partial sums (fixed order) so that four loads are in flight
 __global__ void field_gsum_kernel(FieldParams fp, int L, int ns, int nk, const double2* __restrict__ part,
                                   double2* __restrict__ G) {
   const int L2 = L * L, n_ent = 2 * fp.n_rf * L2;
   const int item = blockIdx.x * blockDim.x + threadIdx.x;
   if (item >= 6 * n_ent) return;
   const int pq = item % L2, c = (item / L2) % 6, fpl = item / (6 * L2);
-  const int e = fpl * L2 + pq;
-  double re = 0.0, im = 0.0;
-  for (int k = 0; k < nk; ++k)
-    for (int s = 0; s < ns; ++s) {
-      const double2 v = part[((size_t)(k * ns + s) * 6 + c) * n_ent + e];
-      re += v.x;
-      im += v.y;
+  const double2* src = part + (size_t)c * n_ent + fpl * L2 + pq;
+  const size_t stride = (size_t)6 * n_ent;  // one (k, s)
+  const int n = nk * ns;
+  double re[4] = {0.0, 0.0, 0.0, 0.0}, im[4] = {0.0, 0.0, 0.0, 0.0};
+  int j = 0;
+  for (; j + 4 <= n; j += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double2 v = src[(size_t)(j + u) * stride];
+      re[u] += v.x;
+      im[u] += v.y;
     }
-  G[item].x += re;
-  G[item].y += im;
+  }
+  for (int u = 0; j < n; ++j, ++u) {
+    const double2 v = src[(size_t)j * stride];
+    re[u] += v.x;
+    im[u] += v.y;
+  }
+  G[item].x += (re[0] + re[1]) + (re[2] + re[3]);
+  G[item].y += (im[0] + im[1]) + (im[2] + im[3]);
 }
 
 }  // namespace

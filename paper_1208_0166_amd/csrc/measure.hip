@@ -190,75 +190,60 @@ __global__ void ml_fold_kernel(const LatDesc* __restrict__ lats, const MLDesc* _
 }
 
 // The same fold for innermost children, one block per (parent slab S, x-row
-// (y, z)): the rows of the stored samples are staged in LDS, so every time
-// line is read from memory once instead of once per separation.  Threads own
-// up to kFoldItems items (x0, k) with x0 fastest; the sample and child order of
-// the sums is that of ml_fold_kernel, so both give the same bits.
+// (y, z)): the rows of all stored samples of all children of S are staged in
+// LDS at once (children * n_child * L values), so every time line is read from
+// memory once instead of once per separation.  Threads own up to kFoldItems
+// items (x0, k) with k fastest (so the accumulator updates are contiguous);
+// the sample and child order of the sums is that of ml_fold_kernel, so both
+// give the same bits.
 constexpr int kFoldItems = 4;
-constexpr int kFoldStage = 8;  // samples per LDS round
+constexpr size_t kFoldLds = 49152;  // bytes of staged rows per block
 __global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls,
                                     const int2* __restrict__ blocks, int child_level, int parent_level, int n_levels,
                                     int n_child, int sample_base, const int* __restrict__ rvals,
                                     const double2* __restrict__ mlbuf, double2* __restrict__ accbuf) {
-  extern __shared__ double2 rowbuf[];  // [kFoldStage][L]
+  extern __shared__ double2 rowbuf[];  // [children][n_child][L]
   const int2 bk = blocks[blockIdx.x];
   const LatDesc d = lats[bk.x];
-  const MLDesc m = mls[bk.x];
+  // fields read through the pointer: a local copy indexed by a run-time level
+  // would live in scratch memory
+  const MLDesc* mp = mls + bk.x;
   const int L = d.L, L2 = L * L;
-  const int ns_child = m.ns[child_level];
-  const int ns_parent = parent_level == n_levels ? 1 : m.ns[parent_level];
+  const int ns_child = mp->ns[child_level];
+  const int ns_parent = parent_level == n_levels ? 1 : mp->ns[parent_level];
+  const int nR = mp->nR, r_off = mp->r_off;
+  const uint64_t ell = mp->ell, acc_parent = mp->acc[parent_level];
   const int children = ns_child / ns_parent;
   const int S = bk.y / L2, row = bk.y - S * L2;
-  const int nitems = L * m.nR;
-  int x0[kFoldItems], xr[kFoldItems];
-  double2 prod[kFoldItems];
-#pragma unroll
-  for (int j = 0; j < kFoldItems; ++j) {
-    const int item = (int)threadIdx.x + j * (int)blockDim.x;
-    const int k = item / L;
-    x0[j] = item - k * L;
-    int x = item < nitems ? x0[j] + rvals[m.r_off + k] : x0[j];
-    x -= x >= L ? L : 0;
-    xr[j] = x;
-    prod[j] = make_double2(1.0, 0.0);
+  const int nitems = L * nR;
+  const int per_child = n_child * L;
+  for (int e = threadIdx.x; e < children * per_child; e += blockDim.x) {
+    const int c = e / per_child, i = (e / L) % n_child, x = e % L;
+    rowbuf[e] = mlbuf[ell + ((size_t)(sample_base + i) * ns_child + S * children + c) * d.L3 + (size_t)row * L + x];
   }
+  __syncthreads();
   const double inv = 1.0 / (double)n_child;
-  for (int c = 0; c < children; ++c) {
-    const int cs = S * children + c;
-    double2 avg[kFoldItems];
-#pragma unroll
-    for (int j = 0; j < kFoldItems; ++j) avg[j] = make_double2(0.0, 0.0);
-    for (int i0 = 0; i0 < n_child; i0 += kFoldStage) {
-      const int nst = min(kFoldStage, n_child - i0);
-      __syncthreads();
-      for (int e = threadIdx.x; e < nst * L; e += blockDim.x) {
-        const int i = e / L, x = e - i * L;
-        rowbuf[e] = mlbuf[m.ell + ((size_t)(sample_base + i0 + i) * ns_child + cs) * d.L3 + (size_t)row * L + x];
-      }
-      __syncthreads();
-      for (int i = 0; i < nst; ++i) {
-        const double2* e = rowbuf + i * L;
-#pragma unroll
-        for (int j = 0; j < kFoldItems; ++j) {
-          if ((int)threadIdx.x + j * (int)blockDim.x < nitems) {
-            const double2 u = e[x0[j]], v = e[xr[j]];
-            avg[j].x += u.x * v.x + u.y * v.y;
-            avg[j].y += u.x * v.y - u.y * v.x;
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < kFoldItems; ++j) prod[j] = cmul(prod[j], make_double2(avg[j].x * inv, avg[j].y * inv));
-  }
 #pragma unroll
   for (int j = 0; j < kFoldItems; ++j) {
     const int item = (int)threadIdx.x + j * (int)blockDim.x;
     if (item < nitems) {
-      const int k = item / L;
-      double2* pp = accbuf + m.acc[parent_level] + ((size_t)S * d.L3 + (size_t)row * L + x0[j]) * m.nR + k;
-      pp->x += prod[j].x;
-      pp->y += prod[j].y;
+      const int x0 = item / nR, k = item - x0 * nR;
+      int xr = x0 + rvals[r_off + k];
+      xr -= xr >= L ? L : 0;
+      double2 prod = make_double2(1.0, 0.0);
+      for (int c = 0; c < children; ++c) {
+        const double2* e = rowbuf + c * per_child;
+        double2 avg = make_double2(0.0, 0.0);
+        for (int i = 0; i < n_child; ++i) {
+          const double2 u = e[i * L + x0], v = e[i * L + xr];
+          avg.x += u.x * v.x + u.y * v.y;
+          avg.y += u.x * v.y - u.y * v.x;
+        }
+        prod = cmul(prod, make_double2(avg.x * inv, avg.y * inv));
+      }
+      double2* pp = accbuf + acc_parent + ((size_t)S * d.L3 + (size_t)row * L + x0) * nR + k;
+      pp->x += prod.x;
+      pp->y += prod.y;
     }
   }
 }
@@ -396,17 +381,17 @@ hipError_t launch_ml_fold(const LatDesc* lats, const MLDesc* mls, BlockTable bt,
   return hipGetLastError();
 }
 
-hipError_t launch_ml_fold_rows(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int threads, int max_L,
+hipError_t launch_ml_fold_rows(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int threads, size_t lds,
                                int child_level, int parent_level, int n_levels, int n_child, int sample_base,
                                const int* rvals, const double2* mlbuf, double2* accbuf, hipStream_t st) {
   if (bt.n_blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(ml_fold_rows_kernel, dim3(bt.n_blocks), dim3(threads),
-                     (size_t)kFoldStage * max_L * sizeof(double2), st, lats, mls, bt.dev, child_level, parent_level,
-                     n_levels, n_child, sample_base, rvals, mlbuf, accbuf);
+  hipLaunchKernelGGL(ml_fold_rows_kernel, dim3(bt.n_blocks), dim3(threads), lds, st, lats, mls, bt.dev, child_level,
+                     parent_level, n_levels, n_child, sample_base, rvals, mlbuf, accbuf);
   return hipGetLastError();
 }
 
 int ml_fold_rows_max_items() { return kFoldItems * 1024; }
+size_t ml_fold_rows_max_lds() { return kFoldLds; }
 
 hipError_t launch_ml_zero(double2* accbuf, uint64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
