@@ -1,0 +1,103 @@
+"""The full-size workloads: 64 batched instances of uneven size and coupling
+(sweeps + one-level multilevel in captured cycles), and the 48^4 lattice with
+the two-level multilevel and the field profiles."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1208_0166_amd import u1ml
+from tests.test_oracle_multilevel import field_ops, plain_corr, polyakov_lines
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def uneven_instances(n=64, seed=7):
+    rng = np.random.default_rng(seed)
+    Ls = [int(v) for v in rng.choice([8, 12, 16, 20, 24], n)]
+    betas = [float(v) for v in rng.choice([0.9, 1.0, 1.1], n)]
+    return Ls, betas, [1000 + i for i in range(n)]
+
+
+def test_64_uneven_instances_fp32_cycles():
+    Ls, betas, seeds = uneven_instances()
+    say(f"[gpu] 64 instances, L counts {dict(zip(*np.unique(Ls, return_counts=True)))}")
+    b = u1ml.batch_create(Ls, Ls, betas, seeds, start=u1ml.COLD, precision=u1ml.FP32)
+    for _ in range(20):
+        u1ml.batch_sweep(b, 1, 3)
+    # one update per level: the multilevel correlator is the plain one of the final links
+    u1ml.batch_cycle(b, 2, 1, 3, 2, 1, use_graph=True)
+    for i in range(64):
+        th = u1ml.batch_get_links(b, i)
+        _, c, _ = u1ml.batch_measure(b, i)
+        ref = [plain_corr(th, r) for r in range(1, Ls[i] // 2 + 1)]
+        np.testing.assert_allclose(c, ref, rtol=0, atol=1e-12)
+    # the configured cycle (th 2, 10 updates), captured and replayed
+    for _ in range(3):
+        u1ml.batch_cycle(b, 2, 1, 3, 2, 10, use_graph=True)
+    for i in range(64):
+        obs, c, _ = u1ml.batch_measure(b, i)
+        assert np.all(np.isfinite(c)) and np.all(np.abs(c) <= 1.0)
+        assert 0.3 < obs["plaquette"] < 0.8
+
+
+def test_64_uneven_instances_fp64_match_oracle(oracle_mod):
+    Ls, betas, seeds = uneven_instances()
+    say("[gpu] 64 instances FP64 vs oracle (sampled)")
+    b = u1ml.batch_create(Ls, Ls, betas, seeds, start=u1ml.HOT, precision=u1ml.FP64)
+    u1ml.batch_sweep(b, 1, 3)
+    u1ml.batch_cycle(b, 1, 1, 3, 2, 10, use_graph=True)
+    picks = [Ls.index(8), Ls.index(16), Ls.index(24)]
+    for i in picks:
+        o = oracle_mod.OracleLattice(Ls[i], Ls[i], betas[i], seeds[i], hot=True)
+        o.sweep(1, 3)
+        o.sweep(1, 3)
+        c_o, _, _ = o.multilevel([2], [10], 1, 3, list(range(1, Ls[i] // 2 + 1)))
+        obs, c_g, _ = u1ml.batch_measure(b, i)
+        np.testing.assert_array_equal(u1ml.batch_get_links(b, i), o.get_links())
+        np.testing.assert_allclose(c_g, c_o, rtol=1e-12, atol=1e-15)
+        assert abs(obs["plaquette"] - o.plaquette()) < 1e-13
+
+
+def field_points(th, beta, r, points):
+    """Plain Eq. (9) definition at one update per level for the listed
+    (plane, dy, dz): (1/V) sum_{x0,t} P*(x0) P(x0 + r) O_c(x0 + m + dy + dz, t)."""
+    T, L = th.shape[0], th.shape[1]
+    P = polyakov_lines(th)
+    w = np.conj(P) * np.roll(P, -r, axis=2)
+    Osum = field_ops(th, beta).sum(axis=1)  # [c][z][y][x]
+    out = []
+    for plane, dy, dz in points:
+        m = (r - 1) // 2 if plane == 0 else r // 2
+        sh = np.roll(np.roll(np.roll(Osum, -m, axis=3), -dy, axis=2), -dz, axis=1)
+        out.append((w[None] * sh).sum(axis=(1, 2, 3)) / (T * L ** 3))
+    return np.array(out)  # [point][c]
+
+
+def test_large_48_identity_fp32():
+    L = T = 48
+    say("[gpu] 48^4 FP32 two-level identity with field")
+    g = u1ml.init_lattice(L, T, 1.0, 5, precision=u1ml.FP32, start=u1ml.COLD)
+    for _ in range(3):
+        u1ml.sweep(g, 1, 3)
+    rl = list(range(1, 25))
+    u1ml.multilevel(g, [4, 2], [1, 1], 1, 3, rl, rf_list=[2, 4, 6])
+    obs, c, f = u1ml.measure(g, correlator=True, field_profile=True)
+    th = u1ml.get_links(g)
+    np.testing.assert_allclose(c, [plain_corr(th, r) for r in rl], rtol=0, atol=1e-12)
+    rng = np.random.default_rng(11)
+    points = [(int(p), int(a), int(b)) for p, a, b in zip(rng.integers(0, 2, 12), rng.integers(0, L, 12),
+                                                       rng.integers(0, L, 12))]
+    points += [(0, 0, 0), (1, 0, 0)]
+    scale = np.abs(f).max()
+    for k, r in enumerate([2, 4, 6]):
+        ref = field_points(th, 1.0, r, points)
+        got = np.array([f[k, p, :, dy, dz] for p, dy, dz in points])
+        assert np.abs(got - ref).max() <= 2e-5 * scale, (r, np.abs(got - ref).max(), scale)
+    assert math.isfinite(obs["plaquette"])
