@@ -1,6 +1,7 @@
 """Benchmark: multilevel compact U(1) on 24^4 lattices at beta = 1 on one MI355X.
 
-One step advances R independent 24^4 chains (one batch, R = 8 by default) by
+One step advances R independent 24^4 chains (R = 24 by default, in 3 batches
+of 8 on 3 streams whose launches overlap) by
 one pass of the whole method each:
   * 100 compound sweeps (1 Metropolis hit + 3 overrelaxation passes per link)
     between measured configurations (Sec. 2.1);
@@ -42,7 +43,8 @@ N_BETWEEN = 100
 N_THERM = 200
 HBM_PEAK_GBS = 8000.0
 WORDS_PER_UPDATE = 9  # 8 link reads + 1 write per update in a class pass
-DEFAULT_REPLICAS = 8
+DEFAULT_REPLICAS = 24
+DEFAULT_STREAMS = 3
 CPU_N_SUB = [2, 5]  # reduced multilevel sample for the oracle
 COPY_ELEMS = 1 << 27  # calibration copy: 512 MiB read, 512 MiB written
 
@@ -109,54 +111,106 @@ def cpu_baseline(seconds: float):
                       f"in {el_ml:.1f} s"}
 
 
-def run_chain(u1ml, torch, stream, prec, R, rf, steps, warmup, with_events=True):
-    """Build R independent 24^4 chains (one batch when R > 1), thermalise, and
-    time `steps` steps.  Returns a dict of timings and the last results."""
-    if R == 1:
-        lat = u1ml.init_lattice(L, T, BETA, 3, start=u1ml.COLD, precision=prec)
-        sw = lambda: u1ml.sweep(lat, 1, 3)  # noqa: E731
-    else:
-        lat = u1ml.batch_create([L] * R, [T] * R, [BETA] * R, [3 + i for i in range(R)], start=u1ml.COLD,
-                                precision=prec, stream=stream.cuda_stream)
-        sw = lambda: u1ml.batch_sweep(lat, 1, 3)  # noqa: E731
+def run_chain(u1ml, torch, prec, R, rf, steps, warmup, n_streams=1):
+    """Build R independent 24^4 chains split into n_streams groups (one batch,
+    or one lattice, per group, each on a stream of its own), thermalise, and
+    time `steps` steps; the groups' launches overlap on the GPU.  Returns a
+    dict of timings and the last results of group 0."""
+    sizes = [R // n_streams + (1 if g < R % n_streams else 0) for g in range(n_streams)]
+    sizes = [n for n in sizes if n > 0]
+    groups = []
+    first = 0
+    for n in sizes:
+        st = torch.cuda.Stream()
+        seeds = [3 + first + i for i in range(n)]
+        if n == 1:
+            lat = u1ml.init_lattice(L, T, BETA, seeds[0], start=u1ml.COLD, precision=prec, stream=st.cuda_stream)
+            sw = (lambda lt: lambda: u1ml.sweep(lt, 1, 3))(lat)
+        else:
+            lat = u1ml.batch_create([L] * n, [T] * n, [BETA] * n, seeds, start=u1ml.COLD, precision=prec,
+                                    stream=st.cuda_stream)
+            sw = (lambda lt: lambda: u1ml.batch_sweep(lt, 1, 3))(lat)
+        groups.append({"lat": lat, "sw": sw, "st": st, "n": n})
+        first += n
     for _ in range(N_THERM):
-        sw()
+        for gr in groups:
+            gr["sw"]()
     torch.cuda.synchronize()
 
-    def step(ev=None):
+    def launch(gr, ev=None):
         if ev:
-            ev[0].record(stream)
+            ev[0].record(gr["st"])
         for _ in range(N_BETWEEN):
-            sw()
+            gr["sw"]()
         if ev:
-            ev[1].record(stream)
-        if R == 1:
-            u1ml.multilevel(lat, LEVELS, N_SUB, 1, 3, R_LIST, rf_list=rf)
+            ev[1].record(gr["st"])
+        if gr["n"] == 1:
+            u1ml.multilevel(gr["lat"], LEVELS, N_SUB, 1, 3, R_LIST, rf_list=rf)
         else:
-            u1ml.batch_multilevel(lat, LEVELS, N_SUB, 1, 3, R_LIST, rf_list=rf)
+            u1ml.batch_multilevel(gr["lat"], LEVELS, N_SUB, 1, 3, R_LIST, rf_list=rf)
         if ev:
-            ev[2].record(stream)
-        if R == 1:
-            return u1ml.measure(lat, correlator=True, field_profile=bool(rf))
-        res = [u1ml.batch_measure(lat, i, correlator=True, field_profile=bool(rf)) for i in range(R)]
-        return res[0]
+            ev[2].record(gr["st"])
+
+    def results(gr):
+        if gr["n"] == 1:
+            return [u1ml.measure(gr["lat"], correlator=True, field_profile=bool(rf))]
+        return [u1ml.batch_measure(gr["lat"], i, correlator=True, field_profile=bool(rf)) for i in range(gr["n"])]
+
+    def step(evs=None):
+        for g, gr in enumerate(groups):  # all groups queued before any result is read
+            launch(gr, evs[g] if evs else None)
+        res = [results(gr) for gr in groups]
+        return res[0][0]
 
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in groups] for _ in range(steps)]
     t0 = time.perf_counter()
     for k in range(steps):
-        obs, corr, field = step(evs[k] if with_events else None)
+        obs, corr, field = step(evs[k])
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    ms_sweeps = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
-    ms_ml = sum(e[1].elapsed_time(e[2]) for e in evs) / steps
+    ms_sweeps = sum(e[0][0].elapsed_time(e[0][1]) for e in evs) / steps  # group 0
+    ms_ml = sum(e[0][1].elapsed_time(e[0][2]) for e in evs) / steps
     up_sw, up_ml = chain_updates_per_step()
-    return {"lat": lat, "el": el, "ms_step": 1e3 * el / steps, "ms_sweeps": ms_sweeps, "ms_ml": ms_ml,
-            "updates_per_s": R * (up_sw + up_ml) * steps / el, "sweep_updates_per_s": R * up_sw / (ms_sweeps * 1e-3),
-            "ml_updates_per_s": R * up_ml / (ms_ml * 1e-3), "samples_per_s": R * samples_per_step() / (ms_ml * 1e-3),
+    n0 = groups[0]["n"]
+    return {"groups": groups, "el": el, "ms_step": 1e3 * el / steps, "ms_sweeps": ms_sweeps, "ms_ml": ms_ml,
+            "updates_per_s": R * (up_sw + up_ml) * steps / el,
+            "samples_per_s": R * samples_per_step() * steps / el,
+            "group0_sweep_updates_per_s": n0 * up_sw / (ms_sweeps * 1e-3),
+            "group0_ml_updates_per_s": n0 * up_ml / (ms_ml * 1e-3),
+            "group0_ml_samples_per_s": n0 * samples_per_step() / (ms_ml * 1e-3),
             "obs": obs, "corr": corr}
+
+
+def roofline_leg(u1ml, torch, prec, R, steps):
+    """The dominant kernel alone: N_BETWEEN compound sweeps of one R-lattice
+    batch on one stream, timed with HIP events around each step's sweeps."""
+    st = torch.cuda.Stream()
+    if R == 1:
+        lat = u1ml.init_lattice(L, T, BETA, 3, start=u1ml.COLD, precision=prec, stream=st.cuda_stream)
+        sw = lambda: u1ml.sweep(lat, 1, 3)  # noqa: E731
+    else:
+        lat = u1ml.batch_create([L] * R, [T] * R, [BETA] * R, [3 + i for i in range(R)], start=u1ml.COLD,
+                                precision=prec, stream=st.cuda_stream)
+        sw = lambda: u1ml.batch_sweep(lat, 1, 3)  # noqa: E731
+    for _ in range(20):
+        sw()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(st)
+        for _ in range(N_BETWEEN):
+            sw()
+        b.record(st)
+    torch.cuda.synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+    if R > 1:
+        iso = u1ml.batch_profile_sweeps(lat, 5, 1, 3)
+    else:
+        iso = u1ml.profile_sweeps(lat, 5, 1, 3)
+    return ms, iso
 
 
 def counters_run(args):
@@ -199,14 +253,16 @@ def main():
                     help="skip the single-chain FP32 and FP64 comparison legs")
     ap.add_argument("--replicas", type=int, default=DEFAULT_REPLICAS,
                     help="independent 24^4 chains advanced by the same launches (one batch)")
+    ap.add_argument("--streams", type=int, default=DEFAULT_STREAMS,
+                    help="the replicas are split into this many batches, each on a stream of its own")
     ap.add_argument("--counters", action="store_true", help="short run for hardware-counter passes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); there is no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
-    if args.replicas < 1:
-        print("--replicas must be >= 1", file=sys.stderr)
+    if args.replicas < 1 or not 1 <= args.streams <= args.replicas:
+        print("need --replicas >= 1 and 1 <= --streams <= --replicas", file=sys.stderr)
         sys.exit(2)
     if args.counters:
         counters_run(args)
@@ -216,34 +272,29 @@ def main():
     from paper_1208_0166_amd import u1ml
 
     torch.cuda.set_device(0)
-    # a dedicated stream: the library queues its kernels on torch's current
-    # stream, and the events below are recorded on the same one
-    stream = torch.cuda.Stream()
-    torch.cuda.set_stream(stream)
+    # every lattice or batch gets a stream of its own (passed explicitly); torch's
+    # own work goes to a dedicated stream as well
+    torch.cuda.set_stream(torch.cuda.Stream())
     prec = u1ml.FP32 if args.precision == "fp32" else u1ml.FP64
     rf = [] if args.no_field else RF_LIST
     R = args.replicas
 
-    main_run = run_chain(u1ml, torch, stream, prec, R, rf, args.steps, args.warmup)
-    lat = main_run["lat"]
+    main_run = run_chain(u1ml, torch, prec, R, rf, args.steps, args.warmup, args.streams)
 
-    # dominant kernel: the class pass (Metropolis or OR, 9 words per update).
-    # Its average duration is taken over the timed region: the sweep phase of
-    # every step is N_BETWEEN compound sweeps of 4 x 8 class passes plus one
-    # pass-id bump, so (sweep phase time) / (class passes) bounds the duration
-    # from above.  The isolated per-launch figure is recorded beside it.
+    # dominant kernel: the class pass (Metropolis or OR, 9 words per update),
+    # timed alone on one stream: N_BETWEEN compound sweeps of 4 x 8 class passes
+    # plus one pass-id bump per step, so (sweep time) / (class passes) bounds
+    # the average dispatch time from above.  Per-launch event timings are
+    # recorded beside it.
     passes_per_step = N_BETWEEN * 4 * 8
-    avg_us = 1e3 * main_run["ms_sweeps"] / passes_per_step
+    ms_rf, (iso_metro, iso_or) = roofline_leg(u1ml, torch, prec, R, args.steps)
+    avg_us = 1e3 * ms_rf / passes_per_step
     bw = 4 if prec == u1ml.FP32 else 8
     updates_per_launch = R * L ** 3 * T // 2
     bytes_per_launch = updates_per_launch * WORDS_PER_UPDATE * bw
     achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
     pname = "Fast32" if prec == u1ml.FP32 else "Det64"
     kname = f"class_pass_batch_kernel<{pname}, mu, kind>" if R > 1 else f"class_pass_kernel<{pname}, mu, kind>"
-    if R > 1:
-        iso_metro, iso_or = u1ml.batch_profile_sweeps(lat, 5, 1, 3)
-    else:
-        iso_metro, iso_or = u1ml.profile_sweeps(lat, 5, 1, 3)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(kname, R, bw),
                 "kernel": kname, "avg_us": avg_us, "launches_timed": passes_per_step * args.steps,
@@ -264,29 +315,30 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == u1ml.FP32 else "f64",
         "data": "synthetic (cold start, 200 thermalisation sweeps, seeds 3..)",
-        "config": {"workload": f"{R} independent 24^4 beta=1 chains, each step per chain: 100 sweeps "
-                               "(1 Metropolis + 3 OR) + two-level multilevel {4,2} x {10,20}, r=1..12, "
-                               "E/B mid-plane profiles at r=2,4,6",
+        "config": {"workload": f"{R} independent 24^4 beta=1 chains on {args.streams} stream(s), each step "
+                               "per chain: 100 sweeps (1 Metropolis + 3 OR) + two-level multilevel {4,2} x {10,20}, "
+                               "r=1..12, E/B mid-plane profiles at r=2,4,6",
                    "lattice": [L, L, L, T], "beta": BETA, "levels": LEVELS, "n_sub": N_SUB,
-                   "r": [1, 12], "field_r": rf, "accumulate": "f64", "replicas": R},
+                   "r": [1, 12], "field_r": rf, "accumulate": "f64", "replicas": R, "streams": args.streams},
         "samples_per_s": main_run["samples_per_s"],
         "samples_per_step": samples_per_step() * R,
         "chain_updates_per_step": R * sum(chain_updates_per_step()),
-        "phase_ms": {"sweeps": main_run["ms_sweeps"], "multilevel": main_run["ms_ml"],
-                     "measure_and_readback": main_run["ms_step"] - main_run["ms_sweeps"] - main_run["ms_ml"]},
-        "sweep_updates_per_s": main_run["sweep_updates_per_s"],
-        "multilevel_chain_updates_per_s": main_run["ml_updates_per_s"],
+        "streams": args.streams,
+        "group0_phase_ms": {"sweeps": main_run["ms_sweeps"], "multilevel": main_run["ms_ml"]},
+        "group0_sweep_updates_per_s": main_run["group0_sweep_updates_per_s"],
+        "group0_multilevel_chain_updates_per_s": main_run["group0_ml_updates_per_s"],
+        "group0_multilevel_phase_samples_per_s": main_run["group0_ml_samples_per_s"],
         "plaquette": obs["plaquette"],
         "poly_abs": obs["poly_abs"],
         "C_r1": [corr[0].real, corr[0].imag],
         "roofline": roofline,
     }
-    del lat, main_run
+    del main_run
     if not args.no_compare:
         # one chain (no batching), FP32 path and plain FP64 path
         legs = {}
         for name, pr in (("single_chain_fp32", u1ml.FP32), ("single_chain_fp64", u1ml.FP64)):
-            r = run_chain(u1ml, torch, stream, pr, 1, rf, 1, 1)
+            r = run_chain(u1ml, torch, pr, 1, rf, 1, 1)
             legs[name] = {"updates_per_s": r["updates_per_s"], "samples_per_s": r["samples_per_s"],
                           "ms_per_step": r["ms_step"], "phase_ms": {"sweeps": r["ms_sweeps"], "multilevel": r["ms_ml"]}}
             del r

@@ -279,7 +279,7 @@ __global__ void field_final_kernel(FieldParams fp, int L, const double2* __restr
 // stored W transforms right away.
 // ---------------------------------------------------------------------------
 constexpr int kFxMaxL = 32;
-constexpr int kFxAcc = 8;         // G accumulators (complex) per thread
+constexpr int kFxEnt = 4;         // G entries (r_f, p, q) per thread, both planes each
 constexpr size_t kFxLds = 64512;  // LDS per block (bytes)
 
 // in-place FFT of the N values v[i * stride] (LDS)
@@ -346,9 +346,12 @@ __global__ __launch_bounds__(256) void field_what_kernel(const LatDesc* __restri
 
 // part[((k * ns + s) * 6 + c) * 2 n_rf L^2 + g], g = (f * 2 + plane) * L^2 + p * L + q:
 //   sum_x What[k][f][s][x - m](p, q) * Ohat_c[k][s][x](p, q),  m_0 = (r - 1) / 2, m_1 = r / 2.
-// Block: (k, s, c) over all x, in groups of npb planes (npb even, pairs of
-// planes as one complex plane).  Thread = row (pair, y) in pass 1, column
-// (pair, q) in pass 2, and owner of the G entries g = tid + j * blockDim.x.
+// Block: (k, s, component triple: E or B) over all x, in groups of npb planes
+// (npb even: pairs of planes as one complex plane) of each of the three
+// components.  Thread = row (c, pair, y) in pass 1, column (c, pair, q) in
+// pass 2, and owner of the G entries (r_f, p, q) of all three components and
+// both planes, e = tid + j * blockDim.x: every W value read serves six sums.
+constexpr int kFxComp = 3;  // field components per block
 template <int L>
 __global__ __launch_bounds__(512) void field_ocon_kernel(const LatDesc* __restrict__ lat,
                                                          const FieldLat* __restrict__ flp, FieldParams fp,
@@ -356,72 +359,104 @@ __global__ __launch_bounds__(512) void field_ocon_kernel(const LatDesc* __restri
                                                          const double* __restrict__ fbuf,
                                                          const double2* __restrict__ what,
                                                          double2* __restrict__ part) {
-  extern __shared__ double2 zb[];  // [pairs][L][L + 1]
-  constexpr int L1 = L + 1, L2 = L * L;
+  extern __shared__ double2 zb[];  // [kFxComp][pairs][L][L + 1]
+  constexpr int L1 = L + 1, L2 = L * L, CG = 6 / kFxComp;
   const LatDesc d = *lat;
   const FieldLat fl = *flp;
   const int ns = fl.ns;
-  const int lb = (int)xcd_block(blockIdx.x, gridDim.x);  // the six c of one (k, s) share an L2
-  const int c = lb % 6, s = (lb / 6) % ns, k = lb / (6 * ns);
-  const int sample = sample0 + k;
-  const double* o = fbuf + fl.oall + (((size_t)sample * 6 + c) * ns + s) * d.L3;
-  const double2* wk = what + ((size_t)k * fp.n_rf * ns + s) * L * L2;  // + (f * ns * L + x) * L2
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x);  // both triples of one (k, s) share an L2
+  const int cg = lb % CG, s = (lb / CG) % ns, k = lb / (CG * ns);
+  const int c0 = cg * kFxComp, sample = sample0 + k;
+  const double* o0 = fbuf + fl.oall + (((size_t)sample * 6 + c0) * ns + s) * d.L3;  // + c * ns * L3
+  const double2* wk = what + ((size_t)k * fp.n_rf * ns + s) * L * L2;                // + (f * ns * L + x) * L2
   const int tid = threadIdx.x;
-  const int n_ent = 2 * fp.n_rf * L2;
-  double2 g[kFxAcc];
+  const int n_fe = fp.n_rf * L2;  // entries (f, pq)
+  // With m_0 = (r - 1) / 2 and m_1 = r / 2 (= m_0 or m_0 + 1), plane 1 at x uses
+  // the W plane that plane 0 used at x - 1 (even r) or the same one (odd r), so
+  // every W value is read once: wp carries W(x - 1 - m_0) from plane to plane.
+  double2 g0[kFxEnt][kFxComp], g1[kFxEnt][kFxComp], wp[kFxEnt];
 #pragma unroll
-  for (int j = 0; j < kFxAcc; ++j) g[j] = make_double2(0.0, 0.0);
+  for (int j = 0; j < kFxEnt; ++j) {
+#pragma unroll
+    for (int c = 0; c < kFxComp; ++c) g0[j][c] = g1[j][c] = make_double2(0.0, 0.0);
+    wp[j] = make_double2(0.0, 0.0);
+    const int e = tid + j * (int)blockDim.x;
+    if (j < nacc && e < n_fe) {
+      const int f = e / L2, pq = e - f * L2, m0 = (fp.rf[f] - 1) / 2;
+      wp[j] = wk[(size_t)f * ns * L * L2 + (size_t)(L - 1 - m0) * L2 + pq];  // W(-1 - m_0)
+    }
+  }
   for (int x0 = 0; x0 < L; x0 += npb) {
     const int np = min(npb, L - x0) >> 1;  // pairs in this group
+    const int cp = kFxComp * np;           // (component, pair) planes in LDS
     __syncthreads();  // the previous group's contraction is done with zb
-    // Z(y, z) = O(xa, y, z) + i O(xa + 1, y, z), xa = x0 + 2 pr, pairs fastest
-    for (int i = tid; i < np * L2; i += blockDim.x) {
-      const int pr = i % np, yz = i / np, y = yz % L, z = yz / L;
-      zb[(pr * L + y) * L1 + z] = *(const double2*)(o + (z * L + y) * L + x0 + 2 * pr);
+    // Z_c(y, z) = O_c(xa, y, z) + i O_c(xa + 1, y, z), xa = x0 + 2 pr; pairs fastest
+    for (int i = tid; i < cp * L2; i += blockDim.x) {
+      const int pr = i % np, c = (i / np) % kFxComp, yz = i / cp, y = yz % L, z = yz / L;
+      zb[((c * np + pr) * L + y) * L1 + z] =
+          *(const double2*)(o0 + (size_t)c * ns * d.L3 + (z * L + y) * L + x0 + 2 * pr);
     }
     __syncthreads();
-    const bool active = tid < np * L;
-    const int pr = tid / L, t = tid - pr * L;
-    if (active) fft_line<L, -1>(zb + (pr * L + t) * L1, 1);  // rows, along z
+    const bool active = tid < cp * L;
+    const int pl = tid / L, t = tid - pl * L;  // plane pl = c * np + pr
+    if (active) fft_line<L, -1>(zb + (pl * L + t) * L1, 1);  // rows, along z
     __syncthreads();
-    if (active) fft_line<L, -1>(zb + pr * L * L1 + t, L1);  // columns, along y
+    // columns, along y, in place: only this thread touches the column
+    if (active) fft_line<L, -1>(zb + pl * L * L1 + t, L1);
     __syncthreads();
     // contraction over the planes of this group
 #pragma unroll
-    for (int j = 0; j < kFxAcc; ++j) {
+    for (int j = 0; j < kFxEnt; ++j) {
       const int e = tid + j * (int)blockDim.x;
-      if (j < nacc && e < n_ent) {
-        const int fpl = e / L2, pq = e - fpl * L2;
-        const int f = fpl >> 1, r = fp.rf[f];
-        const int mm = (fpl & 1) ? r / 2 : (r - 1) / 2;
+      if (j < nacc && e < n_fe) {
+        const int f = e / L2, pq = e - f * L2, r = fp.rf[f];
+        const int m0 = (r - 1) / 2;
+        const bool even = (r & 1) == 0;
         const int p = pq / L, qq = pq - p * L;
         const int ia = p * L1 + qq;                                          // Z(k)
         const int ib = (p == 0 ? 0 : L - p) * L1 + (qq == 0 ? 0 : L - qq);  // Z(-k)
         const double2* wf = wk + (size_t)f * ns * L * L2 + pq;
-        int xw = x0 - mm;  // W plane paired with O plane x: x - m
+        int xw = x0 - m0;  // W plane of plane 0 at x = x0
         xw += xw < 0 ? L : 0;
-        double gx = g[j].x, gy = g[j].y;
+        double2 w1 = wp[j];
         for (int pp = 0; pp < np; ++pp) {
-          const double2 a = zb[pp * L * L1 + ia], bm = zb[pp * L * L1 + ib];
-          const double2 sum = make_double2(0.5 * (a.x + bm.x), 0.5 * (a.y - bm.y));   // Ohat of x
-          const double2 dif = make_double2(0.5 * (a.y + bm.y), -0.5 * (a.x - bm.x));  // Ohat of x + 1
-          int xw1 = xw + 1;
-          xw1 -= xw1 >= L ? L : 0;
-          const double2 wa = wf[(size_t)xw * L2], wb = wf[(size_t)xw1 * L2];
-          gx += (wa.x * sum.x - wa.y * sum.y) + (wb.x * dif.x - wb.y * dif.y);
-          gy += (wa.x * sum.y + wa.y * sum.x) + (wb.x * dif.y + wb.y * dif.x);
-          xw = xw1 + 1;
+          const double2 wa = wf[(size_t)xw * L2];
+          xw += 1;
           xw -= xw >= L ? L : 0;
+          const double2 wb = wf[(size_t)xw * L2];
+          xw += 1;
+          xw -= xw >= L ? L : 0;
+          const double2 ha = even ? w1 : wa, hb = even ? wa : wb;
+#pragma unroll
+          for (int c = 0; c < kFxComp; ++c) {
+            const double2* z = zb + (c * np + pp) * L * L1;
+            const double2 za = z[ia], zm = z[ib];
+            const double2 oa = make_double2(0.5 * (za.x + zm.x), 0.5 * (za.y - zm.y));   // Ohat_c of x
+            const double2 ob = make_double2(0.5 * (za.y + zm.y), -0.5 * (za.x - zm.x));  // Ohat_c of x + 1
+            g0[j][c].x += (wa.x * oa.x - wa.y * oa.y) + (wb.x * ob.x - wb.y * ob.y);
+            g0[j][c].y += (wa.x * oa.y + wa.y * oa.x) + (wb.x * ob.y + wb.y * ob.x);
+            g1[j][c].x += (ha.x * oa.x - ha.y * oa.y) + (hb.x * ob.x - hb.y * ob.y);
+            g1[j][c].y += (ha.x * oa.y + ha.y * oa.x) + (hb.x * ob.y + hb.y * ob.x);
+          }
+          w1 = wb;
         }
-        g[j] = make_double2(gx, gy);
+        wp[j] = w1;
       }
     }
   }
-  double2* out = part + ((size_t)(k * ns + s) * 6 + c) * n_ent;
+  const int n_ent = 2 * n_fe;
 #pragma unroll
-  for (int j = 0; j < kFxAcc; ++j) {
+  for (int j = 0; j < kFxEnt; ++j) {
     const int e = tid + j * (int)blockDim.x;
-    if (j < nacc && e < n_ent) out[e] = g[j];
+    if (j < nacc && e < n_fe) {
+      const int f = e / L2, pq = e - f * L2;
+#pragma unroll
+      for (int c = 0; c < kFxComp; ++c) {
+        double2* out = part + ((size_t)(k * ns + s) * 6 + c0 + c) * n_ent;
+        out[(2 * f) * L2 + pq] = g0[j][c];
+        out[(2 * f + 1) * L2 + pq] = g1[j][c];
+      }
+    }
   }
 }
 
@@ -465,11 +500,13 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
   const size_t plane_bytes = (size_t)L * (L + 1) * sizeof(double2);  // LDS rows padded to L + 1
   const int planes = (int)(kFxLds / plane_bytes);
   const int npb_w = std::min(L, planes);
-  const int npb_o = 2 * std::min(L / 2, planes);
+  const int npb_o = 2 * std::min(L / 2, planes / kFxComp);  // x planes per group of each component
   const int n_ent = 2 * fp.n_rf * (int)L2;
   const int thr_w = (npb_w * L + 63) / 64 * 64;
-  const int thr_o = std::max((npb_o / 2 * L + 63) / 64 * 64, ((n_ent + kFxAcc - 1) / kFxAcc + 63) / 64 * 64);
-  const int nacc = (n_ent + thr_o - 1) / thr_o;
+  const int n_fe = fp.n_rf * (int)L2;
+  const int thr_o =
+      std::max((kFxComp * npb_o / 2 * L + 63) / 64 * 64, ((n_fe + kFxEnt - 1) / kFxEnt + 63) / 64 * 64);
+  const int nacc = (n_fe + thr_o - 1) / thr_o;
   const int ngroups_w = (L + npb_w - 1) / npb_w;
   const uint64_t per_sample = (uint64_t)fp.n_rf * ns * L3 + (uint64_t)ns * 6 * n_ent;
   const int chunk = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, scratch_elems / per_sample));
@@ -480,8 +517,8 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
     double2* part = what + (uint64_t)nk * fp.n_rf * ns * L3;
     hipLaunchKernelGGL(field_what_kernel<L>, dim3((unsigned)((uint64_t)nk * fp.n_rf * ns * ngroups_w)), dim3(thr_w),
                        npb_w * plane_bytes, st, lat, ml, fl, fp, s0, npb_w, mlbuf, fbuf, what);
-    hipLaunchKernelGGL(field_ocon_kernel<L>, dim3((unsigned)((uint64_t)nk * ns * 6)), dim3(thr_o),
-                       (npb_o / 2) * plane_bytes, st, lat, fl, fp, s0, npb_o, nacc, fbuf, what, part);
+    hipLaunchKernelGGL(field_ocon_kernel<L>, dim3((unsigned)((uint64_t)nk * ns * (6 / kFxComp))), dim3(thr_o),
+                       kFxComp * (npb_o / 2) * plane_bytes, st, lat, fl, fp, s0, npb_o, nacc, fbuf, what, part);
     hipLaunchKernelGGL(field_gsum_kernel, dim3(blocks_for(6 * (uint64_t)n_ent, 64)), dim3(64), 0, st, fp, L, ns, nk,
                        part, G);
   }
@@ -489,11 +526,12 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
 }
 
 // the fast path for lattice size L: one of the instantiated lengths, and the G
-// accumulators of one block fit in 512 threads x kFxAcc
+// entries (r_f, p, q) of one block fit in 512 threads x kFxEnt
 typedef hipError_t (*FastContract)(const LatDesc*, const MLDesc*, const FieldLat*, int, FieldParams, const double2*,
                                    const double*, double2*, size_t, double2*, hipStream_t);
 FastContract fast_contract_for(int L, FieldParams fp) {
-  if (L > kFxMaxL || 2 * fp.n_rf * L * L > 512 * kFxAcc) return nullptr;
+  if (L > kFxMaxL || fp.n_rf * L * L > 512 * kFxEnt) return nullptr;
+  if (kFxLds / ((size_t)L * (L + 1) * sizeof(double2)) < (size_t)kFxComp) return nullptr;  // one pair per component
   switch (L) {
     case 2: return launch_fast_contract<2>;
     case 4: return launch_fast_contract<4>;

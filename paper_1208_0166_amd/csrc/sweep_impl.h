@@ -137,11 +137,12 @@ __device__ __forceinline__ void update_link(typename P::real* __restrict__ base,
   const uint32_t V2 = (uint32_t)d.V2;
   const int q = parity ^ 1;
   const int hh = (int)h;
-  // 32-bit byte offsets from the lattice base (scalar base + vector offset loads)
+  // scalar base of each (direction, parity) array + a 32-bit vector byte
+  // offset per neighbour half-index (shared by the arrays that use it)
   const char* cbase = (const char*)base;
   auto ld = [&](int dir, int par, int hi) -> R {
-    const uint32_t byte = ((uint32_t)(2 * dir + par) * V2 + (uint32_t)hi) * (uint32_t)sizeof(R);
-    return *(const R*)(cbase + byte);
+    const char* arr = cbase + (size_t)((uint32_t)(2 * dir + par) * V2) * sizeof(R);
+    return *(const R*)(arr + (uint32_t)hi * (uint32_t)sizeof(R));
   };
   R sr = (R)0, si = (R)0;
 #pragma unroll
