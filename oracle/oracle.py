@@ -67,7 +67,9 @@ def _load():
         "or_field_op": (C.c_double, [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
         "or_field_means": (None, [P, dp]),
         "or_multilevel": (C.c_int, [P, C.c_int, ip, ip, C.c_int, C.c_int, C.c_int, ip, dp,
-                                    C.c_int, ip, dp, u8p, C.c_long, C.POINTER(C.c_long)]),
+                                    C.c_int, ip, dp, u8p, C.c_long, C.POINTER(C.c_long), C.c_int]),
+        "or_bessel_ratio": (C.c_double, [C.c_double]),
+        "or_multihit_mean": (None, [P, C.c_long, dp]),
         "or_philox4x64_10": (None, [u64p, u64p, u64p]),
         "or_sincos": (None, [C.c_double, dp, dp]),
         "or_atan2": (C.c_double, [C.c_double, C.c_double]),
@@ -111,6 +113,11 @@ def sincos(x: float):
     s, c = C.c_double(), C.c_double()
     lib.or_sincos(float(x), C.byref(s), C.byref(c))
     return s.value, c.value
+
+
+def bessel_ratio(x: float) -> float:
+    """I_1(x) / I_0(x)."""
+    return _load().or_bessel_ratio(float(x))
 
 
 def atan2(y: float, x: float) -> float:
@@ -162,6 +169,12 @@ class OracleLattice:
         self._lib.or_staple(self._h, int(n), int(mu), C.byref(re), C.byref(im))
         return re.value, im.value
 
+    def multihit_mean(self, n: int) -> complex:
+        """Conditional mean of exp(i theta_0) at canonical site n given all other links."""
+        out = np.zeros(2)
+        self._lib.or_multihit_mean(self._h, int(n), _dp(out))
+        return complex(out[0], out[1])
+
     def local_delta(self, n: int, mu: int, v: float) -> float:
         return self._lib.or_local_delta(self._h, int(n), int(mu), float(v))
 
@@ -201,7 +214,7 @@ class OracleLattice:
         return out
 
     def multilevel(self, slab_sizes, n_sub, n_metro=1, n_or=3, r_list=(1,), rf_list=(),
-                   log_cap=0):
+                   log_cap=0, multihit=False):
         """Returns (C_ML[r] complex, field[rf][plane][comp][dy][dz] complex, log)."""
         th = np.ascontiguousarray(slab_sizes, dtype=np.int32)
         ns = np.ascontiguousarray(n_sub, dtype=np.int32)
@@ -223,7 +236,7 @@ class OracleLattice:
         used = C.c_long(0)
         rc = self._lib.or_multilevel(self._h, len(th), _ip(th), _ip(ns), n_metro, n_or, len(r), _ip(r),
                                      _dp(corr), n_rf, _ip(rf), _dp(field), _u8p(log) if log_cap else None,
-                                     int(log_cap), C.byref(used))
+                                     int(log_cap), C.byref(used), int(bool(multihit)))
         if rc != 0:
             raise ValueError("invalid multilevel arguments")
         f = field.reshape(max(n_rf, 1), 2, 6, L, L, 2)

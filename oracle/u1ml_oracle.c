@@ -528,8 +528,55 @@ static cplx cmul(cplx a, cplx b)
     return r;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Analytical multihit (Sec. 2.2, the variance reduction the paper applies   */
+/* to the temporal links of the potential).  Given all other links, a link   */
+/* with staple S = |S| e^{i alpha} has the conditional density               */
+/* exp(beta |S| cos(theta + alpha)) / (2 pi I_0(beta |S|)), whose mean of    */
+/* e^{i theta} is e^{-i alpha} I_1(beta |S|) / I_0(beta |S|).                */
+/* ------------------------------------------------------------------------ */
+
+/* I_1(x) / I_0(x) for x >= 0 from the power series
+ *   I_n(x) = sum_k (x/2)^(2k+n) / (k! (k+n)!):
+ * with a_k = (x^2/4)^k / (k!)^2, I_0 = sum_k a_k and I_1 = (x/2) sum_k a_k/(k+1).
+ * Every term is positive, so both sums are accurate to a few ulp.  Above
+ * x = 600 the terms would overflow and the large-x expansion
+ * 1 - 1/(2x) - 1/(8x^2) - 1/(8x^3) - 25/(128x^4) is used (error < 1e-12). */
+double or_bessel_ratio(double x)
+{
+    if (x <= 0.0) return 0.0;
+    if (x > 600.0) {
+        double u = 1.0 / x;
+        return 1.0 - u / 2.0 - u * u / 8.0 - u * u * u / 8.0 - 25.0 * u * u * u * u / 128.0;
+    }
+    double q = x * x / 4.0, a = 1.0, s0 = 1.0, s1 = 1.0;
+    for (int k = 1; k < 2000; ++k) {
+        a *= q / ((double)k * (double)k);
+        s0 += a;
+        s1 += a / (double)(k + 1);
+        if (a < 1e-18 * s0) break;
+    }
+    return 0.5 * x * s1 / s0;
+}
+
+/* multihit mean of the temporal link at canonical site n: out = (re, im) */
+void or_multihit_mean(const or_lat *g, long n, double *out)
+{
+    double sr, si;
+    or_staple(g, n, 0, &sr, &si);
+    double a = hypot(sr, si);
+    if (a == 0.0) {
+        out[0] = out[1] = 0.0;
+        return;
+    }
+    double q = or_bessel_ratio(g->beta * a) / a;
+    out[0] = q * sr;
+    out[1] = -q * si;
+}
+
 typedef struct ml_ctx {
     or_lat *g;
+    int multihit;       /* correlator lines at r >= 2 from multihit means */
     int n_levels;
     const int *th;      /* slab thickness per level, outer to inner */
     const int *n_sub;   /* updates per level */
@@ -553,6 +600,20 @@ static cplx two_link(const or_lat *g, long x0, int t, int r)
     double b = TH(g, site_index(g, t, x + r, y, z), 0);
     cplx ua = {cos(a), -sin(a)};
     cplx ub = {cos(b), sin(b)};
+    return cmul(ua, ub);
+}
+
+/* the same product from the multihit means of both temporal links; used for
+ * the correlator at r >= 2, where the two links share no plaquette */
+static cplx two_link_mh(const or_lat *g, long x0, int t, int r)
+{
+    int L = g->L;
+    int x = (int)(x0 % L), y = (int)((x0 / L) % L), z = (int)(x0 / ((long)L * L));
+    double a[2], b[2];
+    or_multihit_mean(g, site_index(g, t, x, y, z), a);
+    or_multihit_mean(g, site_index(g, t, x + r, y, z), b);
+    cplx ua = {a[0], -a[1]};
+    cplx ub = {b[0], b[1]};
     return cmul(ua, ub);
 }
 
@@ -614,8 +675,9 @@ static void ml_level(ml_ctx *c, int lev, cplx *avg, cplx *favg)
                 for (int k = 0; k < c->n_r; ++k) {
                     cplx p = {1.0, 0.0};
                     if (inner) {
+                        int r = c->r_list[k];
                         for (int t = s * th; t < (s + 1) * th; ++t)
-                            p = cmul(p, two_link(g, x0, t, c->r_list[k]));
+                            p = cmul(p, c->multihit && r >= 2 ? two_link_mh(g, x0, t, r) : two_link(g, x0, t, r));
                     } else {
                         for (int ch = 0; ch < nchild; ++ch)
                             p = cmul(p, cavg[((size_t)(s * nchild + ch) * c->L3 + x0) * c->n_r + k]);
@@ -688,11 +750,15 @@ static void ml_level(ml_ctx *c, int lev, cplx *avg, cplx *favg)
  *   field_out[((((f*2 + plane)*6 + comp)*L + dy)*L + dz)*2 + {0,1}]
  *       = <P*(0) P(r) O_comp(m, dy, dz)> of Eq. (9): (1/V) sum_x0 sum over the
  *         slab s holding the insertion of B_s(x0) prod_{s' != s} A_s'(x0).
- * Every r_f in rf_list must also appear in r_list.  Returns 0, or -1 on a bad
- * argument (slab sizes must divide T and each other). */
+ * Every r_f in rf_list must also appear in r_list.  multihit != 0 replaces,
+ * for every r >= 2, the temporal links of both lines by their multihit means
+ * in the correlator products (and so in the slab averages that multiply a
+ * field insertion elsewhere); r = 1 and the slab holding a field insertion
+ * use the links themselves.  Returns 0, or -1 on a bad argument (slab sizes
+ * must divide T and each other). */
 int or_multilevel(or_lat *g, int n_levels, const int *th, const int *n_sub, int n_metro, int n_or,
                   int n_r, const int *r_list, double *corr_out, int n_rf, const int *rf_list,
-                  double *field_out, unsigned char *log, long log_cap, long *log_used)
+                  double *field_out, unsigned char *log, long log_cap, long *log_used, int multihit)
 {
     if (n_levels < 1 || n_r < 1) return -1;
     for (int l = 0; l < n_levels; ++l) {
@@ -706,7 +772,7 @@ int or_multilevel(or_lat *g, int n_levels, const int *th, const int *n_sub, int 
     }
     ml_ctx c;
     memset(&c, 0, sizeof c);
-    c.g = g; c.n_levels = n_levels; c.th = th; c.n_sub = n_sub;
+    c.g = g; c.n_levels = n_levels; c.th = th; c.n_sub = n_sub; c.multihit = multihit;
     c.n_metro = n_metro; c.n_or = n_or;
     c.n_r = n_r; c.r_list = r_list; c.n_rf = n_rf; c.rf_list = rf_list;
     c.L3 = (long)g->L * g->L * g->L;
