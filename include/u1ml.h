@@ -130,6 +130,17 @@ int u1ml_sweep(u1ml_lattice *lat, int n_metro, int n_or);
 int u1ml_multilevel(u1ml_lattice *lat, int n_levels, const int *slab_sizes, const int *n_sub, int n_metro,
                     int n_or, int n_r, const int *r_list, int n_rf, const int *rf_list);
 
+/* Estimator options of the multilevel runs that follow (default 0).
+ * U1ML_MULTIHIT (Sec. 2.2, the variance reduction the paper applies to the
+ * potential): for every separation r >= 2 the temporal links of both Polyakov
+ * lines are replaced by their multihit means conj(S)/|S| I_1(beta|S|)/I_0(beta|S|)
+ * (S: the link's staple), in the correlator and in the slab averages that
+ * multiply a field insertion made elsewhere; r = 1 (whose two lines share
+ * plaquettes) and the inner slab holding a field insertion use the links
+ * themselves.  Doubles the stored time lines.  EINVAL on unknown bits. */
+#define U1ML_MULTIHIT 1u
+int u1ml_set_estimator(u1ml_lattice *lat, unsigned flags);
+
 /* Measure the current links and return the latest multilevel results.
  *   obs (may be NULL): plain observables of the current links.
  *   correlator (may be NULL): [n_r][2] (Re, Im) of the last multilevel C(r);
@@ -203,6 +214,8 @@ int u1ml_batch_multilevel(u1ml_batch *b, int n_levels, const int *slab_sizes, co
  * whole cycle is captured once into a HIP graph and replayed on later calls
  * with the same arguments.  Asynchronous. */
 int u1ml_batch_cycle(u1ml_batch *b, int n_sweeps, int n_metro, int n_or, int th, int n_sub, int use_graph);
+/* u1ml_set_estimator for every lattice of the batch. */
+int u1ml_batch_set_estimator(u1ml_batch *b, unsigned flags);
 /* Results of lattice i as in u1ml_measure: observables of its current links,
  * correlator [n_r][2] of the last cycle or batch multilevel (r = 1..T_i/2
  * after a cycle), field_profile as in u1ml_measure.  NULL pointers skip.

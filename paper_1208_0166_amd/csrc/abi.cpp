@@ -143,6 +143,7 @@ struct Engine {
   size_t log_cap = 0, log_used = 0;
   bool debug = false;
   bool field_general = false;  // u1ml_set_debug flags & 2
+  unsigned estimator = 0;      // u1ml_set_estimator flags
   // measurement scratch
   DevBuf partial, rows, poly, poly_off, row_begin, red_out, rvals_tmp;
   MLState ml;
@@ -523,6 +524,12 @@ struct Engine {
       for (int l = 0; l < n_levels; ++l) md.ns[l] = d.T / th[l];
       md.ell = ell;
       ell += (uint64_t)n_samples_kept * md.ns[inner] * d.L3;
+      md.multihit = (estimator & U1ML_MULTIHIT) ? 1 : 0;
+      md.ell_mh = md.ell;
+      if (md.multihit) {
+        md.ell_mh = ell;
+        ell += (uint64_t)n_samples_kept * md.ns[inner] * d.L3;
+      }
       for (int l = 0; l < n_levels; ++l) {
         md.acc[l] = acc;
         if (l < inner) acc += (uint64_t)md.ns[l] * d.L3 * md.nR;
@@ -597,7 +604,8 @@ struct Engine {
         const int nsp = parent == m.n_levels ? 1 : m.h_mls[i].ns[parent];
         const int children = m.h_mls[i].ns[child] / nsp;
         max_items = std::max(max_items, h_lats[i].L * m.h_mls[i].nR);
-        max_lds = std::max(max_lds, (size_t)children * m.n[child] * h_lats[i].L * sizeof(double2));
+        max_lds = std::max(max_lds, (size_t)(m.h_mls[i].multihit ? 2 : 1) * children * m.n[child] * h_lats[i].L *
+                                        sizeof(double2));
       }
       if (max_items <= ml_fold_rows_max_items() && max_lds <= ml_fold_rows_max_lds()) {
         std::vector<int> rows;
@@ -685,7 +693,7 @@ struct Engine {
   // n_sweeps_before unfrozen compound sweeps, then a multilevel run
   int multilevel(int n_levels, const int* th, const int* n_sub, int n_metro, int n_or,
                  const std::vector<std::vector<int>>& rl, const std::vector<int>& rf, int n_sweeps_before) {
-    std::vector<long long> key{1, n_levels, n_metro, n_or, n_sweeps_before, (long long)rf.size()};
+    std::vector<long long> key{1, n_levels, n_metro, n_or, n_sweeps_before, (long long)rf.size(), (long long)estimator};
     for (int l = 0; l < n_levels; ++l) {
       key.push_back(th[l]);
       key.push_back(n_sub[l]);
@@ -942,6 +950,28 @@ int u1ml_set_pass_id(u1ml_lattice* lat, uint64_t pass_id) {
   U1_TRY(lat->e.set_device());
   lat->e.h_pass_ids[0] = pass_id;
   return lat->e.upload_pass_ids();
+}
+
+static int set_estimator(Engine& e, unsigned flags) {
+  if (flags & ~U1ML_MULTIHIT) return fail(U1ML_EINVAL, "unknown estimator flags");
+  U1_TRY(e.set_device());
+  if (e.estimator != flags) {
+    U1_HIP(hipStreamSynchronize(e.stream));
+    e.estimator = flags;
+    e.ml.key.clear();  // the next multilevel run lays out its workspace again
+    e.drop_graphs();
+  }
+  return U1ML_OK;
+}
+
+int u1ml_set_estimator(u1ml_lattice* lat, unsigned flags) {
+  if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
+  return set_estimator(lat->e, flags);
+}
+
+int u1ml_batch_set_estimator(u1ml_batch* b, unsigned flags) {
+  if (!b) return fail(U1ML_EINVAL, "batch is NULL");
+  return set_estimator(b->e, flags);
 }
 
 int u1ml_set_debug(u1ml_lattice* lat, unsigned flags, size_t capacity) {

@@ -49,10 +49,12 @@ hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t st);
 constexpr int kMaxLevels = 3;
 struct MLDesc {
   uint64_t ell;                  // double2: [samples][ns_inner][L3] exp(i * slab time-line angle sum)
+  uint64_t ell_mh;               // double2: the same layout, products of multihit means (multihit only)
   uint64_t acc[kMaxLevels + 1];  // double2: level l < inner: [ns_l][L3][nR]; index n_levels = top [L3][nR]
   int ns[kMaxLevels];            // slabs per level
   int nR;                        // separations
   int r_off;                     // r values at rvals[r_off ...]
+  int multihit;                  // correlator lines at r >= 2 from ell_mh
 };
 
 // plaquette sum and field sums: partial[blk][7] then final[7] per lattice

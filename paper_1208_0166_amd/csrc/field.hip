@@ -31,7 +31,10 @@ __global__ void field_tavg_kernel(const LatDesc* __restrict__ lat, const MLDesc*
   const int x0 = (item / fp.n_rf) % d.L3;
   const int s = (item / (fp.n_rf * d.L3)) % fl.ns;
   const int m = item / (fp.n_rf * d.L3 * fl.ns);
-  const double2* ell = mlbuf + ml.ell + (size_t)m * fp.n_inner * fl.ns * d.L3;
+  // the slabs without the insertion take the correlator's lines: multihit
+  // means for r >= 2 when enabled
+  const uint64_t base = ml.multihit && fp.rf[f] >= 2 ? ml.ell_mh : ml.ell;
+  const double2* ell = mlbuf + base + (size_t)m * fp.n_inner * fl.ns * d.L3;
   ((double2*)(fbuf + fl.tavg))[item] = inner_avg(ell, fp.n_inner, fl.ns, d.L3, s, x0, shift_x(d, x0, fp.rf[f]));
 }
 

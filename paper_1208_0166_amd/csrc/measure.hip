@@ -101,6 +101,55 @@ __global__ void poly_corr_kernel(const LatDesc* __restrict__ lats, const int2* _
 // ---------------------------------------------------------------------------
 // multilevel
 // ---------------------------------------------------------------------------
+// I_1(x) / I_0(x), x >= 0: power series of both functions with the common
+// terms a_k = (x^2/4)^k / (k!)^2 (I_0 = sum a_k, I_1 = x/2 sum a_k / (k + 1));
+// beyond x = 600 the large-x expansion to order x^-4
+__device__ __forceinline__ double bessel_i1_over_i0(double x) {
+  if (x <= 0.0) return 0.0;
+  if (x > 600.0) {
+    const double u = 1.0 / x;
+    return 1.0 - u * (0.5 + u * (0.125 + u * (0.125 + u * (25.0 / 128.0))));
+  }
+  const double q = 0.25 * x * x;
+  double a = 1.0, s0 = 1.0, s1 = 1.0;
+  for (int k = 1; k < 2000; ++k) {
+    a *= q / ((double)k * (double)k);
+    s0 += a;
+    s1 += a / (double)(k + 1);
+    if (a < 1e-18 * s0) break;
+  }
+  return 0.5 * x * s1 / s0;
+}
+
+// multihit mean of the temporal link at s: with the staple S of Eq. (3) the
+// link's conditional density is exp(beta |S| cos(theta + arg S)) / norm, and
+// the mean of exp(i theta) is conj(S) / |S| * I_1(beta |S|) / I_0(beta |S|)
+template <typename R>
+__device__ __forceinline__ double2 multihit_mean(const R* links, const LatDesc& d, Site s) {
+  double sr = 0.0, si = 0.0;
+  for (int nu = 1; nu < 4; ++nu) {
+    // forward plaquette: theta_nu(x + 0) - theta_0(x + nu) - theta_nu(x)
+    const double ap = (ld(links, link_at(d, nu, shift2(d, s, 0, 1, nu, 0))) -
+                       ld(links, link_at(d, 0, shift2(d, s, nu, 1, 0, 0)))) -
+                      ld(links, link_at(d, nu, s));
+    // backward plaquette: -(theta_0(x - nu) + theta_nu(x + 0 - nu) - theta_nu(x - nu))
+    const Site b = shift2(d, s, nu, -1, 0, 0);
+    const double am = -((ld(links, link_at(d, 0, b)) + ld(links, link_at(d, nu, shift2(d, s, 0, 1, nu, -1)))) -
+                        ld(links, link_at(d, nu, b)));
+    double sn, cs;
+    sincos(ap, &sn, &cs);
+    sr += cs;
+    si += sn;
+    sincos(am, &sn, &cs);
+    sr += cs;
+    si += sn;
+  }
+  const double a = hypot(sr, si);
+  if (a == 0.0) return make_double2(0.0, 0.0);
+  const double q = bessel_i1_over_i0(d.beta * a) / a;
+  return make_double2(q * sr, -q * si);
+}
+
 template <typename R>
 __global__ void ml_lines_kernel(const R* __restrict__ links, const LatDesc* __restrict__ lats,
                                 const MLDesc* __restrict__ mls, const int2* __restrict__ blocks, int inner_th,
@@ -111,8 +160,22 @@ __global__ void ml_lines_kernel(const R* __restrict__ links, const LatDesc* __re
   const int item = bk.y + (int)threadIdx.x;
   if (item >= ns * d.L3) return;
   const int s = item / d.L3, x3 = item - s * d.L3;
+  const MLDesc* m = mls + bk.x;
+  const size_t at = ((size_t)sample * ns + s) * d.L3 + x3;
   // exp(i l), l = sum of theta_0 over the slab's times: the slab product of U_0
-  mlbuf[mls[bk.x].ell + ((size_t)sample * ns + s) * d.L3 + x3] = cexpi(time_line(links, d, x3, s * inner_th, inner_th));
+  mlbuf[m->ell + at] = cexpi(time_line(links, d, x3, s * inner_th, inner_th));
+  if (m->multihit) {
+    Site st;
+    st.x = x3 % d.L;
+    st.y = (x3 / d.L) % d.L;
+    st.z = x3 / (d.L * d.L);
+    double2 p = make_double2(1.0, 0.0);
+    for (int t = s * inner_th; t < (s + 1) * inner_th; ++t) {
+      st.t = t;
+      p = cmul(p, multihit_mean(links, d, st));
+    }
+    mlbuf[m->ell_mh + at] = p;
+  }
 }
 
 // acc_parent[S][x0][k] += prod over the children of S of the child averages.
@@ -152,15 +215,20 @@ __global__ void ml_fold_kernel(const LatDesc* __restrict__ lats, const MLDesc* _
     for (int j = 0; j < kFoldR; ++j) avg[j] = make_double2(0.0, 0.0);
     if (child_is_inner) {
       const double2* ell = mlbuf + m.ell + ((size_t)sample_base * ns_child + cs) * d.L3;
+      const double2* emh = mlbuf + m.ell_mh + ((size_t)sample_base * ns_child + cs) * d.L3;
       for (int i = 0; i < n_child; ++i) {
         const double2* e = ell + (size_t)i * ns_child * d.L3;
+        const double2* eh = emh + (size_t)i * ns_child * d.L3;
         const double2 u = e[x0];
+        const double2 uh = m.multihit ? eh[x0] : u;
 #pragma unroll
         for (int j = 0; j < kFoldR; ++j) {
           if (j < kn) {
-            const double2 v = e[xr[j]];
-            avg[j].x += u.x * v.x + u.y * v.y;
-            avg[j].y += u.x * v.y - u.y * v.x;
+            // multihit lines for r >= 2 (the two lines share no plaquette)
+            const bool mh = m.multihit && rvals[m.r_off + k0 + j] >= 2;
+            const double2 a = mh ? uh : u, v = mh ? eh[xr[j]] : e[xr[j]];
+            avg[j].x += a.x * v.x + a.y * v.y;
+            avg[j].y += a.x * v.y - a.y * v.x;
           }
         }
       }
@@ -191,11 +259,11 @@ __global__ void ml_fold_kernel(const LatDesc* __restrict__ lats, const MLDesc* _
 
 // The same fold for innermost children, one block per (parent slab S, x-row
 // (y, z)): the rows of all stored samples of all children of S are staged in
-// LDS at once (children * n_child * L values), so every time line is read from
-// memory once instead of once per separation.  Threads own up to kFoldItems
-// items (x0, k) with k fastest (so the accumulator updates are contiguous);
-// the sample and child order of the sums is that of ml_fold_kernel, so both
-// give the same bits.
+// LDS at once (children * n_child * L values, twice with multihit), so every
+// time line is read from memory once instead of once per separation.  Threads
+// own up to kFoldItems items (x0, k) with k fastest (so the accumulator
+// updates are contiguous); the sample and child order of the sums is that of
+// ml_fold_kernel, so both give the same bits.
 constexpr int kFoldItems = 4;
 constexpr size_t kFoldLds = 49152;  // bytes of staged rows per block
 __global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls,
@@ -211,15 +279,19 @@ __global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDe
   const int L = d.L, L2 = L * L;
   const int ns_child = mp->ns[child_level];
   const int ns_parent = parent_level == n_levels ? 1 : mp->ns[parent_level];
-  const int nR = mp->nR, r_off = mp->r_off;
-  const uint64_t ell = mp->ell, acc_parent = mp->acc[parent_level];
+  const int nR = mp->nR, r_off = mp->r_off, multihit = mp->multihit;
+  const uint64_t ell = mp->ell, ell_mh = mp->ell_mh, acc_parent = mp->acc[parent_level];
   const int children = ns_child / ns_parent;
   const int S = bk.y / L2, row = bk.y - S * L2;
   const int nitems = L * nR;
   const int per_child = n_child * L;
-  for (int e = threadIdx.x; e < children * per_child; e += blockDim.x) {
-    const int c = e / per_child, i = (e / L) % n_child, x = e % L;
-    rowbuf[e] = mlbuf[ell + ((size_t)(sample_base + i) * ns_child + S * children + c) * d.L3 + (size_t)row * L + x];
+  // rows of the plain lines, then (multihit) rows of the multihit lines
+  const int staged = children * per_child;
+  for (int e = threadIdx.x; e < (multihit ? 2 : 1) * staged; e += blockDim.x) {
+    const int h = e / staged, ee = e - h * staged;
+    const int c = ee / per_child, i = (ee / L) % n_child, x = ee % L;
+    rowbuf[e] = mlbuf[(h ? ell_mh : ell) + ((size_t)(sample_base + i) * ns_child + S * children + c) * d.L3 +
+                      (size_t)row * L + x];
   }
   __syncthreads();
   const double inv = 1.0 / (double)n_child;
@@ -228,11 +300,14 @@ __global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDe
     const int item = (int)threadIdx.x + j * (int)blockDim.x;
     if (item < nitems) {
       const int x0 = item / nR, k = item - x0 * nR;
-      int xr = x0 + rvals[r_off + k];
+      const int r = rvals[r_off + k];
+      int xr = x0 + r;
       xr -= xr >= L ? L : 0;
+      // multihit lines for r >= 2 (the two lines share no plaquette)
+      const double2* rows = rowbuf + (multihit && r >= 2 ? staged : 0);
       double2 prod = make_double2(1.0, 0.0);
       for (int c = 0; c < children; ++c) {
-        const double2* e = rowbuf + c * per_child;
+        const double2* e = rows + c * per_child;
         double2 avg = make_double2(0.0, 0.0);
         for (int i = 0; i < n_child; ++i) {
           const double2 u = e[i * L + x0], v = e[i * L + xr];

@@ -78,6 +78,8 @@ def load_library(path: str = LIB_PATH):
         "u1ml_get_pass_id": (I, [P, C.POINTER(U64)]),
         "u1ml_set_pass_id": (I, [P, U64]),
         "u1ml_set_debug": (I, [P, C.c_uint, SZ]),
+        "u1ml_set_estimator": (I, [P, C.c_uint]),
+        "u1ml_batch_set_estimator": (I, [P, C.c_uint]),
         "u1ml_get_accept_log": (I, [P, C.POINTER(C.c_uint8), SZ, C.POINTER(SZ)]),
         "u1ml_save": (I, [P, C.c_char_p]),
         "u1ml_load": (I, [P, C.c_char_p]),
@@ -253,6 +255,14 @@ def set_pass_id(lat: Lattice, pass_id: int):
     _check(load_library().u1ml_set_pass_id(lat.handle, int(pass_id)))
 
 
+MULTIHIT = 1
+
+
+def set_estimator(lat: Lattice, multihit: bool = False):
+    """Estimator options of the following multilevel runs (u1ml_set_estimator)."""
+    _check(load_library().u1ml_set_estimator(lat.handle, MULTIHIT if multihit else 0))
+
+
 def set_debug(lat: Lattice, flags: int, capacity: int = 0):
     _check(load_library().u1ml_set_debug(lat.handle, flags, capacity))
 
@@ -360,6 +370,10 @@ def batch_multilevel(b: Batch, slab_sizes, n_sub, n_metro: int = 1, n_or: int = 
     _check(load_library().u1ml_batch_multilevel(b.handle, len(th), thp, nsp, n_metro, n_or, len(r), rp,
                                                 len(rf_list), rfp if len(rf_list) else None))
     b._n_r, b._n_rf = [len(r)] * len(b.L), len(rf_list)
+
+
+def batch_set_estimator(b: Batch, multihit: bool = False):
+    _check(load_library().u1ml_batch_set_estimator(b.handle, MULTIHIT if multihit else 0))
 
 
 def batch_measure(b: Batch, i: int, correlator: bool = True, field_profile: bool = False):

@@ -160,3 +160,47 @@ def test_fused_field_contraction_matches_general(L):
     np.testing.assert_array_equal(res[0][0], res[1][0])
     np.testing.assert_array_equal(res[0][1], res[1][1])
     close_rel(res[0][2], res[1][2])
+
+
+@pytest.mark.parametrize("levels,n_sub,L,T,general", [
+    ([4, 2], [2, 3], 4, 8, False),
+    ([4, 2], [2, 3], 4, 8, True),
+    ([2], [4], 6, 4, False),
+    ([4, 2, 1], [2, 2, 2], 4, 8, False),
+])
+def test_multihit_parity(oracle_mod, levels, n_sub, L, T, general):
+    # analytical multihit for r >= 2 (correlator and the averages multiplying a
+    # field insertion), against the oracle's independent implementation
+    r_list = [1, 2, 3]
+    rf = [2, 3] if len(levels) <= 2 else []
+    say(f"[gpu] multihit parity levels={levels} L={L} general={general}")
+    o = oracle_mod.OracleLattice(L, T, 1.1, 31, hot=True)
+    g = u1ml.init_lattice(L, T, 1.1, 31)
+    u1ml.set_estimator(g, multihit=True)
+    if general:
+        u1ml.set_debug(g, 2)
+    o.sweep(1, 3)
+    u1ml.sweep(g, 1, 3)
+    c_o, f_o, _ = o.multilevel(levels, n_sub, 1, 3, r_list, rf_list=rf, multihit=True)
+    u1ml.multilevel(g, levels, n_sub, 1, 3, r_list, rf_list=rf)
+    _, c_g, f_g = u1ml.measure(g, observables=False, correlator=True, field_profile=bool(rf))
+    np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
+    close_rel(c_g, c_o)
+    if rf:
+        close_rel(f_g, f_o)
+
+
+def test_multihit_batch_and_toggle(oracle_mod):
+    Ls, seeds = [4, 6], [51, 52]
+    say("[gpu] multihit batch vs oracle, then off again")
+    b = u1ml.batch_create(Ls, [8, 8], [1.0, 1.0], seeds)
+    ors = [oracle_mod.OracleLattice(L, 8, 1.0, s) for L, s in zip(Ls, seeds)]
+    for mh in (True, False):
+        u1ml.batch_set_estimator(b, multihit=mh)
+        u1ml.batch_multilevel(b, [4, 2], [2, 2], 1, 2, [1, 2, 3], rf_list=[2])
+        for i, o in enumerate(ors):
+            c_o, f_o, _ = o.multilevel([4, 2], [2, 2], 1, 2, [1, 2, 3], rf_list=[2], multihit=mh)
+            _, c_g, f_g = u1ml.batch_measure(b, i, correlator=True, field_profile=True)
+            np.testing.assert_array_equal(u1ml.batch_get_links(b, i), o.get_links())
+            close_rel(c_g, c_o)
+            close_rel(f_g, f_o)
