@@ -103,7 +103,20 @@ __global__ void poly_corr_kernel(const LatDesc* __restrict__ lats, const int2* _
 // ---------------------------------------------------------------------------
 // I_1(x) / I_0(x), x >= 0: power series of both functions with the common
 // terms a_k = (x^2/4)^k / (k!)^2 (I_0 = sum a_k, I_1 = x/2 sum a_k / (k + 1));
-// beyond x = 600 the large-x expansion to order x^-4
+// beyond x = 600 the large-x expansion to order x^-4.  The factors 1/k^2 and
+// 1/(k+1) of the first kBesselTab terms come from a table (no division).
+constexpr int kBesselTab = 64;
+struct BesselTab {
+  double inv_k2[kBesselTab], inv_k1[kBesselTab];
+  constexpr BesselTab() : inv_k2(), inv_k1() {
+    for (int k = 1; k < kBesselTab; ++k) {
+      inv_k2[k] = 1.0 / ((double)k * (double)k);
+      inv_k1[k] = 1.0 / (double)(k + 1);
+    }
+  }
+};
+__device__ constexpr BesselTab kBessel{};
+
 __device__ __forceinline__ double bessel_i1_over_i0(double x) {
   if (x <= 0.0) return 0.0;
   if (x > 600.0) {
@@ -112,7 +125,14 @@ __device__ __forceinline__ double bessel_i1_over_i0(double x) {
   }
   const double q = 0.25 * x * x;
   double a = 1.0, s0 = 1.0, s1 = 1.0;
-  for (int k = 1; k < 2000; ++k) {
+  int k = 1;
+  for (; k < kBesselTab; ++k) {
+    a *= q * kBessel.inv_k2[k];
+    s0 += a;
+    s1 += a * kBessel.inv_k1[k];
+    if (a < 1e-18 * s0) return 0.5 * x * s1 / s0;
+  }
+  for (; k < 2000; ++k) {
     a *= q / ((double)k * (double)k);
     s0 += a;
     s1 += a / (double)(k + 1);
@@ -121,29 +141,47 @@ __device__ __forceinline__ double bessel_i1_over_i0(double x) {
   return 0.5 * x * s1 / s0;
 }
 
-// multihit mean of the temporal link at s: with the staple S of Eq. (3) the
-// link's conditional density is exp(beta |S| cos(theta + arg S)) / norm, and
-// the mean of exp(i theta) is conj(S) / |S| * I_1(beta |S|) / I_0(beta |S|)
+// staple of the temporal link at s (Eq. (3)): S = sum over nu = 1..3 of the
+// forward phase theta_nu(x + 0) - theta_0(x + nu) - theta_nu(x) and the
+// backward phase -(theta_0(x - nu) + theta_nu(x + 0 - nu) - theta_nu(x - nu)),
+// in the arithmetic of the links (FP64 with library sincos; FP32 with the
+// hardware sine and cosine, the staple arithmetic of the FP32 path)
 template <typename R>
-__device__ __forceinline__ double2 multihit_mean(const R* links, const LatDesc& d, Site s) {
-  double sr = 0.0, si = 0.0;
+__device__ __forceinline__ void temporal_staple(const R* links, const LatDesc& d, Site s, double& sr_out,
+                                                double& si_out) {
+  R sr = (R)0, si = (R)0;
   for (int nu = 1; nu < 4; ++nu) {
-    // forward plaquette: theta_nu(x + 0) - theta_0(x + nu) - theta_nu(x)
-    const double ap = (ld(links, link_at(d, nu, shift2(d, s, 0, 1, nu, 0))) -
-                       ld(links, link_at(d, 0, shift2(d, s, nu, 1, 0, 0)))) -
-                      ld(links, link_at(d, nu, s));
-    // backward plaquette: -(theta_0(x - nu) + theta_nu(x + 0 - nu) - theta_nu(x - nu))
     const Site b = shift2(d, s, nu, -1, 0, 0);
-    const double am = -((ld(links, link_at(d, 0, b)) + ld(links, link_at(d, nu, shift2(d, s, 0, 1, nu, -1)))) -
-                        ld(links, link_at(d, nu, b)));
-    double sn, cs;
-    sincos(ap, &sn, &cs);
-    sr += cs;
-    si += sn;
-    sincos(am, &sn, &cs);
+    const R ap = (links[link_at(d, nu, shift2(d, s, 0, 1, nu, 0))] - links[link_at(d, 0, shift2(d, s, nu, 1, 0, 0))]) -
+                 links[link_at(d, nu, s)];
+    const R am = -((links[link_at(d, 0, b)] + links[link_at(d, nu, shift2(d, s, 0, 1, nu, -1))]) -
+                   links[link_at(d, nu, b)]);
+    R sn, cs;
+    if constexpr (sizeof(R) == 4) {
+      __sincosf(ap, &sn, &cs);
+      sr += cs;
+      si += sn;
+      __sincosf(am, &sn, &cs);
+    } else {
+      sincos(ap, &sn, &cs);
+      sr += cs;
+      si += sn;
+      sincos(am, &sn, &cs);
+    }
     sr += cs;
     si += sn;
   }
+  sr_out = (double)sr;
+  si_out = (double)si;
+}
+
+// multihit mean of the temporal link at s: with the staple S the link's
+// conditional density is exp(beta |S| cos(theta + arg S)) / norm, and the mean
+// of exp(i theta) is conj(S) / |S| * I_1(beta |S|) / I_0(beta |S|)
+template <typename R>
+__device__ __forceinline__ double2 multihit_mean(const R* links, const LatDesc& d, Site s) {
+  double sr, si;
+  temporal_staple(links, d, s, sr, si);
   const double a = hypot(sr, si);
   if (a == 0.0) return make_double2(0.0, 0.0);
   const double q = bessel_i1_over_i0(d.beta * a) / a;

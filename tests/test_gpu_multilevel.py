@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 from paper_1208_0166_amd import u1ml
+from tests.test_oracle_multihit import multihit_corr
 from tests.test_oracle_multilevel import field_identity, plain_corr
 
 pytestmark = pytest.mark.gpu
@@ -204,3 +205,23 @@ def test_multihit_batch_and_toggle(oracle_mod):
             np.testing.assert_array_equal(u1ml.batch_get_links(b, i), o.get_links())
             close_rel(c_g, c_o)
             close_rel(f_g, f_o)
+
+
+@pytest.mark.parametrize("prec", [u1ml.FP64, u1ml.FP32])
+def test_multihit_full_size_24_identity(prec):
+    # 24^4, one update per level: the multihit correlator is the definition on
+    # the final links (numpy); FP32 staples give ~1e-6 relative
+    L = T = 24
+    say(f"[gpu] 24^4 multihit identity prec={prec}")
+    g = u1ml.init_lattice(L, T, 1.0, 13, precision=prec, start=u1ml.COLD)
+    u1ml.set_estimator(g, multihit=True)
+    for _ in range(3):
+        u1ml.sweep(g, 1, 3)
+    rl = [1, 2, 3, 6, 12]
+    u1ml.multilevel(g, [4, 2], [1, 1], 1, 3, rl)
+    _, c, _ = u1ml.measure(g, observables=False, correlator=True)
+    th = u1ml.get_links(g)
+    ref = np.array([plain_corr(th, 1)] + [multihit_corr(th, 1.0, r) for r in rl[1:]])
+    tol = 1e-12 if prec == u1ml.FP64 else 2e-5
+    assert abs(c[0] - ref[0]) < 1e-12
+    assert np.abs(c[1:] - ref[1:]).max() <= tol * np.abs(ref[1:]).max()

@@ -12,6 +12,34 @@ import numpy as np
 import pytest
 from scipy import special
 
+AX = {0: 0, 1: 3, 2: 2, 3: 1}  # direction -> axis of th[t][z][y][x]
+
+
+def multihit_means(th, beta):
+    """m(t, z, y, x) = conj(S)/|S| I_1(beta|S|)/I_0(beta|S|) for every temporal link,
+    S its staple (numpy, from the definition of the Wilson action)."""
+    t0 = th[..., 0]
+    S = np.zeros(t0.shape, dtype=complex)
+    for nu in (1, 2, 3):
+        a = AX[nu]
+        tn = th[..., nu]
+        fwd = np.roll(tn, -1, axis=0) - np.roll(t0, -1, axis=a) - tn
+        bwd = -(np.roll(t0, 1, axis=a) + np.roll(np.roll(tn, -1, axis=0), 1, axis=a) - np.roll(tn, 1, axis=a))
+        S += np.exp(1j * fwd) + np.exp(1j * bwd)
+    mag = np.abs(S)
+    ratio = special.i1e(beta * mag) / special.i0e(beta * mag)
+    out = np.zeros_like(S)
+    nz = mag > 0
+    out[nz] = ratio[nz] * np.conj(S[nz]) / mag[nz]
+    return out
+
+
+def multihit_corr(th, beta, r):
+    """One update per level: (1/L^3) sum_x conj(M(x)) M(x + r), M the product over
+    all times of the multihit means (r >= 2)."""
+    M = multihit_means(th, beta).prod(axis=0)  # [z][y][x]
+    return np.mean(np.conj(M) * np.roll(M, -r, axis=2))
+
 
 @pytest.mark.parametrize("x", [0.0, 1e-9, 1e-3, 0.3, 1.0, 2.5, 6.0, 17.0, 60.0, 250.0])
 def test_bessel_ratio_against_scipy(oracle_mod, x):
@@ -68,3 +96,28 @@ def test_multilevel_multihit_r1_unchanged_and_r2_reduced_variance(oracle_mod):
     d = mh - plain
     assert abs(d.mean()) < 3 * d.std(ddof=1) / np.sqrt(len(d))
     assert mh.std(ddof=1) < plain.std(ddof=1)
+
+
+def test_multihit_means_match_numpy_definition(oracle_mod):
+    L, T, beta = 4, 6, 0.9
+    g = oracle_mod.OracleLattice(L, T, beta, 4, hot=True)
+    th = g.get_links()
+    m = multihit_means(th, beta)
+    for n in (0, 17, 93, 255, 300, L ** 3 * T - 1):
+        t, rem = divmod(n, L ** 3)
+        z, rem = divmod(rem, L * L)
+        y, x = divmod(rem, L)
+        assert abs(g.multihit_mean(n) - m[t, z, y, x]) < 1e-13
+
+
+@pytest.mark.parametrize("levels", [([2], [1]), ([4, 2], [1, 1])])
+def test_multihit_single_update_reduces_to_definition(oracle_mod, levels):
+    L, T, beta = 4, 8, 1.0
+    g = oracle_mod.OracleLattice(L, T, beta, 6, hot=True)
+    g.sweep(1, 3)
+    c, _, _ = g.multilevel(levels[0], levels[1], 1, 3, [1, 2, 3], multihit=True)
+    th = g.get_links()
+    from tests.test_oracle_multilevel import plain_corr
+    assert abs(c[0] - plain_corr(th, 1)) < 1e-13
+    for k, r in enumerate([2, 3], start=1):
+        assert abs(c[k] - multihit_corr(th, beta, r)) < 1e-13
