@@ -66,6 +66,8 @@ def _load():
         "or_plain_correlator": (None, [P, C.c_int, ip, dp]),
         "or_field_op": (C.c_double, [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
         "or_field_means": (None, [P, dp]),
+        "or_field2_means": (None, [P, dp]),
+        "or_field_op2": (C.c_double, [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
         "or_multilevel": (C.c_int, [P, C.c_int, ip, ip, C.c_int, C.c_int, C.c_int, ip, dp,
                                     C.c_int, ip, dp, u8p, C.c_long, C.POINTER(C.c_long), C.c_int]),
         "or_bessel_ratio": (C.c_double, [C.c_double]),
@@ -213,8 +215,17 @@ class OracleLattice:
         self._lib.or_field_means(self._h, _dp(out))
         return out
 
+    def field_op2(self, comp, t, x, y, z) -> float:
+        """beta (1 - Re P) of the plaquette of component comp at (t, x, y, z)."""
+        return self._lib.or_field_op2(self._h, comp, t, x, y, z)
+
+    def field2_means(self):
+        out = np.zeros(6)
+        self._lib.or_field2_means(self._h, _dp(out))
+        return out
+
     def multilevel(self, slab_sizes, n_sub, n_metro=1, n_or=3, r_list=(1,), rf_list=(),
-                   log_cap=0, multihit=False):
+                   log_cap=0, multihit=False, field_squared=False):
         """Returns (C_ML[r] complex, field[rf][plane][comp][dy][dz] complex, log)."""
         th = np.ascontiguousarray(slab_sizes, dtype=np.int32)
         ns = np.ascontiguousarray(n_sub, dtype=np.int32)
@@ -236,7 +247,7 @@ class OracleLattice:
         used = C.c_long(0)
         rc = self._lib.or_multilevel(self._h, len(th), _ip(th), _ip(ns), n_metro, n_or, len(r), _ip(r),
                                      _dp(corr), n_rf, _ip(rf), _dp(field), _u8p(log) if log_cap else None,
-                                     int(log_cap), C.byref(used), int(bool(multihit)))
+                                     int(log_cap), C.byref(used), int(bool(multihit)) | (2 if field_squared else 0))
         if rc != 0:
             raise ValueError("invalid multilevel arguments")
         f = field.reshape(max(n_rf, 1), 2, 6, L, L, 2)

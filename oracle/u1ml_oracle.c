@@ -503,6 +503,29 @@ double or_field_op(const or_lat *g, int comp, int t, int x, int y, int z)
     return sqrt(g->beta) * sin(plaq_angle(g, n, c, FIELD_MU[comp], FIELD_NU[comp]));
 }
 
+/* squared components (Eq. (6)): a^4 F_munu^2 = beta (1 - Re P_munu) */
+double or_field_op2(const or_lat *g, int comp, int t, int x, int y, int z)
+{
+    long n = site_index(g, t, x, y, z);
+    int c[4];
+    site_coords(g, n, c);
+    return g->beta * (1.0 - cos(plaq_angle(g, n, c, FIELD_MU[comp], FIELD_NU[comp])));
+}
+
+/* lattice averages of the six squared components */
+void or_field2_means(const or_lat *g, double *out)
+{
+    int L = g->L;
+    for (int comp = 0; comp < 6; ++comp) {
+        double acc = 0.0;
+        for (int t = 0; t < g->T; ++t)
+            for (int z = 0; z < L; ++z)
+                for (int y = 0; y < L; ++y)
+                    for (int x = 0; x < L; ++x) acc += or_field_op2(g, comp, t, x, y, z);
+        out[comp] = acc / (double)g->V;
+    }
+}
+
 /* lattice averages <O_c> of the six field operators */
 void or_field_means(const or_lat *g, double *out)
 {
@@ -577,6 +600,7 @@ void or_multihit_mean(const or_lat *g, long n, double *out)
 typedef struct ml_ctx {
     or_lat *g;
     int multihit;       /* correlator lines at r >= 2 from multihit means */
+    int field_squared;  /* insert beta (1 - Re P) instead of sqrt(beta) Im P */
     int n_levels;
     const int *th;      /* slab thickness per level, outer to inner */
     const int *n_sub;   /* updates per level */
@@ -619,13 +643,13 @@ static cplx two_link_mh(const or_lat *g, long x0, int t, int r)
 
 /* displacement d of the field operator relative to the source x0:
  * index d = (plane*L + dy)*L + dz, plane 0 at x offset (r-1)/2, plane 1 at r/2 */
-static double field_at(const or_lat *g, int comp, long x0, int t, int rf, int d)
+static double field_at(const or_lat *g, int comp, long x0, int t, int rf, int d, int squared)
 {
     int L = g->L;
     int x = (int)(x0 % L), y = (int)((x0 / L) % L), z = (int)(x0 / ((long)L * L));
     int plane = d / (L * L), dy = (d / L) % L, dz = d % L;
     int m = plane == 0 ? (rf - 1) / 2 : rf / 2;
-    return or_field_op(g, comp, t, x + m, y + dy, z + dz);
+    return squared ? or_field_op2(g, comp, t, x + m, y + dy, z + dz) : or_field_op(g, comp, t, x + m, y + dy, z + dz);
 }
 
 /* Accumulator sizes: corr[slab][x0][r], field[slab][x0][rf][d][comp] (complex) */
@@ -699,7 +723,7 @@ static void ml_level(ml_ctx *c, int lev, cplx *avg, cplx *favg)
                                     for (int t = s * th; t < (s + 1) * th; ++t) {
                                         cplx tl = two_link(g, x0, t, r);
                                         if (t == ti) {
-                                            double o = field_at(g, comp, x0, t, r, d);
+                                            double o = field_at(g, comp, x0, t, r, d, c->field_squared);
                                             tl.re *= o;
                                             tl.im *= o;
                                         }
@@ -750,15 +774,16 @@ static void ml_level(ml_ctx *c, int lev, cplx *avg, cplx *favg)
  *   field_out[((((f*2 + plane)*6 + comp)*L + dy)*L + dz)*2 + {0,1}]
  *       = <P*(0) P(r) O_comp(m, dy, dz)> of Eq. (9): (1/V) sum_x0 sum over the
  *         slab s holding the insertion of B_s(x0) prod_{s' != s} A_s'(x0).
- * Every r_f in rf_list must also appear in r_list.  multihit != 0 replaces,
- * for every r >= 2, the temporal links of both lines by their multihit means
- * in the correlator products (and so in the slab averages that multiply a
- * field insertion elsewhere); r = 1 and the slab holding a field insertion
- * use the links themselves.  Returns 0, or -1 on a bad argument (slab sizes
- * must divide T and each other). */
+ * Every r_f in rf_list must also appear in r_list.  flags & 1 (multihit)
+ * replaces, for every r >= 2, the temporal links of both lines by their
+ * multihit means in the correlator products (and so in the slab averages that
+ * multiply a field insertion elsewhere); r = 1 and the slab holding a field
+ * insertion use the links themselves.  flags & 2 inserts the squared
+ * components beta (1 - Re P) of Eq. (6) instead of sqrt(beta) Im P.  Returns
+ * 0, or -1 on a bad argument (slab sizes must divide T and each other). */
 int or_multilevel(or_lat *g, int n_levels, const int *th, const int *n_sub, int n_metro, int n_or,
                   int n_r, const int *r_list, double *corr_out, int n_rf, const int *rf_list,
-                  double *field_out, unsigned char *log, long log_cap, long *log_used, int multihit)
+                  double *field_out, unsigned char *log, long log_cap, long *log_used, int flags)
 {
     if (n_levels < 1 || n_r < 1) return -1;
     for (int l = 0; l < n_levels; ++l) {
@@ -772,7 +797,8 @@ int or_multilevel(or_lat *g, int n_levels, const int *th, const int *n_sub, int 
     }
     ml_ctx c;
     memset(&c, 0, sizeof c);
-    c.g = g; c.n_levels = n_levels; c.th = th; c.n_sub = n_sub; c.multihit = multihit;
+    c.g = g; c.n_levels = n_levels; c.th = th; c.n_sub = n_sub;
+    c.multihit = flags & 1; c.field_squared = (flags >> 1) & 1;
     c.n_metro = n_metro; c.n_or = n_or;
     c.n_r = n_r; c.r_list = r_list; c.n_rf = n_rf; c.rf_list = rf_list;
     c.L3 = (long)g->L * g->L * g->L;

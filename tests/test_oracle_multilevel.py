@@ -23,22 +23,23 @@ def plain_corr(th, r):
     return np.mean(np.conj(P) * np.roll(P, -r, axis=2))
 
 
-def field_ops(th, beta):
-    """O_c(t, z, y, x) = sqrt(beta) sin(theta_munu) for the six components."""
+def field_ops(th, beta, squared=False):
+    """O_c(t, z, y, x) = sqrt(beta) sin(theta_munu) for the six components, or
+    with squared=True the Eq. (6) components beta (1 - cos(theta_munu))."""
     out = []
     for mu, nu in FIELD_PLANES:
         p = (th[..., mu] + np.roll(th[..., nu], -1, axis=AX[mu])
              - np.roll(th[..., mu], -1, axis=AX[nu]) - th[..., nu])
-        out.append(math.sqrt(beta) * np.sin(p))
+        out.append(beta * (1.0 - np.cos(p)) if squared else math.sqrt(beta) * np.sin(p))
     return np.array(out)
 
 
-def field_identity(th, beta, r):
+def field_identity(th, beta, r, squared=False):
     """(1/V) sum_x0 sum_t P*(x0) P(x0 + r) O(x0 + d, t) for d in both planes."""
     T, L = th.shape[0], th.shape[1]
     P = polyakov_lines(th)
     w = np.conj(P) * np.roll(P, -r, axis=2)          # [z][y][x]
-    Osum = field_ops(th, beta).sum(axis=1)           # [c][z][y][x]
+    Osum = field_ops(th, beta, squared).sum(axis=1)  # [c][z][y][x]
     res = np.zeros((2, 6, L, L), dtype=complex)
     for plane, m in enumerate([(r - 1) // 2, r // 2]):
         for dy in range(L):
@@ -128,3 +129,26 @@ def test_multilevel_and_plain_estimators_agree(oracle_mod):
     assert d < 4 * e, (plain.mean(), ml.mean(), e)
     # the multilevel estimate is the less noisy one per unit of measurement
     assert ml.std() < plain.std()
+
+
+@pytest.mark.parametrize("levels", [([2], [1]), ([4, 2], [1, 1])])
+def test_field_squared_single_update_reduces_to_definition(oracle_mod, levels):
+    # Eq. (6) components inserted instead of Eq. (5)
+    L, T, beta = 4, 8, 1.2
+    g = oracle_mod.OracleLattice(L, T, beta, 29)
+    g.sweep(1, 2)
+    _, f, _ = g.multilevel(levels[0], levels[1], 1, 2, [1, 2, 3], rf_list=[2, 3], field_squared=True)
+    th = g.get_links()
+    for i, r in enumerate([2, 3]):
+        np.testing.assert_allclose(f[i], field_identity(th, beta, r, squared=True), atol=1e-13)
+
+
+def test_field_squared_means_sum_to_the_plaquette(oracle_mod):
+    # sum_c beta (1 - Re P_c) over the six orientations is 6 beta (1 - <plaquette>)
+    g = oracle_mod.OracleLattice(4, 6, 0.8, 3)
+    g.sweep(1, 3)
+    m2 = g.field2_means()
+    assert abs(m2.sum() - 6 * 0.8 * (1.0 - g.plaquette())) < 1e-13
+    assert np.all(m2 > 0)
+    cold = oracle_mod.OracleLattice(4, 4, 1.0, 1, hot=False)
+    np.testing.assert_array_equal(cold.field2_means(), np.zeros(6))
