@@ -86,6 +86,8 @@ typedef struct u1ml_observables {
     double poly_im;       /* Im of the same */
     double poly_abs;      /* its modulus */
     double field_mean[6]; /* lattice averages <O_c> of the Eq. (5) operators (Eq. (7) subtraction) */
+    double field2_mean[6]; /* lattice averages of the squared components of Eq. (6),
+                              beta (1 - Re P_munu), same component order */
 } u1ml_observables;
 
 typedef struct u1ml_lattice u1ml_lattice;
@@ -137,8 +139,14 @@ int u1ml_multilevel(u1ml_lattice *lat, int n_levels, const int *slab_sizes, cons
  * (S: the link's staple), in the correlator and in the slab averages that
  * multiply a field insertion made elsewhere; r = 1 (whose two lines share
  * plaquettes) and the inner slab holding a field insertion use the links
- * themselves.  Doubles the stored time lines.  EINVAL on unknown bits. */
+ * themselves.  Doubles the stored time lines.
+ * U1ML_FIELD_SQUARED (Eq. (6)): the field insertion of Eq. (9) uses the
+ * squared components a^4 F_munu^2 = beta (1 - Re P_munu) in place of the
+ * Eq. (5) operators; same component order, planes and profile layout.
+ * Subtract field2_mean of u1ml_observables for the connected profile of
+ * Eq. (7).  EINVAL on unknown bits. */
 #define U1ML_MULTIHIT 1u
+#define U1ML_FIELD_SQUARED 2u
 int u1ml_set_estimator(u1ml_lattice *lat, unsigned flags);
 
 /* Measure the current links and return the latest multilevel results.

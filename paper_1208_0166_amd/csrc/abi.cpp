@@ -423,14 +423,15 @@ struct Engine {
     for (auto& d : h_lats) items.push_back(2 * d.V2);
     Table* t;
     U1_TRY(table(items, 256, &t));
-    U1_TRY(partial.ensure((size_t)t->n_blocks * 7 * sizeof(double)));
+    const int W = kPlaqFieldWidth;
+    U1_TRY(partial.ensure((size_t)t->n_blocks * W * sizeof(double)));
     U1_TRY(row_begin.ensure((n_lats + 1) * sizeof(int)));
-    U1_TRY(red_out.ensure((size_t)n_lats * 7 * sizeof(double)));
+    U1_TRY(red_out.ensure((size_t)n_lats * W * sizeof(double)));
     U1_HIP(hipStreamSynchronize(stream));
     U1_HIP(hipMemcpy(row_begin.p, t->lat_block_begin.data(), (n_lats + 1) * sizeof(int), hipMemcpyHostToDevice));
     U1_HIP(launch_plaq_field(prec, links.p, lats.as<LatDesc>(), bt(t), partial.as<double>(), stream));
-    U1_HIP(launch_reduce_rows(partial.as<double>(), 7, row_begin.as<int>(), n_lats, red_out.as<double>(), stream));
-    std::vector<double> pf((size_t)n_lats * 7);
+    U1_HIP(launch_reduce_rows(partial.as<double>(), W, row_begin.as<int>(), n_lats, red_out.as<double>(), stream));
+    std::vector<double> pf((size_t)n_lats * W);
     U1_HIP(hipStreamSynchronize(stream));
     U1_HIP(hipMemcpy(pf.data(), red_out.p, pf.size() * sizeof(double), hipMemcpyDeviceToHost));
     std::vector<std::vector<double>> pc;
@@ -438,8 +439,11 @@ struct Engine {
     res.resize(n_lats);
     for (int i = 0; i < n_lats; ++i) {
       const double V = 2.0 * h_lats[i].V2;
-      res[i].plaquette = pf[i * 7] / (6.0 * V);
-      for (int c = 0; c < 6; ++c) res[i].field_mean[c] = pf[i * 7 + 1 + c] / V;
+      res[i].plaquette = pf[i * W] / (6.0 * V);
+      for (int c = 0; c < 6; ++c) {
+        res[i].field_mean[c] = pf[i * W + 1 + c] / V;
+        res[i].field2_mean[c] = pf[i * W + 7 + c] / V;
+      }
       res[i].poly_re = pc[i][0];
       res[i].poly_im = pc[i][1];
       res[i].poly_abs = std::hypot(pc[i][0], pc[i][1]);
@@ -647,7 +651,7 @@ struct Engine {
                            m.mlbuf.as<double2>(), stream));
     if (m.field)
       U1_HIP(launch_field_o(prec, links.p, lats.as<LatDesc>(), m.fls.as<FieldLat>(), bt(t), m.th[inner], sample,
-                            m.fbuf.as<double>(), stream));
+                            (estimator & U1ML_FIELD_SQUARED) != 0, m.fbuf.as<double>(), stream));
     return U1ML_OK;
   }
 
@@ -953,7 +957,7 @@ int u1ml_set_pass_id(u1ml_lattice* lat, uint64_t pass_id) {
 }
 
 static int set_estimator(Engine& e, unsigned flags) {
-  if (flags & ~U1ML_MULTIHIT) return fail(U1ML_EINVAL, "unknown estimator flags");
+  if (flags & ~(U1ML_MULTIHIT | U1ML_FIELD_SQUARED)) return fail(U1ML_EINVAL, "unknown estimator flags");
   U1_TRY(e.set_device());
   if (e.estimator != flags) {
     U1_HIP(hipStreamSynchronize(e.stream));

@@ -57,7 +57,9 @@ struct MLDesc {
   int multihit;                  // correlator lines at r >= 2 from ell_mh
 };
 
-// plaquette sum and field sums: partial[blk][7] then final[7] per lattice
+// plaquette sum, the six field sums and the six squared-component sums:
+// partial[blk][kPlaqFieldWidth], reduced to one such row per lattice
+constexpr int kPlaqFieldWidth = 13;
 hipError_t launch_plaq_field(int prec, const void* links, const LatDesc* lats, BlockTable bt, double* partial,
                              hipStream_t st);
 // reduce per-lattice ranges of 'width'-wide partial rows: out[lat][width]
@@ -107,8 +109,9 @@ struct FieldParams {
   int n_outer;   // n_0 for two levels, 1 for one level
   int n_inner;   // samples per inner run
 };
+// squared = true stores the squared components of Eq. (6) instead of Eq. (5)
 hipError_t launch_field_o(int prec, const void* links, const LatDesc* lats, const FieldLat* fls, BlockTable bt,
-                          int th_inner, int sample, double* fbuf, hipStream_t st);
+                          int th_inner, int sample, bool squared, double* fbuf, hipStream_t st);
 // contraction of all stored samples of one lattice into F [n_rf][2][6][L][L]
 // (complex); general = true takes the stored-transform path for any geometry
 hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,

@@ -22,6 +22,8 @@ namespace {
 // ---------------------------------------------------------------------------
 // plain observables
 // ---------------------------------------------------------------------------
+// Per block: the plaquette sum, the six field operators of Eq. (5) and the
+// six squared components of Eq. (6), summed over the block's sites.
 template <typename R>
 __global__ void plaq_field_kernel(const R* __restrict__ links, const LatDesc* __restrict__ lats,
                                   const int2* __restrict__ blocks, double* __restrict__ partial) {
@@ -29,24 +31,26 @@ __global__ void plaq_field_kernel(const R* __restrict__ links, const LatDesc* __
   const int2 bk = blocks[blockIdx.x];
   const LatDesc d = lats[bk.x];
   const uint32_t n = (uint32_t)bk.y + threadIdx.x;
-  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  double v[kPlaqFieldWidth];
+  for (int j = 0; j < kPlaqFieldWidth; ++j) v[j] = 0.0;
   if (n < 2u * (uint32_t)d.V2) {
     const Site s = as_site(coords_natural(d, n));
-    const double p01 = plaq_angle(links, d, s, 0, 1), p02 = plaq_angle(links, d, s, 0, 2);
-    const double p03 = plaq_angle(links, d, s, 0, 3), p12 = plaq_angle(links, d, s, 1, 2);
-    const double p13 = plaq_angle(links, d, s, 1, 3), p23 = plaq_angle(links, d, s, 2, 3);
-    v[0] = ((((cos(p01) + cos(p02)) + cos(p03)) + cos(p12)) + cos(p13)) + cos(p23);
+    // component order E_x, E_y, E_z, B_x, B_y, B_z from P_01, P_02, P_03,
+    // P_23, P_31 = conj(P_13), P_12
+    const double p[6] = {plaq_angle(links, d, s, 0, 1), plaq_angle(links, d, s, 0, 2),
+                         plaq_angle(links, d, s, 0, 3), plaq_angle(links, d, s, 2, 3),
+                         -plaq_angle(links, d, s, 1, 3), plaq_angle(links, d, s, 1, 2)};
+    v[0] = ((((cos(p[0]) + cos(p[1])) + cos(p[2])) + cos(p[5])) + cos(p[4])) + cos(p[3]);
     const double sb = d.sqrt_beta;
-    v[1] = sb * sin(p01);
-    v[2] = sb * sin(p02);
-    v[3] = sb * sin(p03);
-    v[4] = sb * sin(p23);
-    v[5] = -sb * sin(p13);
-    v[6] = sb * sin(p12);
+    for (int c = 0; c < 6; ++c) {
+      v[1 + c] = sb * sin(p[c]);
+      const double h = sin(0.5 * p[c]);
+      v[7 + c] = 2.0 * d.beta * (h * h);
+    }
   }
-  for (int j = 0; j < 7; ++j) {
+  for (int j = 0; j < kPlaqFieldWidth; ++j) {
     const double r = block_sum(v[j], sh);
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * 7 + j] = r;
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kPlaqFieldWidth + j] = r;
   }
 }
 
@@ -392,20 +396,36 @@ __global__ void ml_final_kernel(const LatDesc* __restrict__ lats, const MLDesc* 
 // ---------------------------------------------------------------------------
 // sin of the plaquette angle: FP64 links in FP64; FP32 links (the fast path)
 // in FP32 arithmetic with the hardware sine, summed by the caller in FP64
-__device__ __forceinline__ double plaq_sin(const double* links, const LatDesc& d, Site s, int mu, int nu) {
-  return sin(plaq_angle(links, d, s, mu, nu));
+// Insertion operator of one plaquette angle: sqrt(beta) Im P (Eq. (5)), or
+// with SQ the squared component beta (1 - Re P) = 2 beta sin^2(theta / 2)
+// (Eq. (6)); the prefactor is applied by the caller.
+template <bool SQ>
+__device__ __forceinline__ double plaq_op(const double* links, const LatDesc& d, Site s, int mu, int nu) {
+  const double a = plaq_angle(links, d, s, mu, nu);
+  if (SQ) {
+    const double h = sin(0.5 * a);
+    return 2.0 * (h * h);
+  }
+  return sin(a);
 }
-__device__ __forceinline__ double plaq_sin(const float* links, const LatDesc& d, Site s, int mu, int nu) {
+template <bool SQ>
+__device__ __forceinline__ double plaq_op(const float* links, const LatDesc& d, Site s, int mu, int nu) {
   const float a = links[link_at(d, mu, s)];
   const float b = links[link_at(d, nu, shift2(d, s, mu, 1, nu, 0))];
   const float c = links[link_at(d, mu, shift2(d, s, nu, 1, mu, 0))];
   const float e = links[link_at(d, nu, s)];
-  return (double)__sinf(((a + b) - c) - e);
+  const float th = ((a + b) - c) - e;
+  if (SQ) {
+    const float h = __sinf(0.5f * th);
+    return (double)(2.0f * (h * h));
+  }
+  return (double)__sinf(th);
 }
 
 // oall[((sample * 6 + c) * ns + s) * L3 + y] = sum over the times t of inner
-// slab s of O_c(y, t), O_c = sqrt(beta) Im P_munu (Eq. (5)).
-template <typename R>
+// slab s of O_c(y, t): O_c = sqrt(beta) Im P_munu (Eq. (5)), or with SQ the
+// squared component beta (1 - Re P_munu) (Eq. (6)).
+template <typename R, bool SQ>
 __global__ void field_o_kernel(const R* __restrict__ links, const LatDesc* __restrict__ lats,
                                const FieldLat* __restrict__ fls, const int2* __restrict__ blocks, int th_inner,
                                int sample, double* __restrict__ fbuf) {
@@ -422,17 +442,20 @@ __global__ void field_o_kernel(const R* __restrict__ links, const LatDesc* __res
   double o[6] = {0, 0, 0, 0, 0, 0};
   for (int t = s * th_inner; t < (s + 1) * th_inner; ++t) {
     st.t = t;
-    o[0] += plaq_sin(links, d, st, 0, 1);
-    o[1] += plaq_sin(links, d, st, 0, 2);
-    o[2] += plaq_sin(links, d, st, 0, 3);
-    o[3] += plaq_sin(links, d, st, 2, 3);
-    o[4] -= plaq_sin(links, d, st, 1, 3);
-    o[5] += plaq_sin(links, d, st, 1, 2);
+    o[0] += plaq_op<SQ>(links, d, st, 0, 1);
+    o[1] += plaq_op<SQ>(links, d, st, 0, 2);
+    o[2] += plaq_op<SQ>(links, d, st, 0, 3);
+    o[3] += plaq_op<SQ>(links, d, st, 2, 3);
+    if (SQ)
+      o[4] += plaq_op<SQ>(links, d, st, 1, 3);
+    else
+      o[4] -= plaq_op<SQ>(links, d, st, 1, 3);
+    o[5] += plaq_op<SQ>(links, d, st, 1, 2);
   }
+  const double pre = SQ ? d.beta : d.sqrt_beta;
   double* out = fbuf + fl.oall + (size_t)sample * 6 * fl.ns * d.L3;
-  for (int c = 0; c < 6; ++c) out[((size_t)c * fl.ns + s) * d.L3 + y3] = d.sqrt_beta * o[c];
+  for (int c = 0; c < 6; ++c) out[((size_t)c * fl.ns + s) * d.L3 + y3] = pre * o[c];
 }
-
 
 }  // namespace
 
@@ -520,14 +543,22 @@ hipError_t launch_ml_final(const LatDesc* lats, const MLDesc* mls, int n_lats, i
 }
 
 hipError_t launch_field_o(int prec, const void* links, const LatDesc* lats, const FieldLat* fls, BlockTable bt,
-                          int th_inner, int sample, double* fbuf, hipStream_t st) {
+                          int th_inner, int sample, bool squared, double* fbuf, hipStream_t st) {
   if (bt.n_blocks == 0) return hipSuccess;
-  if (prec == kFP64)
-    hipLaunchKernelGGL(field_o_kernel<double>, dim3(bt.n_blocks), dim3(bt.block), 0, st, (const double*)links, lats,
-                       fls, bt.dev, th_inner, sample, fbuf);
-  else
-    hipLaunchKernelGGL(field_o_kernel<float>, dim3(bt.n_blocks), dim3(bt.block), 0, st, (const float*)links, lats,
-                       fls, bt.dev, th_inner, sample, fbuf);
+  const dim3 g(bt.n_blocks), b(bt.block);
+  if (prec == kFP64) {
+    const double* l = (const double*)links;
+    if (squared)
+      hipLaunchKernelGGL((field_o_kernel<double, true>), g, b, 0, st, l, lats, fls, bt.dev, th_inner, sample, fbuf);
+    else
+      hipLaunchKernelGGL((field_o_kernel<double, false>), g, b, 0, st, l, lats, fls, bt.dev, th_inner, sample, fbuf);
+  } else {
+    const float* l = (const float*)links;
+    if (squared)
+      hipLaunchKernelGGL((field_o_kernel<float, true>), g, b, 0, st, l, lats, fls, bt.dev, th_inner, sample, fbuf);
+    else
+      hipLaunchKernelGGL((field_o_kernel<float, false>), g, b, 0, st, l, lats, fls, bt.dev, th_inner, sample, fbuf);
+  }
   return hipGetLastError();
 }
 

@@ -41,11 +41,13 @@ class Options(C.Structure):
 
 class Observables(C.Structure):
     _fields_ = [("plaquette", C.c_double), ("poly_re", C.c_double), ("poly_im", C.c_double),
-                ("poly_abs", C.c_double), ("field_mean", C.c_double * 6)]
+                ("poly_abs", C.c_double), ("field_mean", C.c_double * 6),
+                ("field2_mean", C.c_double * 6)]
 
     def as_dict(self):
         return {"plaquette": self.plaquette, "poly": complex(self.poly_re, self.poly_im),
-                "poly_abs": self.poly_abs, "field_mean": list(self.field_mean)}
+                "poly_abs": self.poly_abs, "field_mean": list(self.field_mean),
+                "field2_mean": list(self.field2_mean)}
 
 
 _lib = None
@@ -256,11 +258,16 @@ def set_pass_id(lat: Lattice, pass_id: int):
 
 
 MULTIHIT = 1
+FIELD_SQUARED = 2
 
 
-def set_estimator(lat: Lattice, multihit: bool = False):
+def _estimator_flags(multihit: bool, field_squared: bool) -> int:
+    return (MULTIHIT if multihit else 0) | (FIELD_SQUARED if field_squared else 0)
+
+
+def set_estimator(lat: Lattice, multihit: bool = False, field_squared: bool = False):
     """Estimator options of the following multilevel runs (u1ml_set_estimator)."""
-    _check(load_library().u1ml_set_estimator(lat.handle, MULTIHIT if multihit else 0))
+    _check(load_library().u1ml_set_estimator(lat.handle, _estimator_flags(multihit, field_squared)))
 
 
 def set_debug(lat: Lattice, flags: int, capacity: int = 0):
@@ -372,8 +379,8 @@ def batch_multilevel(b: Batch, slab_sizes, n_sub, n_metro: int = 1, n_or: int = 
     b._n_r, b._n_rf = [len(r)] * len(b.L), len(rf_list)
 
 
-def batch_set_estimator(b: Batch, multihit: bool = False):
-    _check(load_library().u1ml_batch_set_estimator(b.handle, MULTIHIT if multihit else 0))
+def batch_set_estimator(b: Batch, multihit: bool = False, field_squared: bool = False):
+    _check(load_library().u1ml_batch_set_estimator(b.handle, _estimator_flags(multihit, field_squared)))
 
 
 def batch_measure(b: Batch, i: int, correlator: bool = True, field_profile: bool = False):

@@ -225,3 +225,82 @@ def test_multihit_full_size_24_identity(prec):
     tol = 1e-12 if prec == u1ml.FP64 else 2e-5
     assert abs(c[0] - ref[0]) < 1e-12
     assert np.abs(c[1:] - ref[1:]).max() <= tol * np.abs(ref[1:]).max()
+
+
+@pytest.mark.parametrize("levels,n_sub,L,T,mh,general,prec", [
+    ([4, 2], [2, 3], 4, 8, False, False, u1ml.FP64),
+    ([4, 2], [2, 3], 4, 8, True, False, u1ml.FP64),
+    ([4, 2], [2, 3], 4, 8, False, True, u1ml.FP64),
+    ([2], [4], 6, 4, False, False, u1ml.FP64),
+    ([4, 2], [2, 3], 6, 8, False, False, u1ml.FP32),
+])
+def test_field_squared_parity(oracle_mod, levels, n_sub, L, T, mh, general, prec):
+    # squared components of Eq. (6) as the insertion, against the oracle; for
+    # FP32 links the oracle starts from the same (FP32-rounded) links and only
+    # the one-update identity below is exact, so here the chain must match
+    r_list = [1, 2, 3]
+    rf = [2, 3]
+    say(f"[gpu] squared field parity levels={levels} L={L} mh={mh} general={general} prec={prec}")
+    o = oracle_mod.OracleLattice(L, T, 1.2, 41, hot=True)
+    g = u1ml.init_lattice(L, T, 1.2, 41, precision=prec)
+    u1ml.set_estimator(g, multihit=mh, field_squared=True)
+    if general:
+        u1ml.set_debug(g, 2)
+    if prec == u1ml.FP32:
+        # the FP32 update differs from the FP64 chain; compare at one update
+        # per level on the GPU's own links instead
+        u1ml.multilevel(g, levels, [1] * len(levels), 1, 3, r_list, rf_list=rf)
+        _, _, f_g = u1ml.measure(g, observables=False, correlator=False, field_profile=True)
+        th = u1ml.get_links(g)
+        for i, r in enumerate(rf):
+            close_rel(f_g[i], field_identity(th, 1.2, r, squared=True), FIELD_REL[prec])
+        return
+    o.sweep(1, 3)
+    u1ml.sweep(g, 1, 3)
+    c_o, f_o, _ = o.multilevel(levels, n_sub, 1, 3, r_list, rf_list=rf, multihit=mh, field_squared=True)
+    u1ml.multilevel(g, levels, n_sub, 1, 3, r_list, rf_list=rf)
+    _, c_g, f_g = u1ml.measure(g, observables=False, correlator=True, field_profile=True)
+    np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
+    close_rel(c_g, c_o)
+    close_rel(f_g, f_o)
+
+
+def test_field_squared_batch_toggle_and_means(oracle_mod):
+    # the flag switches between the Eq. (5) and Eq. (6) insertions in a batch;
+    # the plain observables carry both lattice means
+    Ls, seeds = [4, 6], [61, 62]
+    say("[gpu] squared field batch toggle")
+    b = u1ml.batch_create(Ls, [8, 8], [0.9, 0.9], seeds)
+    ors = [oracle_mod.OracleLattice(L, 8, 0.9, s) for L, s in zip(Ls, seeds)]
+    for sq in (True, False, True):
+        u1ml.batch_set_estimator(b, field_squared=sq)
+        u1ml.batch_multilevel(b, [4, 2], [2, 2], 1, 2, [1, 2, 3], rf_list=[3])
+        for i, o in enumerate(ors):
+            c_o, f_o, _ = o.multilevel([4, 2], [2, 2], 1, 2, [1, 2, 3], rf_list=[3], field_squared=sq)
+            obs, c_g, f_g = u1ml.batch_measure(b, i, correlator=True, field_profile=True)
+            np.testing.assert_array_equal(u1ml.batch_get_links(b, i), o.get_links())
+            close_rel(c_g, c_o)
+            close_rel(f_g, f_o)
+            np.testing.assert_allclose(obs["field2_mean"], o.field2_means(), rtol=1e-13, atol=1e-15)
+            np.testing.assert_allclose(obs["field_mean"], o.field_means(), atol=1e-14)
+
+
+@pytest.mark.parametrize("prec", [u1ml.FP64, u1ml.FP32])
+def test_field_squared_full_size_24_identity(prec):
+    # 24^4, one update per level, squared insertion at r = 6 and 12: the
+    # profile is the definition on the final links, and the squared means sum
+    # to 6 beta (1 - plaquette)
+    L = T = 24
+    beta = 1.0
+    say(f"[gpu] 24^4 squared field identity prec={prec}")
+    g = u1ml.init_lattice(L, T, beta, 17, precision=prec)
+    u1ml.set_estimator(g, field_squared=True)
+    u1ml.sweep(g, 1, 3)
+    rf = [6, 12]
+    u1ml.multilevel(g, [4, 2], [1, 1], 1, 3, [1, 6, 12], rf_list=rf)
+    obs, _, f = u1ml.measure(g, observables=True, correlator=False, field_profile=True)
+    th = u1ml.get_links(g)
+    for i, r in enumerate(rf):
+        close_rel(f[i], field_identity(th, beta, r, squared=True), FIELD_REL[prec])
+    # both sums are taken in FP64 from the stored links at either precision
+    assert abs(sum(obs["field2_mean"]) - 6 * beta * (1 - obs["plaquette"])) < 1e-12
