@@ -57,7 +57,7 @@ extern "C" {
 #define U1ML_FP32 1 /* FP32 angles, hardware transcendentals; FP64 measurements */
 
 #define U1ML_MAX_LEVELS 3
-#define U1ML_MAX_FIELD_R 8
+#define U1ML_MAX_FIELD_R 32
 
 /* Field components of Eq. (5), in this order, in every field output. */
 #define U1ML_EX 0 /* sqrt(beta) Im P_01 */

@@ -103,8 +103,8 @@ struct FieldLat {
 };
 struct FieldParams {
   int n_rf;
-  int rf[8];     // field separations
-  int rf_k[8];   // index of each rf in the lattice's r list
+  int rf[32];    // field separations (U1ML_MAX_FIELD_R)
+  int rf_k[32];  // index of each rf in the lattice's r list
   int n_levels;  // 1 or 2
   int n_outer;   // n_0 for two levels, 1 for one level
   int n_inner;   // samples per inner run

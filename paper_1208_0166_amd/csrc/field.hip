@@ -353,12 +353,14 @@ __global__ __launch_bounds__(256) void field_what_kernel(const LatDesc* __restri
 // (npb even: pairs of planes as one complex plane) of each of the three
 // components.  Thread = row (c, pair, y) in pass 1, column (c, pair, q) in
 // pass 2, and owner of the G entries (r_f, p, q) of all three components and
-// both planes, e = tid + j * blockDim.x: every W value read serves six sums.
+// both planes, e = e_begin + tid + j * blockDim.x: every W value read serves
+// six sums.  With many separations the entries are split into n_fc chunks of
+// fe_per entries (whole r_f), one block per chunk.
 constexpr int kFxComp = 3;  // field components per block
 template <int L>
 __global__ __launch_bounds__(512) void field_ocon_kernel(const LatDesc* __restrict__ lat,
                                                          const FieldLat* __restrict__ flp, FieldParams fp,
-                                                         int sample0, int npb, int nacc,
+                                                         int sample0, int npb, int nacc, int n_fc, int fe_per,
                                                          const double* __restrict__ fbuf,
                                                          const double2* __restrict__ what,
                                                          double2* __restrict__ part) {
@@ -367,13 +369,14 @@ __global__ __launch_bounds__(512) void field_ocon_kernel(const LatDesc* __restri
   const LatDesc d = *lat;
   const FieldLat fl = *flp;
   const int ns = fl.ns;
-  const int lb = (int)xcd_block(blockIdx.x, gridDim.x);  // both triples of one (k, s) share an L2
-  const int cg = lb % CG, s = (lb / CG) % ns, k = lb / (CG * ns);
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x);  // the blocks of one (k, s) share an L2
+  const int cg = lb % CG, fc = (lb / CG) % n_fc, s = (lb / (CG * n_fc)) % ns, k = lb / (CG * n_fc * ns);
   const int c0 = cg * kFxComp, sample = sample0 + k;
   const double* o0 = fbuf + fl.oall + (((size_t)sample * 6 + c0) * ns + s) * d.L3;  // + c * ns * L3
   const double2* wk = what + ((size_t)k * fp.n_rf * ns + s) * L * L2;                // + (f * ns * L + x) * L2
   const int tid = threadIdx.x;
   const int n_fe = fp.n_rf * L2;  // entries (f, pq)
+  const int e_begin = fc * fe_per, e_end = min(n_fe, e_begin + fe_per);
   // With m_0 = (r - 1) / 2 and m_1 = r / 2 (= m_0 or m_0 + 1), plane 1 at x uses
   // the W plane that plane 0 used at x - 1 (even r) or the same one (odd r), so
   // every W value is read once: wp carries W(x - 1 - m_0) from plane to plane.
@@ -383,8 +386,8 @@ __global__ __launch_bounds__(512) void field_ocon_kernel(const LatDesc* __restri
 #pragma unroll
     for (int c = 0; c < kFxComp; ++c) g0[j][c] = g1[j][c] = make_double2(0.0, 0.0);
     wp[j] = make_double2(0.0, 0.0);
-    const int e = tid + j * (int)blockDim.x;
-    if (j < nacc && e < n_fe) {
+    const int e = e_begin + tid + j * (int)blockDim.x;
+    if (j < nacc && e < e_end) {
       const int f = e / L2, pq = e - f * L2, m0 = (fp.rf[f] - 1) / 2;
       wp[j] = wk[(size_t)f * ns * L * L2 + (size_t)(L - 1 - m0) * L2 + pq];  // W(-1 - m_0)
     }
@@ -410,8 +413,8 @@ __global__ __launch_bounds__(512) void field_ocon_kernel(const LatDesc* __restri
     // contraction over the planes of this group
 #pragma unroll
     for (int j = 0; j < kFxEnt; ++j) {
-      const int e = tid + j * (int)blockDim.x;
-      if (j < nacc && e < n_fe) {
+      const int e = e_begin + tid + j * (int)blockDim.x;
+      if (j < nacc && e < e_end) {
         const int f = e / L2, pq = e - f * L2, r = fp.rf[f];
         const int m0 = (r - 1) / 2;
         const bool even = (r & 1) == 0;
@@ -450,8 +453,8 @@ __global__ __launch_bounds__(512) void field_ocon_kernel(const LatDesc* __restri
   const int n_ent = 2 * n_fe;
 #pragma unroll
   for (int j = 0; j < kFxEnt; ++j) {
-    const int e = tid + j * (int)blockDim.x;
-    if (j < nacc && e < n_fe) {
+    const int e = e_begin + tid + j * (int)blockDim.x;
+    if (j < nacc && e < e_end) {
       const int f = e / L2, pq = e - f * L2;
 #pragma unroll
       for (int c = 0; c < kFxComp; ++c) {
@@ -506,10 +509,12 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
   const int npb_o = 2 * std::min(L / 2, planes / kFxComp);  // x planes per group of each component
   const int n_ent = 2 * fp.n_rf * (int)L2;
   const int thr_w = (npb_w * L + 63) / 64 * 64;
-  const int n_fe = fp.n_rf * (int)L2;
+  // separations per contraction block: at most 512 threads of kFxEnt entries
+  const int fpc = std::min(fp.n_rf, 512 * kFxEnt / (int)L2);
+  const int n_fc = (fp.n_rf + fpc - 1) / fpc, fe_per = fpc * (int)L2;
   const int thr_o =
-      std::max((kFxComp * npb_o / 2 * L + 63) / 64 * 64, ((n_fe + kFxEnt - 1) / kFxEnt + 63) / 64 * 64);
-  const int nacc = (n_fe + thr_o - 1) / thr_o;
+      std::max((kFxComp * npb_o / 2 * L + 63) / 64 * 64, ((fe_per + kFxEnt - 1) / kFxEnt + 63) / 64 * 64);
+  const int nacc = (fe_per + thr_o - 1) / thr_o;
   const int ngroups_w = (L + npb_w - 1) / npb_w;
   const uint64_t per_sample = (uint64_t)fp.n_rf * ns * L3 + (uint64_t)ns * 6 * n_ent;
   const int chunk = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, scratch_elems / per_sample));
@@ -520,8 +525,9 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
     double2* part = what + (uint64_t)nk * fp.n_rf * ns * L3;
     hipLaunchKernelGGL(field_what_kernel<L>, dim3((unsigned)((uint64_t)nk * fp.n_rf * ns * ngroups_w)), dim3(thr_w),
                        npb_w * plane_bytes, st, lat, ml, fl, fp, s0, npb_w, mlbuf, fbuf, what);
-    hipLaunchKernelGGL(field_ocon_kernel<L>, dim3((unsigned)((uint64_t)nk * ns * (6 / kFxComp))), dim3(thr_o),
-                       kFxComp * (npb_o / 2) * plane_bytes, st, lat, fl, fp, s0, npb_o, nacc, fbuf, what, part);
+    hipLaunchKernelGGL(field_ocon_kernel<L>, dim3((unsigned)((uint64_t)nk * ns * n_fc * (6 / kFxComp))),
+                       dim3(thr_o), kFxComp * (npb_o / 2) * plane_bytes, st, lat, fl, fp, s0, npb_o, nacc, n_fc,
+                       fe_per, fbuf, what, part);
     hipLaunchKernelGGL(field_gsum_kernel, dim3(blocks_for(6 * (uint64_t)n_ent, 64)), dim3(64), 0, st, fp, L, ns, nk,
                        part, G);
   }
@@ -533,7 +539,7 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
 typedef hipError_t (*FastContract)(const LatDesc*, const MLDesc*, const FieldLat*, int, FieldParams, const double2*,
                                    const double*, double2*, size_t, double2*, hipStream_t);
 FastContract fast_contract_for(int L, FieldParams fp) {
-  if (L > kFxMaxL || fp.n_rf * L * L > 512 * kFxEnt) return nullptr;
+  if (L > kFxMaxL || L * L > 512 * kFxEnt) return nullptr;
   if (kFxLds / ((size_t)L * (L + 1) * sizeof(double2)) < (size_t)kFxComp) return nullptr;  // one pair per component
   switch (L) {
     case 2: return launch_fast_contract<2>;

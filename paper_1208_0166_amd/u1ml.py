@@ -24,7 +24,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EIO = 0, -1, -2, -3, -4, -5
 COLD, HOT = 0, 1
 FP64, FP32 = 0, 1
 MAX_LEVELS = 3
-MAX_FIELD_R = 8
+MAX_FIELD_R = 32
 FIELD_NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz")
 
 

@@ -143,19 +143,21 @@ def test_batch_multilevel_with_field_matches_oracle(oracle_mod):
         close_rel(f_g, f_o)
 
 
-@pytest.mark.parametrize("L", [10, 12, 20, 32])
-def test_fused_field_contraction_matches_general(L):
+@pytest.mark.parametrize("L,rf", [(10, [2, 3]), (12, [2, 3]), (20, [2, 3]), (32, [2, 3]),
+                                  (24, list(range(1, 13))), (32, [1, 2, 5, 7, 16])])
+def test_fused_field_contraction_matches_general(L, rf):
     # the fused contraction (register FFTs of radices 2, 3, 4, 5) against the
-    # general one (stored direct transforms) on the same chain
+    # general one (stored direct transforms) on the same chain; the long r
+    # lists split the fused contraction into several blocks per sample
     T = 4
-    say(f"[gpu] fused vs general field contraction L={L}")
+    say(f"[gpu] fused vs general field contraction L={L} rf={rf}")
     res = []
     for general in (False, True):
         g = u1ml.init_lattice(L, T, 1.0, 21)
         if general:
             u1ml.set_debug(g, 2)
         u1ml.sweep(g, 1, 2)
-        u1ml.multilevel(g, [2], [2], 1, 2, [1, 2, 3], rf_list=[2, 3])
+        u1ml.multilevel(g, [2], [2], 1, 2, sorted(set([1, 2, 3] + rf)), rf_list=rf)
         _, c, f = u1ml.measure(g, observables=False, correlator=True, field_profile=True)
         res.append((u1ml.get_links(g), c, f))
     np.testing.assert_array_equal(res[0][0], res[1][0])
@@ -263,6 +265,29 @@ def test_field_squared_parity(oracle_mod, levels, n_sub, L, T, mh, general, prec
     np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
     close_rel(c_g, c_o)
     close_rel(f_g, f_o)
+
+
+@pytest.mark.parametrize("L,T,levels,n_sub,general", [
+    (6, 8, [4, 2], [2, 2], False),
+    (6, 8, [4, 2], [2, 2], True),
+    (8, 4, [2], [3], False),
+])
+def test_field_profile_at_every_separation(oracle_mod, L, T, levels, n_sub, general):
+    # E/B profiles for every r = 1 .. L - 1 in one run, against the oracle
+    rf = list(range(1, L))
+    say(f"[gpu] field at all r L={L} T={T} levels={levels} general={general}")
+    o = oracle_mod.OracleLattice(L, T, 1.0, 71, hot=True)
+    g = u1ml.init_lattice(L, T, 1.0, 71)
+    if general:
+        u1ml.set_debug(g, 2)
+    c_o, f_o, _ = o.multilevel(levels, n_sub, 1, 2, rf, rf_list=rf)
+    u1ml.multilevel(g, levels, n_sub, 1, 2, rf, rf_list=rf)
+    _, c_g, f_g = u1ml.measure(g, observables=False, correlator=True, field_profile=True)
+    np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
+    close_rel(c_g, c_o)
+    assert f_g.shape == (L - 1, 2, 6, L, L)
+    for i in range(L - 1):
+        close_rel(f_g[i], f_o[i])
 
 
 def test_field_squared_batch_toggle_and_means(oracle_mod):
