@@ -253,3 +253,22 @@ class OracleLattice:
         f = field.reshape(max(n_rf, 1), 2, 6, L, L, 2)
         f = (f[..., 0] + 1j * f[..., 1])[:n_rf]
         return corr[0::2] + 1j * corr[1::2], f, log[: used.value]
+
+
+def connected_profile(fields, corrs, omeans, r_list, rf_list):
+    """Eq. (7) over an ensemble of multilevel runs:
+
+        <O_c(d)>_{P*P} = mean <P*(0) P(r) O_c(d)> / mean <P*(0) P(r)> - mean <O_c>
+
+    fields[k]: run k's field profile [n_rf][plane][comp][dy][dz] (complex),
+    corrs[k]: its correlator over r_list, omeans[k]: the six lattice means of
+    the inserted operators.  Means are plain averages over the runs; the
+    quotient is the complex one.  Returns [n_rf][plane][comp][dy][dz]."""
+    F = np.mean(np.asarray(fields), axis=0)
+    Cm = np.mean(np.asarray(corrs), axis=0)
+    O = np.mean(np.asarray(omeans, dtype=float), axis=0)
+    r_list = list(r_list)
+    out = np.empty_like(F)
+    for f, r in enumerate(rf_list):
+        out[f] = F[f] / Cm[r_list.index(r)] - O[None, :, None, None]
+    return out

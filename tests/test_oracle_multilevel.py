@@ -152,3 +152,51 @@ def test_field_squared_means_sum_to_the_plaquette(oracle_mod):
     assert np.all(m2 > 0)
     cold = oracle_mod.OracleLattice(4, 4, 1.0, 1, hot=False)
     np.testing.assert_array_equal(cold.field2_means(), np.zeros(6))
+
+
+@pytest.mark.parametrize("squared", [False, True])
+def test_connected_profile_vanishes_for_a_constant_magnetic_field(oracle_mod, squared):
+    # Eq. (7).  theta_y(x) = 2 pi x / L puts the same angle on every xy
+    # plaquette whatever the temporal links are, so B_z is one constant and
+    # B_x = B_y = 0 everywhere.  Identity updates (eps = 0, no OR) keep the
+    # configuration, the field profile is then B_z C(r) at every offset and
+    # the connected B profile is exactly zero; the E components, made from
+    # random temporal links, are not constant and survive the subtraction.
+    L, T, beta = 6, 4, 1.3
+    rng = np.random.default_rng(5)
+    th = np.zeros((T, L, L, L, 4))
+    th[..., 0] = rng.uniform(-np.pi, np.pi, size=(T, L, L, L))
+    th[..., 2] = ((2 * np.pi * np.arange(L) / L) + np.pi) % (2 * np.pi) - np.pi
+    g = oracle_mod.OracleLattice(L, T, beta, 3, hot=False, eps=0.0)
+    g.set_links(th)
+    r_list, rf = [1, 2, 3], [2, 3]
+    fields, corrs, omeans = [], [], []
+    for _ in range(2):
+        c, f, _ = g.multilevel([2], [2], 1, 0, r_list, rf_list=rf, field_squared=squared)
+        fields.append(f)
+        corrs.append(c)
+        omeans.append(g.field2_means() if squared else g.field_means())
+    np.testing.assert_array_equal(g.get_links(), th)
+    # C(r) differs between the field separations, so a wrong r index shows
+    assert abs(corrs[0][1] - corrs[0][2]) > 1e-3
+    conn = oracle_mod.connected_profile(fields, corrs, omeans, r_list, rf)
+    assert conn.shape == (2, 2, 6, L, L)
+    assert np.abs(conn[:, :, 3:]).max() < 1e-13
+    assert np.abs(conn[:, :, :3]).max() > 1e-2
+    bz = beta * (1 - math.cos(2 * np.pi / L)) if squared else math.sqrt(beta) * math.sin(2 * np.pi / L)
+    assert abs(omeans[0][5] - bz) < 1e-13
+    ref = np.broadcast_to(bz * corrs[0][[1, 2], None, None, None], fields[0][:, :, 5].shape)
+    np.testing.assert_allclose(fields[0][:, :, 5], ref, atol=1e-13)
+
+
+def test_connected_profile_of_an_ensemble_uses_ratio_of_means(oracle_mod):
+    # Eq. (7) divides the ensemble means, not run by run: with two runs whose
+    # field profiles and correlators are proportional the ratio is the common
+    # factor; a per-run average of ratios would give a different value here
+    L = 2
+    f1 = np.full((1, 2, 6, L, L), 2.0 + 0j)
+    f2 = np.full((1, 2, 6, L, L), 1.0 + 0j)
+    c1, c2 = np.array([1.0 + 0j]), np.array([3.0 + 0j])
+    o = [np.arange(6) * 0.1, np.arange(6) * 0.3]
+    conn = oracle_mod.connected_profile([f1, f2], [c1, c2], o, [1], [1])
+    np.testing.assert_allclose(conn[0, 0, :, 0, 0], 3.0 / 4.0 - np.arange(6) * 0.2, atol=1e-15)
