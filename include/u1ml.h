@@ -161,6 +161,30 @@ int u1ml_set_estimator(u1ml_lattice *lat, unsigned flags);
  * Synchronises the stream.  Caller owns the host buffers. */
 int u1ml_measure(u1ml_lattice *lat, u1ml_observables *obs, double *correlator, double *field_profile);
 
+/* Ensemble of multilevel runs and the connected profile of Eq. (7).
+ * u1ml_ensemble_add adds the last multilevel run's C(r) and field profile,
+ * and the lattice means <O_c> of the inserted operator set (Eq. (5), or
+ * Eq. (6) with U1ML_FIELD_SQUARED) taken on the current links, to sums kept
+ * on the device.  Every run of one ensemble must have the same r list, field
+ * separations and operator set (EINVAL otherwise; reset to start another);
+ * ESTATE if no multilevel has run.  The first add after a reset sets up the
+ * sums and synchronises the stream; later adds are asynchronous.
+ * u1ml_ensemble_reset empties the ensemble (host-side, no device work). */
+int u1ml_ensemble_reset(u1ml_lattice *lat);
+int u1ml_ensemble_add(u1ml_lattice *lat);
+/* Runs added so far and the sizes the read buffers need (n_r, n_rf of the
+ * ensemble's runs; 0 when empty).  Any pointer may be NULL. */
+int u1ml_ensemble_info(u1ml_lattice *lat, int *n_runs, int *n_r, int *n_rf);
+/* Ensemble means over the n added runs (any pointer may be NULL):
+ *   correlator [n_r][2]: mean C(r);
+ *   field_profile [n_rf][2][6][L][L][2]: mean <P* P O_c>, layout of u1ml_measure;
+ *   connected [n_rf][2][6][L][L][2]: Eq. (7),
+ *     mean <P* P O_c>(r_f, d) / mean C(r_f) - mean <O_c>, complex division
+ *     (computed on the device).
+ * ESTATE if the ensemble is empty, or a field output is asked of runs
+ * without field.  Synchronises the stream.  Caller owns the host buffers. */
+int u1ml_ensemble_read(u1ml_lattice *lat, double *correlator, double *field_profile, double *connected);
+
 /* Plain (single configuration) correlator of the current links:
  * out[2k], out[2k+1] = L^-3 sum_x P*(x) P(x + r_k e_x).  Synchronises. */
 int u1ml_plain_correlator(u1ml_lattice *lat, int n_r, const int *r_list, double *out);
@@ -230,6 +254,11 @@ int u1ml_batch_set_estimator(u1ml_batch *b, unsigned flags);
  * Synchronises. */
 int u1ml_batch_measure(u1ml_batch *b, int i, u1ml_observables *obs, double *correlator, double *field_profile);
 int u1ml_batch_get_links(u1ml_batch *b, int i, double *host);
+/* u1ml_ensemble_* for a batch: one ensemble per lattice, added together. */
+int u1ml_batch_ensemble_reset(u1ml_batch *b);
+int u1ml_batch_ensemble_add(u1ml_batch *b);
+int u1ml_batch_ensemble_info(u1ml_batch *b, int i, int *n_runs, int *n_r, int *n_rf);
+int u1ml_batch_ensemble_read(u1ml_batch *b, int i, double *correlator, double *field_profile, double *connected);
 int u1ml_batch_set_links(u1ml_batch *b, int i, const double *host);
 int u1ml_batch_synchronize(u1ml_batch *b);
 void u1ml_batch_destroy(u1ml_batch *b);

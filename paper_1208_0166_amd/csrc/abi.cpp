@@ -113,6 +113,24 @@ struct MLState {
   std::vector<uint64_t> fout_off;  // per lattice, double2 elements
   DevBuf fls, fbuf, fout, scratch;
   size_t scratch_elems = 0;
+  // shape of the last completed run (r lists, field separations, operator set)
+  std::vector<long long> shape;
+  unsigned run_flags = 0;  // estimator flags of that run
+};
+
+// Sums over multilevel runs of the correlator, the field profile and the
+// lattice means of the inserted operators (Eq. (7)).
+struct Ensemble {
+  std::vector<long long> shape;  // MLState::shape of the runs
+  long long n = 0;
+  unsigned flags = 0;
+  int max_r = 0;
+  std::vector<int> nR;
+  bool field = false;
+  FieldParams fp{};
+  std::vector<uint64_t> fout_off;
+  uint64_t fout_elems = 0;
+  DevBuf corr, fsum, omean, partial, red, row_begin, conn;
 };
 
 struct GraphEntry {
@@ -147,6 +165,7 @@ struct Engine {
   // measurement scratch
   DevBuf partial, rows, poly, poly_off, row_begin, red_out, rvals_tmp;
   MLState ml;
+  Ensemble ens;
   // captured launch sequences
   std::map<std::vector<long long>, GraphEntry> graphs;
   bool capturing = false;
@@ -694,6 +713,91 @@ struct Engine {
     return U1ML_OK;
   }
 
+  // --- ensemble of multilevel runs (Eq. (7)) ---
+  void ensemble_reset() {
+    ens.n = 0;
+    ens.shape.clear();
+  }
+
+  // adds the last run's correlator and field profile and the current links'
+  // means of the inserted operator set; asynchronous after the first call
+  int ensemble_add() {
+    if (!ml.valid) return fail(U1ML_ESTATE, "no multilevel result to add");
+    if (ens.n > 0 && ens.shape != ml.shape)
+      return fail(U1ML_EINVAL, "the ensemble holds runs of another shape; reset it first");
+    const int W = kPlaqFieldWidth;
+    std::vector<int> items;
+    for (auto& d : h_lats) items.push_back(2 * d.V2);
+    Table* t;
+    U1_TRY(table(items, 256, &t));
+    if (ens.n == 0) {
+      ens.shape = ml.shape;
+      ens.flags = ml.run_flags;
+      ens.max_r = ml.max_r;
+      ens.nR = ml.nR;
+      ens.field = ml.field_valid;
+      ens.fp = ml.fp;
+      ens.fout_off = ml.fout_off;
+      ens.fout_elems = 0;
+      size_t conn_elems = 0;
+      if (ens.field)
+        for (int i = 0; i < n_lats; ++i) {
+          const uint64_t n = (uint64_t)ens.fp.n_rf * 12 * h_lats[i].L * h_lats[i].L;
+          ens.fout_elems = std::max<uint64_t>(ens.fout_elems, ens.fout_off[i] + n);
+          conn_elems = std::max<size_t>(conn_elems, n);
+        }
+      U1_TRY(ens.corr.ensure((size_t)n_lats * ens.max_r * sizeof(double2)));
+      U1_TRY(ens.fsum.ensure(ens.fout_elems * sizeof(double2)));
+      U1_TRY(ens.conn.ensure(conn_elems * sizeof(double2)));
+      U1_TRY(ens.omean.ensure((size_t)n_lats * 6 * sizeof(double)));
+      U1_TRY(ens.partial.ensure((size_t)t->n_blocks * W * sizeof(double)));
+      U1_TRY(ens.red.ensure((size_t)n_lats * W * sizeof(double)));
+      U1_TRY(ens.row_begin.ensure((n_lats + 1) * sizeof(int)));
+      U1_HIP(hipStreamSynchronize(stream));
+      U1_HIP(hipMemcpy(ens.row_begin.p, t->lat_block_begin.data(), (n_lats + 1) * sizeof(int),
+                       hipMemcpyHostToDevice));
+      // cleared by kernels, not memset nodes, in case the caller captures the stream
+      U1_HIP(launch_ml_zero(ens.corr.as<double2>(), (uint64_t)n_lats * ens.max_r, stream));
+      U1_HIP(launch_ml_zero(ens.fsum.as<double2>(), ens.fout_elems, stream));
+      U1_HIP(launch_ml_zero(ens.omean.as<double2>(), (uint64_t)n_lats * 3, stream));
+    }
+    U1_HIP(launch_ens_add(ens.corr.as<double>(), ml.corr.as<double>(), (uint64_t)n_lats * ens.max_r * 2, stream));
+    if (ens.field)
+      U1_HIP(launch_ens_add(ens.fsum.as<double>(), ml.fout.as<double>(), ens.fout_elems * 2, stream));
+    U1_HIP(launch_plaq_field(prec, links.p, lats.as<LatDesc>(), bt(t), ens.partial.as<double>(), stream));
+    U1_HIP(launch_reduce_rows(ens.partial.as<double>(), W, ens.row_begin.as<int>(), n_lats, ens.red.as<double>(),
+                              stream));
+    U1_HIP(launch_ens_omean(lats.as<LatDesc>(), ens.red.as<double>(), W, (ens.flags & U1ML_FIELD_SQUARED) ? 7 : 1,
+                            n_lats, ens.omean.as<double>(), stream));
+    ++ens.n;
+    return U1ML_OK;
+  }
+
+  int ensemble_read(int i, double* correlator, double* field_profile, double* connected) {
+    if (ens.n == 0) return fail(U1ML_ESTATE, "the ensemble is empty");
+    if ((field_profile || connected) && !ens.field) return fail(U1ML_ESTATE, "the ensemble's runs had no field");
+    const double inv = 1.0 / (double)ens.n;
+    const int L = h_lats[i].L;
+    const size_t nf = (size_t)ens.fp.n_rf * 12 * L * L;
+    if (connected)
+      U1_HIP(launch_ens_connected(ens.fsum.as<double2>() + ens.fout_off[i], ens.corr.as<double2>() + (size_t)i * ens.max_r,
+                                  ens.omean.as<double>() + 6 * i, ens.fp, L, inv, ens.conn.as<double2>(), stream));
+    U1_HIP(hipStreamSynchronize(stream));
+    if (correlator) {
+      U1_HIP(hipMemcpy(correlator, ens.corr.as<double2>() + (size_t)i * ens.max_r, ens.nR[i] * sizeof(double2),
+                       hipMemcpyDeviceToHost));
+      for (int k = 0; k < 2 * ens.nR[i]; ++k) correlator[k] *= inv;
+    }
+    if (field_profile) {
+      U1_HIP(hipMemcpy(field_profile, ens.fsum.as<double2>() + ens.fout_off[i], nf * sizeof(double2),
+                       hipMemcpyDeviceToHost));
+      for (size_t k = 0; k < 2 * nf; ++k) field_profile[k] *= inv;
+    }
+    if (connected)
+      U1_HIP(hipMemcpy(connected, ens.conn.p, nf * sizeof(double2), hipMemcpyDeviceToHost));
+    return U1ML_OK;
+  }
+
   // n_sweeps_before unfrozen compound sweeps, then a multilevel run
   int multilevel(int n_levels, const int* th, const int* n_sub, int n_metro, int n_or,
                  const std::vector<std::vector<int>>& rl, const std::vector<int>& rf, int n_sweeps_before) {
@@ -718,6 +822,14 @@ struct Engine {
     }));
     ml.valid = true;
     ml.field_valid = ml.field;
+    ml.shape.assign(1, ml.field ? 1 : 0);
+    ml.shape.push_back((estimator & U1ML_FIELD_SQUARED) ? 1 : 0);
+    for (auto& v : rl) {
+      ml.shape.push_back(-(long long)v.size());
+      for (int r : v) ml.shape.push_back(r);
+    }
+    for (int r : rf) ml.shape.push_back(r);
+    ml.run_flags = estimator;
     return U1ML_OK;
   }
 };
@@ -913,6 +1025,37 @@ int u1ml_multilevel(u1ml_lattice* lat, int n_levels, const int* slab_sizes, cons
 int u1ml_measure(u1ml_lattice* lat, u1ml_observables* obs, double* correlator, double* field_profile) {
   if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
   return read_results(lat->e, 0, obs, correlator, field_profile);
+}
+
+static int ensemble_info(Engine& e, int i, int* n_runs, int* n_r, int* n_rf) {
+  const Ensemble& en = e.ens;
+  if (n_runs) *n_runs = (int)en.n;
+  if (n_r) *n_r = en.n ? en.nR[i] : 0;
+  if (n_rf) *n_rf = (en.n && en.field) ? en.fp.n_rf : 0;
+  return U1ML_OK;
+}
+
+int u1ml_ensemble_reset(u1ml_lattice* lat) {
+  if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
+  lat->e.ensemble_reset();
+  return U1ML_OK;
+}
+
+int u1ml_ensemble_add(u1ml_lattice* lat) {
+  if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
+  U1_TRY(lat->e.set_device());
+  return lat->e.ensemble_add();
+}
+
+int u1ml_ensemble_info(u1ml_lattice* lat, int* n_runs, int* n_r, int* n_rf) {
+  if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
+  return ensemble_info(lat->e, 0, n_runs, n_r, n_rf);
+}
+
+int u1ml_ensemble_read(u1ml_lattice* lat, double* correlator, double* field_profile, double* connected) {
+  if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
+  U1_TRY(lat->e.set_device());
+  return lat->e.ensemble_read(0, correlator, field_profile, connected);
 }
 
 int u1ml_plain_correlator(u1ml_lattice* lat, int n_r, const int* r_list, double* out) {
@@ -1128,6 +1271,29 @@ int u1ml_batch_cycle(u1ml_batch* b, int n_sweeps, int n_metro, int n_or, int th,
 int u1ml_batch_measure(u1ml_batch* b, int i, u1ml_observables* obs, double* correlator, double* field_profile) {
   if (!b || i < 0 || i >= b->e.n_lats) return fail(U1ML_EINVAL, "batch_measure arguments");
   return read_results(b->e, i, obs, correlator, field_profile);
+}
+
+int u1ml_batch_ensemble_reset(u1ml_batch* b) {
+  if (!b) return fail(U1ML_EINVAL, "batch is NULL");
+  b->e.ensemble_reset();
+  return U1ML_OK;
+}
+
+int u1ml_batch_ensemble_add(u1ml_batch* b) {
+  if (!b) return fail(U1ML_EINVAL, "batch is NULL");
+  U1_TRY(b->e.set_device());
+  return b->e.ensemble_add();
+}
+
+int u1ml_batch_ensemble_info(u1ml_batch* b, int i, int* n_runs, int* n_r, int* n_rf) {
+  if (!b || i < 0 || i >= b->e.n_lats) return fail(U1ML_EINVAL, "batch_ensemble_info arguments");
+  return ensemble_info(b->e, i, n_runs, n_r, n_rf);
+}
+
+int u1ml_batch_ensemble_read(u1ml_batch* b, int i, double* correlator, double* field_profile, double* connected) {
+  if (!b || i < 0 || i >= b->e.n_lats) return fail(U1ML_EINVAL, "batch_ensemble_read arguments");
+  U1_TRY(b->e.set_device());
+  return b->e.ensemble_read(i, correlator, field_profile, connected);
 }
 
 int u1ml_batch_get_links(u1ml_batch* b, int i, double* host) {

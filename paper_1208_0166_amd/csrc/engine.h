@@ -112,6 +112,14 @@ struct FieldParams {
 // squared = true stores the squared components of Eq. (6) instead of Eq. (5)
 hipError_t launch_field_o(int prec, const void* links, const LatDesc* lats, const FieldLat* fls, BlockTable bt,
                           int th_inner, int sample, bool squared, double* fbuf, hipStream_t st);
+// ensemble sums of multilevel runs (Eq. (7)): acc[i] += src[i]; the field
+// means of one operator set (columns col0 .. col0 + 5 of the reduced rows,
+// divided by V) into acc[lat][6]; the connected profile of one lattice
+hipError_t launch_ens_add(double* acc, const double* src, uint64_t n, hipStream_t st);
+hipError_t launch_ens_omean(const LatDesc* lats, const double* red, int width, int col0, int n_lats, double* acc,
+                            hipStream_t st);
+hipError_t launch_ens_connected(const double2* fsum, const double2* csum, const double* osum, FieldParams fp, int L,
+                                double inv_n, double2* conn, hipStream_t st);
 // contraction of all stored samples of one lattice into F [n_rf][2][6][L][L]
 // (complex); general = true takes the stored-transform path for any geometry
 hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,

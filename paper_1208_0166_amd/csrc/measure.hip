@@ -457,6 +457,41 @@ __global__ void field_o_kernel(const R* __restrict__ links, const LatDesc* __res
   for (int c = 0; c < 6; ++c) out[((size_t)c * fl.ns + s) * d.L3 + y3] = pre * o[c];
 }
 
+// ---------------------------------------------------------------------------
+// ensemble of multilevel runs and the connected profile of Eq. (7)
+// ---------------------------------------------------------------------------
+// acc[i] += src[i]
+__global__ void ens_add_kernel(double* __restrict__ acc, const double* __restrict__ src, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) acc[i] += src[i];
+}
+
+// acc[lat][c] += red[lat][col0 + c] / V: the lattice averages of one set of
+// six field operators from the reduced plain-observable rows
+__global__ void ens_omean_kernel(const LatDesc* __restrict__ lats, const double* __restrict__ red, int width,
+                                 int col0, int n_lats, double* __restrict__ acc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 6 * n_lats) return;
+  const int lat = i / 6, c = i - lat * 6;
+  acc[i] += red[(size_t)lat * width + col0 + c] / (2.0 * (double)lats[lat].V2);
+}
+
+// conn[e] = <P* P O_c>(r_f, d) / <P* P>(r_f) - <O_c> with ensemble means:
+// fsum, csum and osum are sums over the same n runs, so the ratio takes the
+// sums and only the subtracted mean divides by n.  e = ((f * 2 + plane) * 6
+// + c) * L^2 + pq; cidx[f] is the index of r_f in the correlator.
+__global__ void ens_connected_kernel(const double2* __restrict__ fsum, const double2* __restrict__ csum,
+                                     const double* __restrict__ osum, FieldParams fp, int L, double inv_n,
+                                     double2* __restrict__ conn) {
+  const int L2 = L * L;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= fp.n_rf * 12 * L2) return;
+  const int c = (e / L2) % 6, f = e / (12 * L2);
+  const double2 a = fsum[e], b = csum[fp.rf_k[f]];
+  const double den = b.x * b.x + b.y * b.y;
+  conn[e] = make_double2((a.x * b.x + a.y * b.y) / den - osum[c] * inv_n, (a.y * b.x - a.x * b.y) / den);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -559,6 +594,28 @@ hipError_t launch_field_o(int prec, const void* links, const LatDesc* lats, cons
     else
       hipLaunchKernelGGL((field_o_kernel<float, false>), g, b, 0, st, l, lats, fls, bt.dev, th_inner, sample, fbuf);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_ens_add(double* acc, const double* src, uint64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(ens_add_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, acc, src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_ens_omean(const LatDesc* lats, const double* red, int width, int col0, int n_lats, double* acc,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(ens_omean_kernel, dim3(blocks_for(6 * (uint64_t)n_lats, 64)), dim3(64), 0, st, lats, red, width,
+                     col0, n_lats, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_ens_connected(const double2* fsum, const double2* csum, const double* osum, FieldParams fp, int L,
+                                double inv_n, double2* conn, hipStream_t st) {
+  const uint64_t n = (uint64_t)fp.n_rf * 12 * L * L;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(ens_connected_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, fsum, csum, osum, fp, L,
+                     inv_n, conn);
   return hipGetLastError();
 }
 

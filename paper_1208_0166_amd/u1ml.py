@@ -75,6 +75,14 @@ def load_library(path: str = LIB_PATH):
         "u1ml_multilevel": (I, [P, I, ip, ip, I, I, I, ip, I, ip]),
         "u1ml_measure": (I, [P, C.POINTER(Observables), dp, dp]),
         "u1ml_plain_correlator": (I, [P, I, ip, dp]),
+        "u1ml_ensemble_reset": (I, [P]),
+        "u1ml_ensemble_add": (I, [P]),
+        "u1ml_ensemble_info": (I, [P, ip, ip, ip]),
+        "u1ml_ensemble_read": (I, [P, dp, dp, dp]),
+        "u1ml_batch_ensemble_reset": (I, [P]),
+        "u1ml_batch_ensemble_add": (I, [P]),
+        "u1ml_batch_ensemble_info": (I, [P, I, ip, ip, ip]),
+        "u1ml_batch_ensemble_read": (I, [P, I, dp, dp, dp]),
         "u1ml_get_links": (I, [P, dp]),
         "u1ml_set_links": (I, [P, dp]),
         "u1ml_get_pass_id": (I, [P, C.POINTER(U64)]),
@@ -225,6 +233,44 @@ def measure(lat: Lattice, observables: bool = True, correlator: bool = False, fi
         f = fp.reshape(lat._n_rf, 2, 6, lat.L, lat.L, 2)
         f = f[..., 0] + 1j * f[..., 1]
     return (obs.as_dict() if obs is not None else None), c, f
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _ensemble_read(info, read, L, correlator, field_profile, connected):
+    n, nr, nrf = C.c_int(), C.c_int(), C.c_int()
+    _check(info(C.byref(n), C.byref(nr), C.byref(nrf)))
+    corr = np.zeros(2 * nr.value) if correlator else None
+    fp = np.zeros(nrf.value * 2 * 6 * L * L * 2) if field_profile else None
+    cn = np.zeros(nrf.value * 2 * 6 * L * L * 2) if connected else None
+    _check(read(_dptr(corr), _dptr(fp), _dptr(cn)))
+
+    def cplx(a, shape):
+        if a is None:
+            return None
+        a = a.reshape(*shape, 2)
+        return a[..., 0] + 1j * a[..., 1]
+    fshape = (nrf.value, 2, 6, L, L)
+    return n.value, cplx(corr, (nr.value,)), cplx(fp, fshape), cplx(cn, fshape)
+
+
+def ensemble_reset(lat: Lattice):
+    _check(load_library().u1ml_ensemble_reset(lat.handle))
+
+
+def ensemble_add(lat: Lattice):
+    _check(load_library().u1ml_ensemble_add(lat.handle))
+
+
+def ensemble_read(lat: Lattice, correlator: bool = True, field_profile: bool = False, connected: bool = False):
+    """Returns (n_runs, mean C complex[n_r] or None, mean field complex[n_rf][2][6][L][L]
+    or None, connected profile of Eq. (7), same shape, or None)."""
+    lib = load_library()
+    return _ensemble_read(lambda *a: lib.u1ml_ensemble_info(lat.handle, *a),
+                          lambda *a: lib.u1ml_ensemble_read(lat.handle, *a), lat.L, correlator, field_profile,
+                          connected)
 
 
 def plain_correlator(lat: Lattice, r_list):
@@ -381,6 +427,22 @@ def batch_multilevel(b: Batch, slab_sizes, n_sub, n_metro: int = 1, n_or: int = 
 
 def batch_set_estimator(b: Batch, multihit: bool = False, field_squared: bool = False):
     _check(load_library().u1ml_batch_set_estimator(b.handle, _estimator_flags(multihit, field_squared)))
+
+
+def batch_ensemble_reset(b: Batch):
+    _check(load_library().u1ml_batch_ensemble_reset(b.handle))
+
+
+def batch_ensemble_add(b: Batch):
+    _check(load_library().u1ml_batch_ensemble_add(b.handle))
+
+
+def batch_ensemble_read(b: Batch, i: int, correlator: bool = True, field_profile: bool = False,
+                        connected: bool = False):
+    lib = load_library()
+    return _ensemble_read(lambda *a: lib.u1ml_batch_ensemble_info(b.handle, i, *a),
+                          lambda *a: lib.u1ml_batch_ensemble_read(b.handle, i, *a), b.L[i], correlator,
+                          field_profile, connected)
 
 
 def batch_measure(b: Batch, i: int, correlator: bool = True, field_profile: bool = False):

@@ -58,6 +58,12 @@ def test_null_handles_rejected():
     lib = u1ml.load_library()
     assert lib.u1ml_sweep(None, 1, 3) == u1ml.EINVAL
     assert lib.u1ml_measure(None, None, None, None) == u1ml.EINVAL
+    assert lib.u1ml_ensemble_reset(None) == u1ml.EINVAL
+    assert lib.u1ml_ensemble_add(None) == u1ml.EINVAL
+    assert lib.u1ml_ensemble_info(None, None, None, None) == u1ml.EINVAL
+    assert lib.u1ml_ensemble_read(None, None, None, None) == u1ml.EINVAL
+    assert lib.u1ml_batch_ensemble_add(None) == u1ml.EINVAL
+    assert lib.u1ml_batch_ensemble_read(None, 0, None, None, None) == u1ml.EINVAL
     assert lib.u1ml_init_lattice(4, 4, 1.0, 1, None, None) == u1ml.EINVAL
     lib.u1ml_destroy(None)
     lib.u1ml_batch_destroy(None)
