@@ -225,8 +225,9 @@ class OracleLattice:
         return out
 
     def multilevel(self, slab_sizes, n_sub, n_metro=1, n_or=3, r_list=(1,), rf_list=(),
-                   log_cap=0, multihit=False, field_squared=False):
-        """Returns (C_ML[r] complex, field[rf][plane][comp][dy][dz] complex, log)."""
+                   log_cap=0, multihit=False, field_squared=False, symmetric=False):
+        """Returns (C_ML[r] complex, field[rf][plane][comp][dy][dz] complex, log).
+        symmetric: C_ML(r) averaged over the separations along +-x, +-y, +-z."""
         th = np.ascontiguousarray(slab_sizes, dtype=np.int32)
         ns = np.ascontiguousarray(n_sub, dtype=np.int32)
         r = np.ascontiguousarray(r_list, dtype=np.int32)
@@ -247,7 +248,8 @@ class OracleLattice:
         used = C.c_long(0)
         rc = self._lib.or_multilevel(self._h, len(th), _ip(th), _ip(ns), n_metro, n_or, len(r), _ip(r),
                                      _dp(corr), n_rf, _ip(rf), _dp(field), _u8p(log) if log_cap else None,
-                                     int(log_cap), C.byref(used), int(bool(multihit)) | (2 if field_squared else 0))
+                                     int(log_cap), C.byref(used),
+                                     int(bool(multihit)) | (2 if field_squared else 0) | (4 if symmetric else 0))
         if rc != 0:
             raise ValueError("invalid multilevel arguments")
         f = field.reshape(max(n_rf, 1), 2, 6, L, L, 2)

@@ -607,6 +607,7 @@ typedef struct ml_ctx {
     int n_metro, n_or;
     int n_r;
     const int *r_list;
+    int n_dir;          /* 1: separations along +x; 6: along +-x, +-y, +-z */
     int n_rf;           /* field insertion separations (0 = no field) */
     const int *rf_list;
     long L3;
@@ -615,13 +616,23 @@ typedef struct ml_ctx {
     long log_cap, log_used;
 } ml_ctx;
 
-/* T(x0, t, r) = U_0*(x0, t) U_0(x0 + r e_x, t), Eq. (8) without the operator */
-static cplx two_link(const or_lat *g, long x0, int t, int r)
+/* the six directions of a separation: +x, -x, +y, -y, +z, -z */
+static const int DIR_VEC[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+
+/* site x0 + r e_dir at time t */
+static long source_shift(const or_lat *g, long x0, int t, int r, int dir)
 {
     int L = g->L;
     int x = (int)(x0 % L), y = (int)((x0 / L) % L), z = (int)(x0 / ((long)L * L));
-    double a = TH(g, site_index(g, t, x, y, z), 0);
-    double b = TH(g, site_index(g, t, x + r, y, z), 0);
+    return site_index(g, t, x + r * DIR_VEC[dir][0], y + r * DIR_VEC[dir][1], z + r * DIR_VEC[dir][2]);
+}
+
+/* T(x0, t, r) = U_0*(x0, t) U_0(x0 + r e, t), Eq. (8) without the operator,
+ * for the direction e = e_dir */
+static cplx two_link(const or_lat *g, long x0, int t, int r, int dir)
+{
+    double a = TH(g, source_shift(g, x0, t, 0, 0), 0);
+    double b = TH(g, source_shift(g, x0, t, r, dir), 0);
     cplx ua = {cos(a), -sin(a)};
     cplx ub = {cos(b), sin(b)};
     return cmul(ua, ub);
@@ -629,13 +640,11 @@ static cplx two_link(const or_lat *g, long x0, int t, int r)
 
 /* the same product from the multihit means of both temporal links; used for
  * the correlator at r >= 2, where the two links share no plaquette */
-static cplx two_link_mh(const or_lat *g, long x0, int t, int r)
+static cplx two_link_mh(const or_lat *g, long x0, int t, int r, int dir)
 {
-    int L = g->L;
-    int x = (int)(x0 % L), y = (int)((x0 / L) % L), z = (int)(x0 / ((long)L * L));
     double a[2], b[2];
-    or_multihit_mean(g, site_index(g, t, x, y, z), a);
-    or_multihit_mean(g, site_index(g, t, x + r, y, z), b);
+    or_multihit_mean(g, source_shift(g, x0, t, 0, 0), a);
+    or_multihit_mean(g, source_shift(g, x0, t, r, dir), b);
     cplx ua = {a[0], -a[1]};
     cplx ub = {b[0], b[1]};
     return cmul(ua, ub);
@@ -652,8 +661,8 @@ static double field_at(const or_lat *g, int comp, long x0, int t, int rf, int d,
     return squared ? or_field_op2(g, comp, t, x + m, y + dy, z + dz) : or_field_op(g, comp, t, x + m, y + dy, z + dz);
 }
 
-/* Accumulator sizes: corr[slab][x0][r], field[slab][x0][rf][d][comp] (complex) */
-static size_t corr_len(const ml_ctx *c, int nslab) { return (size_t)nslab * c->L3 * c->n_r; }
+/* Accumulator sizes: corr[slab][x0][dir][r], field[slab][x0][rf][d][comp] (complex) */
+static size_t corr_len(const ml_ctx *c, int nslab) { return (size_t)nslab * c->L3 * c->n_dir * c->n_r; }
 static size_t field_len(const ml_ctx *c, int nslab)
 {
     return (size_t)nslab * c->L3 * c->n_rf * c->n_d * 6;
@@ -696,17 +705,19 @@ static void ml_level(ml_ctx *c, int lev, cplx *avg, cplx *favg)
 #pragma omp parallel for schedule(static)
         for (long x0 = 0; x0 < c->L3; ++x0) {
             for (int s = 0; s < nslab; ++s) {
-                for (int k = 0; k < c->n_r; ++k) {
+                int nk = c->n_dir * c->n_r;  /* (direction, r) pairs */
+                for (int k = 0; k < nk; ++k) {
                     cplx p = {1.0, 0.0};
                     if (inner) {
-                        int r = c->r_list[k];
+                        int r = c->r_list[k % c->n_r], dir = k / c->n_r;
                         for (int t = s * th; t < (s + 1) * th; ++t)
-                            p = cmul(p, c->multihit && r >= 2 ? two_link_mh(g, x0, t, r) : two_link(g, x0, t, r));
+                            p = cmul(p, c->multihit && r >= 2 ? two_link_mh(g, x0, t, r, dir)
+                                                              : two_link(g, x0, t, r, dir));
                     } else {
                         for (int ch = 0; ch < nchild; ++ch)
-                            p = cmul(p, cavg[((size_t)(s * nchild + ch) * c->L3 + x0) * c->n_r + k]);
+                            p = cmul(p, cavg[((size_t)(s * nchild + ch) * c->L3 + x0) * nk + k]);
                     }
-                    cplx *a = &avg[((size_t)s * c->L3 + x0) * c->n_r + k];
+                    cplx *a = &avg[((size_t)s * c->L3 + x0) * nk + k];
                     a->re += p.re;
                     a->im += p.im;
                 }
@@ -721,7 +732,7 @@ static void ml_level(ml_ctx *c, int lev, cplx *avg, cplx *favg)
                                 for (int ti = s * th; ti < (s + 1) * th; ++ti) {
                                     cplx p = {1.0, 0.0};
                                     for (int t = s * th; t < (s + 1) * th; ++t) {
-                                        cplx tl = two_link(g, x0, t, r);
+                                        cplx tl = two_link(g, x0, t, r, 0);
                                         if (t == ti) {
                                             double o = field_at(g, comp, x0, t, r, d, c->field_squared);
                                             tl.re *= o;
@@ -743,10 +754,11 @@ static void ml_level(ml_ctx *c, int lev, cplx *avg, cplx *favg)
                                         if (ch == ci)
                                             v = cfavg[((((size_t)sc * c->L3 + x0) * c->n_rf + f) * c->n_d + d) * 6 + comp];
                                         else {
-                                            /* plain average at the field separation r */
-                                            v = cavg[((size_t)sc * c->L3 + x0) * c->n_r + 0];
+                                            /* plain average at the field separation r along +x */
+                                            size_t base = ((size_t)sc * c->L3 + x0) * c->n_dir * c->n_r;
+                                            v = cavg[base];
                                             for (int kk = 0; kk < c->n_r; ++kk)
-                                                if (c->r_list[kk] == r) v = cavg[((size_t)sc * c->L3 + x0) * c->n_r + kk];
+                                                if (c->r_list[kk] == r) v = cavg[base + kk];
                                         }
                                         p = cmul(p, v);
                                     }
@@ -779,7 +791,10 @@ static void ml_level(ml_ctx *c, int lev, cplx *avg, cplx *favg)
  * multihit means in the correlator products (and so in the slab averages that
  * multiply a field insertion elsewhere); r = 1 and the slab holding a field
  * insertion use the links themselves.  flags & 2 inserts the squared
- * components beta (1 - Re P) of Eq. (6) instead of sqrt(beta) Im P.  Returns
+ * components beta (1 - Re P) of Eq. (6) instead of sqrt(beta) Im P.  flags & 4
+ * makes C_ML(r) the average over the six separations r e with e = +-x, +-y,
+ * +-z, each estimated by the same nested averages (the field insertion stays
+ * along +x; its slab averages use the +x lines).  Returns
  * 0, or -1 on a bad argument (slab sizes must divide T and each other). */
 int or_multilevel(or_lat *g, int n_levels, const int *th, const int *n_sub, int n_metro, int n_or,
                   int n_r, const int *r_list, double *corr_out, int n_rf, const int *rf_list,
@@ -799,6 +814,7 @@ int or_multilevel(or_lat *g, int n_levels, const int *th, const int *n_sub, int 
     memset(&c, 0, sizeof c);
     c.g = g; c.n_levels = n_levels; c.th = th; c.n_sub = n_sub;
     c.multihit = flags & 1; c.field_squared = (flags >> 1) & 1;
+    c.n_dir = (flags & 4) ? 6 : 1;
     c.n_metro = n_metro; c.n_or = n_or;
     c.n_r = n_r; c.r_list = r_list; c.n_rf = n_rf; c.rf_list = rf_list;
     c.L3 = (long)g->L * g->L * g->L;
@@ -811,16 +827,22 @@ int or_multilevel(or_lat *g, int n_levels, const int *th, const int *n_sub, int 
     cplx *B = fl ? (cplx *)malloc(fl * sizeof(cplx)) : NULL;
     ml_level(&c, 0, A, B);
 
+    int nk = c.n_dir * n_r;
     for (int k = 0; k < n_r; ++k) {
-        double sr = 0.0, si = 0.0;
-        for (long x0 = 0; x0 < c.L3; ++x0) {
-            cplx p = {1.0, 0.0};
-            for (int s = 0; s < nslab; ++s) p = cmul(p, A[((size_t)s * c.L3 + x0) * n_r + k]);
-            sr += p.re;
-            si += p.im;
+        double cr = 0.0, ci = 0.0;
+        for (int dir = 0; dir < c.n_dir; ++dir) {
+            double sr = 0.0, si = 0.0;
+            for (long x0 = 0; x0 < c.L3; ++x0) {
+                cplx p = {1.0, 0.0};
+                for (int s = 0; s < nslab; ++s) p = cmul(p, A[((size_t)s * c.L3 + x0) * nk + dir * n_r + k]);
+                sr += p.re;
+                si += p.im;
+            }
+            cr += sr / (double)c.L3;
+            ci += si / (double)c.L3;
         }
-        corr_out[2 * k] = sr / (double)c.L3;
-        corr_out[2 * k + 1] = si / (double)c.L3;
+        corr_out[2 * k] = cr / c.n_dir;
+        corr_out[2 * k + 1] = ci / c.n_dir;
     }
     for (int f = 0; f < n_rf; ++f) {
         int kr = 0;
@@ -833,7 +855,7 @@ int or_multilevel(or_lat *g, int n_levels, const int *th, const int *n_sub, int 
                     for (int s = 0; s < nslab; ++s) {
                         cplx p = B[((((size_t)s * c.L3 + x0) * n_rf + f) * c.n_d + d) * 6 + comp];
                         for (int s2 = 0; s2 < nslab; ++s2)
-                            if (s2 != s) p = cmul(p, A[((size_t)s2 * c.L3 + x0) * n_r + kr]);
+                            if (s2 != s) p = cmul(p, A[((size_t)s2 * c.L3 + x0) * nk + kr]);
                         sr += p.re;
                         si += p.im;
                     }

@@ -200,3 +200,47 @@ def test_connected_profile_of_an_ensemble_uses_ratio_of_means(oracle_mod):
     o = [np.arange(6) * 0.1, np.arange(6) * 0.3]
     conn = oracle_mod.connected_profile([f1, f2], [c1, c2], o, [1], [1])
     np.testing.assert_allclose(conn[0, 0, :, 0, 0], 3.0 / 4.0 - np.arange(6) * 0.2, atol=1e-15)
+
+
+def plain_corr_dir(th, r, axis, sign):
+    """L^-3 sum_x P*(x) P(x + sign r e_axis), axis 0, 1, 2 = x, y, z."""
+    P = polyakov_lines(th)  # [z][y][x]
+    return np.mean(np.conj(P) * np.roll(P, -sign * r, axis=2 - axis))
+
+
+def plain_corr_sym(th, r):
+    return np.mean([plain_corr_dir(th, r, a, s) for a in range(3) for s in (1, -1)])
+
+
+@pytest.mark.parametrize("levels", [([2], [1]), ([4, 2], [1, 1]), ([4, 2, 1], [1, 1, 1])])
+def test_symmetric_correlator_single_update_reduces_to_six_directions(oracle_mod, levels):
+    # one update per level: the symmetric multilevel correlator is the plain
+    # one averaged over the separations along +-x, +-y, +-z
+    L, T = 4, 8
+    g = oracle_mod.OracleLattice(L, T, 1.0, 19)
+    g.sweep(1, 2)
+    r_list = [1, 2, 3]
+    c, _, _ = g.multilevel(levels[0], levels[1], 1, 2, r_list, symmetric=True)
+    th = g.get_links()
+    for k, r in enumerate(r_list):
+        assert abs(c[k] - plain_corr_sym(th, r)) < 1e-13
+    # and the six directions differ from one another on this configuration
+    vals = [plain_corr_dir(th, 2, a, s) for a in range(3) for s in (1, -1)]
+    assert np.ptp(np.real(vals)) > 1e-3
+
+
+def test_symmetric_correlator_identity_updates_and_reality(oracle_mod):
+    # identity updates (eps = 0, no OR) keep a random configuration for any
+    # number of updates; both orientations make the average real
+    L, T = 4, 8
+    g = oracle_mod.OracleLattice(L, T, 1.0, 23, hot=True, eps=0.0)
+    th = g.get_links()
+    c, _, _ = g.multilevel([4, 2], [3, 2], 1, 0, [1, 2, 3], symmetric=True)
+    for k, r in enumerate([1, 2, 3]):
+        assert abs(c[k] - plain_corr_sym(th, r)) < 1e-13
+    g2 = oracle_mod.OracleLattice(L, T, 1.0, 23, hot=True)
+    c2, _, _ = g2.multilevel([4, 2], [3, 2], 1, 2, [1, 2, 3], symmetric=True)
+    assert np.abs(c2.imag).max() < 1e-15
+    g3 = oracle_mod.OracleLattice(L, T, 1.0, 23, hot=True)
+    c3, _, _ = g3.multilevel([4, 2], [3, 2], 1, 2, [1, 2, 3])
+    assert np.abs(c3.imag).max() > 1e-6  # one orientation alone is not real
