@@ -147,6 +147,13 @@ int u1ml_multilevel(u1ml_lattice *lat, int n_levels, const int *slab_sizes, cons
  * Eq. (7).  EINVAL on unknown bits. */
 #define U1ML_MULTIHIT 1u
 #define U1ML_FIELD_SQUARED 2u
+/* U1ML_SYMMETRIC: the multilevel correlator C(r) is averaged over the six
+ * separations r e, e = +-x, +-y, +-z, each estimated by the same nested slab
+ * averages (three times the correlator accumulators and fold work).  The -r e
+ * estimate is exactly the complex conjugate of the +r e one, so the result
+ * is the real part of the mean over the three axes (imaginary part 0).  The
+ * field insertion stays along +x and uses the +x lines. */
+#define U1ML_SYMMETRIC 4u
 int u1ml_set_estimator(u1ml_lattice *lat, unsigned flags);
 
 /* Measure the current links and return the latest multilevel results.
@@ -207,7 +214,8 @@ int u1ml_set_pass_id(u1ml_lattice *lat, uint64_t pass_id);
  * per class pass (no fused or captured schedule).  flags & 2 makes the field
  * insertion use the general contraction (both transforms stored, then
  * contracted by tiles) even where the fused one applies; results agree to
- * rounding. */
+ * rounding.  flags & 4 folds the innermost slab averages with the per-site
+ * kernel instead of the row-staged one (same bits). */
 int u1ml_set_debug(u1ml_lattice *lat, unsigned flags, size_t capacity);
 /* Copy the log out: *n_bytes = bytes recorded; copies min(cap, *n_bytes). */
 int u1ml_get_accept_log(u1ml_lattice *lat, uint8_t *out, size_t cap, size_t *n_bytes);

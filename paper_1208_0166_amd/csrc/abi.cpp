@@ -161,6 +161,7 @@ struct Engine {
   size_t log_cap = 0, log_used = 0;
   bool debug = false;
   bool field_general = false;  // u1ml_set_debug flags & 2
+  bool fold_general = false;   // u1ml_set_debug flags & 4
   unsigned estimator = 0;      // u1ml_set_estimator flags
   // measurement scratch
   DevBuf partial, rows, poly, poly_off, row_begin, red_out, rvals_tmp;
@@ -539,11 +540,14 @@ struct Engine {
     for (int i = 0; i < n_lats; ++i) {
       const LatDesc& d = h_lats[i];
       MLDesc& md = m.h_mls[i];
-      md.nR = (int)rl[i].size();
+      md.n_r = (int)rl[i].size();
+      md.n_axes = (estimator & U1ML_SYMMETRIC) ? 3 : 1;
+      md.nR = md.n_axes * md.n_r;
       md.r_off = (int)rv.size();
-      for (int r : rl[i]) rv.push_back(r);
-      m.nR[i] = md.nR;
-      m.max_r = std::max(m.max_r, md.nR);
+      for (int a = 0; a < md.n_axes; ++a)
+        for (int r : rl[i]) rv.push_back(r | a << kRAxisShift);
+      m.nR[i] = md.n_r;
+      m.max_r = std::max(m.max_r, md.n_r);
       for (int l = 0; l < n_levels; ++l) md.ns[l] = d.T / th[l];
       md.ell = ell;
       ell += (uint64_t)n_samples_kept * md.ns[inner] * d.L3;
@@ -620,13 +624,13 @@ struct Engine {
   int ml_fold(int child, int parent, int sample_base) {
     MLState& m = ml;
     const int inner = m.n_levels - 1;
-    if (child == inner) {
+    if (child == inner && !fold_general) {
       int max_items = 0;
       size_t max_lds = 0;
       for (int i = 0; i < n_lats; ++i) {
         const int nsp = parent == m.n_levels ? 1 : m.h_mls[i].ns[parent];
         const int children = m.h_mls[i].ns[child] / nsp;
-        max_items = std::max(max_items, h_lats[i].L * m.h_mls[i].nR);
+        max_items = std::max(max_items, h_lats[i].L * m.h_mls[i].n_r);
         max_lds = std::max(max_lds, (size_t)(m.h_mls[i].multihit ? 2 : 1) * children * m.n[child] * h_lats[i].L *
                                         sizeof(double2));
       }
@@ -634,7 +638,7 @@ struct Engine {
         std::vector<int> rows;
         for (int i = 0; i < n_lats; ++i) {
           const int nsp = parent == m.n_levels ? 1 : m.h_mls[i].ns[parent];
-          rows.push_back(nsp * h_lats[i].L * h_lats[i].L);
+          rows.push_back(nsp * m.h_mls[i].n_axes * h_lats[i].L * h_lats[i].L);
         }
         Table* t;
         U1_TRY(table(rows, 1, &t));
@@ -824,6 +828,7 @@ struct Engine {
     ml.field_valid = ml.field;
     ml.shape.assign(1, ml.field ? 1 : 0);
     ml.shape.push_back((estimator & U1ML_FIELD_SQUARED) ? 1 : 0);
+    ml.shape.push_back((estimator & U1ML_SYMMETRIC) ? 1 : 0);
     for (auto& v : rl) {
       ml.shape.push_back(-(long long)v.size());
       for (int r : v) ml.shape.push_back(r);
@@ -1100,7 +1105,7 @@ int u1ml_set_pass_id(u1ml_lattice* lat, uint64_t pass_id) {
 }
 
 static int set_estimator(Engine& e, unsigned flags) {
-  if (flags & ~(U1ML_MULTIHIT | U1ML_FIELD_SQUARED)) return fail(U1ML_EINVAL, "unknown estimator flags");
+  if (flags & ~(U1ML_MULTIHIT | U1ML_FIELD_SQUARED | U1ML_SYMMETRIC)) return fail(U1ML_EINVAL, "unknown estimator flags");
   U1_TRY(e.set_device());
   if (e.estimator != flags) {
     U1_HIP(hipStreamSynchronize(e.stream));
@@ -1126,9 +1131,10 @@ int u1ml_set_debug(u1ml_lattice* lat, unsigned flags, size_t capacity) {
   Engine& e = lat->e;
   U1_TRY(e.set_device());
   U1_HIP(hipStreamSynchronize(e.stream));
-  if (e.field_general != ((flags & 2u) != 0)) {
-    e.drop_graphs();  // captured schedules hold the other contraction
+  if (e.field_general != ((flags & 2u) != 0) || e.fold_general != ((flags & 4u) != 0)) {
+    e.drop_graphs();  // captured schedules hold the other kernels
     e.field_general = (flags & 2u) != 0;
+    e.fold_general = (flags & 4u) != 0;
   }
   if (flags & 1u) {
     U1_TRY(e.log.ensure(capacity));

@@ -52,10 +52,13 @@ struct MLDesc {
   uint64_t ell_mh;               // double2: the same layout, products of multihit means (multihit only)
   uint64_t acc[kMaxLevels + 1];  // double2: level l < inner: [ns_l][L3][nR]; index n_levels = top [L3][nR]
   int ns[kMaxLevels];            // slabs per level
-  int nR;                        // separations
-  int r_off;                     // r values at rvals[r_off ...]
+  int nR;                        // stored separations: n_axes * n_r, axis slowest
+  int n_r;                       // separations of the r list
+  int n_axes;                    // 1: along x; 3: along x, y, z (symmetric correlator)
+  int r_off;                     // separations at rvals[r_off ...], encoded r | axis << 16
   int multihit;                  // correlator lines at r >= 2 from ell_mh
 };
+constexpr int kRAxisShift = 16;  // rvals entry = r | axis << kRAxisShift
 
 // plaquette sum, the six field sums and the six squared-component sums:
 // partial[blk][kPlaqFieldWidth], reduced to one such row per lattice

@@ -246,7 +246,7 @@ __global__ void ml_fold_kernel(const LatDesc* __restrict__ lats, const MLDesc* _
   double2 prod[kFoldR];
 #pragma unroll
   for (int j = 0; j < kFoldR; ++j) {
-    xr[j] = j < kn ? shift_x(d, x0, rvals[m.r_off + k0 + j]) : x0;
+    xr[j] = j < kn ? shift_axis(d, x0, rvals[m.r_off + k0 + j]) : x0;
     prod[j] = make_double2(1.0, 0.0);
   }
   const double inv = 1.0 / (double)n_child;
@@ -267,7 +267,7 @@ __global__ void ml_fold_kernel(const LatDesc* __restrict__ lats, const MLDesc* _
         for (int j = 0; j < kFoldR; ++j) {
           if (j < kn) {
             // multihit lines for r >= 2 (the two lines share no plaquette)
-            const bool mh = m.multihit && rvals[m.r_off + k0 + j] >= 2;
+            const bool mh = m.multihit && (rvals[m.r_off + k0 + j] & 0xffff) >= 2;
             const double2 a = mh ? uh : u, v = mh ? eh[xr[j]] : e[xr[j]];
             avg[j].x += a.x * v.x + a.y * v.y;
             avg[j].y += a.x * v.y - a.y * v.x;
@@ -299,13 +299,15 @@ __global__ void ml_fold_kernel(const LatDesc* __restrict__ lats, const MLDesc* _
   }
 }
 
-// The same fold for innermost children, one block per (parent slab S, x-row
-// (y, z)): the rows of all stored samples of all children of S are staged in
-// LDS at once (children * n_child * L values, twice with multihit), so every
-// time line is read from memory once instead of once per separation.  Threads
-// own up to kFoldItems items (x0, k) with k fastest (so the accumulator
-// updates are contiguous); the sample and child order of the sums is that of
-// ml_fold_kernel, so both give the same bits.
+// The same fold for innermost children, one block per (parent slab S, axis a,
+// row along a): the rows of all stored samples of all children of S are
+// staged in LDS at once (children * n_child * L values, twice with multihit),
+// so every time line is read from memory once instead of once per
+// separation.  Threads own up to kFoldItems items (position j along the row,
+// separation k of the axis) with k fastest (so the accumulator updates are
+// contiguous); the sample and child order of the sums is that of
+// ml_fold_kernel, so both give the same bits.  Rows along x are contiguous;
+// rows along y and z are strided by L and L^2.
 constexpr int kFoldItems = 4;
 constexpr size_t kFoldLds = 49152;  // bytes of staged rows per block
 __global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls,
@@ -321,11 +323,16 @@ __global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDe
   const int L = d.L, L2 = L * L;
   const int ns_child = mp->ns[child_level];
   const int ns_parent = parent_level == n_levels ? 1 : mp->ns[parent_level];
-  const int nR = mp->nR, r_off = mp->r_off, multihit = mp->multihit;
+  const int nR = mp->nR, n_r = mp->n_r, n_axes = mp->n_axes, r_off = mp->r_off, multihit = mp->multihit;
   const uint64_t ell = mp->ell, ell_mh = mp->ell_mh, acc_parent = mp->acc[parent_level];
   const int children = ns_child / ns_parent;
-  const int S = bk.y / L2, row = bk.y - S * L2;
-  const int nitems = L * nR;
+  const int S = bk.y / (n_axes * L2), rem = bk.y - S * n_axes * L2;
+  const int axis = rem / L2, row = rem - axis * L2;
+  // row (a, b) across the axis: x-rows (y, z), y-rows (x, z), z-rows (x, y)
+  const int ra = row % L, rb = row / L;
+  const int stride = axis == 0 ? 1 : (axis == 1 ? L : L2);
+  const int base = axis == 0 ? row * L : (axis == 1 ? rb * L2 + ra : rb * L + ra);
+  const int nitems = L * n_r;
   const int per_child = n_child * L;
   // rows of the plain lines, then (multihit) rows of the multihit lines
   const int staged = children * per_child;
@@ -333,7 +340,7 @@ __global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDe
     const int h = e / staged, ee = e - h * staged;
     const int c = ee / per_child, i = (ee / L) % n_child, x = ee % L;
     rowbuf[e] = mlbuf[(h ? ell_mh : ell) + ((size_t)(sample_base + i) * ns_child + S * children + c) * d.L3 +
-                      (size_t)row * L + x];
+                      (size_t)base + (size_t)x * stride];
   }
   __syncthreads();
   const double inv = 1.0 / (double)n_child;
@@ -341,8 +348,8 @@ __global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDe
   for (int j = 0; j < kFoldItems; ++j) {
     const int item = (int)threadIdx.x + j * (int)blockDim.x;
     if (item < nitems) {
-      const int x0 = item / nR, k = item - x0 * nR;
-      const int r = rvals[r_off + k];
+      const int x0 = item / n_r, k = axis * n_r + (item - x0 * n_r);
+      const int r = rvals[r_off + k] & 0xffff;
       int xr = x0 + r;
       xr -= xr >= L ? L : 0;
       // multihit lines for r >= 2 (the two lines share no plaquette)
@@ -358,33 +365,39 @@ __global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDe
         }
         prod = cmul(prod, make_double2(avg.x * inv, avg.y * inv));
       }
-      double2* pp = accbuf + acc_parent + ((size_t)S * d.L3 + (size_t)row * L + x0) * nR + k;
+      double2* pp = accbuf + acc_parent + ((size_t)S * d.L3 + (size_t)base + (size_t)x0 * stride) * nR + k;
       pp->x += prod.x;
       pp->y += prod.y;
     }
   }
 }
 
-// out[(lat * max_r + k) * 2 + {0,1}] = L^-3 sum_x0 acc_top[x0][k]
+// out[(lat * max_r + k) * 2 + {0,1}] = L^-3 sum_x0 acc_top[x0][k]; with three
+// axes the mean over the axes of the real part: the separation -r e
+// estimates the complex conjugate of +r e exactly (every factor is), so the
+// real part is the mean of both orientations.
 __global__ void ml_final_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls, int max_r,
                                 int top_level, const double2* __restrict__ accbuf, double* __restrict__ out) {
   __shared__ double sh[16];
   const int lat = blockIdx.x, k = blockIdx.y;
   const LatDesc d = lats[lat];
   const MLDesc m = mls[lat];
-  if (k >= m.nR) return;  // uniform per block
+  if (k >= m.n_r) return;  // uniform per block
   double re = 0.0, im = 0.0;
   const double2* a = accbuf + m.acc[top_level];
-  for (int x0 = threadIdx.x; x0 < d.L3; x0 += blockDim.x) {
-    const double2 v = a[(size_t)x0 * m.nR + k];
-    re += v.x;
-    im += v.y;
+  for (int ax = 0; ax < m.n_axes; ++ax) {
+    double sr = 0.0, si = 0.0;
+    for (int x0 = threadIdx.x; x0 < d.L3; x0 += blockDim.x) {
+      const double2 v = a[(size_t)x0 * m.nR + ax * m.n_r + k];
+      sr += v.x;
+      si += v.y;
+    }
+    re += block_sum(sr, sh) / (double)d.L3;
+    im += block_sum(si, sh) / (double)d.L3;
   }
-  re = block_sum(re, sh);
-  im = block_sum(im, sh);
   if (threadIdx.x == 0) {
-    out[((size_t)lat * max_r + k) * 2] = re / (double)d.L3;
-    out[((size_t)lat * max_r + k) * 2 + 1] = im / (double)d.L3;
+    out[((size_t)lat * max_r + k) * 2] = re / (double)m.n_axes;
+    out[((size_t)lat * max_r + k) * 2 + 1] = m.n_axes == 1 ? im : 0.0;
   }
 }
 

@@ -89,6 +89,17 @@ __device__ __forceinline__ int shift_x(const LatDesc& d, int x3, int r) {
   return x3 - x + xr;
 }
 
+// x3 + r e_axis (periodic) for an encoded separation v = r | axis << 16,
+// axis 0, 1, 2 = x, y, z; x3 = (z L + y) L + x
+__device__ __forceinline__ int shift_axis(const LatDesc& d, int x3, int v) {
+  const int r = v & 0xffff, axis = v >> 16;
+  const int stride = axis == 0 ? 1 : (axis == 1 ? d.L : d.L * d.L);
+  const int c = (x3 / stride) % d.L;
+  int cr = c + r;
+  cr -= (cr >= d.L) ? d.L : 0;
+  return x3 + (cr - c) * stride;
+}
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }

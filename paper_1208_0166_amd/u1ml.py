@@ -305,15 +305,16 @@ def set_pass_id(lat: Lattice, pass_id: int):
 
 MULTIHIT = 1
 FIELD_SQUARED = 2
+SYMMETRIC = 4
 
 
-def _estimator_flags(multihit: bool, field_squared: bool) -> int:
-    return (MULTIHIT if multihit else 0) | (FIELD_SQUARED if field_squared else 0)
+def _estimator_flags(multihit: bool, field_squared: bool, symmetric: bool) -> int:
+    return (MULTIHIT if multihit else 0) | (FIELD_SQUARED if field_squared else 0) | (SYMMETRIC if symmetric else 0)
 
 
-def set_estimator(lat: Lattice, multihit: bool = False, field_squared: bool = False):
+def set_estimator(lat: Lattice, multihit: bool = False, field_squared: bool = False, symmetric: bool = False):
     """Estimator options of the following multilevel runs (u1ml_set_estimator)."""
-    _check(load_library().u1ml_set_estimator(lat.handle, _estimator_flags(multihit, field_squared)))
+    _check(load_library().u1ml_set_estimator(lat.handle, _estimator_flags(multihit, field_squared, symmetric)))
 
 
 def set_debug(lat: Lattice, flags: int, capacity: int = 0):
@@ -425,8 +426,8 @@ def batch_multilevel(b: Batch, slab_sizes, n_sub, n_metro: int = 1, n_or: int = 
     b._n_r, b._n_rf = [len(r)] * len(b.L), len(rf_list)
 
 
-def batch_set_estimator(b: Batch, multihit: bool = False, field_squared: bool = False):
-    _check(load_library().u1ml_batch_set_estimator(b.handle, _estimator_flags(multihit, field_squared)))
+def batch_set_estimator(b: Batch, multihit: bool = False, field_squared: bool = False, symmetric: bool = False):
+    _check(load_library().u1ml_batch_set_estimator(b.handle, _estimator_flags(multihit, field_squared, symmetric)))
 
 
 def batch_ensemble_reset(b: Batch):

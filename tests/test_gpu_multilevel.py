@@ -329,3 +329,62 @@ def test_field_squared_full_size_24_identity(prec):
         close_rel(f[i], field_identity(th, beta, r, squared=True), FIELD_REL[prec])
     # both sums are taken in FP64 from the stored links at either precision
     assert abs(sum(obs["field2_mean"]) - 6 * beta * (1 - obs["plaquette"])) < 1e-12
+
+
+@pytest.mark.parametrize("levels,n_sub,L,T,mh,rf,debug", [
+    ([4, 2], [2, 3], 4, 8, False, [2], 0),
+    ([4, 2], [2, 3], 4, 8, True, [2, 3], 0),
+    ([4, 2], [2, 3], 4, 8, True, [2, 3], 4),
+    ([2], [4], 6, 4, False, [], 0),
+    ([2], [4], 6, 4, False, [], 4),
+    ([4, 2, 1], [2, 2, 2], 4, 8, False, [], 0),
+    ([4, 2], [2, 2], 6, 8, False, [3], 2),
+])
+def test_symmetric_correlator_parity(oracle_mod, levels, n_sub, L, T, mh, rf, debug):
+    # correlator averaged over +-x, +-y, +-z against the oracle's six
+    # literal directions; debug 4 takes the per-site fold, 2 the general field
+    r_list = [1, 2, 3]
+    say(f"[gpu] symmetric correlator levels={levels} L={L} mh={mh} rf={rf} debug={debug}")
+    o = oracle_mod.OracleLattice(L, T, 1.05, 91, hot=True)
+    g = u1ml.init_lattice(L, T, 1.05, 91)
+    u1ml.set_estimator(g, multihit=mh, symmetric=True)
+    if debug:
+        u1ml.set_debug(g, debug)
+    o.sweep(1, 3)
+    u1ml.sweep(g, 1, 3)
+    c_o, f_o, _ = o.multilevel(levels, n_sub, 1, 3, r_list, rf_list=rf, multihit=mh, symmetric=True)
+    u1ml.multilevel(g, levels, n_sub, 1, 3, r_list, rf_list=rf)
+    _, c_g, f_g = u1ml.measure(g, observables=False, correlator=True, field_profile=bool(rf))
+    np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
+    assert np.all(c_g.imag == 0.0)
+    close_rel(c_g.real, c_o.real)
+    assert np.abs(c_o.imag).max() < 1e-15
+    if rf:
+        close_rel(f_g, f_o)
+
+
+def test_symmetric_batch_and_one_update_identity(oracle_mod):
+    # uneven batch (rows of different lengths in one fold launch), then the
+    # one-update identity at 24^4 against numpy's six directions
+    Ls, seeds = [4, 6, 8], [92, 93, 94]
+    say("[gpu] symmetric batch vs oracle")
+    b = u1ml.batch_create(Ls, [8, 8, 8], [1.0] * 3, seeds)
+    u1ml.batch_set_estimator(b, symmetric=True)
+    u1ml.batch_multilevel(b, [4, 2], [2, 2], 1, 2, [1, 2, 3])
+    for i, (L, s) in enumerate(zip(Ls, seeds)):
+        o = oracle_mod.OracleLattice(L, 8, 1.0, s)
+        c_o, _, _ = o.multilevel([4, 2], [2, 2], 1, 2, [1, 2, 3], symmetric=True)
+        _, c_g, _ = u1ml.batch_measure(b, i, correlator=True)
+        np.testing.assert_array_equal(u1ml.batch_get_links(b, i), o.get_links())
+        close_rel(c_g.real, c_o.real)
+    from tests.test_oracle_multilevel import plain_corr_sym
+    say("[gpu] symmetric one-update identity 24^4")
+    g = u1ml.init_lattice(24, 24, 1.0, 95, start=u1ml.COLD)
+    u1ml.set_estimator(g, symmetric=True)
+    u1ml.sweep(g, 1, 3)
+    rl = [1, 2, 5, 12]
+    u1ml.multilevel(g, [4, 2], [1, 1], 1, 3, rl)
+    _, c, _ = u1ml.measure(g, observables=False, correlator=True)
+    th = u1ml.get_links(g)
+    ref = np.array([plain_corr_sym(th, r) for r in rl])
+    assert np.abs(c - ref.real).max() < 1e-12 * np.abs(ref).max()
