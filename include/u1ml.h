@@ -76,8 +76,9 @@ typedef struct u1ml_options {
     size_t dev_bytes; /* its size; must be >= u1ml_link_bytes(L, T, precision) */
     int block;        /* threads per block of the update kernels; 0 = tuned default */
     int no_graphs;    /* 0 (default): repeated sweep / multilevel calls with the same
-                         arguments replay a HIP graph captured on the first call;
-                         1: always launch kernel by kernel */
+                         arguments replay a HIP graph captured on the first call
+                         (multilevel runs of more than 16384 compound sweeps in
+                         all are never captured); 1: always launch kernel by kernel */
 } u1ml_options;
 
 typedef struct u1ml_observables {

@@ -46,6 +46,10 @@ constexpr double kMaxAngle = 64.0;
 // scratch for the field contraction, per engine
 constexpr size_t kFieldScratchBytes = 256u << 20;
 constexpr size_t kMaxGraphs = 16;
+// multilevel runs of more sublattice updates than this launch kernel by
+// kernel: capturing millions of launches costs more host time and memory
+// than the graph saves
+constexpr long long kMaxCapturedUpdates = 1 << 14;
 // the mediator-plane transform keeps (L + L^2) complex values in 64 KiB of LDS
 constexpr int kMaxFieldL = 62;
 
@@ -326,8 +330,8 @@ struct Engine {
   // eagerly (allocating whatever it needs) and then captures a second copy
   // of the same launch sequence for later calls.
   template <class Fn>
-  int run_captured(const std::vector<long long>& key, Fn fn) {
-    const bool can = use_graphs && !debug && !prof[0] && !prof[1];
+  int run_captured(const std::vector<long long>& key, Fn fn, bool capture = true) {
+    const bool can = capture && use_graphs && !debug && !prof[0] && !prof[1];
     if (can) {
       auto it = graphs.find(key);
       if (it != graphs.end()) {
@@ -820,10 +824,19 @@ struct Engine {
       ml.key = key;
     }
     ml.valid = ml.field_valid = false;
-    U1_TRY(run_captured(key, [&]() -> int {
-      for (int s = 0; s < n_sweeps_before; ++s) U1_TRY(sweep(n_metro, n_or, 0));
-      return ml_run();
-    }));
+    // compound sweeps of the run: sum over levels of the product of n_sub
+    long long n_updates = n_sweeps_before, prod = 1;
+    for (int l = 0; l < n_levels; ++l) {
+      prod *= n_sub[l];
+      n_updates += prod;
+    }
+    U1_TRY(run_captured(
+        key,
+        [&]() -> int {
+          for (int s = 0; s < n_sweeps_before; ++s) U1_TRY(sweep(n_metro, n_or, 0));
+          return ml_run();
+        },
+        n_updates <= kMaxCapturedUpdates));
     ml.valid = true;
     ml.field_valid = ml.field;
     ml.shape.assign(1, ml.field ? 1 : 0);
