@@ -216,7 +216,13 @@ int u1ml_set_pass_id(u1ml_lattice *lat, uint64_t pass_id);
  * insertion use the general contraction (both transforms stored, then
  * contracted by tiles) even where the fused one applies; results agree to
  * rounding.  flags & 4 folds the innermost slab averages with the per-site
- * kernel instead of the row-staged one (same bits). */
+ * kernel instead of the row-staged one (same bits).  flags & 8 runs every
+ * two-level multilevel with field insertion in two passes (the mode taken
+ * by itself when storing every inner sample would exceed 16 GiB): a first
+ * pass for the top-level averages, then the same updates again from the
+ * restored links, contracting each outer iteration's samples as it
+ * completes; same links, pass ids and correlator bits, field to rounding,
+ * twice the updates. */
 int u1ml_set_debug(u1ml_lattice *lat, unsigned flags, size_t capacity);
 /* Copy the log out: *n_bytes = bytes recorded; copies min(cap, *n_bytes). */
 int u1ml_get_accept_log(u1ml_lattice *lat, uint8_t *out, size_t cap, size_t *n_bytes);

@@ -45,6 +45,14 @@ int fail(int code, const std::string& msg) {
 constexpr double kMaxAngle = 64.0;
 // scratch for the field contraction, per engine
 constexpr size_t kFieldScratchBytes = 256u << 20;
+// A two-level run with field insertion keeps every inner sample's time lines
+// and field slab sums until the end.  Beyond this many bytes of such storage
+// the run is replayed instead: a first pass computes the top-level averages,
+// a second pass repeats the identical update sequence (counter-based random
+// numbers, restored links and pass ids) and contracts each outer iteration's
+// samples as soon as that iteration completes, so only one outer iteration's
+// samples are stored.
+constexpr size_t kFieldStoreLimit = 16ull << 30;
 constexpr size_t kMaxGraphs = 16;
 // multilevel runs of more sublattice updates than this launch kernel by
 // kernel: capturing millions of launches costs more host time and memory
@@ -117,6 +125,9 @@ struct MLState {
   std::vector<uint64_t> fout_off;  // per lattice, double2 elements
   DevBuf fls, fbuf, fout, scratch;
   size_t scratch_elems = 0;
+  bool replay = false;        // two-pass run, one outer iteration stored
+  bool store_field = true;    // ml_sample stores the field slab sums
+  DevBuf links_backup, pass_backup;
   // shape of the last completed run (r lists, field separations, operator set)
   std::vector<long long> shape;
   unsigned run_flags = 0;  // estimator flags of that run
@@ -166,6 +177,8 @@ struct Engine {
   bool debug = false;
   bool field_general = false;  // u1ml_set_debug flags & 2
   bool fold_general = false;   // u1ml_set_debug flags & 4
+  bool force_replay = false;   // u1ml_set_debug flags & 8
+  bool log_off = false;        // no accept-log recording (replayed updates)
   unsigned estimator = 0;      // u1ml_set_estimator flags
   // measurement scratch
   DevBuf partial, rows, poly, poly_off, row_begin, red_out, rvals_tmp;
@@ -303,7 +316,7 @@ struct Engine {
       for (int mu = 0; mu < 4; ++mu)
         for (int p = 0; p < 2; ++p) {
           uint8_t* lp = nullptr;
-          if (debug && n_lats == 1) {
+          if (debug && n_lats == 1 && !log_off) {
             size_t want = (size_t)h_lats[0].V2 * n_metro;
             if (log_used + want <= log_cap) {
               lp = log.as<uint8_t>() + log_used;
@@ -535,7 +548,17 @@ struct Engine {
     m.field = !rf.empty();
     const int inner = n_levels - 1;
     const int n_outer = n_levels == 2 ? n_sub[0] : 1;
-    const int n_samples_kept = m.field ? n_outer * n_sub[inner] : n_sub[inner];
+    // bytes of stored samples if every outer iteration is kept
+    size_t store_all = 0;
+    if (m.field && n_levels == 2)
+      for (auto& d : h_lats) {
+        const size_t ns_in = d.T / th[inner];
+        const size_t lines = (estimator & U1ML_MULTIHIT) ? 2 : 1;
+        store_all += (size_t)n_outer * n_sub[inner] * ns_in * d.L3 * (6 * sizeof(double) + lines * sizeof(double2));
+      }
+    m.replay = m.field && n_levels == 2 && (force_replay || store_all > kFieldStoreLimit);
+    const int n_stored = m.replay ? 1 : n_outer;
+    const int n_samples_kept = m.field ? n_stored * n_sub[inner] : n_sub[inner];
     m.h_mls.assign(n_lats, MLDesc{});
     m.nR.assign(n_lats, 0);
     std::vector<int> rv;
@@ -591,6 +614,7 @@ struct Engine {
       }
       fp.n_levels = n_levels;
       fp.n_outer = n_outer;
+      fp.n_stored = n_stored;
       fp.n_inner = n_sub[inner];
       m.h_fls.assign(n_lats, FieldLat{});
       m.fout_off.assign(n_lats, 0);
@@ -604,9 +628,9 @@ struct Engine {
         fl.oall = fb;
         fb += (uint64_t)n_samples_kept * 6 * fl.ns * L3;
         fl.tavg = fb;
-        fb += 2ull * n_outer * fl.ns * L3 * fp.n_rf;
+        fb += 2ull * n_stored * fl.ns * L3 * fp.n_rf;
         fl.w = fb;
-        fb += 2ull * n_outer * fl.ns * L3 * fp.n_rf;
+        fb += 2ull * n_stored * fl.ns * L3 * fp.n_rf;
         fl.g = fb;
         fb += 2ull * fp.n_rf * 12 * L2;
         m.fout_off[i] = fo;
@@ -676,7 +700,7 @@ struct Engine {
     U1_TRY(table(it, 256, &t));
     U1_HIP(launch_ml_lines(prec, links.p, lats.as<LatDesc>(), m.mls.as<MLDesc>(), bt(t), m.th[inner], sample,
                            m.mlbuf.as<double2>(), stream));
-    if (m.field)
+    if (m.field && m.store_field)
       U1_HIP(launch_field_o(prec, links.p, lats.as<LatDesc>(), m.fls.as<FieldLat>(), bt(t), m.th[inner], sample,
                             (estimator & U1ML_FIELD_SQUARED) != 0, m.fbuf.as<double>(), stream));
     return U1ML_OK;
@@ -690,15 +714,65 @@ struct Engine {
     for (int it = 0; it < m.n[l]; ++it) {
       U1_TRY(sweep(m.n_metro, m.n_or, m.th[l]));
       const int mo = l == 0 ? it : outer_it;
+      // samples of every outer iteration are kept for the field contraction,
+      // unless the run is replayed
+      const bool keep = m.field && !m.replay;
       if (l == inner) {
-        const int base = (m.field && m.n_levels == 2) ? outer_it * m.n[inner] : 0;
+        const int base = (keep && m.n_levels == 2) ? outer_it * m.n[inner] : 0;
         U1_TRY(ml_sample(base + it));
       } else {
         U1_TRY(ml_level(l + 1, mo));
-        const int base = (m.field && l + 1 == inner) ? mo * m.n[inner] : 0;
+        const int base = (keep && l + 1 == inner) ? mo * m.n[inner] : 0;
         U1_TRY(ml_fold(l + 1, l, base));
       }
     }
+    return U1ML_OK;
+  }
+
+  int field_contract(bool zero_g, bool finalize) {
+    MLState& m = ml;
+    for (int i = 0; i < n_lats; ++i)
+      U1_HIP(launch_field_contract(lats.as<LatDesc>() + i, m.mls.as<MLDesc>() + i, m.fls.as<FieldLat>() + i,
+                                   m.h_fls[i], m.fp, h_lats[i].L, m.mlbuf.as<double2>(), m.accbuf.as<double2>(),
+                                   m.fbuf.as<double>(), m.scratch.as<double2>(), m.scratch_elems,
+                                   m.fout.as<double2>() + m.fout_off[i], field_general, zero_g, finalize, stream));
+    return U1ML_OK;
+  }
+
+  // Two-level run with field insertion in two passes over the same update
+  // sequence: the first folds the correlator averages (the weights of every
+  // insertion need the final top-level averages), the second, from the
+  // restored links and pass ids, contracts each outer iteration's samples
+  // with those weights as soon as the iteration completes.
+  int ml_run_replay() {
+    MLState& m = ml;
+    const size_t lb = link_elems * elem_size(), pb = n_lats * sizeof(uint64_t);
+    U1_TRY(m.links_backup.ensure(lb));
+    U1_TRY(m.pass_backup.ensure(pb));
+    U1_HIP(hipMemcpyAsync(m.links_backup.p, links.p, lb, hipMemcpyDeviceToDevice, stream));
+    U1_HIP(hipMemcpyAsync(m.pass_backup.p, pass_ids.p, pb, hipMemcpyDeviceToDevice, stream));
+    const std::vector<uint64_t> ids = h_pass_ids;
+    m.store_field = false;
+    const int rc = ml_level(0, 0);
+    m.store_field = true;
+    U1_TRY(rc);
+    U1_HIP(hipMemcpyAsync(links.p, m.links_backup.p, lb, hipMemcpyDeviceToDevice, stream));
+    U1_HIP(hipMemcpyAsync(pass_ids.p, m.pass_backup.p, pb, hipMemcpyDeviceToDevice, stream));
+    h_pass_ids = ids;
+    log_off = true;  // the accept log holds the first pass
+    for (int it = 0; it < m.n[0] && !rc; ++it) {
+      int r2 = sweep(m.n_metro, m.n_or, m.th[0]);
+      for (int i = 0; i < m.n[1] && !r2; ++i) {
+        r2 = sweep(m.n_metro, m.n_or, m.th[1]);
+        if (!r2) r2 = ml_sample(i);
+      }
+      if (!r2) r2 = field_contract(it == 0, it == m.n[0] - 1);
+      if (r2) {
+        log_off = false;
+        return r2;
+      }
+    }
+    log_off = false;
     return U1ML_OK;
   }
 
@@ -706,14 +780,12 @@ struct Engine {
   int ml_run() {
     MLState& m = ml;
     U1_HIP(launch_ml_zero(m.accbuf.as<double2>(), m.acc_elems, stream));
-    U1_TRY(ml_level(0, 0));
-    if (m.field) {
+    if (m.replay) {
+      U1_TRY(ml_run_replay());
+    } else {
+      U1_TRY(ml_level(0, 0));
       // the weights need the top-level averages: contract before the top fold
-      for (int i = 0; i < n_lats; ++i)
-        U1_HIP(launch_field_contract(lats.as<LatDesc>() + i, m.mls.as<MLDesc>() + i, m.fls.as<FieldLat>() + i,
-                                     m.h_fls[i], m.fp, h_lats[i].L, m.mlbuf.as<double2>(), m.accbuf.as<double2>(),
-                                     m.fbuf.as<double>(), m.scratch.as<double2>(), m.scratch_elems,
-                                     m.fout.as<double2>() + m.fout_off[i], field_general, stream));
+      if (m.field) U1_TRY(field_contract(true, true));
     }
     U1_TRY(ml_fold(0, m.n_levels, 0));
     U1_HIP(launch_ml_final(lats.as<LatDesc>(), m.mls.as<MLDesc>(), n_lats, m.max_r, m.n_levels,
@@ -1144,10 +1216,13 @@ int u1ml_set_debug(u1ml_lattice* lat, unsigned flags, size_t capacity) {
   Engine& e = lat->e;
   U1_TRY(e.set_device());
   U1_HIP(hipStreamSynchronize(e.stream));
-  if (e.field_general != ((flags & 2u) != 0) || e.fold_general != ((flags & 4u) != 0)) {
+  if (e.field_general != ((flags & 2u) != 0) || e.fold_general != ((flags & 4u) != 0) ||
+      e.force_replay != ((flags & 8u) != 0)) {
     e.drop_graphs();  // captured schedules hold the other kernels
     e.field_general = (flags & 2u) != 0;
     e.fold_general = (flags & 4u) != 0;
+    e.force_replay = (flags & 8u) != 0;
+    e.ml.key.clear();  // the multilevel workspace depends on the replay choice
   }
   if (flags & 1u) {
     U1_TRY(e.log.ensure(capacity));

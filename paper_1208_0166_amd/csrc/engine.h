@@ -110,6 +110,8 @@ struct FieldParams {
   int rf_k[32];  // index of each rf in the lattice's r list
   int n_levels;  // 1 or 2
   int n_outer;   // n_0 for two levels, 1 for one level
+  int n_stored;  // outer iterations whose samples are stored: n_outer, or 1 when
+                 // every outer iteration is contracted as it completes (replay)
   int n_inner;   // samples per inner run
 };
 // squared = true stores the squared components of Eq. (6) instead of Eq. (5)
@@ -123,10 +125,13 @@ hipError_t launch_ens_omean(const LatDesc* lats, const double* red, int width, i
                             hipStream_t st);
 hipError_t launch_ens_connected(const double2* fsum, const double2* csum, const double* osum, FieldParams fp, int L,
                                 double inv_n, double2* conn, hipStream_t st);
-// contraction of all stored samples of one lattice into F [n_rf][2][6][L][L]
-// (complex); general = true takes the stored-transform path for any geometry
+// contraction of all stored samples of one lattice into the Fourier-space
+// accumulator (cleared first if zero_g) and, if finalize, into F
+// [n_rf][2][6][L][L] (complex); general = true takes the stored-transform path
+// for any geometry
 hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,
                                  FieldParams fp, int L, const double2* mlbuf, const double2* accbuf, double* fbuf,
-                                 double2* scratch, size_t scratch_elems, double2* F, bool general, hipStream_t st);
+                                 double2* scratch, size_t scratch_elems, double2* F, bool general, bool zero_g,
+                                 bool finalize, hipStream_t st);
 
 }  // namespace u1ml

@@ -18,7 +18,7 @@ namespace u1ml {
 namespace {
 
 // tavg[((m * ns + s) * L3 + x0) * n_rf + f] = average over the n_inner samples
-// of outer iteration m of T(x0, rf[f]) in inner slab s
+// of stored outer iteration m of T(x0, rf[f]) in inner slab s
 __global__ void field_tavg_kernel(const LatDesc* __restrict__ lat, const MLDesc* __restrict__ mlp,
                                   const FieldLat* __restrict__ flp, FieldParams fp,
                                   const double2* __restrict__ mlbuf, double* __restrict__ fbuf) {
@@ -26,7 +26,7 @@ __global__ void field_tavg_kernel(const LatDesc* __restrict__ lat, const MLDesc*
   const MLDesc ml = *mlp;
   const FieldLat fl = *flp;
   const int item = blockIdx.x * blockDim.x + threadIdx.x;
-  if (item >= fp.n_outer * fl.ns * d.L3 * fp.n_rf) return;
+  if (item >= fp.n_stored * fl.ns * d.L3 * fp.n_rf) return;
   const int f = item % fp.n_rf;
   const int x0 = (item / fp.n_rf) % d.L3;
   const int s = (item / (fp.n_rf * d.L3)) % fl.ns;
@@ -49,7 +49,7 @@ __global__ void field_weights_kernel(const LatDesc* __restrict__ lat, const MLDe
   const MLDesc ml = *mlp;
   const FieldLat fl = *flp;
   const int item = blockIdx.x * blockDim.x + threadIdx.x;
-  if (item >= fp.n_outer * fl.ns * d.L3 * fp.n_rf) return;
+  if (item >= fp.n_stored * fl.ns * d.L3 * fp.n_rf) return;
   const int f = item % fp.n_rf;
   const int x0 = (item / fp.n_rf) % d.L3;
   const int s = (item / (fp.n_rf * d.L3)) % fl.ns;
@@ -518,7 +518,7 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
   const int ngroups_w = (L + npb_w - 1) / npb_w;
   const uint64_t per_sample = (uint64_t)fp.n_rf * ns * L3 + (uint64_t)ns * 6 * n_ent;
   const int chunk = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, scratch_elems / per_sample));
-  const int n_samples = fp.n_outer * fp.n_inner;
+  const int n_samples = fp.n_stored * fp.n_inner;
   for (int s0 = 0; s0 < n_samples; s0 += chunk) {
     const int nk = std::min(chunk, n_samples - s0);
     double2* what = scratch;
@@ -560,27 +560,28 @@ FastContract fast_contract_for(int L, FieldParams fp) {
 
 hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,
                                  FieldParams fp, int L, const double2* mlbuf, const double2* accbuf, double* fbuf,
-                                 double2* scratch, size_t scratch_elems, double2* F, bool general, hipStream_t st) {
+                                 double2* scratch, size_t scratch_elems, double2* F, bool general, bool zero_g,
+                                 bool finalize, hipStream_t st) {
   const uint64_t L3 = (uint64_t)L * L * L, L2 = (uint64_t)L * L;
   const int ns = hfl.ns;
-  const uint64_t nt = (uint64_t)fp.n_outer * ns * L3 * fp.n_rf;
+  const uint64_t nt = (uint64_t)fp.n_stored * ns * L3 * fp.n_rf;
   hipLaunchKernelGGL(field_tavg_kernel, dim3(blocks_for(nt, 256)), dim3(256), 0, st, lat, ml, fl, fp, mlbuf, fbuf);
   hipLaunchKernelGGL(field_weights_kernel, dim3(blocks_for(nt, 256)), dim3(256), 0, st, lat, ml, fl, fp, accbuf,
                      fbuf);
   double2* G = (double2*)(fbuf + hfl.g);
   const uint64_t ng = (uint64_t)fp.n_rf * 12 * L2;
-  hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(ng, 256)), dim3(256), 0, st, G, ng);
+  if (zero_g) hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(ng, 256)), dim3(256), 0, st, G, ng);
   if (FastContract fc = general ? nullptr : fast_contract_for(L, fp)) {
     const hipError_t e = fc(lat, ml, fl, ns, fp, mlbuf, fbuf, scratch, scratch_elems, G, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(field_final_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, G, F);
+    if (finalize) hipLaunchKernelGGL(field_final_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, G, F);
     return hipGetLastError();
   }
   // general path: both transforms stored, contraction by pq tiles
   // scratch per chunk: What [nk][n_rf][ns][L3], Ohat [nk][6][ns][L3], part [nk][n_rf][ns][12][L2]
   const uint64_t per_sample = (uint64_t)(fp.n_rf + 6) * ns * L3 + (uint64_t)fp.n_rf * ns * 12 * L2;
   const int chunk = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, scratch_elems / per_sample));
-  const int n_samples = fp.n_outer * fp.n_inner;
+  const int n_samples = fp.n_stored * fp.n_inner;
   const size_t shm = (size_t)(L + L2) * sizeof(double2);
   // pq tile of the accumulation: LDS holds (n_rf + 1) L pt complex values
   int pt = 64;
@@ -600,9 +601,8 @@ hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const Fie
                        ns, pt, what, ohat, part);
     hipLaunchKernelGGL(field_gred_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, ns, nk, part, G);
   }
-  hipLaunchKernelGGL(field_final_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, G, F);
+  if (finalize) hipLaunchKernelGGL(field_final_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, G, F);
   return hipGetLastError();
 }
-
 
 }  // namespace u1ml

@@ -2,7 +2,7 @@
 the GPU, analysed on the host.
 
     python -m paper_1208_0166_amd.study potential [--replicas 24] [--n1 100] [--n2 1000] ...
-    python -m paper_1208_0166_amd.study width [--replicas 8] [--n1 10] [--n2 100] ...
+    python -m paper_1208_0166_amd.study width [--replicas 8] [--n1 100] [--n2 1000] ...
 
 ``potential``: independent chains at 24^4, beta = 1 (cold start, thermalised),
 one two-level multilevel run per configuration (slabs 4 and 2, analytical
@@ -147,7 +147,7 @@ def main(argv=None):
     ap.add_argument("--no-multihit", action="store_true")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
-    defaults = {"potential": (24, 100, 1000), "width": (8, 10, 100)}[args.study]
+    defaults = {"potential": (24, 100, 1000), "width": (8, 100, 1000)}[args.study]
     args.replicas = args.replicas or defaults[0]
     args.n1 = args.n1 or defaults[1]
     args.n2 = args.n2 or defaults[2]

@@ -388,3 +388,55 @@ def test_symmetric_batch_and_one_update_identity(oracle_mod):
     th = u1ml.get_links(g)
     ref = np.array([plain_corr_sym(th, r) for r in rl])
     assert np.abs(c - ref.real).max() < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("mh,sq,general,L", [
+    (False, False, False, 4),
+    (True, False, False, 4),
+    (False, True, True, 6),
+    (True, True, False, 6),
+])
+def test_replayed_field_run_matches_oracle(oracle_mod, mh, sq, general, L):
+    # two passes over the same updates, one outer iteration of samples stored
+    # at a time: links, pass ids and the accept log of the first pass equal
+    # the oracle's, the correlator and field agree with its single pass
+    T = 8
+    r_list, rf = [1, 2, 3], [2, 3]
+    say(f"[gpu] replayed field run mh={mh} sq={sq} general={general} L={L}")
+    o = oracle_mod.OracleLattice(L, T, 1.0, 101, hot=True)
+    g = u1ml.init_lattice(L, T, 1.0, 101)
+    u1ml.set_estimator(g, multihit=mh, field_squared=sq)
+    u1ml.set_debug(g, 1 | 8 | (2 if general else 0), 1 << 24)
+    c_o, f_o, log_o = o.multilevel([4, 2], [3, 2], 1, 2, r_list, rf_list=rf, log_cap=1 << 24,
+                                   multihit=mh, field_squared=sq)
+    u1ml.multilevel(g, [4, 2], [3, 2], 1, 2, r_list, rf_list=rf)
+    _, c_g, f_g = u1ml.measure(g, observables=False, correlator=True, field_profile=True)
+    np.testing.assert_array_equal(u1ml.get_accept_log(g), log_o)
+    np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
+    assert u1ml.get_pass_id(g) == o.pass_id
+    close_rel(c_g, c_o)
+    close_rel(f_g, f_o)
+
+
+def test_replayed_run_equals_stored_run_under_graph_replay():
+    # the same chain with and without replay: identical links, pass ids and
+    # correlator bits, field to rounding; the first call runs eagerly, the
+    # later ones replay the captured graph
+    say("[gpu] replay vs stored under graph replays")
+    outs = []
+    for flags in (0, 8):
+        g = u1ml.init_lattice(6, 8, 1.1, 113)
+        if flags:
+            u1ml.set_debug(g, flags)
+        runs = []
+        for _ in range(3):  # first call eager, then graph replays
+            u1ml.sweep(g, 1, 3)
+            u1ml.multilevel(g, [4, 2], [2, 3], 1, 3, [1, 2, 3], rf_list=[2, 3])
+            _, c, f = u1ml.measure(g, observables=False, correlator=True, field_profile=True)
+            runs.append((u1ml.get_links(g), c, f, u1ml.get_pass_id(g)))
+        outs.append(runs)
+    for (l0, c0, f0, p0), (l1, c1, f1, p1) in zip(*outs):
+        np.testing.assert_array_equal(l0, l1)
+        np.testing.assert_array_equal(c0, c1)
+        assert p0 == p1
+        close_rel(f1, f0)
