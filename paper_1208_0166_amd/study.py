@@ -121,11 +121,17 @@ def width_study(args):
            "rows": []}
     for r in rf:
         k = r_list.index(r)
-        try:
-            w2, err, p = an.flux_tube_width(profiles[r], corrs[:, k], omeans, comp=0)
-            out["rows"].append({"r": r, "w2": w2, "dw2": err, "ansatz": [float(x) for x in p]})
-        except (RuntimeError, ValueError) as e:  # fit did not converge at this statistics
-            out["rows"].append({"r": r, "error": str(e)})
+        row = {"r": r}
+        # mean connected E_x profile over the mediator plane (planes averaged)
+        conn = an.connected_part(np.mean(profiles[r], axis=0), corrs[:, k].mean(), np.mean(omeans, axis=0))
+        row["profile_Ex"] = np.mean(conn[:, 0], axis=0).tolist()
+        for dims in (2, 1):
+            try:
+                w2, err, p = an.flux_tube_width(profiles[r], corrs[:, k], omeans, comp=0, dims=dims)
+                row.update({f"w2_{dims}d": w2, f"dw2_{dims}d": err, "ansatz": [float(x) for x in p]})
+            except (RuntimeError, ValueError) as e:  # fit did not converge at this statistics
+                row[f"error_{dims}d"] = str(e)
+        out["rows"].append(row)
     out["seconds"] = time.time() - t0
     return out
 
