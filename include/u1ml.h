@@ -218,7 +218,8 @@ int u1ml_set_pass_id(u1ml_lattice *lat, uint64_t pass_id);
  * rounding.  flags & 4 folds the innermost slab averages with the per-site
  * kernel instead of the row-staged one (same bits).  flags & 8 runs every
  * two-level multilevel with field insertion in two passes (the mode taken
- * by itself when storing every inner sample would exceed 16 GiB): a first
+ * by itself when storing every inner sample would take more than 60 % of the
+ * device memory available): a first
  * pass for the top-level averages, then the same updates again from the
  * restored links, contracting each outer iteration's samples as it
  * completes; same links, pass ids and correlator bits, field to rounding,

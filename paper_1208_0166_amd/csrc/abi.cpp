@@ -46,13 +46,14 @@ constexpr double kMaxAngle = 64.0;
 // scratch for the field contraction, per engine
 constexpr size_t kFieldScratchBytes = 256u << 20;
 // A two-level run with field insertion keeps every inner sample's time lines
-// and field slab sums until the end.  Beyond this many bytes of such storage
-// the run is replayed instead: a first pass computes the top-level averages,
-// a second pass repeats the identical update sequence (counter-based random
-// numbers, restored links and pass ids) and contracts each outer iteration's
-// samples as soon as that iteration completes, so only one outer iteration's
-// samples are stored.
-constexpr size_t kFieldStoreLimit = 16ull << 30;
+// and field slab sums until the end.  When that storage would take more than
+// this fraction of the device memory available to the run, the run is
+// replayed instead: a first pass computes the top-level averages, a second
+// pass repeats the identical update sequence (counter-based random numbers,
+// restored links and pass ids) and contracts each outer iteration's samples
+// as soon as that iteration completes, so only one outer iteration's samples
+// are stored.
+constexpr double kFieldStoreFraction = 0.6;
 constexpr size_t kMaxGraphs = 16;
 // multilevel runs of more sublattice updates than this launch kernel by
 // kernel: capturing millions of launches costs more host time and memory
@@ -556,7 +557,15 @@ struct Engine {
         const size_t lines = (estimator & U1ML_MULTIHIT) ? 2 : 1;
         store_all += (size_t)n_outer * n_sub[inner] * ns_in * d.L3 * (6 * sizeof(double) + lines * sizeof(double2));
       }
-    m.replay = m.field && n_levels == 2 && (force_replay || store_all > kFieldStoreLimit);
+    bool too_big = false;
+    if (store_all > 0) {
+      size_t free_b = 0, total_b = 0;
+      U1_HIP(hipMemGetInfo(&free_b, &total_b));
+      // buffers of the previous layout are reused or freed by this one
+      const size_t avail = free_b + m.fbuf.bytes + m.mlbuf.bytes;
+      too_big = (double)store_all > kFieldStoreFraction * (double)avail;
+    }
+    m.replay = m.field && n_levels == 2 && (force_replay || too_big);
     const int n_stored = m.replay ? 1 : n_outer;
     const int n_samples_kept = m.field ? n_stored * n_sub[inner] : n_sub[inner];
     m.h_mls.assign(n_lats, MLDesc{});
