@@ -44,7 +44,7 @@ int fail(int code, const std::string& msg) {
 // [-pi, pi) by whole periods, which needs them to be of moderate size
 constexpr double kMaxAngle = 64.0;
 // scratch for the field contraction, per engine
-constexpr size_t kFieldScratchBytes = 256u << 20;
+constexpr size_t kFieldScratchBytes = 512u << 20;
 // A two-level run with field insertion keeps every inner sample's time lines
 // and field slab sums until the end.  When that storage would take more than
 // this fraction of the device memory available to the run, the run is

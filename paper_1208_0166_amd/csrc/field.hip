@@ -275,15 +275,13 @@ __global__ void field_final_kernel(FieldParams fp, int L, const double2* __restr
 // Fast path (L with factors 2, 3, 5 only, L <= kFxMaxL).  Each 1D transform is
 // a thread-private row or column FFT in registers (fft_reg.h) over planes
 // staged in LDS.  The O planes are real: two neighbouring x planes are
-// transformed together as one complex plane Z = O_a + i O_b and separated in
-// Fourier space,
+// transformed together as one complex plane Z = O_a + i O_b
+// (field_ohat_kernel) and separated in Fourier space by the contraction
+// (field_zcon_kernel),
 //   Ohat_a(k) = (Z(k) + conj Z(-k)) / 2,   Ohat_b(k) = (Z(k) - conj Z(-k)) / 2i.
-// The O transforms never leave LDS: field_ocon_kernel contracts them with the
-// stored W transforms right away.
 // ---------------------------------------------------------------------------
 constexpr int kFxMaxL = 32;
-constexpr int kFxEnt = 4;         // G entries (r_f, p, q) per thread, both planes each
-constexpr size_t kFxLds = 64512;  // LDS per block (bytes)
+constexpr size_t kFxLds = 64512;  // LDS per block of field_what_kernel (bytes)
 
 // in-place FFT of the N values v[i * stride] (LDS)
 template <int N, int SIGN>
@@ -347,122 +345,109 @@ __global__ __launch_bounds__(256) void field_what_kernel(const LatDesc* __restri
   }
 }
 
-// part[((k * ns + s) * 6 + c) * 2 n_rf L^2 + g], g = (f * 2 + plane) * L^2 + p * L + q:
-//   sum_x What[k][f][s][x - m](p, q) * Ohat_c[k][s][x](p, q),  m_0 = (r - 1) / 2, m_1 = r / 2.
-// Block: (k, s, component triple: E or B) over all x, in groups of npb planes
-// (npb even: pairs of planes as one complex plane) of each of the three
-// components.  Thread = row (c, pair, y) in pass 1, column (c, pair, q) in
-// pass 2, and owner of the G entries (r_f, p, q) of all three components and
-// both planes, e = e_begin + tid + j * blockDim.x: every W value read serves
-// six sums.  With many separations the entries are split into n_fc chunks of
-// fe_per entries (whole r_f), one block per chunk.
-constexpr int kFxComp = 3;  // field components per block
+// Zhat[((sample * ns + s) * 6 + c) * (L / 2) + j][p * L + q] (complex): the
+// transform over (y, z) of Z = O_c(2 j) + i O_c(2 j + 1), O_c the sums over
+// the times of inner slab s of the insertion operator (Eq. (5), or Eq. (6)
+// with SQ) at x = 2 j, 2 j + 1.  Block: (unit = (lattice, slab), pair j);
+// a thread per (y, z) sums its two sites' six operators into the six planes,
+// then 6 L threads transform rows (along z) and columns (along y).
+// Zhat[((k * ns + s) * 6 + c) * (L / 2) + j][p * L + q] (complex): the
+// transform over (y, z) of Z = O_c(2 j) + i O_c(2 j + 1) for sample
+// sample0 + k, inner slab s, from the stored slab sums O_c.  Block: (k, s, c,
+// group of np pairs); the pair planes are staged with 16-byte loads of
+// neighbouring x (pairs fastest), then np L threads transform rows (along z)
+// and columns (along y).
 template <int L>
-__global__ __launch_bounds__(512) void field_ocon_kernel(const LatDesc* __restrict__ lat,
-                                                         const FieldLat* __restrict__ flp, FieldParams fp,
-                                                         int sample0, int npb, int nacc, int n_fc, int fe_per,
+__global__ __launch_bounds__(256) void field_ohat_kernel(const LatDesc* __restrict__ lat,
+                                                         const FieldLat* __restrict__ flp, int sample0, int np,
                                                          const double* __restrict__ fbuf,
+                                                         double2* __restrict__ zhat) {
+  extern __shared__ double2 zp[];  // [np][L (y)][L + 1]
+  constexpr int L1 = L + 1, L2 = L * L, NP = L / 2;
+  const LatDesc d = *lat;
+  const FieldLat fl = *flp;
+  const int ns = fl.ns, ngroups = (NP + np - 1) / np;
+  const int b = blockIdx.x;
+  const int grp = b % ngroups, c = (b / ngroups) % 6, s = (b / (ngroups * 6)) % ns, k = b / (ngroups * 6 * ns);
+  const int j0 = grp * np, n = min(np, NP - j0);
+  const double* o = fbuf + fl.oall + (((size_t)(sample0 + k) * 6 + c) * ns + s) * d.L3;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n * L2; i += blockDim.x) {
+    const int pr = i % n, yz = i / n, y = yz % L, z = yz / L;
+    zp[(pr * L + y) * L1 + z] = *(const double2*)(o + (size_t)(z * L + y) * L + 2 * (j0 + pr));
+  }
+  __syncthreads();
+  const bool active = tid < n * L;
+  const int pl = tid / L, t = tid - pl * L;
+  if (active) fft_line<L, -1>(zp + (pl * L + t) * L1, 1);  // rows, along z
+  __syncthreads();
+  if (active) fft_line<L, -1>(zp + pl * L * L1 + t, L1);  // columns, along y
+  __syncthreads();
+  double2* dst = zhat + ((((size_t)k * ns + s) * 6 + c) * NP + j0) * L2;
+  for (int i = tid; i < n * L2; i += blockDim.x) {
+    const int pr = i / L2, pq = i - pr * L2, p = pq / L, q = pq - p * L;
+    dst[(size_t)pr * L2 + pq] = zp[(pr * L + p) * L1 + q];
+  }
+}
+
+// part[((k * ns + s) * 6 + c) * 2 n_rf L^2 + (2 f + plane) L^2 + p L + q]:
+//   sum_x What[k][f][s][x - m](p, q) * Ohat_c[k][s][x](p, q),  m_0 = (r - 1) / 2, m_1 = r / 2.
+// Thread = entry (r_f, p, q) of one (sample k, slab s), with all six
+// components and both planes in registers; Ohat from the pair transforms.  With m_1 = m_0 (odd r) or m_0 + 1 (even r), plane 1 at x uses
+// the W plane that plane 0 used at x (odd) or x - 1 (even), so every W value
+// is read once: w1 carries W(x - 1 - m_0) from pair to pair.
+template <int L>
+__global__ __launch_bounds__(256) void field_zcon_kernel(const FieldLat* __restrict__ flp, FieldParams fp,
+                                                         int nblk_e, const double2* __restrict__ zhat,
                                                          const double2* __restrict__ what,
                                                          double2* __restrict__ part) {
-  extern __shared__ double2 zb[];  // [kFxComp][pairs][L][L + 1]
-  constexpr int L1 = L + 1, L2 = L * L, CG = 6 / kFxComp;
-  const LatDesc d = *lat;
+  constexpr int L2 = L * L, NP = L / 2;
   const FieldLat fl = *flp;
   const int ns = fl.ns;
   const int lb = (int)xcd_block(blockIdx.x, gridDim.x);  // the blocks of one (k, s) share an L2
-  const int cg = lb % CG, fc = (lb / CG) % n_fc, s = (lb / (CG * n_fc)) % ns, k = lb / (CG * n_fc * ns);
-  const int c0 = cg * kFxComp, sample = sample0 + k;
-  const double* o0 = fbuf + fl.oall + (((size_t)sample * 6 + c0) * ns + s) * d.L3;  // + c * ns * L3
-  const double2* wk = what + ((size_t)k * fp.n_rf * ns + s) * L * L2;                // + (f * ns * L + x) * L2
-  const int tid = threadIdx.x;
-  const int n_fe = fp.n_rf * L2;  // entries (f, pq)
-  const int e_begin = fc * fe_per, e_end = min(n_fe, e_begin + fe_per);
-  // With m_0 = (r - 1) / 2 and m_1 = r / 2 (= m_0 or m_0 + 1), plane 1 at x uses
-  // the W plane that plane 0 used at x - 1 (even r) or the same one (odd r), so
-  // every W value is read once: wp carries W(x - 1 - m_0) from plane to plane.
-  double2 g0[kFxEnt][kFxComp], g1[kFxEnt][kFxComp], wp[kFxEnt];
+  const int eb = lb % nblk_e, s = (lb / nblk_e) % ns, k = lb / (nblk_e * ns);
+  const int n_fe = fp.n_rf * L2;
+  const int e = eb * (int)blockDim.x + (int)threadIdx.x;
+  if (e >= n_fe) return;
+  const int f = e / L2, pq = e - f * L2, r = fp.rf[f];
+  const int m0 = (r - 1) / 2;
+  const bool even = (r & 1) == 0;
+  const int p = pq / L, q = pq - p * L;
+  const int ib = (p == 0 ? 0 : L - p) * L + (q == 0 ? 0 : L - q);  // -k
+  const double2* z = zhat + ((size_t)k * ns + s) * 6 * NP * L2;
+  const double2* wf = what + (((size_t)k * fp.n_rf + f) * ns + s) * L * L2 + pq;
+  double2 g0[6], g1[6];
 #pragma unroll
-  for (int j = 0; j < kFxEnt; ++j) {
+  for (int c = 0; c < 6; ++c) g0[c] = g1[c] = make_double2(0.0, 0.0);
+  int xw = m0 == 0 ? 0 : L - m0;                // W plane of plane 0 at x = 0
+  double2 w1 = wf[(size_t)(L - 1 - m0) * L2];  // W(-1 - m_0)
+  for (int jp = 0; jp < NP; ++jp) {
+    const double2 wa = wf[(size_t)xw * L2];
+    xw += 1;
+    xw -= xw >= L ? L : 0;
+    const double2 wb = wf[(size_t)xw * L2];
+    xw += 1;
+    xw -= xw >= L ? L : 0;
+    const double2 ha = even ? w1 : wa, hb = even ? wa : wb;
 #pragma unroll
-    for (int c = 0; c < kFxComp; ++c) g0[j][c] = g1[j][c] = make_double2(0.0, 0.0);
-    wp[j] = make_double2(0.0, 0.0);
-    const int e = e_begin + tid + j * (int)blockDim.x;
-    if (j < nacc && e < e_end) {
-      const int f = e / L2, pq = e - f * L2, m0 = (fp.rf[f] - 1) / 2;
-      wp[j] = wk[(size_t)f * ns * L * L2 + (size_t)(L - 1 - m0) * L2 + pq];  // W(-1 - m_0)
+    for (int c = 0; c < 6; ++c) {
+      const double2* zc = z + ((size_t)c * NP + jp) * L2;
+      const double2 za = zc[pq], zm = zc[ib];
+      const double2 oa = make_double2(0.5 * (za.x + zm.x), 0.5 * (za.y - zm.y));   // Ohat_c of x = 2 jp
+      const double2 ob = make_double2(0.5 * (za.y + zm.y), -0.5 * (za.x - zm.x));  // Ohat_c of x = 2 jp + 1
+      g0[c].x += (wa.x * oa.x - wa.y * oa.y) + (wb.x * ob.x - wb.y * ob.y);
+      g0[c].y += (wa.x * oa.y + wa.y * oa.x) + (wb.x * ob.y + wb.y * ob.x);
+      g1[c].x += (ha.x * oa.x - ha.y * oa.y) + (hb.x * ob.x - hb.y * ob.y);
+      g1[c].y += (ha.x * oa.y + ha.y * oa.x) + (hb.x * ob.y + hb.y * ob.x);
     }
-  }
-  for (int x0 = 0; x0 < L; x0 += npb) {
-    const int np = min(npb, L - x0) >> 1;  // pairs in this group
-    const int cp = kFxComp * np;           // (component, pair) planes in LDS
-    __syncthreads();  // the previous group's contraction is done with zb
-    // Z_c(y, z) = O_c(xa, y, z) + i O_c(xa + 1, y, z), xa = x0 + 2 pr; pairs fastest
-    for (int i = tid; i < cp * L2; i += blockDim.x) {
-      const int pr = i % np, c = (i / np) % kFxComp, yz = i / cp, y = yz % L, z = yz / L;
-      zb[((c * np + pr) * L + y) * L1 + z] =
-          *(const double2*)(o0 + (size_t)c * ns * d.L3 + (z * L + y) * L + x0 + 2 * pr);
-    }
-    __syncthreads();
-    const bool active = tid < cp * L;
-    const int pl = tid / L, t = tid - pl * L;  // plane pl = c * np + pr
-    if (active) fft_line<L, -1>(zb + (pl * L + t) * L1, 1);  // rows, along z
-    __syncthreads();
-    // columns, along y, in place: only this thread touches the column
-    if (active) fft_line<L, -1>(zb + pl * L * L1 + t, L1);
-    __syncthreads();
-    // contraction over the planes of this group
-#pragma unroll
-    for (int j = 0; j < kFxEnt; ++j) {
-      const int e = e_begin + tid + j * (int)blockDim.x;
-      if (j < nacc && e < e_end) {
-        const int f = e / L2, pq = e - f * L2, r = fp.rf[f];
-        const int m0 = (r - 1) / 2;
-        const bool even = (r & 1) == 0;
-        const int p = pq / L, qq = pq - p * L;
-        const int ia = p * L1 + qq;                                          // Z(k)
-        const int ib = (p == 0 ? 0 : L - p) * L1 + (qq == 0 ? 0 : L - qq);  // Z(-k)
-        const double2* wf = wk + (size_t)f * ns * L * L2 + pq;
-        int xw = x0 - m0;  // W plane of plane 0 at x = x0
-        xw += xw < 0 ? L : 0;
-        double2 w1 = wp[j];
-        for (int pp = 0; pp < np; ++pp) {
-          const double2 wa = wf[(size_t)xw * L2];
-          xw += 1;
-          xw -= xw >= L ? L : 0;
-          const double2 wb = wf[(size_t)xw * L2];
-          xw += 1;
-          xw -= xw >= L ? L : 0;
-          const double2 ha = even ? w1 : wa, hb = even ? wa : wb;
-#pragma unroll
-          for (int c = 0; c < kFxComp; ++c) {
-            const double2* z = zb + (c * np + pp) * L * L1;
-            const double2 za = z[ia], zm = z[ib];
-            const double2 oa = make_double2(0.5 * (za.x + zm.x), 0.5 * (za.y - zm.y));   // Ohat_c of x
-            const double2 ob = make_double2(0.5 * (za.y + zm.y), -0.5 * (za.x - zm.x));  // Ohat_c of x + 1
-            g0[j][c].x += (wa.x * oa.x - wa.y * oa.y) + (wb.x * ob.x - wb.y * ob.y);
-            g0[j][c].y += (wa.x * oa.y + wa.y * oa.x) + (wb.x * ob.y + wb.y * ob.x);
-            g1[j][c].x += (ha.x * oa.x - ha.y * oa.y) + (hb.x * ob.x - hb.y * ob.y);
-            g1[j][c].y += (ha.x * oa.y + ha.y * oa.x) + (hb.x * ob.y + hb.y * ob.x);
-          }
-          w1 = wb;
-        }
-        wp[j] = w1;
-      }
-    }
+    w1 = wb;
   }
   const int n_ent = 2 * n_fe;
+  double2* out = part + (size_t)(k * ns + s) * 6 * n_ent + (2 * f) * L2 + pq;
 #pragma unroll
-  for (int j = 0; j < kFxEnt; ++j) {
-    const int e = e_begin + tid + j * (int)blockDim.x;
-    if (j < nacc && e < e_end) {
-      const int f = e / L2, pq = e - f * L2;
-#pragma unroll
-      for (int c = 0; c < kFxComp; ++c) {
-        double2* out = part + ((size_t)(k * ns + s) * 6 + c0 + c) * n_ent;
-        out[(2 * f) * L2 + pq] = g0[j][c];
-        out[(2 * f + 1) * L2 + pq] = g1[j][c];
-      }
-    }
+  for (int c = 0; c < 6; ++c) {
+    out[(size_t)c * n_ent] = g0[c];
+    out[(size_t)c * n_ent + L2] = g1[c];
   }
 }
 
@@ -496,7 +481,6 @@ __global__ void field_gsum_kernel(FieldParams fp, int L, int ns, int nk, const d
   G[item].y += (im[0] + im[1]) + (im[2] + im[3]);
 }
 
-}  // namespace
 
 template <int L>
 hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, int ns, FieldParams fp,
@@ -504,43 +488,40 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
                                 double2* G, hipStream_t st) {
   const uint64_t L3 = (uint64_t)L * L * L, L2 = (uint64_t)L * L;
   const size_t plane_bytes = (size_t)L * (L + 1) * sizeof(double2);  // LDS rows padded to L + 1
-  const int planes = (int)(kFxLds / plane_bytes);
-  const int npb_w = std::min(L, planes);
-  const int npb_o = 2 * std::min(L / 2, planes / kFxComp);  // x planes per group of each component
+  const int npb_w = std::min<int>(L, (int)(kFxLds / plane_bytes));
+  const int np_o = std::min<int>(L / 2, (int)(kFxLds / plane_bytes));  // pair planes per transform block
   const int n_ent = 2 * fp.n_rf * (int)L2;
   const int thr_w = (npb_w * L + 63) / 64 * 64;
-  // separations per contraction block: at most 512 threads of kFxEnt entries
-  const int fpc = std::min(fp.n_rf, 512 * kFxEnt / (int)L2);
-  const int n_fc = (fp.n_rf + fpc - 1) / fpc, fe_per = fpc * (int)L2;
-  const int thr_o =
-      std::max((kFxComp * npb_o / 2 * L + 63) / 64 * 64, ((fe_per + kFxEnt - 1) / kFxEnt + 63) / 64 * 64);
-  const int nacc = (fe_per + thr_o - 1) / thr_o;
+  const int thr_o = std::min(256, (np_o * L + 63) / 64 * 64);
   const int ngroups_w = (L + npb_w - 1) / npb_w;
-  const uint64_t per_sample = (uint64_t)fp.n_rf * ns * L3 + (uint64_t)ns * 6 * n_ent;
+  const int ngroups_o = (L / 2 + np_o - 1) / np_o;
+  const int nblk_e = (int)((fp.n_rf * L2 + 255) / 256);
+  // scratch per sample: What [n_rf][ns][L3], Zhat [ns][6][L3 / 2], part [ns][6][n_ent]
+  const uint64_t per_sample = (uint64_t)fp.n_rf * ns * L3 + (uint64_t)ns * 3 * L3 + (uint64_t)ns * 6 * n_ent;
   const int chunk = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, scratch_elems / per_sample));
   const int n_samples = fp.n_stored * fp.n_inner;
   for (int s0 = 0; s0 < n_samples; s0 += chunk) {
     const int nk = std::min(chunk, n_samples - s0);
     double2* what = scratch;
-    double2* part = what + (uint64_t)nk * fp.n_rf * ns * L3;
+    double2* zhat = what + (uint64_t)nk * fp.n_rf * ns * L3;
+    double2* part = zhat + (uint64_t)nk * ns * 3 * L3;
     hipLaunchKernelGGL(field_what_kernel<L>, dim3((unsigned)((uint64_t)nk * fp.n_rf * ns * ngroups_w)), dim3(thr_w),
                        npb_w * plane_bytes, st, lat, ml, fl, fp, s0, npb_w, mlbuf, fbuf, what);
-    hipLaunchKernelGGL(field_ocon_kernel<L>, dim3((unsigned)((uint64_t)nk * ns * n_fc * (6 / kFxComp))),
-                       dim3(thr_o), kFxComp * (npb_o / 2) * plane_bytes, st, lat, fl, fp, s0, npb_o, nacc, n_fc,
-                       fe_per, fbuf, what, part);
+    hipLaunchKernelGGL(field_ohat_kernel<L>, dim3((unsigned)((uint64_t)nk * ns * 6 * ngroups_o)), dim3(thr_o),
+                       np_o * plane_bytes, st, lat, fl, s0, np_o, fbuf, zhat);
+    hipLaunchKernelGGL(field_zcon_kernel<L>, dim3((unsigned)((uint64_t)nk * ns * nblk_e)), dim3(256), 0, st, fl, fp,
+                       nblk_e, zhat, what, part);
     hipLaunchKernelGGL(field_gsum_kernel, dim3(blocks_for(6 * (uint64_t)n_ent, 64)), dim3(64), 0, st, fp, L, ns, nk,
                        part, G);
   }
   return hipGetLastError();
 }
 
-// the fast path for lattice size L: one of the instantiated lengths, and the G
-// entries (r_f, p, q) of one block fit in 512 threads x kFxEnt
+// the fast path for lattice size L: one of the instantiated lengths
 typedef hipError_t (*FastContract)(const LatDesc*, const MLDesc*, const FieldLat*, int, FieldParams, const double2*,
                                    const double*, double2*, size_t, double2*, hipStream_t);
-FastContract fast_contract_for(int L, FieldParams fp) {
-  if (L > kFxMaxL || L * L > 512 * kFxEnt) return nullptr;
-  if (kFxLds / ((size_t)L * (L + 1) * sizeof(double2)) < (size_t)kFxComp) return nullptr;  // one pair per component
+FastContract fast_contract_for(int L) {
+  if (L > kFxMaxL) return nullptr;
   switch (L) {
     case 2: return launch_fast_contract<2>;
     case 4: return launch_fast_contract<4>;
@@ -558,6 +539,8 @@ FastContract fast_contract_for(int L, FieldParams fp) {
   }
 }
 
+}  // namespace
+
 hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,
                                  FieldParams fp, int L, const double2* mlbuf, const double2* accbuf, double* fbuf,
                                  double2* scratch, size_t scratch_elems, double2* F, bool general, bool zero_g,
@@ -571,7 +554,7 @@ hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const Fie
   double2* G = (double2*)(fbuf + hfl.g);
   const uint64_t ng = (uint64_t)fp.n_rf * 12 * L2;
   if (zero_g) hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(ng, 256)), dim3(256), 0, st, G, ng);
-  if (FastContract fc = general ? nullptr : fast_contract_for(L, fp)) {
+  if (FastContract fc = general ? nullptr : fast_contract_for(L)) {
     const hipError_t e = fc(lat, ml, fl, ns, fp, mlbuf, fbuf, scratch, scratch_elems, G, st);
     if (e != hipSuccess) return e;
     if (finalize) hipLaunchKernelGGL(field_final_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, G, F);

@@ -407,34 +407,6 @@ __global__ void ml_final_kernel(const LatDesc* __restrict__ lats, const MLDesc* 
 // the final weights, as a correlation over the mediator plane evaluated by 2D
 // discrete Fourier transforms in (y, z).
 // ---------------------------------------------------------------------------
-// sin of the plaquette angle: FP64 links in FP64; FP32 links (the fast path)
-// in FP32 arithmetic with the hardware sine, summed by the caller in FP64
-// Insertion operator of one plaquette angle: sqrt(beta) Im P (Eq. (5)), or
-// with SQ the squared component beta (1 - Re P) = 2 beta sin^2(theta / 2)
-// (Eq. (6)); the prefactor is applied by the caller.
-template <bool SQ>
-__device__ __forceinline__ double plaq_op(const double* links, const LatDesc& d, Site s, int mu, int nu) {
-  const double a = plaq_angle(links, d, s, mu, nu);
-  if (SQ) {
-    const double h = sin(0.5 * a);
-    return 2.0 * (h * h);
-  }
-  return sin(a);
-}
-template <bool SQ>
-__device__ __forceinline__ double plaq_op(const float* links, const LatDesc& d, Site s, int mu, int nu) {
-  const float a = links[link_at(d, mu, s)];
-  const float b = links[link_at(d, nu, shift2(d, s, mu, 1, nu, 0))];
-  const float c = links[link_at(d, mu, shift2(d, s, nu, 1, mu, 0))];
-  const float e = links[link_at(d, nu, s)];
-  const float th = ((a + b) - c) - e;
-  if (SQ) {
-    const float h = __sinf(0.5f * th);
-    return (double)(2.0f * (h * h));
-  }
-  return (double)__sinf(th);
-}
-
 // oall[((sample * 6 + c) * ns + s) * L3 + y] = sum over the times t of inner
 // slab s of O_c(y, t): O_c = sqrt(beta) Im P_munu (Eq. (5)), or with SQ the
 // squared component beta (1 - Re P_munu) (Eq. (6)).
@@ -455,15 +427,7 @@ __global__ void field_o_kernel(const R* __restrict__ links, const LatDesc* __res
   double o[6] = {0, 0, 0, 0, 0, 0};
   for (int t = s * th_inner; t < (s + 1) * th_inner; ++t) {
     st.t = t;
-    o[0] += plaq_op<SQ>(links, d, st, 0, 1);
-    o[1] += plaq_op<SQ>(links, d, st, 0, 2);
-    o[2] += plaq_op<SQ>(links, d, st, 0, 3);
-    o[3] += plaq_op<SQ>(links, d, st, 2, 3);
-    if (SQ)
-      o[4] += plaq_op<SQ>(links, d, st, 1, 3);
-    else
-      o[4] -= plaq_op<SQ>(links, d, st, 1, 3);
-    o[5] += plaq_op<SQ>(links, d, st, 1, 2);
+    add_field_ops<SQ>(links, d, st, o);
   }
   const double pre = SQ ? d.beta : d.sqrt_beta;
   double* out = fbuf + fl.oall + (size_t)sample * 6 * fl.ns * d.L3;

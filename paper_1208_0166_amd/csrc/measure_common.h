@@ -67,6 +67,50 @@ __device__ __forceinline__ double plaq_angle(const R* links, const LatDesc& d, S
   return ((a + b) - c) - e;
 }
 
+// Insertion operator of one plaquette angle: sqrt(beta) Im P (Eq. (5)), or
+// with SQ the squared component beta (1 - Re P) = 2 beta sin^2(theta / 2)
+// (Eq. (6)); the prefactor is applied by the caller.  FP32 links (the fast
+// path) in FP32 arithmetic with the hardware sine, returned as FP64 for the
+// FP64 sums.
+template <bool SQ>
+__device__ __forceinline__ double plaq_op(const double* links, const LatDesc& d, Site s, int mu, int nu) {
+  const double a = plaq_angle(links, d, s, mu, nu);
+  if (SQ) {
+    const double h = sin(0.5 * a);
+    return 2.0 * (h * h);
+  }
+  return sin(a);
+}
+template <bool SQ>
+__device__ __forceinline__ double plaq_op(const float* links, const LatDesc& d, Site s, int mu, int nu) {
+  const float a = links[link_at(d, mu, s)];
+  const float b = links[link_at(d, nu, shift2(d, s, mu, 1, nu, 0))];
+  const float c = links[link_at(d, mu, shift2(d, s, nu, 1, mu, 0))];
+  const float e = links[link_at(d, nu, s)];
+  const float th = ((a + b) - c) - e;
+  if (SQ) {
+    const float h = __sinf(0.5f * th);
+    return (double)(2.0f * (h * h));
+  }
+  return (double)__sinf(th);
+}
+
+// o[c] += the six insertion operators at site st, before the prefactor:
+// E_x, E_y, E_z, B_x, B_y, B_z from P_01, P_02, P_03, P_23, P_31 = conj(P_13),
+// P_12 (the squared components do not depend on the orientation)
+template <bool SQ, typename R>
+__device__ __forceinline__ void add_field_ops(const R* links, const LatDesc& d, Site st, double o[6]) {
+  o[0] += plaq_op<SQ>(links, d, st, 0, 1);
+  o[1] += plaq_op<SQ>(links, d, st, 0, 2);
+  o[2] += plaq_op<SQ>(links, d, st, 0, 3);
+  o[3] += plaq_op<SQ>(links, d, st, 2, 3);
+  if (SQ)
+    o[4] += plaq_op<SQ>(links, d, st, 1, 3);
+  else
+    o[4] -= plaq_op<SQ>(links, d, st, 1, 3);
+  o[5] += plaq_op<SQ>(links, d, st, 1, 2);
+}
+
 // sum_t theta_0 over [t0, t0 + nt) at spatial site x3
 template <typename R>
 __device__ __forceinline__ double time_line(const R* links, const LatDesc& d, int x3, int t0, int nt) {
