@@ -392,10 +392,15 @@ __global__ __launch_bounds__(256) void field_ohat_kernel(const LatDesc* __restri
 
 // part[((k * ns + s) * 6 + c) * 2 n_rf L^2 + (2 f + plane) L^2 + p L + q]:
 //   sum_x What[k][f][s][x - m](p, q) * Ohat_c[k][s][x](p, q),  m_0 = (r - 1) / 2, m_1 = r / 2.
-// Thread = entry (r_f, p, q) of one (sample k, slab s), with all six
-// components and both planes in registers; Ohat from the pair transforms.  With m_1 = m_0 (odd r) or m_0 + 1 (even r), plane 1 at x uses
-// the W plane that plane 0 used at x (odd) or x - 1 (even), so every W value
-// is read once: w1 carries W(x - 1 - m_0) from pair to pair.
+// Thread = (sample k, slab s, frequency (p, q), component half h, chunk of up
+// to kZcF separations): the 3 components c = 3 h .. 3 h + 2 of every
+// separation of the chunk and both planes in registers, so that each W value
+// read serves three components and each Ohat value three separations.  Ohat
+// comes from the pair transforms.  With m_1 = m_0 (odd r) or m_0 + 1 (even
+// r), plane 1 at x uses the W plane that plane 0 used at x (odd) or x - 1
+// (even), so every W value is read once per thread: w1 carries W(x - 1 - m_0)
+// from pair to pair.
+constexpr int kZcF = 3;
 template <int L>
 __global__ __launch_bounds__(256) void field_zcon_kernel(const FieldLat* __restrict__ flp, FieldParams fp,
                                                          int nblk_e, const double2* __restrict__ zhat,
@@ -406,48 +411,70 @@ __global__ __launch_bounds__(256) void field_zcon_kernel(const FieldLat* __restr
   const int ns = fl.ns;
   const int lb = (int)xcd_block(blockIdx.x, gridDim.x);  // the blocks of one (k, s) share an L2
   const int eb = lb % nblk_e, s = (lb / nblk_e) % ns, k = lb / (nblk_e * ns);
-  const int n_fe = fp.n_rf * L2;
+  const int n_fc = (fp.n_rf + kZcF - 1) / kZcF;
   const int e = eb * (int)blockDim.x + (int)threadIdx.x;
-  if (e >= n_fe) return;
-  const int f = e / L2, pq = e - f * L2, r = fp.rf[f];
-  const int m0 = (r - 1) / 2;
-  const bool even = (r & 1) == 0;
+  if (e >= n_fc * 2 * L2) return;
+  const int pq = e % L2, h = (e / L2) % 2, f0 = (e / (2 * L2)) * kZcF;
+  const int nf = min(kZcF, fp.n_rf - f0);
   const int p = pq / L, q = pq - p * L;
   const int ib = (p == 0 ? 0 : L - p) * L + (q == 0 ? 0 : L - q);  // -k
-  const double2* z = zhat + ((size_t)k * ns + s) * 6 * NP * L2;
-  const double2* wf = what + (((size_t)k * fp.n_rf + f) * ns + s) * L * L2 + pq;
-  double2 g0[6], g1[6];
+  const double2* z = zhat + (((size_t)k * ns + s) * 6 + 3 * h) * NP * L2;
+  const double2* wk = what + ((size_t)k * fp.n_rf * ns + s) * L * L2 + pq;  // + (f ns L + x) L2
+  double2 g0[kZcF][3], g1[kZcF][3], w1[kZcF];
+  int xw[kZcF];
+  bool even[kZcF];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) g0[c] = g1[c] = make_double2(0.0, 0.0);
-  int xw = m0 == 0 ? 0 : L - m0;                // W plane of plane 0 at x = 0
-  double2 w1 = wf[(size_t)(L - 1 - m0) * L2];  // W(-1 - m_0)
+  for (int j = 0; j < kZcF; ++j) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g0[j][c] = g1[j][c] = make_double2(0.0, 0.0);
+    const int r = j < nf ? fp.rf[f0 + j] : 1, m0 = (r - 1) / 2;
+    even[j] = (r & 1) == 0;
+    xw[j] = m0 == 0 ? 0 : L - m0;  // W plane of plane 0 at x = 0
+    w1[j] = j < nf ? wk[((size_t)(f0 + j) * ns * L + (L - 1 - m0)) * L2] : make_double2(0.0, 0.0);  // W(-1 - m_0)
+  }
+#pragma unroll 2
   for (int jp = 0; jp < NP; ++jp) {
-    const double2 wa = wf[(size_t)xw * L2];
-    xw += 1;
-    xw -= xw >= L ? L : 0;
-    const double2 wb = wf[(size_t)xw * L2];
-    xw += 1;
-    xw -= xw >= L ? L : 0;
-    const double2 ha = even ? w1 : wa, hb = even ? wa : wb;
+    double2 oa[3], ob[3];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
+    for (int c = 0; c < 3; ++c) {
       const double2* zc = z + ((size_t)c * NP + jp) * L2;
       const double2 za = zc[pq], zm = zc[ib];
-      const double2 oa = make_double2(0.5 * (za.x + zm.x), 0.5 * (za.y - zm.y));   // Ohat_c of x = 2 jp
-      const double2 ob = make_double2(0.5 * (za.y + zm.y), -0.5 * (za.x - zm.x));  // Ohat_c of x = 2 jp + 1
-      g0[c].x += (wa.x * oa.x - wa.y * oa.y) + (wb.x * ob.x - wb.y * ob.y);
-      g0[c].y += (wa.x * oa.y + wa.y * oa.x) + (wb.x * ob.y + wb.y * ob.x);
-      g1[c].x += (ha.x * oa.x - ha.y * oa.y) + (hb.x * ob.x - hb.y * ob.y);
-      g1[c].y += (ha.x * oa.y + ha.y * oa.x) + (hb.x * ob.y + hb.y * ob.x);
+      oa[c] = make_double2(0.5 * (za.x + zm.x), 0.5 * (za.y - zm.y));   // Ohat of x = 2 jp
+      ob[c] = make_double2(0.5 * (za.y + zm.y), -0.5 * (za.x - zm.x));  // Ohat of x = 2 jp + 1
     }
-    w1 = wb;
-  }
-  const int n_ent = 2 * n_fe;
-  double2* out = part + (size_t)(k * ns + s) * 6 * n_ent + (2 * f) * L2 + pq;
 #pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    out[(size_t)c * n_ent] = g0[c];
-    out[(size_t)c * n_ent + L2] = g1[c];
+    for (int j = 0; j < kZcF; ++j) {
+      if (j < nf) {
+        const double2* wf = wk + (size_t)(f0 + j) * ns * L * L2;
+        const double2 wa = wf[(size_t)xw[j] * L2];
+        int xn = xw[j] + 1;
+        xn -= xn >= L ? L : 0;
+        const double2 wb = wf[(size_t)xn * L2];
+        xn += 1;
+        xw[j] = xn >= L ? xn - L : xn;
+        const double2 ha = even[j] ? w1[j] : wa, hb = even[j] ? wa : wb;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          g0[j][c].x += (wa.x * oa[c].x - wa.y * oa[c].y) + (wb.x * ob[c].x - wb.y * ob[c].y);
+          g0[j][c].y += (wa.x * oa[c].y + wa.y * oa[c].x) + (wb.x * ob[c].y + wb.y * ob[c].x);
+          g1[j][c].x += (ha.x * oa[c].x - ha.y * oa[c].y) + (hb.x * ob[c].x - hb.y * ob[c].y);
+          g1[j][c].y += (ha.x * oa[c].y + ha.y * oa[c].x) + (hb.x * ob[c].y + hb.y * ob[c].x);
+        }
+        w1[j] = wb;
+      }
+    }
+  }
+  const int n_ent = 2 * fp.n_rf * L2;
+  double2* out = part + ((size_t)(k * ns + s) * 6 + 3 * h) * n_ent + pq;
+#pragma unroll
+  for (int j = 0; j < kZcF; ++j) {
+    if (j < nf) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        out[(size_t)c * n_ent + (2 * (f0 + j)) * L2] = g0[j][c];
+        out[(size_t)c * n_ent + (2 * (f0 + j) + 1) * L2] = g1[j][c];
+      }
+    }
   }
 }
 
@@ -495,7 +522,7 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
   const int thr_o = std::min(256, (np_o * L + 63) / 64 * 64);
   const int ngroups_w = (L + npb_w - 1) / npb_w;
   const int ngroups_o = (L / 2 + np_o - 1) / np_o;
-  const int nblk_e = (int)((fp.n_rf * L2 + 255) / 256);
+  const int nblk_e = (int)((((fp.n_rf + kZcF - 1) / kZcF) * 2 * L2 + 255) / 256);
   // scratch per sample: What [n_rf][ns][L3], Zhat [ns][6][L3 / 2], part [ns][6][n_ent]
   const uint64_t per_sample = (uint64_t)fp.n_rf * ns * L3 + (uint64_t)ns * 3 * L3 + (uint64_t)ns * 6 * n_ent;
   const int chunk = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, scratch_elems / per_sample));
