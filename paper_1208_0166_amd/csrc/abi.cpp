@@ -185,6 +185,10 @@ struct Engine {
   DevBuf partial, rows, poly, poly_off, row_begin, red_out, rvals_tmp;
   MLState ml;
   Ensemble ens;
+  // plain observables of every lattice, valid while the links are unchanged:
+  // epoch advances with every launch sequence that may write links
+  uint64_t epoch = 0, obs_epoch = ~0ull;
+  std::vector<u1ml_observables> obs_cache;
   // captured launch sequences
   std::map<std::vector<long long>, GraphEntry> graphs;
   bool capturing = false;
@@ -274,6 +278,7 @@ struct Engine {
 
   // --- updates ---
   int class_pass(int kind, int mu, int parity, int th_frozen, int n_hits, uint8_t* logp, int bump_n = 0) {
+    ++epoch;
     hipError_t e;
     if (n_lats == 1) {
       if (prec == U1ML_FP64)
@@ -346,6 +351,7 @@ struct Engine {
   template <class Fn>
   int run_captured(const std::vector<long long>& key, Fn fn, bool capture = true) {
     const bool can = capture && use_graphs && !debug && !prof[0] && !prof[1];
+    ++epoch;
     if (can) {
       auto it = graphs.find(key);
       if (it != graphs.end()) {
@@ -381,6 +387,7 @@ struct Engine {
   }
 
   int init_links(int hot) {
+    ++epoch;
     std::vector<int> items;
     for (auto& d : h_lats) items.push_back(8 * d.V2);
     Table* t;
@@ -398,6 +405,7 @@ struct Engine {
   }
 
   int upload_lats() {
+    ++epoch;  // beta enters the field observables
     U1_HIP(hipStreamSynchronize(stream));
     U1_HIP(hipMemcpy(lats.p, h_lats.data(), n_lats * sizeof(LatDesc), hipMemcpyHostToDevice));
     drop_graphs();  // single-lattice kernels take the descriptor by value
@@ -434,6 +442,7 @@ struct Engine {
   }
 
   int set_links(int i, const double* host) {
+    ++epoch;
     const LatDesc& d = h_lats[i];
     const size_t n = 8ull * d.V2;
     for (size_t k = 0; k < n; ++k)
@@ -457,6 +466,10 @@ struct Engine {
 
   // --- plain observables of every lattice ---
   int observables(std::vector<u1ml_observables>& res) {
+    if (obs_epoch == epoch) {
+      res = obs_cache;
+      return U1ML_OK;
+    }
     std::vector<int> items;
     for (auto& d : h_lats) items.push_back(2 * d.V2);
     Table* t;
@@ -486,6 +499,8 @@ struct Engine {
       res[i].poly_im = pc[i][1];
       res[i].poly_abs = std::hypot(pc[i][0], pc[i][1]);
     }
+    obs_cache = res;
+    obs_epoch = epoch;
     return U1ML_OK;
   }
 
@@ -1459,6 +1474,7 @@ int u1ml_autotune(u1ml_lattice* lat, int* best_block) {
   e.block = best;
   e.drop_graphs();  // captured launches carry the old block size
   U1_HIP(hipMemcpyAsync(e.links.p, save.p, e.link_elems * e.elem_size(), hipMemcpyDeviceToDevice, e.stream));
+  ++e.epoch;
   e.h_pass_ids = ids;
   int rc2 = e.upload_pass_ids();
   if (rc) return rc;

@@ -170,3 +170,40 @@ def test_error_paths():
     assert e.value.code == u1ml.EINVAL
     with pytest.raises(u1ml.U1MLError):
         u1ml.set_links(g, np.full(4 * 256, np.nan))
+
+
+def test_observables_follow_every_update(oracle_mod):
+    # the plain observables are cached between link updates: every kind of
+    # update (eager and graph-replayed sweeps, multilevel runs, set_links,
+    # batch sweeps) must invalidate them
+    say("[gpu] observables after each kind of update")
+    o = oracle_mod.OracleLattice(4, 4, 1.0, 7, hot=True)
+    g = u1ml.init_lattice(4, 4, 1.0, 7)
+
+    def check():
+        obs, _, _ = u1ml.measure(g)
+        assert abs(obs["plaquette"] - o.plaquette()) < 1e-13
+        np.testing.assert_allclose(obs["field_mean"], o.field_means(), atol=1e-14)
+
+    check()
+    for _ in range(3):  # the second and third calls replay a captured graph
+        o.sweep(1, 3)
+        u1ml.sweep(g, 1, 3)
+        check()
+    for _ in range(2):
+        o.multilevel([2], [2], 1, 3, [1])
+        u1ml.multilevel(g, [2], [2], 1, 3, [1])
+        check()
+    th = np.random.default_rng(3).uniform(-np.pi, np.pi, size=(4, 4, 4, 4, 4))
+    o.set_links(th)
+    u1ml.set_links(g, th)
+    check()
+    b = u1ml.batch_create([4, 6], [4, 6], [1.0, 0.9], [8, 9])
+    before = [u1ml.batch_measure(b, i, correlator=False)[0]["plaquette"] for i in range(2)]
+    u1ml.batch_sweep(b, 1, 3)
+    after = [u1ml.batch_measure(b, i, correlator=False)[0]["plaquette"] for i in range(2)]
+    assert all(x != y for x, y in zip(before, after))
+    for i, (L, s, beta) in enumerate([(4, 8, 1.0), (6, 9, 0.9)]):
+        ob = oracle_mod.OracleLattice(L, L, beta, s, hot=True)
+        ob.sweep(1, 3)
+        assert abs(after[i] - ob.plaquette()) < 1e-13
