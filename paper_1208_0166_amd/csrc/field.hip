@@ -294,12 +294,45 @@ __device__ __forceinline__ void fft_line(double2* v, int stride) {
   for (int k = 0; k < N; ++k) v[k * stride] = y[k];
 }
 
+// The same transform (N even) by the two lanes h = 0, 1 of a lane pair
+// (adjacent lanes of one wavefront): lane h transforms the samples n = 2 m + h
+// in registers (N / 2 points), lane 1 applies exp(SIGN 2 pi i k / N), and one
+// radix-2 step through LDS combines the halves:
+//   X(k) = U_0(k) + w^k U_1(k),  X(k + N/2) = U_0(k) - w^k U_1(k).
+// A wavefront performs its LDS operations in issue order; the fence keeps
+// the compiler from moving the partner reads above the half write-back, and
+// each output depends on the partner value read at its position, so that
+// read always precedes the write.  Twice the lanes of fft_line per row, for
+// the same LDS.
+template <int N, int SIGN>
+__device__ __forceinline__ void fft_line_pair(double2* v, int stride, int h) {
+  constexpr int M = N / 2;
+  double2 y[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) y[fftreg::kPos<M>.v[m]] = v[(2 * m + h) * stride];
+  fftreg::run<M, SIGN>(y);
+  if (h) {
+#pragma unroll
+    for (int k = 1; k < M; ++k) y[k] = fftreg::cmulc(y[k], fftreg::kTw<N>.c[k], (double)SIGN * fftreg::kTw<N>.s[k]);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // both lanes' reads above are done
+#pragma unroll
+  for (int k = 0; k < M; ++k) v[(h * M + k) * stride] = y[k];
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // the halves are in LDS
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const double2 p = v[((1 - h) * M + k) * stride];
+    v[(h * M + k) * stride] = h ? fftreg::csub(p, y[k]) : fftreg::cadd(y[k], p);
+  }
+}
+
 // What[((k * n_rf + f) * ns + s) * L + x][p * L + q] = sum_{y,z} W(x, y, z) exp(+2 pi i (p y + q z) / L),
 // i.e. the transform of W at (-p, -q).  Block: (k, f, s, group of npb x planes).
 // The planes are built in LDS (coalesced reads), transformed along z by rows
-// (thread = (x, y)) and along y by columns (thread = (x, q)), and stored.
+// (a lane pair per (x, y)) and along y by columns (a lane pair per (x, q)),
+// and stored.
 template <int L>
-__global__ __launch_bounds__(256) void field_what_kernel(const LatDesc* __restrict__ lat,
+__global__ __launch_bounds__(512) void field_what_kernel(const LatDesc* __restrict__ lat,
                                                          const MLDesc* __restrict__ mlp,
                                                          const FieldLat* __restrict__ flp, FieldParams fp,
                                                          int sample0, int npb, const double2* __restrict__ mlbuf,
@@ -332,16 +365,17 @@ __global__ __launch_bounds__(256) void field_what_kernel(const LatDesc* __restri
         cmul(w[(size_t)(row + x) * fp.n_rf], make_double2(u.x * v.x + u.y * v.y, u.x * v.y - u.y * v.x));
   }
   __syncthreads();
-  const bool active = tid < nx * L;
-  const int xc = tid / L, t = tid - xc * L;
-  if (active) fft_line<L, 1>(pl + (xc * L + t) * L1, 1);  // row y = t, along z
+  // a lane pair per row, then per column (fft_line_pair)
+  const bool active = tid < 2 * nx * L;
+  const int xc = tid / (2 * L), t = (tid >> 1) % L, h = tid & 1;
+  if (active) fft_line_pair<L, 1>(pl + (xc * L + t) * L1, 1, h);  // row y = t, along z
   __syncthreads();
-  if (active) {
-    double2* col = pl + xc * L * L1 + t;  // column q = t, along y
-    fft_line<L, 1>(col, L1);
-    double2* dst = what + ((((size_t)k * fp.n_rf + f) * ns + s) * L + x0 + xc) * L * L + t;
-#pragma unroll
-    for (int p = 0; p < L; ++p) dst[p * L] = col[p * L1];
+  if (active) fft_line_pair<L, 1>(pl + xc * L * L1 + t, L1, h);  // column q = t, along y
+  __syncthreads();
+  double2* dst = what + ((((size_t)k * fp.n_rf + f) * ns + s) * L + x0) * L * L;
+  for (int i = tid; i < nx * L * L; i += blockDim.x) {
+    const int c = i / (L * L), pq = i - c * (L * L), p = pq / L, q = pq - p * L;
+    dst[(size_t)c * L * L + pq] = pl[(c * L + p) * L1 + q];
   }
 }
 
@@ -355,10 +389,10 @@ __global__ __launch_bounds__(256) void field_what_kernel(const LatDesc* __restri
 // transform over (y, z) of Z = O_c(2 j) + i O_c(2 j + 1) for sample
 // sample0 + k, inner slab s, from the stored slab sums O_c.  Block: (k, s, c,
 // group of np pairs); the pair planes are staged with 16-byte loads of
-// neighbouring x (pairs fastest), then np L threads transform rows (along z)
-// and columns (along y).
+// neighbouring x (pairs fastest), then np L lane pairs transform rows (along
+// z) and columns (along y).
 template <int L>
-__global__ __launch_bounds__(256) void field_ohat_kernel(const LatDesc* __restrict__ lat,
+__global__ __launch_bounds__(512) void field_ohat_kernel(const LatDesc* __restrict__ lat,
                                                          const FieldLat* __restrict__ flp, int sample0, int np,
                                                          const double* __restrict__ fbuf,
                                                          double2* __restrict__ zhat) {
@@ -377,11 +411,11 @@ __global__ __launch_bounds__(256) void field_ohat_kernel(const LatDesc* __restri
     zp[(pr * L + y) * L1 + z] = *(const double2*)(o + (size_t)(z * L + y) * L + 2 * (j0 + pr));
   }
   __syncthreads();
-  const bool active = tid < n * L;
-  const int pl = tid / L, t = tid - pl * L;
-  if (active) fft_line<L, -1>(zp + (pl * L + t) * L1, 1);  // rows, along z
+  const bool active = tid < 2 * n * L;  // a lane pair per row, then per column
+  const int pl = tid / (2 * L), t = (tid >> 1) % L, h = tid & 1;
+  if (active) fft_line_pair<L, -1>(zp + (pl * L + t) * L1, 1, h);  // rows, along z
   __syncthreads();
-  if (active) fft_line<L, -1>(zp + pl * L * L1 + t, L1);  // columns, along y
+  if (active) fft_line_pair<L, -1>(zp + pl * L * L1 + t, L1, h);  // columns, along y
   __syncthreads();
   double2* dst = zhat + ((((size_t)k * ns + s) * 6 + c) * NP + j0) * L2;
   for (int i = tid; i < n * L2; i += blockDim.x) {
@@ -518,8 +552,8 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
   const int npb_w = std::min<int>(L, (int)(kFxLds / plane_bytes));
   const int np_o = std::min<int>(L / 2, (int)(kFxLds / plane_bytes));  // pair planes per transform block
   const int n_ent = 2 * fp.n_rf * (int)L2;
-  const int thr_w = (npb_w * L + 63) / 64 * 64;
-  const int thr_o = std::min(256, (np_o * L + 63) / 64 * 64);
+  const int thr_w = (2 * npb_w * L + 63) / 64 * 64;  // lane pairs per row
+  const int thr_o = (2 * np_o * L + 63) / 64 * 64;
   const int ngroups_w = (L + npb_w - 1) / npb_w;
   const int ngroups_o = (L / 2 + np_o - 1) / np_o;
   const int nblk_e = (int)((((fp.n_rf + kZcF - 1) / kZcF) * 2 * L2 + 255) / 256);
