@@ -657,6 +657,9 @@ struct Engine {
         fb += 2ull * n_stored * fl.ns * L3 * fp.n_rf;
         fl.g = fb;
         fb += 2ull * fp.n_rf * 12 * L2;
+        fl.n_top = n_levels == 2 ? m.h_mls[i].ns[0] : 1;
+        fl.ptop = fb;
+        fb += 2ull * fl.n_top * fp.n_rf * L3;
         m.fout_off[i] = fo;
         fo += (uint64_t)fp.n_rf * 12 * L2;
         // contraction scratch: one sample's transformed planes plus the per-slab partial sums

@@ -99,10 +99,12 @@ hipError_t launch_ml_final(const LatDesc* lats, const MLDesc* mls, int n_lats, i
 // field insertion: per-lattice layout of the field buffer (offsets in doubles)
 struct FieldLat {
   int ns;         // inner slabs
+  int n_top;      // top-level slabs (two levels), else 1
   uint64_t oall;  // [n_samples][6][ns][L3] slab sums of the field operators
-  uint64_t tavg;  // double2 [n_outer][ns][L3][n_rf]
-  uint64_t w;     // double2 [n_outer][ns][L3][n_rf]
+  uint64_t tavg;  // double2 [n_stored][n_rf][ns][L3]
+  uint64_t w;     // double2 [n_stored][n_rf][ns][L3]
   uint64_t g;     // double2 [n_rf][2][6][L2] Fourier-space accumulator
+  uint64_t ptop;  // double2 [n_top][n_rf][L3] products of the other top slabs' averages
 };
 struct FieldParams {
   int n_rf;

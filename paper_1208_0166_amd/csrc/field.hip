@@ -17,7 +17,7 @@ namespace u1ml {
 
 namespace {
 
-// tavg[((m * ns + s) * L3 + x0) * n_rf + f] = average over the n_inner samples
+// tavg[((m * n_rf + f) * ns + s) * L3 + x0] = average over the n_inner samples
 // of stored outer iteration m of T(x0, rf[f]) in inner slab s
 __global__ void field_tavg_kernel(const LatDesc* __restrict__ lat, const MLDesc* __restrict__ mlp,
                                   const FieldLat* __restrict__ flp, FieldParams fp,
@@ -27,10 +27,10 @@ __global__ void field_tavg_kernel(const LatDesc* __restrict__ lat, const MLDesc*
   const FieldLat fl = *flp;
   const int item = blockIdx.x * blockDim.x + threadIdx.x;
   if (item >= fp.n_stored * fl.ns * d.L3 * fp.n_rf) return;
-  const int f = item % fp.n_rf;
-  const int x0 = (item / fp.n_rf) % d.L3;
-  const int s = (item / (fp.n_rf * d.L3)) % fl.ns;
-  const int m = item / (fp.n_rf * d.L3 * fl.ns);
+  const int x0 = item % d.L3;
+  const int s = (item / d.L3) % fl.ns;
+  const int f = (item / (d.L3 * fl.ns)) % fp.n_rf;
+  const int m = item / (d.L3 * fl.ns * fp.n_rf);
   // the slabs without the insertion take the correlator's lines: multihit
   // means for r >= 2 when enabled
   const uint64_t base = ml.multihit && fp.rf[f] >= 2 ? ml.ell_mh : ml.ell;
@@ -38,42 +38,59 @@ __global__ void field_tavg_kernel(const LatDesc* __restrict__ lat, const MLDesc*
   ((double2*)(fbuf + fl.tavg))[item] = inner_avg(ell, fp.n_inner, fl.ns, d.L3, s, x0, shift_x(d, x0, fp.rf[f]));
 }
 
-// weight of an insertion in inner slab s during outer iteration m:
-//   one level:  prod_{s' != s} [T]_{s'} / (n V)
-//   two levels: prod_{j != k} A_j * prod_{s' in k, s' != s} [T]_{s',m} / (n_0 n_1 V)
-// with k the top slab holding s and A_j the top-level averages.
-__global__ void field_weights_kernel(const LatDesc* __restrict__ lat, const MLDesc* __restrict__ mlp,
-                                     const FieldLat* __restrict__ flp, FieldParams fp,
-                                     const double2* __restrict__ accbuf, double* __restrict__ fbuf) {
+// ptop[(k * n_rf + f) * L3 + x0] = prod_{j != k} A_j(x0, rf[f]) / n_0^(n_top - 1)
+// over the other top-level slabs j (two levels; the final averages A_j are
+// the level-0 sums over the n_0 outer iterations); 1 for one level
+__global__ void field_ptop_kernel(const LatDesc* __restrict__ lat, const MLDesc* __restrict__ mlp,
+                                  const FieldLat* __restrict__ flp, FieldParams fp,
+                                  const double2* __restrict__ accbuf, double* __restrict__ fbuf) {
   const LatDesc d = *lat;
   const MLDesc ml = *mlp;
   const FieldLat fl = *flp;
+  const int ntop = fl.n_top;
   const int item = blockIdx.x * blockDim.x + threadIdx.x;
-  if (item >= fp.n_stored * fl.ns * d.L3 * fp.n_rf) return;
-  const int f = item % fp.n_rf;
-  const int x0 = (item / fp.n_rf) % d.L3;
-  const int s = (item / (fp.n_rf * d.L3)) % fl.ns;
-  const int m = item / (fp.n_rf * d.L3 * fl.ns);
-  const int children = fp.n_levels == 2 ? fl.ns / ml.ns[0] : fl.ns;
-  const int k = s / children;
-  const double2* tavg = (const double2*)(fbuf + fl.tavg);
-  double2 p = make_double2(1.0, 0.0);
-  for (int j = 0; j < children; ++j) {
-    const int sp = k * children + j;
-    if (sp == s) continue;
-    p = cmul(p, tavg[(((size_t)m * fl.ns + sp) * d.L3 + x0) * fp.n_rf + f]);
-  }
-  double norm = (double)fp.n_inner * (double)d.V2 * 2.0;
-  if (fp.n_levels == 2) {
-    const int ntop = ml.ns[0];
-    const double inv = 1.0 / (double)fp.n_outer;
-    for (int j = 0; j < ntop; ++j) {
+  if (item >= ntop * d.L3) return;
+  const int x0 = item % d.L3, k = item / d.L3;
+  const double inv = 1.0 / (double)fp.n_outer;
+  double2* out = (double2*)(fbuf + fl.ptop);
+  for (int f = 0; f < fp.n_rf; ++f) {
+    double2 p = make_double2(1.0, 0.0);
+    for (int j = 0; j < ntop && fp.n_levels == 2; ++j) {
       if (j == k) continue;
       const double2 a = accbuf[ml.acc[0] + ((size_t)j * d.L3 + x0) * ml.nR + fp.rf_k[f]];
       p = cmul(p, make_double2(a.x * inv, a.y * inv));
     }
-    norm *= (double)fp.n_outer;
+    out[((size_t)k * fp.n_rf + f) * d.L3 + x0] = p;
   }
+}
+
+// w[((m * n_rf + f) * ns + s) * L3 + x0] = weight of an insertion in inner
+// slab s during outer iteration m:
+//   one level:  prod_{s' != s} [T]_{s'} / (n V)
+//   two levels: prod_{j != k} A_j * prod_{s' in k, s' != s} [T]_{s',m} / (n_0 n_1 V)
+// with k the top slab holding s and A_j the top-level averages (ptop).
+__global__ void field_weights_kernel(const LatDesc* __restrict__ lat, const FieldLat* __restrict__ flp,
+                                     FieldParams fp, double* __restrict__ fbuf) {
+  const LatDesc d = *lat;
+  const FieldLat fl = *flp;
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= fp.n_stored * fp.n_rf * fl.ns * d.L3) return;
+  const int x0 = item % d.L3;
+  const int s = (item / d.L3) % fl.ns;
+  const int f = (item / (d.L3 * fl.ns)) % fp.n_rf;
+  const int m = item / (d.L3 * fl.ns * fp.n_rf);
+  const int children = fl.ns / fl.n_top;
+  const int k = s / children;
+  const double2* tavg = (const double2*)(fbuf + fl.tavg) + (size_t)m * fp.n_rf * fl.ns * d.L3;
+  double2 p = ((const double2*)(fbuf + fl.ptop))[((size_t)k * fp.n_rf + f) * d.L3 + x0];
+  const int first = (s / children) * children;
+  for (int j = 0; j < children; ++j) {
+    const int sp = first + j;
+    if (sp == s) continue;
+    p = cmul(p, tavg[((size_t)f * fl.ns + sp) * d.L3 + x0]);
+  }
+  double norm = (double)fp.n_inner * (double)d.V2 * 2.0;
+  if (fp.n_levels == 2) norm *= (double)fp.n_outer;
   ((double2*)(fbuf + fl.w))[item] = make_double2(p.x / norm, p.y / norm);
 }
 
@@ -124,7 +141,7 @@ __global__ __launch_bounds__(kDftThreads) void field_dft_kernel(const LatDesc* _
       const int x0 = (z * L + y) * L + x;
       const double2 u = e[x0], v = e[shift_x(d, x0, fp.rf[a])];
       const double2 t = make_double2(u.x * v.x + u.y * v.y, u.x * v.y - u.y * v.x);
-      buf[i] = cmul(w[(((size_t)m * ns + s) * d.L3 + x0) * fp.n_rf + a], t);
+      buf[i] = cmul(w[(((size_t)m * fp.n_rf + a) * ns + s) * d.L3 + x0], t);
     }
   }
   __syncthreads();
@@ -351,7 +368,7 @@ __global__ __launch_bounds__(512) void field_what_kernel(const LatDesc* __restri
   const int sample = sample0 + k, m = sample / fp.n_inner;
   const MLDesc ml = *mlp;
   const double2* e = mlbuf + ml.ell + ((size_t)sample * ns + s) * d.L3;
-  const double2* w = (const double2*)(fbuf + fl.w) + ((size_t)m * ns + s) * d.L3 * fp.n_rf + f;
+  const double2* w = (const double2*)(fbuf + fl.w) + (((size_t)m * fp.n_rf + f) * ns + s) * d.L3;
   const int r = fp.rf[f];
   const int tid = threadIdx.x;
   // W(x, y, z) = w(x0) conj(e(x0)) e(x0 + r), x0 = (z L + y) L + x, x fastest
@@ -362,7 +379,7 @@ __global__ __launch_bounds__(512) void field_what_kernel(const LatDesc* __restri
     const int row = (z * L + y) * L;
     const double2 u = e[row + x], v = e[row + xr];
     pl[(xc * L + y) * L1 + z] =
-        cmul(w[(size_t)(row + x) * fp.n_rf], make_double2(u.x * v.x + u.y * v.y, u.x * v.y - u.y * v.x));
+        cmul(w[row + x], make_double2(u.x * v.x + u.y * v.y, u.x * v.y - u.y * v.x));
   }
   __syncthreads();
   // a lane pair per row, then per column (fft_line_pair)
@@ -610,8 +627,9 @@ hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const Fie
   const int ns = hfl.ns;
   const uint64_t nt = (uint64_t)fp.n_stored * ns * L3 * fp.n_rf;
   hipLaunchKernelGGL(field_tavg_kernel, dim3(blocks_for(nt, 256)), dim3(256), 0, st, lat, ml, fl, fp, mlbuf, fbuf);
-  hipLaunchKernelGGL(field_weights_kernel, dim3(blocks_for(nt, 256)), dim3(256), 0, st, lat, ml, fl, fp, accbuf,
+  hipLaunchKernelGGL(field_ptop_kernel, dim3(blocks_for((uint64_t)hfl.n_top * L3, 256)), dim3(256), 0, st, lat, ml, fl, fp, accbuf,
                      fbuf);
+  hipLaunchKernelGGL(field_weights_kernel, dim3(blocks_for(nt, 256)), dim3(256), 0, st, lat, fl, fp, fbuf);
   double2* G = (double2*)(fbuf + hfl.g);
   const uint64_t ng = (uint64_t)fp.n_rf * 12 * L2;
   if (zero_g) hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(ng, 256)), dim3(256), 0, st, G, ng);
