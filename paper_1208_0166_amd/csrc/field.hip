@@ -529,6 +529,31 @@ __global__ __launch_bounds__(256) void field_zcon_kernel(const FieldLat* __restr
   }
 }
 
+// F = L^-2 sum_{p,q} G(p, q) exp(+2 pi i (p dy + q dz) / L) for every
+// (r_f, plane, c) plane of G (the field_final_kernel sum by row and column
+// FFTs): block per plane, a lane pair per row, then per column.
+template <int L>
+__global__ __launch_bounds__(64) void field_final_fft_kernel(const double2* __restrict__ G, double2* __restrict__ F) {
+  __shared__ double2 pl[L * (L + 1)];
+  constexpr int L1 = L + 1, L2 = L * L;
+  const double2* g = G + (size_t)blockIdx.x * L2;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < L2; i += blockDim.x) pl[(i / L) * L1 + i % L] = g[i];
+  __syncthreads();
+  const bool active = tid < 2 * L;
+  const int t = tid >> 1, h = tid & 1;
+  if (active) fft_line_pair<L, 1>(pl + t * L1, 1, h);  // along q
+  __syncthreads();
+  if (active) fft_line_pair<L, 1>(pl + t, L1, h);  // along p
+  __syncthreads();
+  const double inv = 1.0 / (double)L2;
+  double2* out = F + (size_t)blockIdx.x * L2;
+  for (int i = tid; i < L2; i += blockDim.x) {
+    const double2 v = pl[(i / L) * L1 + i % L];
+    out[i] = make_double2(v.x * inv, v.y * inv);
+  }
+}
+
 // G[((f * 2 + plane) * 6 + c) * L2 + pq] += sum over (k, s) of part, in four
 // interleaved partial sums (fixed order) so that four loads are in flight
 __global__ void field_gsum_kernel(FieldParams fp, int L, int ns, int nk, const double2* __restrict__ part,
@@ -563,7 +588,7 @@ __global__ void field_gsum_kernel(FieldParams fp, int L, int ns, int nk, const d
 template <int L>
 hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, int ns, FieldParams fp,
                                 const double2* mlbuf, const double* fbuf, double2* scratch, size_t scratch_elems,
-                                double2* G, hipStream_t st) {
+                                double2* G, double2* F, bool finalize, hipStream_t st) {
   const uint64_t L3 = (uint64_t)L * L * L, L2 = (uint64_t)L * L;
   const size_t plane_bytes = (size_t)L * (L + 1) * sizeof(double2);  // LDS rows padded to L + 1
   const int npb_w = std::min<int>(L, (int)(kFxLds / plane_bytes));
@@ -592,12 +617,13 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
     hipLaunchKernelGGL(field_gsum_kernel, dim3(blocks_for(6 * (uint64_t)n_ent, 64)), dim3(64), 0, st, fp, L, ns, nk,
                        part, G);
   }
+  if (finalize) hipLaunchKernelGGL(field_final_fft_kernel<L>, dim3(fp.n_rf * 12), dim3(64), 0, st, G, F);
   return hipGetLastError();
 }
 
 // the fast path for lattice size L: one of the instantiated lengths
 typedef hipError_t (*FastContract)(const LatDesc*, const MLDesc*, const FieldLat*, int, FieldParams, const double2*,
-                                   const double*, double2*, size_t, double2*, hipStream_t);
+                                   const double*, double2*, size_t, double2*, double2*, bool, hipStream_t);
 FastContract fast_contract_for(int L) {
   if (L > kFxMaxL) return nullptr;
   switch (L) {
@@ -634,10 +660,7 @@ hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const Fie
   const uint64_t ng = (uint64_t)fp.n_rf * 12 * L2;
   if (zero_g) hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(ng, 256)), dim3(256), 0, st, G, ng);
   if (FastContract fc = general ? nullptr : fast_contract_for(L)) {
-    const hipError_t e = fc(lat, ml, fl, ns, fp, mlbuf, fbuf, scratch, scratch_elems, G, st);
-    if (e != hipSuccess) return e;
-    if (finalize) hipLaunchKernelGGL(field_final_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, G, F);
-    return hipGetLastError();
+    return fc(lat, ml, fl, ns, fp, mlbuf, fbuf, scratch, scratch_elems, G, F, finalize, st);
   }
   // general path: both transforms stored, contraction by pq tiles
   // scratch per chunk: What [nk][n_rf][ns][L3], Ohat [nk][6][ns][L3], part [nk][n_rf][ns][12][L2]
