@@ -297,7 +297,7 @@ __global__ void field_final_kernel(FieldParams fp, int L, const double2* __restr
 // (field_zcon_kernel),
 //   Ohat_a(k) = (Z(k) + conj Z(-k)) / 2,   Ohat_b(k) = (Z(k) - conj Z(-k)) / 2i.
 // ---------------------------------------------------------------------------
-constexpr int kFxMaxL = 32;
+constexpr int kFxMaxL = 48;
 constexpr size_t kFxLds = 64512;  // LDS per block of field_what_kernel (bytes)
 
 // in-place FFT of the N values v[i * stride] (LDS)
@@ -533,7 +533,7 @@ __global__ __launch_bounds__(256) void field_zcon_kernel(const FieldLat* __restr
 // (r_f, plane, c) plane of G (the field_final_kernel sum by row and column
 // FFTs): block per plane, a lane pair per row, then per column.
 template <int L>
-__global__ __launch_bounds__(64) void field_final_fft_kernel(const double2* __restrict__ G, double2* __restrict__ F) {
+__global__ __launch_bounds__(128) void field_final_fft_kernel(const double2* __restrict__ G, double2* __restrict__ F) {
   __shared__ double2 pl[L * (L + 1)];
   constexpr int L1 = L + 1, L2 = L * L;
   const double2* g = G + (size_t)blockIdx.x * L2;
@@ -617,7 +617,8 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
     hipLaunchKernelGGL(field_gsum_kernel, dim3(blocks_for(6 * (uint64_t)n_ent, 64)), dim3(64), 0, st, fp, L, ns, nk,
                        part, G);
   }
-  if (finalize) hipLaunchKernelGGL(field_final_fft_kernel<L>, dim3(fp.n_rf * 12), dim3(64), 0, st, G, F);
+  if (finalize)
+    hipLaunchKernelGGL(field_final_fft_kernel<L>, dim3(fp.n_rf * 12), dim3((2 * L + 63) / 64 * 64), 0, st, G, F);
   return hipGetLastError();
 }
 
@@ -639,6 +640,9 @@ FastContract fast_contract_for(int L) {
     case 24: return launch_fast_contract<24>;
     case 30: return launch_fast_contract<30>;
     case 32: return launch_fast_contract<32>;
+    case 36: return launch_fast_contract<36>;
+    case 40: return launch_fast_contract<40>;
+    case 48: return launch_fast_contract<48>;
     default: return nullptr;
   }
 }

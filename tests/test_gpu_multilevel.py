@@ -144,7 +144,8 @@ def test_batch_multilevel_with_field_matches_oracle(oracle_mod):
 
 
 @pytest.mark.parametrize("L,rf", [(10, [2, 3]), (12, [2, 3]), (20, [2, 3]), (32, [2, 3]),
-                                  (24, list(range(1, 13))), (32, [1, 2, 5, 7, 16])])
+                                  (24, list(range(1, 13))), (32, [1, 2, 5, 7, 16]),
+                                  (36, [5]), (40, [1, 8]), (48, [2, 4, 6])])
 def test_fused_field_contraction_matches_general(L, rf):
     # the fused contraction (register FFTs of radices 2, 3, 4, 5) against the
     # general one (stored direct transforms) on the same chain; the long r
