@@ -327,6 +327,8 @@ def main():
                    "multihit": args.multihit},
         "samples_per_s": main_run["samples_per_s"],
         "samples_per_step": samples_per_step() * R,
+        # complete two-level multilevel estimates (one per chain per step)
+        "multilevel_estimates_per_s": R * args.steps / (main_run["ms_step"] * 1e-3 * args.steps),
         "chain_updates_per_step": R * sum(chain_updates_per_step()),
         "streams": args.streams,
         "group0_phase_ms": {"sweeps": main_run["ms_sweeps"], "multilevel": main_run["ms_ml"]},

@@ -127,7 +127,10 @@ int u1ml_sweep(u1ml_lattice *lat, int n_metro, int n_or);
  *     field profile is measured; each must appear in r_list.  n_rf > 0
  *     requires n_levels <= 2 and L <= 62; every inner sample's time-line sums and field
  *     slab sums are then kept in device memory (56 (T/th_inner) L^3 bytes
- *     per sample) and contracted with the final weights at the end.
+ *     per sample) and contracted with the final weights at the end.  A
+ *     two-level run whose samples would take more than 60 % of the free
+ *     device memory is run twice over the same updates instead, keeping one
+ *     outer iteration's samples (see u1ml_set_debug, flag 8).
  * The chain continues from the updated links (no restore).  Results are
  * kept on the device until u1ml_measure.  Asynchronous; EINVAL on bad sizes. */
 int u1ml_multilevel(u1ml_lattice *lat, int n_levels, const int *slab_sizes, const int *n_sub, int n_metro,
