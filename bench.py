@@ -111,7 +111,7 @@ def cpu_baseline(seconds: float):
                       f"in {el_ml:.1f} s"}
 
 
-def run_chain(u1ml, torch, prec, R, rf, steps, warmup, n_streams=1, multihit=False):
+def run_chain(u1ml, torch, prec, R, rf, steps, warmup, n_streams=1, multihit=False, squared=False, symmetric=False):
     """Build R independent 24^4 chains split into n_streams groups (one batch,
     or one lattice, per group, each on a stream of its own), thermalise, and
     time `steps` steps; the groups' launches overlap on the GPU.  Returns a
@@ -130,8 +130,9 @@ def run_chain(u1ml, torch, prec, R, rf, steps, warmup, n_streams=1, multihit=Fal
             lat = u1ml.batch_create([L] * n, [T] * n, [BETA] * n, seeds, start=u1ml.COLD, precision=prec,
                                     stream=st.cuda_stream)
             sw = (lambda lt: lambda: u1ml.batch_sweep(lt, 1, 3))(lat)
-        if multihit:
-            (u1ml.set_estimator if n == 1 else u1ml.batch_set_estimator)(lat, multihit=True)
+        if multihit or squared or symmetric:
+            (u1ml.set_estimator if n == 1 else u1ml.batch_set_estimator)(lat, multihit=multihit,
+                                                                          field_squared=squared, symmetric=symmetric)
         groups.append({"lat": lat, "sw": sw, "st": st, "n": n})
         first += n
     for _ in range(N_THERM):
@@ -259,6 +260,9 @@ def main():
                     help="the replicas are split into this many batches, each on a stream of its own")
     ap.add_argument("--multihit", action="store_true",
                     help="multihit means for the correlator lines at r >= 2 (the paper's potential)")
+    ap.add_argument("--squared", action="store_true", help="insert the squared field components of Eq. (6)")
+    ap.add_argument("--symmetric", action="store_true",
+                    help="correlator averaged over separations along +-x, +-y, +-z")
     ap.add_argument("--counters", action="store_true", help="short run for hardware-counter passes")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -283,7 +287,8 @@ def main():
     rf = [] if args.no_field else RF_LIST
     R = args.replicas
 
-    main_run = run_chain(u1ml, torch, prec, R, rf, args.steps, args.warmup, args.streams, args.multihit)
+    main_run = run_chain(u1ml, torch, prec, R, rf, args.steps, args.warmup, args.streams, args.multihit,
+                         args.squared, args.symmetric)
 
     # dominant kernel: the class pass (Metropolis or OR, 9 words per update),
     # timed alone on one stream: N_BETWEEN compound sweeps of 4 x 8 class passes
@@ -324,7 +329,7 @@ def main():
                                "r=1..12, E/B mid-plane profiles at r=2,4,6",
                    "lattice": [L, L, L, T], "beta": BETA, "levels": LEVELS, "n_sub": N_SUB,
                    "r": [1, 12], "field_r": rf, "accumulate": "f64", "replicas": R, "streams": args.streams,
-                   "multihit": args.multihit},
+                   "multihit": args.multihit, "field_squared": args.squared, "symmetric": args.symmetric},
         "samples_per_s": main_run["samples_per_s"],
         "samples_per_step": samples_per_step() * R,
         # complete two-level multilevel estimates (one per chain per step)
