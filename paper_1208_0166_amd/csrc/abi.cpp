@@ -680,16 +680,16 @@ struct Engine {
     MLState& m = ml;
     const int inner = m.n_levels - 1;
     if (child == inner && !fold_general) {
-      int max_items = 0;
+      int threads = 64;
       size_t max_lds = 0;
       for (int i = 0; i < n_lats; ++i) {
         const int nsp = parent == m.n_levels ? 1 : m.h_mls[i].ns[parent];
         const int children = m.h_mls[i].ns[child] / nsp;
-        max_items = std::max(max_items, h_lats[i].L * m.h_mls[i].n_r);
+        threads = std::max(threads, ml_fold_rows_threads(h_lats[i].L, m.h_mls[i].n_r));
         max_lds = std::max(max_lds, (size_t)(m.h_mls[i].multihit ? 2 : 1) * children * m.n[child] * h_lats[i].L *
                                         sizeof(double2));
       }
-      if (max_items <= ml_fold_rows_max_items() && max_lds <= ml_fold_rows_max_lds()) {
+      if (max_lds <= ml_fold_rows_max_lds()) {
         std::vector<int> rows;
         for (int i = 0; i < n_lats; ++i) {
           const int nsp = parent == m.n_levels ? 1 : m.h_mls[i].ns[parent];
@@ -697,8 +697,6 @@ struct Engine {
         }
         Table* t;
         U1_TRY(table(rows, 1, &t));
-        const int per = (max_items + 1023) / 1024;  // items per thread, <= 4
-        const int threads = ((max_items + per - 1) / per + 63) / 64 * 64;
         U1_HIP(launch_ml_fold_rows(lats.as<LatDesc>(), m.mls.as<MLDesc>(), bt(t), threads, max_lds, child, parent,
                                    m.n_levels, m.n[child], sample_base, m.rvals.as<int>(), m.mlbuf.as<double2>(),
                                    m.accbuf.as<double2>(), stream));

@@ -83,14 +83,14 @@ hipError_t launch_ml_lines(int prec, const void* links, const LatDesc* lats, con
 hipError_t launch_ml_fold(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int child_level, int parent_level,
                           int n_levels, int child_is_inner, int n_child, int sample_base, const int* rvals,
                           const double2* mlbuf, double2* accbuf, hipStream_t st);
-// the innermost fold by x-rows: bt has one block per (parent slab, (y, z) row)
-// of every lattice; threads * 4 >= L * nR of every lattice (at most
-// ml_fold_rows_max_items()); lds = children * n_child * max L complex values
-// (at most ml_fold_rows_max_lds() bytes)
+// the innermost fold by rows: bt has one block per (parent slab, axis, row)
+// of every lattice; threads = ml_fold_rows_threads(L, n_r) for the largest
+// lattice; lds = children * n_child * max L complex values, twice with
+// multihit (at most ml_fold_rows_max_lds() bytes)
 hipError_t launch_ml_fold_rows(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int threads, size_t lds,
                                int child_level, int parent_level, int n_levels, int n_child, int sample_base,
                                const int* rvals, const double2* mlbuf, double2* accbuf, hipStream_t st);
-int ml_fold_rows_max_items();
+int ml_fold_rows_threads(int L, int n_r);
 size_t ml_fold_rows_max_lds();
 hipError_t launch_ml_zero(double2* accbuf, uint64_t n, hipStream_t st);
 hipError_t launch_ml_final(const LatDesc* lats, const MLDesc* mls, int n_lats, int max_r, int top_level,

@@ -303,19 +303,21 @@ __global__ void ml_fold_kernel(const LatDesc* __restrict__ lats, const MLDesc* _
 // row along a): the rows of all stored samples of all children of S are
 // staged in LDS at once (children * n_child * L values, twice with multihit),
 // so every time line is read from memory once instead of once per
-// separation.  Threads own up to kFoldItems items (position j along the row,
-// separation k of the axis) with k fastest (so the accumulator updates are
-// contiguous); the sample and child order of the sums is that of
-// ml_fold_kernel, so both give the same bits.  Rows along x are contiguous;
-// rows along y and z are strided by L and L^2.
-constexpr int kFoldItems = 4;
+// separation.  A thread owns one position j along the row and up to kFoldK
+// separations of the axis, so the line at j is read once per sample for all
+// of them; the sample and child order of every sum is that of ml_fold_kernel,
+// so both give the same bits.  Rows along x are contiguous; rows along y and
+// z are strided by L and L^2.
+constexpr int kFoldK = 8;
 constexpr size_t kFoldLds = 49152;  // bytes of staged rows per block
 __global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls,
                                     const int2* __restrict__ blocks, int child_level, int parent_level, int n_levels,
                                     int n_child, int sample_base, const int* __restrict__ rvals,
                                     const double2* __restrict__ mlbuf, double2* __restrict__ accbuf) {
   extern __shared__ double2 rowbuf[];  // [children][n_child][L]
-  const int2 bk = blocks[blockIdx.x];
+  // neighbouring rows (adjacent in memory) on one XCD, so that its L2 and
+  // memory requests see contiguous stretches of the time lines
+  const int2 bk = blocks[xcd_block(blockIdx.x, gridDim.x)];
   const LatDesc d = lats[bk.x];
   // fields read through the pointer: a local copy indexed by a run-time level
   // would live in scratch memory
@@ -332,7 +334,7 @@ __global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDe
   const int ra = row % L, rb = row / L;
   const int stride = axis == 0 ? 1 : (axis == 1 ? L : L2);
   const int base = axis == 0 ? row * L : (axis == 1 ? rb * L2 + ra : rb * L + ra);
-  const int nitems = L * n_r;
+  const int ngroups = (n_r + kFoldK - 1) / kFoldK;
   const int per_child = n_child * L;
   // rows of the plain lines, then (multihit) rows of the multihit lines
   const int staged = children * per_child;
@@ -344,30 +346,48 @@ __global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDe
   }
   __syncthreads();
   const double inv = 1.0 / (double)n_child;
+  for (int item = threadIdx.x; item < L * ngroups; item += blockDim.x) {
+    const int x0 = item / ngroups, k0 = (item - x0 * ngroups) * kFoldK;
+    const int kn = min(kFoldK, n_r - k0);
+    int xr[kFoldK];
+    bool mh[kFoldK];
+    double2 prod[kFoldK];
 #pragma unroll
-  for (int j = 0; j < kFoldItems; ++j) {
-    const int item = (int)threadIdx.x + j * (int)blockDim.x;
-    if (item < nitems) {
-      const int x0 = item / n_r, k = axis * n_r + (item - x0 * n_r);
-      const int r = rvals[r_off + k] & 0xffff;
-      int xr = x0 + r;
-      xr -= xr >= L ? L : 0;
+    for (int j = 0; j < kFoldK; ++j) {
+      const int r = j < kn ? rvals[r_off + axis * n_r + k0 + j] & 0xffff : 0;
+      const int t = x0 + r;
+      xr[j] = t >= L ? t - L : t;
       // multihit lines for r >= 2 (the two lines share no plaquette)
-      const double2* rows = rowbuf + (multihit && r >= 2 ? staged : 0);
-      double2 prod = make_double2(1.0, 0.0);
-      for (int c = 0; c < children; ++c) {
-        const double2* e = rows + c * per_child;
-        double2 avg = make_double2(0.0, 0.0);
-        for (int i = 0; i < n_child; ++i) {
-          const double2 u = e[i * L + x0], v = e[i * L + xr];
-          avg.x += u.x * v.x + u.y * v.y;
-          avg.y += u.x * v.y - u.y * v.x;
+      mh[j] = multihit && r >= 2;
+      prod[j] = make_double2(1.0, 0.0);
+    }
+    for (int c = 0; c < children; ++c) {
+      const double2* ep = rowbuf + c * per_child;
+      const double2* eh = ep + (multihit ? staged : 0);
+      double2 avg[kFoldK];
+#pragma unroll
+      for (int j = 0; j < kFoldK; ++j) avg[j] = make_double2(0.0, 0.0);
+      for (int i = 0; i < n_child; ++i) {
+        const double2 u = ep[i * L + x0], uh = eh[i * L + x0];
+#pragma unroll
+        for (int j = 0; j < kFoldK; ++j) {
+          if (j < kn) {
+            const double2 a = mh[j] ? uh : u, v = (mh[j] ? eh : ep)[i * L + xr[j]];
+            avg[j].x += a.x * v.x + a.y * v.y;
+            avg[j].y += a.x * v.y - a.y * v.x;
+          }
         }
-        prod = cmul(prod, make_double2(avg.x * inv, avg.y * inv));
       }
-      double2* pp = accbuf + acc_parent + ((size_t)S * d.L3 + (size_t)base + (size_t)x0 * stride) * nR + k;
-      pp->x += prod.x;
-      pp->y += prod.y;
+#pragma unroll
+      for (int j = 0; j < kFoldK; ++j) prod[j] = cmul(prod[j], make_double2(avg[j].x * inv, avg[j].y * inv));
+    }
+    double2* pp = accbuf + acc_parent + ((size_t)S * d.L3 + (size_t)base + (size_t)x0 * stride) * nR + axis * n_r + k0;
+#pragma unroll
+    for (int j = 0; j < kFoldK; ++j) {
+      if (j < kn) {
+        pp[j].x += prod[j].x;
+        pp[j].y += prod[j].y;
+      }
     }
   }
 }
@@ -538,7 +558,10 @@ hipError_t launch_ml_fold_rows(const LatDesc* lats, const MLDesc* mls, BlockTabl
   return hipGetLastError();
 }
 
-int ml_fold_rows_max_items() { return kFoldItems * 1024; }
+int ml_fold_rows_threads(int L, int n_r) {
+  const int items = L * ((n_r + kFoldK - 1) / kFoldK);
+  return std::min(256, (items + 63) / 64 * 64);
+}
 size_t ml_fold_rows_max_lds() { return kFoldLds; }
 
 hipError_t launch_ml_zero(double2* accbuf, uint64_t n, hipStream_t st) {
