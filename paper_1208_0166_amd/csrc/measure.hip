@@ -205,7 +205,7 @@ __global__ void ml_lines_kernel(const R* __restrict__ links, const LatDesc* __re
   const MLDesc* m = mls + bk.x;
   const size_t at = ((size_t)sample * ns + s) * d.L3 + x3;
   // exp(i l), l = sum of theta_0 over the slab's times: the slab product of U_0
-  mlbuf[m->ell + at] = cexpi(time_line(links, d, x3, s * inner_th, inner_th));
+  store_stream(mlbuf + m->ell + at, cexpi(time_line(links, d, x3, s * inner_th, inner_th)));
   if (m->multihit) {
     Site st;
     st.x = x3 % d.L;
@@ -216,7 +216,7 @@ __global__ void ml_lines_kernel(const R* __restrict__ links, const LatDesc* __re
       st.t = t;
       p = cmul(p, multihit_mean(links, d, st));
     }
-    mlbuf[m->ell_mh + at] = p;
+    store_stream(mlbuf + m->ell_mh + at, p);
   }
 }
 
@@ -451,7 +451,7 @@ __global__ void field_o_kernel(const R* __restrict__ links, const LatDesc* __res
   }
   const double pre = SQ ? d.beta : d.sqrt_beta;
   double* out = fbuf + fl.oall + (size_t)sample * 6 * fl.ns * d.L3;
-  for (int c = 0; c < 6; ++c) out[((size_t)c * fl.ns + s) * d.L3 + y3] = pre * o[c];
+  for (int c = 0; c < 6; ++c) store_stream(out + ((size_t)c * fl.ns + s) * d.L3 + y3, pre * o[c]);
 }
 
 // ---------------------------------------------------------------------------

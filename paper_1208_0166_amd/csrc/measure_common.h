@@ -144,6 +144,15 @@ __device__ __forceinline__ int shift_axis(const LatDesc& d, int x3, int v) {
   return x3 + (cr - c) * stride;
 }
 
+// Stores of per-sample data that is read back only at the end of an outer
+// iteration or of the run: marked non-temporal so that they do not displace
+// the lattices from the caches.
+__device__ __forceinline__ void store_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_stream(double2* p, double2 v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
