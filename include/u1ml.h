@@ -101,6 +101,16 @@ void u1ml_default_options(u1ml_options *opt);
  * of 8 (FP64) or 4 (FP32) bytes).  Pure function; 0 for invalid sizes. */
 size_t u1ml_link_bytes(int L, int T, int precision);
 
+/* Bytes of device memory a u1ml_multilevel run of one L^3 x T lattice with
+ * these arguments and estimator flags allocates for its workspace (time
+ * lines, level accumulators, correlator, and with n_rf > 0 the stored field
+ * sums, weights, transforms and contraction scratch), every inner sample
+ * kept.  Pure function for planning; 0 for invalid arguments.  A run whose
+ * field samples would not fit is replayed with one outer iteration stored
+ * (u1ml_multilevel) and then needs less. */
+size_t u1ml_workspace_bytes(int L, int T, int n_levels, const int *slab_sizes, const int *n_sub, int n_r, int n_rf,
+                            unsigned estimator);
+
 /* Create a lattice (Sec. 2, Sec. 2.1): L, T even, 2 <= L, T <= 256,
  * L^4 T < 2^32; beta >= 0 finite (beta = 1/g^2 of Eq. (3)).
  * Starts cold or hot per opt (NULL = defaults) and sets pass_id = 0.
@@ -240,6 +250,11 @@ int u1ml_load(u1ml_lattice *lat, const char *path);
 
 /* Wait for all queued work of the lattice. */
 int u1ml_synchronize(u1ml_lattice *lat);
+
+/* Bytes the lattice currently holds for multilevel workspaces (the buffers
+ * counted by u1ml_workspace_bytes; they grow to the largest run so far and
+ * are kept for the next).  0 for NULL. */
+size_t u1ml_device_bytes(const u1ml_lattice *lat);
 
 /* Free the lattice and everything the library allocated for it. */
 void u1ml_destroy(u1ml_lattice *lat);

@@ -1114,6 +1114,42 @@ size_t u1ml_link_bytes(int L, int T, int precision) {
   return (size_t)4 * L * L * L * T * (precision == U1ML_FP64 ? 8 : 4);
 }
 
+size_t u1ml_workspace_bytes(int L, int T, int n_levels, const int* slab_sizes, const int* n_sub, int n_r, int n_rf,
+                            unsigned estimator) {
+  if (L < 2 || T < 2 || (L & 1) || (T & 1) || n_levels < 1 || n_levels > U1ML_MAX_LEVELS || !slab_sizes ||
+      !n_sub || n_r < 1 || n_rf < 0 || n_rf > U1ML_MAX_FIELD_R || (n_rf > 0 && n_levels > 2))
+    return 0;
+  for (int l = 0; l < n_levels; ++l)
+    if (slab_sizes[l] < 1 || T % slab_sizes[l] || n_sub[l] < 1 || (l > 0 && slab_sizes[l - 1] % slab_sizes[l]))
+      return 0;
+  // the layout of the multilevel workspace (every inner sample kept when
+  // the field is inserted), as the multilevel set-up allocates it
+  const int inner = n_levels - 1;
+  const int n_outer = n_levels == 2 ? n_sub[0] : 1;
+  const uint64_t kept = n_rf > 0 ? (uint64_t)n_outer * n_sub[inner] : (uint64_t)n_sub[inner];
+  const uint64_t L3 = (uint64_t)L * L * L, L2 = (uint64_t)L * L, ns_in = (uint64_t)(T / slab_sizes[inner]);
+  const uint64_t nR = (uint64_t)((estimator & U1ML_SYMMETRIC) ? 3 : 1) * n_r;
+  const uint64_t ell = kept * ns_in * L3 * ((estimator & U1ML_MULTIHIT) ? 2 : 1);
+  uint64_t acc = L3 * nR;
+  for (int l = 0; l < inner; ++l) acc += (uint64_t)(T / slab_sizes[l]) * L3 * nR;
+  size_t bytes = (ell + acc) * sizeof(double2) + (size_t)n_r * 2 * sizeof(double);
+  if (n_rf > 0) {
+    const uint64_t n_top = n_levels == 2 ? (uint64_t)(T / slab_sizes[0]) : 1;
+    const uint64_t fb = kept * 6 * ns_in * L3 + 4ull * n_outer * ns_in * L3 * n_rf + 2ull * n_rf * 12 * L2 +
+                        2ull * n_top * n_rf * L3;
+    const uint64_t per_sample = (uint64_t)(n_rf + 6) * ns_in * L3 + (uint64_t)n_rf * ns_in * 12 * L2;
+    const uint64_t scratch = std::max<uint64_t>(per_sample, kFieldScratchBytes / sizeof(double2));
+    bytes += fb * sizeof(double) + ((uint64_t)n_rf * 12 * L2 + scratch) * sizeof(double2);
+  }
+  return bytes;
+}
+
+size_t u1ml_device_bytes(const u1ml_lattice* lat) {
+  if (!lat) return 0;
+  const MLState& m = lat->e.ml;
+  return m.mlbuf.bytes + m.accbuf.bytes + m.corr.bytes + m.fbuf.bytes + m.fout.bytes + m.scratch.bytes;
+}
+
 int u1ml_init_lattice(int L, int T, double beta, uint64_t seed, const u1ml_options* opt, u1ml_lattice** out) {
   if (!out) return fail(U1ML_EINVAL, "out is NULL");
   *out = nullptr;

@@ -70,6 +70,8 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "u1ml_default_options": (None, [C.POINTER(Options)]),
         "u1ml_link_bytes": (SZ, [I, I, I]),
+        "u1ml_workspace_bytes": (SZ, [I, I, I, ip, ip, I, I, C.c_uint]),
+        "u1ml_device_bytes": (SZ, [P]),
         "u1ml_init_lattice": (I, [I, I, D, U64, C.POINTER(Options), C.POINTER(P)]),
         "u1ml_sweep": (I, [P, I, I]),
         "u1ml_multilevel": (I, [P, I, ip, ip, I, I, I, ip, I, ip]),
@@ -271,6 +273,19 @@ def ensemble_read(lat: Lattice, correlator: bool = True, field_profile: bool = F
     return _ensemble_read(lambda *a: lib.u1ml_ensemble_info(lat.handle, *a),
                           lambda *a: lib.u1ml_ensemble_read(lat.handle, *a), lat.L, correlator, field_profile,
                           connected)
+
+
+def workspace_bytes(L: int, T: int, slab_sizes, n_sub, n_r: int, n_rf: int = 0, multihit: bool = False,
+                    field_squared: bool = False, symmetric: bool = False) -> int:
+    """Device bytes of a multilevel run's workspace (u1ml_workspace_bytes)."""
+    th, thp = _ints(slab_sizes)
+    ns, nsp = _ints(n_sub)
+    return load_library().u1ml_workspace_bytes(L, T, len(th), thp, nsp, n_r, n_rf,
+                                               _estimator_flags(multihit, field_squared, symmetric))
+
+
+def device_bytes(lat: Lattice) -> int:
+    return load_library().u1ml_device_bytes(lat.handle)
 
 
 def plain_correlator(lat: Lattice, r_list):

@@ -67,3 +67,20 @@ def test_null_handles_rejected():
     assert lib.u1ml_init_lattice(4, 4, 1.0, 1, None, None) == u1ml.EINVAL
     lib.u1ml_destroy(None)
     lib.u1ml_batch_destroy(None)
+
+
+def test_workspace_bytes_is_a_pure_size_function():
+    wb = u1ml.workspace_bytes
+    assert wb(3, 8, [4, 2], [2, 3], 3) == 0            # odd L
+    assert wb(4, 8, [3], [2], 3) == 0                  # slab does not divide T
+    assert wb(4, 8, [4, 2, 1], [1, 1, 1], 3, n_rf=2) == 0  # field with three levels
+    base = wb(4, 8, [4, 2], [2, 3], 3)
+    assert base > 0
+    # multihit doubles the stored lines; the symmetric correlator triples the
+    # accumulators; the field adds the stored sums and at least the scratch
+    L3, kept = 4 ** 3, 3
+    assert wb(4, 8, [4, 2], [2, 3], 3, multihit=True) == base + kept * 4 * L3 * 16
+    acc = (2 * L3 * 3 + L3 * 3) * 16
+    assert wb(4, 8, [4, 2], [2, 3], 3, symmetric=True) == base + 2 * acc
+    assert wb(4, 8, [4, 2], [2, 3], 3, n_rf=2) > base + (512 << 20)
+    assert wb(4, 8, [4, 2], [2, 3], 3, n_rf=2, field_squared=True) == wb(4, 8, [4, 2], [2, 3], 3, n_rf=2)
