@@ -39,13 +39,14 @@ def _chains(args):
     prec = u1ml.FP32 if args.prec == "fp32" else u1ml.FP64
     R = args.replicas
     b = u1ml.batch_create([args.L] * R, [args.L] * R, [args.beta] * R, [args.seed + i for i in range(R)],
-                          start=u1ml.COLD, precision=prec)
+                          start=u1ml.HOT if args.start == "hot" else u1ml.COLD, precision=prec)
     t0 = time.time()
     for _ in range(args.therm):
         u1ml.batch_sweep(b, 1, 3)
     u1ml.batch_synchronize(b)
-    _say(f"[study] {R} chains of {args.L}^4 beta={args.beta} {args.prec}: {args.therm} thermalisation sweeps "
-         f"in {time.time() - t0:.1f} s")
+    obs = [u1ml.batch_measure(b, i, correlator=False)[0]["plaquette"] for i in range(R)]
+    _say(f"[study] {R} chains of {args.L}^4 beta={args.beta} {args.prec}, {args.start} start: {args.therm} "
+         f"thermalisation sweeps in {time.time() - t0:.1f} s, plaquette {np.mean(obs):.5f} +- {np.std(obs):.5f}")
     return b
 
 
@@ -87,7 +88,8 @@ def potential_study(args):
                 [an.fit_potential(r_fit, an.potential(m, n_t)[sel], dV[sel], c=c)["sigma"]]))
             fits[name]["d_sigma_jackknife"] = float(err[0])
     return {
-        "study": "potential", "L": args.L, "beta": args.beta, "precision": args.prec,
+        "study": "potential", "L": args.L, "beta": args.beta, "precision": args.prec, "start": args.start,
+        "therm": args.therm, "between": args.between,
         "configurations": int(corrs.shape[0]), "n1": args.n1, "n2": args.n2, "multihit": not args.no_multihit,
         "r": r_list, "C": Cm.tolist(), "dC": dC.tolist(), "V": V.tolist(), "dV": dV.tolist(),
         "fit_r": r_fit.tolist(), "fits": fits, "seconds": time.time() - t0,
@@ -145,7 +147,8 @@ def main(argv=None):
     ap.add_argument("--n2", type=int, default=None)
     ap.add_argument("--L", type=int, default=24)
     ap.add_argument("--beta", type=float, default=1.0)
-    ap.add_argument("--therm", type=int, default=200)
+    ap.add_argument("--therm", type=int, default=3000)
+    ap.add_argument("--start", choices=["cold", "hot"], default="cold")
     ap.add_argument("--between", type=int, default=100)
     ap.add_argument("--seed", type=int, default=3000)
     ap.add_argument("--rmin", type=int, default=3)
