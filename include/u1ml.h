@@ -10,6 +10,11 @@
  * the Polyakov-loop correlator <P*(0)P(r)> estimated by products of slab
  * averaged two-link operators (Eq. (8)), and the field operators
  * a^2 F_munu = sqrt(beta) Im P_munu (Eq. (5)) inserted as in Eq. (9).
+ * Options (u1ml_set_estimator): the analytical multihit of Sec. 2.2 for the
+ * correlator lines, the squared components of Eq. (6) as the insertion, and
+ * the correlator averaged over the three axes and both orientations.
+ * Ensembles of runs on the device give the connected profile of Eq. (7)
+ * (u1ml_ensemble_*).
  *
  * Conventions shared by every call:
  *  - Sites (t, x, y, z), 0 <= t < T, 0 <= x, y, z < L, periodic; direction
