@@ -760,7 +760,8 @@ struct Engine {
       U1_HIP(launch_field_contract(lats.as<LatDesc>() + i, m.mls.as<MLDesc>() + i, m.fls.as<FieldLat>() + i,
                                    m.h_fls[i], m.fp, h_lats[i].L, m.mlbuf.as<double2>(), m.accbuf.as<double2>(),
                                    m.fbuf.as<double>(), m.scratch.as<double2>(), m.scratch_elems,
-                                   m.fout.as<double2>() + m.fout_off[i], field_general, zero_g, finalize, stream));
+                                   m.fout.as<double2>() + m.fout_off[i], field_general, prec == U1ML_FP32, zero_g,
+                                   finalize, stream));
     return U1ML_OK;
   }
 

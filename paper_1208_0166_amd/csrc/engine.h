@@ -130,10 +130,11 @@ hipError_t launch_ens_connected(const double2* fsum, const double2* csum, const 
 // contraction of all stored samples of one lattice into the Fourier-space
 // accumulator (cleared first if zero_g) and, if finalize, into F
 // [n_rf][2][6][L][L] (complex); general = true takes the stored-transform path
-// for any geometry
+// for any geometry; fp32_store keeps the fast path's per-sample transforms
+// in FP32 between its kernels (FP32 lattices)
 hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,
                                  FieldParams fp, int L, const double2* mlbuf, const double2* accbuf, double* fbuf,
-                                 double2* scratch, size_t scratch_elems, double2* F, bool general, bool zero_g,
-                                 bool finalize, hipStream_t st);
+                                 double2* scratch, size_t scratch_elems, double2* F, bool general, bool fp32_store,
+                                 bool zero_g, bool finalize, hipStream_t st);
 
 }  // namespace u1ml

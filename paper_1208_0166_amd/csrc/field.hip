@@ -300,6 +300,18 @@ __global__ void field_final_kernel(FieldParams fp, int L, const double2* __restr
 constexpr int kFxMaxL = 48;
 constexpr size_t kFxLds = 64512;  // LDS per block of field_what_kernel (bytes)
 
+// Storage of the per-sample transforms between the fast-path kernels: FP64
+// (double2), or FP32 (float2) for FP32 lattices, whose field operators carry
+// FP32 sine errors of order 1e-6 already.  The transforms themselves and
+// every sum are FP64 either way.
+__device__ __forceinline__ void put(double2* p, double2 v) { *p = v; }
+__device__ __forceinline__ void put(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ double2 get(const double2* p) { return *p; }
+__device__ __forceinline__ double2 get(const float2* p) {
+  const float2 v = *p;
+  return make_double2((double)v.x, (double)v.y);
+}
+
 // in-place FFT of the N values v[i * stride] (LDS)
 template <int N, int SIGN>
 __device__ __forceinline__ void fft_line(double2* v, int stride) {
@@ -348,13 +360,12 @@ __device__ __forceinline__ void fft_line_pair(double2* v, int stride, int h) {
 // The planes are built in LDS (coalesced reads), transformed along z by rows
 // (a lane pair per (x, y)) and along y by columns (a lane pair per (x, q)),
 // and stored.
-template <int L>
+template <int L, typename S>
 __global__ __launch_bounds__(512) void field_what_kernel(const LatDesc* __restrict__ lat,
                                                          const MLDesc* __restrict__ mlp,
                                                          const FieldLat* __restrict__ flp, FieldParams fp,
                                                          int sample0, int npb, const double2* __restrict__ mlbuf,
-                                                         const double* __restrict__ fbuf,
-                                                         double2* __restrict__ what) {
+                                                         const double* __restrict__ fbuf, S* __restrict__ what) {
   extern __shared__ double2 pl[];  // [nx][L (y)][L + 1]
   constexpr int L1 = L + 1;
   const LatDesc d = *lat;
@@ -389,10 +400,10 @@ __global__ __launch_bounds__(512) void field_what_kernel(const LatDesc* __restri
   __syncthreads();
   if (active) fft_line_pair<L, 1>(pl + xc * L * L1 + t, L1, h);  // column q = t, along y
   __syncthreads();
-  double2* dst = what + ((((size_t)k * fp.n_rf + f) * ns + s) * L + x0) * L * L;
+  S* dst = what + ((((size_t)k * fp.n_rf + f) * ns + s) * L + x0) * L * L;
   for (int i = tid; i < nx * L * L; i += blockDim.x) {
     const int c = i / (L * L), pq = i - c * (L * L), p = pq / L, q = pq - p * L;
-    dst[(size_t)c * L * L + pq] = pl[(c * L + p) * L1 + q];
+    put(dst + (size_t)c * L * L + pq, pl[(c * L + p) * L1 + q]);
   }
 }
 
@@ -408,11 +419,10 @@ __global__ __launch_bounds__(512) void field_what_kernel(const LatDesc* __restri
 // group of np pairs); the pair planes are staged with 16-byte loads of
 // neighbouring x (pairs fastest), then np L lane pairs transform rows (along
 // z) and columns (along y).
-template <int L>
+template <int L, typename S>
 __global__ __launch_bounds__(512) void field_ohat_kernel(const LatDesc* __restrict__ lat,
                                                          const FieldLat* __restrict__ flp, int sample0, int np,
-                                                         const double* __restrict__ fbuf,
-                                                         double2* __restrict__ zhat) {
+                                                         const double* __restrict__ fbuf, S* __restrict__ zhat) {
   extern __shared__ double2 zp[];  // [np][L (y)][L + 1]
   constexpr int L1 = L + 1, L2 = L * L, NP = L / 2;
   const LatDesc d = *lat;
@@ -434,10 +444,10 @@ __global__ __launch_bounds__(512) void field_ohat_kernel(const LatDesc* __restri
   __syncthreads();
   if (active) fft_line_pair<L, -1>(zp + pl * L * L1 + t, L1, h);  // columns, along y
   __syncthreads();
-  double2* dst = zhat + ((((size_t)k * ns + s) * 6 + c) * NP + j0) * L2;
+  S* dst = zhat + ((((size_t)k * ns + s) * 6 + c) * NP + j0) * L2;
   for (int i = tid; i < n * L2; i += blockDim.x) {
     const int pr = i / L2, pq = i - pr * L2, p = pq / L, q = pq - p * L;
-    dst[(size_t)pr * L2 + pq] = zp[(pr * L + p) * L1 + q];
+    put(dst + (size_t)pr * L2 + pq, zp[(pr * L + p) * L1 + q]);
   }
 }
 
@@ -452,11 +462,10 @@ __global__ __launch_bounds__(512) void field_ohat_kernel(const LatDesc* __restri
 // (even), so every W value is read once per thread: w1 carries W(x - 1 - m_0)
 // from pair to pair.
 constexpr int kZcF = 3;
-template <int L>
+template <int L, typename S>
 __global__ __launch_bounds__(256) void field_zcon_kernel(const FieldLat* __restrict__ flp, FieldParams fp,
-                                                         int nblk_e, const double2* __restrict__ zhat,
-                                                         const double2* __restrict__ what,
-                                                         double2* __restrict__ part) {
+                                                         int nblk_e, const S* __restrict__ zhat,
+                                                         const S* __restrict__ what, double2* __restrict__ part) {
   constexpr int L2 = L * L, NP = L / 2;
   const FieldLat fl = *flp;
   const int ns = fl.ns;
@@ -469,8 +478,8 @@ __global__ __launch_bounds__(256) void field_zcon_kernel(const FieldLat* __restr
   const int nf = min(kZcF, fp.n_rf - f0);
   const int p = pq / L, q = pq - p * L;
   const int ib = (p == 0 ? 0 : L - p) * L + (q == 0 ? 0 : L - q);  // -k
-  const double2* z = zhat + (((size_t)k * ns + s) * 6 + 3 * h) * NP * L2;
-  const double2* wk = what + ((size_t)k * fp.n_rf * ns + s) * L * L2 + pq;  // + (f ns L + x) L2
+  const S* z = zhat + (((size_t)k * ns + s) * 6 + 3 * h) * NP * L2;
+  const S* wk = what + ((size_t)k * fp.n_rf * ns + s) * L * L2 + pq;  // + (f ns L + x) L2
   double2 g0[kZcF][3], g1[kZcF][3], w1[kZcF];
   int xw[kZcF];
   bool even[kZcF];
@@ -481,26 +490,26 @@ __global__ __launch_bounds__(256) void field_zcon_kernel(const FieldLat* __restr
     const int r = j < nf ? fp.rf[f0 + j] : 1, m0 = (r - 1) / 2;
     even[j] = (r & 1) == 0;
     xw[j] = m0 == 0 ? 0 : L - m0;  // W plane of plane 0 at x = 0
-    w1[j] = j < nf ? wk[((size_t)(f0 + j) * ns * L + (L - 1 - m0)) * L2] : make_double2(0.0, 0.0);  // W(-1 - m_0)
+    w1[j] = j < nf ? get(wk + ((size_t)(f0 + j) * ns * L + (L - 1 - m0)) * L2) : make_double2(0.0, 0.0);  // W(-1 - m_0)
   }
 #pragma unroll 2
   for (int jp = 0; jp < NP; ++jp) {
     double2 oa[3], ob[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double2* zc = z + ((size_t)c * NP + jp) * L2;
-      const double2 za = zc[pq], zm = zc[ib];
+      const S* zc = z + ((size_t)c * NP + jp) * L2;
+      const double2 za = get(zc + pq), zm = get(zc + ib);
       oa[c] = make_double2(0.5 * (za.x + zm.x), 0.5 * (za.y - zm.y));   // Ohat of x = 2 jp
       ob[c] = make_double2(0.5 * (za.y + zm.y), -0.5 * (za.x - zm.x));  // Ohat of x = 2 jp + 1
     }
 #pragma unroll
     for (int j = 0; j < kZcF; ++j) {
       if (j < nf) {
-        const double2* wf = wk + (size_t)(f0 + j) * ns * L * L2;
-        const double2 wa = wf[(size_t)xw[j] * L2];
+        const S* wf = wk + (size_t)(f0 + j) * ns * L * L2;
+        const double2 wa = get(wf + (size_t)xw[j] * L2);
         int xn = xw[j] + 1;
         xn -= xn >= L ? L : 0;
-        const double2 wb = wf[(size_t)xn * L2];
+        const double2 wb = get(wf + (size_t)xn * L2);
         xn += 1;
         xw[j] = xn >= L ? xn - L : xn;
         const double2 ha = even[j] ? w1[j] : wa, hb = even[j] ? wa : wb;
@@ -585,7 +594,7 @@ __global__ void field_gsum_kernel(FieldParams fp, int L, int ns, int nk, const d
 }
 
 
-template <int L>
+template <int L, typename S>
 hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, int ns, FieldParams fp,
                                 const double2* mlbuf, const double* fbuf, double2* scratch, size_t scratch_elems,
                                 double2* G, double2* F, bool finalize, hipStream_t st) {
@@ -599,21 +608,25 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
   const int ngroups_w = (L + npb_w - 1) / npb_w;
   const int ngroups_o = (L / 2 + np_o - 1) / np_o;
   const int nblk_e = (int)((((fp.n_rf + kZcF - 1) / kZcF) * 2 * L2 + 255) / 256);
-  // scratch per sample: What [n_rf][ns][L3], Zhat [ns][6][L3 / 2], part [ns][6][n_ent]
-  const uint64_t per_sample = (uint64_t)fp.n_rf * ns * L3 + (uint64_t)ns * 3 * L3 + (uint64_t)ns * 6 * n_ent;
-  const int chunk = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, scratch_elems / per_sample));
+  // scratch bytes per sample: What [n_rf][ns][L3] and Zhat [ns][6][L3 / 2]
+  // (storage type S), part [ns][6][n_ent] (double2)
+  const uint64_t per_sample = ((uint64_t)fp.n_rf * ns * L3 + (uint64_t)ns * 3 * L3) * sizeof(S) +
+                              (uint64_t)ns * 6 * n_ent * sizeof(double2);
+  const int chunk =
+      (int)std::max<uint64_t>(1, std::min<uint64_t>(64, scratch_elems * sizeof(double2) / per_sample));
   const int n_samples = fp.n_stored * fp.n_inner;
   for (int s0 = 0; s0 < n_samples; s0 += chunk) {
     const int nk = std::min(chunk, n_samples - s0);
-    double2* what = scratch;
-    double2* zhat = what + (uint64_t)nk * fp.n_rf * ns * L3;
-    double2* part = zhat + (uint64_t)nk * ns * 3 * L3;
-    hipLaunchKernelGGL(field_what_kernel<L>, dim3((unsigned)((uint64_t)nk * fp.n_rf * ns * ngroups_w)), dim3(thr_w),
+    S* what = (S*)scratch;
+    S* zhat = what + (uint64_t)nk * fp.n_rf * ns * L3;
+    const uint64_t s_elems = (uint64_t)nk * (fp.n_rf * ns * L3 + ns * 3 * L3);
+    double2* part = scratch + (s_elems * sizeof(S) + sizeof(double2) - 1) / sizeof(double2);
+    hipLaunchKernelGGL((field_what_kernel<L, S>), dim3((unsigned)((uint64_t)nk * fp.n_rf * ns * ngroups_w)), dim3(thr_w),
                        npb_w * plane_bytes, st, lat, ml, fl, fp, s0, npb_w, mlbuf, fbuf, what);
-    hipLaunchKernelGGL(field_ohat_kernel<L>, dim3((unsigned)((uint64_t)nk * ns * 6 * ngroups_o)), dim3(thr_o),
+    hipLaunchKernelGGL((field_ohat_kernel<L, S>), dim3((unsigned)((uint64_t)nk * ns * 6 * ngroups_o)), dim3(thr_o),
                        np_o * plane_bytes, st, lat, fl, s0, np_o, fbuf, zhat);
-    hipLaunchKernelGGL(field_zcon_kernel<L>, dim3((unsigned)((uint64_t)nk * ns * nblk_e)), dim3(256), 0, st, fl, fp,
-                       nblk_e, zhat, what, part);
+    hipLaunchKernelGGL((field_zcon_kernel<L, S>), dim3((unsigned)((uint64_t)nk * ns * nblk_e)), dim3(256), 0, st, fl,
+                       fp, nblk_e, zhat, what, part);
     hipLaunchKernelGGL(field_gsum_kernel, dim3(blocks_for(6 * (uint64_t)n_ent, 64)), dim3(64), 0, st, fp, L, ns, nk,
                        part, G);
   }
@@ -625,25 +638,30 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
 // the fast path for lattice size L: one of the instantiated lengths
 typedef hipError_t (*FastContract)(const LatDesc*, const MLDesc*, const FieldLat*, int, FieldParams, const double2*,
                                    const double*, double2*, size_t, double2*, double2*, bool, hipStream_t);
-FastContract fast_contract_for(int L) {
+FastContract fast_contract_for(int L, bool fp32_store) {
   if (L > kFxMaxL) return nullptr;
   switch (L) {
-    case 2: return launch_fast_contract<2>;
-    case 4: return launch_fast_contract<4>;
-    case 6: return launch_fast_contract<6>;
-    case 8: return launch_fast_contract<8>;
-    case 10: return launch_fast_contract<10>;
-    case 12: return launch_fast_contract<12>;
-    case 16: return launch_fast_contract<16>;
-    case 18: return launch_fast_contract<18>;
-    case 20: return launch_fast_contract<20>;
-    case 24: return launch_fast_contract<24>;
-    case 30: return launch_fast_contract<30>;
-    case 32: return launch_fast_contract<32>;
-    case 36: return launch_fast_contract<36>;
-    case 40: return launch_fast_contract<40>;
-    case 48: return launch_fast_contract<48>;
-    default: return nullptr;
+#define U1ML_FAST_L(n) \
+  case n:              \
+    return fp32_store ? launch_fast_contract<n, float2> : launch_fast_contract<n, double2>;
+    U1ML_FAST_L(2)
+    U1ML_FAST_L(4)
+    U1ML_FAST_L(6)
+    U1ML_FAST_L(8)
+    U1ML_FAST_L(10)
+    U1ML_FAST_L(12)
+    U1ML_FAST_L(16)
+    U1ML_FAST_L(18)
+    U1ML_FAST_L(20)
+    U1ML_FAST_L(24)
+    U1ML_FAST_L(30)
+    U1ML_FAST_L(32)
+    U1ML_FAST_L(36)
+    U1ML_FAST_L(40)
+    U1ML_FAST_L(48)
+#undef U1ML_FAST_L
+    default:
+      return nullptr;
   }
 }
 
@@ -651,19 +669,19 @@ FastContract fast_contract_for(int L) {
 
 hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,
                                  FieldParams fp, int L, const double2* mlbuf, const double2* accbuf, double* fbuf,
-                                 double2* scratch, size_t scratch_elems, double2* F, bool general, bool zero_g,
-                                 bool finalize, hipStream_t st) {
+                                 double2* scratch, size_t scratch_elems, double2* F, bool general, bool fp32_store,
+                                 bool zero_g, bool finalize, hipStream_t st) {
   const uint64_t L3 = (uint64_t)L * L * L, L2 = (uint64_t)L * L;
   const int ns = hfl.ns;
   const uint64_t nt = (uint64_t)fp.n_stored * ns * L3 * fp.n_rf;
   hipLaunchKernelGGL(field_tavg_kernel, dim3(blocks_for(nt, 256)), dim3(256), 0, st, lat, ml, fl, fp, mlbuf, fbuf);
-  hipLaunchKernelGGL(field_ptop_kernel, dim3(blocks_for((uint64_t)hfl.n_top * L3, 256)), dim3(256), 0, st, lat, ml, fl, fp, accbuf,
-                     fbuf);
+  hipLaunchKernelGGL(field_ptop_kernel, dim3(blocks_for((uint64_t)hfl.n_top * L3, 256)), dim3(256), 0, st, lat, ml,
+                     fl, fp, accbuf, fbuf);
   hipLaunchKernelGGL(field_weights_kernel, dim3(blocks_for(nt, 256)), dim3(256), 0, st, lat, fl, fp, fbuf);
   double2* G = (double2*)(fbuf + hfl.g);
   const uint64_t ng = (uint64_t)fp.n_rf * 12 * L2;
   if (zero_g) hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(ng, 256)), dim3(256), 0, st, G, ng);
-  if (FastContract fc = general ? nullptr : fast_contract_for(L)) {
+  if (FastContract fc = general ? nullptr : fast_contract_for(L, fp32_store)) {
     return fc(lat, ml, fl, ns, fp, mlbuf, fbuf, scratch, scratch_elems, G, F, finalize, st);
   }
   // general path: both transforms stored, contraction by pq tiles

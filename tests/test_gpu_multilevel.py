@@ -441,3 +441,23 @@ def test_replayed_run_equals_stored_run_under_graph_replay():
         np.testing.assert_array_equal(c0, c1)
         assert p0 == p1
         close_rel(f1, f0)
+
+
+@pytest.mark.parametrize("L", [12, 24])
+def test_fp32_fused_contraction_matches_general(L):
+    # FP32 lattices keep the fused path's per-sample transforms in FP32 (the
+    # transforms and sums stay FP64); the general path stores them in FP64.
+    # Same chain, so the difference is the storage rounding alone.
+    say(f"[gpu] FP32 fused vs general field contraction L={L}")
+    res = []
+    for general in (False, True):
+        g = u1ml.init_lattice(L, 8, 1.0, 23, precision=u1ml.FP32)
+        if general:
+            u1ml.set_debug(g, 2)
+        u1ml.sweep(g, 1, 2)
+        u1ml.multilevel(g, [4, 2], [2, 3], 1, 2, [1, 2, 3, 4], rf_list=[2, 3, 4])
+        _, c, f = u1ml.measure(g, observables=False, correlator=True, field_profile=True)
+        res.append((u1ml.get_links(g), c, f))
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    np.testing.assert_array_equal(res[0][1], res[1][1])
+    close_rel(res[0][2], res[1][2], 1e-6)
