@@ -109,12 +109,13 @@ size_t u1ml_link_bytes(int L, int T, int precision);
 /* Bytes of device memory a u1ml_multilevel run of one L^3 x T lattice with
  * these arguments and estimator flags allocates for its workspace (time
  * lines, level accumulators, correlator, and with n_rf > 0 the stored field
- * sums, weights, transforms and contraction scratch), every inner sample
+ * sums (in the link precision), weights, transforms and contraction
+ * scratch), every inner sample
  * kept.  Pure function for planning; 0 for invalid arguments.  A run whose
  * field samples would not fit is replayed with one outer iteration stored
  * (u1ml_multilevel) and then needs less. */
-size_t u1ml_workspace_bytes(int L, int T, int n_levels, const int *slab_sizes, const int *n_sub, int n_r, int n_rf,
-                            unsigned estimator);
+size_t u1ml_workspace_bytes(int L, int T, int precision, int n_levels, const int *slab_sizes, const int *n_sub,
+                            int n_r, int n_rf, unsigned estimator);
 
 /* Create a lattice (Sec. 2, Sec. 2.1): L, T even, 2 <= L, T <= 256,
  * L^4 T < 2^32; beta >= 0 finite (beta = 1/g^2 of Eq. (3)).

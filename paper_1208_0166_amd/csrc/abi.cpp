@@ -570,7 +570,7 @@ struct Engine {
       for (auto& d : h_lats) {
         const size_t ns_in = d.T / th[inner];
         const size_t lines = (estimator & U1ML_MULTIHIT) ? 2 : 1;
-        store_all += (size_t)n_outer * n_sub[inner] * ns_in * d.L3 * (6 * sizeof(double) + lines * sizeof(double2));
+        store_all += (size_t)n_outer * n_sub[inner] * ns_in * d.L3 * (6 * elem_size() + lines * sizeof(double2));
       }
     bool too_big = false;
     if (store_all > 0) {
@@ -650,7 +650,7 @@ struct Engine {
         fl.ns = m.h_mls[i].ns[inner];
         const uint64_t L3 = d.L3, L2 = (uint64_t)d.L * d.L;
         fl.oall = fb;
-        fb += (uint64_t)n_samples_kept * 6 * fl.ns * L3;
+        fb += ((uint64_t)n_samples_kept * 6 * fl.ns * L3 * elem_size() + sizeof(double) - 1) / sizeof(double);
         fl.tavg = fb;
         fb += 2ull * n_stored * fl.ns * L3 * fp.n_rf;
         fl.w = fb;
@@ -1115,9 +1115,10 @@ size_t u1ml_link_bytes(int L, int T, int precision) {
   return (size_t)4 * L * L * L * T * (precision == U1ML_FP64 ? 8 : 4);
 }
 
-size_t u1ml_workspace_bytes(int L, int T, int n_levels, const int* slab_sizes, const int* n_sub, int n_r, int n_rf,
-                            unsigned estimator) {
-  if (L < 2 || T < 2 || (L & 1) || (T & 1) || n_levels < 1 || n_levels > U1ML_MAX_LEVELS || !slab_sizes ||
+size_t u1ml_workspace_bytes(int L, int T, int precision, int n_levels, const int* slab_sizes, const int* n_sub,
+                            int n_r, int n_rf, unsigned estimator) {
+  if (L < 2 || T < 2 || (L & 1) || (T & 1) || (precision != U1ML_FP64 && precision != U1ML_FP32) || n_levels < 1 ||
+      n_levels > U1ML_MAX_LEVELS || !slab_sizes ||
       !n_sub || n_r < 1 || n_rf < 0 || n_rf > U1ML_MAX_FIELD_R || (n_rf > 0 && n_levels > 2))
     return 0;
   for (int l = 0; l < n_levels; ++l)
@@ -1136,8 +1137,9 @@ size_t u1ml_workspace_bytes(int L, int T, int n_levels, const int* slab_sizes, c
   size_t bytes = (ell + acc) * sizeof(double2) + (size_t)n_r * 2 * sizeof(double);
   if (n_rf > 0) {
     const uint64_t n_top = n_levels == 2 ? (uint64_t)(T / slab_sizes[0]) : 1;
-    const uint64_t fb = kept * 6 * ns_in * L3 + 4ull * n_outer * ns_in * L3 * n_rf + 2ull * n_rf * 12 * L2 +
-                        2ull * n_top * n_rf * L3;
+    const uint64_t esz = precision == U1ML_FP64 ? 8 : 4;  // stored field sums in the link precision
+    const uint64_t fb = (kept * 6 * ns_in * L3 * esz + 7) / 8 + 4ull * n_outer * ns_in * L3 * n_rf +
+                        2ull * n_rf * 12 * L2 + 2ull * n_top * n_rf * L3;
     const uint64_t per_sample = (uint64_t)(n_rf + 6) * ns_in * L3 + (uint64_t)n_rf * ns_in * 12 * L2;
     const uint64_t scratch = std::max<uint64_t>(per_sample, kFieldScratchBytes / sizeof(double2));
     bytes += fb * sizeof(double) + ((uint64_t)n_rf * 12 * L2 + scratch) * sizeof(double2);

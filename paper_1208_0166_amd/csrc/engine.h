@@ -100,7 +100,8 @@ hipError_t launch_ml_final(const LatDesc* lats, const MLDesc* mls, int n_lats, i
 struct FieldLat {
   int ns;         // inner slabs
   int n_top;      // top-level slabs (two levels), else 1
-  uint64_t oall;  // [n_samples][6][ns][L3] slab sums of the field operators
+  uint64_t oall;  // [n_samples][6][ns][L3] slab sums of the field operators, in the
+                  // link precision (FP32 values packed two per double for FP32 links)
   uint64_t tavg;  // double2 [n_stored][n_rf][ns][L3]
   uint64_t w;     // double2 [n_stored][n_rf][ns][L3]
   uint64_t g;     // double2 [n_rf][2][6][L2] Fourier-space accumulator

@@ -103,7 +103,7 @@ __global__ void field_weights_kernel(const LatDesc* __restrict__ lat, const Fiel
 constexpr int kDftThreads = 256;
 constexpr int kDftMaxPer = 16;  // ceil(62^2 / 256)
 
-template <int KIND>
+template <int KIND, typename O>
 __global__ __launch_bounds__(kDftThreads) void field_dft_kernel(const LatDesc* __restrict__ lat,
                                                                 const MLDesc* __restrict__ mlp,
                                                                 const FieldLat* __restrict__ flp, FieldParams fp,
@@ -126,10 +126,10 @@ __global__ __launch_bounds__(kDftThreads) void field_dft_kernel(const LatDesc* _
     tw[i] = make_double2(cs, KIND == 0 ? -sn : sn);
   }
   if (KIND == 0) {
-    const double* src = fbuf + fl.oall + (((size_t)sample * 6 + a) * ns + s) * d.L3;
+    const O* src = (const O*)(fbuf + fl.oall) + (((size_t)sample * 6 + a) * ns + s) * d.L3;
     for (int i = threadIdx.x; i < L2; i += blockDim.x) {
       const int y = i / L, z = i - y * L;
-      buf[i] = make_double2(src[(size_t)(z * L + y) * L + x], 0.0);
+      buf[i] = make_double2((double)src[(size_t)(z * L + y) * L + x], 0.0);
     }
   } else {
     const MLDesc ml = *mlp;
@@ -307,6 +307,14 @@ constexpr size_t kFxLds = 64512;  // LDS per block of field_what_kernel (bytes)
 __device__ __forceinline__ void put(double2* p, double2 v) { *p = v; }
 __device__ __forceinline__ void put(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
 __device__ __forceinline__ double2 get(const double2* p) { return *p; }
+template <typename S>
+struct ScalarOf {
+  using type = double;
+};
+template <>
+struct ScalarOf<float2> {
+  using type = float;
+};
 __device__ __forceinline__ double2 get(const float2* p) {
   const float2 v = *p;
   return make_double2((double)v.x, (double)v.y);
@@ -431,11 +439,14 @@ __global__ __launch_bounds__(512) void field_ohat_kernel(const LatDesc* __restri
   const int b = blockIdx.x;
   const int grp = b % ngroups, c = (b / ngroups) % 6, s = (b / (ngroups * 6)) % ns, k = b / (ngroups * 6 * ns);
   const int j0 = grp * np, n = min(np, NP - j0);
-  const double* o = fbuf + fl.oall + (((size_t)(sample0 + k) * 6 + c) * ns + s) * d.L3;
+  // the stored sums are in the storage precision (FP32 for FP32 links)
+  using O = typename ScalarOf<S>::type;
+  const O* o = (const O*)(fbuf + fl.oall) + (((size_t)(sample0 + k) * 6 + c) * ns + s) * d.L3;
   const int tid = threadIdx.x;
   for (int i = tid; i < n * L2; i += blockDim.x) {
     const int pr = i % n, yz = i / n, y = yz % L, z = yz / L;
-    zp[(pr * L + y) * L1 + z] = *(const double2*)(o + (size_t)(z * L + y) * L + 2 * (j0 + pr));
+    const O* v = o + (size_t)(z * L + y) * L + 2 * (j0 + pr);
+    zp[(pr * L + y) * L1 + z] = make_double2((double)v[0], (double)v[1]);
   }
   __syncthreads();
   const bool active = tid < 2 * n * L;  // a lane pair per row, then per column
@@ -700,10 +711,14 @@ hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const Fie
     double2* what = scratch;
     double2* ohat = what + (uint64_t)nk * fp.n_rf * ns * L3;
     double2* part = ohat + (uint64_t)nk * 6 * ns * L3;
-    hipLaunchKernelGGL(field_dft_kernel<1>, dim3((unsigned)((uint64_t)nk * fp.n_rf * ns * L)), dim3(kDftThreads), shm,
+    hipLaunchKernelGGL((field_dft_kernel<1, double>), dim3((unsigned)((uint64_t)nk * fp.n_rf * ns * L)), dim3(kDftThreads), shm,
                        st, lat, ml, fl, fp, s0, mlbuf, fbuf, what);
-    hipLaunchKernelGGL(field_dft_kernel<0>, dim3((unsigned)((uint64_t)nk * 6 * ns * L)), dim3(kDftThreads), shm, st,
-                       lat, ml, fl, fp, s0, mlbuf, fbuf, ohat);
+    if (fp32_store)
+      hipLaunchKernelGGL((field_dft_kernel<0, float>), dim3((unsigned)((uint64_t)nk * 6 * ns * L)), dim3(kDftThreads),
+                         shm, st, lat, ml, fl, fp, s0, mlbuf, fbuf, ohat);
+    else
+      hipLaunchKernelGGL((field_dft_kernel<0, double>), dim3((unsigned)((uint64_t)nk * 6 * ns * L)),
+                         dim3(kDftThreads), shm, st, lat, ml, fl, fp, s0, mlbuf, fbuf, ohat);
     hipLaunchKernelGGL(field_gacc_kernel, dim3((unsigned)((L2 + pt - 1) / pt), ns, nk), dim3(gthreads), gshm, st, fp, L,
                        ns, pt, what, ohat, part);
     hipLaunchKernelGGL(field_gred_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, ns, nk, part, G);

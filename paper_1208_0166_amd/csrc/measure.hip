@@ -450,7 +450,8 @@ __global__ void field_o_kernel(const R* __restrict__ links, const LatDesc* __res
     add_field_ops<SQ>(links, d, st, o);
   }
   const double pre = SQ ? d.beta : d.sqrt_beta;
-  double* out = fbuf + fl.oall + (size_t)sample * 6 * fl.ns * d.L3;
+  // stored in the link precision: FP32 lattices' sums carry FP32 sine errors
+  R* out = (R*)(fbuf + fl.oall) + (size_t)sample * 6 * fl.ns * d.L3;
   for (int c = 0; c < 6; ++c) store_stream(out + ((size_t)c * fl.ns + s) * d.L3 + y3, pre * o[c]);
 }
 

@@ -148,6 +148,7 @@ __device__ __forceinline__ int shift_axis(const LatDesc& d, int x3, int v) {
 // iteration or of the run: marked non-temporal so that they do not displace
 // the lattices from the caches.
 __device__ __forceinline__ void store_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_stream(float* p, double v) { __builtin_nontemporal_store((float)v, p); }
 __device__ __forceinline__ void store_stream(double2* p, double2 v) {
   __builtin_nontemporal_store(v.x, &p->x);
   __builtin_nontemporal_store(v.y, &p->y);

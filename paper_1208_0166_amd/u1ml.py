@@ -70,7 +70,7 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "u1ml_default_options": (None, [C.POINTER(Options)]),
         "u1ml_link_bytes": (SZ, [I, I, I]),
-        "u1ml_workspace_bytes": (SZ, [I, I, I, ip, ip, I, I, C.c_uint]),
+        "u1ml_workspace_bytes": (SZ, [I, I, I, I, ip, ip, I, I, C.c_uint]),
         "u1ml_device_bytes": (SZ, [P]),
         "u1ml_init_lattice": (I, [I, I, D, U64, C.POINTER(Options), C.POINTER(P)]),
         "u1ml_sweep": (I, [P, I, I]),
@@ -276,11 +276,11 @@ def ensemble_read(lat: Lattice, correlator: bool = True, field_profile: bool = F
 
 
 def workspace_bytes(L: int, T: int, slab_sizes, n_sub, n_r: int, n_rf: int = 0, multihit: bool = False,
-                    field_squared: bool = False, symmetric: bool = False) -> int:
+                    field_squared: bool = False, symmetric: bool = False, precision: int = FP64) -> int:
     """Device bytes of a multilevel run's workspace (u1ml_workspace_bytes)."""
     th, thp = _ints(slab_sizes)
     ns, nsp = _ints(n_sub)
-    return load_library().u1ml_workspace_bytes(L, T, len(th), thp, nsp, n_r, n_rf,
+    return load_library().u1ml_workspace_bytes(L, T, precision, len(th), thp, nsp, n_r, n_rf,
                                                _estimator_flags(multihit, field_squared, symmetric))
 
 

@@ -84,3 +84,8 @@ def test_workspace_bytes_is_a_pure_size_function():
     assert wb(4, 8, [4, 2], [2, 3], 3, symmetric=True) == base + 2 * acc
     assert wb(4, 8, [4, 2], [2, 3], 3, n_rf=2) > base + (512 << 20)
     assert wb(4, 8, [4, 2], [2, 3], 3, n_rf=2, field_squared=True) == wb(4, 8, [4, 2], [2, 3], 3, n_rf=2)
+    # FP32 lattices store the field sums in FP32: 4 of the 8 bytes of each of the
+    # samples x 6 components x 4 slabs x L^3 sums
+    f64 = wb(4, 8, [4, 2], [2, 3], 3, n_rf=2)
+    assert f64 - wb(4, 8, [4, 2], [2, 3], 3, n_rf=2, precision=u1ml.FP32) == 6 * 6 * 4 * L3 * 4  # 2 x 3 samples kept
+    assert wb(4, 8, [4, 2], [2, 3], 3, precision=7) == 0

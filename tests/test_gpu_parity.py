@@ -209,17 +209,19 @@ def test_observables_follow_every_update(oracle_mod):
         assert abs(after[i] - ob.plaquette()) < 1e-13
 
 
-@pytest.mark.parametrize("levels,n_sub,rf,mh,sym", [
-    ([4, 2], [2, 3], [], False, False),
-    ([4, 2], [2, 3], [2], True, False),
-    ([2], [4], [2, 3], False, True),
-    ([4, 2, 1], [1, 2, 2], [], True, True),
+@pytest.mark.parametrize("levels,n_sub,rf,mh,sym,prec", [
+    ([4, 2], [2, 3], [], False, False, u1ml.FP64),
+    ([4, 2], [2, 3], [2], True, False, u1ml.FP64),
+    ([4, 2], [2, 3], [2], True, False, u1ml.FP32),
+    ([2], [3], [2, 3], False, True, u1ml.FP32),
+    ([4, 2, 1], [1, 2, 2], [], True, True, u1ml.FP64),
 ])
-def test_device_bytes_match_the_planned_workspace(levels, n_sub, rf, mh, sym):
-    say(f"[gpu] workspace bytes levels={levels} rf={rf} mh={mh} sym={sym}")
-    g = u1ml.init_lattice(4, 8, 1.0, 3)
+def test_device_bytes_match_the_planned_workspace(levels, n_sub, rf, mh, sym, prec):
+    say(f"[gpu] workspace bytes levels={levels} rf={rf} mh={mh} sym={sym} prec={prec}")
+    g = u1ml.init_lattice(4, 8, 1.0, 3, precision=prec)
     u1ml.set_estimator(g, multihit=mh, symmetric=sym)
     assert u1ml.device_bytes(g) == 0
     u1ml.multilevel(g, levels, n_sub, 1, 2, [1, 2, 3], rf_list=rf)
     u1ml.synchronize(g)
-    assert u1ml.device_bytes(g) == u1ml.workspace_bytes(4, 8, levels, n_sub, 3, len(rf), multihit=mh, symmetric=sym)
+    assert u1ml.device_bytes(g) == u1ml.workspace_bytes(4, 8, levels, n_sub, 3, len(rf), multihit=mh, symmetric=sym,
+                                                        precision=prec)
