@@ -43,7 +43,7 @@ N_BETWEEN = 100
 N_THERM = 200
 HBM_PEAK_GBS = 8000.0
 WORDS_PER_UPDATE = 9  # 8 link reads + 1 write per update in a class pass
-DEFAULT_REPLICAS = 24
+DEFAULT_REPLICAS = 48
 DEFAULT_STREAMS = 3
 CPU_N_SUB = [2, 5]  # reduced multilevel sample for the oracle
 COPY_ELEMS = 1 << 27  # calibration copy: 512 MiB read, 512 MiB written
