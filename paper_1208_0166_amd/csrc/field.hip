@@ -389,16 +389,31 @@ __global__ __launch_bounds__(512) void field_what_kernel(const LatDesc* __restri
   const double2* e = mlbuf + ml.ell + ((size_t)sample * ns + s) * d.L3;
   const double2* w = (const double2*)(fbuf + fl.w) + (((size_t)m * fp.n_rf + f) * ns + s) * d.L3;
   const int r = fp.rf[f];
-  const int tid = threadIdx.x;
-  // W(x, y, z) = w(x0) conj(e(x0)) e(x0 + r), x0 = (z L + y) L + x, x fastest
-  for (int i = tid; i < nx * L * L; i += blockDim.x) {
-    const int xc = i % nx, yz = i / nx, y = yz % L, z = yz / L, x = x0 + xc;
-    int xr = x + r;
-    xr -= xr >= L ? L : 0;
-    const int row = (z * L + y) * L;
-    const double2 u = e[row + x], v = e[row + xr];
-    pl[(xc * L + y) * L1 + z] =
-        cmul(w[row + x], make_double2(u.x * v.x + u.y * v.y, u.x * v.y - u.y * v.x));
+  const int tid = threadIdx.x, bd = blockDim.x, n = nx * L * L;
+  // W(x, y, z) = w(x0) conj(e(x0)) e(x0 + r), x0 = (z L + y) L + x, x fastest.
+  // The loads of kWLd elements are issued together, unconditionally (the
+  // index is clamped; an element past the end is loaded but not stored), so
+  // that no branch separates them.
+  constexpr int kWLd = 6;
+  for (int i0 = tid; i0 < n; i0 += kWLd * bd) {
+    double2 u[kWLd], v[kWLd], wv[kWLd];
+    int at[kWLd];
+#pragma unroll
+    for (int j = 0; j < kWLd; ++j) {
+      const int iu = i0 + j * bd, i = min(iu, n - 1);
+      const int xc = i % nx, yz = i / nx, y = yz % L, z = yz / L, x = x0 + xc;
+      int xr = x + r;
+      xr -= xr >= L ? L : 0;
+      const int row = (z * L + y) * L;
+      u[j] = e[row + x];
+      v[j] = e[row + xr];
+      wv[j] = w[row + x];
+      at[j] = iu < n ? (xc * L + y) * L1 + z : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < kWLd; ++j)
+      if (at[j] >= 0)
+        pl[at[j]] = cmul(wv[j], make_double2(u[j].x * v[j].x + u[j].y * v[j].y, u[j].x * v[j].y - u[j].y * v[j].x));
   }
   __syncthreads();
   // a lane pair per row, then per column (fft_line_pair)
@@ -409,24 +424,18 @@ __global__ __launch_bounds__(512) void field_what_kernel(const LatDesc* __restri
   if (active) fft_line_pair<L, 1>(pl + xc * L * L1 + t, L1, h);  // column q = t, along y
   __syncthreads();
   S* dst = what + ((((size_t)k * fp.n_rf + f) * ns + s) * L + x0) * L * L;
-  for (int i = tid; i < nx * L * L; i += blockDim.x) {
+  for (int i = tid; i < n; i += bd) {
     const int c = i / (L * L), pq = i - c * (L * L), p = pq / L, q = pq - p * L;
     put(dst + (size_t)c * L * L + pq, pl[(c * L + p) * L1 + q]);
   }
 }
 
-// Zhat[((sample * ns + s) * 6 + c) * (L / 2) + j][p * L + q] (complex): the
-// transform over (y, z) of Z = O_c(2 j) + i O_c(2 j + 1), O_c the sums over
-// the times of inner slab s of the insertion operator (Eq. (5), or Eq. (6)
-// with SQ) at x = 2 j, 2 j + 1.  Block: (unit = (lattice, slab), pair j);
-// a thread per (y, z) sums its two sites' six operators into the six planes,
-// then 6 L threads transform rows (along z) and columns (along y).
 // Zhat[((k * ns + s) * 6 + c) * (L / 2) + j][p * L + q] (complex): the
 // transform over (y, z) of Z = O_c(2 j) + i O_c(2 j + 1) for sample
 // sample0 + k, inner slab s, from the stored slab sums O_c.  Block: (k, s, c,
-// group of np pairs); the pair planes are staged with 16-byte loads of
-// neighbouring x (pairs fastest), then np L lane pairs transform rows (along
-// z) and columns (along y).
+// group of np pairs); the pair planes are staged (pairs fastest, so that
+// neighbouring lanes read neighbouring x), then np L lane pairs transform
+// rows (along z) and columns (along y).
 template <int L, typename S>
 __global__ __launch_bounds__(512) void field_ohat_kernel(const LatDesc* __restrict__ lat,
                                                          const FieldLat* __restrict__ flp, int sample0, int np,
@@ -442,11 +451,26 @@ __global__ __launch_bounds__(512) void field_ohat_kernel(const LatDesc* __restri
   // the stored sums are in the storage precision (FP32 for FP32 links)
   using O = typename ScalarOf<S>::type;
   const O* o = (const O*)(fbuf + fl.oall) + (((size_t)(sample0 + k) * 6 + c) * ns + s) * d.L3;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < n * L2; i += blockDim.x) {
-    const int pr = i % n, yz = i / n, y = yz % L, z = yz / L;
-    const O* v = o + (size_t)(z * L + y) * L + 2 * (j0 + pr);
-    zp[(pr * L + y) * L1 + z] = make_double2((double)v[0], (double)v[1]);
+  const int tid = threadIdx.x, bd = blockDim.x;
+  // the loads of kOLd elements are issued together, unconditionally (as in
+  // field_what_kernel)
+  constexpr int kOLd = 12;
+  const int nl = n * L2;
+  for (int i0 = tid; i0 < nl; i0 += kOLd * bd) {
+    O va[kOLd], vb[kOLd];
+    int at[kOLd];
+#pragma unroll
+    for (int j = 0; j < kOLd; ++j) {
+      const int iu = i0 + j * bd, i = min(iu, nl - 1);
+      const int pr = i % n, yz = i / n, y = yz % L, z = yz / L;
+      const O* v = o + (size_t)(z * L + y) * L + 2 * (j0 + pr);
+      va[j] = v[0];
+      vb[j] = v[1];
+      at[j] = iu < nl ? (pr * L + y) * L1 + z : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < kOLd; ++j)
+      if (at[j] >= 0) zp[at[j]] = make_double2((double)va[j], (double)vb[j]);
   }
   __syncthreads();
   const bool active = tid < 2 * n * L;  // a lane pair per row, then per column
@@ -462,26 +486,31 @@ __global__ __launch_bounds__(512) void field_ohat_kernel(const LatDesc* __restri
   }
 }
 
-// part[((k * ns + s) * 6 + c) * 2 n_rf L^2 + (2 f + plane) L^2 + p L + q]:
-//   sum_x What[k][f][s][x - m](p, q) * Ohat_c[k][s][x](p, q),  m_0 = (r - 1) / 2, m_1 = r / 2.
-// Thread = (sample k, slab s, frequency (p, q), component half h, chunk of up
-// to kZcF separations): the 3 components c = 3 h .. 3 h + 2 of every
+// part[((k * nsg + g) * 6 + c) * 2 n_rf L^2 + (2 f + plane) L^2 + p L + q]:
+//   sum over the slabs s of group g (s = g sps .. g sps + sps - 1) and over x
+//   of What[k][f][s][x - m](p, q) * Ohat_c[k][s][x](p, q),  m_0 = (r - 1) / 2, m_1 = r / 2.
+// Thread = (sample k, slab group g, frequency (p, q), component half h, chunk
+// of up to kZcF separations): the 3 components c = 3 h .. 3 h + 2 of every
 // separation of the chunk and both planes in registers, so that each W value
 // read serves three components and each Ohat value three separations.  Ohat
 // comes from the pair transforms.  With m_1 = m_0 (odd r) or m_0 + 1 (even
 // r), plane 1 at x uses the W plane that plane 0 used at x (odd) or x - 1
 // (even), so every W value is read once per thread: w1 carries W(x - 1 - m_0)
-// from pair to pair.
+// from pair to pair.  The values of the next x pair are loaded before the
+// sums of the current one.  Summing the slabs of a group in registers
+// divides the partial sums written, and read back by field_gsum_kernel, by
+// sps.
 constexpr int kZcF = 3;
+constexpr int kZcSlabs = 3;  // slabs per contraction thread
 template <int L, typename S>
 __global__ __launch_bounds__(256) void field_zcon_kernel(const FieldLat* __restrict__ flp, FieldParams fp,
-                                                         int nblk_e, const S* __restrict__ zhat,
+                                                         int nblk_e, int sps, const S* __restrict__ zhat,
                                                          const S* __restrict__ what, double2* __restrict__ part) {
   constexpr int L2 = L * L, NP = L / 2;
   const FieldLat fl = *flp;
-  const int ns = fl.ns;
-  const int lb = (int)xcd_block(blockIdx.x, gridDim.x);  // the blocks of one (k, s) share an L2
-  const int eb = lb % nblk_e, s = (lb / nblk_e) % ns, k = lb / (nblk_e * ns);
+  const int ns = fl.ns, nsg = (ns + sps - 1) / sps;
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x);  // the blocks of one (k, g) share an L2
+  const int eb = lb % nblk_e, sg = (lb / nblk_e) % nsg, k = lb / (nblk_e * nsg);
   const int n_fc = (fp.n_rf + kZcF - 1) / kZcF;
   const int e = eb * (int)blockDim.x + (int)threadIdx.x;
   if (e >= n_fc * 2 * L2) return;
@@ -489,40 +518,76 @@ __global__ __launch_bounds__(256) void field_zcon_kernel(const FieldLat* __restr
   const int nf = min(kZcF, fp.n_rf - f0);
   const int p = pq / L, q = pq - p * L;
   const int ib = (p == 0 ? 0 : L - p) * L + (q == 0 ? 0 : L - q);  // -k
-  const S* z = zhat + (((size_t)k * ns + s) * 6 + 3 * h) * NP * L2;
-  const S* wk = what + ((size_t)k * fp.n_rf * ns + s) * L * L2 + pq;  // + (f ns L + x) L2
-  double2 g0[kZcF][3], g1[kZcF][3], w1[kZcF];
-  int xw[kZcF];
+  // separations past the last of the chunk repeat the last one (loaded and
+  // summed like the others, never stored), so that no branch separates the
+  // loads of one x pair
+  double2 g0[kZcF][3], g1[kZcF][3];
+  int m0[kZcF], fj[kZcF];
   bool even[kZcF];
 #pragma unroll
   for (int j = 0; j < kZcF; ++j) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) g0[j][c] = g1[j][c] = make_double2(0.0, 0.0);
-    const int r = j < nf ? fp.rf[f0 + j] : 1, m0 = (r - 1) / 2;
+    fj[j] = min(f0 + j, fp.n_rf - 1);
+    const int r = fp.rf[fj[j]];
+    m0[j] = (r - 1) / 2;
     even[j] = (r & 1) == 0;
-    xw[j] = m0 == 0 ? 0 : L - m0;  // W plane of plane 0 at x = 0
-    w1[j] = j < nf ? get(wk + ((size_t)(f0 + j) * ns * L + (L - 1 - m0)) * L2) : make_double2(0.0, 0.0);  // W(-1 - m_0)
   }
-#pragma unroll 2
-  for (int jp = 0; jp < NP; ++jp) {
-    double2 oa[3], ob[3];
+  const int s_end = min(ns, (sg + 1) * sps);
+  for (int s = sg * sps; s < s_end; ++s) {
+    const S* z = zhat + (((size_t)k * ns + s) * 6 + 3 * h) * NP * L2;
+    const S* wk = what + ((size_t)k * fp.n_rf * ns + s) * L * L2 + pq;  // + (f ns L + x) L2
+    const S* wfj[kZcF];
+    int xa0[kZcF];  // W plane of plane 0 at x = 0
+    double2 w1[kZcF];
+#pragma unroll
+    for (int j = 0; j < kZcF; ++j) {
+      wfj[j] = wk + (size_t)fj[j] * ns * L * L2;
+      xa0[j] = m0[j] == 0 ? 0 : L - m0[j];
+      w1[j] = get(wfj[j] + (size_t)(L - 1 - m0[j]) * L2);  // W(-1 - m_0)
+    }
+    // offset of the W plane that plane 0 uses at x (0 <= x < L)
+    auto wplane = [&](int j, int x) {
+      const int a = xa0[j] + x;
+      return (size_t)(a >= L ? a - L : a) * L2;
+    };
+    // the stored values of x pair jp (cz, cm: Zhat at k and -k; ca, cb: W of
+    // plane 0 at x = 2 jp, 2 jp + 1); those of pair jp + 1 are loaded before
+    // the sums of pair jp, and the last pair loads itself again (unused)
+    S cz[3], cm[3], ca[kZcF], cb[kZcF];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const S* zc = z + ((size_t)c * NP + jp) * L2;
-      const double2 za = get(zc + pq), zm = get(zc + ib);
-      oa[c] = make_double2(0.5 * (za.x + zm.x), 0.5 * (za.y - zm.y));   // Ohat of x = 2 jp
-      ob[c] = make_double2(0.5 * (za.y + zm.y), -0.5 * (za.x - zm.x));  // Ohat of x = 2 jp + 1
+      cz[c] = z[(size_t)c * NP * L2 + pq];
+      cm[c] = z[(size_t)c * NP * L2 + ib];
     }
 #pragma unroll
     for (int j = 0; j < kZcF; ++j) {
-      if (j < nf) {
-        const S* wf = wk + (size_t)(f0 + j) * ns * L * L2;
-        const double2 wa = get(wf + (size_t)xw[j] * L2);
-        int xn = xw[j] + 1;
-        xn -= xn >= L ? L : 0;
-        const double2 wb = get(wf + (size_t)xn * L2);
-        xn += 1;
-        xw[j] = xn >= L ? xn - L : xn;
+      ca[j] = wfj[j][wplane(j, 0)];
+      cb[j] = wfj[j][wplane(j, 1)];
+    }
+    for (int jp = 0; jp < NP; ++jp) {
+      const int jn = jp + 1 < NP ? jp + 1 : jp;
+      S nz[3], nm[3], na[kZcF], nb[kZcF];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        nz[c] = z[((size_t)c * NP + jn) * L2 + pq];
+        nm[c] = z[((size_t)c * NP + jn) * L2 + ib];
+      }
+#pragma unroll
+      for (int j = 0; j < kZcF; ++j) {
+        na[j] = wfj[j][wplane(j, 2 * jn)];
+        nb[j] = wfj[j][wplane(j, 2 * jn + 1)];
+      }
+      double2 oa[3], ob[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double2 za = get(&cz[c]), zm = get(&cm[c]);
+        oa[c] = make_double2(0.5 * (za.x + zm.x), 0.5 * (za.y - zm.y));   // Ohat of x = 2 jp
+        ob[c] = make_double2(0.5 * (za.y + zm.y), -0.5 * (za.x - zm.x));  // Ohat of x = 2 jp + 1
+      }
+#pragma unroll
+      for (int j = 0; j < kZcF; ++j) {
+        const double2 wa = get(&ca[j]), wb = get(&cb[j]);
         const double2 ha = even[j] ? w1[j] : wa, hb = even[j] ? wa : wb;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -533,10 +598,20 @@ __global__ __launch_bounds__(256) void field_zcon_kernel(const FieldLat* __restr
         }
         w1[j] = wb;
       }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cz[c] = nz[c];
+        cm[c] = nm[c];
+      }
+#pragma unroll
+      for (int j = 0; j < kZcF; ++j) {
+        ca[j] = na[j];
+        cb[j] = nb[j];
+      }
     }
   }
   const int n_ent = 2 * fp.n_rf * L2;
-  double2* out = part + ((size_t)(k * ns + s) * 6 + 3 * h) * n_ent + pq;
+  double2* out = part + ((size_t)(k * nsg + sg) * 6 + 3 * h) * n_ent + pq;
 #pragma unroll
   for (int j = 0; j < kZcF; ++j) {
     if (j < nf) {
@@ -574,36 +649,85 @@ __global__ __launch_bounds__(128) void field_final_fft_kernel(const double2* __r
   }
 }
 
-// G[((f * 2 + plane) * 6 + c) * L2 + pq] += sum over (k, s) of part, in four
-// interleaved partial sums (fixed order) so that four loads are in flight
-__global__ void field_gsum_kernel(FieldParams fp, int L, int ns, int nk, const double2* __restrict__ part,
-                                  double2* __restrict__ G) {
+// G[((f * 2 + plane) * 6 + c) * L2 + pq] += sum over the n_terms (k, g) of
+// part.  Block: kGsEnt entries x kGsSeg segments; segment j sums the terms
+// j, j + kGsSeg, j + 2 kGsSeg, ... in two interleaved partial sums, and the
+// segment sums are added in segment order (a fixed order throughout).
+constexpr int kGsEnt = 32, kGsSeg = 8;
+__global__ __launch_bounds__(kGsEnt * kGsSeg) void field_gsum_kernel(FieldParams fp, int L, int n_terms,
+                                                                     const double2* __restrict__ part,
+                                                                     double2* __restrict__ G) {
+  __shared__ double2 seg[kGsSeg][kGsEnt];
   const int L2 = L * L, n_ent = 2 * fp.n_rf * L2;
-  const int item = blockIdx.x * blockDim.x + threadIdx.x;
-  if (item >= 6 * n_ent) return;
-  const int pq = item % L2, c = (item / L2) % 6, fpl = item / (6 * L2);
-  const double2* src = part + (size_t)c * n_ent + fpl * L2 + pq;
-  const size_t stride = (size_t)6 * n_ent;  // one (k, s)
-  const int n = nk * ns;
-  double re[4] = {0.0, 0.0, 0.0, 0.0}, im[4] = {0.0, 0.0, 0.0, 0.0};
-  int j = 0;
-  for (; j + 4 <= n; j += 4) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double2 v = src[(size_t)(j + u) * stride];
-      re[u] += v.x;
-      im[u] += v.y;
+  const int le = (int)threadIdx.x % kGsEnt, sj = (int)threadIdx.x / kGsEnt;
+  const int item = (int)blockIdx.x * kGsEnt + le;
+  double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+  if (item < 6 * n_ent) {
+    const int pq = item % L2, c = (item / L2) % 6, fpl = item / (6 * L2);
+    const double2* src = part + (size_t)c * n_ent + fpl * L2 + pq;
+    const size_t stride = (size_t)6 * n_ent;  // one term (k, g)
+    int j = sj;
+    for (; j + kGsSeg < n_terms; j += 2 * kGsSeg) {
+      const double2 u = src[(size_t)j * stride], v = src[(size_t)(j + kGsSeg) * stride];
+      a.x += u.x;
+      a.y += u.y;
+      b.x += v.x;
+      b.y += v.y;
+    }
+    if (j < n_terms) {
+      const double2 u = src[(size_t)j * stride];
+      a.x += u.x;
+      a.y += u.y;
     }
   }
-  for (int u = 0; j < n; ++j, ++u) {
-    const double2 v = src[(size_t)j * stride];
-    re[u] += v.x;
-    im[u] += v.y;
+  seg[sj][le] = make_double2(a.x + b.x, a.y + b.y);
+  __syncthreads();
+  if (sj == 0 && item < 6 * n_ent) {
+    double2 t = seg[0][le];
+#pragma unroll
+    for (int u = 1; u < kGsSeg; ++u) {
+      t.x += seg[u][le].x;
+      t.y += seg[u][le].y;
+    }
+    G[item].x += t.x;
+    G[item].y += t.y;
   }
-  G[item].x += (re[0] + re[1]) + (re[2] + re[3]);
-  G[item].y += (im[0] + im[1]) + (im[2] + im[3]);
 }
 
+// planes per block of the transform kernels (field_what_kernel,
+// field_ohat_kernel) over n_planes planes: the count that keeps the most
+// planes resident per compute unit (kCuLds bytes of LDS, blocks of at most
+// kFxLds), with idle lanes of a partial wavefront and idle planes of a
+// partial last group counted as lost
+constexpr size_t kCuLds = 160 * 1024;
+constexpr int kCuThreads = 2048;
+int transform_planes(int L, int n_planes) {
+  const size_t pb = (size_t)L * (L + 1) * sizeof(double2);
+  int best = 1;
+  double best_score = -1.0;
+  for (int np = 1; np <= n_planes && (size_t)np * pb <= kFxLds; ++np) {
+    const int thr = (2 * np * L + 63) / 64 * 64;
+    const int bpc = std::min<int>((int)(kCuLds / ((size_t)np * pb)), kCuThreads / thr);
+    const int groups = (n_planes + np - 1) / np;
+    const double score =
+        (double)bpc * np * (2.0 * np * L / thr) * ((double)n_planes / ((double)groups * np));
+    if (score > best_score + 1e-9) {
+      best = np;
+      best_score = score;
+    }
+  }
+  return best;
+}
+
+// threads per block of field_zcon_kernel for n items per (k, g): the
+// multiple of 64 up to 256 that leaves the fewest idle lanes (the largest
+// among equals)
+int zcon_threads(int n) {
+  int best = 256;
+  for (int t = 256; t >= 64; t -= 64)
+    if ((n + t - 1) / t * t - n < (n + best - 1) / best * best - n) best = t;
+  return best;
+}
 
 template <int L, typename S>
 hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, int ns, FieldParams fp,
@@ -611,18 +735,21 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
                                 double2* G, double2* F, bool finalize, hipStream_t st) {
   const uint64_t L3 = (uint64_t)L * L * L, L2 = (uint64_t)L * L;
   const size_t plane_bytes = (size_t)L * (L + 1) * sizeof(double2);  // LDS rows padded to L + 1
-  const int npb_w = std::min<int>(L, (int)(kFxLds / plane_bytes));
-  const int np_o = std::min<int>(L / 2, (int)(kFxLds / plane_bytes));  // pair planes per transform block
+  const int npb_w = transform_planes(L, L);
+  const int np_o = transform_planes(L, L / 2);  // pair planes per transform block
   const int n_ent = 2 * fp.n_rf * (int)L2;
   const int thr_w = (2 * npb_w * L + 63) / 64 * 64;  // lane pairs per row
   const int thr_o = (2 * np_o * L + 63) / 64 * 64;
   const int ngroups_w = (L + npb_w - 1) / npb_w;
   const int ngroups_o = (L / 2 + np_o - 1) / np_o;
-  const int nblk_e = (int)((((fp.n_rf + kZcF - 1) / kZcF) * 2 * L2 + 255) / 256);
+  const int sps = std::min(ns, kZcSlabs), nsg = (ns + sps - 1) / sps;
+  const int n_zc = ((fp.n_rf + kZcF - 1) / kZcF) * 2 * (int)L2;  // contraction threads per (k, g)
+  const int thr_z = zcon_threads(n_zc);
+  const int nblk_e = (n_zc + thr_z - 1) / thr_z;
   // scratch bytes per sample: What [n_rf][ns][L3] and Zhat [ns][6][L3 / 2]
-  // (storage type S), part [ns][6][n_ent] (double2)
+  // (storage type S), part [nsg][6][n_ent] (double2)
   const uint64_t per_sample = ((uint64_t)fp.n_rf * ns * L3 + (uint64_t)ns * 3 * L3) * sizeof(S) +
-                              (uint64_t)ns * 6 * n_ent * sizeof(double2);
+                              (uint64_t)nsg * 6 * n_ent * sizeof(double2);
   const int chunk =
       (int)std::max<uint64_t>(1, std::min<uint64_t>(64, scratch_elems * sizeof(double2) / per_sample));
   const int n_samples = fp.n_stored * fp.n_inner;
@@ -636,10 +763,10 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
                        npb_w * plane_bytes, st, lat, ml, fl, fp, s0, npb_w, mlbuf, fbuf, what);
     hipLaunchKernelGGL((field_ohat_kernel<L, S>), dim3((unsigned)((uint64_t)nk * ns * 6 * ngroups_o)), dim3(thr_o),
                        np_o * plane_bytes, st, lat, fl, s0, np_o, fbuf, zhat);
-    hipLaunchKernelGGL((field_zcon_kernel<L, S>), dim3((unsigned)((uint64_t)nk * ns * nblk_e)), dim3(256), 0, st, fl,
-                       fp, nblk_e, zhat, what, part);
-    hipLaunchKernelGGL(field_gsum_kernel, dim3(blocks_for(6 * (uint64_t)n_ent, 64)), dim3(64), 0, st, fp, L, ns, nk,
-                       part, G);
+    hipLaunchKernelGGL((field_zcon_kernel<L, S>), dim3((unsigned)((uint64_t)nk * nsg * nblk_e)), dim3(thr_z), 0, st,
+                       fl, fp, nblk_e, sps, zhat, what, part);
+    hipLaunchKernelGGL(field_gsum_kernel, dim3((unsigned)((6 * (uint64_t)n_ent + kGsEnt - 1) / kGsEnt)),
+                       dim3(kGsEnt * kGsSeg), 0, st, fp, L, nk * nsg, part, G);
   }
   if (finalize)
     hipLaunchKernelGGL(field_final_fft_kernel<L>, dim3(fp.n_rf * 12), dim3((2 * L + 63) / 64 * 64), 0, st, G, F);
