@@ -320,18 +320,8 @@ __device__ __forceinline__ double2 get(const float2* p) {
   return make_double2((double)v.x, (double)v.y);
 }
 
-// in-place FFT of the N values v[i * stride] (LDS)
-template <int N, int SIGN>
-__device__ __forceinline__ void fft_line(double2* v, int stride) {
-  double2 y[N];
-#pragma unroll
-  for (int n = 0; n < N; ++n) y[fftreg::kPos<N>.v[n]] = v[n * stride];
-  fftreg::run<N, SIGN>(y);
-#pragma unroll
-  for (int k = 0; k < N; ++k) v[k * stride] = y[k];
-}
-
-// The same transform (N even) by the two lanes h = 0, 1 of a lane pair
+// In-place FFT of the N values v[i * stride] (LDS, N even) by the two lanes
+// h = 0, 1 of a lane pair
 // (adjacent lanes of one wavefront): lane h transforms the samples n = 2 m + h
 // in registers (N / 2 points), lane 1 applies exp(SIGN 2 pi i k / N), and one
 // radix-2 step through LDS combines the halves:
@@ -339,8 +329,7 @@ __device__ __forceinline__ void fft_line(double2* v, int stride) {
 // A wavefront performs its LDS operations in issue order; the fence keeps
 // the compiler from moving the partner reads above the half write-back, and
 // each output depends on the partner value read at its position, so that
-// read always precedes the write.  Twice the lanes of fft_line per row, for
-// the same LDS.
+// read always precedes the write.
 template <int N, int SIGN>
 __device__ __forceinline__ void fft_line_pair(double2* v, int stride, int h) {
   constexpr int M = N / 2;
@@ -363,11 +352,37 @@ __device__ __forceinline__ void fft_line_pair(double2* v, int stride, int h) {
   }
 }
 
+// The combining step of fft_line_pair with the lane's half transform in
+// registers: lane h holds in y[k] the transform U_h(k) of its samples
+// n = 2 m + h; the pair exchanges the twiddled halves through the LDS line v
+// (N values at the given stride, free for the pair to overwrite) and lane h
+// ends with X(k + h N / 2) in y[k].
+template <int N, int SIGN>
+__device__ __forceinline__ void pair_exchange(double2 (&y)[N / 2], double2* v, int stride, int h) {
+  constexpr int M = N / 2;
+  if (h) {
+#pragma unroll
+    for (int k = 1; k < M; ++k) y[k] = fftreg::cmulc(y[k], fftreg::kTw<N>.c[k], (double)SIGN * fftreg::kTw<N>.s[k]);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // earlier reads of the line are done
+#pragma unroll
+  for (int k = 0; k < M; ++k) v[(h * M + k) * stride] = y[k];
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // the halves are in LDS
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const double2 p = v[((1 - h) * M + k) * stride];
+    y[k] = h ? fftreg::csub(p, y[k]) : fftreg::cadd(y[k], p);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // the partner halves are read
+}
+
 // What[((k * n_rf + f) * ns + s) * L + x][p * L + q] = sum_{y,z} W(x, y, z) exp(+2 pi i (p y + q z) / L),
-// i.e. the transform of W at (-p, -q).  Block: (k, f, s, group of npb x planes).
-// The planes are built in LDS (coalesced reads), transformed along z by rows
-// (a lane pair per (x, y)) and along y by columns (a lane pair per (x, q)),
-// and stored.
+// i.e. the transform of W at (-p, -q).  Block: (k, s, f, group of npb x
+// planes), a lane pair per row (x, y) and then per column (x, q).  Each row
+// pair loads its samples of W from memory into registers and transforms them
+// along z (the exchange and the result go to the row in LDS); each column
+// pair transforms along y from LDS and stores its outputs, so that LDS
+// carries only the exchanges and the transposition.
 template <int L, typename S>
 __global__ __launch_bounds__(512) void field_what_kernel(const LatDesc* __restrict__ lat,
                                                          const MLDesc* __restrict__ mlp,
@@ -375,114 +390,110 @@ __global__ __launch_bounds__(512) void field_what_kernel(const LatDesc* __restri
                                                          int sample0, int npb, const double2* __restrict__ mlbuf,
                                                          const double* __restrict__ fbuf, S* __restrict__ what) {
   extern __shared__ double2 pl[];  // [nx][L (y)][L + 1]
-  constexpr int L1 = L + 1;
+  constexpr int L1 = L + 1, M = L / 2;
   const LatDesc d = *lat;
   const FieldLat fl = *flp;
   const int ns = fl.ns;
   const int ngroups = (L + npb - 1) / npb;
-  const int b = blockIdx.x;
-  const int grp = b % ngroups, s = (b / ngroups) % ns, f = (b / (ngroups * ns)) % fp.n_rf;
-  const int k = b / (ngroups * ns * fp.n_rf);
+  // the blocks of one (k, s) read the same time lines: consecutive logical
+  // blocks on one XCD
+  const int b = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int grp = b % ngroups, f = (b / ngroups) % fp.n_rf, s = (b / (ngroups * fp.n_rf)) % ns;
+  const int k = b / (ngroups * fp.n_rf * ns);
   const int x0 = grp * npb, nx = min(npb, L - x0);
   const int sample = sample0 + k, m = sample / fp.n_inner;
   const MLDesc ml = *mlp;
   const double2* e = mlbuf + ml.ell + ((size_t)sample * ns + s) * d.L3;
   const double2* w = (const double2*)(fbuf + fl.w) + (((size_t)m * fp.n_rf + f) * ns + s) * d.L3;
   const int r = fp.rf[f];
-  const int tid = threadIdx.x, bd = blockDim.x, n = nx * L * L;
-  // W(x, y, z) = w(x0) conj(e(x0)) e(x0 + r), x0 = (z L + y) L + x, x fastest.
-  // The loads of kWLd elements are issued together, unconditionally (the
-  // index is clamped; an element past the end is loaded but not stored), so
-  // that no branch separates them.
-  constexpr int kWLd = 6;
-  for (int i0 = tid; i0 < n; i0 += kWLd * bd) {
-    double2 u[kWLd], v[kWLd], wv[kWLd];
-    int at[kWLd];
+  const int tid = threadIdx.x, h = tid & 1, pair = tid >> 1;
+  const bool active = pair < nx * L;
+  // rows: pair = (x, y), x fastest so that neighbouring pairs read
+  // neighbouring x; W(x, y, z) = w(x0) conj(e(x0)) e(x0 + r), x0 = (z L + y) L + x
+  if (active) {
+    const int xc = pair % nx, y = pair / nx, x = x0 + xc;
+    int xr = x + r;
+    xr -= xr >= L ? L : 0;
+    double2 v[M];
 #pragma unroll
-    for (int j = 0; j < kWLd; ++j) {
-      const int iu = i0 + j * bd, i = min(iu, n - 1);
-      const int xc = i % nx, yz = i / nx, y = yz % L, z = yz / L, x = x0 + xc;
-      int xr = x + r;
-      xr -= xr >= L ? L : 0;
-      const int row = (z * L + y) * L;
-      u[j] = e[row + x];
-      v[j] = e[row + xr];
-      wv[j] = w[row + x];
-      at[j] = iu < n ? (xc * L + y) * L1 + z : -1;
+    for (int j = 0; j < M; ++j) {
+      const int row = ((2 * j + h) * L + y) * L;
+      const double2 u = e[row + x], t = e[row + xr];
+      v[fftreg::kPos<M>.v[j]] = cmul(w[row + x], make_double2(u.x * t.x + u.y * t.y, u.x * t.y - u.y * t.x));
     }
+    fftreg::run<M, 1>(v);
+    double2* line = pl + (xc * L + y) * L1;
+    pair_exchange<L, 1>(v, line, 1, h);
 #pragma unroll
-    for (int j = 0; j < kWLd; ++j)
-      if (at[j] >= 0)
-        pl[at[j]] = cmul(wv[j], make_double2(u[j].x * v[j].x + u[j].y * v[j].y, u[j].x * v[j].y - u[j].y * v[j].x));
+    for (int j = 0; j < M; ++j) line[h * M + j] = v[j];
   }
   __syncthreads();
-  // a lane pair per row, then per column (fft_line_pair)
-  const bool active = tid < 2 * nx * L;
-  const int xc = tid / (2 * L), t = (tid >> 1) % L, h = tid & 1;
-  if (active) fft_line_pair<L, 1>(pl + (xc * L + t) * L1, 1, h);  // row y = t, along z
-  __syncthreads();
-  if (active) fft_line_pair<L, 1>(pl + xc * L * L1 + t, L1, h);  // column q = t, along y
-  __syncthreads();
-  S* dst = what + ((((size_t)k * fp.n_rf + f) * ns + s) * L + x0) * L * L;
-  for (int i = tid; i < n; i += bd) {
-    const int c = i / (L * L), pq = i - c * (L * L), p = pq / L, q = pq - p * L;
-    put(dst + (size_t)c * L * L + pq, pl[(c * L + p) * L1 + q]);
+  // columns: pair = (x, q); outputs p = h M + j
+  if (active) {
+    const int xc = pair / L, q = pair % L;
+    double2* col = pl + xc * L * L1 + q;
+    double2 v[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) v[fftreg::kPos<M>.v[j]] = col[(2 * j + h) * L1];
+    fftreg::run<M, 1>(v);
+    pair_exchange<L, 1>(v, col, L1, h);
+    S* dst = what + ((((size_t)k * fp.n_rf + f) * ns + s) * L + x0 + xc) * L * L + q;
+#pragma unroll
+    for (int j = 0; j < M; ++j) put(dst + (size_t)(h * M + j) * L, v[j]);
   }
 }
 
 // Zhat[((k * ns + s) * 6 + c) * (L / 2) + j][p * L + q] (complex): the
 // transform over (y, z) of Z = O_c(2 j) + i O_c(2 j + 1) for sample
 // sample0 + k, inner slab s, from the stored slab sums O_c.  Block: (k, s, c,
-// group of np pairs); the pair planes are staged (pairs fastest, so that
-// neighbouring lanes read neighbouring x), then np L lane pairs transform
-// rows (along z) and columns (along y).
+// group of np pairs); as field_what_kernel, a lane pair per row (pair plane,
+// y) loads its samples from memory and transforms them along z, and a lane
+// pair per column (pair plane, q) transforms along y and stores.
 template <int L, typename S>
 __global__ __launch_bounds__(512) void field_ohat_kernel(const LatDesc* __restrict__ lat,
                                                          const FieldLat* __restrict__ flp, int sample0, int np,
                                                          const double* __restrict__ fbuf, S* __restrict__ zhat) {
   extern __shared__ double2 zp[];  // [np][L (y)][L + 1]
-  constexpr int L1 = L + 1, L2 = L * L, NP = L / 2;
+  constexpr int L1 = L + 1, L2 = L * L, NP = L / 2, M = L / 2;
   const LatDesc d = *lat;
   const FieldLat fl = *flp;
   const int ns = fl.ns, ngroups = (NP + np - 1) / np;
-  const int b = blockIdx.x;
+  const int b = (int)xcd_block(blockIdx.x, gridDim.x);  // the groups of one plane share cache lines
   const int grp = b % ngroups, c = (b / ngroups) % 6, s = (b / (ngroups * 6)) % ns, k = b / (ngroups * 6 * ns);
   const int j0 = grp * np, n = min(np, NP - j0);
   // the stored sums are in the storage precision (FP32 for FP32 links)
   using O = typename ScalarOf<S>::type;
   const O* o = (const O*)(fbuf + fl.oall) + (((size_t)(sample0 + k) * 6 + c) * ns + s) * d.L3;
-  const int tid = threadIdx.x, bd = blockDim.x;
-  // the loads of kOLd elements are issued together, unconditionally (as in
-  // field_what_kernel)
-  constexpr int kOLd = 12;
-  const int nl = n * L2;
-  for (int i0 = tid; i0 < nl; i0 += kOLd * bd) {
-    O va[kOLd], vb[kOLd];
-    int at[kOLd];
+  const int tid = threadIdx.x, h = tid & 1, pair = tid >> 1;
+  const bool active = pair < n * L;
+  // rows: pair = (pair plane, y), pair planes fastest
+  if (active) {
+    const int pr = pair % n, y = pair / n;
+    double2 v[M];
 #pragma unroll
-    for (int j = 0; j < kOLd; ++j) {
-      const int iu = i0 + j * bd, i = min(iu, nl - 1);
-      const int pr = i % n, yz = i / n, y = yz % L, z = yz / L;
-      const O* v = o + (size_t)(z * L + y) * L + 2 * (j0 + pr);
-      va[j] = v[0];
-      vb[j] = v[1];
-      at[j] = iu < nl ? (pr * L + y) * L1 + z : -1;
+    for (int j = 0; j < M; ++j) {
+      const O* a = o + (size_t)((2 * j + h) * L + y) * L + 2 * (j0 + pr);
+      v[fftreg::kPos<M>.v[j]] = make_double2((double)a[0], (double)a[1]);
     }
+    fftreg::run<M, -1>(v);
+    double2* line = zp + (pr * L + y) * L1;
+    pair_exchange<L, -1>(v, line, 1, h);
 #pragma unroll
-    for (int j = 0; j < kOLd; ++j)
-      if (at[j] >= 0) zp[at[j]] = make_double2((double)va[j], (double)vb[j]);
+    for (int j = 0; j < M; ++j) line[h * M + j] = v[j];
   }
   __syncthreads();
-  const bool active = tid < 2 * n * L;  // a lane pair per row, then per column
-  const int pl = tid / (2 * L), t = (tid >> 1) % L, h = tid & 1;
-  if (active) fft_line_pair<L, -1>(zp + (pl * L + t) * L1, 1, h);  // rows, along z
-  __syncthreads();
-  if (active) fft_line_pair<L, -1>(zp + pl * L * L1 + t, L1, h);  // columns, along y
-  __syncthreads();
-  S* dst = zhat + ((((size_t)k * ns + s) * 6 + c) * NP + j0) * L2;
-  for (int i = tid; i < n * L2; i += blockDim.x) {
-    const int pr = i / L2, pq = i - pr * L2, p = pq / L, q = pq - p * L;
-    put(dst + (size_t)pr * L2 + pq, zp[(pr * L + p) * L1 + q]);
+  // columns: pair = (pair plane, q); outputs p = h M + j
+  if (active) {
+    const int pr = pair / L, q = pair % L;
+    double2* col = zp + pr * L * L1 + q;
+    double2 v[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) v[fftreg::kPos<M>.v[j]] = col[(2 * j + h) * L1];
+    fftreg::run<M, -1>(v);
+    pair_exchange<L, -1>(v, col, L1, h);
+    S* dst = zhat + ((((size_t)k * ns + s) * 6 + c) * NP + j0 + pr) * L2 + q;
+#pragma unroll
+    for (int j = 0; j < M; ++j) put(dst + (size_t)(h * M + j) * L, v[j]);
   }
 }
 
