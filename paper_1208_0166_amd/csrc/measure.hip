@@ -337,12 +337,23 @@ __global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDe
   const int ngroups = (n_r + kFoldK - 1) / kFoldK;
   const int per_child = n_child * L;
   // rows of the plain lines, then (multihit) rows of the multihit lines
-  const int staged = children * per_child;
-  for (int e = threadIdx.x; e < (multihit ? 2 : 1) * staged; e += blockDim.x) {
-    const int h = e / staged, ee = e - h * staged;
-    const int c = ee / per_child, i = (ee / L) % n_child, x = ee % L;
-    rowbuf[e] = mlbuf[(h ? ell_mh : ell) + ((size_t)(sample_base + i) * ns_child + S * children + c) * d.L3 +
-                      (size_t)base + (size_t)x * stride];
+  // The loads of kFoldLd values are issued together, unconditionally (the
+  // index is clamped: past the end, the last value is loaded and stored again
+  // in its own place), so that no branch or wait separates them.
+  const int staged = children * per_child, n_st = (multihit ? 2 : 1) * staged;
+  constexpr int kFoldLd = 16;
+  for (int e0 = threadIdx.x; e0 < n_st; e0 += kFoldLd * (int)blockDim.x) {
+    double2 v[kFoldLd];
+#pragma unroll
+    for (int j = 0; j < kFoldLd; ++j) {
+      const int e = min(e0 + j * (int)blockDim.x, n_st - 1);
+      const int rw = e / L, x = e - rw * L;  // row (h, c, i) of the staged rows
+      const int i = rw % n_child, hc = rw / n_child, c = hc % children, h = hc / children;
+      v[j] = mlbuf[(h ? ell_mh : ell) + ((size_t)(sample_base + i) * ns_child + S * children + c) * d.L3 +
+                   (size_t)base + (size_t)x * stride];
+    }
+#pragma unroll
+    for (int j = 0; j < kFoldLd; ++j) rowbuf[min(e0 + j * (int)blockDim.x, n_st - 1)] = v[j];
   }
   __syncthreads();
   const double inv = 1.0 / (double)n_child;
@@ -354,7 +365,9 @@ __global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDe
     double2 prod[kFoldK];
 #pragma unroll
     for (int j = 0; j < kFoldK; ++j) {
-      const int r = j < kn ? rvals[r_off + axis * n_r + k0 + j] & 0xffff : 0;
+      // separations past the group's last are read clamped and never used
+      const int rv = rvals[r_off + axis * n_r + min(k0 + j, n_r - 1)];
+      const int r = j < kn ? rv & 0xffff : 0;
       const int t = x0 + r;
       xr[j] = t >= L ? t - L : t;
       // multihit lines for r >= 2 (the two lines share no plaquette)
@@ -367,28 +380,29 @@ __global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDe
       double2 avg[kFoldK];
 #pragma unroll
       for (int j = 0; j < kFoldK; ++j) avg[j] = make_double2(0.0, 0.0);
+      // every lane sums all kFoldK slots (those past the group's last take
+      // r = 0 and are never stored), so that no branch splits the wavefront
+#pragma unroll 2
       for (int i = 0; i < n_child; ++i) {
         const double2 u = ep[i * L + x0], uh = eh[i * L + x0];
 #pragma unroll
         for (int j = 0; j < kFoldK; ++j) {
-          if (j < kn) {
-            const double2 a = mh[j] ? uh : u, v = (mh[j] ? eh : ep)[i * L + xr[j]];
-            avg[j].x += a.x * v.x + a.y * v.y;
-            avg[j].y += a.x * v.y - a.y * v.x;
-          }
+          const double2 a = mh[j] ? uh : u, v = (mh[j] ? eh : ep)[i * L + xr[j]];
+          avg[j].x += a.x * v.x + a.y * v.y;
+          avg[j].y += a.x * v.y - a.y * v.x;
         }
       }
 #pragma unroll
       for (int j = 0; j < kFoldK; ++j) prod[j] = cmul(prod[j], make_double2(avg[j].x * inv, avg[j].y * inv));
     }
     double2* pp = accbuf + acc_parent + ((size_t)S * d.L3 + (size_t)base + (size_t)x0 * stride) * nR + axis * n_r + k0;
+    // the accumulators are read together (clamped) before the updates
+    double2 old[kFoldK];
 #pragma unroll
-    for (int j = 0; j < kFoldK; ++j) {
-      if (j < kn) {
-        pp[j].x += prod[j].x;
-        pp[j].y += prod[j].y;
-      }
-    }
+    for (int j = 0; j < kFoldK; ++j) old[j] = pp[min(j, kn - 1)];
+#pragma unroll
+    for (int j = 0; j < kFoldK; ++j)
+      if (j < kn) pp[j] = make_double2(old[j].x + prod[j].x, old[j].y + prod[j].y);
   }
 }
 
