@@ -28,7 +28,10 @@ template <typename R>
 __global__ void plaq_field_kernel(const R* __restrict__ links, const LatDesc* __restrict__ lats,
                                   const int2* __restrict__ blocks, double* __restrict__ partial) {
   __shared__ double sh[16];
-  const int2 bk = blocks[blockIdx.x];
+  // neighbouring sites (which read each other's links) on one XCD; the
+  // partial row is that of the logical block
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int2 bk = blocks[lb];
   const LatDesc d = lats[bk.x];
   const uint32_t n = (uint32_t)bk.y + threadIdx.x;
   double v[kPlaqFieldWidth];
@@ -50,7 +53,7 @@ __global__ void plaq_field_kernel(const R* __restrict__ links, const LatDesc* __
   }
   for (int j = 0; j < kPlaqFieldWidth; ++j) {
     const double r = block_sum(v[j], sh);
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kPlaqFieldWidth + j] = r;
+    if (threadIdx.x == 0) partial[(size_t)lb * kPlaqFieldWidth + j] = r;
   }
 }
 
@@ -196,7 +199,7 @@ template <typename R>
 __global__ void ml_lines_kernel(const R* __restrict__ links, const LatDesc* __restrict__ lats,
                                 const MLDesc* __restrict__ mls, const int2* __restrict__ blocks, int inner_th,
                                 int sample, double2* __restrict__ mlbuf) {
-  const int2 bk = blocks[blockIdx.x];
+  const int2 bk = blocks[xcd_block(blockIdx.x, gridDim.x)];  // neighbouring sites on one XCD
   const LatDesc d = lats[bk.x];
   const int ns = d.T / inner_th;
   const int item = bk.y + (int)threadIdx.x;
@@ -228,7 +231,7 @@ __global__ void ml_fold_kernel(const LatDesc* __restrict__ lats, const MLDesc* _
                                const int2* __restrict__ blocks, int child_level, int parent_level, int n_levels,
                                int child_is_inner, int n_child, int sample_base, const int* __restrict__ rvals,
                                const double2* __restrict__ mlbuf, double2* __restrict__ accbuf) {
-  const int2 bk = blocks[blockIdx.x];
+  const int2 bk = blocks[xcd_block(blockIdx.x, gridDim.x)];  // neighbouring sites on one XCD
   const LatDesc d = lats[bk.x];
   const MLDesc m = mls[bk.x];
   const int ns_child = m.ns[child_level];
@@ -448,7 +451,8 @@ template <typename R, bool SQ>
 __global__ void field_o_kernel(const R* __restrict__ links, const LatDesc* __restrict__ lats,
                                const FieldLat* __restrict__ fls, const int2* __restrict__ blocks, int th_inner,
                                int sample, double* __restrict__ fbuf) {
-  const int2 bk = blocks[blockIdx.x];
+  // neighbouring sites (which read each other's links) on one XCD
+  const int2 bk = blocks[xcd_block(blockIdx.x, gridDim.x)];
   const LatDesc d = lats[bk.x];
   const FieldLat fl = fls[bk.x];
   const int item = bk.y + (int)threadIdx.x;
