@@ -290,15 +290,16 @@ __global__ void field_final_kernel(FieldParams fp, int L, const double2* __restr
 
 // ---------------------------------------------------------------------------
 // Fast path (L with factors 2, 3, 5 only, L <= kFxMaxL).  Each 1D transform is
-// a thread-private row or column FFT in registers (fft_reg.h) over planes
-// staged in LDS.  The O planes are real: two neighbouring x planes are
-// transformed together as one complex plane Z = O_a + i O_b
+// split over a lane pair: half-length FFTs in registers (fft_reg.h) and one
+// radix-2 step through LDS, rows from memory into registers and columns from
+// the LDS plane out to memory.  The O planes are real: two neighbouring x
+// planes are transformed together as one complex plane Z = O_a + i O_b
 // (field_ohat_kernel) and separated in Fourier space by the contraction
 // (field_zcon_kernel),
 //   Ohat_a(k) = (Z(k) + conj Z(-k)) / 2,   Ohat_b(k) = (Z(k) - conj Z(-k)) / 2i.
 // ---------------------------------------------------------------------------
 constexpr int kFxMaxL = 48;
-constexpr size_t kFxLds = 64512;  // LDS per block of field_what_kernel (bytes)
+constexpr size_t kFxLds = 64512;  // most LDS per block of the transform kernels (bytes)
 
 // Storage of the per-sample transforms between the fast-path kernels: FP64
 // (double2), or FP32 (float2) for FP32 lattices, whose field operators carry
