@@ -143,22 +143,29 @@ def test_batch_multilevel_with_field_matches_oracle(oracle_mod):
         close_rel(f_g, f_o)
 
 
-@pytest.mark.parametrize("L,rf", [(10, [2, 3]), (12, [2, 3]), (20, [2, 3]), (32, [2, 3]),
-                                  (24, list(range(1, 13))), (32, [1, 2, 5, 7, 16]),
-                                  (36, [5]), (40, [1, 8]), (48, [2, 4, 6])])
-def test_fused_field_contraction_matches_general(L, rf):
+@pytest.mark.parametrize("L,rf,T,levels", [(10, [2, 3], 4, [2]), (12, [2, 3], 4, [2]), (20, [2, 3], 4, [2]),
+                                           (32, [2, 3], 4, [2]), (24, list(range(1, 13)), 4, [2]),
+                                           (32, [1, 2, 5, 7, 16], 4, [2]), (36, [5], 4, [2]), (40, [1, 8], 4, [2]),
+                                           (48, [2, 4, 6], 4, [2]), (2, [1], 4, [2]), (6, [2, 3], 4, [2]),
+                                           (8, [2, 3], 4, [2]), (16, [2, 5], 4, [2]), (18, [2, 3, 7], 4, [2]),
+                                           (30, [2, 11], 4, [2]), (18, [2, 5], 8, [4, 2])])
+def test_fused_field_contraction_matches_general(L, rf, T, levels):
     # the fused contraction (register FFTs of radices 2, 3, 4, 5) against the
-    # general one (stored direct transforms) on the same chain; the long r
-    # lists split the fused contraction into several blocks per sample
-    T = 4
-    say(f"[gpu] fused vs general field contraction L={L} rf={rf}")
+    # general one (stored direct transforms) on the same chain, at every
+    # length of the fused path (transform blocks of 1 to 12 planes, odd
+    # counts and partial last groups among them); the long r lists split the
+    # fused contraction into several blocks per sample; T = 8 with slabs of 2
+    # under slabs of 4 gives four inner slabs, summed by the contraction
+    # threads in groups of three and one
+    say(f"[gpu] fused vs general field contraction L={L} T={T} levels={levels} rf={rf}")
+    r_all = sorted(set(r for r in [1, 2, 3] + rf if r < L))
     res = []
     for general in (False, True):
         g = u1ml.init_lattice(L, T, 1.0, 21)
         if general:
             u1ml.set_debug(g, 2)
         u1ml.sweep(g, 1, 2)
-        u1ml.multilevel(g, [2], [2], 1, 2, sorted(set([1, 2, 3] + rf)), rf_list=rf)
+        u1ml.multilevel(g, levels, [2] * len(levels), 1, 2, r_all, rf_list=rf)
         _, c, f = u1ml.measure(g, observables=False, correlator=True, field_profile=True)
         res.append((u1ml.get_links(g), c, f))
     np.testing.assert_array_equal(res[0][0], res[1][0])
