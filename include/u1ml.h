@@ -32,11 +32,14 @@
  *  - Every int-returning call returns U1ML_OK (0) or a negative error code;
  *    u1ml_last_error() gives a message for the most recent failure on the
  *    calling thread.  Handles are owned by the library, are not thread safe,
- *    and distinct handles are independent.  Host pointers are only read or
- *    written during the call; the library never keeps them.
+ *    and distinct handles are independent (also when driven from different
+ *    threads at once).  Host pointers are only read or written during the
+ *    call; the library never keeps them.
  *  - Work is queued on the stream given in the options (NULL = a stream the
  *    library creates, at default priority, and destroys with the handle).
- *    Calls that return host data synchronise that stream.
+ *    Calls that return host data synchronise that stream; every copy
+ *    between host and device goes through it, never through the legacy
+ *    default stream.
  */
 #ifndef U1ML_H
 #define U1ML_H

@@ -213,6 +213,17 @@ struct Engine {
     return U1ML_OK;
   }
 
+  // Host <-> device copy in this handle's stream order, complete on return.
+  // Never through the legacy default stream: that would tie the handle to
+  // the streams of other handles (and fail while one of them is being
+  // captured into a graph by another thread).
+  int copy(void* dst, const void* src, size_t n, hipMemcpyKind kind) {
+    if (n == 0) return U1ML_OK;
+    U1_HIP(hipMemcpyAsync(dst, src, n, kind, stream));
+    U1_HIP(hipStreamSynchronize(stream));
+    return U1ML_OK;
+  }
+
   // block table for per-lattice item counts (built once, reused)
   int table(const std::vector<int>& items, int blk, Table** out) {
     auto key = std::make_pair(items, blk);
@@ -233,7 +244,7 @@ struct Engine {
     t->block = blk;
     if (!h.empty()) {
       U1_TRY(t->buf.ensure(h.size() * sizeof(int2)));
-      U1_HIP(hipMemcpy(t->buf.p, h.data(), h.size() * sizeof(int2), hipMemcpyHostToDevice));
+      U1_TRY(copy(t->buf.p, h.data(), h.size() * sizeof(int2), hipMemcpyHostToDevice));
     }
     *out = t.get();
     tables[key] = std::move(t);
@@ -261,7 +272,7 @@ struct Engine {
     t->n_blocks = (int)h.size();
     if (!h.empty()) {
       U1_TRY(t->buf.ensure(h.size() * sizeof(int4)));
-      U1_HIP(hipMemcpy(t->buf.p, h.data(), h.size() * sizeof(int4), hipMemcpyHostToDevice));
+      U1_TRY(copy(t->buf.p, h.data(), h.size() * sizeof(int4), hipMemcpyHostToDevice));
     }
     *out = t.get();
     pass_tables[key] = std::move(t);
@@ -399,15 +410,13 @@ struct Engine {
   }
 
   int upload_pass_ids() {
-    U1_HIP(hipStreamSynchronize(stream));
-    U1_HIP(hipMemcpy(pass_ids.p, h_pass_ids.data(), n_lats * sizeof(uint64_t), hipMemcpyHostToDevice));
+    U1_TRY(copy(pass_ids.p, h_pass_ids.data(), n_lats * sizeof(uint64_t), hipMemcpyHostToDevice));
     return U1ML_OK;
   }
 
   int upload_lats() {
     ++epoch;  // beta enters the field observables
-    U1_HIP(hipStreamSynchronize(stream));
-    U1_HIP(hipMemcpy(lats.p, h_lats.data(), n_lats * sizeof(LatDesc), hipMemcpyHostToDevice));
+    U1_TRY(copy(lats.p, h_lats.data(), n_lats * sizeof(LatDesc), hipMemcpyHostToDevice));
     drop_graphs();  // single-lattice kernels take the descriptor by value
     return U1ML_OK;
   }
@@ -429,8 +438,7 @@ struct Engine {
     const LatDesc& d = h_lats[i];
     const size_t n = 8ull * d.V2;
     std::vector<char> raw(n * elem_size());
-    U1_HIP(hipStreamSynchronize(stream));
-    U1_HIP(hipMemcpy(raw.data(), links.as<char>() + d.off * elem_size(), raw.size(), hipMemcpyDeviceToHost));
+    U1_TRY(copy(raw.data(), links.as<char>() + d.off * elem_size(), raw.size(), hipMemcpyDeviceToHost));
     for (int mu = 0; mu < 4; ++mu)
       for (int p = 0; p < 2; ++p)
         for (uint32_t h = 0; h < (uint32_t)d.V2; ++h) {
@@ -459,8 +467,7 @@ struct Engine {
           else
             ((float*)raw.data())[dst] = (float)v;
         }
-    U1_HIP(hipStreamSynchronize(stream));
-    U1_HIP(hipMemcpy(links.as<char>() + d.off * elem_size(), raw.data(), raw.size(), hipMemcpyHostToDevice));
+    U1_TRY(copy(links.as<char>() + d.off * elem_size(), raw.data(), raw.size(), hipMemcpyHostToDevice));
     return U1ML_OK;
   }
 
@@ -478,13 +485,11 @@ struct Engine {
     U1_TRY(partial.ensure((size_t)t->n_blocks * W * sizeof(double)));
     U1_TRY(row_begin.ensure((n_lats + 1) * sizeof(int)));
     U1_TRY(red_out.ensure((size_t)n_lats * W * sizeof(double)));
-    U1_HIP(hipStreamSynchronize(stream));
-    U1_HIP(hipMemcpy(row_begin.p, t->lat_block_begin.data(), (n_lats + 1) * sizeof(int), hipMemcpyHostToDevice));
+    U1_TRY(copy(row_begin.p, t->lat_block_begin.data(), (n_lats + 1) * sizeof(int), hipMemcpyHostToDevice));
     U1_HIP(launch_plaq_field(prec, links.p, lats.as<LatDesc>(), bt(t), partial.as<double>(), stream));
     U1_HIP(launch_reduce_rows(partial.as<double>(), W, row_begin.as<int>(), n_lats, red_out.as<double>(), stream));
     std::vector<double> pf((size_t)n_lats * W);
-    U1_HIP(hipStreamSynchronize(stream));
-    U1_HIP(hipMemcpy(pf.data(), red_out.p, pf.size() * sizeof(double), hipMemcpyDeviceToHost));
+    U1_TRY(copy(pf.data(), red_out.p, pf.size() * sizeof(double), hipMemcpyDeviceToHost));
     std::vector<std::vector<double>> pc;
     U1_TRY(poly_corr(std::vector<int>(), pc));
     res.resize(n_lats);
@@ -526,18 +531,16 @@ struct Engine {
     U1_TRY(row_begin.ensure(rb.size() * sizeof(int)));
     U1_TRY(rvals_tmp.ensure(std::max(nR, 1) * sizeof(int)));
     U1_TRY(red_out.ensure((size_t)n_lats * width * sizeof(double)));
-    U1_HIP(hipStreamSynchronize(stream));
-    U1_HIP(hipMemcpy(poly_off.p, offs.data(), offs.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
-    U1_HIP(hipMemcpy(row_begin.p, rb.data(), rb.size() * sizeof(int), hipMemcpyHostToDevice));
-    if (nR) U1_HIP(hipMemcpy(rvals_tmp.p, r_list.data(), nR * sizeof(int), hipMemcpyHostToDevice));
+    U1_TRY(copy(poly_off.p, offs.data(), offs.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    U1_TRY(copy(row_begin.p, rb.data(), rb.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (nR) U1_TRY(copy(rvals_tmp.p, r_list.data(), nR * sizeof(int), hipMemcpyHostToDevice));
     U1_HIP(launch_poly_lines(prec, links.p, lats.as<LatDesc>(), bt(t), poly_off.as<uint64_t>(), poly.as<double>(),
                              stream));
     U1_HIP(launch_poly_corr(lats.as<LatDesc>(), bt(t), poly_off.as<uint64_t>(), poly.as<double>(),
                             rvals_tmp.as<int>(), nR, row_begin.as<int>(), rows.as<double>(), stream));
     U1_HIP(launch_reduce_rows(rows.as<double>(), width, row_begin.as<int>(), n_lats, red_out.as<double>(), stream));
     std::vector<double> h((size_t)n_lats * width);
-    U1_HIP(hipStreamSynchronize(stream));
-    U1_HIP(hipMemcpy(h.data(), red_out.p, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    U1_TRY(copy(h.data(), red_out.p, h.size() * sizeof(double), hipMemcpyDeviceToHost));
     out.assign(n_lats, std::vector<double>(width));
     for (int i = 0; i < n_lats; ++i)
       for (int c = 0; c < width; ++c) out[i][c] = h[(size_t)i * width + c] / (double)h_lats[i].L3;
@@ -626,8 +629,8 @@ struct Engine {
     U1_TRY(m.mlbuf.ensure(ell * sizeof(double2)));
     U1_TRY(m.accbuf.ensure(acc * sizeof(double2)));
     U1_TRY(m.corr.ensure((size_t)n_lats * m.max_r * 2 * sizeof(double)));
-    U1_HIP(hipMemcpy(m.mls.p, m.h_mls.data(), n_lats * sizeof(MLDesc), hipMemcpyHostToDevice));
-    U1_HIP(hipMemcpy(m.rvals.p, rv.data(), rv.size() * sizeof(int), hipMemcpyHostToDevice));
+    U1_TRY(copy(m.mls.p, m.h_mls.data(), n_lats * sizeof(MLDesc), hipMemcpyHostToDevice));
+    U1_TRY(copy(m.rvals.p, rv.data(), rv.size() * sizeof(int), hipMemcpyHostToDevice));
     if (m.field) {
       FieldParams& fp = m.fp;
       fp = FieldParams{};
@@ -671,7 +674,7 @@ struct Engine {
       U1_TRY(m.fbuf.ensure(fb * sizeof(double)));
       U1_TRY(m.fout.ensure(fo * sizeof(double2)));
       U1_TRY(m.scratch.ensure(m.scratch_elems * sizeof(double2)));
-      U1_HIP(hipMemcpy(m.fls.p, m.h_fls.data(), n_lats * sizeof(FieldLat), hipMemcpyHostToDevice));
+      U1_TRY(copy(m.fls.p, m.h_fls.data(), n_lats * sizeof(FieldLat), hipMemcpyHostToDevice));
     }
     return U1ML_OK;
   }
@@ -859,9 +862,7 @@ struct Engine {
       U1_TRY(ens.partial.ensure((size_t)t->n_blocks * W * sizeof(double)));
       U1_TRY(ens.red.ensure((size_t)n_lats * W * sizeof(double)));
       U1_TRY(ens.row_begin.ensure((n_lats + 1) * sizeof(int)));
-      U1_HIP(hipStreamSynchronize(stream));
-      U1_HIP(hipMemcpy(ens.row_begin.p, t->lat_block_begin.data(), (n_lats + 1) * sizeof(int),
-                       hipMemcpyHostToDevice));
+      U1_TRY(copy(ens.row_begin.p, t->lat_block_begin.data(), (n_lats + 1) * sizeof(int), hipMemcpyHostToDevice));
       // cleared by kernels, not memset nodes, in case the caller captures the stream
       U1_HIP(launch_ml_zero(ens.corr.as<double2>(), (uint64_t)n_lats * ens.max_r, stream));
       U1_HIP(launch_ml_zero(ens.fsum.as<double2>(), ens.fout_elems, stream));
@@ -890,17 +891,17 @@ struct Engine {
                                   ens.omean.as<double>() + 6 * i, ens.fp, L, inv, ens.conn.as<double2>(), stream));
     U1_HIP(hipStreamSynchronize(stream));
     if (correlator) {
-      U1_HIP(hipMemcpy(correlator, ens.corr.as<double2>() + (size_t)i * ens.max_r, ens.nR[i] * sizeof(double2),
-                       hipMemcpyDeviceToHost));
+      U1_TRY(copy(correlator, ens.corr.as<double2>() + (size_t)i * ens.max_r, ens.nR[i] * sizeof(double2),
+                  hipMemcpyDeviceToHost));
       for (int k = 0; k < 2 * ens.nR[i]; ++k) correlator[k] *= inv;
     }
     if (field_profile) {
-      U1_HIP(hipMemcpy(field_profile, ens.fsum.as<double2>() + ens.fout_off[i], nf * sizeof(double2),
-                       hipMemcpyDeviceToHost));
+      U1_TRY(copy(field_profile, ens.fsum.as<double2>() + ens.fout_off[i], nf * sizeof(double2),
+                  hipMemcpyDeviceToHost));
       for (size_t k = 0; k < 2 * nf; ++k) field_profile[k] *= inv;
     }
     if (connected)
-      U1_HIP(hipMemcpy(connected, ens.conn.p, nf * sizeof(double2), hipMemcpyDeviceToHost));
+      U1_TRY(copy(connected, ens.conn.p, nf * sizeof(double2), hipMemcpyDeviceToHost));
     return U1ML_OK;
   }
 
@@ -1085,12 +1086,12 @@ int read_results(Engine& e, int i, u1ml_observables* obs, double* correlator, do
   }
   U1_HIP(hipStreamSynchronize(e.stream));
   if (correlator)
-    U1_HIP(hipMemcpy(correlator, e.ml.corr.as<double>() + (size_t)i * e.ml.max_r * 2, e.ml.nR[i] * 2 * sizeof(double),
-                     hipMemcpyDeviceToHost));
+    U1_TRY(e.copy(correlator, e.ml.corr.as<double>() + (size_t)i * e.ml.max_r * 2, e.ml.nR[i] * 2 * sizeof(double),
+                  hipMemcpyDeviceToHost));
   if (field_profile) {
     const int L = e.h_lats[i].L;
-    U1_HIP(hipMemcpy(field_profile, e.ml.fout.as<double2>() + e.ml.fout_off[i],
-                     (size_t)e.ml.fp.n_rf * 12 * L * L * sizeof(double2), hipMemcpyDeviceToHost));
+    U1_TRY(e.copy(field_profile, e.ml.fout.as<double2>() + e.ml.fout_off[i],
+                  (size_t)e.ml.fp.n_rf * 12 * L * L * sizeof(double2), hipMemcpyDeviceToHost));
   }
   return U1ML_OK;
 }
@@ -1309,7 +1310,7 @@ int u1ml_get_accept_log(u1ml_lattice* lat, uint8_t* out, size_t cap, size_t* n_b
   U1_HIP(hipStreamSynchronize(e.stream));
   if (n_bytes) *n_bytes = e.log_used;
   size_t n = std::min(cap, e.log_used);
-  if (out && n) U1_HIP(hipMemcpy(out, e.log.p, n, hipMemcpyDeviceToHost));
+  if (out && n) U1_TRY(e.copy(out, e.log.p, n, hipMemcpyDeviceToHost));
   return U1ML_OK;
 }
 
