@@ -243,6 +243,66 @@ def counters_run(args):
                       "replicas": R, "sweeps": 4}), flush=True)
 
 
+LARGE_L = 48
+LARGE_LEVELS = [4, 2]
+LARGE_N_SUB = [20, 10]
+LARGE_THERM = 500
+
+
+def large_run(args):
+    """One 48^4 beta=1 chain per precision (same seed, cold start): LARGE_THERM
+    sweeps, then N_BETWEEN timed sweeps and one timed two-level multilevel
+    {4,2} x {20,10}, r = 1..24, E/B profiles at r = 2, 4, 6.  Reports the
+    sweep and multilevel throughput of the FP32 and FP64 paths and the
+    deviation of their observables (two chains of the same distribution: the
+    FP32 path draws its own random numbers, so the difference is
+    statistical)."""
+    import torch
+    from paper_1208_0166_amd import u1ml
+
+    torch.cuda.set_device(0)
+    r_list = list(range(1, LARGE_L // 2 + 1))
+    res = {}
+    for name, prec in (("fp32", u1ml.FP32), ("fp64", u1ml.FP64)):
+        st = torch.cuda.Stream()
+        g = u1ml.init_lattice(LARGE_L, LARGE_L, BETA, 3, start=u1ml.COLD, precision=prec, stream=st.cuda_stream)
+        for _ in range(LARGE_THERM):
+            u1ml.sweep(g, 1, 3)
+        u1ml.multilevel(g, LARGE_LEVELS, LARGE_N_SUB, 1, 3, r_list, rf_list=RF_LIST)  # set-up, capture
+        u1ml.synchronize(g)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(st)
+        for _ in range(N_BETWEEN):
+            u1ml.sweep(g, 1, 3)
+        ev[1].record(st)
+        u1ml.multilevel(g, LARGE_LEVELS, LARGE_N_SUB, 1, 3, r_list, rf_list=RF_LIST)
+        ev[2].record(st)
+        obs, corr, _ = u1ml.measure(g, correlator=True, field_profile=True)
+        ms_sw, ms_ml = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+        V = LARGE_L ** 4
+        up_ml = 0
+        prod = 1
+        for l, th in enumerate(LARGE_LEVELS):
+            prod *= LARGE_N_SUB[l]
+            up_ml += prod * (4 * V - 3 * V // th)  # links not frozen at level l
+        up_ml *= 1 + 3  # Metropolis + 3 OR
+        res[name] = {"sweep_updates_per_s": N_BETWEEN * 16 * V / (ms_sw * 1e-3), "ms_100_sweeps": ms_sw,
+                     "multilevel_ms": ms_ml, "multilevel_updates_per_s": up_ml / (ms_ml * 1e-3),
+                     "plaquette": obs["plaquette"], "C": [[c.real, c.imag] for c in corr[:6]]}
+        del g
+    d_plaq = abs(res["fp32"]["plaquette"] - res["fp64"]["plaquette"]) / abs(res["fp64"]["plaquette"])
+    out = {"metric": "link updates/s (Metropolis+OR), 48^4 beta=1, FP32 and FP64 paths",
+           "value": res["fp32"]["sweep_updates_per_s"], "unit": "link updates/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic (cold start, seed 3)",
+           "config": {"workload": f"one 48^4 beta=1 chain per precision: {LARGE_THERM} sweeps, then "
+                                  f"{N_BETWEEN} timed sweeps and one two-level multilevel {{4,2}} x {{20,10}}, "
+                                  "r=1..24, E/B mid-plane profiles at r=2,4,6"},
+           "fp32": res["fp32"], "fp64": res["fp64"],
+           "fp32_over_fp64_sweeps": res["fp32"]["sweep_updates_per_s"] / res["fp64"]["sweep_updates_per_s"],
+           "plaquette_rel_deviation": d_plaq}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +324,8 @@ def main():
     ap.add_argument("--symmetric", action="store_true",
                     help="correlator averaged over separations along +-x, +-y, +-z")
     ap.add_argument("--counters", action="store_true", help="short run for hardware-counter passes")
+    ap.add_argument("--large", action="store_true",
+                    help="instead of the 24^4 workload: one 48^4 chain per precision (FP32 vs FP64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); there is no multi-GPU path",
@@ -274,6 +336,9 @@ def main():
         sys.exit(2)
     if args.counters:
         counters_run(args)
+        return
+    if args.large:
+        large_run(args)
         return
 
     import torch
