@@ -303,6 +303,66 @@ def large_run(args):
     print(json.dumps(out), flush=True)
 
 
+UNEVEN_N = 64
+UNEVEN_SWEEPS = 10
+UNEVEN_TH, UNEVEN_NSUB = 2, 10
+
+
+def uneven_run(args):
+    """64 independent lattices of sizes drawn from {8,12,16,20,24}^4 and beta
+    from {0.9, 1.0, 1.1} (numpy default_rng(7)), FP32 links, one batch on one
+    stream: after N_THERM sweeps, 10 x steps cycles of UNEVEN_SWEEPS compound
+    sweeps plus a single-level multilevel (slab thickness 2, 10 updates) with
+    correlators at r = 1..L/2, each cycle one captured HIP graph; then every
+    lattice's results are read back."""
+    import numpy as np
+    import torch
+    from paper_1208_0166_amd import u1ml
+
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(7)
+    Ls = [int(v) for v in rng.choice([8, 12, 16, 20, 24], UNEVEN_N)]
+    betas = [float(v) for v in rng.choice([0.9, 1.0, 1.1], UNEVEN_N)]
+    st = torch.cuda.Stream()
+    b = u1ml.batch_create(Ls, Ls, betas, [1000 + i for i in range(UNEVEN_N)], start=u1ml.COLD,
+                          precision=u1ml.FP32, stream=st.cuda_stream)
+    for _ in range(N_THERM):
+        u1ml.batch_sweep(b, 1, 3)
+
+    def cycle():
+        u1ml.batch_cycle(b, UNEVEN_SWEEPS, 1, 3, UNEVEN_TH, UNEVEN_NSUB, use_graph=True)
+
+    for _ in range(max(args.warmup, 1)):
+        cycle()
+    u1ml.batch_synchronize(b)
+    n_cycles = 10 * args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    t0 = time.perf_counter()
+    ev[0].record(st)
+    for _ in range(n_cycles):
+        cycle()
+    ev[1].record(st)
+    res = [u1ml.batch_measure(b, i, correlator=True) for i in range(UNEVEN_N)]
+    el = time.perf_counter() - t0
+    ms_cycles = ev[0].elapsed_time(ev[1])
+    V = [L ** 4 for L in Ls]
+    up = sum(UNEVEN_SWEEPS * 16 * v + UNEVEN_NSUB * 4 * (4 * v - 3 * v // UNEVEN_TH) for v in V)
+    samples = sum(UNEVEN_NSUB * (L // UNEVEN_TH) for L in Ls)
+    counts = {int(k): int(c) for k, c in zip(*np.unique(Ls, return_counts=True))}
+    out = {"metric": "link updates/s (Metropolis+OR) and multilevel correlator samples/s, 64 uneven instances",
+           "value": up * n_cycles / el, "unit": "link updates/s", "n_gpus": 1, "steps": n_cycles,
+           "warmup": max(args.warmup, 1), "ms_per_step": 1e3 * el / n_cycles, "higher_is_better": True,
+           "dtype": "f32", "data": "synthetic (cold start, 200 thermalisation sweeps, sizes and beta from default_rng(7))",
+           "config": {"workload": f"64 independent lattices L^4, L counts {counts}, beta in {{0.9, 1.0, 1.1}}, one "
+                                  f"batch; per cycle {UNEVEN_SWEEPS} sweeps + single-level multilevel (th 2, 10 "
+                                  "updates), r = 1..L/2, one captured graph per cycle"},
+           "samples_per_s": samples * n_cycles / el,
+           "gpu_ms_per_cycle": ms_cycles / n_cycles,
+           "updates_per_s_gpu": up * n_cycles / (ms_cycles * 1e-3),
+           "plaquette_min_max": [min(r[0]["plaquette"] for r in res), max(r[0]["plaquette"] for r in res)]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,6 +386,8 @@ def main():
     ap.add_argument("--counters", action="store_true", help="short run for hardware-counter passes")
     ap.add_argument("--large", action="store_true",
                     help="instead of the 24^4 workload: one 48^4 chain per precision (FP32 vs FP64)")
+    ap.add_argument("--uneven", action="store_true",
+                    help="instead of the 24^4 workload: 64 lattices of uneven size and beta in captured cycles")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); there is no multi-GPU path",
@@ -339,6 +401,9 @@ def main():
         return
     if args.large:
         large_run(args)
+        return
+    if args.uneven:
+        uneven_run(args)
         return
 
     import torch
