@@ -726,11 +726,9 @@ struct Engine {
     for (int i = 0; i < n_lats; ++i) it.push_back(m.h_mls[i].ns[inner] * h_lats[i].L3);
     Table* t;
     U1_TRY(table(it, 256, &t));
-    U1_HIP(launch_ml_lines(prec, links.p, lats.as<LatDesc>(), m.mls.as<MLDesc>(), bt(t), m.th[inner], sample,
-                           m.mlbuf.as<double2>(), stream));
-    if (m.field && m.store_field)
-      U1_HIP(launch_field_o(prec, links.p, lats.as<LatDesc>(), m.fls.as<FieldLat>(), bt(t), m.th[inner], sample,
-                            (estimator & U1ML_FIELD_SQUARED) != 0, m.fbuf.as<double>(), stream));
+    U1_HIP(launch_ml_sample(prec, links.p, lats.as<LatDesc>(), m.mls.as<MLDesc>(), m.fls.as<FieldLat>(), bt(t),
+                            m.th[inner], sample, m.field && m.store_field, (estimator & U1ML_FIELD_SQUARED) != 0,
+                            m.mlbuf.as<double2>(), m.fbuf.as<double>(), stream));
     return U1ML_OK;
   }
 

@@ -77,8 +77,12 @@ hipError_t launch_poly_corr(const LatDesc* lats, BlockTable bt, const uint64_t* 
                             const int* rvals, int nR, const int* row_begin, double* rows, hipStream_t st);
 
 // multilevel
-hipError_t launch_ml_lines(int prec, const void* links, const LatDesc* lats, const MLDesc* mls, BlockTable bt,
-                           int inner_th, int sample, double2* mlbuf, hipStream_t st);
+struct FieldLat;
+// one inner sample: time lines (and multihit means), and with field the slab
+// sums of the insertion operators (squared: Eq. (6) instead of Eq. (5))
+hipError_t launch_ml_sample(int prec, const void* links, const LatDesc* lats, const MLDesc* mls, const FieldLat* fls,
+                            BlockTable bt, int inner_th, int sample, bool field, bool squared, double2* mlbuf,
+                            double* fbuf, hipStream_t st);
 // sample_base: first stored inner sample of the current inner run (field runs keep them all)
 hipError_t launch_ml_fold(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int child_level, int parent_level,
                           int n_levels, int child_is_inner, int n_child, int sample_base, const int* rvals,
@@ -117,9 +121,6 @@ struct FieldParams {
                  // every outer iteration is contracted as it completes (replay)
   int n_inner;   // samples per inner run
 };
-// squared = true stores the squared components of Eq. (6) instead of Eq. (5)
-hipError_t launch_field_o(int prec, const void* links, const LatDesc* lats, const FieldLat* fls, BlockTable bt,
-                          int th_inner, int sample, bool squared, double* fbuf, hipStream_t st);
 // ensemble sums of multilevel runs (Eq. (7)): acc[i] += src[i]; the field
 // means of one operator set (columns col0 .. col0 + 5 of the reduced rows,
 // divided by V) into acc[lat][6]; the connected profile of one lattice

@@ -195,11 +195,20 @@ __device__ __forceinline__ double2 multihit_mean(const R* links, const LatDesc& 
   return make_double2(q * sr, -q * si);
 }
 
-template <typename R>
-__global__ void ml_lines_kernel(const R* __restrict__ links, const LatDesc* __restrict__ lats,
-                                const MLDesc* __restrict__ mls, const int2* __restrict__ blocks, int inner_th,
-                                int sample, double2* __restrict__ mlbuf) {
-  const int2 bk = blocks[xcd_block(blockIdx.x, gridDim.x)];  // neighbouring sites on one XCD
+// One inner sample of every lattice, a thread per (inner slab s, spatial
+// site x3): the slab's time line exp(i sum_t theta_0) (Eq. (8)), with
+// multihit also the product of the temporal links' multihit means, and with
+// FIELD the slab sums over t of the insertion operators O_c(x3, t) (Eq. (5),
+// or Eq. (6) with SQ), stored in the link precision (FP32 lattices' sums
+// carry FP32 sine errors):
+//   oall[((sample * 6 + c) * ns + s) * L3 + x3].
+template <typename R, bool FIELD, bool SQ>
+__global__ void ml_sample_kernel(const R* __restrict__ links, const LatDesc* __restrict__ lats,
+                                 const MLDesc* __restrict__ mls, const FieldLat* __restrict__ fls,
+                                 const int2* __restrict__ blocks, int inner_th, int sample,
+                                 double2* __restrict__ mlbuf, double* __restrict__ fbuf) {
+  // neighbouring sites (which read each other's links) on one XCD
+  const int2 bk = blocks[xcd_block(blockIdx.x, gridDim.x)];
   const LatDesc d = lats[bk.x];
   const int ns = d.T / inner_th;
   const int item = bk.y + (int)threadIdx.x;
@@ -207,19 +216,33 @@ __global__ void ml_lines_kernel(const R* __restrict__ links, const LatDesc* __re
   const int s = item / d.L3, x3 = item - s * d.L3;
   const MLDesc* m = mls + bk.x;
   const size_t at = ((size_t)sample * ns + s) * d.L3 + x3;
+  Site st;
+  st.x = x3 % d.L;
+  st.y = (x3 / d.L) % d.L;
+  st.z = x3 / (d.L * d.L);
   // exp(i l), l = sum of theta_0 over the slab's times: the slab product of U_0
-  store_stream(mlbuf + m->ell + at, cexpi(time_line(links, d, x3, s * inner_th, inner_th)));
+  const double l = time_line(links, d, x3, s * inner_th, inner_th);
+  double o[6] = {0, 0, 0, 0, 0, 0};
+  if (FIELD) {
+    for (int t = s * inner_th; t < (s + 1) * inner_th; ++t) {
+      st.t = t;
+      add_field_ops<SQ>(links, d, st, o);
+    }
+  }
+  store_stream(mlbuf + m->ell + at, cexpi(l));
   if (m->multihit) {
-    Site st;
-    st.x = x3 % d.L;
-    st.y = (x3 / d.L) % d.L;
-    st.z = x3 / (d.L * d.L);
     double2 p = make_double2(1.0, 0.0);
     for (int t = s * inner_th; t < (s + 1) * inner_th; ++t) {
       st.t = t;
       p = cmul(p, multihit_mean(links, d, st));
     }
     store_stream(mlbuf + m->ell_mh + at, p);
+  }
+  if (FIELD) {
+    const FieldLat fl = fls[bk.x];
+    const double pre = SQ ? d.beta : d.sqrt_beta;
+    R* out = (R*)(fbuf + fl.oall) + (size_t)sample * 6 * ns * d.L3;
+    for (int c = 0; c < 6; ++c) store_stream(out + ((size_t)c * ns + s) * d.L3 + x3, pre * o[c]);
   }
 }
 
@@ -444,35 +467,6 @@ __global__ void ml_final_kernel(const LatDesc* __restrict__ lats, const MLDesc* 
 // the final weights, as a correlation over the mediator plane evaluated by 2D
 // discrete Fourier transforms in (y, z).
 // ---------------------------------------------------------------------------
-// oall[((sample * 6 + c) * ns + s) * L3 + y] = sum over the times t of inner
-// slab s of O_c(y, t): O_c = sqrt(beta) Im P_munu (Eq. (5)), or with SQ the
-// squared component beta (1 - Re P_munu) (Eq. (6)).
-template <typename R, bool SQ>
-__global__ void field_o_kernel(const R* __restrict__ links, const LatDesc* __restrict__ lats,
-                               const FieldLat* __restrict__ fls, const int2* __restrict__ blocks, int th_inner,
-                               int sample, double* __restrict__ fbuf) {
-  // neighbouring sites (which read each other's links) on one XCD
-  const int2 bk = blocks[xcd_block(blockIdx.x, gridDim.x)];
-  const LatDesc d = lats[bk.x];
-  const FieldLat fl = fls[bk.x];
-  const int item = bk.y + (int)threadIdx.x;
-  if (item >= fl.ns * d.L3) return;
-  const int s = item / d.L3, y3 = item - s * d.L3;
-  Site st;
-  st.x = y3 % d.L;
-  st.y = (y3 / d.L) % d.L;
-  st.z = y3 / (d.L * d.L);
-  double o[6] = {0, 0, 0, 0, 0, 0};
-  for (int t = s * th_inner; t < (s + 1) * th_inner; ++t) {
-    st.t = t;
-    add_field_ops<SQ>(links, d, st, o);
-  }
-  const double pre = SQ ? d.beta : d.sqrt_beta;
-  // stored in the link precision: FP32 lattices' sums carry FP32 sine errors
-  R* out = (R*)(fbuf + fl.oall) + (size_t)sample * 6 * fl.ns * d.L3;
-  for (int c = 0; c < 6; ++c) store_stream(out + ((size_t)c * fl.ns + s) * d.L3 + y3, pre * o[c]);
-}
-
 // ---------------------------------------------------------------------------
 // ensemble of multilevel runs and the connected profile of Eq. (7)
 // ---------------------------------------------------------------------------
@@ -549,14 +543,33 @@ hipError_t launch_poly_corr(const LatDesc* lats, BlockTable bt, const uint64_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_ml_lines(int prec, const void* links, const LatDesc* lats, const MLDesc* mls, BlockTable bt,
-                           int inner_th, int sample, double2* mlbuf, hipStream_t st) {
-  if (prec == kFP64)
-    hipLaunchKernelGGL(ml_lines_kernel<double>, dim3(bt.n_blocks), dim3(bt.block), 0, st, (const double*)links,
-                       lats, mls, bt.dev, inner_th, sample, mlbuf);
+namespace {
+template <typename R, bool FIELD, bool SQ>
+void launch_sample_t(const void* links, const LatDesc* lats, const MLDesc* mls, const FieldLat* fls, BlockTable bt,
+                     int inner_th, int sample, double2* mlbuf, double* fbuf, hipStream_t st) {
+  hipLaunchKernelGGL((ml_sample_kernel<R, FIELD, SQ>), dim3(bt.n_blocks), dim3(bt.block), 0, st, (const R*)links,
+                     lats, mls, fls, bt.dev, inner_th, sample, mlbuf, fbuf);
+}
+template <typename R>
+void launch_sample_r(const void* links, const LatDesc* lats, const MLDesc* mls, const FieldLat* fls, BlockTable bt,
+                     int inner_th, int sample, bool field, bool squared, double2* mlbuf, double* fbuf, hipStream_t st) {
+  if (!field)
+    launch_sample_t<R, false, false>(links, lats, mls, fls, bt, inner_th, sample, mlbuf, fbuf, st);
+  else if (squared)
+    launch_sample_t<R, true, true>(links, lats, mls, fls, bt, inner_th, sample, mlbuf, fbuf, st);
   else
-    hipLaunchKernelGGL(ml_lines_kernel<float>, dim3(bt.n_blocks), dim3(bt.block), 0, st, (const float*)links,
-                       lats, mls, bt.dev, inner_th, sample, mlbuf);
+    launch_sample_t<R, true, false>(links, lats, mls, fls, bt, inner_th, sample, mlbuf, fbuf, st);
+}
+}  // namespace
+
+hipError_t launch_ml_sample(int prec, const void* links, const LatDesc* lats, const MLDesc* mls, const FieldLat* fls,
+                            BlockTable bt, int inner_th, int sample, bool field, bool squared, double2* mlbuf,
+                            double* fbuf, hipStream_t st) {
+  if (bt.n_blocks == 0) return hipSuccess;
+  if (prec == kFP64)
+    launch_sample_r<double>(links, lats, mls, fls, bt, inner_th, sample, field, squared, mlbuf, fbuf, st);
+  else
+    launch_sample_r<float>(links, lats, mls, fls, bt, inner_th, sample, field, squared, mlbuf, fbuf, st);
   return hipGetLastError();
 }
 
@@ -593,26 +606,6 @@ hipError_t launch_ml_final(const LatDesc* lats, const MLDesc* mls, int n_lats, i
                            const double2* accbuf, double* out, hipStream_t st) {
   hipLaunchKernelGGL(ml_final_kernel, dim3(n_lats, max_r), dim3(kRedBlock), 0, st, lats, mls, max_r, top_level,
                      accbuf, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_field_o(int prec, const void* links, const LatDesc* lats, const FieldLat* fls, BlockTable bt,
-                          int th_inner, int sample, bool squared, double* fbuf, hipStream_t st) {
-  if (bt.n_blocks == 0) return hipSuccess;
-  const dim3 g(bt.n_blocks), b(bt.block);
-  if (prec == kFP64) {
-    const double* l = (const double*)links;
-    if (squared)
-      hipLaunchKernelGGL((field_o_kernel<double, true>), g, b, 0, st, l, lats, fls, bt.dev, th_inner, sample, fbuf);
-    else
-      hipLaunchKernelGGL((field_o_kernel<double, false>), g, b, 0, st, l, lats, fls, bt.dev, th_inner, sample, fbuf);
-  } else {
-    const float* l = (const float*)links;
-    if (squared)
-      hipLaunchKernelGGL((field_o_kernel<float, true>), g, b, 0, st, l, lats, fls, bt.dev, th_inner, sample, fbuf);
-    else
-      hipLaunchKernelGGL((field_o_kernel<float, false>), g, b, 0, st, l, lats, fls, bt.dev, th_inner, sample, fbuf);
-  }
   return hipGetLastError();
 }
 
