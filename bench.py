@@ -474,6 +474,11 @@ def main():
         "poly_abs": obs["poly_abs"],
         "C_r1": [corr[0].real, corr[0].imag],
         "roofline": roofline,
+        # the whole step against the same bound: every link update at 9 words
+        # per update and the HBM peak (the field contraction, folds and
+        # time-line sums are work on top of the updates, not counted as updates)
+        "step_roofline": {"updates_per_s_at_peak": HBM_PEAK_GBS * 1e9 / (WORDS_PER_UPDATE * bw),
+                          "frac": main_run["updates_per_s"] / (HBM_PEAK_GBS * 1e9 / (WORDS_PER_UPDATE * bw))},
     }
     del main_run
     if not args.no_compare:
