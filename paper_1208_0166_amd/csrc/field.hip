@@ -498,10 +498,10 @@ __global__ __launch_bounds__(512) void field_ohat_kernel(const LatDesc* __restri
   }
 }
 
-// part[((k * nsg + g) * 6 + c) * 2 n_rf L^2 + (2 f + plane) L^2 + p L + q]:
-//   sum over the slabs s of group g (s = g sps .. g sps + sps - 1) and over x
+// part[((k * nsg + sg) * 6 + c) * 2 n_rf L^2 + (2 f + plane) L^2 + p L + q]:
+//   sum over the slabs s of group sg (s = sg sps .. sg sps + sps - 1) and over x
 //   of What[k][f][s][x - m](p, q) * Ohat_c[k][s][x](p, q),  m_0 = (r - 1) / 2, m_1 = r / 2.
-// Thread = (sample k, slab group g, frequency (p, q), component half h, chunk
+// Thread = (sample k, slab group sg, frequency (p, q), component half h, chunk
 // of up to kZcF separations): the 3 components c = 3 h .. 3 h + 2 of every
 // separation of the chunk and both planes in registers, so that each W value
 // read serves three components and each Ohat value three separations.  Ohat
@@ -521,7 +521,7 @@ __global__ __launch_bounds__(256) void field_zcon_kernel(const FieldLat* __restr
   constexpr int L2 = L * L, NP = L / 2;
   const FieldLat fl = *flp;
   const int ns = fl.ns, nsg = (ns + sps - 1) / sps;
-  const int lb = (int)xcd_block(blockIdx.x, gridDim.x);  // the blocks of one (k, g) share an L2
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x);  // the blocks of one (k, sg) share an L2
   const int eb = lb % nblk_e, sg = (lb / nblk_e) % nsg, k = lb / (nblk_e * nsg);
   const int n_fc = (fp.n_rf + kZcF - 1) / kZcF;
   const int e = eb * (int)blockDim.x + (int)threadIdx.x;
@@ -529,7 +529,7 @@ __global__ __launch_bounds__(256) void field_zcon_kernel(const FieldLat* __restr
   const int pq = e % L2, h = (e / L2) % 2, f0 = (e / (2 * L2)) * kZcF;
   const int nf = min(kZcF, fp.n_rf - f0);
   const int p = pq / L, q = pq - p * L;
-  const int ib = (p == 0 ? 0 : L - p) * L + (q == 0 ? 0 : L - q);  // -k
+  const int ib = (p == 0 ? 0 : L - p) * L + (q == 0 ? 0 : L - q);  // (-p, -q)
   // separations past the last of the chunk repeat the last one (loaded and
   // summed like the others, never stored), so that no branch separates the
   // loads of one x pair
@@ -563,9 +563,10 @@ __global__ __launch_bounds__(256) void field_zcon_kernel(const FieldLat* __restr
       const int a = xa0[j] + x;
       return (size_t)(a >= L ? a - L : a) * L2;
     };
-    // the stored values of x pair jp (cz, cm: Zhat at k and -k; ca, cb: W of
-    // plane 0 at x = 2 jp, 2 jp + 1); those of pair jp + 1 are loaded before
-    // the sums of pair jp, and the last pair loads itself again (unused)
+    // the stored values of x pair jp (cz, cm: Zhat at (p, q) and (-p, -q);
+    // ca, cb: W of plane 0 at x = 2 jp, 2 jp + 1); those of pair jp + 1 are
+    // loaded before the sums of pair jp, and the last pair loads itself again
+    // (unused)
     S cz[3], cm[3], ca[kZcF], cb[kZcF];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
