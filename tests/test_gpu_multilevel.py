@@ -468,3 +468,51 @@ def test_fp32_fused_contraction_matches_general(L):
     np.testing.assert_array_equal(res[0][0], res[1][0])
     np.testing.assert_array_equal(res[0][1], res[1][1])
     close_rel(res[0][2], res[1][2], 1e-6)
+
+
+def test_field_size_and_separation_limits():
+    # the most field separations a run takes (32: r = 1..32 at L = 40), fused
+    # against general; 33 separations, and a field run at L = 64 (> 62), are
+    # refused; at L = 62, the largest (62 is not a length of the fused path,
+    # so the general contraction runs), one update per level makes the field
+    # the plain Eq. (9) definition on the final links, computed here at
+    # sampled offsets of both planes
+    from tests.test_oracle_multilevel import field_ops, polyakov_lines
+
+    say("[gpu] field limits: 32 separations at L=40, refusals, L=62 sampled")
+    L, T = 40, 4
+    rf = list(range(1, 33))
+    res = []
+    for general in (False, True):
+        g = u1ml.init_lattice(L, T, 1.0, 31)
+        if general:
+            u1ml.set_debug(g, 2)
+        u1ml.sweep(g, 1, 2)
+        u1ml.multilevel(g, [2], [2], 1, 2, rf, rf_list=rf)
+        _, c, f = u1ml.measure(g, observables=False, correlator=True, field_profile=True)
+        res.append((c, f))
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    close_rel(res[0][1], res[1][1])
+    with pytest.raises(u1ml.U1MLError) as e:
+        u1ml.multilevel(g, [2], [1], 1, 1, list(range(1, 34)), rf_list=list(range(1, 34)))
+    assert e.value.code == u1ml.EINVAL
+    g64 = u1ml.init_lattice(64, 4, 1.0, 31)
+    with pytest.raises(u1ml.U1MLError) as e:
+        u1ml.multilevel(g64, [2], [1], 1, 1, [2], rf_list=[2])
+    assert e.value.code == u1ml.EINVAL
+    L, r = 62, 2
+    g = u1ml.init_lattice(L, T, 1.0, 31)
+    u1ml.sweep(g, 1, 3)
+    u1ml.multilevel(g, [2], [1], 1, 3, [1, 2], rf_list=[r])
+    _, c, f = u1ml.measure(g, observables=False, correlator=True, field_profile=True)
+    th = u1ml.get_links(g)
+    np.testing.assert_allclose(c, [plain_corr(th, k) for k in (1, 2)], atol=1e-12)
+    P = polyakov_lines(th)
+    w = np.conj(P) * np.roll(P, -r, axis=2)
+    osum = field_ops(th, 1.0).sum(axis=1)  # [c][z][y][x]
+    scale = np.abs(f[0]).max()
+    for plane, m in enumerate([(r - 1) // 2, r // 2]):
+        for dy, dz in [(0, 0), (1, 0), (0, 61), (30, 17), (61, 61)]:
+            sh = np.roll(np.roll(np.roll(osum, -m, axis=3), -dy, axis=2), -dz, axis=1)
+            want = (w[None] * sh).sum(axis=(1, 2, 3)) / (T * L ** 3)
+            assert np.abs(f[0][plane, :, dy, dz] - want).max() <= 1e-12 * scale
