@@ -202,6 +202,9 @@ __device__ __forceinline__ double2 multihit_mean(const R* links, const LatDesc& 
 // or Eq. (6) with SQ), stored in the link precision (FP32 lattices' sums
 // carry FP32 sine errors):
 //   oall[((sample * 6 + c) * ns + s) * L3 + x3].
+// With the field inserted every inner sample is kept; after the run the
+// samples are contracted with the final weights as a correlation over the
+// mediator plane (field.hip).
 template <typename R, bool FIELD, bool SQ>
 __global__ void ml_sample_kernel(const R* __restrict__ links, const LatDesc* __restrict__ lats,
                                  const MLDesc* __restrict__ mls, const FieldLat* __restrict__ fls,
@@ -461,12 +464,6 @@ __global__ void ml_final_kernel(const LatDesc* __restrict__ lats, const MLDesc* 
   }
 }
 
-// ---------------------------------------------------------------------------
-// field insertion: every inner sample keeps its time-line sums (ell) and its
-// slab sums of the field operators; after the run they are contracted with
-// the final weights, as a correlation over the mediator plane evaluated by 2D
-// discrete Fourier transforms in (y, z).
-// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // ensemble of multilevel runs and the connected profile of Eq. (7)
 // ---------------------------------------------------------------------------
