@@ -378,7 +378,7 @@ __device__ __forceinline__ void pair_exchange(double2 (&y)[N / 2], double2* v, i
 }
 
 // What[((k * n_rf + f) * ns + s) * L + x][p * L + q] = sum_{y,z} W(x, y, z) exp(+2 pi i (p y + q z) / L),
-// i.e. the transform of W at (-p, -q).  Block: (k, s, f, group of npb x
+// i.e. the transform of W at (-p, -q).  Block: (s, k, f, group of npb x
 // planes), a lane pair per row (x, y) and then per column (x, q).  Each row
 // pair loads its samples of W from memory into registers and transforms them
 // along z (the exchange and the result go to the row in LDS); each column
@@ -396,11 +396,15 @@ __global__ __launch_bounds__(512) void field_what_kernel(const LatDesc* __restri
   const FieldLat fl = *flp;
   const int ns = fl.ns;
   const int ngroups = (L + npb - 1) / npb;
-  // the blocks of one (k, s) read the same time lines: consecutive logical
-  // blocks on one XCD
+  // logical block order [s][k][f][group], consecutive logical blocks on one
+  // XCD: the blocks of one (k, s) read the same time lines, and consecutive
+  // samples of one outer iteration the same weights of (m, f, s), which an
+  // XCD's L2 then keeps (samples outermost, every sample would fetch all the
+  // weights of its outer iteration again)
   const int b = (int)xcd_block(blockIdx.x, gridDim.x);
-  const int grp = b % ngroups, f = (b / ngroups) % fp.n_rf, s = (b / (ngroups * fp.n_rf)) % ns;
-  const int k = b / (ngroups * fp.n_rf * ns);
+  const int nk = (int)gridDim.x / (ngroups * fp.n_rf * ns);
+  const int grp = b % ngroups, f = (b / ngroups) % fp.n_rf, k = (b / (ngroups * fp.n_rf)) % nk;
+  const int s = b / (ngroups * fp.n_rf * nk);
   const int x0 = grp * npb, nx = min(npb, L - x0);
   const int sample = sample0 + k, m = sample / fp.n_inner;
   const MLDesc ml = *mlp;
