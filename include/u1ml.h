@@ -65,6 +65,10 @@ extern "C" {
 #define U1ML_FP32 1 /* FP32 angles, hardware transcendentals; FP64 measurements */
 
 #define U1ML_MAX_LEVELS 3
+/* Metropolis hits per link and pass: the hit index is one byte of the
+ * random-number counter, so every entry point taking n_metro requires
+ * 0 <= n_metro <= U1ML_MAX_HITS (EINVAL otherwise). */
+#define U1ML_MAX_HITS 255
 #define U1ML_MAX_FIELD_R 32
 
 /* Field components of Eq. (5), in this order, in every field output. */
@@ -78,7 +82,8 @@ extern "C" {
 typedef struct u1ml_options {
     int start;        /* U1ML_COLD or U1ML_HOT (default HOT) */
     int precision;    /* U1ML_FP64 or U1ML_FP32 (default FP64) */
-    double eps;       /* Metropolis proposal theta + eps * U(-1, 1) (default 1.0) */
+    double eps;       /* Metropolis proposal theta + eps * U(-1, 1), 0 <= eps <= 2 pi
+                         (default 1.0) */
     void *stream;     /* hipStream_t to queue work on; NULL = a library-owned stream */
     void *dev_buf;    /* optional caller device buffer for the links, or NULL */
     size_t dev_bytes; /* its size; must be >= u1ml_link_bytes(L, T, precision) */
@@ -131,7 +136,7 @@ int u1ml_init_lattice(int L, int T, double beta, uint64_t seed, const u1ml_optio
 /* One compound sweep (Sec. 2.1): a Metropolis pass with n_metro hits per link
  * followed by n_or overrelaxation passes; each pass visits the checkerboard
  * classes mu = 0..3 (outer), parity 0, 1 (inner).  pass_id += (n_metro > 0).
- * n_metro, n_or >= 0.  Asynchronous. */
+ * 0 <= n_metro <= U1ML_MAX_HITS, n_or >= 0.  Asynchronous. */
 int u1ml_sweep(u1ml_lattice *lat, int n_metro, int n_or);
 
 /* The multilevel algorithm (Sec. 2.2) for the Polyakov correlator and the

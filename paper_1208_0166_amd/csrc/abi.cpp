@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -43,6 +44,10 @@ int fail(int code, const std::string& msg) {
 // largest |theta| accepted from the host; the updates fold angles back into
 // [-pi, pi) by whole periods, which needs them to be of moderate size
 constexpr double kMaxAngle = 64.0;
+// largest Metropolis width: theta + eps (2u - 1) with eps <= 2 pi already
+// reaches every angle, and a bounded proposal keeps the fold into [-pi, pi)
+// to a few periods
+constexpr double kMaxEps = 2.0 * 3.14159265358979323846;
 // scratch for the field contraction, per engine
 constexpr size_t kFieldScratchBytes = 512u << 20;
 // A two-level run with field insertion keeps every inner sample's time lines
@@ -958,7 +963,29 @@ struct u1ml_batch {
 
 namespace {
 
-std::map<std::tuple<int, int, int>, int> g_tuned_block;  // (L, T, precision) -> block
+// block sizes found by u1ml_autotune, shared by every handle created later
+// in the process: (L, T, precision) -> block
+std::mutex g_tuned_mutex;
+std::map<std::tuple<int, int, int>, int> g_tuned_block;
+
+int tuned_block(int L, int T, int prec, int fallback) {
+  std::lock_guard<std::mutex> lk(g_tuned_mutex);
+  auto it = g_tuned_block.find(std::make_tuple(L, T, prec));
+  return it != g_tuned_block.end() ? it->second : fallback;
+}
+
+void set_tuned_block(int L, int T, int prec, int block) {
+  std::lock_guard<std::mutex> lk(g_tuned_mutex);
+  g_tuned_block[std::make_tuple(L, T, prec)] = block;
+}
+
+// Metropolis hits per link of one pass: the hit index is a byte of the
+// random-number counter
+int check_hits(int n_metro, int n_or) {
+  if (n_metro < 0 || n_metro > U1ML_MAX_HITS || n_or < 0)
+    return fail(U1ML_EINVAL, "need 0 <= n_metro <= 255 and n_or >= 0");
+  return U1ML_OK;
+}
 
 int validate_size(int L, int T) {
   if (L < 2 || T < 2 || (L & 1) || (T & 1) || L > 256 || T > 256)
@@ -993,7 +1020,7 @@ int engine_create(Engine& e, const std::vector<int>& L, const std::vector<int>& 
   if (opt) o = *opt;
   if (o.precision != U1ML_FP64 && o.precision != U1ML_FP32) return fail(U1ML_EINVAL, "precision");
   if (o.start != U1ML_COLD && o.start != U1ML_HOT) return fail(U1ML_EINVAL, "start");
-  if (!std::isfinite(o.eps) || o.eps < 0) return fail(U1ML_EINVAL, "eps must be finite and >= 0");
+  if (!(o.eps >= 0 && o.eps <= kMaxEps)) return fail(U1ML_EINVAL, "eps must be in [0, 2 pi]");
   if (o.block != 0 && (o.block < 64 || o.block > 1024 || (o.block % 64)))
     return fail(U1ML_EINVAL, "block must be a multiple of 64 in [64, 1024]");
   const int n = (int)L.size();
@@ -1015,12 +1042,7 @@ int engine_create(Engine& e, const std::vector<int>& L, const std::vector<int>& 
   e.prec = o.precision;
   e.n_lats = n;
   e.link_elems = off;
-  if (o.block)
-    e.block = o.block;
-  else {
-    auto it = g_tuned_block.find(std::make_tuple(L[0], T[0], o.precision));
-    e.block = it != g_tuned_block.end() ? it->second : 256;
-  }
+  e.block = o.block ? o.block : tuned_block(L[0], T[0], o.precision, 256);
   if (allow_dev_buf && o.dev_buf) {
     if (o.dev_bytes < off * e.elem_size()) return fail(U1ML_EINVAL, "dev_buf smaller than u1ml_link_bytes");
     e.links.p = o.dev_buf;
@@ -1040,8 +1062,8 @@ int engine_create(Engine& e, const std::vector<int>& L, const std::vector<int>& 
 }
 
 int check_ml_args(const Engine& e, int n_levels, const int* th, const int* n_sub, int n_metro, int n_or) {
-  if (n_levels < 1 || n_levels > U1ML_MAX_LEVELS || !th || !n_sub || n_metro < 0 || n_or < 0)
-    return fail(U1ML_EINVAL, "multilevel arguments");
+  if (n_levels < 1 || n_levels > U1ML_MAX_LEVELS || !th || !n_sub) return fail(U1ML_EINVAL, "multilevel arguments");
+  U1_TRY(check_hits(n_metro, n_or));
   for (int l = 0; l < n_levels; ++l) {
     if (th[l] < 1 || n_sub[l] < 1) return fail(U1ML_EINVAL, "slab sizes and n_sub must be >= 1");
     if (l > 0 && th[l - 1] % th[l]) return fail(U1ML_EINVAL, "each slab size must divide the previous one");
@@ -1163,7 +1185,8 @@ int u1ml_init_lattice(int L, int T, double beta, uint64_t seed, const u1ml_optio
 }
 
 int u1ml_sweep(u1ml_lattice* lat, int n_metro, int n_or) {
-  if (!lat || n_metro < 0 || n_or < 0) return fail(U1ML_EINVAL, "sweep arguments");
+  U1_TRY(check_hits(n_metro, n_or));
+  if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
   Engine& e = lat->e;
   U1_TRY(e.set_device());
   return e.run_captured({0, n_metro, n_or}, [&]() { return e.sweep(n_metro, n_or, 0); });
@@ -1171,6 +1194,7 @@ int u1ml_sweep(u1ml_lattice* lat, int n_metro, int n_or) {
 
 int u1ml_multilevel(u1ml_lattice* lat, int n_levels, const int* slab_sizes, const int* n_sub, int n_metro, int n_or,
                     int n_r, const int* r_list, int n_rf, const int* rf_list) {
+  U1_TRY(check_hits(n_metro, n_or));
   if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
   return ml_entry(lat->e, n_levels, slab_sizes, n_sub, n_metro, n_or, n_r, r_list, n_rf, rf_list);
 }
@@ -1352,7 +1376,7 @@ int u1ml_load(u1ml_lattice* lat, const char* path) {
     std::fclose(f);
     return fail(U1ML_EINVAL, "checkpoint shape or precision differs from the lattice");
   }
-  if (!std::isfinite(beta) || beta < 0 || !std::isfinite(eps) || eps < 0) {
+  if (!std::isfinite(beta) || beta < 0 || !(eps >= 0 && eps <= kMaxEps)) {
     std::fclose(f);
     return fail(U1ML_EINVAL, "checkpoint beta or eps out of range");
   }
@@ -1398,7 +1422,8 @@ int u1ml_batch_create(int n, const int* L, const int* T, const double* beta, con
 }
 
 int u1ml_batch_sweep(u1ml_batch* b, int n_metro, int n_or) {
-  if (!b || n_metro < 0 || n_or < 0) return fail(U1ML_EINVAL, "batch_sweep arguments");
+  U1_TRY(check_hits(n_metro, n_or));
+  if (!b) return fail(U1ML_EINVAL, "batch is NULL");
   Engine& e = b->e;
   U1_TRY(e.set_device());
   return e.run_captured({0, n_metro, n_or}, [&]() { return e.sweep(n_metro, n_or, 0); });
@@ -1406,11 +1431,13 @@ int u1ml_batch_sweep(u1ml_batch* b, int n_metro, int n_or) {
 
 int u1ml_batch_multilevel(u1ml_batch* b, int n_levels, const int* slab_sizes, const int* n_sub, int n_metro,
                           int n_or, int n_r, const int* r_list, int n_rf, const int* rf_list) {
+  U1_TRY(check_hits(n_metro, n_or));
   if (!b) return fail(U1ML_EINVAL, "batch is NULL");
   return ml_entry(b->e, n_levels, slab_sizes, n_sub, n_metro, n_or, n_r, r_list, n_rf, rf_list);
 }
 
 int u1ml_batch_cycle(u1ml_batch* b, int n_sweeps, int n_metro, int n_or, int th, int n_sub, int use_graph) {
+  U1_TRY(check_hits(n_metro, n_or));
   if (!b || n_sweeps < 0) return fail(U1ML_EINVAL, "batch_cycle arguments");
   Engine& e = b->e;
   U1_TRY(check_ml_args(e, 1, &th, &n_sub, n_metro, n_or));
@@ -1518,13 +1545,14 @@ int u1ml_autotune(u1ml_lattice* lat, int* best_block) {
   int rc2 = e.upload_pass_ids();
   if (rc) return rc;
   if (rc2) return rc2;
-  g_tuned_block[std::make_tuple(e.h_lats[0].L, e.h_lats[0].T, e.prec)] = best;
+  set_tuned_block(e.h_lats[0].L, e.h_lats[0].T, e.prec, best);
   if (best_block) *best_block = best;
   return U1ML_OK;
 }
 
 static int profile_sweeps(Engine& e, int n_sweeps, int n_metro, int n_or, double* avg_us) {
-  if (!avg_us || n_sweeps < 0 || n_metro < 0 || n_or < 0) return fail(U1ML_EINVAL, "profile arguments");
+  if (!avg_us || n_sweeps < 0) return fail(U1ML_EINVAL, "profile arguments");
+  U1_TRY(check_hits(n_metro, n_or));
   U1_TRY(e.set_device());
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
   e.prof[0] = &ev[0];

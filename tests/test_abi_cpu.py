@@ -42,6 +42,10 @@ def test_strerror_codes():
     (4, 4, float("nan"), 0, 1.0, 0),
     (4, 4, 1.0, 5, 1.0, 0),      # precision
     (4, 4, 1.0, 0, -1.0, 0),     # eps
+    (4, 4, 1.0, 0, 6.3, 0),      # eps above 2 pi
+    (4, 4, 1.0, 1, 1e20, 0),     # huge eps (the proposal's fold into [-pi, pi) would not end)
+    (4, 4, 1.0, 0, float("inf"), 0),
+    (4, 4, 1.0, 0, float("nan"), 0),
     (4, 4, 1.0, 0, 1.0, 100),    # block not a multiple of 64
 ])
 def test_init_rejects_bad_arguments(L, T, beta, prec, eps, block):
@@ -89,3 +93,22 @@ def test_workspace_bytes_is_a_pure_size_function():
     f64 = wb(4, 8, [4, 2], [2, 3], 3, n_rf=2)
     assert f64 - wb(4, 8, [4, 2], [2, 3], 3, n_rf=2, precision=u1ml.FP32) == 6 * 6 * 4 * L3 * 4  # 2 x 3 samples kept
     assert wb(4, 8, [4, 2], [2, 3], 3, precision=7) == 0
+
+
+@pytest.mark.parametrize("n_metro,n_or", [(256, 3), (1000, 0), (-1, 3), (1, -1)])
+def test_hit_count_out_of_range_rejected(n_metro, n_or):
+    # the hit index is one byte of the random-number counter: more than 255
+    # hits per pass would repeat random numbers, so every entry point refuses
+    # them (checked before the handle, so no GPU is needed here)
+    lib = u1ml.load_library()
+    one = (C.c_int * 1)(2)
+    calls = [
+        lambda: lib.u1ml_sweep(None, n_metro, n_or),
+        lambda: lib.u1ml_batch_sweep(None, n_metro, n_or),
+        lambda: lib.u1ml_multilevel(None, 1, one, one, n_metro, n_or, 1, one, 0, None),
+        lambda: lib.u1ml_batch_multilevel(None, 1, one, one, n_metro, n_or, 1, one, 0, None),
+        lambda: lib.u1ml_batch_cycle(None, 1, n_metro, n_or, 2, 2, 0),
+    ]
+    for call in calls:
+        assert call() == u1ml.EINVAL
+        assert b"n_metro" in lib.u1ml_last_error()
