@@ -25,7 +25,7 @@ namespace {
 // Per block: the plaquette sum, the six field operators of Eq. (5) and the
 // six squared components of Eq. (6), summed over the block's sites.
 template <typename R>
-__global__ void plaq_field_kernel(const R* __restrict__ links, const LatDesc* __restrict__ lats,
+__global__ __launch_bounds__(256) void plaq_field_kernel(const R* __restrict__ links, const LatDesc* __restrict__ lats,
                                   const int2* __restrict__ blocks, double* __restrict__ partial) {
   __shared__ double sh[16];
   // neighbouring sites (which read each other's links) on one XCD; the
@@ -253,13 +253,13 @@ __global__ void ml_sample_kernel(const R* __restrict__ links, const LatDesc* __r
 // parent_level == n_levels denotes the top (one slab spanning all of T).
 // One thread per (S, x0, block of up to kFoldR separations).
 constexpr int kFoldR = 8;
-__global__ void ml_fold_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls,
+__global__ __launch_bounds__(256) void ml_fold_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls,
                                const int2* __restrict__ blocks, int child_level, int parent_level, int n_levels,
                                int child_is_inner, int n_child, int sample_base, const int* __restrict__ rvals,
                                const double2* __restrict__ mlbuf, double2* __restrict__ accbuf) {
   const int2 bk = blocks[xcd_block(blockIdx.x, gridDim.x)];  // neighbouring sites on one XCD
   const LatDesc d = lats[bk.x];
-  const MLDesc m = mls[bk.x];
+  const MLDesc& m = mls[bk.x];  // through the pointer (run-time level indices)
   const int ns_child = m.ns[child_level];
   const int ns_parent = parent_level == n_levels ? 1 : m.ns[parent_level];
   const int children = ns_child / ns_parent;
@@ -339,7 +339,7 @@ __global__ void ml_fold_kernel(const LatDesc* __restrict__ lats, const MLDesc* _
 // z are strided by L and L^2.
 constexpr int kFoldK = 8;
 constexpr size_t kFoldLds = 49152;  // bytes of staged rows per block
-__global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls,
+__global__ __launch_bounds__(256) void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls,
                                     const int2* __restrict__ blocks, int child_level, int parent_level, int n_levels,
                                     int n_child, int sample_base, const int* __restrict__ rvals,
                                     const double2* __restrict__ mlbuf, double2* __restrict__ accbuf) {
@@ -439,12 +439,14 @@ __global__ void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDe
 // axes the mean over the axes of the real part: the separation -r e
 // estimates the complex conjugate of +r e exactly (every factor is), so the
 // real part is the mean of both orientations.
-__global__ void ml_final_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls, int max_r,
+__global__ __launch_bounds__(kRedBlock) void ml_final_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls, int max_r,
                                 int top_level, const double2* __restrict__ accbuf, double* __restrict__ out) {
   __shared__ double sh[16];
   const int lat = blockIdx.x, k = blockIdx.y;
   const LatDesc d = lats[lat];
-  const MLDesc m = mls[lat];
+  // read through the pointer: a local copy indexed by the run-time level
+  // would live in scratch memory
+  const MLDesc& m = mls[lat];
   if (k >= m.n_r) return;  // uniform per block
   double re = 0.0, im = 0.0;
   const double2* a = accbuf + m.acc[top_level];
