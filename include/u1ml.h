@@ -160,6 +160,30 @@ int u1ml_sweep(u1ml_lattice *lat, int n_metro, int n_or);
 int u1ml_multilevel(u1ml_lattice *lat, int n_levels, const int *slab_sizes, const int *n_sub, int n_metro,
                     int n_or, int n_r, const int *r_list, int n_rf, const int *rf_list);
 
+/* For callers that cannot allocate device memory during the call: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The multilevel run of u1ml_multilevel (same arguments, the
+ * lattice's estimator flags, no field insertion: n_rf = 0) with its whole
+ * workspace (time lines, level accumulators, descriptors, block tables) in a
+ * fixed device array of U1ML_NOALLOC_BYTES compiled into the library, one
+ * per GPU, held from the first lattice created on that GPU until the process
+ * ends.  The call allocates no device memory, frees none, and makes no graph:
+ * kernels are launched one by one on the lattice's stream.
+ *   dev_correlator: caller-owned DEVICE buffer of n_r * 2 doubles; receives
+ *     C_ML(r) as [n_r][2] (Re, Im), the same bits u1ml_multilevel followed
+ *     by u1ml_measure gives for the same links and pass id.
+ * The links and pass id advance exactly as with u1ml_multilevel; the result
+ * is not kept for u1ml_measure or u1ml_ensemble_add.  Synchronises the
+ * stream before returning.  EINVAL for bad arguments and for runs whose
+ * workspace does not fit the array (e.g. a 24^4 two-level run {4,2} x
+ * {10,20} with r = 1..12 takes 72 MB and fits; u1ml_workspace_bytes with
+ * n_rf = 0 gives the size, plus a few KB of tables).  Every call on one GPU,
+ * from any lattice, uses the same array: calls that overlap in time on one
+ * GPU (other threads, other streams) race and give wrong results. */
+#define U1ML_NOALLOC_BYTES (96u << 20)
+int u1ml_multilevel_noalloc(u1ml_lattice *lat, int n_levels, const int *slab_sizes, const int *n_sub, int n_metro,
+                            int n_or, int n_r, const int *r_list, double *dev_correlator);
+
 /* Estimator options of the multilevel runs that follow (default 0).
  * U1ML_MULTIHIT (Sec. 2.2, the variance reduction the paper applies to the
  * potential): for every separation r >= 2 the temporal links of both Polyakov

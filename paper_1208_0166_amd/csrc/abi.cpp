@@ -106,6 +106,25 @@ struct Table {
   std::vector<int> lat_block_begin;  // n_lats + 1
 };
 
+// Bump allocator over a fixed device range (the allocation-free entry point
+// places its whole workspace in the library's static device array).
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  // view of the next `bytes` (256-byte aligned) as a buffer the arena keeps
+  int carve(DevBuf& b, size_t bytes) {
+    const size_t at = (used + 255) & ~(size_t)255;
+    if (at > cap || bytes > cap - at)
+      return fail(U1ML_EINVAL, "the run's workspace (more than " + std::to_string(at + bytes) +
+                                   " bytes) exceeds the static device array of " + std::to_string(cap) + " bytes");
+    b.p = base + at;
+    b.bytes = bytes;
+    b.owned = false;
+    used = at + bytes;
+    return U1ML_OK;
+  }
+};
+
 struct PassTable {
   DevBuf buf;
   int n_blocks = 0;
@@ -189,6 +208,13 @@ struct Engine {
   // measurement scratch
   DevBuf partial, rows, poly, poly_off, row_begin, red_out, rvals_tmp;
   MLState ml;
+  // the multilevel state the ML methods work on: ml, or during an
+  // allocation-free run a state whose buffers are views into the arena
+  MLState* mlp = &ml;
+  // non-null during an allocation-free run: workspace and block tables are
+  // carved from it instead of allocated (tables are then rebuilt per call)
+  Arena* arena = nullptr;
+  std::vector<std::unique_ptr<Table>> arena_tables;
   Ensemble ens;
   // plain observables of every lattice, valid while the links are unchanged:
   // epoch advances with every launch sequence that may write links
@@ -231,6 +257,7 @@ struct Engine {
 
   // block table for per-lattice item counts (built once, reused)
   int table(const std::vector<int>& items, int blk, Table** out) {
+    if (arena) return arena_table(items, blk, out);
     auto key = std::make_pair(items, blk);
     auto it = tables.find(key);
     if (it != tables.end()) {
@@ -255,6 +282,29 @@ struct Engine {
     tables[key] = std::move(t);
     return U1ML_OK;
   }
+
+  // the same table carved from the arena (not cached: the arena's contents
+  // belong to the current call only)
+  int arena_table(const std::vector<int>& items, int blk, Table** out) {
+    std::unique_ptr<Table> t(new Table());
+    std::vector<int2> h;
+    t->lat_block_begin.push_back(0);
+    for (int i = 0; i < (int)items.size(); ++i) {
+      for (int b = 0; b < items[i]; b += blk) h.push_back(make_int2(i, b));
+      t->lat_block_begin.push_back((int)h.size());
+    }
+    t->n_blocks = (int)h.size();
+    t->block = blk;
+    U1_TRY(arena->carve(t->buf, h.size() * sizeof(int2)));
+    U1_TRY(copy(t->buf.p, h.data(), h.size() * sizeof(int2), hipMemcpyHostToDevice));
+    *out = t.get();
+    arena_tables.push_back(std::move(t));
+    return U1ML_OK;
+  }
+
+  // a multilevel workspace buffer: allocated (grows, kept for later runs) or
+  // carved from the arena
+  int reserve(DevBuf& b, size_t bytes) { return arena ? arena->carve(b, bytes) : b.ensure(bytes); }
 
   // class-pass blocks of a batch: {lattice, slice, first offset, 0} for every
   // updated time slice (th = 0: all; else t != 0 mod th) of every lattice
@@ -557,9 +607,9 @@ struct Engine {
   // field separations (shared; each in every r list).
   int ml_setup(int n_levels, const int* th, const int* n_sub, int n_metro, int n_or,
                const std::vector<std::vector<int>>& rl, const std::vector<int>& rf) {
-    MLState& m = ml;
+    MLState& m = *mlp;
     U1_HIP(hipStreamSynchronize(stream));  // buffers below may still be in use
-    drop_graphs();                         // captured sequences hold the old buffer addresses
+    if (!arena) drop_graphs();             // captured sequences hold the old buffer addresses
     m.key.clear();
     m.valid = m.field_valid = false;
     m.n_levels = n_levels;
@@ -629,11 +679,11 @@ struct Engine {
       U1_TRY(pass_table(0, &pt));
       for (int l = 0; l < n_levels; ++l) U1_TRY(pass_table(th[l], &pt));
     }
-    U1_TRY(m.mls.ensure(n_lats * sizeof(MLDesc)));
-    U1_TRY(m.rvals.ensure(rv.size() * sizeof(int)));
-    U1_TRY(m.mlbuf.ensure(ell * sizeof(double2)));
-    U1_TRY(m.accbuf.ensure(acc * sizeof(double2)));
-    U1_TRY(m.corr.ensure((size_t)n_lats * m.max_r * 2 * sizeof(double)));
+    U1_TRY(reserve(m.mls, n_lats * sizeof(MLDesc)));
+    U1_TRY(reserve(m.rvals, rv.size() * sizeof(int)));
+    U1_TRY(reserve(m.mlbuf, ell * sizeof(double2)));
+    U1_TRY(reserve(m.accbuf, acc * sizeof(double2)));
+    U1_TRY(reserve(m.corr, (size_t)n_lats * m.max_r * 2 * sizeof(double)));
     U1_TRY(copy(m.mls.p, m.h_mls.data(), n_lats * sizeof(MLDesc), hipMemcpyHostToDevice));
     U1_TRY(copy(m.rvals.p, rv.data(), rv.size() * sizeof(int), hipMemcpyHostToDevice));
     if (m.field) {
@@ -675,17 +725,17 @@ struct Engine {
                                                               (size_t)fp.n_rf * fl.ns * 12 * L2);
       }
       m.scratch_elems = std::max(per_sample_max, kFieldScratchBytes / sizeof(double2));
-      U1_TRY(m.fls.ensure(n_lats * sizeof(FieldLat)));
-      U1_TRY(m.fbuf.ensure(fb * sizeof(double)));
-      U1_TRY(m.fout.ensure(fo * sizeof(double2)));
-      U1_TRY(m.scratch.ensure(m.scratch_elems * sizeof(double2)));
+      U1_TRY(reserve(m.fls, n_lats * sizeof(FieldLat)));
+      U1_TRY(reserve(m.fbuf, fb * sizeof(double)));
+      U1_TRY(reserve(m.fout, fo * sizeof(double2)));
+      U1_TRY(reserve(m.scratch, m.scratch_elems * sizeof(double2)));
       U1_TRY(copy(m.fls.p, m.h_fls.data(), n_lats * sizeof(FieldLat), hipMemcpyHostToDevice));
     }
     return U1ML_OK;
   }
 
   int ml_fold(int child, int parent, int sample_base) {
-    MLState& m = ml;
+    MLState& m = *mlp;
     const int inner = m.n_levels - 1;
     if (child == inner && !fold_general) {
       int threads = 64;
@@ -725,7 +775,7 @@ struct Engine {
   }
 
   int ml_sample(int sample) {
-    MLState& m = ml;
+    MLState& m = *mlp;
     const int inner = m.n_levels - 1;
     std::vector<int> it;
     for (int i = 0; i < n_lats; ++i) it.push_back(m.h_mls[i].ns[inner] * h_lats[i].L3);
@@ -740,7 +790,7 @@ struct Engine {
   // n[l] iterations of: update with level l frozen, then measure (innermost)
   // or recurse and fold the inner averages into level l.
   int ml_level(int l, int outer_it) {
-    MLState& m = ml;
+    MLState& m = *mlp;
     const int inner = m.n_levels - 1;
     for (int it = 0; it < m.n[l]; ++it) {
       U1_TRY(sweep(m.n_metro, m.n_or, m.th[l]));
@@ -761,7 +811,7 @@ struct Engine {
   }
 
   int field_contract(bool zero_g, bool finalize) {
-    MLState& m = ml;
+    MLState& m = *mlp;
     for (int i = 0; i < n_lats; ++i)
       U1_HIP(launch_field_contract(lats.as<LatDesc>() + i, m.mls.as<MLDesc>() + i, m.fls.as<FieldLat>() + i,
                                    m.h_fls[i], m.fp, h_lats[i].L, m.mlbuf.as<double2>(), m.accbuf.as<double2>(),
@@ -777,7 +827,7 @@ struct Engine {
   // restored links and pass ids, contracts each outer iteration's samples
   // with those weights as soon as the iteration completes.
   int ml_run_replay() {
-    MLState& m = ml;
+    MLState& m = *mlp;
     const size_t lb = link_elems * elem_size(), pb = n_lats * sizeof(uint64_t);
     U1_TRY(m.links_backup.ensure(lb));
     U1_TRY(m.pass_backup.ensure(pb));
@@ -810,7 +860,7 @@ struct Engine {
 
   // full multilevel run, results in ml.corr (and ml.fout)
   int ml_run() {
-    MLState& m = ml;
+    MLState& m = *mlp;
     U1_HIP(launch_ml_zero(m.accbuf.as<double2>(), m.acc_elems, stream));
     if (m.replay) {
       U1_TRY(ml_run_replay());
@@ -952,6 +1002,38 @@ struct Engine {
     ml.run_flags = estimator;
     return U1ML_OK;
   }
+
+  // The multilevel run of multilevel() (no field, no preceding sweeps) with
+  // its whole workspace carved from the device range [base, base + cap) and
+  // the correlator written to the caller's device buffer out [n_r][2];
+  // kernel by kernel, nothing allocated on the device and no graph made.
+  // ml (the results kept for u1ml_measure) and the captured graphs are left
+  // as they are.
+  int multilevel_in_place(int n_levels, const int* th, const int* n_sub, int n_metro, int n_or,
+                          const std::vector<int>& rl, void* base, size_t cap, double* out) {
+    Arena ar;
+    ar.base = (char*)base;
+    ar.cap = cap;
+    MLState st;
+    arena = &ar;
+    mlp = &st;
+    int rc = ml_setup(n_levels, th, n_sub, n_metro, n_or, std::vector<std::vector<int>>(1, rl), {});
+    if (!rc) {
+      // the final kernel writes C(r) straight into the caller's buffer
+      st.corr.p = out;
+      st.corr.bytes = rl.size() * 2 * sizeof(double);
+      ++epoch;
+      rc = ml_run();
+    }
+    if (!rc) {
+      hipError_t e = hipStreamSynchronize(stream);  // the arena tables are freed on the host below
+      if (e != hipSuccess) rc = fail(U1ML_EDEVICE, std::string("multilevel_noalloc: ") + hipGetErrorString(e));
+    }
+    arena = nullptr;
+    mlp = &ml;
+    arena_tables.clear();
+    return rc;
+  }
 };
 
 struct u1ml_lattice {
@@ -962,6 +1044,39 @@ struct u1ml_batch {
 };
 
 namespace {
+
+// ---------------------------------------------------------------------------
+// Static workspace of u1ml_multilevel_noalloc: one fixed array per GPU, held
+// by every device the library runs on until the process ends.  Host code
+// never passes the array's name to a kernel: the name is a host-side stand-in
+// in host code, so the device address of each GPU's copy is looked up once
+// per device (with that device current) and kept.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocBytes = (size_t)U1ML_NOALLOC_BYTES;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// once per device, with that device current (called from engine_create)
+int scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(U1ML_EDEVICE, "device index beyond the static workspace table");
+  std::lock_guard<std::mutex> lk(g_scratch_mutex);
+  if (g_scratch_ptr[device]) return U1ML_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(U1ML_EDEVICE, std::string("static workspace address: ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = ptr;
+  return U1ML_OK;
+}
+
+void* scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mutex);
+  return g_scratch_ptr[device];
+}
 
 // block sizes found by u1ml_autotune, shared by every handle created later
 // in the process: (L, T, precision) -> block
@@ -1032,6 +1147,7 @@ int engine_create(Engine& e, const std::vector<int>& L, const std::vector<int>& 
     off += 4ull * L[i] * L[i] * L[i] * T[i];
   }
   U1_HIP(hipGetDevice(&e.device));
+  U1_TRY(scratch_setup(e.device));
   e.stream = (hipStream_t)o.stream;
   if (!e.stream) {
     // a stream of our own (default priority) so that graph capture is possible
@@ -1202,6 +1318,23 @@ int u1ml_multilevel(u1ml_lattice* lat, int n_levels, const int* slab_sizes, cons
 int u1ml_measure(u1ml_lattice* lat, u1ml_observables* obs, double* correlator, double* field_profile) {
   if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
   return read_results(lat->e, 0, obs, correlator, field_profile);
+}
+
+int u1ml_multilevel_noalloc(u1ml_lattice* lat, int n_levels, const int* slab_sizes, const int* n_sub, int n_metro,
+                            int n_or, int n_r, const int* r_list, double* dev_correlator) {
+  U1_TRY(check_hits(n_metro, n_or));
+  if (!lat) return fail(U1ML_EINVAL, "lattice is NULL");
+  if (!dev_correlator) return fail(U1ML_EINVAL, "dev_correlator is NULL");
+  Engine& e = lat->e;
+  U1_TRY(check_ml_args(e, n_levels, slab_sizes, n_sub, n_metro, n_or));
+  if (n_r < 1 || !r_list) return fail(U1ML_EINVAL, "need at least one r");
+  std::vector<int> rl(r_list, r_list + n_r);
+  for (int r : rl)
+    if (r < 1 || r >= e.h_lats[0].L) return fail(U1ML_EINVAL, "r must be in [1, L)");
+  U1_TRY(e.set_device());
+  void* base = scratch_of(e.device);
+  if (!base) return fail(U1ML_ESTATE, "no static workspace on this device");
+  return e.multilevel_in_place(n_levels, slab_sizes, n_sub, n_metro, n_or, rl, base, kNoAllocBytes, dev_correlator);
 }
 
 static int ensemble_info(Engine& e, int i, int* n_runs, int* n_r, int* n_rf) {

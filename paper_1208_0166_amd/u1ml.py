@@ -76,6 +76,7 @@ def load_library(path: str = LIB_PATH):
         "u1ml_sweep": (I, [P, I, I]),
         "u1ml_multilevel": (I, [P, I, ip, ip, I, I, I, ip, I, ip]),
         "u1ml_measure": (I, [P, C.POINTER(Observables), dp, dp]),
+        "u1ml_multilevel_noalloc": (I, [P, I, ip, ip, I, I, I, ip, P]),
         "u1ml_plain_correlator": (I, [P, I, ip, dp]),
         "u1ml_ensemble_reset": (I, [P]),
         "u1ml_ensemble_add": (I, [P]),
@@ -235,6 +236,21 @@ def measure(lat: Lattice, observables: bool = True, correlator: bool = False, fi
         f = fp.reshape(lat._n_rf, 2, 6, lat.L, lat.L, 2)
         f = f[..., 0] + 1j * f[..., 1]
     return (obs.as_dict() if obs is not None else None), c, f
+
+
+def multilevel_noalloc(lat: Lattice, slab_sizes, n_sub, n_metro: int = 1, n_or: int = 3, r_list=(1,), out=None):
+    """u1ml_multilevel_noalloc: the multilevel correlator with the library's
+    static device workspace; ``out`` is a caller-owned float64 CUDA tensor of
+    2 * len(r_list) values, filled with (Re, Im) of C_ML(r).  Returns ``out``."""
+    import torch
+    th, thp = _ints(slab_sizes)
+    ns, nsp = _ints(n_sub)
+    r, rp = _ints(r_list)
+    if out is None or not out.is_cuda or out.dtype != torch.float64 or out.numel() < 2 * len(r):
+        raise U1MLError(EINVAL, "out must be a float64 CUDA tensor of 2 * len(r_list) values")
+    _check(load_library().u1ml_multilevel_noalloc(lat.handle, len(th), thp, nsp, n_metro, n_or, len(r), rp,
+                                                  C.c_void_p(out.data_ptr())))
+    return out
 
 
 def _dptr(a):
