@@ -48,17 +48,29 @@ def test_64_uneven_instances_fp32_cycles():
 
 
 def test_64_uneven_instances_fp64_match_oracle(oracle_mod):
+    # the FP64 twin of the uneven batch: the same 64 sizes and couplings in one
+    # batch, hot start, one sweep, then two measurement cycles (one sweep plus
+    # the single-level multilevel with slabs of 2 and 10 updates, r = 1..L/2),
+    # the second replayed from the captured graph.  One lattice of every
+    # (L, beta) pair present is followed by the oracle through the same
+    # sequence: links bit-identical and C_ML(r) to 1e-12.
     Ls, betas, seeds = uneven_instances()
-    say("[gpu] 64 instances FP64 vs oracle (sampled)")
+    say("[gpu] 64 instances FP64 vs oracle, every (L, beta) present")
     b = u1ml.batch_create(Ls, Ls, betas, seeds, start=u1ml.HOT, precision=u1ml.FP64)
     u1ml.batch_sweep(b, 1, 3)
     u1ml.batch_cycle(b, 1, 1, 3, 2, 10, use_graph=True)
-    picks = [Ls.index(8), Ls.index(16), Ls.index(24)]
-    for i in picks:
-        o = oracle_mod.OracleLattice(Ls[i], Ls[i], betas[i], seeds[i], hot=True)
+    u1ml.batch_cycle(b, 1, 1, 3, 2, 10, use_graph=True)
+    picks = {}
+    for i, (L, be) in enumerate(zip(Ls, betas)):
+        picks.setdefault((L, be), i)
+    assert sorted({L for L, _ in picks}) == [8, 12, 16, 20, 24]
+    for (L, be), i in sorted(picks.items()):
+        say(f"  lattice {i}: L={L} beta={be}")
+        o = oracle_mod.OracleLattice(L, L, be, seeds[i], hot=True)
         o.sweep(1, 3)
-        o.sweep(1, 3)
-        c_o, _, _ = o.multilevel([2], [10], 1, 3, list(range(1, Ls[i] // 2 + 1)))
+        for _ in range(2):
+            o.sweep(1, 3)
+            c_o, _, _ = o.multilevel([2], [10], 1, 3, list(range(1, L // 2 + 1)))
         obs, c_g, _ = u1ml.batch_measure(b, i)
         np.testing.assert_array_equal(u1ml.batch_get_links(b, i), o.get_links())
         np.testing.assert_allclose(c_g, c_o, rtol=1e-12, atol=1e-15)
