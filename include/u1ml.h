@@ -341,6 +341,44 @@ void u1ml_batch_destroy(u1ml_batch *b);
  * unchanged (they are saved and restored).  Synchronises. */
 int u1ml_autotune(u1ml_lattice *lat, int *best_block);
 
+/* Launch shapes of the kernels of a lattice or batch.  Every value gives the
+ * same results bit for bit (each output has one owner thread and a fixed
+ * summation order); they only change the speed.  u1ml_*_set_tuning checks
+ * the ranges (EINVAL), waits for queued work and drops captured graphs. */
+typedef struct u1ml_tuning {
+    int pass_block;         /* threads per block of the class-pass kernels: 64..1024, multiple of 64 */
+    int pass_xcd_map;       /* 1: a class pass's blocks run in one contiguous range per XCD, so that
+                               neighbouring sites share an L2; 0: the hardware's round-robin order */
+    int sample_block;       /* threads per block of the per-sample kernel (time lines, field
+                               operator sums): 64..1024, multiple of 64 */
+    int fold_threads;       /* threads per block of the row fold of the inner averages: 64..256,
+                               multiple of 64; 0 = chosen from L and the r list */
+    int field_w_planes;     /* x planes per block of the field W transform: 1..64, clamped to what
+                               one block's LDS holds; 0 = chosen for occupancy */
+    int field_o_planes;     /* x-plane pairs per block of the field O transform; as above */
+    int field_zcon_threads; /* threads per block of the field contraction: 64..256, multiple of
+                               64; 0 = chosen for the fewest idle lanes */
+} u1ml_tuning;
+int u1ml_get_tuning(u1ml_lattice *lat, u1ml_tuning *t);
+int u1ml_set_tuning(u1ml_lattice *lat, const u1ml_tuning *t);
+int u1ml_batch_get_tuning(u1ml_batch *b, u1ml_tuning *t);
+int u1ml_batch_set_tuning(u1ml_batch *b, const u1ml_tuning *t);
+
+/* Autotuner of a batch: times the candidate launch shapes on this batch and
+ * keeps the fastest of each kernel family (one family at a time, the others
+ * at their current values): the class passes' block size (64..1024) and XCD
+ * block order over three compound sweeps per candidate (best of two); then,
+ * if n_levels > 0, with multilevel runs of the given shape (u1ml_multilevel
+ * arguments with n_metro = 1, n_or = 3; pass a small n_sub), the per-sample
+ * kernel's block size, the row fold's threads and, with field separations
+ * on the fast contraction path, the planes per block of both field
+ * transforms and the contraction's threads, each timed over its own launches
+ * only.  The links and pass ids are restored; the last multilevel result is
+ * discarded (ESTATE until the next run).  *best (may be NULL) receives the
+ * chosen shapes.  Synchronises. */
+int u1ml_batch_autotune(u1ml_batch *b, int n_levels, const int *slab_sizes, const int *n_sub, int n_r,
+                        const int *r_list, int n_rf, const int *rf_list, u1ml_tuning *best);
+
 /* Run n_sweeps compound sweeps (n_metro, n_or) like u1ml_sweep, recording a
  * HIP event pair on the lattice's stream around every class-pass kernel, and
  * return the average kernel duration in microseconds: avg_us[0] over the

@@ -186,7 +186,11 @@ struct Engine {
   bool own_stream = false;
   bool use_graphs = true;
   int prec = U1ML_FP64;
-  int block = 256;
+  int block = 256;         // class-pass threads per block
+  int xcd_map = 1;         // class-pass blocks in XCD-contiguous order
+  int sample_block = 256;  // threads per block of the per-sample kernel
+  int fold_threads = 0;    // threads per block of the row fold; 0 = by L and n_r
+  FieldTuning ftune;       // launch shapes of the fast field path
   int n_lats = 0;
   std::vector<LatDesc> h_lats;
   DevBuf lats;
@@ -225,6 +229,11 @@ struct Engine {
   bool capturing = false;
   // optional per-kernel timing (u1ml_profile_sweeps)
   std::vector<std::pair<hipEvent_t, hipEvent_t>>* prof[2] = {nullptr, nullptr};
+  // optional timing of one measurement kernel family (autotuner): events
+  // around every launch of family fam_id
+  enum Family { kFamSample = 0, kFamFold = 1, kFamField = 2 };
+  std::vector<std::pair<hipEvent_t, hipEvent_t>>* fam_prof = nullptr;
+  int fam_id = -1;
 
   ~Engine() {
     if (stream) (void)hipStreamSynchronize(stream);
@@ -348,22 +357,24 @@ struct Engine {
     hipError_t e;
     if (n_lats == 1) {
       if (prec == U1ML_FP64)
-        e = launch_class_pass_f64(kind, links.as<double>(), h_lats[0], block, mu, parity, th_frozen, n_hits,
+        e = launch_class_pass_f64(kind, links.as<double>(), h_lats[0], block, xcd_map, mu, parity, th_frozen,
+                                  n_hits,
                                   pass_ids.as<uint64_t>(), logp, bump_n, stream);
       else
-        e = launch_class_pass_f32(kind, links.as<float>(), h_lats[0], block, mu, parity, th_frozen, n_hits,
+        e = launch_class_pass_f32(kind, links.as<float>(), h_lats[0], block, xcd_map, mu, parity, th_frozen,
+                                  n_hits,
                                   pass_ids.as<uint64_t>(), logp, bump_n, stream);
     } else {
       PassTable* t;
       U1_TRY(pass_table(mu > 0 && th_frozen > 0 ? th_frozen : 0, &t));
       if (prec == U1ML_FP64)
         e = launch_class_pass_batch_f64(kind, links.as<double>(), lats.as<LatDesc>(), t->buf.as<int4>(),
-                                        t->n_blocks, block, mu, parity, n_hits, pass_ids.as<uint64_t>(), bump_n,
-                                        stream);
+                                        t->n_blocks, block, xcd_map, mu, parity, n_hits, pass_ids.as<uint64_t>(),
+                                        bump_n, stream);
       else
         e = launch_class_pass_batch_f32(kind, links.as<float>(), lats.as<LatDesc>(), t->buf.as<int4>(),
-                                        t->n_blocks, block, mu, parity, n_hits, pass_ids.as<uint64_t>(), bump_n,
-                                        stream);
+                                        t->n_blocks, block, xcd_map, mu, parity, n_hits, pass_ids.as<uint64_t>(),
+                                        bump_n, stream);
     }
     U1_HIP(e);
     return U1ML_OK;
@@ -416,7 +427,7 @@ struct Engine {
   // of the same launch sequence for later calls.
   template <class Fn>
   int run_captured(const std::vector<long long>& key, Fn fn, bool capture = true) {
-    const bool can = capture && use_graphs && !debug && !prof[0] && !prof[1];
+    const bool can = capture && use_graphs && !debug && !prof[0] && !prof[1] && !fam_prof;
     ++epoch;
     if (can) {
       auto it = graphs.find(key);
@@ -743,7 +754,7 @@ struct Engine {
       for (int i = 0; i < n_lats; ++i) {
         const int nsp = parent == m.n_levels ? 1 : m.h_mls[i].ns[parent];
         const int children = m.h_mls[i].ns[child] / nsp;
-        threads = std::max(threads, ml_fold_rows_threads(h_lats[i].L, m.h_mls[i].n_r));
+        threads = std::max(threads, fold_threads > 0 ? fold_threads : ml_fold_rows_threads(h_lats[i].L, m.h_mls[i].n_r));
         max_lds = std::max(max_lds, (size_t)(m.h_mls[i].multihit ? 2 : 1) * children * m.n[child] * h_lats[i].L *
                                         sizeof(double2));
       }
@@ -755,10 +766,11 @@ struct Engine {
         }
         Table* t;
         U1_TRY(table(rows, 1, &t));
+        U1_TRY(fam_begin(kFamFold));
         U1_HIP(launch_ml_fold_rows(lats.as<LatDesc>(), m.mls.as<MLDesc>(), bt(t), threads, max_lds, child, parent,
                                    m.n_levels, m.n[child], sample_base, m.rvals.as<int>(), m.mlbuf.as<double2>(),
                                    m.accbuf.as<double2>(), stream));
-        return U1ML_OK;
+        return fam_end(kFamFold);
       }
     }
     std::vector<int> it;
@@ -780,11 +792,12 @@ struct Engine {
     std::vector<int> it;
     for (int i = 0; i < n_lats; ++i) it.push_back(m.h_mls[i].ns[inner] * h_lats[i].L3);
     Table* t;
-    U1_TRY(table(it, 256, &t));
+    U1_TRY(table(it, sample_block, &t));
+    U1_TRY(fam_begin(kFamSample));
     U1_HIP(launch_ml_sample(prec, links.p, lats.as<LatDesc>(), m.mls.as<MLDesc>(), m.fls.as<FieldLat>(), bt(t),
                             m.th[inner], sample, m.field && m.store_field, (estimator & U1ML_FIELD_SQUARED) != 0,
                             m.mlbuf.as<double2>(), m.fbuf.as<double>(), stream));
-    return U1ML_OK;
+    return fam_end(kFamSample);
   }
 
   // n[l] iterations of: update with level l frozen, then measure (innermost)
@@ -812,12 +825,33 @@ struct Engine {
 
   int field_contract(bool zero_g, bool finalize) {
     MLState& m = *mlp;
+    U1_TRY(fam_begin(kFamField));
     for (int i = 0; i < n_lats; ++i)
       U1_HIP(launch_field_contract(lats.as<LatDesc>() + i, m.mls.as<MLDesc>() + i, m.fls.as<FieldLat>() + i,
                                    m.h_fls[i], m.fp, h_lats[i].L, m.mlbuf.as<double2>(), m.accbuf.as<double2>(),
                                    m.fbuf.as<double>(), m.scratch.as<double2>(), m.scratch_elems,
                                    m.fout.as<double2>() + m.fout_off[i], field_general, prec == U1ML_FP32, zero_g,
-                                   finalize, stream));
+                                   finalize, ftune, stream));
+    return fam_end(kFamField);
+  }
+
+  // event pair around the launches of one kernel family (autotuner timing)
+  int fam_begin(int fam) {
+    if (!fam_prof || fam != fam_id) return U1ML_OK;
+    hipEvent_t a, z;
+    U1_HIP(hipEventCreate(&a));
+    hipError_t e = hipEventCreate(&z);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(a);
+      U1_HIP(e);
+    }
+    fam_prof->push_back(std::make_pair(a, z));
+    U1_HIP(hipEventRecord(a, stream));
+    return U1ML_OK;
+  }
+  int fam_end(int fam) {
+    if (!fam_prof || fam != fam_id) return U1ML_OK;
+    U1_HIP(hipEventRecord(fam_prof->back().second, stream));
     return U1ML_OK;
   }
 
@@ -1683,6 +1717,167 @@ int u1ml_autotune(u1ml_lattice* lat, int* best_block) {
   return U1ML_OK;
 }
 
+// --- launch-shape tuning ---
+static void get_tuning(const Engine& e, u1ml_tuning* t) {
+  t->pass_block = e.block;
+  t->pass_xcd_map = e.xcd_map;
+  t->sample_block = e.sample_block;
+  t->fold_threads = e.fold_threads;
+  t->field_w_planes = e.ftune.w_planes;
+  t->field_o_planes = e.ftune.o_planes;
+  t->field_zcon_threads = e.ftune.zcon_threads;
+}
+
+static int set_tuning(Engine& e, const u1ml_tuning& t) {
+  auto mult64 = [](int v, int lo, int hi) { return v >= lo && v <= hi && v % 64 == 0; };
+  if (!mult64(t.pass_block, 64, 1024) || (t.pass_xcd_map != 0 && t.pass_xcd_map != 1) ||
+      !mult64(t.sample_block, 64, 1024) || (t.fold_threads != 0 && !mult64(t.fold_threads, 64, 256)) ||
+      t.field_w_planes < 0 || t.field_w_planes > 64 || t.field_o_planes < 0 || t.field_o_planes > 64 ||
+      (t.field_zcon_threads != 0 && !mult64(t.field_zcon_threads, 64, 256)))
+    return fail(U1ML_EINVAL, "tuning values out of range");
+  U1_TRY(e.set_device());
+  U1_HIP(hipStreamSynchronize(e.stream));
+  e.block = t.pass_block;
+  e.xcd_map = t.pass_xcd_map;
+  e.sample_block = t.sample_block;
+  e.fold_threads = t.fold_threads;
+  e.ftune.w_planes = t.field_w_planes;
+  e.ftune.o_planes = t.field_o_planes;
+  e.ftune.zcon_threads = t.field_zcon_threads;
+  e.drop_graphs();  // captured launches carry the old shapes
+  return U1ML_OK;
+}
+
+// average of the recorded event intervals (ms); destroys the events
+static int events_avg(Engine& e, std::vector<std::pair<hipEvent_t, hipEvent_t>>& ev, double* avg_ms) {
+  hipError_t se = hipStreamSynchronize(e.stream);
+  double tot = 0.0;
+  for (auto& pr : ev) {
+    float ms = 0.f;
+    if (se == hipSuccess) (void)hipEventElapsedTime(&ms, pr.first, pr.second);
+    tot += ms;
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  *avg_ms = ev.empty() ? 0.0 : tot / (double)ev.size();
+  ev.clear();
+  U1_HIP(se);
+  return U1ML_OK;
+}
+
+// Coordinate search over the launch shapes, one kernel family at a time (the
+// others at their current best): class-pass block size and XCD order timed
+// over compound sweeps; then with a multilevel run of the given shape the
+// per-sample kernel's block size, the row fold's threads, and with field
+// separations the planes per block of both field transforms and the
+// contraction's threads, each timed over its own launches only.  Every
+// choice gives the same bits, and the links and pass ids are restored.
+static int autotune_engine(Engine& e, int n_levels, const int* th, const int* n_sub,
+                           const std::vector<std::vector<int>>& rl, const std::vector<int>& rf, u1ml_tuning* best) {
+  if (e.debug) return fail(U1ML_ESTATE, "autotune with the debug log enabled");
+  U1_TRY(e.set_device());
+  DevBuf save, save_ids;
+  const size_t lb = e.link_elems * e.elem_size(), ib = e.n_lats * sizeof(uint64_t);
+  U1_TRY(save.ensure(lb));
+  U1_TRY(save_ids.ensure(ib));
+  U1_HIP(hipMemcpyAsync(save.p, e.links.p, lb, hipMemcpyDeviceToDevice, e.stream));
+  U1_HIP(hipMemcpyAsync(save_ids.p, e.pass_ids.p, ib, hipMemcpyDeviceToDevice, e.stream));
+  const std::vector<uint64_t> ids = e.h_pass_ids;
+  e.drop_graphs();
+  int rc = U1ML_OK;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  // 1. class passes: block size x block order, the best of two timings of 3 compound sweeps
+  {
+    double best_ms = 1e300;
+    int bb = e.block, bx = e.xcd_map;
+    for (int xcd = 1; xcd >= 0 && !rc; --xcd)
+      for (int blk = 64; blk <= 1024 && !rc; blk *= 2) {
+        e.block = blk;
+        e.xcd_map = xcd;
+        if ((rc = e.sweep(1, 1, 0))) break;  // warm-up (block tables of this size)
+        double t_min = 1e300;
+        for (int rep = 0; rep < 2 && !rc; ++rep) {
+          e.prof[0] = e.prof[1] = &ev;
+          for (int k = 0; k < 3 && !rc; ++k) rc = e.sweep(1, 3, 0);
+          e.prof[0] = e.prof[1] = nullptr;
+          double ms = 0;
+          if (!rc) rc = events_avg(e, ev, &ms);
+          t_min = std::min(t_min, ms);
+        }
+        if (!rc && t_min < best_ms) {
+          best_ms = t_min;
+          bb = blk;
+          bx = xcd;
+        }
+      }
+    e.block = bb;
+    e.xcd_map = bx;
+  }
+  // 2. measurement kernels, each timed over a multilevel run of the given shape
+  auto time_family = [&](int fam, double* ms) -> int {
+    e.fam_prof = &ev;
+    e.fam_id = fam;
+    int r = e.multilevel(n_levels, th, n_sub, 1, 3, rl, rf, 0);
+    e.fam_prof = nullptr;
+    e.fam_id = -1;
+    if (r) {
+      for (auto& pr : ev) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+      }
+      ev.clear();
+      return r;
+    }
+    return events_avg(e, ev, ms);
+  };
+  auto search = [&](int fam, int* knob, const std::vector<int>& cand) -> int {
+    double best_ms = 1e300;
+    int keep = *knob;
+    for (int v : cand) {
+      *knob = v;
+      double ms = 0.0;
+      U1_TRY(time_family(fam, &ms));
+      if (ms < best_ms) {
+        best_ms = ms;
+        keep = v;
+      }
+    }
+    *knob = keep;
+    return U1ML_OK;
+  };
+  if (!rc && n_levels > 0) {
+    // the first run sets up the workspace and loads the kernels
+    double ms = 0;
+    rc = time_family(-1, &ms);
+    if (!rc) rc = search(Engine::kFamSample, &e.sample_block, {64, 128, 256, 512, 1024});
+    if (!rc) rc = search(Engine::kFamFold, &e.fold_threads, {64, 128, 192, 256});
+    int max_w = 64, max_o = 64;
+    for (auto& d : e.h_lats) {
+      max_w = std::min(max_w, field_max_planes(d.L, false));
+      max_o = std::min(max_o, field_max_planes(d.L, true));
+    }
+    if (!rc && !rf.empty() && !e.field_general && max_w > 0 && max_o > 0) {
+      std::vector<int> cw, co;
+      for (int v = 1; v <= max_w; ++v) cw.push_back(v);
+      for (int v = 1; v <= max_o; ++v) co.push_back(v);
+      rc = search(Engine::kFamField, &e.ftune.w_planes, cw);
+      if (!rc) rc = search(Engine::kFamField, &e.ftune.o_planes, co);
+      if (!rc) rc = search(Engine::kFamField, &e.ftune.zcon_threads, {64, 128, 192, 256});
+    }
+  }
+  // restore the chain; the tuning runs' results are not kept
+  e.drop_graphs();
+  U1_HIP(hipMemcpyAsync(e.links.p, save.p, lb, hipMemcpyDeviceToDevice, e.stream));
+  U1_HIP(hipMemcpyAsync(e.pass_ids.p, save_ids.p, ib, hipMemcpyDeviceToDevice, e.stream));
+  U1_HIP(hipStreamSynchronize(e.stream));
+  e.h_pass_ids = ids;
+  ++e.epoch;
+  e.ml.valid = e.ml.field_valid = false;
+  if (rc) return rc;
+  if (best) get_tuning(e, best);
+  return U1ML_OK;
+}
+
 static int profile_sweeps(Engine& e, int n_sweeps, int n_metro, int n_or, double* avg_us) {
   if (!avg_us || n_sweeps < 0) return fail(U1ML_EINVAL, "profile arguments");
   U1_TRY(check_hits(n_metro, n_or));
@@ -1708,6 +1903,55 @@ static int profile_sweeps(Engine& e, int n_sweeps, int n_metro, int n_or, double
   if (rc) return rc;
   U1_HIP(se);
   return U1ML_OK;
+}
+
+int u1ml_get_tuning(u1ml_lattice* lat, u1ml_tuning* t) {
+  if (!lat || !t) return fail(U1ML_EINVAL, "get_tuning arguments");
+  get_tuning(lat->e, t);
+  return U1ML_OK;
+}
+
+int u1ml_set_tuning(u1ml_lattice* lat, const u1ml_tuning* t) {
+  if (!lat || !t) return fail(U1ML_EINVAL, "set_tuning arguments");
+  return set_tuning(lat->e, *t);
+}
+
+int u1ml_batch_get_tuning(u1ml_batch* b, u1ml_tuning* t) {
+  if (!b || !t) return fail(U1ML_EINVAL, "batch_get_tuning arguments");
+  get_tuning(b->e, t);
+  return U1ML_OK;
+}
+
+int u1ml_batch_set_tuning(u1ml_batch* b, const u1ml_tuning* t) {
+  if (!b || !t) return fail(U1ML_EINVAL, "batch_set_tuning arguments");
+  return set_tuning(b->e, *t);
+}
+
+int u1ml_batch_autotune(u1ml_batch* b, int n_levels, const int* slab_sizes, const int* n_sub, int n_r,
+                        const int* r_list, int n_rf, const int* rf_list, u1ml_tuning* best) {
+  if (!b) return fail(U1ML_EINVAL, "batch is NULL");
+  Engine& e = b->e;
+  std::vector<std::vector<int>> rl(e.n_lats);
+  std::vector<int> rf;
+  if (n_levels > 0) {
+    U1_TRY(check_ml_args(e, n_levels, slab_sizes, n_sub, 1, 3));
+    if (n_r < 1 || !r_list) return fail(U1ML_EINVAL, "need at least one r");
+    if (n_rf < 0 || n_rf > U1ML_MAX_FIELD_R || (n_rf > 0 && (!rf_list || n_levels > 2)))
+      return fail(U1ML_EINVAL, "field r list");
+    for (auto& d : e.h_lats)
+      for (int k = 0; k < n_r; ++k)
+        if (r_list[k] < 1 || r_list[k] >= d.L || (n_rf > 0 && d.L > kMaxFieldL))
+          return fail(U1ML_EINVAL, "r must be in [1, L) (field: L <= 62)");
+    for (int f = 0; f < n_rf; ++f) {
+      if (std::find(r_list, r_list + n_r, rf_list[f]) == r_list + n_r)
+        return fail(U1ML_EINVAL, "every field r must appear in r_list");
+      rf.push_back(rf_list[f]);
+    }
+    for (auto& v : rl) v.assign(r_list, r_list + n_r);
+  } else if (n_levels < 0) {
+    return fail(U1ML_EINVAL, "n_levels must be >= 0");
+  }
+  return autotune_engine(e, n_levels, slab_sizes, n_sub, rl, rf, best);
 }
 
 int u1ml_profile_sweeps(u1ml_lattice* lat, int n_sweeps, int n_metro, int n_or, double* avg_us) {

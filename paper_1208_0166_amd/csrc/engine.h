@@ -25,19 +25,20 @@ hipError_t launch_init_f32(float* links, const LatDesc* lats, BlockTable bt, int
 // bump_n > 0 (overrelaxation passes only, which do not read the pass ids):
 // the pass also adds 1 to pass_ids[0 .. bump_n), once all its blocks are done
 // reading nothing from them; used on the last pass of a compound sweep.
-hipError_t launch_class_pass_f64(int kind, double* links, const LatDesc& d, int block, int mu, int parity,
+// xcd_map != 0: blocks in XCD-contiguous order (xcd_block), else hardware order
+hipError_t launch_class_pass_f64(int kind, double* links, const LatDesc& d, int block, int xcd_map, int mu, int parity,
                                  int th_frozen, int n_hits, uint64_t* pass_ids, uint8_t* log, int bump_n,
                                  hipStream_t st);
-hipError_t launch_class_pass_f32(int kind, float* links, const LatDesc& d, int block, int mu, int parity,
+hipError_t launch_class_pass_f32(int kind, float* links, const LatDesc& d, int block, int xcd_map, int mu, int parity,
                                  int th_frozen, int n_hits, uint64_t* pass_ids, uint8_t* log, int bump_n,
                                  hipStream_t st);
 // one class pass of every lattice of a batch; blocks[b] = {lattice, time slice,
 // first offset within the slice, 0}, one block per (updated slice, chunk)
 hipError_t launch_class_pass_batch_f64(int kind, double* links, const LatDesc* lats, const int4* blocks,
-                                       int n_blocks, int block, int mu, int parity, int n_hits,
+                                       int n_blocks, int block, int xcd_map, int mu, int parity, int n_hits,
                                        uint64_t* pass_ids, int bump_n, hipStream_t st);
 hipError_t launch_class_pass_batch_f32(int kind, float* links, const LatDesc* lats, const int4* blocks,
-                                       int n_blocks, int block, int mu, int parity, int n_hits,
+                                       int n_blocks, int block, int xcd_map, int mu, int parity, int n_hits,
                                        uint64_t* pass_ids, int bump_n, hipStream_t st);
 hipError_t launch_bump_pass_ids(uint64_t* pass_ids, int n, hipStream_t st);
 // fill n bytes with v (graph-safe replacement of a memset)
@@ -129,6 +130,15 @@ hipError_t launch_ens_omean(const LatDesc* lats, const double* red, int width, i
                             hipStream_t st);
 hipError_t launch_ens_connected(const double2* fsum, const double2* csum, const double* osum, FieldParams fp, int L,
                                 double inv_n, double2* conn, hipStream_t st);
+// launch shapes of the fast field path (0 = the default of the kernel): x
+// planes per block of the W transform, plane pairs per block of the O
+// transform, threads per block of the contraction; every choice gives the
+// same bits
+struct FieldTuning {
+  int w_planes = 0;
+  int o_planes = 0;
+  int zcon_threads = 0;
+};
 // contraction of all stored samples of one lattice into the Fourier-space
 // accumulator (cleared first if zero_g) and, if finalize, into F
 // [n_rf][2][6][L][L] (complex); general = true takes the stored-transform path
@@ -137,6 +147,10 @@ hipError_t launch_ens_connected(const double2* fsum, const double2* csum, const 
 hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,
                                  FieldParams fp, int L, const double2* mlbuf, const double2* accbuf, double* fbuf,
                                  double2* scratch, size_t scratch_elems, double2* F, bool general, bool fp32_store,
-                                 bool zero_g, bool finalize, hipStream_t st);
+                                 bool zero_g, bool finalize, FieldTuning tune, hipStream_t st);
+// the largest x planes per block the W (pairs = false) or O (pairs = true)
+// transform accepts at lattice size L (LDS and block-size limits); 0 when L
+// has no fast path
+int field_max_planes(int L, bool pairs);
 
 }  // namespace u1ml

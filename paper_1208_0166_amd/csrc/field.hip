@@ -746,14 +746,23 @@ int zcon_threads(int n) {
   return best;
 }
 
+// the most planes per block a transform block can hold: LDS (kFxLds) and
+// 512 threads (a lane pair per row of every plane)
+int max_transform_planes(int L, int n_planes) {
+  const size_t pb = (size_t)L * (L + 1) * sizeof(double2);
+  return std::max(1, std::min<int>({n_planes, (int)(kFxLds / pb), 512 / (2 * L)}));
+}
+
 template <int L, typename S>
 hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, int ns, FieldParams fp,
                                 const double2* mlbuf, const double* fbuf, double2* scratch, size_t scratch_elems,
-                                double2* G, double2* F, bool finalize, hipStream_t st) {
+                                double2* G, double2* F, bool finalize, FieldTuning tune, hipStream_t st) {
   const uint64_t L3 = (uint64_t)L * L * L, L2 = (uint64_t)L * L;
   const size_t plane_bytes = (size_t)L * (L + 1) * sizeof(double2);  // LDS rows padded to L + 1
-  const int npb_w = transform_planes(L, L);
-  const int np_o = transform_planes(L, L / 2);  // pair planes per transform block
+  const int npb_w = tune.w_planes > 0 ? std::min(tune.w_planes, max_transform_planes(L, L)) : transform_planes(L, L);
+  // pair planes per transform block
+  const int np_o =
+      tune.o_planes > 0 ? std::min(tune.o_planes, max_transform_planes(L, L / 2)) : transform_planes(L, L / 2);
   const int n_ent = 2 * fp.n_rf * (int)L2;
   const int thr_w = (2 * npb_w * L + 63) / 64 * 64;  // lane pairs per row
   const int thr_o = (2 * np_o * L + 63) / 64 * 64;
@@ -761,7 +770,7 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
   const int ngroups_o = (L / 2 + np_o - 1) / np_o;
   const int sps = std::min(ns, kZcSlabs), nsg = (ns + sps - 1) / sps;
   const int n_zc = ((fp.n_rf + kZcF - 1) / kZcF) * 2 * (int)L2;  // contraction threads per (k, g)
-  const int thr_z = zcon_threads(n_zc);
+  const int thr_z = tune.zcon_threads > 0 ? std::min(256, (tune.zcon_threads + 63) / 64 * 64) : zcon_threads(n_zc);
   const int nblk_e = (n_zc + thr_z - 1) / thr_z;
   // scratch bytes per sample: What [n_rf][ns][L3] and Zhat [ns][6][L3 / 2]
   // (storage type S), part [nsg][6][n_ent] (double2)
@@ -792,7 +801,8 @@ hipError_t launch_fast_contract(const LatDesc* lat, const MLDesc* ml, const Fiel
 
 // the fast path for lattice size L: one of the instantiated lengths
 typedef hipError_t (*FastContract)(const LatDesc*, const MLDesc*, const FieldLat*, int, FieldParams, const double2*,
-                                   const double*, double2*, size_t, double2*, double2*, bool, hipStream_t);
+                                   const double*, double2*, size_t, double2*, double2*, bool, FieldTuning,
+                                   hipStream_t);
 FastContract fast_contract_for(int L, bool fp32_store) {
   if (L > kFxMaxL) return nullptr;
   switch (L) {
@@ -825,7 +835,7 @@ FastContract fast_contract_for(int L, bool fp32_store) {
 hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,
                                  FieldParams fp, int L, const double2* mlbuf, const double2* accbuf, double* fbuf,
                                  double2* scratch, size_t scratch_elems, double2* F, bool general, bool fp32_store,
-                                 bool zero_g, bool finalize, hipStream_t st) {
+                                 bool zero_g, bool finalize, FieldTuning tune, hipStream_t st) {
   const uint64_t L3 = (uint64_t)L * L * L, L2 = (uint64_t)L * L;
   const int ns = hfl.ns;
   const uint64_t nt = (uint64_t)fp.n_stored * ns * L3 * fp.n_rf;
@@ -837,7 +847,7 @@ hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const Fie
   const uint64_t ng = (uint64_t)fp.n_rf * 12 * L2;
   if (zero_g) hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(ng, 256)), dim3(256), 0, st, G, ng);
   if (FastContract fc = general ? nullptr : fast_contract_for(L, fp32_store)) {
-    return fc(lat, ml, fl, ns, fp, mlbuf, fbuf, scratch, scratch_elems, G, F, finalize, st);
+    return fc(lat, ml, fl, ns, fp, mlbuf, fbuf, scratch, scratch_elems, G, F, finalize, tune, st);
   }
   // general path: both transforms stored, contraction by pq tiles
   // scratch per chunk: What [nk][n_rf][ns][L3], Ohat [nk][6][ns][L3], part [nk][n_rf][ns][12][L2]
@@ -869,6 +879,11 @@ hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const Fie
   }
   if (finalize) hipLaunchKernelGGL(field_final_kernel, dim3(blocks_for(ng, 64)), dim3(64), 0, st, fp, L, G, F);
   return hipGetLastError();
+}
+
+int field_max_planes(int L, bool pairs) {
+  if (!fast_contract_for(L, false)) return 0;
+  return max_transform_planes(L, pairs ? L / 2 : L);
 }
 
 }  // namespace u1ml

@@ -12,20 +12,20 @@ hipError_t launch_init_f64(double* links, const LatDesc* lats, BlockTable bt, in
   return hipGetLastError();
 }
 
-hipError_t launch_class_pass_f64(int kind, double* links, const LatDesc& d, int block, int mu, int parity,
+hipError_t launch_class_pass_f64(int kind, double* links, const LatDesc& d, int block, int xcd_map, int mu, int parity,
                                  int th_frozen, int n_hits, uint64_t* pass_ids, uint8_t* log, int bump_n,
                                  hipStream_t st) {
   if (kind == kMetropolis)
-    return launch_pass_single<Det64, 0>(links, d, block, mu, parity, th_frozen, n_hits, pass_ids, log, 0, st);
-  return launch_pass_single<Det64, 1>(links, d, block, mu, parity, th_frozen, n_hits, pass_ids, log, bump_n, st);
+    return launch_pass_single<Det64, 0>(links, d, block, xcd_map, mu, parity, th_frozen, n_hits, pass_ids, log, 0, st);
+  return launch_pass_single<Det64, 1>(links, d, block, xcd_map, mu, parity, th_frozen, n_hits, pass_ids, log, bump_n, st);
 }
 
 hipError_t launch_class_pass_batch_f64(int kind, double* links, const LatDesc* lats, const int4* blocks,
-                                       int n_blocks, int block, int mu, int parity, int n_hits,
+                                       int n_blocks, int block, int xcd_map, int mu, int parity, int n_hits,
                                        uint64_t* pass_ids, int bump_n, hipStream_t st) {
   if (kind == kMetropolis)
-    return launch_pass_batch<Det64, 0>(links, lats, blocks, n_blocks, block, mu, parity, n_hits, pass_ids, 0, st);
-  return launch_pass_batch<Det64, 1>(links, lats, blocks, n_blocks, block, mu, parity, n_hits, pass_ids, bump_n,
+    return launch_pass_batch<Det64, 0>(links, lats, blocks, n_blocks, block, xcd_map, mu, parity, n_hits, pass_ids, 0, st);
+  return launch_pass_batch<Det64, 1>(links, lats, blocks, n_blocks, block, xcd_map, mu, parity, n_hits, pass_ids, bump_n,
                                      st);
 }
 

@@ -194,14 +194,16 @@ __device__ __forceinline__ void update_link(typename P::real* __restrict__ base,
 }
 
 // Single lattice: geometry in the kernel arguments; grid (blocks per slice,
-// updated slices), walked in XCD-contiguous order.
+// updated slices), walked in XCD-contiguous order (xcd_map != 0) or in the
+// hardware's round-robin order.
 template <class P, int MU, int KIND>
 __global__ void class_pass_kernel(typename P::real* __restrict__ links, LatDesc d, int parity, int th_frozen,
                                   int n_hits, uint64_t* __restrict__ pass_ids, uint8_t* __restrict__ log,
-                                  int bump_n) {
+                                  int bump_n, int xcd_map) {
   if (KIND == 1 && bump_n > 0 && blockIdx.x == 0 && blockIdx.y == 0)
     for (int i = threadIdx.x; i < bump_n; i += blockDim.x) pass_ids[i] += 1;
-  const uint32_t lb = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const uint32_t lin = blockIdx.y * gridDim.x + blockIdx.x;
+  const uint32_t lb = xcd_map ? xcd_block(lin, gridDim.x * gridDim.y) : lin;
   const uint32_t by = lb / gridDim.x, bx = lb - by * gridDim.x;
   const uint32_t off = bx * blockDim.x + threadIdx.x;
   if (off >= ((uint32_t)d.L3 >> 1)) return;
@@ -210,14 +212,14 @@ __global__ void class_pass_kernel(typename P::real* __restrict__ links, LatDesc 
 }
 
 // Batch: blocks[b] = {lattice, time slice, first offset in the slice, 0},
-// walked in XCD-contiguous order.
+// walked in XCD-contiguous order (xcd_map != 0) or in table order.
 template <class P, int MU, int KIND>
 __global__ void class_pass_batch_kernel(typename P::real* __restrict__ links, const LatDesc* __restrict__ lats,
                                         const int4* __restrict__ blocks, int parity, int n_hits,
-                                        uint64_t* __restrict__ pass_ids, int bump_n) {
+                                        uint64_t* __restrict__ pass_ids, int bump_n, int xcd_map) {
   if (KIND == 1 && bump_n > 0 && blockIdx.x == 0)
     for (int i = threadIdx.x; i < bump_n; i += blockDim.x) pass_ids[i] += 1;
-  const int4 bk = blocks[xcd_block(blockIdx.x, gridDim.x)];
+  const int4 bk = blocks[xcd_map ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x];
   const LatDesc d = lats[bk.x];
   const uint32_t off = (uint32_t)bk.z + threadIdx.x;
   if (off >= ((uint32_t)d.L3 >> 1)) return;
@@ -228,27 +230,27 @@ hipError_t launch_bump_pass_ids(uint64_t* pass_ids, int n, hipStream_t st);
 
 // Launch helpers shared by the FP64 and FP32 translation units.
 template <class P, int KIND>
-hipError_t launch_pass_single(typename P::real* links, const LatDesc& d, int block, int mu, int parity, int th,
-                              int n_hits, uint64_t* pass_ids, uint8_t* log, int bump_n, hipStream_t st) {
+hipError_t launch_pass_single(typename P::real* links, const LatDesc& d, int block, int xcd_map, int mu, int parity,
+                              int th, int n_hits, uint64_t* pass_ids, uint8_t* log, int bump_n, hipStream_t st) {
   const int slices = class_slices(d.T, mu, th);
   if (slices == 0) return bump_n > 0 ? launch_bump_pass_ids(pass_ids, bump_n, st) : hipSuccess;
   const dim3 grid((d.L3 / 2 + block - 1) / block, slices);
   switch (mu) {
     case 0:
       hipLaunchKernelGGL((class_pass_kernel<P, 0, KIND>), grid, dim3(block), 0, st, links, d, parity, th, n_hits,
-                         pass_ids, log, bump_n);
+                         pass_ids, log, bump_n, xcd_map);
       break;
     case 1:
       hipLaunchKernelGGL((class_pass_kernel<P, 1, KIND>), grid, dim3(block), 0, st, links, d, parity, th, n_hits,
-                         pass_ids, log, bump_n);
+                         pass_ids, log, bump_n, xcd_map);
       break;
     case 2:
       hipLaunchKernelGGL((class_pass_kernel<P, 2, KIND>), grid, dim3(block), 0, st, links, d, parity, th, n_hits,
-                         pass_ids, log, bump_n);
+                         pass_ids, log, bump_n, xcd_map);
       break;
     default:
       hipLaunchKernelGGL((class_pass_kernel<P, 3, KIND>), grid, dim3(block), 0, st, links, d, parity, th, n_hits,
-                         pass_ids, log, bump_n);
+                         pass_ids, log, bump_n, xcd_map);
       break;
   }
   return hipGetLastError();
@@ -256,25 +258,25 @@ hipError_t launch_pass_single(typename P::real* links, const LatDesc& d, int blo
 
 template <class P, int KIND>
 hipError_t launch_pass_batch(typename P::real* links, const LatDesc* lats, const int4* blocks, int n_blocks,
-                             int block, int mu, int parity, int n_hits, uint64_t* pass_ids, int bump_n,
+                             int block, int xcd_map, int mu, int parity, int n_hits, uint64_t* pass_ids, int bump_n,
                              hipStream_t st) {
   if (n_blocks == 0) return bump_n > 0 ? launch_bump_pass_ids(pass_ids, bump_n, st) : hipSuccess;
   switch (mu) {
     case 0:
       hipLaunchKernelGGL((class_pass_batch_kernel<P, 0, KIND>), dim3(n_blocks), dim3(block), 0, st, links, lats,
-                         blocks, parity, n_hits, pass_ids, bump_n);
+                         blocks, parity, n_hits, pass_ids, bump_n, xcd_map);
       break;
     case 1:
       hipLaunchKernelGGL((class_pass_batch_kernel<P, 1, KIND>), dim3(n_blocks), dim3(block), 0, st, links, lats,
-                         blocks, parity, n_hits, pass_ids, bump_n);
+                         blocks, parity, n_hits, pass_ids, bump_n, xcd_map);
       break;
     case 2:
       hipLaunchKernelGGL((class_pass_batch_kernel<P, 2, KIND>), dim3(n_blocks), dim3(block), 0, st, links, lats,
-                         blocks, parity, n_hits, pass_ids, bump_n);
+                         blocks, parity, n_hits, pass_ids, bump_n, xcd_map);
       break;
     default:
       hipLaunchKernelGGL((class_pass_batch_kernel<P, 3, KIND>), dim3(n_blocks), dim3(block), 0, st, links, lats,
-                         blocks, parity, n_hits, pass_ids, bump_n);
+                         blocks, parity, n_hits, pass_ids, bump_n, xcd_map);
       break;
   }
   return hipGetLastError();

@@ -50,6 +50,16 @@ class Observables(C.Structure):
                 "field2_mean": list(self.field2_mean)}
 
 
+class Tuning(C.Structure):
+    """u1ml_tuning: launch shapes of the kernels (results do not depend on them)."""
+    _fields_ = [("pass_block", C.c_int), ("pass_xcd_map", C.c_int), ("sample_block", C.c_int),
+                ("fold_threads", C.c_int), ("field_w_planes", C.c_int), ("field_o_planes", C.c_int),
+                ("field_zcon_threads", C.c_int)]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -108,6 +118,11 @@ def load_library(path: str = LIB_PATH):
         "u1ml_batch_synchronize": (I, [P]),
         "u1ml_batch_destroy": (None, [P]),
         "u1ml_autotune": (I, [P, ip]),
+        "u1ml_get_tuning": (I, [P, C.POINTER(Tuning)]),
+        "u1ml_set_tuning": (I, [P, C.POINTER(Tuning)]),
+        "u1ml_batch_get_tuning": (I, [P, C.POINTER(Tuning)]),
+        "u1ml_batch_set_tuning": (I, [P, C.POINTER(Tuning)]),
+        "u1ml_batch_autotune": (I, [P, I, ip, ip, I, ip, I, ip, C.POINTER(Tuning)]),
         "u1ml_profile_sweeps": (I, [P, I, I, I, dp]),
         "u1ml_batch_profile_sweeps": (I, [P, I, I, I, dp]),
         "u1ml_strerror": (C.c_char_p, [I]),
@@ -378,6 +393,42 @@ def autotune(lat: Lattice) -> int:
     b = C.c_int()
     _check(load_library().u1ml_autotune(lat.handle, C.byref(b)))
     return int(b.value)
+
+
+def get_tuning(obj) -> dict:
+    """Launch shapes of a Lattice or Batch (u1ml_get_tuning / u1ml_batch_get_tuning)."""
+    t = Tuning()
+    lib = load_library()
+    f = lib.u1ml_batch_get_tuning if isinstance(obj, Batch) else lib.u1ml_get_tuning
+    _check(f(obj.handle, C.byref(t)))
+    return t.as_dict()
+
+
+def set_tuning(obj, **values):
+    """Change some launch shapes of a Lattice or Batch; the others keep their values."""
+    cur = get_tuning(obj)
+    unknown = set(values) - set(cur)
+    if unknown:
+        raise U1MLError(EINVAL, f"unknown tuning fields {sorted(unknown)}")
+    cur.update(values)
+    t = Tuning(**cur)
+    lib = load_library()
+    f = lib.u1ml_batch_set_tuning if isinstance(obj, Batch) else lib.u1ml_set_tuning
+    _check(f(obj.handle, C.byref(t)))
+
+
+def batch_autotune(b, slab_sizes=(), n_sub=(), r_list=(), rf_list=()) -> dict:
+    """u1ml_batch_autotune; with slab_sizes empty only the class passes are tuned."""
+    th, thp = _ints(slab_sizes if len(slab_sizes) else [0])
+    ns, nsp = _ints(n_sub if len(n_sub) else [0])
+    r, rp = _ints(r_list if len(r_list) else [0])
+    rf, rfp = _ints(rf_list if len(rf_list) else [0])
+    t = Tuning()
+    _check(load_library().u1ml_batch_autotune(b.handle, len(slab_sizes), thp if len(slab_sizes) else None,
+                                              nsp if len(slab_sizes) else None, len(r_list),
+                                              rp if len(r_list) else None, len(rf_list),
+                                              rfp if len(rf_list) else None, C.byref(t)))
+    return t.as_dict()
 
 
 def profile_sweeps(lat: Lattice, n_sweeps: int, n_metro: int = 1, n_or: int = 3):
