@@ -1,8 +1,8 @@
 """Benchmark: multilevel compact U(1) on 24^4 lattices at beta = 1 on one MI355X.
 
-One step advances R independent 24^4 chains (R = 24 by default, in 3 batches
-of 8 on 3 streams whose launches overlap) by
-one pass of the whole method each:
+One step advances R independent 24^4 chains (R = 48 by default, in 3 batches
+of 16 on 3 streams whose launches overlap) by one pass of the whole method
+each:
   * 100 compound sweeps (1 Metropolis hit + 3 overrelaxation passes per link)
     between measured configurations (Sec. 2.1);
   * one two-level multilevel measurement (Sec. 2.2): slabs of 4 (10 updates)
@@ -10,15 +10,21 @@ one pass of the whole method each:
     x, and the E/B field profiles (Eq. (5), Eq. (9)) over the 24^2 planes at
     the mid-point of charges at r = 2, 4, 6;
   * the plain observables and the read-back of all results.
-The lattices are synthetic (cold start + 200 thermalisation sweeps, seeds 3..).
+The lattices are synthetic (cold start + 200 thermalisation sweeps, seeds 3..);
+the launch shapes of every kernel family are picked by the batch autotuner
+first.
 
 Printed: one JSON line with link updates/s of the Markov chains (the replay of
 the update sequence that the field insertion needs is not counted as
 updates), multilevel samples/s (one sample = one innermost-slab update
 followed by its two-link measurement for all L^3 sources and all r), the
-roofline of the dominant kernel, single-chain FP32 and FP64 legs, and the
-CPU oracle timed on this host.  --counters makes the short run used for the
-hardware-counter passes instead.
+roofline of the dominant kernel (the class pass, on the benchmark's batch,
+which fits the 256 MB Infinity Cache) and of the same kernel on a batch that
+does not fit it, a plain device copy for the achievable bandwidth, the
+FP32-vs-FP64 deviation of each observable, the 64-lattice uneven batch, one
+48^4 lattice in FP32 and FP64, single-chain legs, and the CPU oracle timed on
+this host with one thread and with all.  --counters makes the short run used
+for the hardware-counter passes instead.
 """
 from __future__ import annotations
 
@@ -42,10 +48,14 @@ RF_LIST = [2, 4, 6]
 N_BETWEEN = 100
 N_THERM = 200
 HBM_PEAK_GBS = 8000.0
+INFINITY_CACHE_BYTES = 256 << 20
 WORDS_PER_UPDATE = 9  # 8 link reads + 1 write per update in a class pass
 DEFAULT_REPLICAS = 48
 DEFAULT_STREAMS = 3
 CPU_N_SUB = [2, 5]  # reduced multilevel sample for the oracle
+CPU_N_SUB_1T = [1, 2]  # the same on one thread
+SPILL_REPLICAS = 64  # 64 x 24^4 FP32 = 340 MB of links: more than the 256 MB Infinity Cache
+TUNE_N_SUB = [1, 2]  # multilevel shape the autotuner times
 COPY_ELEMS = 1 << 27  # calibration copy: 512 MiB read, 512 MiB written
 
 
@@ -78,18 +88,27 @@ def traffic_from_profiles(kernel_key, replicas, bytes_per_word):
         with open(p) as f:
             d = json.load(f)
         e = d.get(kernel_key)
-        if (e and e.get("sources_sha") == sweep_sources_sha() and e.get("replicas") == replicas
-                and e.get("bytes_per_word") == bytes_per_word):
-            return e["bytes_per_launch"]
-    except (OSError, ValueError):
+        if e and e.get("sources_sha") == sweep_sources_sha() and e.get("bytes_per_word") == bytes_per_word:
+            r = e.get("by_replicas", {}).get(str(replicas))
+            if r:
+                return r["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
         pass
     return None
 
 
-def cpu_baseline(seconds: float):
-    """The FP64 oracle on this host: compound sweeps of the 24^4 lattice for
-    about `seconds`, and one reduced multilevel run for samples/s."""
-    import oracle
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_leg(oracle, seconds, n_sub):
     o = oracle.OracleLattice(L, T, BETA, 3, hot=False)
     o.sweep(1, 3)  # warm-up
     n, t0 = 0, time.perf_counter()
@@ -101,17 +120,36 @@ def cpu_baseline(seconds: float):
             break
     ups = n * 16 * L ** 3 * T / el
     t0 = time.perf_counter()
-    o.multilevel(LEVELS, CPU_N_SUB, 1, 3, R_LIST)  # no field: the oracle's field accumulators exceed memory at 24^4
+    o.multilevel(LEVELS, n_sub, 1, 3, R_LIST)  # no field: the oracle's field accumulators exceed memory at 24^4
     el_ml = time.perf_counter() - t0
-    samp = CPU_N_SUB[0] * CPU_N_SUB[1] * (T // LEVELS[-1])
-    return {"value": ups, "unit": "link updates/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "samples_per_s": samp / el_ml,
+    samp = n_sub[0] * n_sub[1] * (T // LEVELS[-1])
+    return ups, samp / el_ml, n, el, samp, el_ml
+
+
+def cpu_baseline(seconds: float):
+    """The FP64 oracle on this host, on all its cores and on one: compound
+    sweeps of the 24^4 lattice for about `seconds` each, and one reduced
+    multilevel run for samples/s."""
+    import oracle
+    n_all = oracle.max_threads()
+    ups, sps, n, el, samp, el_ml = _oracle_leg(oracle, seconds, CPU_N_SUB)
+    oracle.set_threads(1)
+    try:
+        ups1, sps1, n1, el1, samp1, el_ml1 = _oracle_leg(oracle, seconds, CPU_N_SUB_1T)
+    finally:
+        oracle.set_threads(n_all)
+    return {"value": ups, "unit": "link updates/s", "cores": n_all, "kind": "oracle",
+            "samples_per_s": sps, "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"{n} compound sweeps (1 Metropolis + 3 OR) of 24^4 FP64 in {el:.1f} s; "
                       f"multilevel levels {LEVELS} with n_sub {CPU_N_SUB}, r = 1..12, no field ({samp} samples) "
-                      f"in {el_ml:.1f} s"}
+                      f"in {el_ml:.1f} s",
+            "single_thread": {"value": ups1, "unit": "link updates/s", "cores": 1, "samples_per_s": sps1,
+                              "sample": f"{n1} compound sweeps in {el1:.1f} s; multilevel n_sub {CPU_N_SUB_1T} "
+                                        f"({samp1} samples) in {el_ml1:.1f} s"}}
 
 
-def run_chain(u1ml, torch, prec, R, rf, steps, warmup, n_streams=1, multihit=False, squared=False, symmetric=False):
+def run_chain(u1ml, torch, prec, R, rf, steps, warmup, n_streams=1, multihit=False, squared=False, symmetric=False,
+              tune=True):
     """Build R independent 24^4 chains split into n_streams groups (one batch,
     or one lattice, per group, each on a stream of its own), thermalise, and
     time `steps` steps; the groups' launches overlap on the GPU.  Returns a
@@ -135,6 +173,13 @@ def run_chain(u1ml, torch, prec, R, rf, steps, warmup, n_streams=1, multihit=Fal
                                                                           field_squared=squared, symmetric=symmetric)
         groups.append({"lat": lat, "sw": sw, "st": st, "n": n})
         first += n
+    tuning = None
+    if tune and groups[0]["n"] > 1:
+        # launch shapes picked on the first batch, applied to the others (same shape)
+        tuning = u1ml.batch_autotune(groups[0]["lat"], LEVELS, TUNE_N_SUB, R_LIST, rf)
+        for gr in groups[1:]:
+            if gr["n"] > 1:
+                u1ml.set_tuning(gr["lat"], **tuning)
     for _ in range(N_THERM):
         for gr in groups:
             gr["sw"]()
@@ -184,13 +229,15 @@ def run_chain(u1ml, torch, prec, R, rf, steps, warmup, n_streams=1, multihit=Fal
             "group0_sweep_updates_per_s": n0 * up_sw / (ms_sweeps * 1e-3),
             "group0_ml_updates_per_s": n0 * up_ml / (ms_ml * 1e-3),
             "group0_ml_samples_per_s": n0 * samples_per_step() / (ms_ml * 1e-3),
-            "obs": obs, "corr": corr}
+            "obs": obs, "corr": corr, "tuning": tuning}
 
 
-def roofline_leg(u1ml, torch, prec, R, steps):
-    """The dominant kernel alone: N_BETWEEN compound sweeps of one R-lattice
-    batch on one stream, timed with HIP events around each step's sweeps."""
+def roofline_leg(u1ml, torch, prec, R, steps, n_sweeps=N_BETWEEN, tune=True):
+    """The dominant kernel alone: n_sweeps compound sweeps of one R-lattice
+    batch on one stream (class-pass shapes from the autotuner), timed with HIP
+    events on that stream around each step's sweeps."""
     st = torch.cuda.Stream()
+    tuning = None
     if R == 1:
         lat = u1ml.init_lattice(L, T, BETA, 3, start=u1ml.COLD, precision=prec, stream=st.cuda_stream)
         sw = lambda: u1ml.sweep(lat, 1, 3)  # noqa: E731
@@ -198,13 +245,15 @@ def roofline_leg(u1ml, torch, prec, R, steps):
         lat = u1ml.batch_create([L] * R, [T] * R, [BETA] * R, [3 + i for i in range(R)], start=u1ml.COLD,
                                 precision=prec, stream=st.cuda_stream)
         sw = lambda: u1ml.batch_sweep(lat, 1, 3)  # noqa: E731
+        if tune:
+            tuning = u1ml.batch_autotune(lat)
     for _ in range(20):
         sw()
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     for a, b in ev:
         a.record(st)
-        for _ in range(N_BETWEEN):
+        for _ in range(n_sweeps):
             sw()
         b.record(st)
     torch.cuda.synchronize()
@@ -213,7 +262,62 @@ def roofline_leg(u1ml, torch, prec, R, steps):
         iso = u1ml.batch_profile_sweeps(lat, 5, 1, 3)
     else:
         iso = u1ml.profile_sweeps(lat, 5, 1, 3)
-    return ms, iso
+    del lat
+    return ms, iso, tuning
+
+
+def roofline_entry(u1ml, prec, R, ms, n_sweeps, steps, iso, tuning, traffic):
+    """Class-pass roofline from the average duration of the timed sweeps:
+    algorithmic bytes (9 link words per update) per launch over the average
+    launch time, against the 8 TB/s HBM peak."""
+    passes_per_step = n_sweeps * 4 * 8
+    avg_us = 1e3 * ms / passes_per_step
+    bw = 4 if prec == u1ml.FP32 else 8
+    updates_per_launch = R * L ** 3 * T // 2
+    bytes_per_launch = updates_per_launch * WORDS_PER_UPDATE * bw
+    achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
+    pname = "Fast32" if prec == u1ml.FP32 else "Det64"
+    kname = f"class_pass_batch_kernel<{pname}, mu, kind>" if R > 1 else f"class_pass_kernel<{pname}, mu, kind>"
+    batch_bytes = R * 4 * L ** 3 * T * bw
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname, "avg_us": avg_us,
+            "launches_timed": passes_per_step * steps, "replicas": R, "batch_bytes": batch_bytes,
+            "cache_resident": batch_bytes <= INFINITY_CACHE_BYTES,
+            "isolated_event_us": {"metropolis": iso[0], "or": iso[1]},
+            "algorithmic_bytes_per_launch": bytes_per_launch, "tuning": tuning}
+
+
+def copy_bandwidth(torch, n_bytes=2 << 30, reps=5):
+    """A plain device-to-device copy of n_bytes (read + write counted), timed
+    with HIP events: the bandwidth a streaming kernel reaches on this GPU."""
+    src = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record(st)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return {"bytes_moved": 2 * n_bytes, "GB_per_s": 2 * n_bytes / (ms * 1e-3) / 1e9, "frac_of_peak":
+            2 * n_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def precision_leg():
+    """FP32 sweeps / FP64 accumulation against the FP64 path on the benchmark's
+    workload (24^4, beta = 1, multilevel {4,2} x {10,20}): 8 chains per
+    precision, 3 configurations 50 sweeps apart after 200 thermalisation
+    sweeps; relative deviation and its size in combined jackknife errors."""
+    from paper_1208_0166_amd import precision
+    rows = precision.compare(L=L, beta=BETA, n_chains=8, n_therm=N_THERM, n_configs=3, n_between=50,
+                             levels=tuple(LEVELS), n_sub=tuple(N_SUB), r_list=(1, 2, 3, 4), seed0=2000)
+    return {"chains_per_precision": 8, "configurations_per_chain": 3,
+            "observables": {r["name"]: {"rel_dev": r["rel_dev"], "sigmas": r["sigmas"], "rel_err": r["rel_err"],
+                                        "fp32": r["fp32"], "fp64": r["fp64"]} for r in rows}}
 
 
 def counters_run(args):
@@ -249,24 +353,20 @@ LARGE_N_SUB = [20, 10]
 LARGE_THERM = 500
 
 
-def large_run(args):
-    """One 48^4 beta=1 chain per precision (same seed, cold start): LARGE_THERM
+def large_leg(u1ml, torch, n_therm=LARGE_THERM):
+    """One 48^4 beta=1 chain per precision (same seed, cold start): n_therm
     sweeps, then N_BETWEEN timed sweeps and one timed two-level multilevel
-    {4,2} x {20,10}, r = 1..24, E/B profiles at r = 2, 4, 6.  Reports the
+    {4,2} x {20,10}, r = 1..24, E/B profiles at r = 2, 4, 6.  Returns the
     sweep and multilevel throughput of the FP32 and FP64 paths and the
     deviation of their observables (two chains of the same distribution: the
     FP32 path draws its own random numbers, so the difference is
     statistical)."""
-    import torch
-    from paper_1208_0166_amd import u1ml
-
-    torch.cuda.set_device(0)
     r_list = list(range(1, LARGE_L // 2 + 1))
     res = {}
     for name, prec in (("fp32", u1ml.FP32), ("fp64", u1ml.FP64)):
         st = torch.cuda.Stream()
         g = u1ml.init_lattice(LARGE_L, LARGE_L, BETA, 3, start=u1ml.COLD, precision=prec, stream=st.cuda_stream)
-        for _ in range(LARGE_THERM):
+        for _ in range(n_therm):
             u1ml.sweep(g, 1, 3)
         u1ml.multilevel(g, LARGE_LEVELS, LARGE_N_SUB, 1, 3, r_list, rf_list=RF_LIST)  # set-up, capture
         u1ml.synchronize(g)
@@ -288,18 +388,33 @@ def large_run(args):
         up_ml *= 1 + 3  # Metropolis + 3 OR
         res[name] = {"sweep_updates_per_s": N_BETWEEN * 16 * V / (ms_sw * 1e-3), "ms_100_sweeps": ms_sw,
                      "multilevel_ms": ms_ml, "multilevel_updates_per_s": up_ml / (ms_ml * 1e-3),
-                     "plaquette": obs["plaquette"], "C": [[c.real, c.imag] for c in corr[:6]]}
+                     "plaquette": obs["plaquette"], "poly_abs": obs["poly_abs"],
+                     "C": [[c.real, c.imag] for c in corr[:6]]}
         del g
     d_plaq = abs(res["fp32"]["plaquette"] - res["fp64"]["plaquette"]) / abs(res["fp64"]["plaquette"])
+    return {"workload": f"one 48^4 beta=1 chain per precision: {n_therm} sweeps, then {N_BETWEEN} timed sweeps "
+                        f"and one two-level multilevel {{4,2}} x {{20,10}}, r=1..24, E/B mid-plane profiles at "
+                        "r=2,4,6",
+            "fp32": res["fp32"], "fp64": res["fp64"],
+            "fp32_over_fp64_sweeps": res["fp32"]["sweep_updates_per_s"] / res["fp64"]["sweep_updates_per_s"],
+            "fp32_over_fp64_multilevel": res["fp32"]["multilevel_updates_per_s"] /
+                                         res["fp64"]["multilevel_updates_per_s"],
+            "plaquette_rel_deviation": d_plaq,
+            "note": "one chain per precision: the deviation is one draw of a statistical difference; the "
+                    "controlled 3-sigma comparison is precision_split"}
+
+
+def large_run(args):
+    import torch
+    from paper_1208_0166_amd import u1ml
+
+    torch.cuda.set_device(0)
+    leg = large_leg(u1ml, torch)
     out = {"metric": "link updates/s (Metropolis+OR), 48^4 beta=1, FP32 and FP64 paths",
-           "value": res["fp32"]["sweep_updates_per_s"], "unit": "link updates/s", "n_gpus": 1,
+           "value": leg["fp32"]["sweep_updates_per_s"], "unit": "link updates/s", "n_gpus": 1,
            "higher_is_better": True, "dtype": "f32", "data": "synthetic (cold start, seed 3)",
-           "config": {"workload": f"one 48^4 beta=1 chain per precision: {LARGE_THERM} sweeps, then "
-                                  f"{N_BETWEEN} timed sweeps and one two-level multilevel {{4,2}} x {{20,10}}, "
-                                  "r=1..24, E/B mid-plane profiles at r=2,4,6"},
-           "fp32": res["fp32"], "fp64": res["fp64"],
-           "fp32_over_fp64_sweeps": res["fp32"]["sweep_updates_per_s"] / res["fp64"]["sweep_updates_per_s"],
-           "plaquette_rel_deviation": d_plaq}
+           "config": {"workload": leg["workload"]}}
+    out.update({k: v for k, v in leg.items() if k != "workload"})
     print(json.dumps(out), flush=True)
 
 
@@ -308,34 +423,32 @@ UNEVEN_SWEEPS = 10
 UNEVEN_TH, UNEVEN_NSUB = 2, 10
 
 
-def uneven_run(args):
+def uneven_leg(u1ml, torch, n_cycles, warmup=1, tune=True):
     """64 independent lattices of sizes drawn from {8,12,16,20,24}^4 and beta
     from {0.9, 1.0, 1.1} (numpy default_rng(7)), FP32 links, one batch on one
-    stream: after N_THERM sweeps, 10 x steps cycles of UNEVEN_SWEEPS compound
-    sweeps plus a single-level multilevel (slab thickness 2, 10 updates) with
-    correlators at r = 1..L/2, each cycle one captured HIP graph; then every
-    lattice's results are read back."""
+    stream (class-pass shapes from the autotuner): after N_THERM sweeps,
+    n_cycles cycles of UNEVEN_SWEEPS compound sweeps plus a single-level
+    multilevel (slab thickness 2, 10 updates) with correlators at r = 1..L/2,
+    each cycle one captured HIP graph; then every lattice's results are read
+    back."""
     import numpy as np
-    import torch
-    from paper_1208_0166_amd import u1ml
 
-    torch.cuda.set_device(0)
     rng = np.random.default_rng(7)
     Ls = [int(v) for v in rng.choice([8, 12, 16, 20, 24], UNEVEN_N)]
     betas = [float(v) for v in rng.choice([0.9, 1.0, 1.1], UNEVEN_N)]
     st = torch.cuda.Stream()
     b = u1ml.batch_create(Ls, Ls, betas, [1000 + i for i in range(UNEVEN_N)], start=u1ml.COLD,
                           precision=u1ml.FP32, stream=st.cuda_stream)
+    tuning = u1ml.batch_autotune(b) if tune else None
     for _ in range(N_THERM):
         u1ml.batch_sweep(b, 1, 3)
 
     def cycle():
         u1ml.batch_cycle(b, UNEVEN_SWEEPS, 1, 3, UNEVEN_TH, UNEVEN_NSUB, use_graph=True)
 
-    for _ in range(max(args.warmup, 1)):
+    for _ in range(max(warmup, 1)):
         cycle()
     u1ml.batch_synchronize(b)
-    n_cycles = 10 * args.steps
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     t0 = time.perf_counter()
     ev[0].record(st)
@@ -345,21 +458,34 @@ def uneven_run(args):
     res = [u1ml.batch_measure(b, i, correlator=True) for i in range(UNEVEN_N)]
     el = time.perf_counter() - t0
     ms_cycles = ev[0].elapsed_time(ev[1])
-    V = [L ** 4 for L in Ls]
+    V = [L_ ** 4 for L_ in Ls]
     up = sum(UNEVEN_SWEEPS * 16 * v + UNEVEN_NSUB * 4 * (4 * v - 3 * v // UNEVEN_TH) for v in V)
-    samples = sum(UNEVEN_NSUB * (L // UNEVEN_TH) for L in Ls)
+    samples = sum(UNEVEN_NSUB * (L_ // UNEVEN_TH) for L_ in Ls)
     counts = {int(k): int(c) for k, c in zip(*np.unique(Ls, return_counts=True))}
+    del b
+    return {"workload": f"64 independent lattices L^4, L counts {counts}, beta in {{0.9, 1.0, 1.1}}, one "
+                        f"batch; per cycle {UNEVEN_SWEEPS} sweeps + single-level multilevel (th 2, 10 "
+                        "updates), r = 1..L/2, one captured graph per cycle",
+            "updates_per_s": up * n_cycles / el, "samples_per_s": samples * n_cycles / el,
+            "cycles": n_cycles, "ms_per_cycle": 1e3 * el / n_cycles, "gpu_ms_per_cycle": ms_cycles / n_cycles,
+            "updates_per_s_gpu": up * n_cycles / (ms_cycles * 1e-3),
+            "step_roofline_frac": up * n_cycles / el / (HBM_PEAK_GBS * 1e9 / (WORDS_PER_UPDATE * 4)),
+            "plaquette_min_max": [min(r[0]["plaquette"] for r in res), max(r[0]["plaquette"] for r in res)],
+            "tuning": tuning}
+
+
+def uneven_run(args):
+    import torch
+    from paper_1208_0166_amd import u1ml
+
+    torch.cuda.set_device(0)
+    leg = uneven_leg(u1ml, torch, 10 * args.steps, args.warmup)
     out = {"metric": "link updates/s (Metropolis+OR) and multilevel correlator samples/s, 64 uneven instances",
-           "value": up * n_cycles / el, "unit": "link updates/s", "n_gpus": 1, "steps": n_cycles,
-           "warmup": max(args.warmup, 1), "ms_per_step": 1e3 * el / n_cycles, "higher_is_better": True,
+           "value": leg["updates_per_s"], "unit": "link updates/s", "n_gpus": 1, "steps": leg["cycles"],
+           "warmup": max(args.warmup, 1), "ms_per_step": leg["ms_per_cycle"], "higher_is_better": True,
            "dtype": "f32", "data": "synthetic (cold start, 200 thermalisation sweeps, sizes and beta from default_rng(7))",
-           "config": {"workload": f"64 independent lattices L^4, L counts {counts}, beta in {{0.9, 1.0, 1.1}}, one "
-                                  f"batch; per cycle {UNEVEN_SWEEPS} sweeps + single-level multilevel (th 2, 10 "
-                                  "updates), r = 1..L/2, one captured graph per cycle"},
-           "samples_per_s": samples * n_cycles / el,
-           "gpu_ms_per_cycle": ms_cycles / n_cycles,
-           "updates_per_s_gpu": up * n_cycles / (ms_cycles * 1e-3),
-           "plaquette_min_max": [min(r[0]["plaquette"] for r in res), max(r[0]["plaquette"] for r in res)]}
+           "config": {"workload": leg["workload"]}}
+    out.update({k: v for k, v in leg.items() if k != "workload"})
     print(json.dumps(out), flush=True)
 
 
@@ -370,10 +496,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-field", action="store_true", help="skip the field-profile insertion")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the single-chain FP32 and FP64 comparison legs")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the cache-spilling roofline, copy, precision, uneven and 48^4 legs")
+    ap.add_argument("--no-tune", action="store_true", help="default launch shapes instead of the autotuner's")
     ap.add_argument("--replicas", type=int, default=DEFAULT_REPLICAS,
                     help="independent 24^4 chains advanced by the same launches (one batch)")
     ap.add_argument("--streams", type=int, default=DEFAULT_STREAMS,
@@ -409,6 +538,9 @@ def main():
     import torch
     from paper_1208_0166_amd import u1ml
 
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     torch.cuda.set_device(0)
     # every lattice or batch gets a stream of its own (passed explicitly); torch's
     # own work goes to a dedicated stream as well
@@ -416,29 +548,26 @@ def main():
     prec = u1ml.FP32 if args.precision == "fp32" else u1ml.FP64
     rf = [] if args.no_field else RF_LIST
     R = args.replicas
+    tune = not args.no_tune
 
+    progress("main run")
     main_run = run_chain(u1ml, torch, prec, R, rf, args.steps, args.warmup, args.streams, args.multihit,
-                         args.squared, args.symmetric)
+                         args.squared, args.symmetric, tune=tune)
 
     # dominant kernel: the class pass (Metropolis or OR, 9 words per update),
     # timed alone on one stream: N_BETWEEN compound sweeps of 4 x 8 class passes
     # plus one pass-id bump per step, so (sweep time) / (class passes) bounds
     # the average dispatch time from above.  Per-launch event timings are
     # recorded beside it.
-    passes_per_step = N_BETWEEN * 4 * 8
-    ms_rf, (iso_metro, iso_or) = roofline_leg(u1ml, torch, prec, R, args.steps)
-    avg_us = 1e3 * ms_rf / passes_per_step
+    progress("roofline leg")
     bw = 4 if prec == u1ml.FP32 else 8
-    updates_per_launch = R * L ** 3 * T // 2
-    bytes_per_launch = updates_per_launch * WORDS_PER_UPDATE * bw
-    achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
+    ms_rf, iso, rf_tuning = roofline_leg(u1ml, torch, prec, R, args.steps, tune=tune)
     pname = "Fast32" if prec == u1ml.FP32 else "Det64"
     kname = f"class_pass_batch_kernel<{pname}, mu, kind>" if R > 1 else f"class_pass_kernel<{pname}, mu, kind>"
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(kname, R, bw),
-                "kernel": kname, "avg_us": avg_us, "launches_timed": passes_per_step * args.steps,
-                "isolated_event_us": {"metropolis": iso_metro, "or": iso_or},
-                "algorithmic_bytes_per_launch": bytes_per_launch}
+    roofline = roofline_entry(u1ml, prec, R, ms_rf, N_BETWEEN, args.steps, iso, rf_tuning,
+                              traffic_from_profiles(kname, R, bw))
+    roofline["note"] = ("the benchmark's batch fits the 256 MB Infinity Cache, which serves part of every class "
+                        "pass; roofline_spilled is the same kernel on a batch larger than the cache")
 
     obs, corr = main_run["obs"], main_run["corr"]
     out = {
@@ -466,6 +595,7 @@ def main():
         "multilevel_estimates_per_s": R * args.steps / (main_run["ms_step"] * 1e-3 * args.steps),
         "chain_updates_per_step": R * sum(chain_updates_per_step()),
         "streams": args.streams,
+        "tuning": main_run["tuning"],
         "group0_phase_ms": {"sweeps": main_run["ms_sweeps"], "multilevel": main_run["ms_ml"]},
         "group0_sweep_updates_per_s": main_run["group0_sweep_updates_per_s"],
         "group0_multilevel_chain_updates_per_s": main_run["group0_ml_updates_per_s"],
@@ -481,17 +611,32 @@ def main():
                           "frac": main_run["updates_per_s"] / (HBM_PEAK_GBS * 1e9 / (WORDS_PER_UPDATE * bw))},
     }
     del main_run
+    if not args.no_extra:
+        progress("cache-spilling roofline leg")
+        ms_sp, iso_sp, tun_sp = roofline_leg(u1ml, torch, prec, SPILL_REPLICAS, 3, tune=tune)
+        out["roofline_spilled"] = roofline_entry(u1ml, prec, SPILL_REPLICAS, ms_sp, N_BETWEEN, 3, iso_sp, tun_sp,
+                                                 traffic_from_profiles(kname, SPILL_REPLICAS, bw))
+        progress("copy bandwidth")
+        out["device_copy"] = copy_bandwidth(torch)
+        progress("precision split")
+        out["precision_split"] = precision_leg()
+        progress("uneven batch")
+        out["uneven_64"] = uneven_leg(u1ml, torch, 10, tune=tune)
+        progress("48^4 lattice")
+        out["large_48"] = large_leg(u1ml, torch, n_therm=200)
     if not args.no_compare:
         # one chain (no batching), FP32 path and plain FP64 path
+        progress("single-chain legs")
         legs = {}
         for name, pr in (("single_chain_fp32", u1ml.FP32), ("single_chain_fp64", u1ml.FP64)):
-            r = run_chain(u1ml, torch, pr, 1, rf, 1, 1)
+            r = run_chain(u1ml, torch, pr, 1, rf, 1, 1, tune=False)
             legs[name] = {"updates_per_s": r["updates_per_s"], "samples_per_s": r["samples_per_s"],
                           "ms_per_step": r["ms_step"], "phase_ms": {"sweeps": r["ms_sweeps"], "multilevel": r["ms_ml"]}}
             del r
         legs["speedup_vs_single_chain_fp64"] = out["value"] / legs["single_chain_fp64"]["updates_per_s"]
         out["compare"] = legs
     if not args.no_cpu:
+        progress("CPU oracle")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

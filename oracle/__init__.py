@@ -5,4 +5,4 @@ and by the CPU-baseline leg of ``bench.py``.  The product library never
 imports or links anything from here.
 """
 from .oracle import (OracleLattice, atan2, bessel_ratio, build_oracle, connected_profile,  # noqa: F401
-                     max_threads, philox4x64_10, sincos)
+                     max_threads, philox4x64_10, set_threads, sincos)

@@ -51,6 +51,7 @@ def _load():
         "or_destroy": (None, [P]),
         "or_volume": (C.c_long, [P]),
         "or_max_threads": (C.c_int, []),
+        "or_set_threads": (None, [C.c_int]),
         "or_get_pass_id": (C.c_uint64, [P]),
         "or_set_pass_id": (None, [P, C.c_uint64]),
         "or_set_beta": (None, [P, C.c_double]),
@@ -108,6 +109,11 @@ def philox4x64_10(ctr, key):
 
 def max_threads() -> int:
     return int(_load().or_max_threads())
+
+
+def set_threads(n: int):
+    """Threads of the oracle's OpenMP loops from now on (results do not depend on it)."""
+    _load().or_set_threads(int(n))
 
 
 def sincos(x: float):

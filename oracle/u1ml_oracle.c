@@ -244,6 +244,17 @@ void or_destroy(or_lat *g)
 long or_volume(const or_lat *g) { return g->V; }
 
 /* threads the OpenMP loops of the oracle use */
+/* threads of the OpenMP loops that follow (results do not depend on it) */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int or_max_threads(void)
 {
 #ifdef _OPENMP

@@ -110,3 +110,26 @@ def test_hot_start_range_and_uniformity(oracle_mod):
     assert np.mean(g.get_links() == h.get_links()) < 1e-3
     # hot-start lattices are disordered: plaquette near 0
     assert abs(g.plaquette()) < 5 / math.sqrt(6 * L ** 3 * T)
+
+
+def test_oracle_results_do_not_depend_on_the_thread_count(oracle_mod):
+    # the class passes and sums run over OpenMP threads; links, accept logs and
+    # multilevel results are the same bits with one thread and with all
+    runs = []
+    n_all = oracle_mod.max_threads()
+    try:
+        for n in (1, max(n_all, 2)):
+            oracle_mod.set_threads(n)
+            g = oracle_mod.OracleLattice(6, 8, 1.0, 21, hot=True)
+            logs = [g.sweep(1, 3, want_log=True) for _ in range(2)]
+            c, f, _ = g.multilevel([4, 2], [2, 2], 1, 3, [1, 2, 3], rf_list=[2])
+            runs.append((g.get_links(), logs, c, f, g.plaquette()))
+    finally:
+        oracle_mod.set_threads(n_all)
+    (l1, g1, c1, f1, p1), (l2, g2, c2, f2, p2) = runs
+    np.testing.assert_array_equal(l1, l2)
+    for a, b in zip(g1, g2):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(c1, c2)
+    np.testing.assert_array_equal(f1, f2)
+    assert p1 == p2
