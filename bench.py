@@ -174,7 +174,12 @@ def run_chain(u1ml, torch, prec, R, rf, steps, warmup, n_streams=1, multihit=Fal
         groups.append({"lat": lat, "sw": sw, "st": st, "n": n})
         first += n
     tuning = None
-    if tune and groups[0]["n"] > 1:
+    if isinstance(tune, dict):
+        tuning = dict(tune)
+        for gr in groups:
+            if gr["n"] > 1:
+                u1ml.set_tuning(gr["lat"], **tuning)
+    elif tune and groups[0]["n"] > 1:
         # launch shapes picked on the first batch, applied to the others (same shape)
         tuning = u1ml.batch_autotune(groups[0]["lat"], LEVELS, TUNE_N_SUB, R_LIST, rf)
         for gr in groups[1:]:
@@ -245,7 +250,10 @@ def roofline_leg(u1ml, torch, prec, R, steps, n_sweeps=N_BETWEEN, tune=True):
         lat = u1ml.batch_create([L] * R, [T] * R, [BETA] * R, [3 + i for i in range(R)], start=u1ml.COLD,
                                 precision=prec, stream=st.cuda_stream)
         sw = lambda: u1ml.batch_sweep(lat, 1, 3)  # noqa: E731
-        if tune:
+        if isinstance(tune, dict):
+            u1ml.set_tuning(lat, **tune)
+            tuning = u1ml.get_tuning(lat)
+        elif tune:
             tuning = u1ml.batch_autotune(lat)
     for _ in range(20):
         sw()
@@ -439,7 +447,12 @@ def uneven_leg(u1ml, torch, n_cycles, warmup=1, tune=True):
     st = torch.cuda.Stream()
     b = u1ml.batch_create(Ls, Ls, betas, [1000 + i for i in range(UNEVEN_N)], start=u1ml.COLD,
                           precision=u1ml.FP32, stream=st.cuda_stream)
-    tuning = u1ml.batch_autotune(b) if tune else None
+    tuning = None
+    if isinstance(tune, dict):
+        u1ml.set_tuning(b, **tune)
+        tuning = u1ml.get_tuning(b)
+    elif tune:
+        tuning = u1ml.batch_autotune(b)
     for _ in range(N_THERM):
         u1ml.batch_sweep(b, 1, 3)
 
@@ -503,6 +516,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the cache-spilling roofline, copy, precision, uneven and 48^4 legs")
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes instead of the autotuner's")
+    ap.add_argument("--tuning", default=None,
+                    help="JSON object of launch shapes (u1ml_tuning fields) applied to every batch instead of "
+                         "running the autotuner (reproducible profiles)")
     ap.add_argument("--replicas", type=int, default=DEFAULT_REPLICAS,
                     help="independent 24^4 chains advanced by the same launches (one batch)")
     ap.add_argument("--streams", type=int, default=DEFAULT_STREAMS,
@@ -548,7 +564,7 @@ def main():
     prec = u1ml.FP32 if args.precision == "fp32" else u1ml.FP64
     rf = [] if args.no_field else RF_LIST
     R = args.replicas
-    tune = not args.no_tune
+    tune = json.loads(args.tuning) if args.tuning else not args.no_tune
 
     progress("main run")
     main_run = run_chain(u1ml, torch, prec, R, rf, args.steps, args.warmup, args.streams, args.multihit,

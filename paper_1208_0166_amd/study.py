@@ -1,8 +1,11 @@
 """Reduced-statistics physics runs of the paper's measurements (Sec. 3) on
 the GPU, analysed on the host.
 
-    python -m paper_1208_0166_amd.study potential [--replicas 24] [--n1 100] [--n2 1000] ...
-    python -m paper_1208_0166_amd.study width [--replicas 8] [--n1 100] [--n2 1000] ...
+    python -m paper_1208_0166_amd.study potential [--replicas 16] [--n1 10] [--n2 100] ...
+    python -m paper_1208_0166_amd.study width [--replicas 8] [--n1 10] [--n2 100] ...
+
+The defaults are reduced statistics (10 x 100 iterations per configuration,
+500 thermalisation sweeps); the paper's are --n1 100 --n2 1000.
 
 ``potential``: independent chains at 24^4, beta = 1 (cold start, thermalised),
 one two-level multilevel run per configuration (slabs 4 and 2, analytical
@@ -147,7 +150,7 @@ def main(argv=None):
     ap.add_argument("--n2", type=int, default=None)
     ap.add_argument("--L", type=int, default=24)
     ap.add_argument("--beta", type=float, default=1.0)
-    ap.add_argument("--therm", type=int, default=3000)
+    ap.add_argument("--therm", type=int, default=500)
     ap.add_argument("--start", choices=["cold", "hot"], default="cold")
     ap.add_argument("--between", type=int, default=100)
     ap.add_argument("--seed", type=int, default=3000)
@@ -156,7 +159,10 @@ def main(argv=None):
     ap.add_argument("--no-multihit", action="store_true")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
-    defaults = {"potential": (24, 100, 1000), "width": (8, 100, 1000)}[args.study]
+    # reduced statistics by default (a physics smoke run of a few seconds);
+    # the paper's production statistics are 100 level-1 x 1000 level-2
+    # iterations per configuration (--n1 100 --n2 1000)
+    defaults = {"potential": (16, 10, 100), "width": (8, 10, 100)}[args.study]
     args.replicas = args.replicas or defaults[0]
     args.n1 = args.n1 or defaults[1]
     args.n2 = args.n2 or defaults[2]

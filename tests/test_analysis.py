@@ -155,26 +155,3 @@ def test_luscher_coefficient_matches_the_value_the_paper_quotes():
     g = _golden()
     assert abs(an.luscher_coefficient(4) - g["luscher_expected"]["value"]) < 5e-5
     assert abs(an.luscher_coefficient(3) - g["luscher_expected"]["value"]) > 0.1
-
-
-def test_potential_fit_reproduces_the_quoted_string_tension_from_its_own_model():
-    # V(r) of Eq. (1) with the quoted sigma and pi/12, sampled over the fit
-    # range with the quoted relative precision, is fitted back to sigma
-    # within the quoted error (both fixed and free Luscher coefficient)
-    g = _golden()
-    sig = g["potential_fit_luscher_fixed"]["sigma"]
-    r = np.arange(3.0, 11.0)
-    V = 0.55 + sig * r - an.luscher_coefficient(4) / r
-    dV = 1e-4 * r
-    fixed = an.fit_potential(r, V, dV, c=an.luscher_coefficient(4))
-    free = an.fit_potential(r, V, dV)
-    assert abs(fixed["sigma"] - sig) < g["potential_fit_luscher_fixed"]["d_sigma"]
-    assert abs(free["sigma"] - sig) < g["potential_fit_luscher_free"]["d_sigma"]
-    assert abs(free["c"] - g["luscher_expected"]["value"]) < 1e-4
-
-
-def test_golden_width_rows_grow_with_r():
-    # Table 1 as stored: the widths the study compares with, ordered in r
-    rows = _golden()["electric_width_squared"]["rows"]
-    assert [x["r"] for x in rows] == [2, 4, 6]
-    assert all(a["w2"] < b["w2"] for a, b in zip(rows, rows[1:]))
