@@ -151,6 +151,7 @@ struct MLState {
   DevBuf fls, fbuf, fout, scratch;
   size_t scratch_elems = 0;
   bool replay = false;        // two-pass run, one outer iteration stored
+  bool tavg_from_fold = false;  // every inner fold of the run stored the field inner averages
   bool store_field = true;    // ml_sample stores the field slab sums
   DevBuf links_backup, pass_backup;
   // shape of the last completed run (r lists, field separations, operator set)
@@ -766,13 +767,20 @@ struct Engine {
         }
         Table* t;
         U1_TRY(table(rows, 1, &t));
+        // two levels with the field stored: the fold also writes the inner
+        // averages of the field separations of this outer iteration
+        const int tavg_m = (m.field && m.store_field && !m.replay && m.n_levels == 2 && parent == 0)
+                               ? sample_base / m.n[child]
+                               : -1;
         U1_TRY(fam_begin(kFamFold));
         U1_HIP(launch_ml_fold_rows(lats.as<LatDesc>(), m.mls.as<MLDesc>(), bt(t), threads, max_lds, child, parent,
                                    m.n_levels, m.n[child], sample_base, m.rvals.as<int>(), m.mlbuf.as<double2>(),
-                                   m.accbuf.as<double2>(), stream));
+                                   m.accbuf.as<double2>(), m.fls.as<FieldLat>(), m.fp, tavg_m, m.fbuf.as<double>(),
+                                   stream));
         return fam_end(kFamFold);
       }
     }
+    if (child == inner) m.tavg_from_fold = false;
     std::vector<int> it;
     for (int i = 0; i < n_lats; ++i) {
       int nsp = parent == m.n_levels ? 1 : m.h_mls[i].ns[parent];
@@ -831,7 +839,7 @@ struct Engine {
                                    m.h_fls[i], m.fp, h_lats[i].L, m.mlbuf.as<double2>(), m.accbuf.as<double2>(),
                                    m.fbuf.as<double>(), m.scratch.as<double2>(), m.scratch_elems,
                                    m.fout.as<double2>() + m.fout_off[i], field_general, prec == U1ML_FP32, zero_g,
-                                   finalize, ftune, stream));
+                                   finalize, m.tavg_from_fold, ftune, stream));
     return fam_end(kFamField);
   }
 
@@ -895,6 +903,9 @@ struct Engine {
   // full multilevel run, results in ml.corr (and ml.fout)
   int ml_run() {
     MLState& m = *mlp;
+    // the inner folds of a stored two-level field run write the field inner
+    // averages, unless one of them takes the per-site fold (which clears this)
+    m.tavg_from_fold = m.field && !m.replay && m.n_levels == 2;
     U1_HIP(launch_ml_zero(m.accbuf.as<double2>(), m.acc_elems, stream));
     if (m.replay) {
       U1_TRY(ml_run_replay());

@@ -92,9 +92,13 @@ hipError_t launch_ml_fold(const LatDesc* lats, const MLDesc* mls, BlockTable bt,
 // of every lattice; threads = ml_fold_rows_threads(L, n_r) for the largest
 // lattice; lds = children * n_child * max L complex values, twice with
 // multihit (at most ml_fold_rows_max_lds() bytes)
+// tavg_m >= 0: also store the inner averages of the field separations of
+// outer iteration tavg_m into the field buffer (FieldLat::tavg)
+struct FieldParams;
 hipError_t launch_ml_fold_rows(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int threads, size_t lds,
                                int child_level, int parent_level, int n_levels, int n_child, int sample_base,
-                               const int* rvals, const double2* mlbuf, double2* accbuf, hipStream_t st);
+                               const int* rvals, const double2* mlbuf, double2* accbuf, const FieldLat* fls,
+                               const FieldParams& fp, int tavg_m, double* fbuf, hipStream_t st);
 int ml_fold_rows_threads(int L, int n_r);
 size_t ml_fold_rows_max_lds();
 hipError_t launch_ml_zero(double2* accbuf, uint64_t n, hipStream_t st);
@@ -141,13 +145,15 @@ struct FieldTuning {
 };
 // contraction of all stored samples of one lattice into the Fourier-space
 // accumulator (cleared first if zero_g) and, if finalize, into F
+// (tavg_ready: the inner averages of the field separations are in place
+// already, written by the row fold)
 // [n_rf][2][6][L][L] (complex); general = true takes the stored-transform path
 // for any geometry; fp32_store keeps the fast path's per-sample transforms
 // in FP32 between its kernels (FP32 lattices)
 hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,
                                  FieldParams fp, int L, const double2* mlbuf, const double2* accbuf, double* fbuf,
                                  double2* scratch, size_t scratch_elems, double2* F, bool general, bool fp32_store,
-                                 bool zero_g, bool finalize, FieldTuning tune, hipStream_t st);
+                                 bool zero_g, bool finalize, bool tavg_ready, FieldTuning tune, hipStream_t st);
 // the largest x planes per block the W (pairs = false) or O (pairs = true)
 // transform accepts at lattice size L (LDS and block-size limits); 0 when L
 // has no fast path

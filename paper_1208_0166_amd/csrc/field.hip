@@ -835,11 +835,12 @@ FastContract fast_contract_for(int L, bool fp32_store) {
 hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const FieldLat* fl, const FieldLat& hfl,
                                  FieldParams fp, int L, const double2* mlbuf, const double2* accbuf, double* fbuf,
                                  double2* scratch, size_t scratch_elems, double2* F, bool general, bool fp32_store,
-                                 bool zero_g, bool finalize, FieldTuning tune, hipStream_t st) {
+                                 bool zero_g, bool finalize, bool tavg_ready, FieldTuning tune, hipStream_t st) {
   const uint64_t L3 = (uint64_t)L * L * L, L2 = (uint64_t)L * L;
   const int ns = hfl.ns;
   const uint64_t nt = (uint64_t)fp.n_stored * ns * L3 * fp.n_rf;
-  hipLaunchKernelGGL(field_tavg_kernel, dim3(blocks_for(nt, 256)), dim3(256), 0, st, lat, ml, fl, fp, mlbuf, fbuf);
+  if (!tavg_ready)
+    hipLaunchKernelGGL(field_tavg_kernel, dim3(blocks_for(nt, 256)), dim3(256), 0, st, lat, ml, fl, fp, mlbuf, fbuf);
   hipLaunchKernelGGL(field_ptop_kernel, dim3(blocks_for((uint64_t)hfl.n_top * L3, 256)), dim3(256), 0, st, lat, ml,
                      fl, fp, accbuf, fbuf);
   hipLaunchKernelGGL(field_weights_kernel, dim3(blocks_for(nt, 256)), dim3(256), 0, st, lat, fl, fp, fbuf);

@@ -224,13 +224,18 @@ __global__ void ml_sample_kernel(const R* __restrict__ links, const LatDesc* __r
   st.y = (x3 / d.L) % d.L;
   st.z = x3 / (d.L * d.L);
   // exp(i l), l = sum of theta_0 over the slab's times: the slab product of U_0
-  const double l = time_line(links, d, x3, s * inner_th, inner_th);
+  double l = 0.0;
   double o[6] = {0, 0, 0, 0, 0, 0};
   if (FIELD) {
+    // the slab's six plaquettes per time from sixteen loads per site
     for (int t = s * inner_th; t < (s + 1) * inner_th; ++t) {
-      st.t = t;
-      add_field_ops<SQ>(links, d, st, o);
+      SiteLinks<R> sl;
+      load_site_links(links, d, t, st.x, st.y, st.z, sl);
+      l += (double)sl.at[0];
+      add_field_ops_loaded<SQ>(sl, o);
     }
+  } else {
+    l = time_line(links, d, x3, s * inner_th, inner_th);
   }
   store_stream(mlbuf + m->ell + at, cexpi(l));
   if (m->multihit) {
@@ -339,10 +344,16 @@ __global__ __launch_bounds__(256) void ml_fold_kernel(const LatDesc* __restrict_
 // z are strided by L and L^2.
 constexpr int kFoldK = 8;
 constexpr size_t kFoldLds = 49152;  // bytes of staged rows per block
+// With tavg_m >= 0 (two-level runs with the field inserted) the x rows also
+// store the inner averages of the field separations, tavg[((tavg_m n_rf + f)
+// ns + s) L3 + x0] (the inputs of the field weights), so that the field
+// contraction need not average the stored samples again.
 __global__ __launch_bounds__(256) void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls,
                                     const int2* __restrict__ blocks, int child_level, int parent_level, int n_levels,
                                     int n_child, int sample_base, const int* __restrict__ rvals,
-                                    const double2* __restrict__ mlbuf, double2* __restrict__ accbuf) {
+                                    const double2* __restrict__ mlbuf, double2* __restrict__ accbuf,
+                                    const FieldLat* __restrict__ fls, FieldParams fp, int tavg_m,
+                                    double* __restrict__ fbuf) {
   extern __shared__ double2 rowbuf[];  // [children][n_child][L]
   // neighbouring rows (adjacent in memory) on one XCD, so that its L2 and
   // memory requests see contiguous stretches of the time lines
@@ -403,6 +414,21 @@ __global__ __launch_bounds__(256) void ml_fold_rows_kernel(const LatDesc* __rest
       mh[j] = multihit && r >= 2;
       prod[j] = make_double2(1.0, 0.0);
     }
+    // field separation of each slot (or -1) when the x rows store the field
+    // inner averages (uniform per block)
+    const bool tavg_on = tavg_m >= 0 && axis == 0;
+    int fslot[kFoldK];
+    double2* tv = nullptr;
+#pragma unroll
+    for (int j = 0; j < kFoldK; ++j) fslot[j] = -1;
+    if (tavg_on) {
+      tv = (double2*)(fbuf + fls[bk.x].tavg) + (size_t)tavg_m * fp.n_rf * ns_child * d.L3;
+      for (int f = 0; f < fp.n_rf; ++f) {
+#pragma unroll
+        for (int j = 0; j < kFoldK; ++j)
+          if (j < kn && fp.rf_k[f] == k0 + j) fslot[j] = f;
+      }
+    }
     for (int c = 0; c < children; ++c) {
       const double2* ep = rowbuf + c * per_child;
       const double2* eh = ep + (multihit ? staged : 0);
@@ -423,6 +449,15 @@ __global__ __launch_bounds__(256) void ml_fold_rows_kernel(const LatDesc* __rest
       }
 #pragma unroll
       for (int j = 0; j < kFoldK; ++j) prod[j] = cmul(prod[j], make_double2(avg[j].x * inv, avg[j].y * inv));
+      if (tavg_on) {
+        // streamed: read back only by the field weights after the run
+        const int s = S * children + c;
+#pragma unroll
+        for (int j = 0; j < kFoldK; ++j)
+          if (fslot[j] >= 0)
+            store_stream(tv + ((size_t)fslot[j] * ns_child + s) * d.L3 + base + x0,
+                         make_double2(avg[j].x * inv, avg[j].y * inv));
+      }
     }
     double2* pp = accbuf + acc_parent + ((size_t)S * d.L3 + (size_t)base + (size_t)x0 * stride) * nR + axis * n_r + k0;
     // the accumulators are read together (clamped) before the updates
@@ -582,10 +617,11 @@ hipError_t launch_ml_fold(const LatDesc* lats, const MLDesc* mls, BlockTable bt,
 
 hipError_t launch_ml_fold_rows(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int threads, size_t lds,
                                int child_level, int parent_level, int n_levels, int n_child, int sample_base,
-                               const int* rvals, const double2* mlbuf, double2* accbuf, hipStream_t st) {
+                               const int* rvals, const double2* mlbuf, double2* accbuf, const FieldLat* fls,
+                               const FieldParams& fp, int tavg_m, double* fbuf, hipStream_t st) {
   if (bt.n_blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(ml_fold_rows_kernel, dim3(bt.n_blocks), dim3(threads), lds, st, lats, mls, bt.dev, child_level,
-                     parent_level, n_levels, n_child, sample_base, rvals, mlbuf, accbuf);
+                     parent_level, n_levels, n_child, sample_base, rvals, mlbuf, accbuf, fls, fp, tavg_m, fbuf);
   return hipGetLastError();
 }
 

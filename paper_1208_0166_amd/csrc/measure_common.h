@@ -111,6 +111,75 @@ __device__ __forceinline__ void add_field_ops(const R* links, const LatDesc& d, 
   o[5] += plaq_op<SQ>(links, d, st, 1, 2);
 }
 
+// The links the six plaquettes at one site read, each loaded once: the four
+// links theta_mu(s) of the site and the twelve links theta_a(s + b) (a != b)
+// of its four forward neighbours.  Site indices come from one natural index
+// and the periodic forward displacements (not recomputed per plaquette).
+template <typename R>
+struct SiteLinks {
+  R at[4];      // at[mu] = theta_mu(s)
+  R fwd[4][4];  // fwd[b][a] = theta_a(s + b), a != b
+};
+
+template <typename R>
+__device__ __forceinline__ void load_site_links(const R* links, const LatDesc& d, int t, int x, int y, int z,
+                                                SiteLinks<R>& sl) {
+  const uint32_t L = (uint32_t)d.L, L2 = L * L, L3 = (uint32_t)d.L3;
+  const uint32_t n = (((uint32_t)t * L + (uint32_t)z) * L + (uint32_t)y) * L + (uint32_t)x;
+  const int p = (t + x + y + z) & 1;
+  const uint64_t V2 = (uint64_t)d.V2;
+  const R* base = links + d.off;
+  // natural index of the forward neighbour along b (t, x, y, z), periodic
+  const uint32_t nb[4] = {t == d.T - 1 ? n - (uint32_t)(d.T - 1) * L3 : n + L3,
+                          x == d.L - 1 ? n - (L - 1) : n + 1,
+                          y == d.L - 1 ? n - (L - 1) * L : n + L,
+                          z == d.L - 1 ? n - (L - 1) * L2 : n + L2};
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) sl.at[mu] = base[(uint64_t)(2 * mu + p) * V2 + (n >> 1)];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      if (a != b) sl.fwd[b][a] = base[(uint64_t)(2 * a + (p ^ 1)) * V2 + (nb[b] >> 1)];
+  }
+}
+
+// insertion operator of the plaquette (mu, nu) from the loaded links, in the
+// arithmetic of plaq_op (FP64 with the library sine; FP32 with the hardware
+// sine, returned as FP64), before the prefactor
+template <bool SQ>
+__device__ __forceinline__ double plaq_op_loaded(const SiteLinks<double>& sl, int mu, int nu) {
+  const double a = ((sl.at[mu] + sl.fwd[mu][nu]) - sl.fwd[nu][mu]) - sl.at[nu];
+  if (SQ) {
+    const double h = sin(0.5 * a);
+    return 2.0 * (h * h);
+  }
+  return sin(a);
+}
+template <bool SQ>
+__device__ __forceinline__ double plaq_op_loaded(const SiteLinks<float>& sl, int mu, int nu) {
+  const float th = ((sl.at[mu] + sl.fwd[mu][nu]) - sl.fwd[nu][mu]) - sl.at[nu];
+  if (SQ) {
+    const float h = __sinf(0.5f * th);
+    return (double)(2.0f * (h * h));
+  }
+  return (double)__sinf(th);
+}
+
+// add_field_ops from the loaded links (same components, order and signs)
+template <bool SQ, typename R>
+__device__ __forceinline__ void add_field_ops_loaded(const SiteLinks<R>& sl, double o[6]) {
+  o[0] += plaq_op_loaded<SQ>(sl, 0, 1);
+  o[1] += plaq_op_loaded<SQ>(sl, 0, 2);
+  o[2] += plaq_op_loaded<SQ>(sl, 0, 3);
+  o[3] += plaq_op_loaded<SQ>(sl, 2, 3);
+  if (SQ)
+    o[4] += plaq_op_loaded<SQ>(sl, 1, 3);
+  else
+    o[4] -= plaq_op_loaded<SQ>(sl, 1, 3);
+  o[5] += plaq_op_loaded<SQ>(sl, 1, 2);
+}
+
 // sum_t theta_0 over [t0, t0 + nt) at spatial site x3
 template <typename R>
 __device__ __forceinline__ double time_line(const R* links, const LatDesc& d, int x3, int t0, int nt) {
