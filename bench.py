@@ -59,9 +59,9 @@ TUNE_N_SUB = [1, 2]  # multilevel shape the autotuner times
 COPY_ELEMS = 1 << 27  # calibration copy: 512 MiB read, 512 MiB written
 
 
-def chain_updates_per_step():
+def chain_updates_per_step(n_between=N_BETWEEN):
     V = L ** 3 * T
-    sweeps = N_BETWEEN * 4 * (4 * V)            # 4 passes (1 Metropolis + 3 OR) over 4V links
+    sweeps = n_between * 4 * (4 * V)            # 4 passes (1 Metropolis + 3 OR) over 4V links
     free1 = 4 * V - (T // LEVELS[0]) * 3 * L ** 3
     free2 = 4 * V - (T // LEVELS[1]) * 3 * L ** 3
     ml = N_SUB[0] * 4 * free1 + N_SUB[0] * N_SUB[1] * 4 * free2
@@ -149,7 +149,7 @@ def cpu_baseline(seconds: float):
 
 
 def run_chain(u1ml, torch, prec, R, rf, steps, warmup, n_streams=1, multihit=False, squared=False, symmetric=False,
-              tune=True):
+              tune=True, n_between=N_BETWEEN):
     """Build R independent 24^4 chains split into n_streams groups (one batch,
     or one lattice, per group, each on a stream of its own), thermalise, and
     time `steps` steps; the groups' launches overlap on the GPU.  Returns a
@@ -193,7 +193,7 @@ def run_chain(u1ml, torch, prec, R, rf, steps, warmup, n_streams=1, multihit=Fal
     def launch(gr, ev=None):
         if ev:
             ev[0].record(gr["st"])
-        for _ in range(N_BETWEEN):
+        for _ in range(n_between):
             gr["sw"]()
         if ev:
             ev[1].record(gr["st"])
@@ -226,12 +226,12 @@ def run_chain(u1ml, torch, prec, R, rf, steps, warmup, n_streams=1, multihit=Fal
     el = time.perf_counter() - t0
     ms_sweeps = sum(e[0][0].elapsed_time(e[0][1]) for e in evs) / steps  # group 0
     ms_ml = sum(e[0][1].elapsed_time(e[0][2]) for e in evs) / steps
-    up_sw, up_ml = chain_updates_per_step()
+    up_sw, up_ml = chain_updates_per_step(n_between)
     n0 = groups[0]["n"]
     return {"groups": groups, "el": el, "ms_step": 1e3 * el / steps, "ms_sweeps": ms_sweeps, "ms_ml": ms_ml,
             "updates_per_s": R * (up_sw + up_ml) * steps / el,
             "samples_per_s": R * samples_per_step() * steps / el,
-            "group0_sweep_updates_per_s": n0 * up_sw / (ms_sweeps * 1e-3),
+            "group0_sweep_updates_per_s": n0 * up_sw / (ms_sweeps * 1e-3) if ms_sweeps > 0 else None,
             "group0_ml_updates_per_s": n0 * up_ml / (ms_ml * 1e-3),
             "group0_ml_samples_per_s": n0 * samples_per_step() / (ms_ml * 1e-3),
             "obs": obs, "corr": corr, "tuning": tuning}
@@ -293,6 +293,15 @@ def roofline_entry(u1ml, prec, R, ms, n_sweeps, steps, iso, tuning, traffic):
             "cache_resident": batch_bytes <= INFINITY_CACHE_BYTES,
             "isolated_event_us": {"metropolis": iso[0], "or": iso[1]},
             "algorithmic_bytes_per_launch": bytes_per_launch, "tuning": tuning}
+
+
+def main_tuning(tune, out):
+    """The launch shapes the main run used (its autotuner's choice), for legs of the same shape."""
+    if isinstance(tune, dict):
+        return tune
+    if tune and out.get("tuning"):
+        return out["tuning"]
+    return tune
 
 
 def copy_bandwidth(torch, n_bytes=2 << 30, reps=5):
@@ -628,6 +637,18 @@ def main():
     }
     del main_run
     if not args.no_extra:
+        # the multilevel measurement alone (no sweeps between configurations):
+        # the samples/s of the two-level run itself
+        progress("multilevel-only leg")
+        ml_run = run_chain(u1ml, torch, prec, R, rf, args.steps, 1, args.streams, args.multihit, args.squared,
+                           args.symmetric, tune=main_tuning(tune, out), n_between=0)
+        out["multilevel_only"] = {
+            "workload": f"{R} chains, each step one two-level multilevel {{4,2}} x {{10,20}} per chain, r=1..12, "
+                        f"field at r={rf}, no sweeps between",
+            "samples_per_s": ml_run["samples_per_s"], "updates_per_s": ml_run["updates_per_s"],
+            "ms_per_step": ml_run["ms_step"],
+            "step_roofline_frac": ml_run["updates_per_s"] / (HBM_PEAK_GBS * 1e9 / (WORDS_PER_UPDATE * bw))}
+        del ml_run
         progress("cache-spilling roofline leg")
         ms_sp, iso_sp, tun_sp = roofline_leg(u1ml, torch, prec, SPILL_REPLICAS, 3, tune=tune)
         out["roofline_spilled"] = roofline_entry(u1ml, prec, SPILL_REPLICAS, ms_sp, N_BETWEEN, 3, iso_sp, tun_sp,
