@@ -328,10 +328,11 @@ def precision_leg():
     """FP32 sweeps / FP64 accumulation against the FP64 path on the benchmark's
     workload (24^4, beta = 1, multilevel {4,2} x {10,20}): 8 chains per
     precision, 3 configurations 50 sweeps apart after 200 thermalisation
-    sweeps; relative deviation and its size in combined jackknife errors."""
+    sweeps; relative deviation and its size in combined jackknife errors, for
+    the plaquette, |P|, C_ML(r = 1..4) and the E_x insertion at r = 2."""
     from paper_1208_0166_amd import precision
     rows = precision.compare(L=L, beta=BETA, n_chains=8, n_therm=N_THERM, n_configs=3, n_between=50,
-                             levels=tuple(LEVELS), n_sub=tuple(N_SUB), r_list=(1, 2, 3, 4), seed0=2000)
+                             levels=tuple(LEVELS), n_sub=tuple(N_SUB), r_list=(1, 2, 3, 4), seed0=2000, rf=2)
     return {"chains_per_precision": 8, "configurations_per_chain": 3,
             "observables": {r["name"]: {"rel_dev": r["rel_dev"], "sigmas": r["sigmas"], "rel_err": r["rel_err"],
                                         "fp32": r["fp32"], "fp64": r["fp64"]} for r in rows}}

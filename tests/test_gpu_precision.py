@@ -4,8 +4,9 @@ tie bit for bit to the oracle.  Both run the same protocol (cold start,
 thermalisation, then configurations separated by sweeps, each measured by a
 two-level multilevel run, Sec. 2.2), so every observable has one expectation;
 the test asserts agreement within 3 sigma (jackknife over independent chains)
-for the plaquette, |P| and the multilevel correlator <P*(0) P(r)> at r = 1..4,
-and prints the relative deviation of each."""
+for the plaquette, |P|, the multilevel correlator <P*(0) P(r)> at r = 1..4 and
+the E_x insertion at r = 2 (Eq. (9): the FP32 path's field sums carry FP32
+sines), and prints the relative deviation of each."""
 import sys
 
 import numpy as np
@@ -24,7 +25,7 @@ def say(*a):
 def test_fp32_vs_fp64_at_24_beta1_within_3_sigma():
     say("[gpu] 24^4 beta=1: 16 FP32 and 16 FP64 chains, 6 configurations each, multilevel {4,2} x {10,20}")
     rows = precision.compare(L=24, beta=1.0, n_chains=16, n_therm=200, n_configs=6, n_between=50,
-                             levels=(4, 2), n_sub=(10, 20), r_list=(1, 2, 3, 4), seed0=2000,
+                             levels=(4, 2), n_sub=(10, 20), r_list=(1, 2, 3, 4), seed0=2000, rf=2,
                              on_config=lambda name, k: say(f"  {name} configuration {k} done"))
     for row in rows:
         say(f"  {row['name']:>12}: fp32 {row['fp32'][0]:.6e} +- {row['fp32'][1]:.1e}  "
@@ -39,3 +40,7 @@ def test_fp32_vs_fp64_at_24_beta1_within_3_sigma():
     assert 0 < c[0] < 1e-3 and c[1] < c[0]
     # plaquette and |P| are resolved to better than 1 % relative
     assert by["plaquette"]["rel_err"] < 1e-2 and np.isfinite(by["poly_abs"]["rel_err"])
+    # the E_x flux through the mediator plane is resolved (its sign fixed by
+    # the charges): the comparison is not vacuous
+    flux = by["Im E_x(r=2, plane sum)"]
+    assert abs(flux["fp64"][0]) > 3 * flux["fp64"][1]
