@@ -304,24 +304,15 @@ def main_tuning(tune, out):
     return tune
 
 
-def copy_bandwidth(torch, n_bytes=2 << 30, reps=5):
-    """A plain device-to-device copy of n_bytes (read + write counted), timed
-    with HIP events: the bandwidth a streaming kernel reaches on this GPU."""
-    src = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    st = torch.cuda.current_stream()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(st)
-    for _ in range(reps):
-        dst.copy_(src)
-    b.record(st)
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / reps
-    del src, dst
-    return {"bytes_moved": 2 * n_bytes, "GB_per_s": 2 * n_bytes / (ms * 1e-3) / 1e9, "frac_of_peak":
-            2 * n_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+def stream_bandwidth(u1ml, n_bytes=2 << 30, cached_bytes=192 << 20, reps=5):
+    """Reference streaming rates of this GPU from the library's plain
+    grid-stride kernels of 16-byte accesses, timed with HIP events: a read of
+    n_bytes (HBM), a read of cached_bytes repeated (small enough to stay in the
+    256 MB Infinity Cache), and a copy of n_bytes (read + write counted)."""
+    return {"read_GB_per_s": u1ml.stream_bandwidth("read", n_bytes, reps),
+            "read_cache_resident_GB_per_s": u1ml.stream_bandwidth("read", cached_bytes, 4 * reps),
+            "copy_GB_per_s": u1ml.stream_bandwidth("copy", n_bytes, reps),
+            "bytes": {"read": n_bytes, "read_cache_resident": cached_bytes, "copy": 2 * n_bytes}}
 
 
 def precision_leg():
@@ -654,8 +645,11 @@ def main():
         ms_sp, iso_sp, tun_sp = roofline_leg(u1ml, torch, prec, SPILL_REPLICAS, 3, tune=tune)
         out["roofline_spilled"] = roofline_entry(u1ml, prec, SPILL_REPLICAS, ms_sp, N_BETWEEN, 3, iso_sp, tun_sp,
                                                  traffic_from_profiles(kname, SPILL_REPLICAS, bw))
-        progress("copy bandwidth")
-        out["device_copy"] = copy_bandwidth(torch)
+        progress("streaming references")
+        out["device_stream"] = stream_bandwidth(u1ml)
+        cp = out["device_stream"]
+        out["roofline"]["frac_of_cache_resident_read"] = out["roofline"]["achieved"] / cp["read_cache_resident_GB_per_s"]
+        out["roofline_spilled"]["frac_of_hbm_read"] = out["roofline_spilled"]["achieved"] / cp["read_GB_per_s"]
         progress("precision split")
         out["precision_split"] = precision_leg()
         progress("uneven batch")

@@ -388,6 +388,17 @@ int u1ml_profile_sweeps(u1ml_lattice *lat, int n_sweeps, int n_metro, int n_or, 
 /* The same for a batch (one class-pass kernel covers every lattice). */
 int u1ml_batch_profile_sweeps(u1ml_batch *b, int n_sweeps, int n_metro, int n_or, double *avg_us);
 
+/* Streaming bandwidth of the current device measured with plain grid-stride
+ * kernels of 16-byte accesses (context for the roofline fractions of the
+ * update kernels; not part of the method): kind 0 reads n_bytes (a buffer
+ * larger than the 256 MB Infinity Cache streams HBM, a smaller one is served
+ * by the cache once warm), kind 1 copies n_bytes (bytes read plus bytes
+ * written counted).  One warm-up launch, then reps launches timed with HIP
+ * events; *gb_per_s receives GB/s.  Allocates and frees its own buffers on a
+ * stream of its own.  EINVAL unless kind is 0 or 1, n_bytes >= 1 MiB and a
+ * multiple of 16, reps >= 1; ENOMEM, EDEVICE. */
+int u1ml_stream_bandwidth(int kind, size_t n_bytes, int reps, double *gb_per_s);
+
 /* Text for an error code. */
 const char *u1ml_strerror(int code);
 /* Message of the most recent failure on this thread ("" if none). */

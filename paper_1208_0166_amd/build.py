@@ -25,6 +25,7 @@ SOURCES = {
     "sweep_f32.hip": [],
     "measure.hip": [],
     "field.hip": [],
+    "probe.hip": [],
     "abi.cpp": ["-x", "hip"],
 }
 

@@ -1975,6 +1975,41 @@ int u1ml_batch_profile_sweeps(u1ml_batch* b, int n_sweeps, int n_metro, int n_or
   return profile_sweeps(b->e, n_sweeps, n_metro, n_or, avg_us);
 }
 
+int u1ml_stream_bandwidth(int kind, size_t n_bytes, int reps, double* gb_per_s) {
+  if ((kind != 0 && kind != 1) || n_bytes < (1u << 20) || n_bytes % 16 || reps < 1 || !gb_per_s)
+    return fail(U1ML_EINVAL, "stream_bandwidth: kind 0 or 1, n_bytes >= 1 MiB and a multiple of 16, reps >= 1");
+  *gb_per_s = 0.0;
+  // 8 blocks of 256 threads per compute unit in grid-stride loops
+  constexpr int kBlocks = 2048;
+  DevBuf a, b, sink;
+  U1_TRY(a.ensure(n_bytes));
+  if (kind == 1) U1_TRY(b.ensure(n_bytes));
+  U1_TRY(sink.ensure(sizeof(float)));
+  hipStream_t st;
+  U1_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  // zeros in the source: the read kernel's guarded store never happens
+  if (e == hipSuccess) e = launch_stream_probe(2, nullptr, a.p, n_bytes, nullptr, kBlocks, st);
+  if (e == hipSuccess) e = launch_stream_probe(kind, a.p, b.p, n_bytes, sink.as<float>(), kBlocks, st);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  for (int k = 0; k < reps && e == hipSuccess; ++k)
+    e = launch_stream_probe(kind, a.p, b.p, n_bytes, sink.as<float>(), kBlocks, st);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  (void)hipStreamDestroy(st);
+  U1_HIP(e);
+  if (!(ms > 0.f)) return fail(U1ML_EDEVICE, "stream_bandwidth: no elapsed time");
+  *gb_per_s = (double)reps * (double)n_bytes * (kind == 1 ? 2.0 : 1.0) / (ms * 1e-3) / 1e9;
+  return U1ML_OK;
+}
+
 const char* u1ml_strerror(int code) {
   switch (code) {
     case U1ML_OK: return "success";

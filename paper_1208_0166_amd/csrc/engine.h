@@ -159,4 +159,9 @@ hipError_t launch_field_contract(const LatDesc* lat, const MLDesc* ml, const Fie
 // has no fast path
 int field_max_planes(int L, bool pairs);
 
+// streaming probe (probe.hip): kind 0 reads n_bytes of a (16-byte loads),
+// kind 1 copies a to b, kind 2 zeroes b; grid-stride over `blocks` blocks of 256
+hipError_t launch_stream_probe(int kind, const void* a, void* b, size_t n_bytes, float* sink, int blocks,
+                               hipStream_t st);
+
 }  // namespace u1ml

@@ -125,6 +125,7 @@ def load_library(path: str = LIB_PATH):
         "u1ml_batch_autotune": (I, [P, I, ip, ip, I, ip, I, ip, C.POINTER(Tuning)]),
         "u1ml_profile_sweeps": (I, [P, I, I, I, dp]),
         "u1ml_batch_profile_sweeps": (I, [P, I, I, I, dp]),
+        "u1ml_stream_bandwidth": (I, [I, SZ, I, dp]),
         "u1ml_strerror": (C.c_char_p, [I]),
         "u1ml_last_error": (C.c_char_p, []),
     }
@@ -429,6 +430,14 @@ def batch_autotune(b, slab_sizes=(), n_sub=(), r_list=(), rf_list=()) -> dict:
                                               rp if len(r_list) else None, len(rf_list),
                                               rfp if len(rf_list) else None, C.byref(t)))
     return t.as_dict()
+
+
+def stream_bandwidth(kind: str, n_bytes: int, reps: int = 5) -> float:
+    """u1ml_stream_bandwidth: GB/s of a plain read ("read") or copy ("copy") stream."""
+    out = C.c_double()
+    _check(load_library().u1ml_stream_bandwidth({"read": 0, "copy": 1}[kind], int(n_bytes), int(reps),
+                                                C.byref(out)))
+    return float(out.value)
 
 
 def profile_sweeps(lat: Lattice, n_sweeps: int, n_metro: int = 1, n_or: int = 3):

@@ -112,3 +112,12 @@ def test_hit_count_out_of_range_rejected(n_metro, n_or):
     for call in calls:
         assert call() == u1ml.EINVAL
         assert b"n_metro" in lib.u1ml_last_error()
+
+
+def test_stream_bandwidth_arguments_checked():
+    # the bandwidth probe refuses bad arguments before touching the device
+    lib = u1ml.load_library()
+    out = C.c_double()
+    for kind, n, reps in ((2, 1 << 24, 1), (-1, 1 << 24, 1), (0, 1 << 10, 1), (0, (1 << 24) + 8, 1), (1, 1 << 24, 0)):
+        assert lib.u1ml_stream_bandwidth(kind, n, reps, C.byref(out)) == u1ml.EINVAL
+    assert lib.u1ml_stream_bandwidth(0, 1 << 24, 1, None) == u1ml.EINVAL
