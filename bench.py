@@ -149,11 +149,16 @@ def cpu_baseline(seconds: float):
 
 
 def run_chain(u1ml, torch, prec, R, rf, steps, warmup, n_streams=1, multihit=False, squared=False, symmetric=False,
-              tune=True, n_between=N_BETWEEN):
+              tune=True, n_between=N_BETWEEN, pipeline=True):
     """Build R independent 24^4 chains split into n_streams groups (one batch,
     or one lattice, per group, each on a stream of its own), thermalise, and
-    time `steps` steps; the groups' launches overlap on the GPU.  Returns a
-    dict of timings and the last results of group 0."""
+    time `steps` steps; the groups' launches overlap on the GPU.  With
+    pipeline, a step queues every group's sweeps before it reads the previous
+    step's results of each group and queues that group's multilevel run, so
+    that no stream idles at the step boundary; every step's results are read
+    inside the timed region, and the plain observables are then those of the
+    links after the next step's sweeps.  Returns a dict of timings and the
+    last results of group 0."""
     sizes = [R // n_streams + (1 if g < R % n_streams else 0) for g in range(n_streams)]
     sizes = [n for n in sizes if n > 0]
     groups = []
@@ -190,19 +195,25 @@ def run_chain(u1ml, torch, prec, R, rf, steps, warmup, n_streams=1, multihit=Fal
             gr["sw"]()
     torch.cuda.synchronize()
 
-    def launch(gr, ev=None):
+    def queue_sweeps(gr, ev=None):
         if ev:
             ev[0].record(gr["st"])
         for _ in range(n_between):
             gr["sw"]()
         if ev:
             ev[1].record(gr["st"])
+
+    def queue_ml(gr, ev=None):
         if gr["n"] == 1:
             u1ml.multilevel(gr["lat"], LEVELS, N_SUB, 1, 3, R_LIST, rf_list=rf)
         else:
             u1ml.batch_multilevel(gr["lat"], LEVELS, N_SUB, 1, 3, R_LIST, rf_list=rf)
         if ev:
             ev[2].record(gr["st"])
+
+    def launch(gr, ev=None):
+        queue_sweeps(gr, ev)
+        queue_ml(gr, ev)
 
     def results(gr):
         if gr["n"] == 1:
@@ -215,13 +226,39 @@ def run_chain(u1ml, torch, prec, R, rf, steps, warmup, n_streams=1, multihit=Fal
         res = [results(gr) for gr in groups]
         return res[0][0]
 
-    for _ in range(warmup):
-        step()
+    def pipelined_step(read_prev, evs=None):
+        # every group's sweeps first; then per group: the previous step's
+        # results (waits for that group's stream), and this step's multilevel
+        for g, gr in enumerate(groups):
+            queue_sweeps(gr, evs[g] if evs else None)
+        first = None
+        for g, gr in enumerate(groups):
+            if read_prev:
+                r = results(gr)
+                first = first or r[0]
+            queue_ml(gr, evs[g] if evs else None)
+        return first
+
+    def drain():
+        return [results(gr) for gr in groups][0][0]
+
+    for w in range(warmup):
+        if pipeline:
+            pipelined_step(w > 0)
+        else:
+            step()
+    if pipeline and warmup:
+        drain()
     torch.cuda.synchronize()
     evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in groups] for _ in range(steps)]
     t0 = time.perf_counter()
     for k in range(steps):
-        obs, corr, field = step(evs[k])
+        if pipeline:
+            pipelined_step(k > 0, evs[k])
+        else:
+            obs, corr, field = step(evs[k])
+    if pipeline:
+        obs, corr, field = drain()  # the last step's results
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms_sweeps = sum(e[0][0].elapsed_time(e[0][1]) for e in evs) / steps  # group 0
@@ -517,6 +554,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the cache-spilling roofline, copy, precision, uneven and 48^4 legs")
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes instead of the autotuner's")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="read every step's results before the next step is queued (the streams drain per step)")
     ap.add_argument("--tuning", default=None,
                     help="JSON object of launch shapes (u1ml_tuning fields) applied to every batch instead of "
                          "running the autotuner (reproducible profiles)")
@@ -569,7 +608,7 @@ def main():
 
     progress("main run")
     main_run = run_chain(u1ml, torch, prec, R, rf, args.steps, args.warmup, args.streams, args.multihit,
-                         args.squared, args.symmetric, tune=tune)
+                         args.squared, args.symmetric, tune=tune, pipeline=not args.no_pipeline)
 
     # dominant kernel: the class pass (Metropolis or OR, 9 words per update),
     # timed alone on one stream: N_BETWEEN compound sweeps of 4 x 8 class passes
@@ -605,7 +644,8 @@ def main():
                                "r=1..12, E/B mid-plane profiles at r=2,4,6",
                    "lattice": [L, L, L, T], "beta": BETA, "levels": LEVELS, "n_sub": N_SUB,
                    "r": [1, 12], "field_r": rf, "accumulate": "f64", "replicas": R, "streams": args.streams,
-                   "multihit": args.multihit, "field_squared": args.squared, "symmetric": args.symmetric},
+                   "multihit": args.multihit, "field_squared": args.squared, "symmetric": args.symmetric,
+                   "pipelined_steps": not args.no_pipeline},
         "samples_per_s": main_run["samples_per_s"],
         "samples_per_step": samples_per_step() * R,
         # complete two-level multilevel estimates (one per chain per step)
@@ -633,7 +673,7 @@ def main():
         # the samples/s of the two-level run itself
         progress("multilevel-only leg")
         ml_run = run_chain(u1ml, torch, prec, R, rf, args.steps, 1, args.streams, args.multihit, args.squared,
-                           args.symmetric, tune=main_tuning(tune, out), n_between=0)
+                           args.symmetric, tune=main_tuning(tune, out), n_between=0, pipeline=not args.no_pipeline)
         out["multilevel_only"] = {
             "workload": f"{R} chains, each step one two-level multilevel {{4,2}} x {{10,20}} per chain, r=1..12, "
                         f"field at r={rf}, no sweeps between",
