@@ -50,7 +50,9 @@ __global__ void field_ptop_kernel(const LatDesc* __restrict__ lat, const MLDesc*
   const int ntop = fl.n_top;
   const int item = blockIdx.x * blockDim.x + threadIdx.x;
   if (item >= ntop * d.L3) return;
-  const int x0 = item % d.L3, k = item / d.L3;
+  // site-major: the n_top threads of one site read the same accumulator
+  // lines, which the caches then serve
+  const int k = item % ntop, x0 = item / ntop;
   const double inv = 1.0 / (double)fp.n_outer;
   double2* out = (double2*)(fbuf + fl.ptop);
   for (int f = 0; f < fp.n_rf; ++f) {

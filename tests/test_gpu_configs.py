@@ -113,3 +113,47 @@ def test_large_48_identity_fp32():
         got = np.array([f[k, p, :, dy, dz] for p, dy, dz in points])
         assert np.abs(got - ref).max() <= 2e-5 * scale, (r, np.abs(got - ref).max(), scale)
     assert math.isfinite(obs["plaquette"])
+
+
+def test_64_uneven_instances_fp32_agree_with_fp64_statistically():
+    # the batched FP32 form against its FP64 twin: both batches of the 64 sizes
+    # and couplings from a cold start, 200 sweeps, then 20 captured cycles (2
+    # sweeps + single-level multilevel, slabs of 2, 10 updates, r = 1..L/2).
+    # Lattice i of one batch and lattice i of the other are independent chains
+    # of the same law, so their difference d_i of the cycle averages (plaquette,
+    # Re C(1)) has mean zero.  Per (L, beta) group a t-test on the d_i (their
+    # spread gives the error), and Fisher's combination of the group p-values
+    # over all groups must not reject at 1e-3.
+    from scipy import stats
+    Ls, betas, seeds = uneven_instances()
+    say("[gpu] 64 instances FP32 vs FP64, 20 cycles each")
+    avg = {}
+    for prec in (u1ml.FP32, u1ml.FP64):
+        b = u1ml.batch_create(Ls, Ls, betas, seeds, start=u1ml.COLD, precision=prec)
+        for _ in range(200):
+            u1ml.batch_sweep(b, 1, 3)
+        acc = np.zeros((64, 2))
+        for _ in range(20):
+            u1ml.batch_cycle(b, 2, 1, 3, 2, 10, use_graph=True)
+            for i in range(64):
+                obs, c, _ = u1ml.batch_measure(b, i)
+                acc[i] += [obs["plaquette"], c[0].real]
+        avg[prec] = acc / 20
+        b.close()
+    d = avg[u1ml.FP32] - avg[u1ml.FP64]
+    groups = {}
+    for i, key in enumerate(zip(Ls, betas)):
+        groups.setdefault(key, []).append(i)
+    for j, name in enumerate(("plaquette", "C(1)")):
+        pvals = []
+        for key, idx in sorted(groups.items()):
+            if len(idx) < 2:
+                continue
+            x = d[idx, j]
+            t = x.mean() / (x.std(ddof=1) / np.sqrt(len(x)))
+            pvals.append(2 * stats.t.sf(abs(t), len(x) - 1))
+        chi2 = -2 * np.sum(np.log(pvals))
+        p = stats.chi2.sf(chi2, 2 * len(pvals))
+        say(f"  {name}: {len(pvals)} groups, Fisher chi2 {chi2:.1f} on {2 * len(pvals)} dof, p = {p:.3f}; "
+            f"mean |relative deviation| {np.mean(np.abs(d[:, j] / avg[u1ml.FP64][:, j])):.2e}")
+        assert p > 1e-3, (name, p)
