@@ -96,3 +96,14 @@ def test_tuning_values_are_checked():
     # class passes only (no multilevel shape)
     best = u1ml.batch_autotune(b)
     assert best["pass_block"] in (64, 128, 256, 512, 1024)
+
+
+def test_stream_bandwidth_probe():
+    # the streaming references of the bench: a read of more than the Infinity
+    # Cache, a cache-sized read and a copy give positive rates below the
+    # nameplate 8 TB/s (with headroom for the cache)
+    rd = u1ml.stream_bandwidth("read", 1 << 30, 3)
+    rc = u1ml.stream_bandwidth("read", 64 << 20, 10)
+    cp = u1ml.stream_bandwidth("copy", 1 << 30, 3)
+    say(f"  read {rd:.0f}, cache-sized read {rc:.0f}, copy {cp:.0f} GB/s")
+    assert 1000 < rd < 8500 and 1000 < cp < 8500 and 1000 < rc < 20000

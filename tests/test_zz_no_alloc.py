@@ -90,6 +90,24 @@ def test_noalloc_at_the_benchmark_shape_and_repeated():
     np.testing.assert_array_equal(c.cpu().numpy()[0::2] + 1j * c.cpu().numpy()[1::2], c_ref)
 
 
+@pytest.mark.parametrize("flags", [dict(multihit=True), dict(symmetric=True), dict(multihit=True, symmetric=True)])
+def test_noalloc_with_estimator_options(flags):
+    # the lattice's estimator flags apply to the allocation-free run as well:
+    # multihit lines (twice the stored lines) and the correlator over +-x, +-y, +-z
+    say(f"[gpu] noalloc with {flags}")
+    a, b = twin(8, u1ml.FP64, 61)
+    for g in (a, b):
+        u1ml.set_estimator(g, **flags)
+    r_list = [1, 2, 3]
+    u1ml.multilevel(a, [4, 2], [2, 3], 1, 3, r_list)
+    _, c_ref, _ = u1ml.measure(a, observables=False, correlator=True)
+    out = torch.empty(2 * len(r_list), dtype=torch.float64, device="cuda")
+    assert call_noalloc(b, [4, 2], [2, 3], r_list, out) == 0
+    got = out.cpu().numpy()
+    np.testing.assert_array_equal(got[0::2] + 1j * got[1::2], c_ref)
+    np.testing.assert_array_equal(u1ml.get_links(b), u1ml.get_links(a))
+
+
 def test_noalloc_refuses_runs_beyond_the_static_array():
     lib = u1ml.load_library()
     g = u1ml.init_lattice(24, 24, 1.0, 3, precision=u1ml.FP32)
