@@ -750,13 +750,20 @@ struct Engine {
     MLState& m = *mlp;
     const int inner = m.n_levels - 1;
     if (child == inner && !fold_general) {
-      int threads = 64;
+      int threads = 64, max_nr = 1;
       size_t max_lds = 0;
+      const bool multihit = m.h_mls[0].multihit != 0;
+      for (int i = 0; i < n_lats; ++i) {
+        max_nr = std::max(max_nr, m.h_mls[i].n_r);
+        if ((m.h_mls[i].multihit != 0) != multihit) return fail(U1ML_EINVAL, "mixed estimators in one run");
+      }
+      const int k_slots = ml_fold_rows_k(max_nr);
       for (int i = 0; i < n_lats; ++i) {
         const int nsp = parent == m.n_levels ? 1 : m.h_mls[i].ns[parent];
         const int children = m.h_mls[i].ns[child] / nsp;
-        threads = std::max(threads, fold_threads > 0 ? fold_threads : ml_fold_rows_threads(h_lats[i].L, m.h_mls[i].n_r));
-        max_lds = std::max(max_lds, (size_t)(m.h_mls[i].multihit ? 2 : 1) * children * m.n[child] * h_lats[i].L *
+        threads = std::max(threads, fold_threads > 0 ? fold_threads
+                                                     : ml_fold_rows_threads(h_lats[i].L, m.h_mls[i].n_r, k_slots));
+        max_lds = std::max(max_lds, (size_t)(multihit ? 2 : 1) * children * m.n[child] * h_lats[i].L *
                                         sizeof(double2));
       }
       if (max_lds <= ml_fold_rows_max_lds()) {
@@ -773,8 +780,8 @@ struct Engine {
                                ? sample_base / m.n[child]
                                : -1;
         U1_TRY(fam_begin(kFamFold));
-        U1_HIP(launch_ml_fold_rows(lats.as<LatDesc>(), m.mls.as<MLDesc>(), bt(t), threads, max_lds, child, parent,
-                                   m.n_levels, m.n[child], sample_base, m.rvals.as<int>(), m.mlbuf.as<double2>(),
+        U1_HIP(launch_ml_fold_rows(lats.as<LatDesc>(), m.mls.as<MLDesc>(), bt(t), threads, max_lds, k_slots,
+                                   multihit, child, parent, m.n_levels, m.n[child], sample_base, m.rvals.as<int>(), m.mlbuf.as<double2>(),
                                    m.accbuf.as<double2>(), m.fls.as<FieldLat>(), m.fp, tavg_m, m.fbuf.as<double>(),
                                    stream));
         return fam_end(kFamFold);

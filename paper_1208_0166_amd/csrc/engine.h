@@ -89,17 +89,21 @@ hipError_t launch_ml_fold(const LatDesc* lats, const MLDesc* mls, BlockTable bt,
                           int n_levels, int child_is_inner, int n_child, int sample_base, const int* rvals,
                           const double2* mlbuf, double2* accbuf, hipStream_t st);
 // the innermost fold by rows: bt has one block per (parent slab, axis, row)
-// of every lattice; threads = ml_fold_rows_threads(L, n_r) for the largest
+// of every lattice; k_slots = ml_fold_rows_k(largest n_r) separations per
+// thread; threads = ml_fold_rows_threads(L, n_r, k_slots) for the largest
 // lattice; lds = children * n_child * max L complex values, twice with
-// multihit (at most ml_fold_rows_max_lds() bytes)
+// multihit (at most ml_fold_rows_max_lds() bytes); multihit: the run's
+// estimator (the same for every lattice of a run)
 // tavg_m >= 0: also store the inner averages of the field separations of
 // outer iteration tavg_m into the field buffer (FieldLat::tavg)
 struct FieldParams;
 hipError_t launch_ml_fold_rows(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int threads, size_t lds,
-                               int child_level, int parent_level, int n_levels, int n_child, int sample_base,
-                               const int* rvals, const double2* mlbuf, double2* accbuf, const FieldLat* fls,
-                               const FieldParams& fp, int tavg_m, double* fbuf, hipStream_t st);
-int ml_fold_rows_threads(int L, int n_r);
+                               int k_slots, bool multihit, int child_level, int parent_level, int n_levels,
+                               int n_child, int sample_base, const int* rvals, const double2* mlbuf,
+                               double2* accbuf, const FieldLat* fls, const FieldParams& fp, int tavg_m, double* fbuf,
+                               hipStream_t st);
+int ml_fold_rows_k(int max_n_r);
+int ml_fold_rows_threads(int L, int n_r, int k_slots);
 size_t ml_fold_rows_max_lds();
 hipError_t launch_ml_zero(double2* accbuf, uint64_t n, hipStream_t st);
 hipError_t launch_ml_final(const LatDesc* lats, const MLDesc* mls, int n_lats, int max_r, int top_level,

@@ -337,24 +337,27 @@ __global__ __launch_bounds__(256) void ml_fold_kernel(const LatDesc* __restrict_
 // row along a): the rows of all stored samples of all children of S are
 // staged in LDS at once (children * n_child * L values, twice with multihit),
 // so every time line is read from memory once instead of once per
-// separation.  A thread owns one position j along the row and up to kFoldK
-// separations of the axis, so the line at j is read once per sample for all
-// of them; the sample and child order of every sum is that of ml_fold_kernel,
-// so both give the same bits.  Rows along x are contiguous; rows along y and
-// z are strided by L and L^2.
-constexpr int kFoldK = 8;
+// separation.  A thread owns one position j along the row and K separations
+// of the axis (K = 4, 6 or 8, chosen per launch so that the groups of K
+// cover the separations with the fewest unused slots), so the line at j is
+// read once per sample for all of them; the sample and child order of every
+// sum is that of ml_fold_kernel, so both give the same bits.  MH: the run
+// uses the multihit lines (known per launch, so that the plain run reads
+// each line once).  Rows along x are contiguous; rows along y and z are
+// strided by L and L^2.
 constexpr size_t kFoldLds = 49152;  // bytes of staged rows per block
 // With tavg_m >= 0 (two-level runs with the field inserted) the x rows also
 // store the inner averages of the field separations, tavg[((tavg_m n_rf + f)
 // ns + s) L3 + x0] (the inputs of the field weights), so that the field
 // contraction need not average the stored samples again.
+template <int K, bool MH>
 __global__ __launch_bounds__(256) void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls,
                                     const int2* __restrict__ blocks, int child_level, int parent_level, int n_levels,
                                     int n_child, int sample_base, const int* __restrict__ rvals,
                                     const double2* __restrict__ mlbuf, double2* __restrict__ accbuf,
                                     const FieldLat* __restrict__ fls, FieldParams fp, int tavg_m,
                                     double* __restrict__ fbuf) {
-  extern __shared__ double2 rowbuf[];  // [children][n_child][L]
+  extern __shared__ double2 rowbuf[];  // [children][n_child][L] (then the multihit rows)
   // neighbouring rows (adjacent in memory) on one XCD, so that its L2 and
   // memory requests see contiguous stretches of the time lines
   const int2 bk = blocks[xcd_block(blockIdx.x, gridDim.x)];
@@ -365,7 +368,7 @@ __global__ __launch_bounds__(256) void ml_fold_rows_kernel(const LatDesc* __rest
   const int L = d.L, L2 = L * L;
   const int ns_child = mp->ns[child_level];
   const int ns_parent = parent_level == n_levels ? 1 : mp->ns[parent_level];
-  const int nR = mp->nR, n_r = mp->n_r, n_axes = mp->n_axes, r_off = mp->r_off, multihit = mp->multihit;
+  const int nR = mp->nR, n_r = mp->n_r, n_axes = mp->n_axes, r_off = mp->r_off;
   const uint64_t ell = mp->ell, ell_mh = mp->ell_mh, acc_parent = mp->acc[parent_level];
   const int children = ns_child / ns_parent;
   const int S = bk.y / (n_axes * L2), rem = bk.y - S * n_axes * L2;
@@ -374,13 +377,13 @@ __global__ __launch_bounds__(256) void ml_fold_rows_kernel(const LatDesc* __rest
   const int ra = row % L, rb = row / L;
   const int stride = axis == 0 ? 1 : (axis == 1 ? L : L2);
   const int base = axis == 0 ? row * L : (axis == 1 ? rb * L2 + ra : rb * L + ra);
-  const int ngroups = (n_r + kFoldK - 1) / kFoldK;
+  const int ngroups = (n_r + K - 1) / K;
   const int per_child = n_child * L;
   // rows of the plain lines, then (multihit) rows of the multihit lines
   // The loads of kFoldLd values are issued together, unconditionally (the
   // index is clamped: past the end, the last value is loaded and stored again
   // in its own place), so that no branch or wait separates them.
-  const int staged = children * per_child, n_st = (multihit ? 2 : 1) * staged;
+  const int staged = children * per_child, n_st = (MH ? 2 : 1) * staged;
   constexpr int kFoldLd = 16;
   for (int e0 = threadIdx.x; e0 < n_st; e0 += kFoldLd * (int)blockDim.x) {
     double2 v[kFoldLd];
@@ -398,62 +401,63 @@ __global__ __launch_bounds__(256) void ml_fold_rows_kernel(const LatDesc* __rest
   __syncthreads();
   const double inv = 1.0 / (double)n_child;
   for (int item = threadIdx.x; item < L * ngroups; item += blockDim.x) {
-    const int x0 = item / ngroups, k0 = (item - x0 * ngroups) * kFoldK;
-    const int kn = min(kFoldK, n_r - k0);
-    int xr[kFoldK];
-    bool mh[kFoldK];
-    double2 prod[kFoldK];
+    const int x0 = item / ngroups, k0 = (item - x0 * ngroups) * K;
+    const int kn = min(K, n_r - k0);
+    int xr[K];
+    bool mh[K];
+    double2 prod[K];
 #pragma unroll
-    for (int j = 0; j < kFoldK; ++j) {
+    for (int j = 0; j < K; ++j) {
       // separations past the group's last are read clamped and never used
       const int rv = rvals[r_off + axis * n_r + min(k0 + j, n_r - 1)];
       const int r = j < kn ? rv & 0xffff : 0;
       const int t = x0 + r;
       xr[j] = t >= L ? t - L : t;
       // multihit lines for r >= 2 (the two lines share no plaquette)
-      mh[j] = multihit && r >= 2;
+      mh[j] = MH && r >= 2;
       prod[j] = make_double2(1.0, 0.0);
     }
     // field separation of each slot (or -1) when the x rows store the field
     // inner averages (uniform per block)
     const bool tavg_on = tavg_m >= 0 && axis == 0;
-    int fslot[kFoldK];
+    int fslot[K];
     double2* tv = nullptr;
 #pragma unroll
-    for (int j = 0; j < kFoldK; ++j) fslot[j] = -1;
+    for (int j = 0; j < K; ++j) fslot[j] = -1;
     if (tavg_on) {
       tv = (double2*)(fbuf + fls[bk.x].tavg) + (size_t)tavg_m * fp.n_rf * ns_child * d.L3;
       for (int f = 0; f < fp.n_rf; ++f) {
 #pragma unroll
-        for (int j = 0; j < kFoldK; ++j)
+        for (int j = 0; j < K; ++j)
           if (j < kn && fp.rf_k[f] == k0 + j) fslot[j] = f;
       }
     }
     for (int c = 0; c < children; ++c) {
       const double2* ep = rowbuf + c * per_child;
-      const double2* eh = ep + (multihit ? staged : 0);
-      double2 avg[kFoldK];
+      double2 avg[K];
 #pragma unroll
-      for (int j = 0; j < kFoldK; ++j) avg[j] = make_double2(0.0, 0.0);
-      // every lane sums all kFoldK slots (those past the group's last take
-      // r = 0 and are never stored), so that no branch splits the wavefront
+      for (int j = 0; j < K; ++j) avg[j] = make_double2(0.0, 0.0);
+      // every lane sums all K slots (those past the group's last take r = 0
+      // and are never stored), so that no branch splits the wavefront
 #pragma unroll 2
       for (int i = 0; i < n_child; ++i) {
-        const double2 u = ep[i * L + x0], uh = eh[i * L + x0];
+        const double2 u = ep[i * L + x0];
+        double2 uh = u;
+        if (MH) uh = ep[staged + i * L + x0];
 #pragma unroll
-        for (int j = 0; j < kFoldK; ++j) {
-          const double2 a = mh[j] ? uh : u, v = (mh[j] ? eh : ep)[i * L + xr[j]];
+        for (int j = 0; j < K; ++j) {
+          const double2 a = mh[j] ? uh : u, v = ep[(mh[j] ? staged : 0) + i * L + xr[j]];
           avg[j].x += a.x * v.x + a.y * v.y;
           avg[j].y += a.x * v.y - a.y * v.x;
         }
       }
 #pragma unroll
-      for (int j = 0; j < kFoldK; ++j) prod[j] = cmul(prod[j], make_double2(avg[j].x * inv, avg[j].y * inv));
+      for (int j = 0; j < K; ++j) prod[j] = cmul(prod[j], make_double2(avg[j].x * inv, avg[j].y * inv));
       if (tavg_on) {
         // streamed: read back only by the field weights after the run
         const int s = S * children + c;
 #pragma unroll
-        for (int j = 0; j < kFoldK; ++j)
+        for (int j = 0; j < K; ++j)
           if (fslot[j] >= 0)
             store_stream(tv + ((size_t)fslot[j] * ns_child + s) * d.L3 + base + x0,
                          make_double2(avg[j].x * inv, avg[j].y * inv));
@@ -461,11 +465,11 @@ __global__ __launch_bounds__(256) void ml_fold_rows_kernel(const LatDesc* __rest
     }
     double2* pp = accbuf + acc_parent + ((size_t)S * d.L3 + (size_t)base + (size_t)x0 * stride) * nR + axis * n_r + k0;
     // the accumulators are read together (clamped) before the updates
-    double2 old[kFoldK];
+    double2 old[K];
 #pragma unroll
-    for (int j = 0; j < kFoldK; ++j) old[j] = pp[min(j, kn - 1)];
+    for (int j = 0; j < K; ++j) old[j] = pp[min(j, kn - 1)];
 #pragma unroll
-    for (int j = 0; j < kFoldK; ++j)
+    for (int j = 0; j < K; ++j)
       if (j < kn) pp[j] = make_double2(old[j].x + prod[j].x, old[j].y + prod[j].y);
   }
 }
@@ -615,18 +619,51 @@ hipError_t launch_ml_fold(const LatDesc* lats, const MLDesc* mls, BlockTable bt,
   return hipGetLastError();
 }
 
+template <int K>
+void launch_fold_rows_k(bool multihit, BlockTable bt, int threads, size_t lds, const LatDesc* lats,
+                        const MLDesc* mls, int child_level, int parent_level, int n_levels, int n_child,
+                        int sample_base, const int* rvals, const double2* mlbuf, double2* accbuf,
+                        const FieldLat* fls, const FieldParams& fp, int tavg_m, double* fbuf, hipStream_t st) {
+  if (multihit)
+    hipLaunchKernelGGL((ml_fold_rows_kernel<K, true>), dim3(bt.n_blocks), dim3(threads), lds, st, lats, mls, bt.dev,
+                       child_level, parent_level, n_levels, n_child, sample_base, rvals, mlbuf, accbuf, fls, fp,
+                       tavg_m, fbuf);
+  else
+    hipLaunchKernelGGL((ml_fold_rows_kernel<K, false>), dim3(bt.n_blocks), dim3(threads), lds, st, lats, mls, bt.dev,
+                       child_level, parent_level, n_levels, n_child, sample_base, rvals, mlbuf, accbuf, fls, fp,
+                       tavg_m, fbuf);
+}
+
 hipError_t launch_ml_fold_rows(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int threads, size_t lds,
-                               int child_level, int parent_level, int n_levels, int n_child, int sample_base,
-                               const int* rvals, const double2* mlbuf, double2* accbuf, const FieldLat* fls,
-                               const FieldParams& fp, int tavg_m, double* fbuf, hipStream_t st) {
+                               int k_slots, bool multihit, int child_level, int parent_level, int n_levels,
+                               int n_child, int sample_base, const int* rvals, const double2* mlbuf,
+                               double2* accbuf, const FieldLat* fls, const FieldParams& fp, int tavg_m, double* fbuf,
+                               hipStream_t st) {
   if (bt.n_blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(ml_fold_rows_kernel, dim3(bt.n_blocks), dim3(threads), lds, st, lats, mls, bt.dev, child_level,
-                     parent_level, n_levels, n_child, sample_base, rvals, mlbuf, accbuf, fls, fp, tavg_m, fbuf);
+  if (k_slots == 4)
+    launch_fold_rows_k<4>(multihit, bt, threads, lds, lats, mls, child_level, parent_level, n_levels, n_child,
+                          sample_base, rvals, mlbuf, accbuf, fls, fp, tavg_m, fbuf, st);
+  else if (k_slots == 6)
+    launch_fold_rows_k<6>(multihit, bt, threads, lds, lats, mls, child_level, parent_level, n_levels, n_child,
+                          sample_base, rvals, mlbuf, accbuf, fls, fp, tavg_m, fbuf, st);
+  else if (k_slots == 8)
+    launch_fold_rows_k<8>(multihit, bt, threads, lds, lats, mls, child_level, parent_level, n_levels, n_child,
+                          sample_base, rvals, mlbuf, accbuf, fls, fp, tavg_m, fbuf, st);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-int ml_fold_rows_threads(int L, int n_r) {
-  const int items = L * ((n_r + kFoldK - 1) / kFoldK);
+int ml_fold_rows_k(int max_n_r) {
+  // the fewest groups of at most 8, then the smallest K of 4, 6, 8 that
+  // covers the separations in that many groups
+  const int groups = (std::max(max_n_r, 1) + 7) / 8;
+  const int per = (std::max(max_n_r, 1) + groups - 1) / groups;
+  return per <= 4 ? 4 : (per <= 6 ? 6 : 8);
+}
+
+int ml_fold_rows_threads(int L, int n_r, int k_slots) {
+  const int items = L * ((n_r + k_slots - 1) / k_slots);
   return std::min(256, (items + 63) / 64 * 64);
 }
 size_t ml_fold_rows_max_lds() { return kFoldLds; }
