@@ -369,11 +369,14 @@ int u1ml_batch_set_tuning(u1ml_batch *b, const u1ml_tuning *t);
  * at their current values): the class passes' block size (64..1024) and XCD
  * block order over three compound sweeps per candidate (best of two); then,
  * if n_levels > 0, with multilevel runs of the given shape (u1ml_multilevel
- * arguments with n_metro = 1, n_or = 3; pass a small n_sub), the per-sample
- * kernel's block size, the row fold's threads and, with field separations
- * on the fast contraction path, the planes per block of both field
- * transforms and the contraction's threads, each timed over its own launches
- * only.  The links and pass ids are restored; the last multilevel result is
+ * arguments with n_metro = 1, n_or = 3), the per-sample kernel's block
+ * size, the row fold's threads and, with field separations on the fast
+ * contraction path, the planes per block of both field transforms and the
+ * contraction's threads, each timed over its own launches only (best of two
+ * runs per candidate).  The shape should keep as many samples per lattice as
+ * the runs to be tuned contract at once (up to a few tens; fewer samples make
+ * smaller field grids, which favour smaller blocks) while costing a small
+ * n_sub.  The links and pass ids are restored; the last multilevel result is
  * discarded (ESTATE until the next run).  *best (may be NULL) receives the
  * chosen shapes.  Synchronises. */
 int u1ml_batch_autotune(u1ml_batch *b, int n_levels, const int *slab_sizes, const int *n_sub, int n_r,

@@ -48,12 +48,12 @@ def test_fp32_vs_fp64_at_24_beta1_within_3_sigma():
 
 def test_fp32_vs_fp64_at_48_beta1_within_3_sigma():
     # the large-lattice workload (48^4, beta = 1: 85 MB of FP32 links per
-    # chain): 16 chains per precision from the same cold start, a short
-    # thermalisation and two measured configurations, each with a small
-    # two-level run; every observable agrees within 3 sigma
-    say("[gpu] 48^4 beta=1: 16 FP32 and 16 FP64 chains, 2 configurations each, multilevel {4,2} x {2,3}")
+    # chain) with its multilevel shape ({4,2} x {20,10}): 16 chains per
+    # precision from the same cold start, a short thermalisation and two
+    # measured configurations; every observable agrees within 3 sigma
+    say("[gpu] 48^4 beta=1: 16 FP32 and 16 FP64 chains, 2 configurations each, multilevel {4,2} x {20,10}")
     rows = precision.compare(L=48, beta=1.0, n_chains=16, n_therm=100, n_configs=2, n_between=40,
-                             levels=(4, 2), n_sub=(2, 3), r_list=(1, 2), seed0=4000,
+                             levels=(4, 2), n_sub=(20, 10), r_list=(1, 2), seed0=4000,
                              on_config=lambda name, k: say(f"  {name} configuration {k} done"))
     for row in rows:
         say(f"  {row['name']:>12}: fp32 {row['fp32'][0]:.6e} +- {row['fp32'][1]:.1e}  "
@@ -62,6 +62,8 @@ def test_fp32_vs_fp64_at_48_beta1_within_3_sigma():
     for row in rows:
         assert row["sigmas"] < 3.0, row
     by = {r["name"]: r for r in rows}
-    # the plaquette is resolved to better than 0.1 % (the comparison is not vacuous)
+    # the plaquette and C_ML(r = 1) are resolved (the comparison is not vacuous)
     assert by["plaquette"]["rel_err"] < 1e-3
     assert 0.5 < by["plaquette"]["fp64"][0] < 0.65
+    c1 = by["C_ML(r=1)"]
+    assert c1["fp64"][0] > 3 * c1["fp64"][1] and c1["fp32"][0] > 3 * c1["fp32"][1]
