@@ -370,8 +370,11 @@ def precision_leg():
 
 def counters_run(args):
     """Short run for hardware-counter passes: a plain elementwise copy of a known
-    size (the calibration of FETCH_SIZE / WRITE_SIZE), then a few compound
-    sweeps of the benchmark batch."""
+    size (the calibration of FETCH_SIZE / WRITE_SIZE); the library's streaming
+    read of a 1 GiB buffer (HBM) and then of a 64 MiB one (served by the
+    Infinity Cache once warm), the references of the L2-miss read latency
+    (1 + 3 and 1 + 10 dispatches of `stream_read_kernel`, in that order);
+    then a few compound sweeps of the benchmark batch."""
     import torch
     from paper_1208_0166_amd import u1ml
     torch.cuda.set_device(0)
@@ -384,6 +387,8 @@ def counters_run(args):
         torch.neg(src, out=dst)
     torch.cuda.synchronize()
     del src, dst
+    u1ml.stream_bandwidth("read", 1 << 30, 3)
+    u1ml.stream_bandwidth("read", 64 << 20, 10)
     R = args.replicas
     prec = u1ml.FP32 if args.precision == "fp32" else u1ml.FP64
     lat = u1ml.batch_create([L] * R, [T] * R, [BETA] * R, [3 + i for i in range(R)], start=u1ml.COLD,
