@@ -118,6 +118,9 @@ def test_quantised_constant_field(oracle_mod, n_flux):
     assert abs(g.plaquette() - (5 + math.cos(phi)) / 6) < 1e-15
     fm = g.field_means()
     np.testing.assert_allclose(fm, [0, 0, 0, 0, 0, math.sqrt(beta) * math.sin(phi)], atol=1e-14)
+    # Eq. (3): only the V xy plaquettes contribute, each beta (1 - cos phi)
+    V = L ** 3 * T
+    assert abs(g.total_action() - beta * V * (1 - math.cos(phi))) < 1e-11
 
 
 def test_overrelaxation_conserves_action_and_is_involution(oracle_mod):
