@@ -47,6 +47,8 @@ def test_strerror_codes():
     (4, 4, 1.0, 0, float("inf"), 0),
     (4, 4, 1.0, 0, float("nan"), 0),
     (4, 4, 1.0, 0, 1.0, 100),    # block not a multiple of 64
+    (86, 86, 1.0, 1, 1.0, 0),    # V L = 4.7e9: beyond the kernels' 32-bit site arithmetic
+    (86, 84, 1.0, 0, 1.0, 0),    # V L = 4.6e9
 ])
 def test_init_rejects_bad_arguments(L, T, beta, prec, eps, block):
     lib = u1ml.load_library()
