@@ -100,6 +100,38 @@ def test_special_couplings(oracle_mod):
     np.testing.assert_array_equal(u1ml.get_links(g0), th)
 
 
+def test_sweeps_without_metropolis_hits(oracle_mod):
+    # n_metro = 0: no Metropolis pass and no pass id consumed, OR passes only;
+    # n_metro = n_or = 0: nothing changes.  Single lattice, a two-lattice
+    # batch and a multilevel run with OR-only sublattice updates, against
+    # the oracle.
+    L, T = 6, 4
+    o = oracle_mod.OracleLattice(L, T, 1.1, 41, hot=True)
+    g = gpu_lattice(L, T, 1.1, 41)
+    for (nm, no) in [(0, 2), (0, 0), (1, 1), (0, 3), (0, 0)]:
+        th = u1ml.get_links(g)
+        o.sweep(nm, no)
+        u1ml.sweep(g, nm, no)
+        np.testing.assert_array_equal(u1ml.get_links(g), o.get_links(), err_msg=f"sweep ({nm}, {no})")
+        assert u1ml.get_pass_id(g) == o.pass_id
+        if nm == 0 and no == 0:
+            np.testing.assert_array_equal(u1ml.get_links(g), th)
+    assert o.pass_id == 1
+    c_o, _, _ = o.multilevel([2], [3], 0, 1, r_list=(1, 2, 3))
+    u1ml.multilevel(g, [2], [3], 0, 1, [1, 2, 3])
+    _, c_g, _ = u1ml.measure(g, correlator=True)
+    np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
+    np.testing.assert_allclose(c_g, c_o, rtol=0, atol=1e-12 * np.abs(c_o).max())
+    b = u1ml.batch_create([6, 4], [4, 6], [1.1, 0.9], [41, 42], precision=u1ml.FP64)
+    ob = [oracle_mod.OracleLattice(6, 4, 1.1, 41, hot=True), oracle_mod.OracleLattice(4, 6, 0.9, 42, hot=True)]
+    for (nm, no) in [(0, 2), (0, 0), (2, 1)]:
+        u1ml.batch_sweep(b, nm, no)
+        for i, oi in enumerate(ob):
+            oi.sweep(nm, no)
+            np.testing.assert_array_equal(u1ml.batch_get_links(b, i), oi.get_links(), err_msg=f"lattice {i}")
+    b.close()
+
+
 def test_cold_start_and_set_links_roundtrip(oracle_mod):
     L, T = 4, 6
     g = gpu_lattice(L, T, 1.0, 9, start=u1ml.COLD)
