@@ -51,20 +51,17 @@ def test_64_uneven_instances_fp64_match_oracle(oracle_mod):
     # the FP64 twin of the uneven batch: the same 64 sizes and couplings in one
     # batch, hot start, one sweep, then two measurement cycles (one sweep plus
     # the single-level multilevel with slabs of 2 and 10 updates, r = 1..L/2),
-    # the second replayed from the captured graph.  One lattice of every
-    # (L, beta) pair present is followed by the oracle through the same
-    # sequence: links bit-identical and C_ML(r) to 1e-12.
+    # the second replayed from the captured graph.  Every lattice is followed
+    # by the oracle through the same sequence: links bit-identical and C_ML(r)
+    # to 1e-12.
     Ls, betas, seeds = uneven_instances()
-    say("[gpu] 64 instances FP64 vs oracle, every (L, beta) present")
+    say("[gpu] 64 instances FP64 vs oracle, every lattice")
     b = u1ml.batch_create(Ls, Ls, betas, seeds, start=u1ml.HOT, precision=u1ml.FP64)
     u1ml.batch_sweep(b, 1, 3)
     u1ml.batch_cycle(b, 1, 1, 3, 2, 10, use_graph=True)
     u1ml.batch_cycle(b, 1, 1, 3, 2, 10, use_graph=True)
-    picks = {}
+    assert sorted(set(Ls)) == [8, 12, 16, 20, 24] and len({(L, be) for L, be in zip(Ls, betas)}) == 15
     for i, (L, be) in enumerate(zip(Ls, betas)):
-        picks.setdefault((L, be), i)
-    assert sorted({L for L, _ in picks}) == [8, 12, 16, 20, 24]
-    for (L, be), i in sorted(picks.items()):
         say(f"  lattice {i}: L={L} beta={be}")
         o = oracle_mod.OracleLattice(L, L, be, seeds[i], hot=True)
         o.sweep(1, 3)
