@@ -518,23 +518,26 @@ def test_field_size_and_separation_limits():
             assert np.abs(f[0][plane, :, dy, dz] - want).max() <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("n_sub", [[2, 3], [10, 20]])
 @pytest.mark.parametrize("prec_fold", ["rows", "general"])
-def test_full_size_24_two_level_several_samples_match_oracle(oracle_mod, prec_fold):
+def test_full_size_24_two_level_several_samples_match_oracle(oracle_mod, prec_fold, n_sub):
     # the benchmark's shape at 24^4 (levels {4, 2}, r = 1..12) with several
     # updates per level, so that every level average is over more than one
-    # sample: FP64 links bit-identical to the oracle and C_ML(r) to 1e-12,
-    # with the row-staged fold of the inner averages and with the per-site one
+    # sample, up to the benchmark's own {10, 20} (the row fold then stages 20
+    # samples of both children per row): FP64 links bit-identical to the
+    # oracle and C_ML(r) to 1e-12, with the row-staged fold of the inner
+    # averages and with the per-site one
     L = T = 24
     r_list = list(range(1, 13))
-    say(f"[gpu] 24^4 FP64 two-level {{4,2}} x {{2,3}} r=1..12 vs oracle, fold={prec_fold}")
+    say(f"[gpu] 24^4 FP64 two-level {{4,2}} x {n_sub} r=1..12 vs oracle, fold={prec_fold}")
     o = oracle_mod.OracleLattice(L, T, 1.0, 31, hot=True)
     g = u1ml.init_lattice(L, T, 1.0, 31)
     if prec_fold == "general":
         u1ml.set_debug(g, 4)
     o.sweep(1, 3)
     u1ml.sweep(g, 1, 3)
-    c_o, _, _ = o.multilevel([4, 2], [2, 3], 1, 3, r_list)
-    u1ml.multilevel(g, [4, 2], [2, 3], 1, 3, r_list)
+    c_o, _, _ = o.multilevel([4, 2], n_sub, 1, 3, r_list)
+    u1ml.multilevel(g, [4, 2], n_sub, 1, 3, r_list)
     obs, c_g, _ = u1ml.measure(g, correlator=True)
     np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
     np.testing.assert_allclose(c_g, c_o, rtol=1e-12, atol=0)
