@@ -112,6 +112,40 @@ def test_large_48_identity_fp32():
     assert math.isfinite(obs["plaquette"])
 
 
+def test_bench_batch_shape_identity_fp32():
+    # the benchmark's launch configuration: a batch of 24^4 FP32 lattices with
+    # its tuned shapes (class pass 256 threads, XCD-contiguous; transforms of
+    # 4 planes per block; contraction 128 threads) through the two-level run
+    # with the field at r = 2, 4, 6, one update per level: every lattice's
+    # C_ML(r), r = 1..12, equals the plain correlator of its final links and
+    # its field the plain Eq. (9) definition at sampled offsets
+    L = T = 24
+    n = 3
+    say(f"[gpu] batch of {n} x 24^4 FP32 with the bench's shapes, one-update identity")
+    b = u1ml.batch_create([L] * n, [T] * n, [1.0] * n, [61 + i for i in range(n)], precision=u1ml.FP32,
+                          start=u1ml.COLD)
+    u1ml.set_tuning(b, pass_block=256, pass_xcd_map=1, sample_block=256, fold_threads=64, field_w_planes=4,
+                    field_o_planes=4, field_zcon_threads=128)
+    for _ in range(3):
+        u1ml.batch_sweep(b, 1, 3)
+    rl = list(range(1, 13))
+    u1ml.batch_multilevel(b, [4, 2], [1, 1], 1, 3, rl, rf_list=[2, 4, 6])
+    rng = np.random.default_rng(12)
+    points = [(int(p), int(a), int(c)) for p, a, c in zip(rng.integers(0, 2, 8), rng.integers(0, L, 8),
+                                                       rng.integers(0, L, 8))]
+    points += [(0, 0, 0), (1, 0, 0)]
+    for i in range(n):
+        _, c, f = u1ml.batch_measure(b, i, correlator=True, field_profile=True)
+        th = u1ml.batch_get_links(b, i)
+        np.testing.assert_allclose(c, [plain_corr(th, r) for r in rl], rtol=0, atol=1e-12)
+        scale = np.abs(f).max()
+        for k, r in enumerate([2, 4, 6]):
+            ref = field_points(th, 1.0, r, points)
+            got = np.array([f[k, p, :, dy, dz] for p, dy, dz in points])
+            assert np.abs(got - ref).max() <= 2e-5 * scale, (i, r, np.abs(got - ref).max(), scale)
+    b.close()
+
+
 def test_64_uneven_instances_fp32_agree_with_fp64_statistically():
     # the batched FP32 form against its FP64 twin: both batches of the 64 sizes
     # and couplings from a cold start, 200 sweeps, then 20 captured cycles (2
