@@ -682,8 +682,13 @@ def main():
         # the whole step against the same bound: every link update at 9 words
         # per update and the HBM peak (the field contraction, folds and
         # time-line sums are work on top of the updates, not counted as updates)
+        # samples come with the updates of their step, so the samples/s at
+        # the same bound is the step's samples over the time of its updates
+        # at peak, and their fraction equals the updates' fraction
         "step_roofline": {"updates_per_s_at_peak": HBM_PEAK_GBS * 1e9 / (WORDS_PER_UPDATE * bw),
-                          "frac": main_run["updates_per_s"] / (HBM_PEAK_GBS * 1e9 / (WORDS_PER_UPDATE * bw))},
+                          "frac": main_run["updates_per_s"] / (HBM_PEAK_GBS * 1e9 / (WORDS_PER_UPDATE * bw)),
+                          "samples_per_s_at_peak": samples_per_step() * HBM_PEAK_GBS * 1e9 /
+                                                   (WORDS_PER_UPDATE * bw * sum(chain_updates_per_step()))},
     }
     del main_run
     if not args.no_extra:
@@ -697,7 +702,9 @@ def main():
                         f"field at r={rf}, no sweeps between",
             "samples_per_s": ml_run["samples_per_s"], "updates_per_s": ml_run["updates_per_s"],
             "ms_per_step": ml_run["ms_step"],
-            "step_roofline_frac": ml_run["updates_per_s"] / (HBM_PEAK_GBS * 1e9 / (WORDS_PER_UPDATE * bw))}
+            "step_roofline_frac": ml_run["updates_per_s"] / (HBM_PEAK_GBS * 1e9 / (WORDS_PER_UPDATE * bw)),
+            "samples_per_s_at_peak": samples_per_step() * HBM_PEAK_GBS * 1e9 /
+                                     (WORDS_PER_UPDATE * bw * chain_updates_per_step(0)[1])}
         del ml_run
         progress("cache-spilling roofline leg")
         ms_sp, iso_sp, tun_sp = roofline_leg(u1ml, torch, prec, SPILL_REPLICAS, 3, tune=tune)
