@@ -132,6 +132,28 @@ def test_sweeps_without_metropolis_hits(oracle_mod):
     b.close()
 
 
+@pytest.mark.parametrize("T", [32, 6])
+def test_large_slice_parity(oracle_mod, T):
+    # an FP64 lattice whose time slice of links is 1 MiB (L = 32), square and
+    # with six slices, through a sweep (accept log and links) and a
+    # single-level multilevel run whose spatial passes cover only the
+    # unfrozen slices: links and correlator stay the oracle's
+    L = 32
+    o = oracle_mod.OracleLattice(L, T, 1.0, 71, hot=True)
+    g = gpu_lattice(L, T, 1.0, 71)
+    u1ml.set_debug(g, 1, 1 << 26)
+    lo = o.sweep(1, 3, want_log=True)
+    u1ml.sweep(g, 1, 3)
+    np.testing.assert_array_equal(u1ml.get_accept_log(g)[:lo.size], lo)
+    np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
+    u1ml.set_debug(g, 0)
+    c_o, _, _ = o.multilevel([2], [2], 1, 3, r_list=(1, 2, 16))
+    u1ml.multilevel(g, [2], [2], 1, 3, [1, 2, 16])
+    _, c_g, _ = u1ml.measure(g, correlator=True)
+    np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
+    np.testing.assert_allclose(c_g, c_o, rtol=1e-12, atol=0)
+
+
 def test_cold_start_and_set_links_roundtrip(oracle_mod):
     L, T = 4, 6
     g = gpu_lattice(L, T, 1.0, 9, start=u1ml.COLD)
