@@ -189,17 +189,20 @@ def test_results_independent_of_block_size():
                 np.testing.assert_array_equal(c, ref[prec][1])
 
 
-def test_checkpoint_resume_bit_exact(tmp_path):
+@pytest.mark.parametrize("prec", [u1ml.FP64, u1ml.FP32])
+def test_checkpoint_resume_bit_exact(tmp_path, prec):
+    # the checkpoint holds the links as FP64 (exact for FP32 links) and the
+    # pass id, so a resumed chain continues with the same random numbers
     L, T = 6, 6
-    a = gpu_lattice(L, T, 1.0, 31)
+    a = gpu_lattice(L, T, 1.0, 31, prec=prec)
     for _ in range(6):
         u1ml.sweep(a, 1, 2)
-    b = gpu_lattice(L, T, 1.0, 31)
+    b = gpu_lattice(L, T, 1.0, 31, prec=prec)
     for _ in range(2):
         u1ml.sweep(b, 1, 2)
     path = str(tmp_path / "ck.bin")
     u1ml.save(b, path)
-    c = gpu_lattice(L, T, 0.5, 999, start=u1ml.COLD)
+    c = gpu_lattice(L, T, 0.5, 999, prec=prec, start=u1ml.COLD)
     u1ml.load(c, path)
     assert u1ml.get_pass_id(c) == 2
     for _ in range(4):
