@@ -546,3 +546,25 @@ def test_full_size_24_two_level_several_samples_match_oracle(oracle_mod, prec_fo
     # one-update identity); at r = 1 both are of the same order
     plain = o.plain_correlator([1])[0]
     assert abs(c_g[0] - plain) > 1e-6 * abs(plain)
+
+
+@pytest.mark.parametrize("symmetric", [False, True])
+def test_full_size_24_multihit_several_samples_match_oracle(oracle_mod, symmetric):
+    # the benchmark's shape at 24^4 (levels {4, 2}, r = 1..12, so the row fold
+    # takes six separations per thread and the multihit lines) with the
+    # analytical multihit estimator, alone and with the correlator averaged
+    # over +-x, +-y, +-z: FP64 links bit-identical to the oracle, C_ML(r) to
+    # 1e-12 of its largest entry
+    L = T = 24
+    r_list = list(range(1, 13))
+    say(f"[gpu] 24^4 FP64 two-level {{4,2}} x {{2,3}} multihit symmetric={symmetric} vs oracle")
+    o = oracle_mod.OracleLattice(L, T, 1.0, 33, hot=True)
+    g = u1ml.init_lattice(L, T, 1.0, 33)
+    u1ml.set_estimator(g, multihit=True, symmetric=symmetric)
+    o.sweep(1, 3)
+    u1ml.sweep(g, 1, 3)
+    c_o, _, _ = o.multilevel([4, 2], [2, 3], 1, 3, r_list, multihit=True, symmetric=symmetric)
+    u1ml.multilevel(g, [4, 2], [2, 3], 1, 3, r_list)
+    _, c_g, _ = u1ml.measure(g, observables=False, correlator=True)
+    np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
+    close_rel(c_g, c_o)
