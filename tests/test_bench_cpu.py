@@ -59,3 +59,15 @@ def test_counter_summary_matches_the_class_pass_sources():
         assert t is not None, R
         algo = R * bench.L ** 3 * bench.T // 2 * bench.WORDS_PER_UPDATE * 4
         assert 1.0 <= t / algo < 1.1
+
+
+def test_samples_at_the_update_roofline():
+    # the samples/s the bench reports at peak: a step's samples over the time
+    # of its updates at 36 B per update and 8 TB/s; the multilevel alone (no
+    # sweeps) gives 7.5e5 samples/s, the full step (100 sweeps per
+    # configuration) 4.3e5
+    peak = bench.HBM_PEAK_GBS * 1e9 / (bench.WORDS_PER_UPDATE * 4)
+    sweeps, ml = bench.chain_updates_per_step()
+    assert bench.chain_updates_per_step(0) == (0, ml)
+    assert abs(bench.samples_per_step() * peak / ml - 7.547e5) < 1e2
+    assert abs(bench.samples_per_step() * peak / (sweeps + ml) - 4.310e5) < 1e2
