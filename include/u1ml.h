@@ -332,6 +332,19 @@ int u1ml_batch_ensemble_add(u1ml_batch *b);
 int u1ml_batch_ensemble_info(u1ml_batch *b, int i, int *n_runs, int *n_r, int *n_rf);
 int u1ml_batch_ensemble_read(u1ml_batch *b, int i, double *correlator, double *field_profile, double *connected);
 int u1ml_batch_set_links(u1ml_batch *b, int i, const double *host);
+/* Pass id of lattice i (the Metropolis-pass counter of its random numbers,
+ * as u1ml_get/set_pass_id).  EINVAL for i outside [0, n). */
+int u1ml_batch_get_pass_id(u1ml_batch *b, int i, uint64_t *pass_id);
+int u1ml_batch_set_pass_id(u1ml_batch *b, int i, uint64_t pass_id);
+/* Checkpoint of a batch: a header line with the number of lattices, then
+ * for every lattice in order the record u1ml_save writes (header line and
+ * FP64 links).  load requires a batch of as many lattices with the same L,
+ * T and precision each, reads and checks every record before changing any
+ * lattice, then restores links, beta, eps, seed and pass id of each, so the
+ * chains continue with the random numbers they would have drawn.  EIO on
+ * file errors, EINVAL on a mismatch (the batch is then unchanged). */
+int u1ml_batch_save(u1ml_batch *b, const char *path);
+int u1ml_batch_load(u1ml_batch *b, const char *path);
 int u1ml_batch_synchronize(u1ml_batch *b);
 void u1ml_batch_destroy(u1ml_batch *b);
 

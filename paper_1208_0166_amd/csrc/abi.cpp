@@ -1521,63 +1521,109 @@ int u1ml_get_accept_log(u1ml_lattice* lat, uint8_t* out, size_t cap, size_t* n_b
   return U1ML_OK;
 }
 
-int u1ml_save(u1ml_lattice* lat, const char* path) {
-  if (!lat || !path) return fail(U1ML_EINVAL, "save arguments");
-  Engine& e = lat->e;
-  const LatDesc& d = e.h_lats[0];
+}  // extern "C"
+
+namespace {
+
+// One lattice's checkpoint record: a text header line (format, L, T, beta,
+// eps, seed, pass id, precision), then its FP64 links in the host order.
+struct Record {
+  double beta = 0.0, eps = 0.0;
+  unsigned long long seed = 0, pass_id = 0;
+  std::vector<double> links;
+};
+
+int write_record(Engine& e, int i, FILE* f) {
+  const LatDesc& d = e.h_lats[i];
   std::vector<double> h(8ull * d.V2);
+  U1_TRY(e.get_links(i, h.data()));
+  if (std::fprintf(f, "u1ml-checkpoint-1 L=%d T=%d beta=%.17g eps=%.17g seed=%llu pass_id=%llu precision=%d\n",
+                   d.L, d.T, d.beta, d.eps, (unsigned long long)d.seed, (unsigned long long)e.h_pass_ids[i],
+                   e.prec) < 0 ||
+      std::fwrite(h.data(), sizeof(double), h.size(), f) != h.size())
+    return fail(U1ML_EIO, "short write");
+  return U1ML_OK;
+}
+
+// reads the record of lattice i and checks it against that lattice; changes nothing
+int read_record(const Engine& e, int i, FILE* f, Record* r) {
+  char line[512];
+  if (!std::fgets(line, sizeof line, f)) return fail(U1ML_EIO, "missing header");
+  int L = 0, T = 0, prec = -1;
+  if (std::sscanf(line, "u1ml-checkpoint-1 L=%d T=%d beta=%lg eps=%lg seed=%llu pass_id=%llu precision=%d", &L, &T,
+                  &r->beta, &r->eps, &r->seed, &r->pass_id, &prec) != 7)
+    return fail(U1ML_EIO, "bad header");
+  const LatDesc& d = e.h_lats[i];
+  if (L != d.L || T != d.T || prec != e.prec)
+    return fail(U1ML_EINVAL, "checkpoint shape or precision differs from the lattice");
+  if (!std::isfinite(r->beta) || r->beta < 0 || !(r->eps >= 0 && r->eps <= kMaxEps))
+    return fail(U1ML_EINVAL, "checkpoint beta or eps out of range");
+  r->links.resize(8ull * d.V2);
+  if (std::fread(r->links.data(), sizeof(double), r->links.size(), f) != r->links.size())
+    return fail(U1ML_EIO, "short read");
+  return U1ML_OK;
+}
+
+// installs checked records for lattices 0..n-1 of the engine
+int apply_records(Engine& e, const std::vector<Record>& rs) {
   U1_TRY(e.set_device());
-  U1_TRY(e.get_links(0, h.data()));
+  for (size_t i = 0; i < rs.size(); ++i) {
+    LatDesc& d = e.h_lats[i];
+    d.beta = rs[i].beta;
+    d.eps = rs[i].eps;
+    d.sqrt_beta = std::sqrt(rs[i].beta);
+    d.seed = rs[i].seed;
+    e.h_pass_ids[i] = rs[i].pass_id;
+  }
+  U1_TRY(e.upload_lats());
+  U1_TRY(e.upload_pass_ids());
+  for (size_t i = 0; i < rs.size(); ++i) U1_TRY(e.set_links((int)i, rs[i].links.data()));
+  return U1ML_OK;
+}
+
+int save_engine(Engine& e, const char* path, bool batch) {
+  U1_TRY(e.set_device());
   FILE* f = std::fopen(path, "wb");
   if (!f) return fail(U1ML_EIO, std::string("cannot open ") + path);
-  std::fprintf(f, "u1ml-checkpoint-1 L=%d T=%d beta=%.17g eps=%.17g seed=%llu pass_id=%llu precision=%d\n", d.L, d.T,
-               d.beta, d.eps, (unsigned long long)d.seed, (unsigned long long)e.h_pass_ids[0], e.prec);
-  size_t w = std::fwrite(h.data(), sizeof(double), h.size(), f);
-  int cl = std::fclose(f);
-  if (w != h.size() || cl != 0) return fail(U1ML_EIO, "short write");
-  return U1ML_OK;
+  int rc = U1ML_OK;
+  if (batch && std::fprintf(f, "u1ml-batch-checkpoint-1 n=%d\n", e.n_lats) < 0) rc = fail(U1ML_EIO, "short write");
+  for (int i = 0; i < e.n_lats && !rc; ++i) rc = write_record(e, i, f);
+  if (std::fclose(f) != 0 && !rc) rc = fail(U1ML_EIO, "short write");
+  return rc;
+}
+
+int load_engine(Engine& e, const char* path, bool batch) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(U1ML_EIO, std::string("cannot open ") + path);
+  int rc = U1ML_OK;
+  if (batch) {
+    char line[128];
+    int n = -1;
+    if (!std::fgets(line, sizeof line, f) || std::sscanf(line, "u1ml-batch-checkpoint-1 n=%d", &n) != 1)
+      rc = fail(U1ML_EIO, "bad batch header");
+    else if (n != e.n_lats)
+      rc = fail(U1ML_EINVAL, "checkpoint holds another number of lattices");
+  }
+  // every record is read and checked before any lattice changes
+  std::vector<Record> rs(e.n_lats);
+  for (int i = 0; i < e.n_lats && !rc; ++i) rc = read_record(e, i, f, &rs[i]);
+  std::fclose(f);
+  if (rc) return rc;
+  return apply_records(e, rs);
+}
+
+}  // namespace
+
+extern "C" {
+
+int u1ml_save(u1ml_lattice* lat, const char* path) {
+  if (!lat || !path) return fail(U1ML_EINVAL, "save arguments");
+  return save_engine(lat->e, path, false);
 }
 
 int u1ml_load(u1ml_lattice* lat, const char* path) {
   if (!lat || !path) return fail(U1ML_EINVAL, "load arguments");
-  Engine& e = lat->e;
-  FILE* f = std::fopen(path, "rb");
-  if (!f) return fail(U1ML_EIO, std::string("cannot open ") + path);
-  char line[512];
-  if (!std::fgets(line, sizeof line, f)) {
-    std::fclose(f);
-    return fail(U1ML_EIO, "missing header");
-  }
-  int L = 0, T = 0, prec = -1;
-  double beta = 0, eps = 0;
-  unsigned long long seed = 0, pid = 0;
-  if (std::sscanf(line, "u1ml-checkpoint-1 L=%d T=%d beta=%lg eps=%lg seed=%llu pass_id=%llu precision=%d", &L, &T,
-                  &beta, &eps, &seed, &pid, &prec) != 7) {
-    std::fclose(f);
-    return fail(U1ML_EIO, "bad header");
-  }
-  LatDesc& d = e.h_lats[0];
-  if (L != d.L || T != d.T || prec != e.prec) {
-    std::fclose(f);
-    return fail(U1ML_EINVAL, "checkpoint shape or precision differs from the lattice");
-  }
-  if (!std::isfinite(beta) || beta < 0 || !(eps >= 0 && eps <= kMaxEps)) {
-    std::fclose(f);
-    return fail(U1ML_EINVAL, "checkpoint beta or eps out of range");
-  }
-  std::vector<double> h(8ull * d.V2);
-  size_t r = std::fread(h.data(), sizeof(double), h.size(), f);
-  std::fclose(f);
-  if (r != h.size()) return fail(U1ML_EIO, "short read");
-  U1_TRY(e.set_device());
-  d.beta = beta;
-  d.eps = eps;
-  d.sqrt_beta = std::sqrt(beta);
-  d.seed = seed;
-  U1_TRY(e.upload_lats());
-  e.h_pass_ids[0] = pid;
-  U1_TRY(e.upload_pass_ids());
-  return e.set_links(0, h.data());
+  return load_engine(lat->e, path, false);
 }
 
 int u1ml_synchronize(u1ml_lattice* lat) {
@@ -1675,6 +1721,29 @@ int u1ml_batch_set_links(u1ml_batch* b, int i, const double* host) {
   if (!b || i < 0 || i >= b->e.n_lats || !host) return fail(U1ML_EINVAL, "batch_set_links arguments");
   U1_TRY(b->e.set_device());
   return b->e.set_links(i, host);
+}
+
+int u1ml_batch_get_pass_id(u1ml_batch* b, int i, uint64_t* pass_id) {
+  if (!b || i < 0 || i >= b->e.n_lats || !pass_id) return fail(U1ML_EINVAL, "batch_get_pass_id arguments");
+  *pass_id = b->e.h_pass_ids[i];
+  return U1ML_OK;
+}
+
+int u1ml_batch_set_pass_id(u1ml_batch* b, int i, uint64_t pass_id) {
+  if (!b || i < 0 || i >= b->e.n_lats) return fail(U1ML_EINVAL, "batch_set_pass_id arguments");
+  U1_TRY(b->e.set_device());
+  b->e.h_pass_ids[i] = pass_id;
+  return b->e.upload_pass_ids();
+}
+
+int u1ml_batch_save(u1ml_batch* b, const char* path) {
+  if (!b || !path) return fail(U1ML_EINVAL, "batch_save arguments");
+  return save_engine(b->e, path, true);
+}
+
+int u1ml_batch_load(u1ml_batch* b, const char* path) {
+  if (!b || !path) return fail(U1ML_EINVAL, "batch_load arguments");
+  return load_engine(b->e, path, true);
 }
 
 int u1ml_batch_synchronize(u1ml_batch* b) {

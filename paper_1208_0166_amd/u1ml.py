@@ -115,6 +115,10 @@ def load_library(path: str = LIB_PATH):
         "u1ml_batch_measure": (I, [P, I, C.POINTER(Observables), dp, dp]),
         "u1ml_batch_get_links": (I, [P, I, dp]),
         "u1ml_batch_set_links": (I, [P, I, dp]),
+        "u1ml_batch_get_pass_id": (I, [P, I, C.POINTER(U64)]),
+        "u1ml_batch_set_pass_id": (I, [P, I, U64]),
+        "u1ml_batch_save": (I, [P, C.c_char_p]),
+        "u1ml_batch_load": (I, [P, C.c_char_p]),
         "u1ml_batch_synchronize": (I, [P]),
         "u1ml_batch_destroy": (None, [P]),
         "u1ml_autotune": (I, [P, ip]),
@@ -563,6 +567,24 @@ def batch_get_links(b: Batch, i: int) -> np.ndarray:
 def batch_set_links(b: Batch, i: int, th: np.ndarray):
     a = np.ascontiguousarray(th, dtype=np.float64)
     _check(load_library().u1ml_batch_set_links(b.handle, i, a.ctypes.data_as(C.POINTER(C.c_double))))
+
+
+def batch_get_pass_id(b: Batch, i: int) -> int:
+    v = C.c_uint64()
+    _check(load_library().u1ml_batch_get_pass_id(b.handle, i, C.byref(v)))
+    return int(v.value)
+
+
+def batch_set_pass_id(b: Batch, i: int, pass_id: int):
+    _check(load_library().u1ml_batch_set_pass_id(b.handle, i, int(pass_id)))
+
+
+def batch_save(b: Batch, path: str):
+    _check(load_library().u1ml_batch_save(b.handle, path.encode()))
+
+
+def batch_load(b: Batch, path: str):
+    _check(load_library().u1ml_batch_load(b.handle, path.encode()))
 
 
 def batch_synchronize(b: Batch):

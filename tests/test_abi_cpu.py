@@ -71,6 +71,11 @@ def test_null_handles_rejected():
     assert lib.u1ml_batch_ensemble_add(None) == u1ml.EINVAL
     assert lib.u1ml_batch_ensemble_read(None, 0, None, None, None) == u1ml.EINVAL
     assert lib.u1ml_init_lattice(4, 4, 1.0, 1, None, None) == u1ml.EINVAL
+    assert lib.u1ml_batch_save(None, b"x") == u1ml.EINVAL
+    assert lib.u1ml_batch_load(None, b"x") == u1ml.EINVAL
+    pid = C.c_uint64()
+    assert lib.u1ml_batch_get_pass_id(None, 0, C.byref(pid)) == u1ml.EINVAL
+    assert lib.u1ml_batch_set_pass_id(None, 0, 1) == u1ml.EINVAL
     lib.u1ml_destroy(None)
     lib.u1ml_batch_destroy(None)
 

@@ -210,6 +210,58 @@ def test_checkpoint_resume_bit_exact(tmp_path, prec):
     np.testing.assert_array_equal(u1ml.get_links(c), u1ml.get_links(a))
 
 
+@pytest.mark.parametrize("prec", [u1ml.FP64, u1ml.FP32])
+def test_batch_checkpoint_resume_bit_exact(tmp_path, prec):
+    # a batch checkpoint holds every lattice's links, coupling, seed and pass
+    # id: a batch restored from it continues with the bits of the uninterrupted
+    # chains; a file for other shapes, another batch size or a cut file is
+    # refused and leaves the batch unchanged
+    Ls, Ts, betas, seeds = [6, 4], [6, 8], [1.0, 0.9], [31, 32]
+    say(f"[gpu] batch checkpoint prec={prec}")
+    a = u1ml.batch_create(Ls, Ts, betas, seeds, precision=prec)
+    for _ in range(6):
+        u1ml.batch_sweep(a, 1, 2)
+    b = u1ml.batch_create(Ls, Ts, betas, seeds, precision=prec)
+    for _ in range(2):
+        u1ml.batch_sweep(b, 1, 2)
+    path = str(tmp_path / "batch.ck")
+    u1ml.batch_save(b, path)
+    c = u1ml.batch_create(Ls, Ts, [0.5, 0.5], [7, 8], precision=prec, start=u1ml.COLD)
+    u1ml.batch_load(c, path)
+    assert [u1ml.batch_get_pass_id(c, i) for i in range(2)] == [2, 2]
+    for _ in range(4):
+        u1ml.batch_sweep(c, 1, 2)
+    for i in range(2):
+        np.testing.assert_array_equal(u1ml.batch_get_links(c, i), u1ml.batch_get_links(a, i))
+    # refusals
+    other = u1ml.batch_create([6, 6], [6, 8], betas, seeds, precision=prec)
+    before = u1ml.batch_get_links(other, 0)
+    with pytest.raises(u1ml.U1MLError) as e:
+        u1ml.batch_load(other, path)
+    assert e.value.code == u1ml.EINVAL
+    np.testing.assert_array_equal(u1ml.batch_get_links(other, 0), before)
+    assert u1ml.batch_get_pass_id(other, 0) == 0
+    three = u1ml.batch_create(Ls + [4], Ts + [4], betas + [1.0], seeds + [33], precision=prec)
+    with pytest.raises(u1ml.U1MLError) as e:
+        u1ml.batch_load(three, path)
+    assert e.value.code == u1ml.EINVAL
+    cut = str(tmp_path / "cut.ck")
+    with open(path, "rb") as fh:
+        data = fh.read()
+    with open(cut, "wb") as fh:
+        fh.write(data[:-8])
+    before = [u1ml.batch_get_links(c, i) for i in range(2)]
+    with pytest.raises(u1ml.U1MLError) as e:
+        u1ml.batch_load(c, cut)
+    assert e.value.code == u1ml.EIO
+    for i in range(2):
+        np.testing.assert_array_equal(u1ml.batch_get_links(c, i), before[i])
+    u1ml.batch_set_pass_id(c, 1, 17)
+    assert u1ml.batch_get_pass_id(c, 1) == 17
+    for g in (a, b, c, other, three):
+        g.close()
+
+
 def test_error_paths():
     g = gpu_lattice(4, 4, 1.0, 1)
     with pytest.raises(u1ml.U1MLError) as e:
