@@ -191,6 +191,7 @@ struct Engine {
   int xcd_map = 1;         // class-pass blocks in XCD-contiguous order
   int sample_block = 256;  // threads per block of the per-sample kernel
   int fold_threads = 0;    // threads per block of the row fold; 0 = by L and n_r
+  int fold_stage = 0;      // row fold staging: 1 all children, 2 one child at a time, 0 by size
   FieldTuning ftune;       // launch shapes of the fast field path
   int n_lats = 0;
   std::vector<LatDesc> h_lats;
@@ -751,22 +752,47 @@ struct Engine {
     const int inner = m.n_levels - 1;
     if (child == inner && !fold_general) {
       int threads = 64, max_nr = 1;
-      size_t max_lds = 0;
       const bool multihit = m.h_mls[0].multihit != 0;
       for (int i = 0; i < n_lats; ++i) {
         max_nr = std::max(max_nr, m.h_mls[i].n_r);
         if ((m.h_mls[i].multihit != 0) != multihit) return fail(U1ML_EINVAL, "mixed estimators in one run");
       }
       const int k_slots = ml_fold_rows_k(max_nr);
+      size_t all_lds = 0, child_lds = 0;
+      int items = 0;
       for (int i = 0; i < n_lats; ++i) {
         const int nsp = parent == m.n_levels ? 1 : m.h_mls[i].ns[parent];
         const int children = m.h_mls[i].ns[child] / nsp;
         threads = std::max(threads, fold_threads > 0 ? fold_threads
                                                      : ml_fold_rows_threads(h_lats[i].L, m.h_mls[i].n_r, k_slots));
-        max_lds = std::max(max_lds, (size_t)(multihit ? 2 : 1) * children * m.n[child] * h_lats[i].L *
-                                        sizeof(double2));
+        const size_t rows = (size_t)(multihit ? 2 : 1) * m.n[child] * h_lats[i].L * sizeof(double2);
+        child_lds = std::max(child_lds, rows);
+        all_lds = std::max(all_lds, children * rows);
+        items = std::max(items, h_lats[i].L * ((m.h_mls[i].n_r + k_slots - 1) / k_slots));
       }
-      if (max_lds <= ml_fold_rows_max_lds()) {
+      // one child at a time where asked (or, by default, where all children
+      // would take more than 16 KB of LDS per block and so limit the blocks
+      // per CU) and one thread per item fits a block; all at once where the
+      // other does not apply
+      const size_t max_lds_ok = ml_fold_rows_max_lds();
+      const int pc_threads = (items + 63) / 64 * 64;
+      const bool pc_fits = pc_threads <= 256 && child_lds <= max_lds_ok;
+      const bool want_pc = fold_stage == 2 || (fold_stage == 0 && all_lds > 16384);
+      const bool per_child = pc_fits && (want_pc || all_lds > max_lds_ok);
+      size_t max_lds = per_child ? child_lds : all_lds;
+      if (per_child) {
+        threads = std::max(threads, pc_threads);
+        // two buffers and enough threads to hold one child's rows in
+        // registers: the next child's rows load while one is folded
+        const int np = ml_fold_rows_prefetch(multihit);
+        const int vals = (int)(child_lds / sizeof(double2));
+        const int pipe_threads = ((vals + np - 1) / np + 63) / 64 * 64;
+        if (pipe_threads <= 256 && 2 * child_lds <= max_lds_ok) {
+          threads = std::max(threads, pipe_threads);
+          max_lds = 2 * child_lds;
+        }
+      }
+      if (max_lds <= max_lds_ok) {
         std::vector<int> rows;
         for (int i = 0; i < n_lats; ++i) {
           const int nsp = parent == m.n_levels ? 1 : m.h_mls[i].ns[parent];
@@ -781,7 +807,7 @@ struct Engine {
                                : -1;
         U1_TRY(fam_begin(kFamFold));
         U1_HIP(launch_ml_fold_rows(lats.as<LatDesc>(), m.mls.as<MLDesc>(), bt(t), threads, max_lds, k_slots,
-                                   multihit, child, parent, m.n_levels, m.n[child], sample_base, m.rvals.as<int>(), m.mlbuf.as<double2>(),
+                                   multihit, per_child, child, parent, m.n_levels, m.n[child], sample_base, m.rvals.as<int>(), m.mlbuf.as<double2>(),
                                    m.accbuf.as<double2>(), m.fls.as<FieldLat>(), m.fp, tavg_m, m.fbuf.as<double>(),
                                    stream));
         return fam_end(kFamFold);
@@ -1813,6 +1839,7 @@ static void get_tuning(const Engine& e, u1ml_tuning* t) {
   t->field_w_planes = e.ftune.w_planes;
   t->field_o_planes = e.ftune.o_planes;
   t->field_zcon_threads = e.ftune.zcon_threads;
+  t->fold_stage = e.fold_stage;
 }
 
 static int set_tuning(Engine& e, const u1ml_tuning& t) {
@@ -1820,7 +1847,8 @@ static int set_tuning(Engine& e, const u1ml_tuning& t) {
   if (!mult64(t.pass_block, 64, 1024) || (t.pass_xcd_map != 0 && t.pass_xcd_map != 1) ||
       !mult64(t.sample_block, 64, 1024) || (t.fold_threads != 0 && !mult64(t.fold_threads, 64, 256)) ||
       t.field_w_planes < 0 || t.field_w_planes > 64 || t.field_o_planes < 0 || t.field_o_planes > 64 ||
-      (t.field_zcon_threads != 0 && !mult64(t.field_zcon_threads, 64, 256)))
+      (t.field_zcon_threads != 0 && !mult64(t.field_zcon_threads, 64, 256)) || t.fold_stage < 0 ||
+      t.fold_stage > 2)
     return fail(U1ML_EINVAL, "tuning values out of range");
   U1_TRY(e.set_device());
   U1_HIP(hipStreamSynchronize(e.stream));
@@ -1831,6 +1859,7 @@ static int set_tuning(Engine& e, const u1ml_tuning& t) {
   e.ftune.w_planes = t.field_w_planes;
   e.ftune.o_planes = t.field_o_planes;
   e.ftune.zcon_threads = t.field_zcon_threads;
+  e.fold_stage = t.fold_stage;
   e.drop_graphs();  // captured launches carry the old shapes
   return U1ML_OK;
 }
@@ -1943,6 +1972,7 @@ static int autotune_engine(Engine& e, int n_levels, const int* th, const int* n_
     double ms = 0;
     rc = time_family(-1, &ms);
     if (!rc) rc = search(Engine::kFamSample, &e.sample_block, {64, 128, 256, 512, 1024});
+    if (!rc) rc = search(Engine::kFamFold, &e.fold_stage, {1, 2});
     if (!rc) rc = search(Engine::kFamFold, &e.fold_threads, {64, 128, 192, 256});
     int max_w = 64, max_o = 64;
     for (auto& d : e.h_lats) {

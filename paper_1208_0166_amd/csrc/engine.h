@@ -91,20 +91,26 @@ hipError_t launch_ml_fold(const LatDesc* lats, const MLDesc* mls, BlockTable bt,
 // the innermost fold by rows: bt has one block per (parent slab, axis, row)
 // of every lattice; k_slots = ml_fold_rows_k(largest n_r) separations per
 // thread; threads = ml_fold_rows_threads(L, n_r, k_slots) for the largest
-// lattice; lds = children * n_child * max L complex values, twice with
-// multihit (at most ml_fold_rows_max_lds() bytes); multihit: the run's
-// estimator (the same for every lattice of a run)
+// lattice; multihit: the run's estimator (the same for every lattice of a
+// run).  per_child false: all children of a parent slab staged at once, lds =
+// children * n_child * max L complex values; per_child true: one child at a
+// time, lds = n_child * max L complex values, and threads >= L * groups of
+// every lattice (one item per thread); with twice that lds and threads *
+// ml_fold_rows_prefetch(multihit) >= those values, the rows of the next
+// child are loaded while the current one is folded.  Values count twice
+// with multihit; lds is at most ml_fold_rows_max_lds() bytes.
 // tavg_m >= 0: also store the inner averages of the field separations of
 // outer iteration tavg_m into the field buffer (FieldLat::tavg)
 struct FieldParams;
 hipError_t launch_ml_fold_rows(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int threads, size_t lds,
-                               int k_slots, bool multihit, int child_level, int parent_level, int n_levels,
-                               int n_child, int sample_base, const int* rvals, const double2* mlbuf,
+                               int k_slots, bool multihit, bool per_child, int child_level, int parent_level,
+                               int n_levels, int n_child, int sample_base, const int* rvals, const double2* mlbuf,
                                double2* accbuf, const FieldLat* fls, const FieldParams& fp, int tavg_m, double* fbuf,
                                hipStream_t st);
 int ml_fold_rows_k(int max_n_r);
 int ml_fold_rows_threads(int L, int n_r, int k_slots);
 size_t ml_fold_rows_max_lds();
+int ml_fold_rows_prefetch(bool multihit);
 hipError_t launch_ml_zero(double2* accbuf, uint64_t n, hipStream_t st);
 hipError_t launch_ml_final(const LatDesc* lats, const MLDesc* mls, int n_lats, int max_r, int top_level,
                            const double2* accbuf, double* out, hipStream_t st);

@@ -302,20 +302,18 @@ __global__ __launch_bounds__(256) void ml_fold_kernel(const LatDesc* __restrict_
           if (j < kn) {
             // multihit lines for r >= 2 (the two lines share no plaquette)
             const bool mh = m.multihit && (rvals[m.r_off + k0 + j] & 0xffff) >= 2;
-            const double2 a = mh ? uh : u, v = mh ? eh[xr[j]] : e[xr[j]];
-            avg[j].x += a.x * v.x + a.y * v.y;
-            avg[j].y += a.x * v.y - a.y * v.x;
+            avg[j] = cmac_conj(avg[j], mh ? uh : u, mh ? eh[xr[j]] : e[xr[j]]);
           }
         }
       }
 #pragma unroll
-      for (int j = 0; j < kFoldR; ++j) avg[j] = make_double2(avg[j].x * inv, avg[j].y * inv);
+      for (int j = 0; j < kFoldR; ++j) avg[j] = cscale(avg[j], inv);
     } else {
       double2* cp = accbuf + m.acc[child_level] + ((size_t)cs * d.L3 + x0) * m.nR + k0;
 #pragma unroll
       for (int j = 0; j < kFoldR; ++j) {
         if (j < kn) {
-          avg[j] = make_double2(cp[j].x * inv, cp[j].y * inv);
+          avg[j] = cscale(cp[j], inv);
           cp[j] = make_double2(0.0, 0.0);
         }
       }
@@ -325,39 +323,143 @@ __global__ __launch_bounds__(256) void ml_fold_kernel(const LatDesc* __restrict_
   }
   double2* pp = accbuf + m.acc[parent_level] + ((size_t)S * d.L3 + x0) * m.nR + k0;
 #pragma unroll
-  for (int j = 0; j < kFoldR; ++j) {
-    if (j < kn) {
-      pp[j].x += prod[j].x;
-      pp[j].y += prod[j].y;
-    }
-  }
+  for (int j = 0; j < kFoldR; ++j)
+    if (j < kn) pp[j] = cadd(pp[j], prod[j]);
 }
 
 // The same fold for innermost children, one block per (parent slab S, axis a,
-// row along a): the rows of all stored samples of all children of S are
-// staged in LDS at once (children * n_child * L values, twice with multihit),
-// so every time line is read from memory once instead of once per
-// separation.  A thread owns one position j along the row and K separations
-// of the axis (K = 4, 6 or 8, chosen per launch so that the groups of K
-// cover the separations with the fewest unused slots), so the line at j is
-// read once per sample for all of them; the sample and child order of every
-// sum is that of ml_fold_kernel, so both give the same bits.  MH: the run
-// uses the multihit lines (known per launch, so that the plain run reads
-// each line once).  Rows along x are contiguous; rows along y and z are
-// strided by L and L^2.
+// row along a), with the rows of the stored samples staged in LDS, so that
+// every time line is read from memory once instead of once per separation.  A
+// thread owns one position j along the row and K separations of the axis (K =
+// 4, 6 or 8, chosen per launch so that the groups of K cover the separations
+// with the fewest unused slots), so the line at j is read once per sample for
+// all of them; the sample and child order of every sum is that of
+// ml_fold_kernel and every step is one of the explicitly rounded complex
+// helpers, so both (and both stagings) give the same bits.  MH: the run uses the multihit
+// lines (known per launch, so that the plain run reads each line once).  Rows
+// along x are contiguous; rows along y and z are strided by L and L^2.
+// Staging: all children of S at once (PC false: children * n_child * L
+// values, twice with multihit, one __syncthreads), or one child at a time (PC
+// true: n_child * L values, two __syncthreads per child, every (j, group)
+// item held by its own thread, blockDim >= L * groups), which keeps the LDS
+// of a block small where S has many children (a single level: T / t_h).
 constexpr size_t kFoldLds = 49152;  // bytes of staged rows per block
+// values per thread that the pipelined one-child staging holds in registers
+constexpr int fold_prefetch(bool mh) { return mh ? 8 : 4; }
 // With tavg_m >= 0 (two-level runs with the field inserted) the x rows also
 // store the inner averages of the field separations, tavg[((tavg_m n_rf + f)
 // ns + s) L3 + x0] (the inputs of the field weights), so that the field
 // contraction need not average the stored samples again.
+
+// One position along the row and its group of K separations.
 template <int K, bool MH>
+struct FoldItem {
+  int x0, k0, kn;
+  int xr[K];      // position of x0 + r (periodic)
+  bool mh[K];     // read the multihit lines (r >= 2)
+  int fslot[K];   // field separation index, or -1
+  double2 prod[K];
+};
+
+template <int K, bool MH>
+__device__ __forceinline__ void fold_item_init(FoldItem<K, MH>& it, int item, int ngroups, int L, int axis, int n_r,
+                                               int r_off, const int* __restrict__ rvals, bool tavg_on,
+                                               const FieldParams& fp) {
+  it.x0 = item / ngroups;
+  it.k0 = (item - it.x0 * ngroups) * K;
+  it.kn = min(K, n_r - it.k0);
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    // separations past the group's last are read clamped and never used
+    const int rv = rvals[r_off + axis * n_r + min(it.k0 + j, n_r - 1)];
+    const int r = j < it.kn ? rv & 0xffff : 0;
+    const int t = it.x0 + r;
+    it.xr[j] = t >= L ? t - L : t;
+    // multihit lines for r >= 2 (the two lines share no plaquette)
+    it.mh[j] = MH && r >= 2;
+    it.prod[j] = make_double2(1.0, 0.0);
+    it.fslot[j] = -1;
+  }
+  if (tavg_on) {
+    for (int f = 0; f < fp.n_rf; ++f) {
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        if (j < it.kn && fp.rf_k[f] == it.k0 + j) it.fslot[j] = f;
+    }
+  }
+}
+
+// Average over the n_child samples of one child (rows ep[i * L + x], the
+// multihit rows at ep[mh_off + i * L + x]), multiplied into the products;
+// tavg_c: where the field inner averages of this child go, or nullptr.
+template <int K, bool MH>
+__device__ __forceinline__ void fold_item_child(FoldItem<K, MH>& it, const double2* ep, int mh_off, int n_child,
+                                                int L, double inv, double2* tavg_c, size_t tavg_stride) {
+  double2 avg[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) avg[j] = make_double2(0.0, 0.0);
+  // every lane sums all K slots (those past the group's last take r = 0 and
+  // are never stored), so that no branch splits the wavefront
+#pragma unroll 2
+  for (int i = 0; i < n_child; ++i) {
+    const double2 u = ep[i * L + it.x0];
+    double2 uh = u;
+    if (MH) uh = ep[mh_off + i * L + it.x0];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      avg[j] = cmac_conj(avg[j], it.mh[j] ? uh : u, ep[(it.mh[j] ? mh_off : 0) + i * L + it.xr[j]]);
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    avg[j] = cscale(avg[j], inv);
+    it.prod[j] = cmul(it.prod[j], avg[j]);
+  }
+  if (tavg_c) {
+    // streamed: read back only by the field weights after the run
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      if (it.fslot[j] >= 0) store_stream(tavg_c + (size_t)it.fslot[j] * tavg_stride + it.x0, avg[j]);
+  }
+}
+
+// acc[k0 + j] += prod[j] for the group's separations
+template <int K, bool MH>
+__device__ __forceinline__ void fold_item_store(const FoldItem<K, MH>& it, double2* pp) {
+  // the accumulators are read together (clamped) before the updates
+  double2 old[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) old[j] = pp[min(j, it.kn - 1)];
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+    if (j < it.kn) pp[j] = cadd(old[j], it.prod[j]);
+}
+
+// rowbuf[e] = mlbuf[src(e)] for e < n.  The NLD loads of a thread are issued
+// together, unconditionally (the index is clamped: past the end, the last
+// value is loaded and stored again in its own place), so that no branch or
+// wait separates them.
+template <int NLD, typename Src>
+__device__ __forceinline__ void fold_stage(double2* rowbuf, int n, const double2* __restrict__ mlbuf, Src src) {
+  for (int e0 = threadIdx.x; e0 < n; e0 += NLD * (int)blockDim.x) {
+    double2 v[NLD];
+#pragma unroll
+    for (int j = 0; j < NLD; ++j) v[j] = mlbuf[src(min(e0 + j * (int)blockDim.x, n - 1))];
+#pragma unroll
+    for (int j = 0; j < NLD; ++j) rowbuf[min(e0 + j * (int)blockDim.x, n - 1)] = v[j];
+  }
+}
+
+template <int K, bool MH, bool PC>
 __global__ __launch_bounds__(256) void ml_fold_rows_kernel(const LatDesc* __restrict__ lats, const MLDesc* __restrict__ mls,
                                     const int2* __restrict__ blocks, int child_level, int parent_level, int n_levels,
                                     int n_child, int sample_base, const int* __restrict__ rvals,
                                     const double2* __restrict__ mlbuf, double2* __restrict__ accbuf,
                                     const FieldLat* __restrict__ fls, FieldParams fp, int tavg_m,
-                                    double* __restrict__ fbuf) {
-  extern __shared__ double2 rowbuf[];  // [children][n_child][L] (then the multihit rows)
+                                    double* __restrict__ fbuf, int lds_vals) {
+  // PC false: [children][n_child][L], then the multihit rows likewise;
+  // PC true: [n_child][L] of one child, then its multihit rows (twice, for
+  // the pipelined staging, where lds_vals, the double2 capacity, allows)
+  extern __shared__ double2 rowbuf[];
   // neighbouring rows (adjacent in memory) on one XCD, so that its L2 and
   // memory requests see contiguous stretches of the time lines
   const int2 bk = blocks[xcd_block(blockIdx.x, gridDim.x)];
@@ -379,98 +481,91 @@ __global__ __launch_bounds__(256) void ml_fold_rows_kernel(const LatDesc* __rest
   const int base = axis == 0 ? row * L : (axis == 1 ? rb * L2 + ra : rb * L + ra);
   const int ngroups = (n_r + K - 1) / K;
   const int per_child = n_child * L;
-  // rows of the plain lines, then (multihit) rows of the multihit lines
-  // The loads of kFoldLd values are issued together, unconditionally (the
-  // index is clamped: past the end, the last value is loaded and stored again
-  // in its own place), so that no branch or wait separates them.
-  const int staged = children * per_child, n_st = (MH ? 2 : 1) * staged;
-  constexpr int kFoldLd = 16;
-  for (int e0 = threadIdx.x; e0 < n_st; e0 += kFoldLd * (int)blockDim.x) {
-    double2 v[kFoldLd];
-#pragma unroll
-    for (int j = 0; j < kFoldLd; ++j) {
-      const int e = min(e0 + j * (int)blockDim.x, n_st - 1);
-      const int rw = e / L, x = e - rw * L;  // row (h, c, i) of the staged rows
-      const int i = rw % n_child, hc = rw / n_child, c = hc % children, h = hc / children;
-      v[j] = mlbuf[(h ? ell_mh : ell) + ((size_t)(sample_base + i) * ns_child + S * children + c) * d.L3 +
-                   (size_t)base + (size_t)x * stride];
-    }
-#pragma unroll
-    for (int j = 0; j < kFoldLd; ++j) rowbuf[min(e0 + j * (int)blockDim.x, n_st - 1)] = v[j];
-  }
-  __syncthreads();
+  // field separations stored by the x rows (uniform per block)
+  const bool tavg_on = tavg_m >= 0 && axis == 0;
+  double2* tv = tavg_on ? (double2*)(fbuf + fls[bk.x].tavg) + (size_t)tavg_m * fp.n_rf * ns_child * d.L3 : nullptr;
+  const size_t tavg_stride = (size_t)ns_child * d.L3;
   const double inv = 1.0 / (double)n_child;
-  for (int item = threadIdx.x; item < L * ngroups; item += blockDim.x) {
-    const int x0 = item / ngroups, k0 = (item - x0 * ngroups) * K;
-    const int kn = min(K, n_r - k0);
-    int xr[K];
-    bool mh[K];
-    double2 prod[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      // separations past the group's last are read clamped and never used
-      const int rv = rvals[r_off + axis * n_r + min(k0 + j, n_r - 1)];
-      const int r = j < kn ? rv & 0xffff : 0;
-      const int t = x0 + r;
-      xr[j] = t >= L ? t - L : t;
-      // multihit lines for r >= 2 (the two lines share no plaquette)
-      mh[j] = MH && r >= 2;
-      prod[j] = make_double2(1.0, 0.0);
+  // element (h, c, i, x) of the staged rows: line h (plain, multihit) of
+  // sample i of child c at position x along the row
+  auto line = [&](int h, int c, int i, int x) -> size_t {
+    return (h ? ell_mh : ell) + ((size_t)(sample_base + i) * ns_child + S * children + c) * d.L3 + (size_t)base +
+           (size_t)x * stride;
+  };
+  auto acc = [&](const FoldItem<K, MH>& it) {
+    return accbuf + acc_parent + ((size_t)S * d.L3 + (size_t)base + (size_t)it.x0 * stride) * nR + axis * n_r + it.k0;
+  };
+  if constexpr (!PC) {
+    const int staged = children * per_child;
+    fold_stage<16>(rowbuf, (MH ? 2 : 1) * staged, mlbuf, [&](int e) {
+      const int rw = e / L, x = e - rw * L;
+      const int i = rw % n_child, hc = rw / n_child, c = hc % children, h = hc / children;
+      return line(h, c, i, x);
+    });
+    __syncthreads();
+    for (int item = threadIdx.x; item < L * ngroups; item += blockDim.x) {
+      FoldItem<K, MH> it;
+      fold_item_init(it, item, ngroups, L, axis, n_r, r_off, rvals, tavg_on, fp);
+      for (int c = 0; c < children; ++c)
+        fold_item_child(it, rowbuf + c * per_child, staged, n_child, L, inv,
+                        tv ? tv + (size_t)(S * children + c) * d.L3 + base : nullptr, tavg_stride);
+      fold_item_store(it, acc(it));
     }
-    // field separation of each slot (or -1) when the x rows store the field
-    // inner averages (uniform per block)
-    const bool tavg_on = tavg_m >= 0 && axis == 0;
-    int fslot[K];
-    double2* tv = nullptr;
+  } else {
+    const int items = L * ngroups;
+    const bool active = (int)threadIdx.x < items;
+    FoldItem<K, MH> it;
+    fold_item_init(it, min((int)threadIdx.x, items - 1), ngroups, L, axis, n_r, r_off, rvals, tavg_on, fp);
+    const int n_c = (MH ? 2 : 1) * per_child;  // staged values of one child
+    auto src = [&](int c, int e) {
+      const int rw = e / L, x = e - rw * L;
+      return line(rw / n_child, c, rw % n_child, x);
+    };
+    auto fold_child = [&](int c, const double2* rows) {
+      if (active)
+        fold_item_child(it, rows, per_child, n_child, L, inv,
+                        tv ? tv + (size_t)(S * children + c) * d.L3 + base : nullptr, tavg_stride);
+    };
+    constexpr int NP = fold_prefetch(MH);
+    if (n_c <= NP * (int)blockDim.x && 2 * n_c <= lds_vals) {
+      // software pipeline: the rows of child c + 1 are loaded into registers
+      // while child c is folded from one of two LDS buffers, then stored to
+      // the other.  One barrier per child: buffer (c + 1) & 1 was last read
+      // while folding child c - 1, before the barrier that ended that step.
+      // The loads and stores are clamped: past the end, the last value is
+      // loaded and stored again in its own place.
+      fold_stage<NP>(rowbuf, n_c, mlbuf, [&](int e) { return src(0, e); });
+      __syncthreads();
+      for (int c = 0; c < children; ++c) {
+        const bool next = c + 1 < children;
+        // plain doubles: an array of double2 here is kept in scratch memory
+        double vx[NP], vy[NP];
+        if (next) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) fslot[j] = -1;
-    if (tavg_on) {
-      tv = (double2*)(fbuf + fls[bk.x].tavg) + (size_t)tavg_m * fp.n_rf * ns_child * d.L3;
-      for (int f = 0; f < fp.n_rf; ++f) {
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-          if (j < kn && fp.rf_k[f] == k0 + j) fslot[j] = f;
-      }
-    }
-    for (int c = 0; c < children; ++c) {
-      const double2* ep = rowbuf + c * per_child;
-      double2 avg[K];
-#pragma unroll
-      for (int j = 0; j < K; ++j) avg[j] = make_double2(0.0, 0.0);
-      // every lane sums all K slots (those past the group's last take r = 0
-      // and are never stored), so that no branch splits the wavefront
-#pragma unroll 2
-      for (int i = 0; i < n_child; ++i) {
-        const double2 u = ep[i * L + x0];
-        double2 uh = u;
-        if (MH) uh = ep[staged + i * L + x0];
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const double2 a = mh[j] ? uh : u, v = ep[(mh[j] ? staged : 0) + i * L + xr[j]];
-          avg[j].x += a.x * v.x + a.y * v.y;
-          avg[j].y += a.x * v.y - a.y * v.x;
+          for (int j = 0; j < NP; ++j) {
+            const double2 t = mlbuf[src(c + 1, min((int)threadIdx.x + j * (int)blockDim.x, n_c - 1))];
+            vx[j] = t.x;
+            vy[j] = t.y;
+          }
         }
+        fold_child(c, rowbuf + (c & 1) * n_c);
+        if (next) {
+          double2* buf = rowbuf + ((c + 1) & 1) * n_c;
+#pragma unroll
+          for (int j = 0; j < NP; ++j)
+            buf[min((int)threadIdx.x + j * (int)blockDim.x, n_c - 1)] = make_double2(vx[j], vy[j]);
+        }
+        __syncthreads();
       }
-#pragma unroll
-      for (int j = 0; j < K; ++j) prod[j] = cmul(prod[j], make_double2(avg[j].x * inv, avg[j].y * inv));
-      if (tavg_on) {
-        // streamed: read back only by the field weights after the run
-        const int s = S * children + c;
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-          if (fslot[j] >= 0)
-            store_stream(tv + ((size_t)fslot[j] * ns_child + s) * d.L3 + base + x0,
-                         make_double2(avg[j].x * inv, avg[j].y * inv));
+    } else {
+      for (int c = 0; c < children; ++c) {
+        if (c) __syncthreads();  // the previous child's rows are no longer read
+        fold_stage<4>(rowbuf, n_c, mlbuf, [&](int e) { return src(c, e); });
+        __syncthreads();
+        fold_child(c, rowbuf);
       }
     }
-    double2* pp = accbuf + acc_parent + ((size_t)S * d.L3 + (size_t)base + (size_t)x0 * stride) * nR + axis * n_r + k0;
-    // the accumulators are read together (clamped) before the updates
-    double2 old[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) old[j] = pp[min(j, kn - 1)];
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-      if (j < kn) pp[j] = make_double2(old[j].x + prod[j].x, old[j].y + prod[j].y);
+    if (active) fold_item_store(it, acc(it));
   }
 }
 
@@ -619,36 +714,49 @@ hipError_t launch_ml_fold(const LatDesc* lats, const MLDesc* mls, BlockTable bt,
   return hipGetLastError();
 }
 
+template <int K, bool MH>
+void launch_fold_rows_km(bool per_child, BlockTable bt, int threads, size_t lds, const LatDesc* lats,
+                         const MLDesc* mls, int child_level, int parent_level, int n_levels, int n_child,
+                         int sample_base, const int* rvals, const double2* mlbuf, double2* accbuf,
+                         const FieldLat* fls, const FieldParams& fp, int tavg_m, double* fbuf, hipStream_t st) {
+  if (per_child)
+    hipLaunchKernelGGL((ml_fold_rows_kernel<K, MH, true>), dim3(bt.n_blocks), dim3(threads), lds, st, lats, mls,
+                       bt.dev, child_level, parent_level, n_levels, n_child, sample_base, rvals, mlbuf, accbuf, fls,
+                       fp, tavg_m, fbuf, (int)(lds / sizeof(double2)));
+  else
+    hipLaunchKernelGGL((ml_fold_rows_kernel<K, MH, false>), dim3(bt.n_blocks), dim3(threads), lds, st, lats, mls,
+                       bt.dev, child_level, parent_level, n_levels, n_child, sample_base, rvals, mlbuf, accbuf, fls,
+                       fp, tavg_m, fbuf, (int)(lds / sizeof(double2)));
+}
+
 template <int K>
-void launch_fold_rows_k(bool multihit, BlockTable bt, int threads, size_t lds, const LatDesc* lats,
+void launch_fold_rows_k(bool multihit, bool per_child, BlockTable bt, int threads, size_t lds, const LatDesc* lats,
                         const MLDesc* mls, int child_level, int parent_level, int n_levels, int n_child,
                         int sample_base, const int* rvals, const double2* mlbuf, double2* accbuf,
                         const FieldLat* fls, const FieldParams& fp, int tavg_m, double* fbuf, hipStream_t st) {
   if (multihit)
-    hipLaunchKernelGGL((ml_fold_rows_kernel<K, true>), dim3(bt.n_blocks), dim3(threads), lds, st, lats, mls, bt.dev,
-                       child_level, parent_level, n_levels, n_child, sample_base, rvals, mlbuf, accbuf, fls, fp,
-                       tavg_m, fbuf);
+    launch_fold_rows_km<K, true>(per_child, bt, threads, lds, lats, mls, child_level, parent_level, n_levels, n_child,
+                                 sample_base, rvals, mlbuf, accbuf, fls, fp, tavg_m, fbuf, st);
   else
-    hipLaunchKernelGGL((ml_fold_rows_kernel<K, false>), dim3(bt.n_blocks), dim3(threads), lds, st, lats, mls, bt.dev,
-                       child_level, parent_level, n_levels, n_child, sample_base, rvals, mlbuf, accbuf, fls, fp,
-                       tavg_m, fbuf);
+    launch_fold_rows_km<K, false>(per_child, bt, threads, lds, lats, mls, child_level, parent_level, n_levels,
+                                  n_child, sample_base, rvals, mlbuf, accbuf, fls, fp, tavg_m, fbuf, st);
 }
 
 hipError_t launch_ml_fold_rows(const LatDesc* lats, const MLDesc* mls, BlockTable bt, int threads, size_t lds,
-                               int k_slots, bool multihit, int child_level, int parent_level, int n_levels,
-                               int n_child, int sample_base, const int* rvals, const double2* mlbuf,
+                               int k_slots, bool multihit, bool per_child, int child_level, int parent_level,
+                               int n_levels, int n_child, int sample_base, const int* rvals, const double2* mlbuf,
                                double2* accbuf, const FieldLat* fls, const FieldParams& fp, int tavg_m, double* fbuf,
                                hipStream_t st) {
   if (bt.n_blocks == 0) return hipSuccess;
   if (k_slots == 4)
-    launch_fold_rows_k<4>(multihit, bt, threads, lds, lats, mls, child_level, parent_level, n_levels, n_child,
-                          sample_base, rvals, mlbuf, accbuf, fls, fp, tavg_m, fbuf, st);
+    launch_fold_rows_k<4>(multihit, per_child, bt, threads, lds, lats, mls, child_level, parent_level, n_levels,
+                          n_child, sample_base, rvals, mlbuf, accbuf, fls, fp, tavg_m, fbuf, st);
   else if (k_slots == 6)
-    launch_fold_rows_k<6>(multihit, bt, threads, lds, lats, mls, child_level, parent_level, n_levels, n_child,
-                          sample_base, rvals, mlbuf, accbuf, fls, fp, tavg_m, fbuf, st);
+    launch_fold_rows_k<6>(multihit, per_child, bt, threads, lds, lats, mls, child_level, parent_level, n_levels,
+                          n_child, sample_base, rvals, mlbuf, accbuf, fls, fp, tavg_m, fbuf, st);
   else if (k_slots == 8)
-    launch_fold_rows_k<8>(multihit, bt, threads, lds, lats, mls, child_level, parent_level, n_levels, n_child,
-                          sample_base, rvals, mlbuf, accbuf, fls, fp, tavg_m, fbuf, st);
+    launch_fold_rows_k<8>(multihit, per_child, bt, threads, lds, lats, mls, child_level, parent_level, n_levels,
+                          n_child, sample_base, rvals, mlbuf, accbuf, fls, fp, tavg_m, fbuf, st);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -667,6 +775,7 @@ int ml_fold_rows_threads(int L, int n_r, int k_slots) {
   return std::min(256, (items + 63) / 64 * 64);
 }
 size_t ml_fold_rows_max_lds() { return kFoldLds; }
+int ml_fold_rows_prefetch(bool multihit) { return fold_prefetch(multihit); }
 
 hipError_t launch_ml_zero(double2* accbuf, uint64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;

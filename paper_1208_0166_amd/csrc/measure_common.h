@@ -223,8 +223,29 @@ __device__ __forceinline__ void store_stream(double2* p, double2 v) {
   __builtin_nontemporal_store(v.y, &p->y);
 }
 
+// Complex arithmetic of the level averages and their products, written as
+// explicit fused multiply-adds with contraction off around them: every
+// kernel that forms the same average, product or sum (the row-staged and the
+// per-site fold, the field weights) rounds it the same way, whatever the
+// code around it.
+// a b
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+#pragma clang fp contract(off)
+  return make_double2(__builtin_fma(a.x, b.x, -(a.y * b.y)), __builtin_fma(a.x, b.y, a.y * b.x));
+}
+// acc + conj(a) b
+__device__ __forceinline__ double2 cmac_conj(double2 acc, double2 a, double2 b) {
+#pragma clang fp contract(off)
+  return make_double2(__builtin_fma(a.x, b.x, __builtin_fma(a.y, b.y, acc.x)),
+                      __builtin_fma(a.x, b.y, __builtin_fma(-a.y, b.x, acc.y)));
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+#pragma clang fp contract(off)
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 cscale(double2 a, double s) {
+#pragma clang fp contract(off)
+  return make_double2(a.x * s, a.y * s);
 }
 
 __device__ __forceinline__ double2 cexpi(double phi) {
@@ -239,12 +260,9 @@ __device__ __forceinline__ double2 inner_avg(const double2* ell, int n_samples, 
   double2 a = make_double2(0.0, 0.0);
   for (int i = 0; i < n_samples; ++i) {
     const double2* e = ell + ((size_t)i * ns + cs) * L3;
-    const double2 u = e[x0], v = e[x0r];
-    a.x += u.x * v.x + u.y * v.y;
-    a.y += u.x * v.y - u.y * v.x;
+    a = cmac_conj(a, e[x0], e[x0r]);
   }
-  const double inv = 1.0 / (double)n_samples;
-  return make_double2(a.x * inv, a.y * inv);
+  return cscale(a, 1.0 / (double)n_samples);
 }
 
 __global__ void zero_kernel(double2* __restrict__ p, uint64_t n) {

@@ -54,7 +54,7 @@ class Tuning(C.Structure):
     """u1ml_tuning: launch shapes of the kernels (results do not depend on them)."""
     _fields_ = [("pass_block", C.c_int), ("pass_xcd_map", C.c_int), ("sample_block", C.c_int),
                 ("fold_threads", C.c_int), ("field_w_planes", C.c_int), ("field_o_planes", C.c_int),
-                ("field_zcon_threads", C.c_int)]
+                ("field_zcon_threads", C.c_int), ("fold_stage", C.c_int)]
 
     def as_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}

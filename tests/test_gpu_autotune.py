@@ -1,7 +1,7 @@
 """Launch shapes and the batch autotuner: results are bit-identical for every
 shape of every kernel family (class-pass block size and XCD order, per-sample
-kernel block, row-fold threads, field transform planes per block and
-contraction threads), and the autotuner leaves the chain where it was."""
+kernel block, row-fold staging and threads, field transform planes per block
+and contraction threads), and the autotuner leaves the chain where it was."""
 import sys
 
 import numpy as np
@@ -20,11 +20,11 @@ RF = [2, 4]
 
 SHAPES = [
     dict(pass_block=64, pass_xcd_map=0, sample_block=1024, fold_threads=64, field_w_planes=1, field_o_planes=1,
-         field_zcon_threads=64),
+         field_zcon_threads=64, fold_stage=2),
     dict(pass_block=1024, pass_xcd_map=1, sample_block=64, fold_threads=256, field_w_planes=64, field_o_planes=64,
-         field_zcon_threads=256),
+         field_zcon_threads=256, fold_stage=1),
     dict(pass_block=128, pass_xcd_map=0, sample_block=512, fold_threads=192, field_w_planes=2, field_o_planes=3,
-         field_zcon_threads=192),
+         field_zcon_threads=192, fold_stage=2),
 ]
 
 
@@ -77,7 +77,7 @@ def test_autotune_keeps_the_chain_and_its_choice_gives_the_same_bits():
     assert best["pass_block"] in (64, 128, 256, 512, 1024) and best["pass_xcd_map"] in (0, 1)
     assert best["sample_block"] in (64, 128, 256, 512, 1024) and best["fold_threads"] in (64, 128, 192, 256)
     assert best["field_w_planes"] >= 1 and best["field_o_planes"] >= 1
-    assert best["field_zcon_threads"] in (64, 128, 192, 256)
+    assert best["field_zcon_threads"] in (64, 128, 192, 256) and best["fold_stage"] in (1, 2)
     assert u1ml.get_tuning(b) == best
     for i in range(len(LS)):
         np.testing.assert_array_equal(u1ml.batch_get_links(b, i), th0[i])
@@ -90,7 +90,7 @@ def test_autotune_keeps_the_chain_and_its_choice_gives_the_same_bits():
 def test_tuning_values_are_checked():
     b = u1ml.batch_create([8, 8], [8, 8], [1.0, 1.0], [1, 2])
     for bad in (dict(pass_block=100), dict(pass_xcd_map=2), dict(sample_block=2048), dict(fold_threads=512),
-                dict(field_w_planes=-1), dict(field_zcon_threads=96)):
+                dict(field_w_planes=-1), dict(field_zcon_threads=96), dict(fold_stage=3), dict(fold_stage=-1)):
         with pytest.raises(u1ml.U1MLError):
             u1ml.set_tuning(b, **bad)
     # class passes only (no multilevel shape)

@@ -519,14 +519,15 @@ def test_field_size_and_separation_limits():
 
 
 @pytest.mark.parametrize("n_sub", [[2, 3], [10, 20]])
-@pytest.mark.parametrize("prec_fold", ["rows", "general"])
+@pytest.mark.parametrize("prec_fold", ["rows", "rows_per_child", "general"])
 def test_full_size_24_two_level_several_samples_match_oracle(oracle_mod, prec_fold, n_sub):
     # the benchmark's shape at 24^4 (levels {4, 2}, r = 1..12) with several
     # updates per level, so that every level average is over more than one
     # sample, up to the benchmark's own {10, 20} (the row fold then stages 20
     # samples of both children per row): FP64 links bit-identical to the
     # oracle and C_ML(r) to 1e-12, with the row-staged fold of the inner
-    # averages and with the per-site one
+    # averages (both children at once, or one at a time) and with the
+    # per-site one
     L = T = 24
     r_list = list(range(1, 13))
     say(f"[gpu] 24^4 FP64 two-level {{4,2}} x {n_sub} r=1..12 vs oracle, fold={prec_fold}")
@@ -534,6 +535,8 @@ def test_full_size_24_two_level_several_samples_match_oracle(oracle_mod, prec_fo
     g = u1ml.init_lattice(L, T, 1.0, 31)
     if prec_fold == "general":
         u1ml.set_debug(g, 4)
+    else:
+        u1ml.set_tuning(g, fold_stage=2 if prec_fold == "rows_per_child" else 1)
     o.sweep(1, 3)
     u1ml.sweep(g, 1, 3)
     c_o, _, _ = o.multilevel([4, 2], n_sub, 1, 3, r_list)
@@ -568,3 +571,40 @@ def test_full_size_24_multihit_several_samples_match_oracle(oracle_mod, symmetri
     _, c_g, _ = u1ml.measure(g, observables=False, correlator=True)
     np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
     close_rel(c_g, c_o)
+
+
+@pytest.mark.parametrize("multihit", [False, True])
+def test_single_level_fold_modes_give_the_same_bits(oracle_mod, multihit):
+    # the single-level run of the uneven batch at its largest size (24^4,
+    # slabs of 2, 10 updates, r = 1..12): the row fold's parent slab is the
+    # whole lattice, with 12 children of 10 samples (46 KB of rows, 92 KB
+    # with the multihit lines, which only the per-child staging holds).  The
+    # fold staging all children at once, one child at a time (the default
+    # here) and the per-site fold give the same bits, and the oracle's
+    # C_ML(r) to 1e-12 (cold start and two sweeps, so that C_ML(r) is of
+    # order 1e-4 to 1e-3 at every r).
+    L = T = 24
+    r_list = list(range(1, 13))
+    runs = []
+    for mode in ("auto", "all", "per_child", "general"):
+        say(f"[gpu] 24^4 FP64 single level [2] x [10] r=1..12 multihit={multihit} fold={mode}")
+        g = u1ml.init_lattice(L, T, 1.0, 41, start=u1ml.COLD)
+        u1ml.set_estimator(g, multihit=multihit)
+        if mode == "general":
+            u1ml.set_debug(g, 4)
+        elif mode != "auto":
+            u1ml.set_tuning(g, fold_stage=1 if mode == "all" else 2)
+        for _ in range(2):
+            u1ml.sweep(g, 1, 3)
+        u1ml.multilevel(g, [2], [10], 1, 3, r_list)
+        _, c, _ = u1ml.measure(g, observables=False, correlator=True)
+        runs.append((u1ml.get_links(g), c))
+    for th, c in runs[1:]:
+        np.testing.assert_array_equal(th, runs[0][0])
+        np.testing.assert_array_equal(c, runs[0][1])
+    o = oracle_mod.OracleLattice(L, T, 1.0, 41, hot=False)
+    for _ in range(2):
+        o.sweep(1, 3)
+    c_o, _, _ = o.multilevel([2], [10], 1, 3, r_list, multihit=multihit)
+    np.testing.assert_array_equal(runs[0][0], o.get_links())
+    np.testing.assert_allclose(runs[0][1], c_o, rtol=1e-12, atol=0)
