@@ -374,9 +374,10 @@ typedef struct u1ml_tuning {
     int fold_stage;         /* rows the row fold stages in LDS at once: 1 = those of all children
                                of a parent slab, 2 = those of one child at a time (one thread per
                                position and separation group, so at least that many threads per
-                               block); 0 = 2 where 1 would take more than 16 KB per block.  Where
-                               the mode asked for does not fit (LDS, 256 threads), the other is
-                               taken, else the per-site fold */
+                               block); 0 = 2 where 1 would take more than 16 KB per block (the
+                               faster choice on the shapes measured; the autotuner leaves this
+                               value as it is).  Where the mode asked for does not fit (LDS, 256
+                               threads), the other is taken, else the per-site fold */
 } u1ml_tuning;
 int u1ml_get_tuning(u1ml_lattice *lat, u1ml_tuning *t);
 int u1ml_set_tuning(u1ml_lattice *lat, const u1ml_tuning *t);
@@ -389,7 +390,7 @@ int u1ml_batch_set_tuning(u1ml_batch *b, const u1ml_tuning *t);
  * block order over three compound sweeps per candidate (best of two); then,
  * if n_levels > 0, with multilevel runs of the given shape (u1ml_multilevel
  * arguments with n_metro = 1, n_or = 3), the per-sample kernel's block
- * size, the row fold's staging and threads and, with field separations on the fast
+ * size, the row fold's threads and, with field separations on the fast
  * contraction path, the planes per block of both field transforms and the
  * contraction's threads, each timed over its own launches only (best of two
  * runs per candidate).  The shape should keep as many samples per lattice as

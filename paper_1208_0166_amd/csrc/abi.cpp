@@ -1972,7 +1972,6 @@ static int autotune_engine(Engine& e, int n_levels, const int* th, const int* n_
     double ms = 0;
     rc = time_family(-1, &ms);
     if (!rc) rc = search(Engine::kFamSample, &e.sample_block, {64, 128, 256, 512, 1024});
-    if (!rc) rc = search(Engine::kFamFold, &e.fold_stage, {1, 2});
     if (!rc) rc = search(Engine::kFamFold, &e.fold_threads, {64, 128, 192, 256});
     int max_w = 64, max_o = 64;
     for (auto& d : e.h_lats) {
