@@ -74,6 +74,53 @@ def samples_per_step():
     return N_SUB[0] * N_SUB[1] * (T // LEVELS[-1])
 
 
+def pass_words(spatial, th):
+    """(reads, writes) of one class pass in link words per lattice site: the
+    distinct links it needs.  A pass updates the direction-mu links at the
+    sites of one parity and reads every link of the plaquettes that contain
+    them (Sec. 2.1).  With no frozen slices (th = 0), or for time links, that
+    is the whole lattice (4 words per site) for half the sites' updates.
+    Inside slabs of th time slices (Sec. 2.2) a spatial pass updates the
+    slices t != 0 mod th (a fraction f of them) and reads all four links there
+    plus, on the frozen slices, the opposite-parity mu links (the time
+    plaquettes' far sides) and the time links leaving them: 4 f + 1.5 (1 - f)."""
+    if not spatial or th == 0:
+        return 4.0, 0.5
+    f = (th - 1) / th
+    return 4.0 * f + 1.5 * (1.0 - f), f / 2.0
+
+
+def hit_words(th):
+    """Link words of one hit (one Metropolis or one OR pass over every class:
+    2 parities x (1 time + 3 spatial directions)) per lattice site."""
+    return 2 * sum(pass_words(False, th)) + 6 * sum(pass_words(True, th))
+
+
+def stencil_words(V, n_sweeps, levels, n_sub):
+    """Link words the class passes of n_sweeps compound sweeps and one
+    multilevel run (levels, n_sub) move on one lattice of V sites, each pass
+    counted by its stencil (pass_words); 4 hits (1 Metropolis + 3 OR) per
+    compound sweep."""
+    words = n_sweeps * 4 * hit_words(0)
+    reps = 1
+    for th, n in zip(levels, n_sub):
+        reps *= n
+        words += reps * 4 * hit_words(th)
+    return words * V
+
+
+def chain_stencil_words(n_between=N_BETWEEN):
+    return stencil_words(L ** 3 * T, n_between, LEVELS, N_SUB)
+
+
+def stencil_roofline(words, bytes_per_word, ms):
+    """The link traffic of a step counted by its stencils, against the HBM
+    peak: bytes, the step time at peak, and the fraction of it achieved."""
+    b = words * bytes_per_word
+    ms_peak = b / (HBM_PEAK_GBS * 1e9) * 1e3
+    return {"bytes_per_step": b, "ms_at_peak": ms_peak, "frac": ms_peak / ms}
+
+
 def sweep_sources_sha():
     h = hashlib.sha256()
     for f in ("sweep_impl.h", "device_common.h", "sweep_f32.hip", "sweep_f64.hip"):
@@ -395,9 +442,14 @@ def counters_run(args):
                             precision=prec, stream=stream.cuda_stream)
     for _ in range(4):
         u1ml.batch_sweep(lat, 1, 3)
+    if args.counters_multilevel:
+        # the class passes inside slabs of 4 and of 2 (one update per level),
+        # told apart from the plain passes by their grid sizes: R V / 2
+        # threads plain, R V 3 / 8 in slabs of 4, R V / 4 in slabs of 2
+        u1ml.batch_multilevel(lat, LEVELS, [1, 1], 1, 3, [1])
     torch.cuda.synchronize()
     print(json.dumps({"counters_run": True, "copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
-                      "replicas": R, "sweeps": 4}), flush=True)
+                      "replicas": R, "sweeps": 4, "multilevel": bool(args.counters_multilevel)}), flush=True)
 
 
 LARGE_L = 48
@@ -539,6 +591,8 @@ def uneven_leg(u1ml, torch, n_cycles, warmup=1, tune=True):
             "cycles": n_cycles, "ms_per_cycle": 1e3 * el / n_cycles, "gpu_ms_per_cycle": ms_cycles / n_cycles,
             "updates_per_s_gpu": up * n_cycles / (ms_cycles * 1e-3),
             "step_roofline_frac": up * n_cycles / el / (HBM_PEAK_GBS * 1e9 / (WORDS_PER_UPDATE * 4)),
+            "stencil_exact": stencil_roofline(sum(stencil_words(v, UNEVEN_SWEEPS, [UNEVEN_TH], [UNEVEN_NSUB])
+                                                  for v in V), 4, 1e3 * el / n_cycles),
             "plaquette_min_max": [min(r[0]["plaquette"] for r in res), max(r[0]["plaquette"] for r in res)],
             "tuning": tuning}
 
@@ -587,6 +641,8 @@ def main():
     ap.add_argument("--symmetric", action="store_true",
                     help="correlator averaged over separations along +-x, +-y, +-z")
     ap.add_argument("--counters", action="store_true", help="short run for hardware-counter passes")
+    ap.add_argument("--counters-multilevel", action="store_true",
+                    help="with --counters: one multilevel run {4,2} x {1,1} after the sweeps")
     ap.add_argument("--large", action="store_true",
                     help="instead of the 24^4 workload: one 48^4 chain per precision (FP32 vs FP64)")
     ap.add_argument("--uneven", action="store_true",
@@ -688,7 +744,12 @@ def main():
         "step_roofline": {"updates_per_s_at_peak": HBM_PEAK_GBS * 1e9 / (WORDS_PER_UPDATE * bw),
                           "frac": main_run["updates_per_s"] / (HBM_PEAK_GBS * 1e9 / (WORDS_PER_UPDATE * bw)),
                           "samples_per_s_at_peak": samples_per_step() * HBM_PEAK_GBS * 1e9 /
-                                                   (WORDS_PER_UPDATE * bw * sum(chain_updates_per_step()))},
+                                                   (WORDS_PER_UPDATE * bw * sum(chain_updates_per_step())),
+                          # the passes inside slabs read their frozen neighbour
+                          # slices too: 12 words per update with slabs of 2,
+                          # 10 with slabs of 4 (pass_words); every pass counted
+                          # by its stencil
+                          "stencil_exact": stencil_roofline(R * chain_stencil_words(), bw, main_run["ms_step"])},
     }
     del main_run
     if not args.no_extra:
@@ -704,7 +765,8 @@ def main():
             "ms_per_step": ml_run["ms_step"],
             "step_roofline_frac": ml_run["updates_per_s"] / (HBM_PEAK_GBS * 1e9 / (WORDS_PER_UPDATE * bw)),
             "samples_per_s_at_peak": samples_per_step() * HBM_PEAK_GBS * 1e9 /
-                                     (WORDS_PER_UPDATE * bw * chain_updates_per_step(0)[1])}
+                                     (WORDS_PER_UPDATE * bw * chain_updates_per_step(0)[1]),
+            "stencil_exact": stencil_roofline(R * chain_stencil_words(0), bw, ml_run["ms_step"])}
         del ml_run
         progress("cache-spilling roofline leg")
         ms_sp, iso_sp, tun_sp = roofline_leg(u1ml, torch, prec, SPILL_REPLICAS, 3, tune=tune)

@@ -71,3 +71,70 @@ def test_samples_at_the_update_roofline():
     assert bench.chain_updates_per_step(0) == (0, ml)
     assert abs(bench.samples_per_step() * peak / ml - 7.547e5) < 1e2
     assert abs(bench.samples_per_step() * peak / (sweeps + ml) - 4.310e5) < 1e2
+
+
+def _pass_links_bruteforce(L, T, mu, parity, th):
+    """(links read, links written) by one class pass on an L^3 x T lattice,
+    by enumeration: every plaquette of the lattice as its four links, the
+    updated links (direction mu at the sites of one parity, the spatial ones
+    on frozen slices t = 0 mod th excepted), and every link of a plaquette
+    containing an updated link read.  Direction 0 is time."""
+    shape = (T, L, L, L)
+    V = T * L ** 3
+    t, z, y, x = np.indices(shape)
+    coords = [t, z, y, x]
+    ext = [T, L, L, L]
+
+    def link_id(c, d):
+        return ((((c[0] % T) * L + c[1] % L) * L + c[2] % L) * L + c[3] % L) * 4 + d
+
+    def shift(c, d):
+        c = list(c)
+        c[d] = c[d] + 1
+        return c
+
+    plaqs = []
+    for a in range(4):
+        for b in range(a + 1, 4):
+            plaqs.append(np.stack([link_id(coords, a), link_id(shift(coords, a), b),
+                                   link_id(shift(coords, b), a), link_id(coords, b)], axis=-1).reshape(-1, 4))
+    plaqs = np.concatenate(plaqs)
+    assert plaqs.shape == (6 * V, 4) and ext[0] == T
+    upd = (t + z + y + x) % 2 == parity
+    if mu != 0 and th:
+        upd &= t % th != 0
+    updated = np.zeros(4 * V, dtype=bool)
+    updated[link_id(coords, mu)[upd]] = True
+    touching = updated[plaqs].any(axis=1)
+    read = np.zeros(4 * V, dtype=bool)
+    read[plaqs[touching].ravel()] = True
+    return int(read.sum()), int(updated.sum())
+
+
+def test_stencil_words_match_a_brute_force_count():
+    # every class pass of a plain sweep and inside slabs of 2 and 4 (frozen
+    # spatial links at t = 0 mod th), both parities, every direction
+    L, T = 4, 8
+    V = T * L ** 3
+    for th in (0, 2, 4):
+        for mu in range(4):
+            for p in (0, 1):
+                r, w = _pass_links_bruteforce(L, T, mu, p, th)
+                er, ew = bench.pass_words(mu != 0, th)
+                assert (r, w) == (er * V, ew * V), (th, mu, p, r, w)
+    # per update: 9 words without slabs, 12 with slabs of 2, 10 with slabs of 4
+    for th, per_update in ((0, 9), (2, 12), (4, 10)):
+        r, w = bench.pass_words(True, th)
+        assert (r + w) / w == per_update
+
+
+def test_stencil_step_words():
+    # the benchmark's step on one 24^4 chain: 100 sweeps (4 hits of 36 words
+    # per site), 10 level-0 sweeps in slabs of 4 (31.5 words per site and
+    # hit) and 200 level-1 sweeps in slabs of 2 (27 words)
+    V = bench.L ** 3 * bench.T
+    assert bench.hit_words(0) == 36 and bench.hit_words(2) == 27 and bench.hit_words(4) == 31.5
+    assert bench.chain_stencil_words() == (100 * 4 * 36 + 10 * 4 * 31.5 + 200 * 4 * 27) * V
+    assert bench.chain_stencil_words(0) == (10 * 4 * 31.5 + 200 * 4 * 27) * V
+    ro = bench.stencil_roofline(48 * bench.chain_stencil_words(), 4, 440.0)
+    assert abs(ro["ms_at_peak"] - 296.687) < 1e-2 and abs(ro["frac"] - 296.687 / 440.0) < 1e-4
