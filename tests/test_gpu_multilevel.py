@@ -608,3 +608,36 @@ def test_single_level_fold_modes_give_the_same_bits(oracle_mod, multihit):
     c_o, _, _ = o.multilevel([2], [10], 1, 3, r_list, multihit=multihit)
     np.testing.assert_array_equal(runs[0][0], o.get_links())
     np.testing.assert_allclose(runs[0][1], c_o, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("multihit", [False, True])
+def test_single_level_fold_with_long_rows(oracle_mod, multihit):
+    # 24^3 x 8, slabs of 2, 40 updates per slab, r = 1..12: one child's rows
+    # take 15 KB (30 KB with the multihit lines) and all four children more
+    # than the 48 KB a block stages, so the fold goes child by child; the
+    # plain run prefetches the next child's rows with 256 threads for 48
+    # items, the multihit run (two buffers would take 60 KB) stages each
+    # child in turn.  Same bits as the per-site fold, C_ML(r) to 1e-12 of
+    # the oracle's.
+    L, T = 24, 8
+    r_list = list(range(1, 13))
+    runs = []
+    for mode in ("auto", "general"):
+        say(f"[gpu] 24^3x8 FP64 single level [2] x [40] r=1..12 multihit={multihit} fold={mode}")
+        g = u1ml.init_lattice(L, T, 1.0, 43, start=u1ml.COLD)
+        u1ml.set_estimator(g, multihit=multihit)
+        if mode == "general":
+            u1ml.set_debug(g, 4)
+        for _ in range(2):
+            u1ml.sweep(g, 1, 3)
+        u1ml.multilevel(g, [2], [40], 1, 3, r_list)
+        _, c, _ = u1ml.measure(g, observables=False, correlator=True)
+        runs.append((u1ml.get_links(g), c))
+    np.testing.assert_array_equal(runs[1][0], runs[0][0])
+    np.testing.assert_array_equal(runs[1][1], runs[0][1])
+    o = oracle_mod.OracleLattice(L, T, 1.0, 43, hot=False)
+    for _ in range(2):
+        o.sweep(1, 3)
+    c_o, _, _ = o.multilevel([2], [40], 1, 3, r_list, multihit=multihit)
+    np.testing.assert_array_equal(runs[0][0], o.get_links())
+    np.testing.assert_allclose(runs[0][1], c_o, rtol=1e-12, atol=0)
