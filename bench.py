@@ -113,12 +113,16 @@ def chain_stencil_words(n_between=N_BETWEEN):
     return stencil_words(L ** 3 * T, n_between, LEVELS, N_SUB)
 
 
-def stencil_roofline(words, bytes_per_word, ms):
+def stencil_roofline(words, bytes_per_word, ms, samples=None):
     """The link traffic of a step counted by its stencils, against the HBM
-    peak: bytes, the step time at peak, and the fraction of it achieved."""
+    peak: bytes, the step time at peak, the fraction of it achieved and, with
+    the step's samples, the samples/s at peak."""
     b = words * bytes_per_word
     ms_peak = b / (HBM_PEAK_GBS * 1e9) * 1e3
-    return {"bytes_per_step": b, "ms_at_peak": ms_peak, "frac": ms_peak / ms}
+    out = {"bytes_per_step": b, "ms_at_peak": ms_peak, "frac": ms_peak / ms}
+    if samples is not None:
+        out["samples_per_s_at_peak"] = samples / (ms_peak * 1e-3)
+    return out
 
 
 def sweep_sources_sha():
@@ -749,7 +753,8 @@ def main():
                           # slices too: 12 words per update with slabs of 2,
                           # 10 with slabs of 4 (pass_words); every pass counted
                           # by its stencil
-                          "stencil_exact": stencil_roofline(R * chain_stencil_words(), bw, main_run["ms_step"])},
+                          "stencil_exact": stencil_roofline(R * chain_stencil_words(), bw, main_run["ms_step"],
+                                                            R * samples_per_step())},
     }
     del main_run
     if not args.no_extra:
@@ -766,7 +771,7 @@ def main():
             "step_roofline_frac": ml_run["updates_per_s"] / (HBM_PEAK_GBS * 1e9 / (WORDS_PER_UPDATE * bw)),
             "samples_per_s_at_peak": samples_per_step() * HBM_PEAK_GBS * 1e9 /
                                      (WORDS_PER_UPDATE * bw * chain_updates_per_step(0)[1]),
-            "stencil_exact": stencil_roofline(R * chain_stencil_words(0), bw, ml_run["ms_step"])}
+            "stencil_exact": stencil_roofline(R * chain_stencil_words(0), bw, ml_run["ms_step"], R * samples_per_step())}
         del ml_run
         progress("cache-spilling roofline leg")
         ms_sp, iso_sp, tun_sp = roofline_leg(u1ml, torch, prec, SPILL_REPLICAS, 3, tune=tune)

@@ -138,3 +138,7 @@ def test_stencil_step_words():
     assert bench.chain_stencil_words(0) == (10 * 4 * 31.5 + 200 * 4 * 27) * V
     ro = bench.stencil_roofline(48 * bench.chain_stencil_words(), 4, 440.0)
     assert abs(ro["ms_at_peak"] - 296.687) < 1e-2 and abs(ro["frac"] - 296.687 / 440.0) < 1e-4
+    # the measurement alone: 48 x 2400 samples in 182.0 ms at peak
+    ro = bench.stencil_roofline(48 * bench.chain_stencil_words(0), 4, 305.0, 48 * bench.samples_per_step())
+    assert bench.samples_per_step() == 2400
+    assert abs(ro["samples_per_s_at_peak"] - 115200 / 0.18202558) < 1.0
