@@ -76,6 +76,11 @@ def test_null_handles_rejected():
     pid = C.c_uint64()
     assert lib.u1ml_batch_get_pass_id(None, 0, C.byref(pid)) == u1ml.EINVAL
     assert lib.u1ml_batch_set_pass_id(None, 0, 1) == u1ml.EINVAL
+    # an empty batch is refused before any device call
+    one_i, one_d, one_u = (C.c_int * 1)(8), (C.c_double * 1)(1.0), (C.c_uint64 * 1)(1)
+    bp = C.c_void_p()
+    assert lib.u1ml_batch_create(0, one_i, one_i, one_d, one_u, None, C.byref(bp)) == u1ml.EINVAL
+    assert not bp.value
     lib.u1ml_destroy(None)
     lib.u1ml_batch_destroy(None)
 

@@ -271,9 +271,11 @@ def test_error_paths():
         with pytest.raises(u1ml.U1MLError) as e:
             u1ml.multilevel(g, args[0], args[1], 1, 1, [1])
         assert e.value.code == u1ml.EINVAL
-    with pytest.raises(u1ml.U1MLError) as e:
-        u1ml.multilevel(g, [2], [1], 1, 1, [4])
-    assert e.value.code == u1ml.EINVAL
+    # a separation of L or more, and no separation at all
+    for r_list in ([4], []):
+        with pytest.raises(u1ml.U1MLError) as e:
+            u1ml.multilevel(g, [2], [1], 1, 1, r_list)
+        assert e.value.code == u1ml.EINVAL
     with pytest.raises(u1ml.U1MLError) as e:
         u1ml.multilevel(g, [2], [1], 1, 1, [1], rf_list=[2])
     assert e.value.code == u1ml.EINVAL
