@@ -641,3 +641,27 @@ def test_single_level_fold_with_long_rows(oracle_mod, multihit):
     c_o, _, _ = o.multilevel([2], [40], 1, 3, r_list, multihit=multihit)
     np.testing.assert_array_equal(runs[0][0], o.get_links())
     np.testing.assert_allclose(runs[0][1], c_o, rtol=1e-12, atol=0)
+
+
+def test_batch_fold_mixes_staging_paths(oracle_mod):
+    # one fold launch over a 4^3 x 8 and a 24^3 x 8 lattice with the multihit
+    # lines, slabs of 2 and 40 updates: the 24^3 rows of a child (30 KB) are
+    # staged child by child, while the 4^3 blocks hold theirs twice over and
+    # prefetch the next child; both lattices against the oracle (links
+    # bit-identical, C_ML(r) to 1e-12)
+    Ls, seeds = [4, 24], [44, 45]
+    r_list = [1, 2, 3]
+    say("[gpu] batch 4^3x8 + 24^3x8 FP64 single level [2] x [40] multihit vs oracle")
+    b = u1ml.batch_create(Ls, [8, 8], [1.0, 1.0], seeds, start=u1ml.COLD)
+    u1ml.batch_set_estimator(b, multihit=True)
+    for _ in range(2):
+        u1ml.batch_sweep(b, 1, 3)
+    u1ml.batch_multilevel(b, [2], [40], 1, 3, r_list)
+    for i, (L, s) in enumerate(zip(Ls, seeds)):
+        o = oracle_mod.OracleLattice(L, 8, 1.0, s, hot=False)
+        for _ in range(2):
+            o.sweep(1, 3)
+        c_o, _, _ = o.multilevel([2], [40], 1, 3, r_list, multihit=True)
+        _, c_g, _ = u1ml.batch_measure(b, i, correlator=True)
+        np.testing.assert_array_equal(u1ml.batch_get_links(b, i), o.get_links())
+        np.testing.assert_allclose(c_g, c_o, rtol=1e-12, atol=0)
