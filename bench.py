@@ -86,6 +86,8 @@ def pass_words(spatial, th):
     plaquettes' far sides) and the time links leaving them: 4 f + 1.5 (1 - f)."""
     if not spatial or th == 0:
         return 4.0, 0.5
+    if th == 1:
+        return 0.0, 0.0  # every spatial link frozen: the pass updates and reads nothing
     f = (th - 1) / th
     return 4.0 * f + 1.5 * (1.0 - f), f / 2.0
 

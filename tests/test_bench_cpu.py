@@ -112,11 +112,11 @@ def _pass_links_bruteforce(L, T, mu, parity, th):
 
 
 def test_stencil_words_match_a_brute_force_count():
-    # every class pass of a plain sweep and inside slabs of 2 and 4 (frozen
+    # every class pass of a plain sweep and inside slabs of 1, 2 and 4 (frozen
     # spatial links at t = 0 mod th), both parities, every direction
     L, T = 4, 8
     V = T * L ** 3
-    for th in (0, 2, 4):
+    for th in (0, 1, 2, 4):
         for mu in range(4):
             for p in (0, 1):
                 r, w = _pass_links_bruteforce(L, T, mu, p, th)
