@@ -548,7 +548,8 @@ UNEVEN_TH, UNEVEN_NSUB = 2, 10
 def uneven_leg(u1ml, torch, n_cycles, warmup=1, tune=True):
     """64 independent lattices of sizes drawn from {8,12,16,20,24}^4 and beta
     from {0.9, 1.0, 1.1} (numpy default_rng(7)), FP32 links, one batch on one
-    stream (class-pass shapes from the autotuner): after N_THERM sweeps,
+    stream (launch shapes from the autotuner, timed on the cycle's multilevel
+    shape with r = 1..4): after N_THERM sweeps,
     n_cycles cycles of UNEVEN_SWEEPS compound sweeps plus a single-level
     multilevel (slab thickness 2, 10 updates) with correlators at r = 1..L/2,
     each cycle one captured HIP graph; then every lattice's results are read
@@ -566,7 +567,8 @@ def uneven_leg(u1ml, torch, n_cycles, warmup=1, tune=True):
         u1ml.set_tuning(b, **tune)
         tuning = u1ml.get_tuning(b)
     elif tune:
-        tuning = u1ml.batch_autotune(b)
+        # the cycle's multilevel shape, with the separations every lattice has
+        tuning = u1ml.batch_autotune(b, [UNEVEN_TH], [UNEVEN_NSUB], list(range(1, min(Ls) // 2 + 1)))
     for _ in range(N_THERM):
         u1ml.batch_sweep(b, 1, 3)
 
