@@ -244,3 +244,84 @@ def test_symmetric_correlator_identity_updates_and_reality(oracle_mod):
     g3 = oracle_mod.OracleLattice(L, T, 1.0, 23, hot=True)
     c3, _, _ = g3.multilevel([4, 2], [3, 2], 1, 2, [1, 2, 3])
     assert np.abs(c3.imag).max() > 1e-6  # one orientation alone is not real
+
+
+def _two_level_by_replay(g, th0, th1, n0, n1, n_metro, n_or, r_list, rf, beta):
+    """C_ML(r) and the field estimator of Eq. (9) at separation rf of a
+    two-level run (Sec. 2.2), rebuilt in numpy from the configurations the
+    same slab-frozen sweeps produce: level-0 slabs of th0 (n0 updates), each
+    followed by n1 updates in slabs of th1; per inner configuration the
+    two-link products over each inner slab and the field operators summed over
+    its times; inner averages over the n1 configurations, their products over
+    the children of each top slab averaged over the n0 iterations; the
+    insertion in one child with the other children's plain averages, and in
+    one top slab with the other top slabs' averages."""
+    th = g.get_links()
+    T, L = th.shape[0], th.shape[1]
+    ns0, nch, ns1 = T // th0, th0 // th1, T // th1
+    nr, kf = len(r_list), list(r_list).index(rf)
+    A = np.zeros((ns0, L, L, L, nr), dtype=complex)
+    B = np.zeros((ns0, L, L, L, 2, 6, L, L), dtype=complex)
+    for _ in range(n0):
+        g.sweep(n_metro, n_or, th_frozen=th0)
+        a1 = np.zeros((ns1, L, L, L, nr), dtype=complex)
+        b1 = np.zeros((ns1, L, L, L, 2, 6, L, L), dtype=complex)
+        for _ in range(n1):
+            g.sweep(n_metro, n_or, th_frozen=th1)
+            th = g.get_links()
+            ph = th[..., 0]  # [t][z][y][x]
+            for k, r in enumerate(r_list):
+                tl = np.exp(1j * (np.roll(ph, -r, axis=3) - ph))
+                a1[..., k] += tl.reshape(ns1, th1, L, L, L).prod(axis=1)
+            tslab = np.exp(1j * (np.roll(ph, -rf, axis=3) - ph)).reshape(ns1, th1, L, L, L).prod(axis=1)
+            osl = field_ops(th, beta).reshape(6, ns1, th1, L, L, L).sum(axis=2)  # [c][slab][z][y][x]
+            for plane, m in enumerate([(rf - 1) // 2, rf // 2]):
+                for dy in range(L):
+                    for dz in range(L):
+                        sh = np.roll(np.roll(np.roll(osl, -m, axis=4), -dy, axis=3), -dz, axis=2)
+                        b1[..., plane, :, dy, dz] += tslab[..., None] * np.moveaxis(sh, 0, -1)
+        a1 /= n1
+        b1 /= n1
+        a1c = a1.reshape(ns0, nch, L, L, L, nr)
+        A += a1c.prod(axis=1)
+        b1c = b1.reshape(ns0, nch, L, L, L, 2, 6, L, L)
+        for ci in range(nch):
+            other = np.ones((ns0, L, L, L), dtype=complex)
+            for ch in range(nch):
+                if ch != ci:
+                    other = other * a1c[:, ch, ..., kf]
+            B += b1c[:, ci] * other[..., None, None, None, None]
+    A /= n0
+    B /= n0
+    C = A.prod(axis=0).mean(axis=(0, 1, 2))
+    F = np.zeros((2, 6, L, L), dtype=complex)
+    for s in range(ns0):
+        other = np.ones((L, L, L), dtype=complex)
+        for s2 in range(ns0):
+            if s2 != s:
+                other = other * A[s2, ..., kf]
+        F += (B[s] * other[..., None, None, None, None]).sum(axis=(0, 1, 2))
+    return C, F / (T * L ** 3)
+
+
+@pytest.mark.parametrize("levels,n_sub", [([4, 2], [2, 3]), ([8, 2], [3, 2])])
+def test_two_level_estimators_rebuilt_from_the_configurations(oracle_mod, levels, n_sub):
+    # several updates per level, so that every average is over more than one
+    # configuration: the oracle's nested averages (correlator and field
+    # insertion) against the same averages taken in numpy from the
+    # configurations of the same update sequence
+    L, T, beta = 4, 8, 1.0
+    r_list, rf = [1, 2, 3], 2
+    g1 = oracle_mod.OracleLattice(L, T, beta, 61)
+    g2 = oracle_mod.OracleLattice(L, T, beta, 61)
+    for g in (g1, g2):
+        for _ in range(2):
+            g.sweep(1, 2)
+    c1, f1, _ = g1.multilevel(levels, n_sub, 1, 2, r_list, rf_list=[rf])
+    c2, f2 = _two_level_by_replay(g2, levels[0], levels[1], n_sub[0], n_sub[1], 1, 2, r_list, rf, beta)
+    np.testing.assert_array_equal(g1.get_links(), g2.get_links())
+    assert g1.pass_id == g2.pass_id
+    np.testing.assert_allclose(c1, c2, rtol=1e-12, atol=0)
+    assert np.abs(f1[0] - f2).max() <= 1e-12 * np.abs(f2).max()
+    # the estimates are not the plain ones of the final configuration
+    assert abs(c1[0] - plain_corr(g1.get_links(), 1)) > 1e-6
