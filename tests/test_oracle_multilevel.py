@@ -246,7 +246,7 @@ def test_symmetric_correlator_identity_updates_and_reality(oracle_mod):
     assert np.abs(c3.imag).max() > 1e-6  # one orientation alone is not real
 
 
-def _two_level_by_replay(g, th0, th1, n0, n1, n_metro, n_or, r_list, rf, beta):
+def _two_level_by_replay(g, th0, th1, n0, n1, n_metro, n_or, r_list, rf, beta, multihit=False):
     """C_ML(r) and the field estimator of Eq. (9) at separation rf of a
     two-level run (Sec. 2.2), rebuilt in numpy from the configurations the
     same slab-frozen sweeps produce: level-0 slabs of th0 (n0 updates), each
@@ -255,7 +255,10 @@ def _two_level_by_replay(g, th0, th1, n0, n1, n_metro, n_or, r_list, rf, beta):
     its times; inner averages over the n1 configurations, their products over
     the children of each top slab averaged over the n0 iterations; the
     insertion in one child with the other children's plain averages, and in
-    one top slab with the other top slabs' averages."""
+    one top slab with the other top slabs' averages.  multihit: for r >= 2 the
+    correlator lines take the temporal links' multihit means (so also the
+    averages that multiply an insertion elsewhere); the slab holding the
+    insertion keeps the links themselves."""
     th = g.get_links()
     T, L = th.shape[0], th.shape[1]
     ns0, nch, ns1 = T // th0, th0 // th1, T // th1
@@ -270,8 +273,14 @@ def _two_level_by_replay(g, th0, th1, n0, n1, n_metro, n_or, r_list, rf, beta):
             g.sweep(n_metro, n_or, th_frozen=th1)
             th = g.get_links()
             ph = th[..., 0]  # [t][z][y][x]
+            if multihit:
+                from tests.test_oracle_multihit import multihit_means
+                mm = multihit_means(th, beta)
             for k, r in enumerate(r_list):
-                tl = np.exp(1j * (np.roll(ph, -r, axis=3) - ph))
+                if multihit and r >= 2:
+                    tl = np.conj(mm) * np.roll(mm, -r, axis=3)
+                else:
+                    tl = np.exp(1j * (np.roll(ph, -r, axis=3) - ph))
                 a1[..., k] += tl.reshape(ns1, th1, L, L, L).prod(axis=1)
             tslab = np.exp(1j * (np.roll(ph, -rf, axis=3) - ph)).reshape(ns1, th1, L, L, L).prod(axis=1)
             osl = field_ops(th, beta).reshape(6, ns1, th1, L, L, L).sum(axis=2)  # [c][slab][z][y][x]
@@ -304,8 +313,9 @@ def _two_level_by_replay(g, th0, th1, n0, n1, n_metro, n_or, r_list, rf, beta):
     return C, F / (T * L ** 3)
 
 
+@pytest.mark.parametrize("multihit", [False, True])
 @pytest.mark.parametrize("levels,n_sub", [([4, 2], [2, 3]), ([8, 2], [3, 2])])
-def test_two_level_estimators_rebuilt_from_the_configurations(oracle_mod, levels, n_sub):
+def test_two_level_estimators_rebuilt_from_the_configurations(oracle_mod, levels, n_sub, multihit):
     # several updates per level, so that every average is over more than one
     # configuration: the oracle's nested averages (correlator and field
     # insertion) against the same averages taken in numpy from the
@@ -317,8 +327,9 @@ def test_two_level_estimators_rebuilt_from_the_configurations(oracle_mod, levels
     for g in (g1, g2):
         for _ in range(2):
             g.sweep(1, 2)
-    c1, f1, _ = g1.multilevel(levels, n_sub, 1, 2, r_list, rf_list=[rf])
-    c2, f2 = _two_level_by_replay(g2, levels[0], levels[1], n_sub[0], n_sub[1], 1, 2, r_list, rf, beta)
+    c1, f1, _ = g1.multilevel(levels, n_sub, 1, 2, r_list, rf_list=[rf], multihit=multihit)
+    c2, f2 = _two_level_by_replay(g2, levels[0], levels[1], n_sub[0], n_sub[1], 1, 2, r_list, rf, beta,
+                                  multihit=multihit)
     np.testing.assert_array_equal(g1.get_links(), g2.get_links())
     assert g1.pass_id == g2.pass_id
     np.testing.assert_allclose(c1, c2, rtol=1e-12, atol=0)
