@@ -246,7 +246,15 @@ def test_symmetric_correlator_identity_updates_and_reality(oracle_mod):
     assert np.abs(c3.imag).max() > 1e-6  # one orientation alone is not real
 
 
-def _two_level_by_replay(g, th0, th1, n0, n1, n_metro, n_or, r_list, rf, beta, multihit=False):
+def _shift(a, r, e):
+    """a at x0 + r e for a[..., z, y, x] (periodic), e a unit vector (ex, ey, ez)."""
+    return np.roll(np.roll(np.roll(a, -r * e[0], axis=-1), -r * e[1], axis=-2), -r * e[2], axis=-3)
+
+
+DIRS6 = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+
+
+def _two_level_by_replay(g, th0, th1, n0, n1, n_metro, n_or, r_list, rf, beta, multihit=False, symmetric=False):
     """C_ML(r) and the field estimator of Eq. (9) at separation rf of a
     two-level run (Sec. 2.2), rebuilt in numpy from the configurations the
     same slab-frozen sweeps produce: level-0 slabs of th0 (n0 updates), each
@@ -258,31 +266,34 @@ def _two_level_by_replay(g, th0, th1, n0, n1, n_metro, n_or, r_list, rf, beta, m
     one top slab with the other top slabs' averages.  multihit: for r >= 2 the
     correlator lines take the temporal links' multihit means (so also the
     averages that multiply an insertion elsewhere); the slab holding the
-    insertion keeps the links themselves."""
+    insertion keeps the links themselves.  symmetric: C_ML(r) is the mean of
+    the estimates along +-x, +-y, +-z, each with its own nested averages; the
+    insertion stays along +x."""
     th = g.get_links()
     T, L = th.shape[0], th.shape[1]
     ns0, nch, ns1 = T // th0, th0 // th1, T // th1
     nr, kf = len(r_list), list(r_list).index(rf)
-    A = np.zeros((ns0, L, L, L, nr), dtype=complex)
+    dirs = DIRS6 if symmetric else DIRS6[:1]
+    nd = len(dirs)
+    A = np.zeros((ns0, L, L, L, nd, nr), dtype=complex)
     B = np.zeros((ns0, L, L, L, 2, 6, L, L), dtype=complex)
     for _ in range(n0):
         g.sweep(n_metro, n_or, th_frozen=th0)
-        a1 = np.zeros((ns1, L, L, L, nr), dtype=complex)
+        a1 = np.zeros((ns1, L, L, L, nd, nr), dtype=complex)
         b1 = np.zeros((ns1, L, L, L, 2, 6, L, L), dtype=complex)
         for _ in range(n1):
             g.sweep(n_metro, n_or, th_frozen=th1)
             th = g.get_links()
-            ph = th[..., 0]  # [t][z][y][x]
+            u = np.exp(1j * th[..., 0])  # [t][z][y][x]
             if multihit:
                 from tests.test_oracle_multihit import multihit_means
                 mm = multihit_means(th, beta)
-            for k, r in enumerate(r_list):
-                if multihit and r >= 2:
-                    tl = np.conj(mm) * np.roll(mm, -r, axis=3)
-                else:
-                    tl = np.exp(1j * (np.roll(ph, -r, axis=3) - ph))
-                a1[..., k] += tl.reshape(ns1, th1, L, L, L).prod(axis=1)
-            tslab = np.exp(1j * (np.roll(ph, -rf, axis=3) - ph)).reshape(ns1, th1, L, L, L).prod(axis=1)
+            for di, e in enumerate(dirs):
+                for k, r in enumerate(r_list):
+                    v = mm if multihit and r >= 2 else u
+                    tl = np.conj(v) * _shift(v, r, e)
+                    a1[..., di, k] += tl.reshape(ns1, th1, L, L, L).prod(axis=1)
+            tslab = (np.conj(u) * _shift(u, rf, (1, 0, 0))).reshape(ns1, th1, L, L, L).prod(axis=1)
             osl = field_ops(th, beta).reshape(6, ns1, th1, L, L, L).sum(axis=2)  # [c][slab][z][y][x]
             for plane, m in enumerate([(rf - 1) // 2, rf // 2]):
                 for dy in range(L):
@@ -291,31 +302,31 @@ def _two_level_by_replay(g, th0, th1, n0, n1, n_metro, n_or, r_list, rf, beta, m
                         b1[..., plane, :, dy, dz] += tslab[..., None] * np.moveaxis(sh, 0, -1)
         a1 /= n1
         b1 /= n1
-        a1c = a1.reshape(ns0, nch, L, L, L, nr)
+        a1c = a1.reshape(ns0, nch, L, L, L, nd, nr)
         A += a1c.prod(axis=1)
         b1c = b1.reshape(ns0, nch, L, L, L, 2, 6, L, L)
         for ci in range(nch):
             other = np.ones((ns0, L, L, L), dtype=complex)
             for ch in range(nch):
                 if ch != ci:
-                    other = other * a1c[:, ch, ..., kf]
+                    other = other * a1c[:, ch, ..., 0, kf]
             B += b1c[:, ci] * other[..., None, None, None, None]
     A /= n0
     B /= n0
-    C = A.prod(axis=0).mean(axis=(0, 1, 2))
+    C = A.prod(axis=0).mean(axis=(0, 1, 2)).mean(axis=0)
     F = np.zeros((2, 6, L, L), dtype=complex)
     for s in range(ns0):
         other = np.ones((L, L, L), dtype=complex)
         for s2 in range(ns0):
             if s2 != s:
-                other = other * A[s2, ..., kf]
+                other = other * A[s2, ..., 0, kf]
         F += (B[s] * other[..., None, None, None, None]).sum(axis=(0, 1, 2))
     return C, F / (T * L ** 3)
 
 
-@pytest.mark.parametrize("multihit", [False, True])
+@pytest.mark.parametrize("multihit,symmetric", [(False, False), (True, False), (False, True), (True, True)])
 @pytest.mark.parametrize("levels,n_sub", [([4, 2], [2, 3]), ([8, 2], [3, 2])])
-def test_two_level_estimators_rebuilt_from_the_configurations(oracle_mod, levels, n_sub, multihit):
+def test_two_level_estimators_rebuilt_from_the_configurations(oracle_mod, levels, n_sub, multihit, symmetric):
     # several updates per level, so that every average is over more than one
     # configuration: the oracle's nested averages (correlator and field
     # insertion) against the same averages taken in numpy from the
@@ -327,9 +338,9 @@ def test_two_level_estimators_rebuilt_from_the_configurations(oracle_mod, levels
     for g in (g1, g2):
         for _ in range(2):
             g.sweep(1, 2)
-    c1, f1, _ = g1.multilevel(levels, n_sub, 1, 2, r_list, rf_list=[rf], multihit=multihit)
+    c1, f1, _ = g1.multilevel(levels, n_sub, 1, 2, r_list, rf_list=[rf], multihit=multihit, symmetric=symmetric)
     c2, f2 = _two_level_by_replay(g2, levels[0], levels[1], n_sub[0], n_sub[1], 1, 2, r_list, rf, beta,
-                                  multihit=multihit)
+                                  multihit=multihit, symmetric=symmetric)
     np.testing.assert_array_equal(g1.get_links(), g2.get_links())
     assert g1.pass_id == g2.pass_id
     np.testing.assert_allclose(c1, c2, rtol=1e-12, atol=0)
