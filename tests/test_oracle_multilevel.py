@@ -347,3 +347,52 @@ def test_two_level_estimators_rebuilt_from_the_configurations(oracle_mod, levels
     assert np.abs(f1[0] - f2).max() <= 1e-12 * np.abs(f2).max()
     # the estimates are not the plain ones of the final configuration
     assert abs(c1[0] - plain_corr(g1.get_links(), 1)) > 1e-6
+
+
+def _level_by_replay(g, lev, ths, n_subs, r_list, beta, multihit, dirs):
+    """Averages over n_subs[lev] updates in slabs of ths[lev] of the slab
+    products: two-link lines over the slab's times at the innermost level,
+    else the products of the children's averages (Sec. 2.2).  Returns
+    [slab][z][y][x][dir][r]."""
+    th = g.get_links()
+    T, L = th.shape[0], th.shape[1]
+    ns = T // ths[lev]
+    acc = np.zeros((ns, L, L, L, len(dirs), len(r_list)), dtype=complex)
+    for _ in range(n_subs[lev]):
+        g.sweep(1, 2, th_frozen=ths[lev])
+        if lev == len(ths) - 1:
+            th = g.get_links()
+            u = np.exp(1j * th[..., 0])
+            if multihit:
+                from tests.test_oracle_multihit import multihit_means
+                mm = multihit_means(th, beta)
+            for di, e in enumerate(dirs):
+                for k, r in enumerate(r_list):
+                    v = mm if multihit and r >= 2 else u
+                    tl = np.conj(v) * _shift(v, r, e)
+                    acc[..., di, k] += tl.reshape(ns, ths[lev], L, L, L).prod(axis=1)
+        else:
+            child = _level_by_replay(g, lev + 1, ths, n_subs, r_list, beta, multihit, dirs)
+            nch = ths[lev] // ths[lev + 1]
+            acc += child.reshape((ns, nch) + child.shape[1:]).prod(axis=1)
+    return acc / n_subs[lev]
+
+
+@pytest.mark.parametrize("ths,n_subs", [([8, 4, 2], [2, 2, 3]), ([4, 2, 1], [2, 2, 2])])
+@pytest.mark.parametrize("multihit,symmetric", [(False, False), (True, True)])
+def test_three_level_correlator_rebuilt_from_the_configurations(oracle_mod, multihit, symmetric, ths, n_subs):
+    # three levels on 4^3 x 8, every average over more than one
+    # configuration: one top slab spanning T, or two top slabs with innermost
+    # slabs of one time slice (only temporal links updated there)
+    L, T, beta = 4, 8, 1.0
+    r_list = [1, 2, 3]
+    g1 = oracle_mod.OracleLattice(L, T, beta, 67)
+    g2 = oracle_mod.OracleLattice(L, T, beta, 67)
+    for g in (g1, g2):
+        g.sweep(1, 2)
+    c1, _, _ = g1.multilevel(ths, n_subs, 1, 2, r_list, multihit=multihit, symmetric=symmetric)
+    dirs = DIRS6 if symmetric else DIRS6[:1]
+    A = _level_by_replay(g2, 0, ths, n_subs, r_list, beta, multihit, dirs)
+    c2 = A.prod(axis=0).mean(axis=(0, 1, 2)).mean(axis=0)
+    np.testing.assert_array_equal(g1.get_links(), g2.get_links())
+    np.testing.assert_allclose(c1, c2, rtol=1e-12, atol=0)
