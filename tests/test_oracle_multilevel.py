@@ -1,13 +1,18 @@
 """Pins of the oracle's multilevel estimators (Sec. 2.2, Eqs. (8), (9)).
 
 Special cases where the nested averages collapse to the plain definitions
-(one update per level; updates that are the identity; a cold lattice), plus a
-statistical check that the multilevel estimator and the plain estimator agree.
+(one update per level; updates that are the identity; a cold lattice); the
+nested averages of runs with several updates per level rebuilt in numpy from
+the configurations of the same slab-frozen sweeps (two and three levels,
+field insertion, multihit lines, the six directions); and a statistical check
+that the multilevel estimator and the plain estimator agree.
 """
 import math
 
 import numpy as np
 import pytest
+
+from tests.test_oracle_multihit import multihit_means
 
 AX = {0: 0, 1: 3, 2: 2, 3: 1}
 FIELD_PLANES = [(0, 1), (0, 2), (0, 3), (2, 3), (3, 1), (1, 2)]  # E_x..E_z, B_x..B_z
@@ -286,7 +291,6 @@ def _two_level_by_replay(g, th0, th1, n0, n1, n_metro, n_or, r_list, rf, beta, m
             th = g.get_links()
             u = np.exp(1j * th[..., 0])  # [t][z][y][x]
             if multihit:
-                from tests.test_oracle_multihit import multihit_means
                 mm = multihit_means(th, beta)
             for di, e in enumerate(dirs):
                 for k, r in enumerate(r_list):
@@ -364,7 +368,6 @@ def _level_by_replay(g, lev, ths, n_subs, r_list, beta, multihit, dirs):
             th = g.get_links()
             u = np.exp(1j * th[..., 0])
             if multihit:
-                from tests.test_oracle_multihit import multihit_means
                 mm = multihit_means(th, beta)
             for di, e in enumerate(dirs):
                 for k, r in enumerate(r_list):
