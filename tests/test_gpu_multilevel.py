@@ -665,3 +665,35 @@ def test_batch_fold_mixes_staging_paths(oracle_mod):
         _, c_g, _ = u1ml.batch_measure(b, i, correlator=True)
         np.testing.assert_array_equal(u1ml.batch_get_links(b, i), o.get_links())
         np.testing.assert_allclose(c_g, c_o, rtol=1e-12, atol=0)
+
+
+def test_full_size_48_two_level_several_samples_match_oracle(oracle_mod):
+    # the large configuration's lattice, 48^4 FP64 (one lattice, the
+    # single-lattice class passes), a two-level run {4,2} x {2,2} with
+    # r = 1..24 (four groups of six separations per row): the three fold
+    # modes give the same bits, the links are the oracle's and C_ML(r) is to
+    # 1e-12
+    L = T = 48
+    r_list = list(range(1, 25))
+    runs = []
+    for mode in ("all", "per_child", "general"):
+        say(f"[gpu] 48^4 FP64 two-level {{4,2}} x {{2,2}} r=1..24 fold={mode}")
+        g = u1ml.init_lattice(L, T, 1.0, 73)
+        if mode == "general":
+            u1ml.set_debug(g, 4)
+        else:
+            u1ml.set_tuning(g, fold_stage=1 if mode == "all" else 2)
+        u1ml.sweep(g, 1, 3)
+        u1ml.multilevel(g, [4, 2], [2, 2], 1, 3, r_list)
+        _, c, _ = u1ml.measure(g, observables=False, correlator=True)
+        runs.append((u1ml.get_links(g), c))
+        del g
+    for th, c in runs[1:]:
+        np.testing.assert_array_equal(th, runs[0][0])
+        np.testing.assert_array_equal(c, runs[0][1])
+    say("  oracle 48^4")
+    o = oracle_mod.OracleLattice(L, T, 1.0, 73, hot=True)
+    o.sweep(1, 3)
+    c_o, _, _ = o.multilevel([4, 2], [2, 2], 1, 3, r_list)
+    np.testing.assert_array_equal(runs[0][0], o.get_links())
+    np.testing.assert_allclose(runs[0][1], c_o, rtol=1e-12, atol=0)
