@@ -697,3 +697,26 @@ def test_full_size_48_two_level_several_samples_match_oracle(oracle_mod):
     c_o, _, _ = o.multilevel([4, 2], [2, 2], 1, 3, r_list)
     np.testing.assert_array_equal(runs[0][0], o.get_links())
     np.testing.assert_allclose(runs[0][1], c_o, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("L,T,levels,n_sub,rf", [
+    (12, 12, [6, 2], [2, 2], [3, 6]),
+    (16, 8, [4, 2], [2, 3], [2, 4]),
+])
+def test_field_with_several_samples_at_larger_sizes(oracle_mod, L, T, levels, n_sub, rf):
+    # the fused contraction at sizes with several transform blocks per plane
+    # set and lengths 12 (radices 4, 3) and 16 (4, 4), three children per top
+    # slab or two top slabs, several updates per level: the correlator
+    # (r = 1..L/2) and the E/B profiles against the oracle
+    r_list = list(range(1, L // 2 + 1))
+    say(f"[gpu] field with several samples L={L} T={T} levels={levels} n_sub={n_sub} rf={rf}")
+    o = oracle_mod.OracleLattice(L, T, 1.0, 77, hot=True)
+    g = u1ml.init_lattice(L, T, 1.0, 77)
+    o.sweep(1, 3)
+    u1ml.sweep(g, 1, 3)
+    c_o, f_o, _ = o.multilevel(levels, n_sub, 1, 3, r_list, rf_list=rf)
+    u1ml.multilevel(g, levels, n_sub, 1, 3, r_list, rf_list=rf)
+    _, c_g, f_g = u1ml.measure(g, observables=False, correlator=True, field_profile=True)
+    np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
+    np.testing.assert_allclose(c_g, c_o, rtol=1e-12, atol=0)
+    close_rel(f_g, f_o)
