@@ -442,6 +442,24 @@ def counters_run(args):
     del src, dst
     u1ml.stream_bandwidth("read", 1 << 30, 3)
     u1ml.stream_bandwidth("read", 64 << 20, 10)
+    if args.counters_uneven:
+        # the 64 uneven lattices: two sweeps and one measurement cycle (one
+        # sweep, the single-level run with slabs of 2 and 10 updates,
+        # r = 1..L/2), launched one kernel at a time
+        import numpy as np
+
+        rng = np.random.default_rng(7)
+        Ls = [int(v) for v in rng.choice([8, 12, 16, 20, 24], UNEVEN_N)]
+        betas = [float(v) for v in rng.choice([0.9, 1.0, 1.1], UNEVEN_N)]
+        b = u1ml.batch_create(Ls, Ls, betas, [1000 + i for i in range(UNEVEN_N)], start=u1ml.COLD,
+                              precision=u1ml.FP32, stream=stream.cuda_stream)
+        for _ in range(2):
+            u1ml.batch_sweep(b, 1, 3)
+        u1ml.batch_cycle(b, 1, 1, 3, UNEVEN_TH, UNEVEN_NSUB, use_graph=False)
+        u1ml.batch_synchronize(b)
+        print(json.dumps({"counters_run": True, "copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
+                          "uneven": UNEVEN_N}), flush=True)
+        return
     R = args.replicas
     prec = u1ml.FP32 if args.precision == "fp32" else u1ml.FP64
     lat = u1ml.batch_create([L] * R, [T] * R, [BETA] * R, [3 + i for i in range(R)], start=u1ml.COLD,
@@ -651,6 +669,8 @@ def main():
     ap.add_argument("--counters", action="store_true", help="short run for hardware-counter passes")
     ap.add_argument("--counters-multilevel", action="store_true",
                     help="with --counters: one multilevel run {4,2} x {1,1} after the sweeps")
+    ap.add_argument("--counters-uneven", action="store_true",
+                    help="with --counters: the 64 uneven lattices (two sweeps and one measurement cycle) instead")
     ap.add_argument("--large", action="store_true",
                     help="instead of the 24^4 workload: one 48^4 chain per precision (FP32 vs FP64)")
     ap.add_argument("--uneven", action="store_true",
