@@ -113,14 +113,15 @@ def test_large_48_identity_fp32():
 
 
 def test_bench_batch_shape_identity_fp32():
-    # the benchmark's launch configuration: a batch of 24^4 FP32 lattices with
-    # its tuned shapes (class pass 256 threads, XCD-contiguous; transforms of
-    # 4 planes per block; contraction 128 threads) through the two-level run
+    # the benchmark's launch configuration: a batch of 16 24^4 FP32 lattices
+    # (one of its three batches) with its tuned shapes (class pass 256
+    # threads, XCD-contiguous; transforms of 4 planes per block; contraction
+    # 128 threads) through the two-level run
     # with the field at r = 2, 4, 6, one update per level: every lattice's
     # C_ML(r), r = 1..12, equals the plain correlator of its final links and
     # its field the plain Eq. (9) definition at sampled offsets
     L = T = 24
-    n = 3
+    n = 16
     say(f"[gpu] batch of {n} x 24^4 FP32 with the bench's shapes, one-update identity")
     b = u1ml.batch_create([L] * n, [T] * n, [1.0] * n, [61 + i for i in range(n)], precision=u1ml.FP32,
                           start=u1ml.COLD)
