@@ -6,8 +6,8 @@ starts from the same angles to FP32 rounding and, after its own sweep, has the
 FP64 chain's plaquette to within the fluctuation of a 5e7-site average; and a
 single-level multilevel run with one update per slab reproduces the plain
 correlator of its final configuration (the slab updates are disjoint,
-Sec. 2.2), through the general fold (42 slabs of 84 sites exceed the row
-fold's staging)."""
+Sec. 2.2), through the row fold staging one child slab at a time (42 slabs
+of 84 sites exceed what one block stages at once)."""
 import sys
 
 import numpy as np
