@@ -720,3 +720,31 @@ def test_field_with_several_samples_at_larger_sizes(oracle_mod, L, T, levels, n_
     np.testing.assert_array_equal(u1ml.get_links(g), o.get_links())
     np.testing.assert_allclose(c_g, c_o, rtol=1e-12, atol=0)
     close_rel(f_g, f_o)
+
+
+@pytest.mark.parametrize("multihit", [False, True])
+def test_fold_stagings_with_the_symmetric_correlator(oracle_mod, multihit):
+    # rows along y and z (strided by L and L^2) staged all at once and one
+    # child slab at a time: same bits, and the oracle's six literal
+    # directions to 1e-12 of the largest entry (12^4, slabs of 2, 10 updates)
+    L = T = 12
+    r_list = [1, 2, 3, 5]
+    runs = []
+    for stage in (1, 2):
+        say(f"[gpu] symmetric correlator 12^4 [2] x [10] multihit={multihit} fold_stage={stage}")
+        g = u1ml.init_lattice(L, T, 1.0, 79, start=u1ml.COLD)
+        u1ml.set_estimator(g, multihit=multihit, symmetric=True)
+        u1ml.set_tuning(g, fold_stage=stage)
+        for _ in range(2):
+            u1ml.sweep(g, 1, 3)
+        u1ml.multilevel(g, [2], [10], 1, 3, r_list)
+        _, c, _ = u1ml.measure(g, observables=False, correlator=True)
+        runs.append((u1ml.get_links(g), c))
+    np.testing.assert_array_equal(runs[1][0], runs[0][0])
+    np.testing.assert_array_equal(runs[1][1], runs[0][1])
+    o = oracle_mod.OracleLattice(L, T, 1.0, 79, hot=False)
+    for _ in range(2):
+        o.sweep(1, 3)
+    c_o, _, _ = o.multilevel([2], [10], 1, 3, r_list, multihit=multihit, symmetric=True)
+    np.testing.assert_array_equal(runs[0][0], o.get_links())
+    close_rel(runs[0][1].real, c_o.real)
